@@ -1,0 +1,155 @@
+/*
+ * qoc.h - C ABI of the MI355X second-order adjoint quantum optimal-control library.
+ *
+ * Problem (paper Sec. II): given a real symmetric core Hamiltonian H0 and dipole matrix M
+ * (n x n), an initial state psi0 and a target psi_target (complex n-vectors), a time grid
+ * of nt steps of size dt and a control model f_j = (B theta)_j sampled at t_j = j dt
+ * (eq. eom, eq. Zdef), the library evaluates the discretised objective
+ *
+ *     C(theta) = (gamma/2) sum_{j<nt} f_j^2 + (rho/2) || a_nt - psi_target ||^2,
+ *     a_{j+1} = exp(-i dt (H0 + f_j M)) a_j,  a_0 = psi0          (eq. discTDSE, discretecost)
+ *
+ * together with its exact gradient (Alg. 1, eq. dLdf), exact Hessian (Alg. 2, eq. d2Ldf2)
+ * and Hessian-vector products.  One control direction is supported (the paper's
+ * experiments use the z dipole only, Sec. II).  All arithmetic is IEEE FP64 on the GPU.
+ *
+ * Conventions
+ *  - Every call returns qoc_status; 0 is success, negative values are errors.  No C++
+ *    exception crosses this boundary.  On error, output buffers are left untouched and
+ *    qoc_last_error(handle) holds a message.
+ *  - Matrices are row-major.  Complex vectors are interleaved (re, im) doubles.
+ *  - Host-pointer entry points copy their inputs; no pointer is retained after return.
+ *    They block until results are on the host.
+ *  - *_dev entry points take device pointers valid on the handle's stream and only
+ *    enqueue work on that stream; the caller keeps the buffers alive until the stream
+ *    has passed them.  Device-side failures of a *_dev call (Jacobi non-convergence)
+ *    are reported by qoc_sync(handle).
+ *  - A handle is not thread-safe; separate handles are independent.
+ *  - psi0 and psi_target are used as given (not normalised).  The Hessian is returned
+ *    symmetric by construction (the two-sweep form of the second-order adjoint).
+ */
+#ifndef QOC_H
+#define QOC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t qoc_status;
+
+#define QOC_OK                  0
+#define QOC_ERR_INVALID_ARG    -1  /* NULL pointer, bad size, non-finite input, dt <= 0 ...  */
+#define QOC_ERR_NOT_SYMMETRIC  -2  /* |X - X^T| > 1e-12 |X| for H0 or M                      */
+#define QOC_ERR_STATE          -3  /* compute called before system and basis were set          */
+#define QOC_ERR_UNSUPPORTED    -4  /* n above the build limit (128) or P above 4096          */
+#define QOC_ERR_NOCONV         -5  /* Jacobi sweep cap reached on some step                   */
+#define QOC_ERR_DEVICE         -6  /* HIP runtime failure (message in qoc_last_error)         */
+#define QOC_ERR_OOM            -7  /* device allocation failed                                 */
+#define QOC_ERR_NOT_CONVERGED  -8  /* trust-region solve hit max_iter (outputs still written)  */
+
+typedef struct qoc_problem qoc_problem;
+typedef struct qoc_batch qoc_batch;
+
+typedef enum {
+    QOC_BASIS_FOURIER = 0,   /* B[j,k-1] = cos(k pi t_j/T), B[j,K+k-1] = sin(k pi t_j/T), k=1..K; P=2K */
+    QOC_BASIS_IDENTITY = 1,  /* maximal model f_j = theta_j (eq. maximal): P = nt                   */
+    QOC_BASIS_DENSE = 2      /* caller-supplied nt x P row-major B                                 */
+} qoc_basis_kind;
+
+/* Create a handle on HIP device `device`.  hip_stream: a hipStream_t to run on, or NULL for a
+ * library-owned stream.  *out receives the handle. */
+qoc_status qoc_create(int device, void* hip_stream, qoc_problem** out);
+/* Release the handle and all device memory it owns.  NULL-safe. */
+void qoc_destroy(qoc_problem* p);
+/* Switch the stream later calls are enqueued on (NULL: library-owned stream). */
+qoc_status qoc_set_stream(qoc_problem* p, void* hip_stream);
+
+/* System of eq. matrixTDSE with one control (Sec. II): h0, m are n x n real symmetric
+ * (symmetry checked to 1e-12 relative); psi0, psi_target are n complex (2n doubles). */
+qoc_status qoc_set_system(qoc_problem* p, int32_t n, const double* h0, const double* m,
+                          const double* psi0, const double* psi_target);
+/* Replace only the target state (2n doubles); cheap, keeps all other settings. */
+qoc_status qoc_set_target(qoc_problem* p, const double* psi_target);
+
+/* Control model f(j dt; theta) (Sec. II) on a grid of nt steps of size dt (T = nt dt).
+ * FOURIER: k_or_p = K >= 1, b = NULL.  IDENTITY: k_or_p ignored, b = NULL.
+ * DENSE: k_or_p = P >= 1, b = nt x P row-major (copied). */
+qoc_status qoc_set_control_basis(qoc_problem* p, qoc_basis_kind kind, int32_t nt, double dt,
+                                 int32_t k_or_p, const double* b);
+/* Weights of eq. discretecost: gamma on the field energy (paper: 1), rho on the terminal
+ * error.  Default gamma = 2 dt, rho = 2, i.e. C = dt sum f_j^2 + |a_nt - psi_target|^2. */
+qoc_status qoc_set_weights(qoc_problem* p, double gamma, double rho);
+/* Number of control parameters P of the current basis. */
+qoc_status qoc_get_num_params(const qoc_problem* p, int32_t* num_params);
+
+/* Cost only: forward sweep of Alg. 1 lines 1-5 and eq. discretecost. theta: P doubles. */
+qoc_status qoc_cost(qoc_problem* p, const double* theta, double* cost);
+/* Cost and gradient: Alg. 1 lines 1-11 (first-order adjoint, eq. lambdasys, eq. dLdf). */
+qoc_status qoc_grad(qoc_problem* p, const double* theta, double* cost, double* grad);
+/* Cost, gradient and P x P Hessian (row-major): Alg. 2 lines 1-27 (eq. musys, eq. gradatheta,
+ * eq. d2Ldf2).  Any of cost / grad may be NULL. */
+qoc_status qoc_hess(qoc_problem* p, const double* theta, double* cost, double* grad, double* hess);
+/* Hessian-vector product H(theta) v (Alg. 2's tangent and second-adjoint sweeps for a single
+ * direction).  v, hv: P doubles.  grad may be NULL; if not, receives the gradient too. */
+qoc_status qoc_hvp(qoc_problem* p, const double* theta, const double* v, double* hv, double* grad);
+/* `count` independent theta (count x P row-major) on the same system, evaluated together.
+ * costs: count, grads: count x P, hess: count x P x P; any output may be NULL. */
+qoc_status qoc_hess_many(qoc_problem* p, int32_t count, const double* thetas,
+                         double* costs, double* grads, double* hess);
+qoc_status qoc_grad_many(qoc_problem* p, int32_t count, const double* thetas,
+                         double* costs, double* grads);
+
+/* Device-pointer twins (same kernels, enqueue only, no synchronisation). */
+qoc_status qoc_cost_dev(qoc_problem* p, const double* theta, double* cost);
+qoc_status qoc_grad_dev(qoc_problem* p, const double* theta, double* cost, double* grad);
+qoc_status qoc_hess_dev(qoc_problem* p, const double* theta, double* cost, double* grad, double* hess);
+qoc_status qoc_hvp_dev(qoc_problem* p, const double* theta, const double* v, double* hv, double* grad);
+qoc_status qoc_hess_many_dev(qoc_problem* p, int32_t count, const double* thetas,
+                             double* costs, double* grads, double* hess);
+/* Wait for the handle's stream and report device-side failures of earlier *_dev calls. */
+qoc_status qoc_sync(qoc_problem* p);
+
+/* Per-step propagator data from the device eigendecomposition at step j for parameters
+ * theta (test and inspection aid): u, u1, u2 receive U_j, dU_j/df, d^2U_j/df^2 as n x n
+ * complex row-major (2 n^2 doubles each; any may be NULL). */
+qoc_status qoc_step_propagators(qoc_problem* p, const double* theta, int32_t j,
+                                double* u, double* u1, double* u2);
+
+/* Checkpoint interval (steps) for the gradient / HVP paths: 0 stores every step's
+ * eigen-data; k > 0 keeps only states every k steps and recomputes one segment's
+ * eigen-data at a time in the backward sweep (the memory reduction the paper names as
+ * future work, Sec. V). */
+qoc_status qoc_set_checkpoint_interval(qoc_problem* p, int32_t steps);
+/* Device bytes currently held by the handle's workspaces, and the high-water mark. */
+qoc_status qoc_memory_usage(const qoc_problem* p, int64_t* current_bytes, int64_t* peak_bytes);
+
+/* Exact-Hessian trust-region solve (Alg. 2 lines 27-28 with a Newton trust-region step):
+ * from theta0 iterate until ||grad||_2 < gtol or max_iter.  theta_out: P doubles;
+ * cost_out, iters_out may be NULL.  Returns QOC_ERR_NOT_CONVERGED (outputs written) when
+ * max_iter is reached. */
+qoc_status qoc_tr_solve(qoc_problem* p, const double* theta0, double gtol, int32_t max_iter,
+                        double* theta_out, double* cost_out, int32_t* iters_out);
+
+/* Batched evaluation of independent problems of uneven (n, nt, P) in one persistent launch
+ * sequence (captured as a HIP graph on first use).  problems: `count` configured handles on
+ * the same device; the batch copies their systems and bases. */
+qoc_status qoc_batch_create(int device, int32_t count, qoc_problem* const* problems, qoc_batch** out);
+void       qoc_batch_destroy(qoc_batch* b);
+/* thetas[i], costs[i], grads[i], hessians[i]: host pointers for problem i (outputs may be NULL). */
+qoc_status qoc_batch_hess(qoc_batch* b, const double* const* thetas, double* const* costs,
+                          double* const* grads, double* const* hessians);
+/* Same work as separate per-problem launches (the reference point of the batched path). */
+qoc_status qoc_batch_hess_unbatched(qoc_batch* b, const double* const* thetas, double* const* costs,
+                                    double* const* grads, double* const* hessians);
+const char* qoc_batch_last_error(const qoc_batch* b);
+
+/* Static strings; never NULL. */
+const char* qoc_status_string(qoc_status s);
+const char* qoc_last_error(const qoc_problem* p);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QOC_H */

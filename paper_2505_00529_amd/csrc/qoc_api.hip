@@ -1,0 +1,621 @@
+// C ABI of the library: handles, validation, workspaces and the host / device entry points.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/qoc.h"
+#include "qoc_api_internal.h"
+#include "qoc_internal.h"
+
+using namespace qoc;
+
+namespace {
+
+constexpr double kJacobiTol = 1e-15;   // off-diagonal target relative to ||H_j||_F
+constexpr int kJacobiMaxSweeps = 40;
+
+std::mutex g_cfg_mu;
+bool g_cfg_done[64] = {false};
+
+const char* status_text(qoc_status s) {
+  switch (s) {
+    case QOC_OK: return "ok";
+    case QOC_ERR_INVALID_ARG: return "invalid argument";
+    case QOC_ERR_NOT_SYMMETRIC: return "matrix not symmetric";
+    case QOC_ERR_STATE: return "system or control basis not set";
+    case QOC_ERR_UNSUPPORTED: return "unsupported size";
+    case QOC_ERR_NOCONV: return "Jacobi eigensolver did not converge";
+    case QOC_ERR_DEVICE: return "HIP device error";
+    case QOC_ERR_OOM: return "device out of memory";
+    case QOC_ERR_NOT_CONVERGED: return "trust-region solve reached max_iter";
+    default: return "unknown status";
+  }
+}
+
+bool all_finite(const double* x, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(x[i])) return false;
+  return true;
+}
+
+}  // namespace
+
+qoc_status qoc_problem::fail(qoc_status s, const std::string& msg) {
+  err = msg.empty() ? std::string(status_text(s)) : msg;
+  return s;
+}
+
+qoc_status qoc_problem::hip_fail(hipError_t e, const char* what) {
+  std::string m = std::string(what) + ": " + hipGetErrorString(e);
+  return fail(e == hipErrorOutOfMemory ? QOC_ERR_OOM : QOC_ERR_DEVICE, m);
+}
+
+qoc_status qoc_problem::dmalloc(void** ptr, size_t bytes, const char* what) {
+  hipError_t e = hipMalloc(ptr, bytes == 0 ? 8 : bytes);
+  if (e != hipSuccess) {
+    *ptr = nullptr;
+    (void)hipGetLastError();
+    return hip_fail(e, what);
+  }
+  cur_bytes += (int64_t)bytes;
+  peak_bytes = std::max(peak_bytes, cur_bytes);
+  return QOC_OK;
+}
+
+void qoc_problem::dfree(void* ptr, size_t bytes) {
+  if (ptr) {
+    (void)hipFree(ptr);
+    cur_bytes -= (int64_t)bytes;
+  }
+}
+
+void qoc_problem::release_work() {
+  dfree(work_mem, work_bytes);
+  work_mem = nullptr;
+  work_bytes = 0;
+  w = Work();
+  work_key_nb = 0;
+}
+
+qoc_problem::~qoc_problem() {
+  if (device >= 0) (void)hipSetDevice(device);
+  release_work();
+  dfree(d_h0, sizeof(double) * n * n);
+  dfree(d_m, sizeof(double) * n * n);
+  dfree(d_psi0, sizeof(double) * 2 * n);
+  dfree(d_psit, sizeof(double) * 2 * n);
+  dfree(d_B, b_bytes);
+  dfree(d_io, io_bytes);
+  dfree(d_status, sizeof(int));
+  dfree(d_props, props_bytes);
+  if (own_stream && stream) (void)hipStreamDestroy(stream);
+}
+
+// Lay out (and if needed grow) one evaluation workspace for nb thetas.
+qoc_status qoc_problem::ensure_work(int nb) {
+  const int np = pad_even(n);
+  int nchunks_target = std::max(1, (2048 + nb - 1) / nb);
+  int chunk = std::max(8, (nt + nchunks_target - 1) / nchunks_target);
+  int nchunks = (nt + chunk - 1) / chunk;
+  if (work_mem && work_key_nb == nb && w.n == n && w.nt == nt && w.P == P && w.chunk == chunk) return QOC_OK;
+  release_work();
+  const size_t ntn = (size_t)nt * n, nn = (size_t)n * n;
+  struct Item {
+    void** ptr;
+    size_t bytes;
+  };
+  Work nw;
+  nw.n = n;
+  nw.np = np;
+  nw.nt = nt;
+  nw.P = P;
+  nw.nb = nb;
+  nw.nchunks = nchunks;
+  nw.chunk = chunk;
+  const size_t B8 = sizeof(double), B16 = sizeof(double2);
+  std::vector<Item> items = {
+      {(void**)&nw.f, B8 * nb * nt},
+      {(void**)&nw.u, B8 * nb * nt},
+      {(void**)&nw.lam, B8 * nb * ntn},
+      {(void**)&nw.mt, B8 * nb * nt * nn},
+      {(void**)&nw.sm, B8 * nb * nt * nn},
+      {(void**)&nw.ov, B8 * nb * nt * nn},
+      {(void**)&nw.vfirst, B8 * nb * nchunks * nn},
+      {(void**)&nw.vlast, B8 * nb * nchunks * nn},
+      {(void**)&nw.gscratch, B8 * eig_scratch_doubles(n, nb, nchunks)},
+      {(void**)&nw.at, B16 * nb * ntn},
+      {(void**)&nw.yt, B16 * nb * ntn},
+      {(void**)&nw.mu, B16 * nb * ntn},
+      {(void**)&nw.ah, B16 * nb * ntn},
+      {(void**)&nw.s, B8 * nb * nt},
+      {(void**)&nw.q, B8 * nb * nt},
+      {(void**)&nw.e, B8 * nb * nt},
+      {(void**)&nw.K, B8 * nb * nt * P},
+      {(void**)&nw.xf, B16 * nb * n * (1 + P)},
+      {(void**)&nw.binit, B16 * nb * n * 2},
+      {(void**)&nw.rr, B8 * nb},
+      {(void**)&nw.aa, B8 * nb * P * P},
+  };
+  size_t total = 0;
+  for (auto& it : items) total += (it.bytes + 255) & ~(size_t)255;
+  void* mem = nullptr;
+  qoc_status st = dmalloc(&mem, total, "workspace allocation");
+  if (st != QOC_OK) return st;
+  char* cur = (char*)mem;
+  for (auto& it : items) {
+    *it.ptr = it.bytes ? (void*)cur : nullptr;
+    cur += (it.bytes + 255) & ~(size_t)255;
+  }
+  nw.status = d_status;
+  w = nw;
+  work_mem = mem;
+  work_bytes = total;
+  work_key_nb = nb;
+  return QOC_OK;
+}
+
+// Staging area for host-pointer calls: thetas, directions and outputs.
+qoc_status qoc_problem::ensure_io(size_t doubles) {
+  const size_t bytes = doubles * sizeof(double);
+  if (d_io && io_bytes >= bytes) return QOC_OK;
+  dfree(d_io, io_bytes);
+  d_io = nullptr;
+  io_bytes = 0;
+  qoc_status st = dmalloc((void**)&d_io, bytes, "staging allocation");
+  if (st == QOC_OK) io_bytes = bytes;
+  return st;
+}
+
+qoc_status qoc_problem::ready() {
+  if (!has_system || !has_basis) return fail(QOC_ERR_STATE, "set_system and set_control_basis must be called first");
+  hipError_t e = hipSetDevice(device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  return QOC_OK;
+}
+
+// Enqueue one evaluation of `nb` thetas (device pointers) on the handle's stream.
+qoc_status qoc_problem::enqueue(Mode mode, int nb, const double* d_theta, const double* d_v, double* d_cost,
+                                double* d_grad, double* d_out) {
+  qoc_status st = ensure_work(nb);
+  if (st != QOC_OK) return st;
+  SysDev sy;
+  sy.n = n;
+  sy.h0 = d_h0;
+  sy.m = d_m;
+  sy.psi0 = d_psi0;
+  sy.psit = d_psit;
+  BasisDev bs;
+  bs.nt = nt;
+  bs.P = P;
+  bs.dt = dt;
+  bs.B = d_B;
+  hipError_t e;
+#define QOC_LAUNCH(call)                                  \
+  do {                                                    \
+    e = (call);                                           \
+    if (e != hipSuccess) return hip_fail(e, #call);       \
+  } while (0)
+  QOC_LAUNCH(launch_controls(bs, d_theta, w.f, nb, stream));
+  if (mode == Mode::Hvp) QOC_LAUNCH(launch_controls(bs, d_v, w.u, nb, stream));
+  QOC_LAUNCH(launch_eig(sy, bs, w, mode != Mode::Cost, kJacobiTol, jacobi_max_sweeps, stream));
+  QOC_LAUNCH(launch_forward(sy, bs, w, mode, stream));
+  QOC_LAUNCH(launch_terminal(sy, bs, w, mode, rho, stream));
+  if (mode != Mode::Cost) QOC_LAUNCH(launch_backward(sy, bs, w, mode, stream));
+  if (mode == Mode::Hess || mode == Mode::Hvp) QOC_LAUNCH(launch_sterm(sy, bs, w, stream));
+  QOC_LAUNCH(launch_assemble(bs, w, mode, gamma, rho, d_cost, d_grad, d_out, stream));
+#undef QOC_LAUNCH
+  return QOC_OK;
+}
+
+qoc_status qoc_problem::check_device_status() {
+  int hs = 0;
+  hipError_t e = hipMemcpyAsync(&hs, d_status, sizeof(int), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return hip_fail(e, "status readback");
+  if (hs != 0) {
+    e = hipMemsetAsync(d_status, 0, sizeof(int), stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (hs & kStatusNoConv) return fail(QOC_ERR_NOCONV, "Jacobi sweep cap reached on at least one step");
+  }
+  return QOC_OK;
+}
+
+// Host-pointer evaluation of `count` thetas: stage, enqueue, copy back, synchronise.
+qoc_status qoc_problem::run_host(Mode mode, int count, const double* theta, const double* v, double* cost,
+                                 double* grad, double* out) {
+  qoc_status st = ready();
+  if (st != QOC_OK) return st;
+  if (count < 1 || !theta) return fail(QOC_ERR_INVALID_ARG, "theta must be non-NULL and count >= 1");
+  if (!all_finite(theta, (size_t)count * P)) return fail(QOC_ERR_INVALID_ARG, "theta has non-finite entries");
+  if (mode == Mode::Hvp) {
+    if (!v) return fail(QOC_ERR_INVALID_ARG, "v must be non-NULL");
+    if (!all_finite(v, (size_t)count * P)) return fail(QOC_ERR_INVALID_ARG, "v has non-finite entries");
+  }
+  const size_t nth = (size_t)count * P;
+  const size_t nout = mode == Mode::Hess ? (size_t)count * P * P : (mode == Mode::Hvp ? nth : 0);
+  st = ensure_io(2 * nth + count + nth + nout);
+  if (st != QOC_OK) return st;
+  double* d_th = d_io;
+  double* d_vv = d_th + nth;
+  double* d_c = d_vv + nth;
+  double* d_g = d_c + count;
+  double* d_o = d_g + nth;
+  hipError_t e = hipMemcpyAsync(d_th, theta, nth * sizeof(double), hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess && mode == Mode::Hvp)
+    e = hipMemcpyAsync(d_vv, v, nth * sizeof(double), hipMemcpyHostToDevice, stream);
+  if (e != hipSuccess) return hip_fail(e, "input upload");
+  st = enqueue(mode, count, d_th, d_vv, d_c, mode == Mode::Cost ? nullptr : d_g, nout ? d_o : nullptr);
+  if (st != QOC_OK) return st;
+  std::vector<double> hc(count), hg(mode == Mode::Cost ? 0 : nth), ho(nout);
+  e = hipMemcpyAsync(hc.data(), d_c, count * sizeof(double), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess && !hg.empty())
+    e = hipMemcpyAsync(hg.data(), d_g, nth * sizeof(double), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess && nout) e = hipMemcpyAsync(ho.data(), d_o, nout * sizeof(double), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return hip_fail(e, "result download");
+  st = check_device_status();
+  if (st != QOC_OK) return st;
+  if (cost) std::memcpy(cost, hc.data(), count * sizeof(double));
+  if (grad && !hg.empty()) std::memcpy(grad, hg.data(), nth * sizeof(double));
+  if (out && nout) std::memcpy(out, ho.data(), nout * sizeof(double));
+  return QOC_OK;
+}
+
+// ------------------------------------------------------------------------ C ABI
+
+extern "C" {
+
+const char* qoc_status_string(qoc_status s) { return status_text(s); }
+
+const char* qoc_last_error(const qoc_problem* p) {
+  if (!p) return "NULL handle";
+  return p->err.c_str();
+}
+
+qoc_status qoc_create(int device, void* hip_stream, qoc_problem** out) {
+  if (!out) return QOC_ERR_INVALID_ARG;
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return QOC_ERR_DEVICE;
+  }
+  if (device < 0 || device >= ndev) return QOC_ERR_INVALID_ARG;
+  e = hipSetDevice(device);
+  if (e != hipSuccess) return QOC_ERR_DEVICE;
+  {
+    std::lock_guard<std::mutex> lk(g_cfg_mu);
+    if (device < 64 && !g_cfg_done[device]) {
+      e = configure_kernels();
+      if (e != hipSuccess) return QOC_ERR_DEVICE;
+      g_cfg_done[device] = true;
+    }
+  }
+  qoc_problem* p = new (std::nothrow) qoc_problem();
+  if (!p) return QOC_ERR_OOM;
+  p->device = device;
+  if (hip_stream) {
+    p->stream = (hipStream_t)hip_stream;
+    p->own_stream = false;
+  } else {
+    e = hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      delete p;
+      return QOC_ERR_DEVICE;
+    }
+    p->own_stream = true;
+  }
+  if (p->dmalloc((void**)&p->d_status, sizeof(int), "status word") != QOC_OK ||
+      hipMemsetAsync(p->d_status, 0, sizeof(int), p->stream) != hipSuccess ||
+      hipStreamSynchronize(p->stream) != hipSuccess) {
+    delete p;
+    return QOC_ERR_DEVICE;
+  }
+  *out = p;
+  return QOC_OK;
+}
+
+void qoc_destroy(qoc_problem* p) { delete p; }
+
+qoc_status qoc_set_stream(qoc_problem* p, void* hip_stream) {
+  if (!p) return QOC_ERR_INVALID_ARG;
+  hipError_t e = hipStreamSynchronize(p->stream);
+  if (e != hipSuccess) return p->hip_fail(e, "stream switch");
+  if (p->own_stream) {
+    (void)hipStreamDestroy(p->stream);
+    p->own_stream = false;
+    p->stream = nullptr;
+  }
+  if (hip_stream) {
+    p->stream = (hipStream_t)hip_stream;
+  } else {
+    e = hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return p->hip_fail(e, "stream create");
+    p->own_stream = true;
+  }
+  return QOC_OK;
+}
+
+qoc_status qoc_set_system(qoc_problem* p, int32_t n, const double* h0, const double* m, const double* psi0,
+                          const double* psi_target) {
+  if (!p) return QOC_ERR_INVALID_ARG;
+  if (!h0 || !m || !psi0 || !psi_target) return p->fail(QOC_ERR_INVALID_ARG, "NULL system pointer");
+  if (n < 1) return p->fail(QOC_ERR_INVALID_ARG, "n must be >= 1");
+  if (n > kMaxN) return p->fail(QOC_ERR_UNSUPPORTED, "n above the build limit (128)");
+  const size_t nn = (size_t)n * n;
+  if (!all_finite(h0, nn) || !all_finite(m, nn) || !all_finite(psi0, 2 * (size_t)n) ||
+      !all_finite(psi_target, 2 * (size_t)n))
+    return p->fail(QOC_ERR_INVALID_ARG, "non-finite system entry");
+  for (const double* x : {h0, m}) {
+    double nrm = 0.0, asym = 0.0;
+    for (size_t i = 0; i < nn; ++i) nrm += x[i] * x[i];
+    for (int i = 0; i < n; ++i)
+      for (int k = i + 1; k < n; ++k) {
+        const double d = x[i * n + k] - x[k * n + i];
+        asym += 2 * d * d;
+      }
+    if (std::sqrt(asym) > 1e-12 * std::sqrt(nrm))
+      return p->fail(QOC_ERR_NOT_SYMMETRIC, x == h0 ? "H0 is not symmetric" : "M is not symmetric");
+  }
+  hipError_t e = hipSetDevice(p->device);
+  if (e != hipSuccess) return p->hip_fail(e, "hipSetDevice");
+  p->release_work();
+  p->dfree(p->d_h0, sizeof(double) * p->n * p->n);
+  p->dfree(p->d_m, sizeof(double) * p->n * p->n);
+  p->dfree(p->d_psi0, sizeof(double) * 2 * p->n);
+  p->dfree(p->d_psit, sizeof(double) * 2 * p->n);
+  p->d_h0 = p->d_m = p->d_psi0 = p->d_psit = nullptr;
+  p->has_system = false;
+  qoc_status st;
+  if ((st = p->dmalloc((void**)&p->d_h0, sizeof(double) * nn, "H0")) != QOC_OK) return st;
+  if ((st = p->dmalloc((void**)&p->d_m, sizeof(double) * nn, "M")) != QOC_OK) return st;
+  if ((st = p->dmalloc((void**)&p->d_psi0, sizeof(double) * 2 * n, "psi0")) != QOC_OK) return st;
+  if ((st = p->dmalloc((void**)&p->d_psit, sizeof(double) * 2 * n, "psi_target")) != QOC_OK) return st;
+  p->n = n;
+  // symmetrise exactly (the check above allows 1e-12 relative asymmetry)
+  std::vector<double> hs(nn), ms(nn);
+  for (int i = 0; i < n; ++i)
+    for (int k = 0; k < n; ++k) {
+      hs[i * n + k] = 0.5 * (h0[i * n + k] + h0[k * n + i]);
+      ms[i * n + k] = 0.5 * (m[i * n + k] + m[k * n + i]);
+    }
+  e = hipMemcpyAsync(p->d_h0, hs.data(), sizeof(double) * nn, hipMemcpyHostToDevice, p->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(p->d_m, ms.data(), sizeof(double) * nn, hipMemcpyHostToDevice, p->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(p->d_psi0, psi0, sizeof(double) * 2 * n, hipMemcpyHostToDevice, p->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(p->d_psit, psi_target, sizeof(double) * 2 * n, hipMemcpyHostToDevice, p->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+  if (e != hipSuccess) return p->hip_fail(e, "system upload");
+  p->h_m.assign(ms.begin(), ms.end());
+  p->h_h0.assign(hs.begin(), hs.end());
+  p->h_psi0.assign(psi0, psi0 + 2 * n);
+  p->h_psit.assign(psi_target, psi_target + 2 * n);
+  p->has_system = true;
+  return QOC_OK;
+}
+
+qoc_status qoc_set_target(qoc_problem* p, const double* psi_target) {
+  if (!p) return QOC_ERR_INVALID_ARG;
+  if (!p->has_system) return p->fail(QOC_ERR_STATE, "set_system first");
+  if (!psi_target) return p->fail(QOC_ERR_INVALID_ARG, "NULL target");
+  if (!all_finite(psi_target, 2 * (size_t)p->n)) return p->fail(QOC_ERR_INVALID_ARG, "non-finite target");
+  hipError_t e = hipMemcpyAsync(p->d_psit, psi_target, sizeof(double) * 2 * p->n, hipMemcpyHostToDevice, p->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+  if (e != hipSuccess) return p->hip_fail(e, "target upload");
+  p->h_psit.assign(psi_target, psi_target + 2 * p->n);
+  return QOC_OK;
+}
+
+qoc_status qoc_set_control_basis(qoc_problem* p, qoc_basis_kind kind, int32_t nt, double dt, int32_t k_or_p,
+                                 const double* b) {
+  if (!p) return QOC_ERR_INVALID_ARG;
+  if (nt < 1) return p->fail(QOC_ERR_INVALID_ARG, "nt must be >= 1");
+  if (!std::isfinite(dt) || dt <= 0.0) return p->fail(QOC_ERR_INVALID_ARG, "dt must be finite and > 0");
+  int P = 0;
+  switch (kind) {
+    case QOC_BASIS_FOURIER:
+      if (k_or_p < 1) return p->fail(QOC_ERR_INVALID_ARG, "Fourier basis needs K >= 1");
+      P = 2 * k_or_p;
+      break;
+    case QOC_BASIS_IDENTITY:
+      P = nt;
+      break;
+    case QOC_BASIS_DENSE:
+      if (k_or_p < 1) return p->fail(QOC_ERR_INVALID_ARG, "dense basis needs P >= 1");
+      if (!b) return p->fail(QOC_ERR_INVALID_ARG, "dense basis needs b");
+      P = k_or_p;
+      if (!all_finite(b, (size_t)nt * P)) return p->fail(QOC_ERR_INVALID_ARG, "non-finite basis entry");
+      break;
+    default:
+      return p->fail(QOC_ERR_INVALID_ARG, "unknown basis kind");
+  }
+  if (P > kMaxP) return p->fail(QOC_ERR_UNSUPPORTED, "P above the build limit (4096)");
+  hipError_t e = hipSetDevice(p->device);
+  if (e != hipSuccess) return p->hip_fail(e, "hipSetDevice");
+  p->release_work();
+  p->dfree(p->d_B, p->b_bytes);
+  p->d_B = nullptr;
+  p->b_bytes = 0;
+  p->has_basis = false;
+  const size_t bytes = sizeof(double) * (size_t)nt * P;
+  qoc_status st = p->dmalloc((void**)&p->d_B, bytes, "basis");
+  if (st != QOC_OK) return st;
+  p->b_bytes = bytes;
+  if (kind == QOC_BASIS_FOURIER) e = launch_fourier_basis(p->d_B, nt, k_or_p, p->stream);
+  else if (kind == QOC_BASIS_IDENTITY) e = launch_identity_basis(p->d_B, nt, p->stream);
+  else e = hipMemcpyAsync(p->d_B, b, bytes, hipMemcpyHostToDevice, p->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+  if (e != hipSuccess) return p->hip_fail(e, "basis setup");
+  p->nt = nt;
+  p->dt = dt;
+  p->P = P;
+  p->kind = kind;
+  if (!p->weights_explicit) {
+    p->gamma = 2.0 * dt;
+    p->rho = 2.0;
+  }
+  p->has_basis = true;
+  return QOC_OK;
+}
+
+qoc_status qoc_set_weights(qoc_problem* p, double gamma, double rho) {
+  if (!p) return QOC_ERR_INVALID_ARG;
+  if (!std::isfinite(gamma) || !std::isfinite(rho) || gamma < 0 || rho < 0)
+    return p->fail(QOC_ERR_INVALID_ARG, "weights must be finite and >= 0");
+  p->gamma = gamma;
+  p->rho = rho;
+  p->weights_explicit = true;
+  return QOC_OK;
+}
+
+qoc_status qoc_get_num_params(const qoc_problem* p, int32_t* num_params) {
+  if (!p || !num_params) return QOC_ERR_INVALID_ARG;
+  if (!p->has_basis) return QOC_ERR_STATE;
+  *num_params = p->P;
+  return QOC_OK;
+}
+
+qoc_status qoc_cost(qoc_problem* p, const double* theta, double* cost) {
+  if (!p) return QOC_ERR_INVALID_ARG;
+  if (!cost) return p->fail(QOC_ERR_INVALID_ARG, "NULL cost");
+  return p->run_host(Mode::Cost, 1, theta, nullptr, cost, nullptr, nullptr);
+}
+
+qoc_status qoc_grad(qoc_problem* p, const double* theta, double* cost, double* grad) {
+  if (!p) return QOC_ERR_INVALID_ARG;
+  if (!grad) return p->fail(QOC_ERR_INVALID_ARG, "NULL grad");
+  return p->run_host(Mode::Grad, 1, theta, nullptr, cost, grad, nullptr);
+}
+
+qoc_status qoc_hess(qoc_problem* p, const double* theta, double* cost, double* grad, double* hess) {
+  if (!p) return QOC_ERR_INVALID_ARG;
+  if (!hess) return p->fail(QOC_ERR_INVALID_ARG, "NULL hess");
+  return p->run_host(Mode::Hess, 1, theta, nullptr, cost, grad, hess);
+}
+
+qoc_status qoc_hvp(qoc_problem* p, const double* theta, const double* v, double* hv, double* grad) {
+  if (!p) return QOC_ERR_INVALID_ARG;
+  if (!hv) return p->fail(QOC_ERR_INVALID_ARG, "NULL hv");
+  return p->run_host(Mode::Hvp, 1, theta, v, nullptr, grad, hv);
+}
+
+qoc_status qoc_hess_many(qoc_problem* p, int32_t count, const double* thetas, double* costs, double* grads,
+                         double* hess) {
+  if (!p) return QOC_ERR_INVALID_ARG;
+  return p->run_host(Mode::Hess, count, thetas, nullptr, costs, grads, hess);
+}
+
+qoc_status qoc_grad_many(qoc_problem* p, int32_t count, const double* thetas, double* costs, double* grads) {
+  if (!p) return QOC_ERR_INVALID_ARG;
+  return p->run_host(Mode::Grad, count, thetas, nullptr, costs, grads, nullptr);
+}
+
+static qoc_status run_dev(qoc_problem* p, Mode mode, int count, const double* theta, const double* v, double* cost,
+                          double* grad, double* out) {
+  if (!p) return QOC_ERR_INVALID_ARG;
+  qoc_status st = p->ready();
+  if (st != QOC_OK) return st;
+  if (count < 1 || !theta) return p->fail(QOC_ERR_INVALID_ARG, "theta must be non-NULL and count >= 1");
+  if (mode == Mode::Hvp && !v) return p->fail(QOC_ERR_INVALID_ARG, "v must be non-NULL");
+  return p->enqueue(mode, count, theta, v, cost, grad, out);
+}
+
+qoc_status qoc_cost_dev(qoc_problem* p, const double* theta, double* cost) {
+  return run_dev(p, Mode::Cost, 1, theta, nullptr, cost, nullptr, nullptr);
+}
+qoc_status qoc_grad_dev(qoc_problem* p, const double* theta, double* cost, double* grad) {
+  return run_dev(p, Mode::Grad, 1, theta, nullptr, cost, grad, nullptr);
+}
+qoc_status qoc_hess_dev(qoc_problem* p, const double* theta, double* cost, double* grad, double* hess) {
+  return run_dev(p, Mode::Hess, 1, theta, nullptr, cost, grad, hess);
+}
+qoc_status qoc_hvp_dev(qoc_problem* p, const double* theta, const double* v, double* hv, double* grad) {
+  return run_dev(p, Mode::Hvp, 1, theta, v, nullptr, grad, hv);
+}
+qoc_status qoc_hess_many_dev(qoc_problem* p, int32_t count, const double* thetas, double* costs, double* grads,
+                             double* hess) {
+  return run_dev(p, Mode::Hess, count, thetas, nullptr, costs, grads, hess);
+}
+
+qoc_status qoc_sync(qoc_problem* p) {
+  if (!p) return QOC_ERR_INVALID_ARG;
+  hipError_t e = hipStreamSynchronize(p->stream);
+  if (e != hipSuccess) return p->hip_fail(e, "stream synchronise");
+  return p->check_device_status();
+}
+
+qoc_status qoc_step_propagators(qoc_problem* p, const double* theta, int32_t j, double* u, double* u1, double* u2) {
+  if (!p) return QOC_ERR_INVALID_ARG;
+  qoc_status st = p->ready();
+  if (st != QOC_OK) return st;
+  if (!theta) return p->fail(QOC_ERR_INVALID_ARG, "NULL theta");
+  if (j < 0 || j >= p->nt) return p->fail(QOC_ERR_INVALID_ARG, "step index out of range");
+  st = p->ensure_work(1);
+  if (st != QOC_OK) return st;
+  st = p->ensure_io(p->P + 6 * (size_t)p->n * p->n);
+  if (st != QOC_OK) return st;
+  const size_t need = step_props_scratch_doubles(p->n) * sizeof(double);
+  if (!p->d_props || p->props_bytes < need) {
+    p->dfree(p->d_props, p->props_bytes);
+    p->d_props = nullptr;
+    p->props_bytes = 0;
+    st = p->dmalloc((void**)&p->d_props, need, "inspection scratch");
+    if (st != QOC_OK) return st;
+    p->props_bytes = need;
+  }
+  double* d_th = p->d_io;
+  double* d_u = d_th + p->P;
+  const size_t nn2 = 2 * (size_t)p->n * p->n;
+  hipError_t e = hipMemcpyAsync(d_th, theta, sizeof(double) * p->P, hipMemcpyHostToDevice, p->stream);
+  if (e != hipSuccess) return p->hip_fail(e, "theta upload");
+  BasisDev bs;
+  bs.nt = p->nt;
+  bs.P = p->P;
+  bs.dt = p->dt;
+  bs.B = p->d_B;
+  e = launch_controls(bs, d_th, p->w.f, 1, p->stream);
+  if (e != hipSuccess) return p->hip_fail(e, "controls");
+  double fj = 0.0;
+  e = hipMemcpyAsync(&fj, p->w.f + j, sizeof(double), hipMemcpyDeviceToHost, p->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+  if (e != hipSuccess) return p->hip_fail(e, "control readback");
+  SysDev sy;
+  sy.n = p->n;
+  sy.h0 = p->d_h0;
+  sy.m = p->d_m;
+  e = launch_step_props(sy, fj, p->dt, p->d_props, d_u, d_u + nn2, d_u + 2 * nn2, p->d_status, p->stream);
+  if (e != hipSuccess) return p->hip_fail(e, "step propagators");
+  std::vector<double> h(3 * nn2);
+  e = hipMemcpyAsync(h.data(), d_u, sizeof(double) * 3 * nn2, hipMemcpyDeviceToHost, p->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+  if (e != hipSuccess) return p->hip_fail(e, "propagator download");
+  st = p->check_device_status();
+  if (st != QOC_OK) return st;
+  if (u) std::memcpy(u, h.data(), sizeof(double) * nn2);
+  if (u1) std::memcpy(u1, h.data() + nn2, sizeof(double) * nn2);
+  if (u2) std::memcpy(u2, h.data() + 2 * nn2, sizeof(double) * nn2);
+  return QOC_OK;
+}
+
+qoc_status qoc_set_checkpoint_interval(qoc_problem* p, int32_t steps) {
+  if (!p) return QOC_ERR_INVALID_ARG;
+  if (steps < 0) return p->fail(QOC_ERR_INVALID_ARG, "interval must be >= 0");
+  p->ckpt = steps;
+  return QOC_OK;
+}
+
+qoc_status qoc_memory_usage(const qoc_problem* p, int64_t* current_bytes, int64_t* peak_bytes) {
+  if (!p) return QOC_ERR_INVALID_ARG;
+  if (current_bytes) *current_bytes = p->cur_bytes;
+  if (peak_bytes) *peak_bytes = p->peak_bytes;
+  return QOC_OK;
+}
+
+}  // extern "C"

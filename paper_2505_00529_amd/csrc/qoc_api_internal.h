@@ -1,0 +1,67 @@
+// Definition of the opaque handle behind the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/qoc.h"
+#include "qoc_internal.h"
+
+struct qoc_problem {
+  int device = -1;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+
+  // system (device copies, and host copies for solvers built on top)
+  int n = 0;
+  bool has_system = false;
+  double* d_h0 = nullptr;
+  double* d_m = nullptr;
+  double* d_psi0 = nullptr;
+  double* d_psit = nullptr;
+  std::vector<double> h_h0, h_m, h_psi0, h_psit;
+
+  // control model
+  int nt = 0, P = 0, kind = 0;
+  double dt = 0.0;
+  bool has_basis = false;
+  double* d_B = nullptr;
+  size_t b_bytes = 0;
+
+  double gamma = 0.0, rho = 2.0;
+  bool weights_explicit = false;
+  int ckpt = 0;
+  int jacobi_max_sweeps = 40;
+
+  // workspace
+  qoc::Work w;
+  void* work_mem = nullptr;
+  size_t work_bytes = 0;
+  int work_key_nb = 0;
+  double* d_io = nullptr;
+  size_t io_bytes = 0;
+  double* d_props = nullptr;
+  size_t props_bytes = 0;
+  int* d_status = nullptr;
+
+  std::string err;
+  int64_t cur_bytes = 0, peak_bytes = 0;
+
+  ~qoc_problem();
+  qoc_status fail(qoc_status s, const std::string& msg);
+  qoc_status hip_fail(hipError_t e, const char* what);
+  qoc_status dmalloc(void** ptr, size_t bytes, const char* what);
+  void dfree(void* ptr, size_t bytes);
+  void release_work();
+  qoc_status ensure_work(int nb);
+  qoc_status ensure_io(size_t doubles);
+  qoc_status ready();
+  qoc_status enqueue(qoc::Mode mode, int nb, const double* d_theta, const double* d_v, double* d_cost,
+                     double* d_grad, double* d_out);
+  qoc_status check_device_status();
+  qoc_status run_host(qoc::Mode mode, int count, const double* theta, const double* v, double* cost, double* grad,
+                      double* out);
+};

@@ -1,0 +1,296 @@
+// Device helpers: complex FP64 arithmetic, block reductions, divided differences of
+// phi(x) = exp(-i dt x), the parallel-order Jacobi eigensolver and small LDS GEMMs.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include "qoc_internal.h"
+
+namespace qoc {
+
+__device__ __forceinline__ double2 c_make(double re, double im) { return make_double2(re, im); }
+__device__ __forceinline__ double2 c_add(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 c_sub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 c_mul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 c_conj(double2 a) { return make_double2(a.x, -a.y); }
+__device__ __forceinline__ double2 c_scale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+// conj(a) * b
+__device__ __forceinline__ double2 c_cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+
+// exp(-i dt x)
+__device__ __forceinline__ double2 phase(double x, double dt) {
+  double s, c;
+  sincos(dt * x, &s, &c);
+  return make_double2(c, -s);
+}
+
+// sin(u)/u, accurate for all u (no cancellation for u != 0; series near 0).
+__device__ __forceinline__ double sinc(double u) {
+  if (fabs(u) < 1e-3) {
+    const double u2 = u * u;
+    return 1.0 - u2 * (1.0 / 6.0) + u2 * u2 * (1.0 / 120.0);
+  }
+  return sin(u) / u;
+}
+
+// First divided difference phi[x, y] of phi(t) = exp(-i dt t):
+//   phi[x, y] = -i dt exp(-i dt (x + y)/2) sinc(dt (x - y)/2),
+// an identity valid for every gap, confluent case (phi'(x)) included.
+__device__ __forceinline__ double2 dd1(double x, double y, double dt) {
+  const double2 h = phase(0.5 * (x + y), dt);
+  const double sc = dt * sinc(0.5 * dt * (x - y));
+  // -i * sc * h
+  return make_double2(sc * h.y, -sc * h.x);
+}
+
+// Second divided difference phi[x, y, z] of phi(t) = exp(-i dt t).
+// Wide spread: order the points a <= b <= c and use (phi[b,c] - phi[a,b]) / (c - a), whose
+// relative rounding error is about 2 eps / (dt (c - a)).  Narrow spread: the series about
+// the mean m,  phi[x,y,z] = exp(-i dt m) sum_{k>=2} (-i dt)^k / k! h_{k-2}(x-m, y-m, z-m),
+// with h_n the complete homogeneous symmetric polynomial (divided differences of u^k are
+// h_{k-2} of the nodes).
+__device__ __forceinline__ double2 dd2(double x, double y, double z, double dt) {
+  double a = fmin(x, fmin(y, z));
+  double c = fmax(x, fmax(y, z));
+  double b = fmax(fmin(x, y), fmin(fmax(x, y), z));
+  const double spread = dt * (c - a);
+  if (spread > 0.05) {
+    const double2 d1 = dd1(b, c, dt);
+    const double2 d0 = dd1(a, b, dt);
+    const double inv = 1.0 / (c - a);
+    return make_double2((d1.x - d0.x) * inv, (d1.y - d0.y) * inv);
+  }
+  const double m = (a + b + c) * (1.0 / 3.0);
+  const double da = dt * (a - m), db = dt * (b - m), dc = dt * (c - m);
+  const double dmax = fmax(fabs(da), fmax(fabs(db), fabs(dc)));
+  // h_n(da, db, dc) by h_n(x) = x^n, h_n(x,y) = h_n(x) + y h_{n-1}(x,y), h_n(x,y,z) = h_n(x,y) + z h_{n-1}(x,y,z).
+  // Truncate by the bound |h_n| <= C(n+2, 2) dmax^n (a term's own value can vanish, e.g. h_1 = 0
+  // for centred nodes, so it is not a stopping signal).
+  double hx = 1.0, hxy = 1.0, hxyz = 1.0;     // n = 0
+  double fact = 2.0;                           // k! for k = 2
+  double re = -0.5, im = 0.0;                  // k = 2 term: (-i)^2 / 2! * h_0
+  double dpow = 1.0;                           // dmax^(k-2)
+  for (int k = 3; k < 40; ++k) {
+    hx *= da;
+    hxy = hx + db * hxy;
+    hxyz = hxy + dc * hxyz;                    // h_{k-2}
+    fact *= (double)k;
+    dpow *= dmax;
+    const double t = hxyz / fact;
+    switch (k & 3) {                           // (-i)^k: k%4 = 0:1, 1:-i, 2:-1, 3:i
+      case 0: re += t; break;
+      case 1: im -= t; break;
+      case 2: re -= t; break;
+      default: im += t; break;
+    }
+    const double nn = (double)(k - 2);
+    if (0.5 * (nn + 2.0) * (nn + 3.0) * dpow * dmax / (fact * (double)(k + 1)) < 1e-18) break;
+  }
+  const double2 e = phase(m, dt);
+  const double dt2 = dt * dt;
+  return make_double2(dt2 * (e.x * re - e.y * im), dt2 * (e.x * im + e.y * re));
+}
+
+// Workgroup reductions (kThreads threads; red has kThreads doubles of LDS).
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  const int t = threadIdx.x;
+  red[t] = v;
+  __syncthreads();
+  for (int s = kThreads / 2; s > 0; s >>= 1) {
+    if (t < s) red[t] += red[t + s];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+__device__ __forceinline__ double block_max(double v, double* red) {
+  const int t = threadIdx.x;
+  red[t] = v;
+  __syncthreads();
+  for (int s = kThreads / 2; s > 0; s >>= 1) {
+    if (t < s) red[t] = fmax(red[t], red[t + s]);
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// Round-robin ("circle") pairing of np players (np even) in round r of np-1: player np-1
+// meets r; the others pair as (r+k, r-k) mod (np-1).  Every unordered pair meets once per
+// sweep.  Returns the pair ordered p < q.
+__device__ __forceinline__ void rr_pair(int r, int k, int np, int& p, int& q) {
+  const int m = np - 1;
+  int a, b;
+  if (k == 0) {
+    a = m;
+    b = r;
+  } else {
+    a = (r + k) % m;
+    b = (r - k + m) % m;
+  }
+  p = a < b ? a : b;
+  q = a < b ? b : a;
+}
+
+// Parallel-order cyclic Jacobi on the symmetric np x np matrix A (row-major, stride np),
+// accumulating rotations into V (V <- V J).  All np/2 disjoint rotations of a round are
+// computed from the same A and applied together as A <- J^T A J.  Sweeps stop once every
+// off-diagonal |A_pq| <= tol_abs; returns false if max_sweeps sweeps did not get there.
+// rot: np doubles of LDS, prs: np ints of LDS, red: kThreads doubles of LDS.
+__device__ bool jacobi_eig(double* A, double* V, int np, double tol_abs, int max_sweeps,
+                           double* rot, int* prs, double* red, int* sweeps_done) {
+  const int tid = threadIdx.x;
+  const int half = np / 2;
+  const int nblk = half * (half + 1) / 2;
+  for (int sweep = 0;; ++sweep) {
+    double loc = 0.0;
+    for (int idx = tid; idx < np * np; idx += kThreads) {
+      const int i = idx / np, k = idx - i * np;
+      if (i < k) loc = fmax(loc, fabs(A[idx]));
+    }
+    const double off = block_max(loc, red);
+    if (off <= tol_abs) {
+      if (sweeps_done) *sweeps_done = sweep;
+      return true;
+    }
+    if (sweep >= max_sweeps) {
+      if (sweeps_done) *sweeps_done = sweep;
+      return false;
+    }
+    for (int r = 0; r < np - 1; ++r) {
+      if (tid < half) {
+        int p, q;
+        rr_pair(r, tid, np, p, q);
+        const double app = A[p * np + p], aqq = A[q * np + q], apq = A[p * np + q];
+        double c = 1.0, s = 0.0;
+        if (apq != 0.0) {
+          // symmetric Schur decomposition of [[app, apq], [apq, aqq]]
+          const double tau = (aqq - app) / (2.0 * apq);
+          double t;
+          if (fabs(tau) > 1e150) {
+            t = 0.5 / tau;
+          } else {
+            t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+          }
+          c = 1.0 / sqrt(1.0 + t * t);
+          s = t * c;
+        }
+        rot[2 * tid] = c;
+        rot[2 * tid + 1] = s;
+        prs[2 * tid] = p;
+        prs[2 * tid + 1] = q;
+      }
+      __syncthreads();
+      // A <- J^T A J on 2x2 blocks (I, K), I <= K; block (K, I) is the transpose.
+      for (int w = tid; w < nblk; w += kThreads) {
+        // triangular decode of w into (I, K), I <= K
+        int I = (int)((2.0 * half + 1.0 - sqrt((2.0 * half + 1.0) * (2.0 * half + 1.0) - 8.0 * w)) * 0.5);
+        if (I < 0) I = 0;
+        while (I > 0 && I * half - I * (I - 1) / 2 > w) --I;
+        while ((I + 1) * half - (I + 1) * I / 2 <= w) ++I;
+        const int K = I + (w - (I * half - I * (I - 1) / 2));
+        const int pI = prs[2 * I], qI = prs[2 * I + 1];
+        const int pK = prs[2 * K], qK = prs[2 * K + 1];
+        const double cI = rot[2 * I], sI = rot[2 * I + 1];
+        const double cK = rot[2 * K], sK = rot[2 * K + 1];
+        const double a00 = A[pI * np + pK], a01 = A[pI * np + qK];
+        const double a10 = A[qI * np + pK], a11 = A[qI * np + qK];
+        // T = A_IK R_K,  R = [[c, s], [-s, c]]
+        const double t00 = a00 * cK - a01 * sK, t01 = a00 * sK + a01 * cK;
+        const double t10 = a10 * cK - a11 * sK, t11 = a10 * sK + a11 * cK;
+        // R_I^T T
+        double b00 = cI * t00 - sI * t10, b01 = cI * t01 - sI * t11;
+        double b10 = sI * t00 + cI * t10, b11 = sI * t01 + cI * t11;
+        if (I == K) {
+          b01 = 0.0;
+          b10 = 0.0;
+          A[pI * np + pI] = b00;
+          A[pI * np + qI] = 0.0;
+          A[qI * np + pI] = 0.0;
+          A[qI * np + qI] = b11;
+        } else {
+          A[pI * np + pK] = b00;
+          A[pI * np + qK] = b01;
+          A[qI * np + pK] = b10;
+          A[qI * np + qK] = b11;
+          A[pK * np + pI] = b00;
+          A[qK * np + pI] = b01;
+          A[pK * np + qI] = b10;
+          A[qK * np + qI] = b11;
+        }
+      }
+      // V <- V J on column pairs
+      for (int w = tid; w < np * half; w += kThreads) {
+        const int i = w / half, K = w - i * half;
+        const int p = prs[2 * K], q = prs[2 * K + 1];
+        const double c = rot[2 * K], s = rot[2 * K + 1];
+        const double vp = V[i * np + p], vq = V[i * np + q];
+        V[i * np + p] = c * vp - s * vq;
+        V[i * np + q] = s * vp + c * vq;
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// C = op(A) * B for np x np matrices (row-major, stride np), op(A) = A or A^T.
+// 2x2 register tiles per thread.  Caller synchronises before reading C.
+template <bool TRANS_A>
+__device__ void gemm_sq(const double* A, const double* B, double* C, int np) {
+  const int nt2 = np / 2;
+  for (int w = threadIdx.x; w < nt2 * nt2; w += kThreads) {
+    const int ti = w / nt2, tj = w - ti * nt2;
+    const int i0 = 2 * ti, j0 = 2 * tj;
+    double c00 = 0, c01 = 0, c10 = 0, c11 = 0;
+    for (int k = 0; k < np; ++k) {
+      double a0, a1;
+      if (TRANS_A) {
+        a0 = A[k * np + i0];
+        a1 = A[k * np + i0 + 1];
+      } else {
+        a0 = A[i0 * np + k];
+        a1 = A[(i0 + 1) * np + k];
+      }
+      const double b0 = B[k * np + j0], b1 = B[k * np + j0 + 1];
+      c00 = fma(a0, b0, c00);
+      c01 = fma(a0, b1, c01);
+      c10 = fma(a1, b0, c10);
+      c11 = fma(a1, b1, c11);
+    }
+    C[i0 * np + j0] = c00;
+    C[i0 * np + j0 + 1] = c01;
+    C[(i0 + 1) * np + j0] = c10;
+    C[(i0 + 1) * np + j0 + 1] = c11;
+  }
+}
+
+// C = Mg * B where Mg is the n x n global matrix (stride n) zero-padded to np x np.
+__device__ void gemm_global_left(const double* Mg, int n, const double* B, double* C, int np) {
+  const int nt2 = np / 2;
+  for (int w = threadIdx.x; w < nt2 * nt2; w += kThreads) {
+    const int ti = w / nt2, tj = w - ti * nt2;
+    const int i0 = 2 * ti, j0 = 2 * tj;
+    double c00 = 0, c01 = 0, c10 = 0, c11 = 0;
+    for (int k = 0; k < n; ++k) {
+      const double a0 = i0 < n ? Mg[i0 * n + k] : 0.0;
+      const double a1 = i0 + 1 < n ? Mg[(i0 + 1) * n + k] : 0.0;
+      const double b0 = B[k * np + j0], b1 = B[k * np + j0 + 1];
+      c00 = fma(a0, b0, c00);
+      c01 = fma(a0, b1, c01);
+      c10 = fma(a1, b0, c10);
+      c11 = fma(a1, b1, c11);
+    }
+    C[i0 * np + j0] = c00;
+    C[i0 * np + j0 + 1] = c01;
+    C[(i0 + 1) * np + j0] = c10;
+    C[(i0 + 1) * np + j0 + 1] = c11;
+  }
+}
+
+}  // namespace qoc

@@ -1,0 +1,90 @@
+// Internal declarations shared by the kernel and API translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace qoc {
+
+constexpr int kMaxN = 128;       // largest supported system dimension
+constexpr int kMaxP = 4096;      // largest supported parameter count
+constexpr int kThreads = 256;    // threads per workgroup of every kernel
+constexpr int kMaxPg = 32;       // tangent / second-adjoint columns carried per workgroup
+
+// Pad n to an even count of Jacobi "players" (a dummy index when n is odd).
+inline int pad_even(int n) { return (n + 1) & ~1; }
+
+// Device status word bits.
+constexpr int kStatusNoConv = 1;
+
+// Pointers into one evaluation workspace; every per-theta array is laid out
+// [theta][step][...] with theta-major strides given by nt and n.
+struct Work {
+  int n = 0, np = 0, nt = 0, P = 0, nb = 0;
+  int nchunks = 0, chunk = 0;
+  double* f = nullptr;        // [nb][nt]          control samples f_j
+  double* u = nullptr;        // [nb][nt]          u = B v (HVP forcing)
+  double* lam = nullptr;      // [nb][nt][n]       eigenvalues of H_j
+  double* mt = nullptr;       // [nb][nt][n][n]    Mt_j = V_j^T M V_j
+  double* sm = nullptr;       // [nb][nt][n][n]    S_j = sinc(dt (l_p - l_q)/2) o Mt_j
+  double* ov = nullptr;       // [nb][nt][n][n]    O_j = V_{j+1}^T V_j   (j < nt-1)
+  double* vfirst = nullptr;   // [nb][nchunks][n][n]  V at the first step of each chunk
+  double* vlast = nullptr;    // [nb][nchunks][n][n]  V at the last step of each chunk
+  double* gscratch = nullptr; // eigen-kernel matrices when they do not fit in LDS
+  double2* at = nullptr;      // [nb][nt][n]  state a_j in basis j
+  double2* yt = nullptr;      // [nb][nt][n]  y_j = U'_j a_j in basis j
+  double2* mu = nullptr;      // [nb][nt][n]  costate lambda_{j+1} in basis j
+  double2* ah = nullptr;      // [nb][nt][n]  HVP tangent a'_j in basis j
+  double* s = nullptr;        // [nb][nt]     s_j = Re(lambda_{j+1}^H U''_j a_j)
+  double* q = nullptr;        // [nb][nt]     q_j = Re(lambda_{j+1}^H U'_j a_j)
+  double* e = nullptr;        // [nb][nt]     HVP per-step terms
+  double* K = nullptr;        // [nb][nt][P]  K_j = Re(xi_j^H y_j)
+  double2* xf = nullptr;      // [nb][n][1+P] final X (a_J and A'_J in basis nt-1)
+  double2* binit = nullptr;   // [nb][n][2]   backward-sweep initial columns
+  double* rr = nullptr;       // [nb]         |a_J - beta|^2
+  double* aa = nullptr;       // [nb][P][P]   rho Re(A'_J^H A'_J)
+  int* status = nullptr;
+};
+
+struct SysDev {
+  int n = 0;
+  const double* h0 = nullptr;     // [n][n]
+  const double* m = nullptr;      // [n][n]
+  const double* psi0 = nullptr;   // [n] complex
+  const double* psit = nullptr;   // [n] complex
+};
+
+struct BasisDev {
+  int nt = 0, P = 0;
+  double dt = 0.0;
+  const double* B = nullptr;      // [nt][P]
+};
+
+enum class Mode { Cost = 0, Grad = 1, Hess = 2, Hvp = 3 };
+
+// Launchers (all enqueue on `stream`; return hipSuccess or the first launch error).
+hipError_t launch_fourier_basis(double* B, int nt, int K, hipStream_t stream);
+hipError_t launch_controls(const BasisDev& bs, const double* theta, double* f, int nb, hipStream_t stream);
+hipError_t launch_eig(const SysDev& sy, const BasisDev& bs, Work& w, bool store_derivs,
+                      double tol_rel, int max_sweeps, hipStream_t stream);
+hipError_t launch_forward(const SysDev& sy, const BasisDev& bs, Work& w, Mode mode, hipStream_t stream);
+hipError_t launch_terminal(const SysDev& sy, const BasisDev& bs, Work& w, Mode mode, double rho,
+                           hipStream_t stream);
+hipError_t launch_backward(const SysDev& sy, const BasisDev& bs, Work& w, Mode mode, hipStream_t stream);
+hipError_t launch_sterm(const SysDev& sy, const BasisDev& bs, Work& w, hipStream_t stream);
+hipError_t launch_assemble(const BasisDev& bs, Work& w, Mode mode, double gamma, double rho,
+                           double* cost, double* grad, double* hess_or_hv, hipStream_t stream);
+hipError_t launch_identity_basis(double* B, int nt, hipStream_t stream);
+// U_j, U'_j, U''_j for control value fj from a cold eigendecomposition (inspection aid).
+// gs: device scratch of step_props_scratch_doubles(n) doubles.
+hipError_t launch_step_props(const SysDev& sy, double fj, double dt, double* gs, double* u, double* u1,
+                             double* u2, int* status, hipStream_t stream);
+size_t step_props_scratch_doubles(int n);
+
+// Largest dynamic LDS request of any kernel; set once per device.
+hipError_t configure_kernels();
+size_t eig_scratch_doubles(int n, int nb, int nchunks);
+int choose_pg(int P, int nb);
+
+}  // namespace qoc

@@ -1,0 +1,289 @@
+"""Thin Python binding of the C ABI in include/qoc.h (argument marshalling only).
+
+Every computation runs in the HIP library ``libqoc.so`` built in-tree for gfx950
+(``python -m paper_2505_00529_amd.build``).  There is no fallback: if the library is
+missing or the device is unavailable, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqoc.so")
+
+QOC_OK = 0
+QOC_ERR_INVALID_ARG = -1
+QOC_ERR_NOT_SYMMETRIC = -2
+QOC_ERR_STATE = -3
+QOC_ERR_UNSUPPORTED = -4
+QOC_ERR_NOCONV = -5
+QOC_ERR_DEVICE = -6
+QOC_ERR_OOM = -7
+QOC_ERR_NOT_CONVERGED = -8
+
+QOC_BASIS_FOURIER = 0
+QOC_BASIS_IDENTITY = 1
+QOC_BASIS_DENSE = 2
+
+_lib = None
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_st = ctypes.c_int32
+
+# name -> (restype, argtypes)
+SIGNATURES = {
+    "qoc_create": (_st, [ctypes.c_int, _vp, ctypes.POINTER(_vp)]),
+    "qoc_destroy": (None, [_vp]),
+    "qoc_set_stream": (_st, [_vp, _vp]),
+    "qoc_set_system": (_st, [_vp, _i32, _dp, _dp, _dp, _dp]),
+    "qoc_set_target": (_st, [_vp, _dp]),
+    "qoc_set_control_basis": (_st, [_vp, ctypes.c_int, _i32, ctypes.c_double, _i32, _dp]),
+    "qoc_set_weights": (_st, [_vp, ctypes.c_double, ctypes.c_double]),
+    "qoc_get_num_params": (_st, [_vp, ctypes.POINTER(_i32)]),
+    "qoc_cost": (_st, [_vp, _dp, _dp]),
+    "qoc_grad": (_st, [_vp, _dp, _dp, _dp]),
+    "qoc_hess": (_st, [_vp, _dp, _dp, _dp, _dp]),
+    "qoc_hvp": (_st, [_vp, _dp, _dp, _dp, _dp]),
+    "qoc_hess_many": (_st, [_vp, _i32, _dp, _dp, _dp, _dp]),
+    "qoc_grad_many": (_st, [_vp, _i32, _dp, _dp, _dp]),
+    "qoc_cost_dev": (_st, [_vp, _vp, _vp]),
+    "qoc_grad_dev": (_st, [_vp, _vp, _vp, _vp]),
+    "qoc_hess_dev": (_st, [_vp, _vp, _vp, _vp, _vp]),
+    "qoc_hvp_dev": (_st, [_vp, _vp, _vp, _vp, _vp]),
+    "qoc_hess_many_dev": (_st, [_vp, _i32, _vp, _vp, _vp, _vp]),
+    "qoc_sync": (_st, [_vp]),
+    "qoc_step_propagators": (_st, [_vp, _dp, _i32, _dp, _dp, _dp]),
+    "qoc_set_checkpoint_interval": (_st, [_vp, _i32]),
+    "qoc_memory_usage": (_st, [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
+    "qoc_tr_solve": (_st, [_vp, _dp, ctypes.c_double, _i32, _dp, _dp, ctypes.POINTER(_i32)]),
+    "qoc_batch_create": (_st, [ctypes.c_int, _i32, ctypes.POINTER(_vp), ctypes.POINTER(_vp)]),
+    "qoc_batch_destroy": (None, [_vp]),
+    "qoc_batch_hess": (_st, [_vp, ctypes.POINTER(_dp), ctypes.POINTER(_dp), ctypes.POINTER(_dp),
+                             ctypes.POINTER(_dp)]),
+    "qoc_batch_hess_unbatched": (_st, [_vp, ctypes.POINTER(_dp), ctypes.POINTER(_dp),
+                                       ctypes.POINTER(_dp), ctypes.POINTER(_dp)]),
+    "qoc_batch_last_error": (ctypes.c_char_p, [_vp]),
+    "qoc_status_string": (ctypes.c_char_p, [_st]),
+    "qoc_last_error": (ctypes.c_char_p, [_vp]),
+}
+
+
+class QocError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"qoc status {status}: {message}")
+        self.status = status
+
+
+def lib() -> ctypes.CDLL:
+    """Load libqoc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} not found: build it with `python -m paper_2505_00529_amd.build`")
+        handle = ctypes.CDLL(LIB_PATH, mode=ctypes.RTLD_GLOBAL)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(handle, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = handle
+    return _lib
+
+
+def status_string(status: int) -> str:
+    return lib().qoc_status_string(status).decode()
+
+
+def _f64(x, size=None) -> np.ndarray:
+    a = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+    if size is not None and a.size != size:
+        raise ValueError(f"expected {size} values, got {a.size}")
+    return a
+
+
+def _cplx(x, n) -> np.ndarray:
+    a = np.ascontiguousarray(np.asarray(x, dtype=np.complex128).reshape(n))
+    return a.view(np.float64)
+
+
+def _ptr(a: Optional[np.ndarray]):
+    if a is None:
+        return None
+    return a.ctypes.data_as(_dp)
+
+
+class Problem:
+    """Handle over one system + control basis (``qoc_problem``)."""
+
+    def __init__(self, device: int = 0, stream: Optional[int] = None):
+        self._h = _vp()
+        st = lib().qoc_create(device, _vp(stream) if stream else None, ctypes.byref(self._h))
+        if st != QOC_OK:
+            raise QocError(st, status_string(st))
+        self.n = 0
+        self.P = 0
+
+    # -- lifecycle
+    def close(self):
+        if self._h:
+            lib().qoc_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def _check(self, st: int):
+        if st != QOC_OK:
+            raise QocError(st, lib().qoc_last_error(self._h).decode())
+
+    # -- configuration
+    def set_stream(self, stream: Optional[int]):
+        self._check(lib().qoc_set_stream(self._h, _vp(stream) if stream else None))
+
+    def set_system(self, h0, m, psi0, psi_target):
+        h0 = _f64(h0)
+        n = h0.shape[0]
+        m = _f64(m, n * n)
+        self._check(lib().qoc_set_system(self._h, n, _ptr(h0), _ptr(m), _ptr(_cplx(psi0, n)),
+                                         _ptr(_cplx(psi_target, n))))
+        self.n = n
+
+    def set_target(self, psi_target):
+        self._check(lib().qoc_set_target(self._h, _ptr(_cplx(psi_target, self.n))))
+
+    def set_control_basis(self, kind: int, nt: int, dt: float, k_or_p: int = 0, b=None):
+        bb = None if b is None else _f64(b)
+        self._check(lib().qoc_set_control_basis(self._h, kind, nt, dt, k_or_p, _ptr(bb)))
+        p = _i32()
+        self._check(lib().qoc_get_num_params(self._h, ctypes.byref(p)))
+        self.P = p.value
+        self.nt = nt
+
+    def set_weights(self, gamma: float, rho: float):
+        self._check(lib().qoc_set_weights(self._h, gamma, rho))
+
+    def set_checkpoint_interval(self, steps: int):
+        self._check(lib().qoc_set_checkpoint_interval(self._h, steps))
+
+    def memory_usage(self) -> Tuple[int, int]:
+        c = ctypes.c_int64()
+        pk = ctypes.c_int64()
+        self._check(lib().qoc_memory_usage(self._h, ctypes.byref(c), ctypes.byref(pk)))
+        return c.value, pk.value
+
+    # -- evaluation (host arrays)
+    def cost(self, theta) -> float:
+        th = _f64(theta, self.P)
+        c = np.zeros(1)
+        self._check(lib().qoc_cost(self._h, _ptr(th), _ptr(c)))
+        return float(c[0])
+
+    def grad(self, theta):
+        th = _f64(theta, self.P)
+        c = np.zeros(1)
+        g = np.zeros(self.P)
+        self._check(lib().qoc_grad(self._h, _ptr(th), _ptr(c), _ptr(g)))
+        return float(c[0]), g
+
+    def hess(self, theta):
+        th = _f64(theta, self.P)
+        c = np.zeros(1)
+        g = np.zeros(self.P)
+        h = np.zeros((self.P, self.P))
+        self._check(lib().qoc_hess(self._h, _ptr(th), _ptr(c), _ptr(g), _ptr(h)))
+        return float(c[0]), g, h
+
+    def hvp(self, theta, v, with_grad: bool = False):
+        th = _f64(theta, self.P)
+        vv = _f64(v, self.P)
+        hv = np.zeros(self.P)
+        g = np.zeros(self.P) if with_grad else None
+        self._check(lib().qoc_hvp(self._h, _ptr(th), _ptr(vv), _ptr(hv), _ptr(g)))
+        return (hv, g) if with_grad else hv
+
+    def hess_many(self, thetas):
+        th = _f64(thetas)
+        count = th.size // self.P
+        th = th.reshape(count, self.P)
+        c = np.zeros(count)
+        g = np.zeros((count, self.P))
+        h = np.zeros((count, self.P, self.P))
+        self._check(lib().qoc_hess_many(self._h, count, _ptr(th), _ptr(c), _ptr(g), _ptr(h)))
+        return c, g, h
+
+    def grad_many(self, thetas):
+        th = _f64(thetas)
+        count = th.size // self.P
+        th = th.reshape(count, self.P)
+        c = np.zeros(count)
+        g = np.zeros((count, self.P))
+        self._check(lib().qoc_grad_many(self._h, count, _ptr(th), _ptr(c), _ptr(g)))
+        return c, g
+
+    # -- evaluation (device pointers, enqueue only)
+    def cost_dev(self, theta_ptr: int, cost_ptr: int):
+        self._check(lib().qoc_cost_dev(self._h, _vp(theta_ptr), _vp(cost_ptr)))
+
+    def grad_dev(self, theta_ptr: int, cost_ptr: Optional[int], grad_ptr: int):
+        self._check(lib().qoc_grad_dev(self._h, _vp(theta_ptr), _vp(cost_ptr) if cost_ptr else None,
+                                       _vp(grad_ptr)))
+
+    def hess_dev(self, theta_ptr, cost_ptr, grad_ptr, hess_ptr):
+        self._check(lib().qoc_hess_dev(self._h, _vp(theta_ptr), _vp(cost_ptr) if cost_ptr else None,
+                                       _vp(grad_ptr) if grad_ptr else None, _vp(hess_ptr)))
+
+    def hvp_dev(self, theta_ptr, v_ptr, hv_ptr, grad_ptr=None):
+        self._check(lib().qoc_hvp_dev(self._h, _vp(theta_ptr), _vp(v_ptr), _vp(hv_ptr),
+                                      _vp(grad_ptr) if grad_ptr else None))
+
+    def hess_many_dev(self, count, thetas_ptr, costs_ptr, grads_ptr, hess_ptr):
+        self._check(lib().qoc_hess_many_dev(self._h, count, _vp(thetas_ptr),
+                                            _vp(costs_ptr) if costs_ptr else None,
+                                            _vp(grads_ptr) if grads_ptr else None,
+                                            _vp(hess_ptr) if hess_ptr else None))
+
+    def sync(self):
+        self._check(lib().qoc_sync(self._h))
+
+    # -- inspection and solvers
+    def step_propagators(self, theta, j: int):
+        th = _f64(theta, self.P)
+        n = self.n
+        u = np.zeros((n, n), np.complex128)
+        u1 = np.zeros((n, n), np.complex128)
+        u2 = np.zeros((n, n), np.complex128)
+        self._check(lib().qoc_step_propagators(self._h, _ptr(th), j, _ptr(u.view(np.float64)),
+                                               _ptr(u1.view(np.float64)), _ptr(u2.view(np.float64))))
+        return u, u1, u2
+
+    def tr_solve(self, theta0, gtol: float = 1e-8, max_iter: int = 10000):
+        th = _f64(theta0, self.P)
+        out = np.zeros(self.P)
+        c = np.zeros(1)
+        it = _i32()
+        st = lib().qoc_tr_solve(self._h, _ptr(th), gtol, max_iter, _ptr(out), _ptr(c), ctypes.byref(it))
+        if st not in (QOC_OK, QOC_ERR_NOT_CONVERGED):
+            self._check(st)
+        return out, float(c[0]), int(it.value), st == QOC_OK
+
+
+def problem_from_workload(w, device: int = 0) -> Problem:
+    """Configure a handle from a paper_2505_00529_amd.inputs.Workload (Fourier model)."""
+    p = Problem(device)
+    s = w.system
+    p.set_system(s.h0, s.m, s.psi0, s.psi_target)
+    p.set_control_basis(QOC_BASIS_FOURIER, w.nt, w.dt, w.k)
+    p.set_weights(w.gamma, w.rho)
+    return p
