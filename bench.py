@@ -1,0 +1,176 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the second-order adjoint evaluation on one MI355X.
+
+One step = cost + exact gradient + exact Hessian (every row of the hot path: controls,
+eigen-data, forward sweep, terminal residual, backward sweep, U'' contraction, assembly)
+for a batch of independent control-coefficient vectors theta on the molecule-sized
+workload (N=36, J=4000 steps of dt=0.02, Fourier model with K=16 harmonics, P=32).
+Inputs are synthetic (seeded generators) and resident in HBM before timing starts.
+
+Prints one JSON line.  --gpus N with N > 1 exits: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+from paper_2505_00529_amd import inputs, qoc  # noqa: E402
+
+PEAK_FP64 = 78.6e12          # MI355X FP64 vector (= FP64 matrix) peak, FLOP/s
+PEAK_HBM = 8.0e12            # bytes/s
+
+
+def alg_flops_per_step(kernel: str, n: int, p: int) -> float:
+    """Algorithmic FLOPs per (theta, time step) of each kernel (method's nominal counts)."""
+    return {
+        "eig": 9.0 * n ** 3 + 4.0 * n ** 3,   # eigendecomposition + Mt = V^T M V
+        "forward": 8.0 * n * n * p,           # N x N . N x P complex tangent product
+        "backward": 8.0 * n * n * p,          # N x N . N x P complex second-adjoint product
+        "sterm": 8.0 * n ** 3,                # U'' contraction (two N x N complex-real products)
+    }.get(kernel, 0.0)
+
+
+def log(msg: str) -> None:
+    sys.stderr.write(msg + "\n")
+    sys.stderr.flush()
+
+
+def cpu_baseline(w) -> dict:
+    """The CPU oracle timed on one theta of the same workload (full cost + grad + Hessian)."""
+    from oracle import qoc_oracle as O
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([int(x.get("num_threads", 1)) for x in threadpool_info()] or [1])
+    except Exception:  # pragma: no cover
+        threads = os.cpu_count() or 1
+    s = w.system
+    basis = O.fourier_basis(w.nt, w.dt, w.k)
+    th = inputs.draw_thetas(w.p, 1, w.seed)[0]
+    t0 = time.perf_counter()
+    O.cost_grad_hess(s.h0, s.m, s.psi0, s.psi_target, basis, w.dt, th, w.gamma, w.rho)
+    dt = time.perf_counter() - t0
+    return {"value": 1.0 / dt, "unit": "evals/s", "cores": threads, "kind": "oracle",
+            "sample": f"1 theta of the same workload (N={s.n}, J={w.nt}, P={w.p}), full cost+grad+Hessian, "
+                      f"{dt:.1f} s; forward-over-forward oracle with block-triangular exponentials"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--batch", type=int, default=256, help="independent theta per step")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build measures one GPU only (one process, one MI355X); "
+              "--gpus above 1 is not supported", file=sys.stderr)
+        return 2
+
+    import torch
+
+    torch.cuda.set_device(0)
+    w = inputs.make_workload("molecule")
+    n, P, nt, B = w.system.n, w.p, w.nt, args.batch
+    log(f"bench: workload molecule n={n} nt={nt} P={P} batch={B}")
+    prob = qoc.problem_from_workload(w, device=0)
+    stream = torch.cuda.current_stream()
+    prob.set_stream(stream.cuda_stream)
+
+    thetas = torch.tensor(inputs.draw_thetas(P, B, w.seed), dtype=torch.float64, device="cuda")
+    costs = torch.empty(B, dtype=torch.float64, device="cuda")
+    grads = torch.empty(B, P, dtype=torch.float64, device="cuda")
+    hess = torch.empty(B, P, P, dtype=torch.float64, device="cuda")
+
+    def step():
+        prob.hess_many_dev(B, thetas.data_ptr(), costs.data_ptr(), grads.data_ptr(), hess.data_ptr())
+
+    for i in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        log(f"bench: warmup {i + 1}/{args.warmup} done")
+    prob.sync()
+    prob.jacobi_stats(reset=True)
+    prob.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prob.sync()
+    log(f"bench: {args.steps} timed steps in {t1 - t0:.3f} s")
+
+    kernels = ["controls", "eig", "boundary", "forward", "terminal", "backward", "sterm", "assemble"]
+    ktimes = {}
+    for k in kernels:
+        ms, cnt = prob.profile_kernel_ms(k)
+        if cnt:
+            ktimes[k] = (ms / cnt, cnt)
+    prob.profile_enable(False)
+    eig_steps, eig_sweeps = prob.jacobi_stats(reset=True)
+    dom = max(ktimes, key=lambda k: ktimes[k][0])
+    avg_ms = ktimes[dom][0]
+    flops_launch = alg_flops_per_step(dom, n, P) * nt * B
+    achieved = flops_launch / (avg_ms * 1e-3) / 1e12
+    peak = PEAK_FP64 / 1e12
+
+    h = hess.cpu().numpy()
+    assert np.all(np.isfinite(h)) and np.all(np.isfinite(costs.cpu().numpy()))
+
+    elapsed = t1 - t0
+    value = B * args.steps / elapsed
+    f_alg = sum(alg_flops_per_step(k, n, P) for k in ("eig", "forward", "backward", "sterm")) * nt
+    out = {
+        "metric": "grad+Hessian evals/s (FP64, N=36, P=32)",
+        "value": value,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "molecule: N=36, J=4000, dt=0.02, Fourier K=16 (P=32), "
+                        f"{B} independent theta ~ N(0, 0.1^2) per step",
+            "n": n, "nt": nt, "P": P, "batch": B, "parallelism": "single GPU",
+        },
+        "roofline": {
+            "kernel": dom,
+            "bound": "alu" if dom == "eig" else "mfma",
+            "achieved": achieved,
+            "peak": peak,
+            "unit": "TFLOP/s",
+            "frac": achieved / peak,
+            "traffic": None,
+        },
+        "kernel_ms": {k: round(v[0], 4) for k, v in ktimes.items()},
+        "jacobi_sweeps_per_step": eig_sweeps / max(eig_steps, 1),
+        "path_alg_flops_per_eval": f_alg,
+        "path_roofline_frac": f_alg * value / PEAK_FP64,
+    }
+    if not args.no_cpu_baseline:
+        log("bench: timing the CPU oracle on one theta ...")
+        out["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(out), flush=True)
+    prob.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

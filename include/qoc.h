@@ -145,6 +145,19 @@ qoc_status qoc_batch_hess_unbatched(qoc_batch* b, const double* const* thetas, d
                                     double* const* grads, double* const* hessians);
 const char* qoc_batch_last_error(const qoc_batch* b);
 
+/* Per-kernel timing with HIP events recorded around every launch on the handle's stream.
+ * qoc_profile_enable(p, 1) starts recording (and clears earlier totals), 0 stops.
+ * qoc_profile_kernel_ms: total milliseconds and launch count since enabling, for one of
+ * "controls", "eig", "boundary", "forward", "terminal", "backward", "sterm", "assemble"
+ * (synchronises the stream).  Unknown names give 0 ms and 0 launches. */
+qoc_status qoc_profile_enable(qoc_problem* p, int32_t on);
+qoc_status qoc_profile_kernel_ms(qoc_problem* p, const char* kernel, double* total_ms, int32_t* launches);
+
+/* Eigensolver statistics accumulated since the last reset (inspection aid): number of
+ * per-step decompositions that converged and the Jacobi sweeps they took.  reset != 0
+ * clears the counters after reading. */
+qoc_status qoc_jacobi_stats(qoc_problem* p, int64_t* steps, int64_t* sweeps, int32_t reset);
+
 /* Static strings; never NULL. */
 const char* qoc_status_string(qoc_status s);
 const char* qoc_last_error(const qoc_problem* p);

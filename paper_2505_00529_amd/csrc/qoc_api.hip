@@ -94,7 +94,10 @@ qoc_problem::~qoc_problem() {
   dfree(d_B, b_bytes);
   dfree(d_io, io_bytes);
   dfree(d_status, sizeof(int));
+  dfree(d_stats, 2 * sizeof(unsigned long long));
   dfree(d_props, props_bytes);
+  (void)prof_collect();
+  for (hipEvent_t e : prof_pool) (void)hipEventDestroy(e);
   if (own_stream && stream) (void)hipStreamDestroy(stream);
 }
 
@@ -154,6 +157,7 @@ qoc_status qoc_problem::ensure_work(int nb) {
     cur += (it.bytes + 255) & ~(size_t)255;
   }
   nw.status = d_status;
+  nw.stats = d_stats;
   w = nw;
   work_mem = mem;
   work_bytes = total;
@@ -197,20 +201,68 @@ qoc_status qoc_problem::enqueue(Mode mode, int nb, const double* d_theta, const 
   bs.dt = dt;
   bs.B = d_B;
   hipError_t e;
-#define QOC_LAUNCH(call)                                  \
+  hipEvent_t ev = nullptr;
+#define QOC_LAUNCH(tag, call)                             \
   do {                                                    \
+    prof_begin(tag, &ev);                                 \
     e = (call);                                           \
     if (e != hipSuccess) return hip_fail(e, #call);       \
+    prof_end(tag, ev);                                    \
   } while (0)
-  QOC_LAUNCH(launch_controls(bs, d_theta, w.f, nb, stream));
-  if (mode == Mode::Hvp) QOC_LAUNCH(launch_controls(bs, d_v, w.u, nb, stream));
-  QOC_LAUNCH(launch_eig(sy, bs, w, mode != Mode::Cost, kJacobiTol, jacobi_max_sweeps, stream));
-  QOC_LAUNCH(launch_forward(sy, bs, w, mode, stream));
-  QOC_LAUNCH(launch_terminal(sy, bs, w, mode, rho, stream));
-  if (mode != Mode::Cost) QOC_LAUNCH(launch_backward(sy, bs, w, mode, stream));
-  if (mode == Mode::Hess || mode == Mode::Hvp) QOC_LAUNCH(launch_sterm(sy, bs, w, stream));
-  QOC_LAUNCH(launch_assemble(bs, w, mode, gamma, rho, d_cost, d_grad, d_out, stream));
+  QOC_LAUNCH("controls", launch_controls(bs, d_theta, w.f, nb, stream));
+  if (mode == Mode::Hvp) QOC_LAUNCH("controls", launch_controls(bs, d_v, w.u, nb, stream));
+  QOC_LAUNCH("eig", launch_eig(sy, bs, w, mode != Mode::Cost, kJacobiTol, jacobi_max_sweeps, stream));
+  QOC_LAUNCH("boundary", launch_boundary(w, stream));
+  QOC_LAUNCH("forward", launch_forward(sy, bs, w, mode, stream));
+  QOC_LAUNCH("terminal", launch_terminal(sy, bs, w, mode, rho, stream));
+  if (mode != Mode::Cost) QOC_LAUNCH("backward", launch_backward(sy, bs, w, mode, stream));
+  if (mode == Mode::Hess || mode == Mode::Hvp) QOC_LAUNCH("sterm", launch_sterm(sy, bs, w, stream));
+  QOC_LAUNCH("assemble", launch_assemble(bs, w, mode, gamma, rho, d_cost, d_grad, d_out, stream));
 #undef QOC_LAUNCH
+  return QOC_OK;
+}
+
+hipEvent_t qoc_problem::prof_event() {
+  if (!prof_pool.empty()) {
+    hipEvent_t e = prof_pool.back();
+    prof_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+void qoc_problem::prof_begin(const char* name, hipEvent_t* a) {
+  (void)name;
+  *a = nullptr;
+  if (!profiling) return;
+  *a = prof_event();
+  if (*a) (void)hipEventRecord(*a, stream);
+}
+
+void qoc_problem::prof_end(const char* name, hipEvent_t a) {
+  if (!profiling || !a) return;
+  hipEvent_t b = prof_event();
+  if (!b) return;
+  (void)hipEventRecord(b, stream);
+  prof_pending.push_back({name, a, b});
+}
+
+qoc_status qoc_problem::prof_collect() {
+  hipError_t e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return hip_fail(e, "profile synchronise");
+  for (auto& r : prof_pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.start, r.stop) == hipSuccess) {
+      auto& acc = prof_acc[r.name];
+      acc.first += ms;
+      acc.second += 1;
+    }
+    prof_pool.push_back(r.start);
+    prof_pool.push_back(r.stop);
+  }
+  prof_pending.clear();
   return QOC_OK;
 }
 
@@ -313,7 +365,9 @@ qoc_status qoc_create(int device, void* hip_stream, qoc_problem** out) {
     p->own_stream = true;
   }
   if (p->dmalloc((void**)&p->d_status, sizeof(int), "status word") != QOC_OK ||
+      p->dmalloc((void**)&p->d_stats, 2 * sizeof(unsigned long long), "statistics") != QOC_OK ||
       hipMemsetAsync(p->d_status, 0, sizeof(int), p->stream) != hipSuccess ||
+      hipMemsetAsync(p->d_stats, 0, 2 * sizeof(unsigned long long), p->stream) != hipSuccess ||
       hipStreamSynchronize(p->stream) != hipSuccess) {
     delete p;
     return QOC_ERR_DEVICE;
@@ -608,6 +662,37 @@ qoc_status qoc_set_checkpoint_interval(qoc_problem* p, int32_t steps) {
   if (!p) return QOC_ERR_INVALID_ARG;
   if (steps < 0) return p->fail(QOC_ERR_INVALID_ARG, "interval must be >= 0");
   p->ckpt = steps;
+  return QOC_OK;
+}
+
+qoc_status qoc_profile_enable(qoc_problem* p, int32_t on) {
+  if (!p) return QOC_ERR_INVALID_ARG;
+  qoc_status st = p->prof_collect();
+  if (st != QOC_OK) return st;
+  if (on) p->prof_acc.clear();
+  p->profiling = on != 0;
+  return QOC_OK;
+}
+
+qoc_status qoc_profile_kernel_ms(qoc_problem* p, const char* kernel, double* total_ms, int32_t* launches) {
+  if (!p || !kernel) return QOC_ERR_INVALID_ARG;
+  qoc_status st = p->prof_collect();
+  if (st != QOC_OK) return st;
+  auto it = p->prof_acc.find(kernel);
+  if (total_ms) *total_ms = it == p->prof_acc.end() ? 0.0 : it->second.first;
+  if (launches) *launches = it == p->prof_acc.end() ? 0 : it->second.second;
+  return QOC_OK;
+}
+
+qoc_status qoc_jacobi_stats(qoc_problem* p, int64_t* steps, int64_t* sweeps, int32_t reset) {
+  if (!p) return QOC_ERR_INVALID_ARG;
+  unsigned long long h[2] = {0, 0};
+  hipError_t e = hipMemcpyAsync(h, p->d_stats, sizeof(h), hipMemcpyDeviceToHost, p->stream);
+  if (e == hipSuccess && reset) e = hipMemsetAsync(p->d_stats, 0, sizeof(h), p->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+  if (e != hipSuccess) return p->hip_fail(e, "statistics readback");
+  if (steps) *steps = (int64_t)h[0];
+  if (sweeps) *sweeps = (int64_t)h[1];
   return QOC_OK;
 }
 

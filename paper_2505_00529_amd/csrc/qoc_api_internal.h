@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -46,9 +47,24 @@ struct qoc_problem {
   double* d_props = nullptr;
   size_t props_bytes = 0;
   int* d_status = nullptr;
+  unsigned long long* d_stats = nullptr;
 
   std::string err;
   int64_t cur_bytes = 0, peak_bytes = 0;
+
+  // event profiling
+  struct ProfRec {
+    const char* name;
+    hipEvent_t start, stop;
+  };
+  bool profiling = false;
+  std::vector<ProfRec> prof_pending;
+  std::vector<hipEvent_t> prof_pool;
+  std::map<std::string, std::pair<double, int>> prof_acc;
+  hipEvent_t prof_event();
+  void prof_begin(const char* name, hipEvent_t* a);
+  void prof_end(const char* name, hipEvent_t a);
+  qoc_status prof_collect();
 
   ~qoc_problem();
   qoc_status fail(qoc_status s, const std::string& msg);

@@ -121,6 +121,26 @@ __device__ __forceinline__ double block_max(double v, double* red) {
   return r;
 }
 
+// Wave-level (64-lane) reductions.
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
+__device__ __forceinline__ double wave_min(double v) {
+  for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
+  return v;
+}
+// Broadcast lane `src` (wave-uniform) of a double.
+__device__ __forceinline__ double readlane_d(double v, int src) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+  return __hiloint2double(hi, lo);
+}
+
 // Round-robin ("circle") pairing of np players (np even) in round r of np-1: player np-1
 // meets r; the others pair as (r+k, r-k) mod (np-1).  Every unordered pair meets once per
 // sweep.  Returns the pair ordered p < q.

@@ -45,6 +45,7 @@ struct Work {
   double* rr = nullptr;       // [nb]         |a_J - beta|^2
   double* aa = nullptr;       // [nb][P][P]   rho Re(A'_J^H A'_J)
   int* status = nullptr;
+  unsigned long long* stats = nullptr;   // [0] eigen steps, [1] Jacobi sweeps
 };
 
 struct SysDev {
@@ -68,6 +69,7 @@ hipError_t launch_fourier_basis(double* B, int nt, int K, hipStream_t stream);
 hipError_t launch_controls(const BasisDev& bs, const double* theta, double* f, int nb, hipStream_t stream);
 hipError_t launch_eig(const SysDev& sy, const BasisDev& bs, Work& w, bool store_derivs,
                       double tol_rel, int max_sweeps, hipStream_t stream);
+hipError_t launch_boundary(Work& w, hipStream_t stream);
 hipError_t launch_forward(const SysDev& sy, const BasisDev& bs, Work& w, Mode mode, hipStream_t stream);
 hipError_t launch_terminal(const SysDev& sy, const BasisDev& bs, Work& w, Mode mode, double rho,
                            hipStream_t stream);

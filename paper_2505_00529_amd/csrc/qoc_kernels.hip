@@ -69,6 +69,7 @@ struct EigArgs {
   double* vlast;
   double* gscratch;
   int* status;
+  unsigned long long* stats;
 };
 
 __host__ __device__ inline size_t eig_small_doubles(int np) { return (size_t)2 * np + kThreads + np; }
@@ -131,6 +132,10 @@ __global__ __launch_bounds__(kThreads) void k_eig_chunk(EigArgs a) {
     int sweeps = 0;
     const bool ok = jacobi_eig(A, V, np, a.tol_rel * fro, a.max_sweeps, rot, prs, red, &sweeps);
     if (!ok && tid == 0) atomicOr(a.status, kStatusNoConv);
+    if (ok && tid == 0 && a.stats) {
+      atomicAdd(a.stats, 1ull);
+      atomicAdd(a.stats + 1, (unsigned long long)sweeps);
+    }
     for (int i = tid; i < np; i += kThreads) lamv[i] = A[i * np + i];
     __syncthreads();
     // X = M V ; A = V^T X = Mt_j
@@ -192,6 +197,272 @@ __global__ __launch_bounds__(kThreads) void k_boundary_overlap(const double* vfi
   }
 }
 
+// ---------------------------------------------------------------- eigen-data, one wave per problem
+
+// Circle schedule in "slot" space for NP players: slot 0 holds player 0 for good; slots 1..NP-1
+// sit on a circle of M = NP-1 positions and advance one position per round, so pairs are always
+// slots (2k, 2k+1) and every unordered pair of players meets once per sweep.  Slot s sits at
+// position pos(s); the player in slot s at round r is slot_of_pos((pos(s) + r) mod M).
+__host__ __device__ constexpr int circ_pos(int s, int NP) {
+  return s == 1 ? 0 : ((s & 1) == 0 ? s / 2 : NP - 1 - (s - 1) / 2);
+}
+__host__ __device__ constexpr int circ_slot(int c, int NP) {
+  return c == 0 ? 1 : (c <= NP / 2 - 1 ? 2 * c : 2 * (NP - 1 - c) + 1);
+}
+__device__ __forceinline__ int circ_player(int s, int r, int NP) {
+  if (s == 0) return 0;
+  int c = circ_pos(s, NP) + r;
+  c -= (c >= NP - 1) ? NP - 1 : 0;
+  return circ_slot(c, NP);
+}
+
+// After round r, the row of V held by a lane moves so that slot s holds the player of round r+1:
+// new[slot(c)] = old[slot(c+1)] along the circle (a compile-time register rotation).
+template <int NP>
+__device__ __forceinline__ void circ_advance(double (&v)[NP]) {
+  const double t = v[circ_slot(0, NP)];
+#pragma unroll
+  for (int c = 0; c < NP - 2; ++c) v[circ_slot(c, NP)] = v[circ_slot(c + 1, NP)];
+  v[circ_slot(NP - 2, NP)] = t;
+}
+
+// Same work as k_eig_chunk, with one 64-lane wave per (theta, chunk): A lives in LDS, lane i keeps
+// row i of V in registers (slot order = column order at sweep boundaries), and the basis products
+// O_{j-1} = V_j^T V_{j-1}, X = M V_j, Mt_j = V_j^T X use three rotating LDS buffers.
+template <int NP>
+__global__ __launch_bounds__(64, 2) void k_eig_wave(EigArgs a) {
+  constexpr int H = NP / 2;
+  constexpr int NBLK = H * (H + 1) / 2;
+  constexpr int BPL = (NBLK + 63) / 64;    // 2x2 blocks per lane
+  extern __shared__ double smem[];
+  double* buf0 = smem;
+  double* buf1 = buf0 + NP * NP;
+  double* buf2 = buf1 + NP * NP;
+  double* rot = buf2 + NP * NP;            // c, s per pair
+  double* lamv = rot + NP;                 // eigenvalues
+  int* prs = (int*)(lamv + NP);            // players of each pair
+  const int lane = threadIdx.x;
+  const int c = blockIdx.x, b = blockIdx.y;
+  const int n = a.n, nt = a.nt;
+  const int j0 = c * a.chunk;
+  const int j1 = min(nt, j0 + a.chunk);
+  if (j0 >= j1) return;
+  const double* fb = a.f + (size_t)b * nt;
+  const size_t nn = (size_t)n * n;
+
+  // fixed block list of this lane: (I, K), I <= K
+  int bI[BPL], bK[BPL];
+#pragma unroll
+  for (int t = 0; t < BPL; ++t) {
+    const int w = lane + 64 * t;
+    int I = 0, K = 0;
+    if (w < NBLK) {
+      I = (int)((2.0 * H + 1.0 - sqrt((2.0 * H + 1.0) * (2.0 * H + 1.0) - 8.0 * w)) * 0.5);
+      if (I < 0) I = 0;
+      while (I > 0 && I * H - I * (I - 1) / 2 > w) --I;
+      while ((I + 1) * H - (I + 1) * I / 2 <= w) ++I;
+      K = I + (w - (I * H - I * (I - 1) / 2));
+    }
+    bI[t] = w < NBLK ? I : -1;
+    bK[t] = K;
+  }
+
+  double v[NP];
+  double* Bm = buf0;   // A_j / later X
+  double* Bv = buf1;   // V_{j-1} staged
+  double* Bx = buf2;   // V_j staged
+  for (int j = j0; j < j1; ++j) {
+    const double fj = fb[j];
+    if (j == j0) {
+      for (int idx = lane; idx < NP * NP; idx += 64) {
+        const int i = idx / NP, k = idx - i * NP;
+        Bm[idx] = (i < n && k < n) ? a.h0[i * n + k] + fj * a.m[i * n + k] : 0.0;
+      }
+#pragma unroll
+      for (int s = 0; s < NP; ++s) v[s] = (s == lane) ? 1.0 : 0.0;
+    } else {
+      const double df = fj - fb[j - 1];
+      for (int idx = lane; idx < NP * NP; idx += 64) {
+        const int i = idx / NP, k = idx - i * NP;
+        Bm[idx] = df * Bm[idx] + (i == k ? lamv[i] : 0.0);   // Bm held Mt_{j-1}
+      }
+      // warm start: V_{j-1} (staged in Bv) as the initial rotation accumulator
+#pragma unroll
+      for (int s2 = 0; s2 < NP; ++s2) v[s2] = lane < NP ? Bv[lane * NP + s2] : 0.0;
+    }
+    __syncthreads();
+    double loc = 0.0;
+    for (int idx = lane; idx < NP * NP; idx += 64) loc += Bm[idx] * Bm[idx];
+    const double tol = a.tol_rel * sqrt(wave_sum(loc));
+#pragma unroll 1
+    for (int sweep = 0;; ++sweep) {
+      double off = 0.0;
+      for (int idx = lane; idx < NP * NP; idx += 64) {
+        const int i = idx / NP, k = idx - i * NP;
+        if (i < k) off = fmax(off, fabs(Bm[idx]));
+      }
+      off = wave_max(off);
+      if (off <= tol) {
+        if (lane == 0 && a.stats) {
+          atomicAdd(a.stats, 1ull);
+          atomicAdd(a.stats + 1, (unsigned long long)sweep);
+        }
+        break;
+      }
+      if (sweep >= a.max_sweeps) {
+        if (lane == 0) atomicOr(a.status, kStatusNoConv);
+        break;
+      }
+#pragma unroll 1
+      for (int r = 0; r < NP - 1; ++r) {
+        if (lane < H) {
+          const int p = circ_player(2 * lane, r, NP), q = circ_player(2 * lane + 1, r, NP);
+          const double app = Bm[p * NP + p], aqq = Bm[q * NP + q], apq = Bm[p * NP + q];
+          double cc = 1.0, ss = 0.0;
+          if (apq != 0.0) {
+            const double tau = (aqq - app) / (2.0 * apq);
+            double t;
+            if (fabs(tau) > 1e150) t = 0.5 / tau;
+            else t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+            cc = 1.0 / sqrt(1.0 + t * t);
+            ss = t * cc;
+          }
+          rot[2 * lane] = cc;
+          rot[2 * lane + 1] = ss;
+          prs[2 * lane] = p;
+          prs[2 * lane + 1] = q;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < BPL; ++t) {
+          const int I = bI[t];
+          if (I >= 0) {
+            const int K = bK[t];
+            const int pI = prs[2 * I], qI = prs[2 * I + 1];
+            const int pK = prs[2 * K], qK = prs[2 * K + 1];
+            const double cI = rot[2 * I], sI = rot[2 * I + 1];
+            const double cK = rot[2 * K], sK = rot[2 * K + 1];
+            const double a00 = Bm[pI * NP + pK], a01 = Bm[pI * NP + qK];
+            const double a10 = Bm[qI * NP + pK], a11 = Bm[qI * NP + qK];
+            const double t00 = a00 * cK - a01 * sK, t01 = a00 * sK + a01 * cK;
+            const double t10 = a10 * cK - a11 * sK, t11 = a10 * sK + a11 * cK;
+            const double b00 = cI * t00 - sI * t10, b01 = cI * t01 - sI * t11;
+            const double b10 = sI * t00 + cI * t10, b11 = sI * t01 + cI * t11;
+            if (I == K) {
+              Bm[pI * NP + pI] = b00;
+              Bm[pI * NP + qI] = 0.0;
+              Bm[qI * NP + pI] = 0.0;
+              Bm[qI * NP + qI] = b11;
+            } else {
+              Bm[pI * NP + pK] = b00;
+              Bm[pI * NP + qK] = b01;
+              Bm[qI * NP + pK] = b10;
+              Bm[qI * NP + qK] = b11;
+              Bm[pK * NP + pI] = b00;
+              Bm[qK * NP + pI] = b01;
+              Bm[pK * NP + qI] = b10;
+              Bm[qK * NP + qI] = b11;
+            }
+          }
+        }
+        // V <- V J on slot pairs (2k, 2k+1)
+#pragma unroll
+        for (int k = 0; k < H; ++k) {
+          const double cc = rot[2 * k], ss = rot[2 * k + 1];
+          const double vp = v[2 * k], vq = v[2 * k + 1];
+          v[2 * k] = cc * vp - ss * vq;
+          v[2 * k + 1] = ss * vp + cc * vq;
+        }
+        circ_advance<NP>(v);
+        __syncthreads();
+      }
+    }
+    if (lane < NP) lamv[lane] = Bm[lane * NP + lane];
+    // stage V_j
+    if (lane < NP) {
+#pragma unroll
+      for (int s = 0; s < NP; ++s) Bx[lane * NP + s] = v[s];
+    }
+    __syncthreads();
+    const size_t step = (size_t)b * nt + j;
+    double acc[NP];
+    // O_{j-1} = V_j^T V_{j-1}: row `lane`
+    if (j > j0) {
+#pragma unroll
+      for (int k = 0; k < NP; ++k) acc[k] = 0.0;
+#pragma unroll 1
+    for (int r = 0; r < n; ++r) {
+        const double vri = lane < NP ? Bx[r * NP + lane] : 0.0;
+#pragma unroll
+        for (int k = 0; k < NP; ++k) acc[k] = fma(vri, Bv[r * NP + k], acc[k]);
+      }
+      if (lane < n) {
+        double* dst = a.ov + (step - 1) * nn + (size_t)lane * n;
+#pragma unroll
+        for (int k = 0; k < NP; ++k)
+          if (k < n) dst[k] = acc[k];
+      }
+    }
+    // X = M V_j into Bm (A is no longer needed), row `lane`
+#pragma unroll
+    for (int k = 0; k < NP; ++k) acc[k] = 0.0;
+#pragma unroll 1
+    for (int r = 0; r < n; ++r) {
+      const double mir = lane < n ? a.m[r * n + lane] : 0.0;   // M symmetric
+#pragma unroll
+      for (int k = 0; k < NP; ++k) acc[k] = fma(mir, Bx[r * NP + k], acc[k]);
+    }
+    __syncthreads();
+    if (lane < NP) {
+#pragma unroll
+      for (int k = 0; k < NP; ++k) Bm[lane * NP + k] = acc[k];
+    }
+    __syncthreads();
+    // Mt_j = V_j^T X, row `lane`; goes to Bv (V_{j-1} no longer needed) and to global
+#pragma unroll
+    for (int k = 0; k < NP; ++k) acc[k] = 0.0;
+#pragma unroll 1
+    for (int r = 0; r < n; ++r) {
+      const double vri = lane < NP ? Bx[r * NP + lane] : 0.0;
+#pragma unroll
+      for (int k = 0; k < NP; ++k) acc[k] = fma(vri, Bm[r * NP + k], acc[k]);
+    }
+    if (lane < NP) {
+#pragma unroll
+      for (int k = 0; k < NP; ++k) Bv[lane * NP + k] = acc[k];
+    }
+    if (lane < n) {
+      a.lam[step * n + lane] = lamv[lane];
+      if (a.store_derivs) {
+        double* dm = a.mt + step * nn + (size_t)lane * n;
+        double* ds = a.sm + step * nn + (size_t)lane * n;
+        const double li = lamv[lane];
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+          if (k < n) {
+            dm[k] = acc[k];
+            ds[k] = sinc(0.5 * a.dt * (li - lamv[k])) * acc[k];
+          }
+        }
+      }
+      if (j == j0 || j == j1 - 1) {
+        double* dst = (j == j0 ? a.vfirst : a.vlast) + ((size_t)b * a.nchunks + c) * nn + (size_t)lane * n;
+        for (int k = 0; k < n; ++k) dst[k] = Bx[lane * NP + k];
+      }
+      if (j == j0 && j == j1 - 1) {
+        double* dst = a.vlast + ((size_t)b * a.nchunks + c) * nn + (size_t)lane * n;
+        for (int k = 0; k < n; ++k) dst[k] = Bx[lane * NP + k];
+      }
+    }
+    __syncthreads();
+    // roles for the next step: Mt_j (Bv) becomes A, V_j (Bx) becomes V_{j-1}, Bm is free
+    double* t0 = Bm;
+    Bm = Bv;
+    Bv = Bx;
+    Bx = t0;
+  }
+}
+
 // ---------------------------------------------------------------- sweeps
 
 struct SweepArgs {
@@ -217,11 +488,22 @@ struct SweepArgs {
   const double2* binit;
 };
 
+// Sweep kernels keep the current step's O, S and lambda in LDS (STAGE: n <= 64) and load the
+// next step's into registers while the current step computes, so the dependent chain of
+// steps never waits on HBM.  Product tiles are 4 rows x 1 complex column per thread.
+constexpr int kPrefetch = 16;   // doubles per thread per staged n x n matrix (n*n <= 16*256)
+
+struct StepStage {
+  double po[kPrefetch], ps[kPrefetch];
+  double pl;
+};
+
 // Forward sweep (Alg. 2 lines 1-5 and 13-19, eq. gradatheta) for one theta and one group of
 // tangent columns.  Column 0 carries the state a_j, columns 1..pg the tangents da_j/dtheta_l
 // of the group, all in the eigenbasis of step j:
 //   y_j = U'_j a_j = -i dt h o (S_j (h o a_j)),  h = exp(-i dt l_j / 2)
 //   X   = [phi o a_j | phi o A'_j + y_j F_j^T],  then [a_{j+1} | A'_{j+1}] = O_j X.
+template <bool STAGE>
 __global__ __launch_bounds__(kThreads) void k_forward(SweepArgs a) {
   extern __shared__ double smem[];
   const int g = blockIdx.x, b = blockIdx.y;
@@ -229,13 +511,47 @@ __global__ __launch_bounds__(kThreads) void k_forward(SweepArgs a) {
   const int c0 = g * a.pg;
   const int ncol = max(0, min(a.pg, a.P - c0));
   const int w = 1 + ncol;           // columns carried
-  double2* cur = (double2*)smem;    // [n][w]
+  const size_t nn = (size_t)n * n;
+  double* Ob = smem;                // O_j^T: Ob[r*n + p] = O_j[p][r]
+  double* Sb = Ob + (STAGE ? nn : 0);
+  double2* cur = (double2*)(Sb + (STAGE ? nn : 0));   // [n][w]
   double2* X = cur + n * w;         // [n][w]
   double2* hh = X + n * w;          // [n]
   double2* ph = hh + n;             // [n]
   double2* yv = ph + n;             // [n]
-  const size_t nn = (size_t)n * n;
   const double* Fb = a.F + (size_t)b * a.f_bstride;
+  const size_t sb0 = (size_t)b * nt;
+
+  auto load_step = [&](int j, StepStage& st) {
+    const size_t step = sb0 + j;
+    if (STAGE) {
+#pragma unroll
+      for (int i = 0; i < kPrefetch; ++i) {
+        const int idx = tid + i * kThreads;
+        st.po[i] = (idx < (int)nn && j + 1 < nt) ? a.ov[step * nn + idx] : 0.0;
+        st.ps[i] = (idx < (int)nn && a.need_y) ? a.sm[step * nn + idx] : 0.0;
+      }
+    }
+    st.pl = tid < n ? a.lam[step * n + tid] : 0.0;
+  };
+  auto commit_step = [&](const StepStage& st) {
+    if (STAGE) {
+#pragma unroll
+      for (int i = 0; i < kPrefetch; ++i) {
+        const int idx = tid + i * kThreads;
+        if (idx < (int)nn) {
+          const int pr = idx / n, rr = idx - pr * n;
+          Ob[rr * n + pr] = st.po[i];
+          Sb[idx] = st.ps[i];
+        }
+      }
+    }
+    if (tid < n) {
+      const double2 h = phase(0.5 * st.pl, a.dt);
+      hh[tid] = h;
+      ph[tid] = c_mul(h, h);
+    }
+  };
 
   // a_0 = alpha in basis 0: V_0^T alpha
   const double* V0 = a.vfirst + (size_t)b * a.nchunks * nn;
@@ -251,37 +567,36 @@ __global__ __launch_bounds__(kThreads) void k_forward(SweepArgs a) {
     }
     cur[idx] = v;
   }
+  {
+    StepStage st;
+    load_step(0, st);
+    commit_step(st);
+  }
   __syncthreads();
 
+  const int nrb = (n + 3) / 4;
   for (int j = 0; j < nt; ++j) {
-    const size_t step = (size_t)b * nt + j;
-    const double* lam = a.lam + step * n;
-    for (int p = tid; p < n; p += kThreads) {
-      const double2 h = phase(0.5 * lam[p], a.dt);
-      hh[p] = h;
-      ph[p] = c_mul(h, h);
-    }
-    __syncthreads();
-    const double* S = a.sm + step * nn;
-    for (int p = tid; p < n && a.need_y; p += kThreads) {
+    const size_t step = sb0 + j;
+    StepStage nx;
+    if (j + 1 < nt) load_step(j + 1, nx);
+    const double* S = STAGE ? Sb : a.sm + step * nn;
+    if (a.need_y && tid < n) {
+      const int p = tid;
       double2 acc = make_double2(0.0, 0.0);
       for (int r = 0; r < n; ++r) {
         const double2 t = c_mul(hh[r], cur[r * w]);
-        const double sv = S[p * n + r];
+        const double sv = S[r * n + p];   // S symmetric
         acc.x = fma(sv, t.x, acc.x);
         acc.y = fma(sv, t.y, acc.y);
       }
       const double2 hp = c_mul(hh[p], acc);
-      // -i dt * hp
-      yv[p] = make_double2(a.dt * hp.y, -a.dt * hp.x);
+      yv[p] = make_double2(a.dt * hp.y, -a.dt * hp.x);   // -i dt * hp
     }
     __syncthreads();
-    if (g == 0 && a.need_y) {
-      for (int p = tid; p < n; p += kThreads) {
-        a.at[step * n + p] = cur[p * w];
-        a.yt[step * n + p] = yv[p];
-        if (a.ah) a.ah[step * n + p] = cur[p * w + 1];
-      }
+    if (g == 0 && a.need_y && tid < n) {
+      a.at[step * n + tid] = cur[tid * w];
+      a.yt[step * n + tid] = yv[tid];
+      if (a.ah) a.ah[step * n + tid] = cur[tid * w + 1];
     }
     for (int idx = tid; idx < n * w; idx += kThreads) {
       const int p = idx / w, col = idx - p * w;
@@ -295,17 +610,26 @@ __global__ __launch_bounds__(kThreads) void k_forward(SweepArgs a) {
     }
     __syncthreads();
     if (j + 1 < nt) {
-      const double* Oj = a.ov + step * nn;
-      for (int idx = tid; idx < n * w; idx += kThreads) {
-        const int p = idx / w, col = idx - p * w;
-        double2 acc = make_double2(0.0, 0.0);
+      const double* Og = a.ov + step * nn;
+      for (int t = tid; t < nrb * w; t += kThreads) {
+        const int rb = t / w, col = t - rb * w;
+        const int p0 = rb * 4;
+        double2 acc[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[i] = make_double2(0.0, 0.0);
         for (int r = 0; r < n; ++r) {
-          const double o = Oj[p * n + r];
           const double2 x = X[r * w + col];
-          acc.x = fma(o, x.x, acc.x);
-          acc.y = fma(o, x.y, acc.y);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int p = p0 + i;
+            const double o = p < n ? (STAGE ? Ob[r * n + p] : Og[(size_t)p * n + r]) : 0.0;
+            acc[i].x = fma(o, x.x, acc[i].x);
+            acc[i].y = fma(o, x.y, acc[i].y);
+          }
         }
-        cur[idx] = acc;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (p0 + i < n) cur[(p0 + i) * w + col] = acc[i];
       }
     } else {
       // X holds a_J and A'_J in basis nt-1
@@ -320,6 +644,10 @@ __global__ __launch_bounds__(kThreads) void k_forward(SweepArgs a) {
       }
     }
     __syncthreads();
+    if (j + 1 < nt) {
+      commit_step(nx);
+      __syncthreads();
+    }
   }
 }
 
@@ -370,22 +698,67 @@ __global__ __launch_bounds__(kThreads) void k_terminal(const double2* xf, const 
 // Hessian (two-sweep form): xi_{J-1} = 0, K_j = Re(xi_j^H y_j),
 //   xi_{j-1} = U_j^H xi_j + z_j b_j^T.
 // HVP: mu_J = rho a'_J, mu_j = U_j^H mu_{j+1} + z_j u_j, e_j = Re(mu^H y_j) + Re(z_j^H a'_j).
+struct BwdStage {
+  double po[kPrefetch], ps[kPrefetch];
+  double pl;
+  double2 py, pa;
+};
+
+template <bool STAGE>
 __global__ __launch_bounds__(kThreads) void k_backward(SweepArgs a) {
   extern __shared__ double smem[];
-  __shared__ double red[kThreads];
   const int g = blockIdx.x, b = blockIdx.y;
   const int n = a.n, nt = a.nt, tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
   const int c0 = g * a.pg;
   const int ncol = max(0, min(a.pg, a.P - c0));
   const int w = 1 + ncol;
-  double2* cur = (double2*)smem;
+  const size_t nn = (size_t)n * n;
+  double* Ob = smem;                // O_{j-1} as stored: Ob[r*n + p] = O_{j-1}[r][p]
+  double* Sb = Ob + (STAGE ? nn : 0);
+  double2* cur = (double2*)(Sb + (STAGE ? nn : 0));
   double2* X = cur + n * w;
   double2* hh = X + n * w;
   double2* ph = hh + n;
   double2* zv = ph + n;
   double2* yv = zv + n;
-  const size_t nn = (size_t)n * n;
+  double2* av = yv + n;
   const double* Fb = a.F + (size_t)b * a.f_bstride;
+  const size_t sb0 = (size_t)b * nt;
+
+  auto load_step = [&](int j, BwdStage& st) {
+    const size_t step = sb0 + j;
+    if (STAGE) {
+#pragma unroll
+      for (int i = 0; i < kPrefetch; ++i) {
+        const int idx = tid + i * kThreads;
+        st.po[i] = (idx < (int)nn && j >= 1) ? a.ov[(step - 1) * nn + idx] : 0.0;
+        st.ps[i] = idx < (int)nn ? a.sm[step * nn + idx] : 0.0;
+      }
+    }
+    st.pl = tid < n ? a.lam[step * n + tid] : 0.0;
+    st.py = tid < n ? a.yt[step * n + tid] : make_double2(0.0, 0.0);
+    st.pa = (tid < n && a.hvp) ? a.ah[step * n + tid] : make_double2(0.0, 0.0);
+  };
+  auto commit_step = [&](const BwdStage& st) {
+    if (STAGE) {
+#pragma unroll
+      for (int i = 0; i < kPrefetch; ++i) {
+        const int idx = tid + i * kThreads;
+        if (idx < (int)nn) {
+          Ob[idx] = st.po[i];
+          Sb[idx] = st.ps[i];
+        }
+      }
+    }
+    if (tid < n) {
+      const double2 h = c_conj(phase(0.5 * st.pl, a.dt));   // conj(h)
+      hh[tid] = h;
+      ph[tid] = c_mul(h, h);                                  // conj(phi)
+      yv[tid] = st.py;
+      av[tid] = st.pa;
+    }
+  };
 
   for (int idx = tid; idx < n * w; idx += kThreads) {
     const int p = idx / w, col = idx - p * w;
@@ -394,61 +767,59 @@ __global__ __launch_bounds__(kThreads) void k_backward(SweepArgs a) {
     else if (a.hvp) v = a.binit[((size_t)b * n + p) * 2 + 1];
     cur[idx] = v;
   }
+  {
+    BwdStage st;
+    load_step(nt - 1, st);
+    commit_step(st);
+  }
   __syncthreads();
 
+  const int nrb = (n + 3) / 4;
   for (int j = nt - 1; j >= 0; --j) {
-    const size_t step = (size_t)b * nt + j;
-    const double* lam = a.lam + step * n;
-    for (int p = tid; p < n; p += kThreads) {
-      const double2 h = c_conj(phase(0.5 * lam[p], a.dt));   // conj(h)
-      hh[p] = h;
-      ph[p] = c_mul(h, h);                                  // conj(phi)
-      yv[p] = a.yt[step * n + p];
-    }
-    __syncthreads();
-    const double* S = a.sm + step * nn;
-    for (int p = tid; p < n; p += kThreads) {
+    const size_t step = sb0 + j;
+    BwdStage nx;
+    if (j >= 1) load_step(j - 1, nx);
+    const double* S = STAGE ? Sb : a.sm + step * nn;
+    if (tid < n) {
+      const int p = tid;
       double2 acc = make_double2(0.0, 0.0);
       for (int r = 0; r < n; ++r) {
         const double2 t = c_mul(hh[r], cur[r * w]);
-        const double sv = S[p * n + r];
+        const double sv = S[r * n + p];
         acc.x = fma(sv, t.x, acc.x);
         acc.y = fma(sv, t.y, acc.y);
       }
       const double2 hp = c_mul(hh[p], acc);
-      // i dt * hp
-      zv[p] = make_double2(-a.dt * hp.y, a.dt * hp.x);
+      zv[p] = make_double2(-a.dt * hp.y, a.dt * hp.x);   // i dt * hp
     }
     __syncthreads();
-    // per-step reductions
-    if (g == 0) {
+    // per-step reductions (wave 0) and K_j (one thread per column)
+    if (g == 0 && wv == 0) {
       double lq = 0.0, le = 0.0;
-      for (int p = tid; p < n; p += kThreads) {
+      for (int p = lane; p < n; p += 64) {
         const double2 l = cur[p * w];
         lq += l.x * yv[p].x + l.y * yv[p].y;
         a.mu[step * n + p] = l;
         if (a.hvp) {
           const double2 nu = cur[p * w + 1];
-          const double2 ahv = a.ah[step * n + p];
-          le += nu.x * yv[p].x + nu.y * yv[p].y + zv[p].x * ahv.x + zv[p].y * ahv.y;
+          le += nu.x * yv[p].x + nu.y * yv[p].y + zv[p].x * av[p].x + zv[p].y * av[p].y;
         }
       }
-      const double sq = block_sum(lq, red);
-      if (tid == 0) a.q[step] = sq;
-      if (a.hvp) {
-        const double se = block_sum(le, red);
-        if (tid == 0) a.e[step] = se;
+      lq = wave_sum(lq);
+      if (a.hvp) le = wave_sum(le);
+      if (lane == 0) {
+        a.q[step] = lq;
+        if (a.hvp) a.e[step] = le;
       }
     }
-    if (!a.hvp && a.K) {
-      for (int col = tid; col < ncol; col += kThreads) {
-        double acc = 0.0;
-        for (int p = 0; p < n; ++p) {
-          const double2 xi = cur[p * w + 1 + col];
-          acc += xi.x * yv[p].x + xi.y * yv[p].y;
-        }
-        a.K[step * a.P + c0 + col] = acc;
+    if (!a.hvp && a.K && tid >= 64 && tid - 64 < ncol) {
+      const int col = tid - 64;
+      double acc = 0.0;
+      for (int p = 0; p < n; ++p) {
+        const double2 xi = cur[p * w + 1 + col];
+        acc += xi.x * yv[p].x + xi.y * yv[p].y;
       }
+      a.K[step * a.P + c0 + col] = acc;
     }
     if (j >= 1) {
       for (int idx = tid; idx < n * w; idx += kThreads) {
@@ -462,18 +833,29 @@ __global__ __launch_bounds__(kThreads) void k_backward(SweepArgs a) {
         X[idx] = v;
       }
       __syncthreads();
-      const double* Oj = a.ov + (step - 1) * nn;   // O_{j-1}; apply its transpose
-      for (int idx = tid; idx < n * w; idx += kThreads) {
-        const int p = idx / w, col = idx - p * w;
-        double2 acc = make_double2(0.0, 0.0);
+      const double* Og = a.ov + (step - 1) * nn;   // O_{j-1}; apply its transpose
+      for (int t = tid; t < nrb * w; t += kThreads) {
+        const int rb = t / w, col = t - rb * w;
+        const int p0 = rb * 4;
+        double2 acc[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[i] = make_double2(0.0, 0.0);
         for (int r = 0; r < n; ++r) {
-          const double o = Oj[r * n + p];
           const double2 x = X[r * w + col];
-          acc.x = fma(o, x.x, acc.x);
-          acc.y = fma(o, x.y, acc.y);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int p = p0 + i;
+            const double o = p < n ? (STAGE ? Ob[r * n + p] : Og[(size_t)r * n + p]) : 0.0;
+            acc[i].x = fma(o, x.x, acc[i].x);
+            acc[i].y = fma(o, x.y, acc[i].y);
+          }
         }
-        cur[idx] = acc;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (p0 + i < n) cur[(p0 + i) * w + col] = acc[i];
       }
+      __syncthreads();
+      commit_step(nx);
     }
     __syncthreads();
   }
@@ -482,12 +864,18 @@ __global__ __launch_bounds__(kThreads) void k_backward(SweepArgs a) {
 // ---------------------------------------------------------------- U'' contraction
 
 // s_j = Re(lambda_{j+1}^H U''_j a_j) = Re(mu^H T_j a) in basis j (second derivative of exp in
-// eq. d2Ldf2, Daleckii-Krein form).  T_pq = 2 sum_r phi[l_p, l_r, l_q] Mt_pr Mt_rq.  For a
-// well-separated pair, T_pq = 2 (Y_pq - Y_qp) / (l_p - l_q) with Y = (Phi o Mt) Mt, since
-// Phi_pr - Phi_qr = (l_p - l_q) phi[l_p, l_q, l_r]; close pairs and the diagonal use the
-// stable second divided difference term by term.
+// eq. d2Ldf2, Daleckii-Krein form), T_pq = 2 sum_r phi[l_p, l_r, l_q] Mt_pr Mt_rq.
+//
+// Moment-series evaluation (one wave per (theta, step)).  About the spectral centre m of step
+// j, with x = l - m and c = -i dt, the divided differences of exp(c t) are
+//   phi[l_p, l_r, l_q] = exp(c m) sum_{n>=0} c^{n+2}/(n+2)! h_n(x_p, x_r, x_q),
+// and h_n is a sum of monomials x_p^a x_r^b x_q^d (a+b+d = n), so
+//   mu^H T a = 2 exp(c m) sum_n c^{n+2}/(n+2)! sum_{a+b+d=n} sum_r x_r^b conj(P_a[r]) Q_d[r],
+//   P_a = Mt (x^a o mu),  Q_d = Mt (x^d o a).
+// The series is truncated by the bound |h_n| <= C(n+2,2) (dt r)^n, r = max |x|; a step whose
+// spread is too wide for kStermNmax terms falls back to the pairwise form below.
 struct StermArgs {
-  int n, nt, jper;
+  int n, nt, ntasks;
   double dt, tau;
   const double* mt;
   const double* sm;
@@ -497,72 +885,183 @@ struct StermArgs {
   double* s;
 };
 
-__global__ __launch_bounds__(kThreads) void k_sterm(StermArgs a) {
-  __shared__ double red[kThreads];
-  __shared__ double lam_s[kMaxN];
-  __shared__ double2 h_s[kMaxN], mu_s[kMaxN], at_s[kMaxN];
-  const int b = blockIdx.y, tid = threadIdx.x;
-  const int n = a.n, nt = a.nt;
+constexpr int kStermNmax = 10;
+
+// Pairwise fallback: T_pq = 2 (Y_pq - Y_qp)/(l_p - l_q), Y = (Phi o Mt) Mt for separated pairs,
+// the stable second divided difference term by term for close pairs and the diagonal.
+__device__ double sterm_pairs_wave(const StermArgs& a, size_t step, int lane) {
+  const int n = a.n;
   const size_t nn = (size_t)n * n;
+  const double* Mt = a.mt + step * nn;
+  const double* S = a.sm + step * nn;
+  const double* lam = a.lam + step * n;
+  const double2* mu = a.mu + step * n;
+  const double2* at = a.at + step * n;
   const int npairs = n * (n + 1) / 2;
-  const int jb = blockIdx.x * a.jper;
-  const int je = min(nt, jb + a.jper);
-  for (int j = jb; j < je; ++j) {
-    const size_t step = (size_t)b * nt + j;
-    for (int p = tid; p < n; p += kThreads) {
-      lam_s[p] = a.lam[step * n + p];
-      h_s[p] = phase(0.5 * lam_s[p], a.dt);
-      mu_s[p] = a.mu[step * n + p];
-      at_s[p] = a.at[step * n + p];
-    }
-    __syncthreads();
-    const double* Mt = a.mt + step * nn;
-    const double* S = a.sm + step * nn;
-    double loc = 0.0;
-    for (int w = tid; w < npairs; w += kThreads) {
-      // decode w -> (p, q), p <= q
-      int p = (int)((2.0 * n + 1.0 - sqrt((2.0 * n + 1.0) * (2.0 * n + 1.0) - 8.0 * w)) * 0.5);
-      if (p < 0) p = 0;
-      while (p > 0 && p * n - p * (p - 1) / 2 > w) --p;
-      while ((p + 1) * n - (p + 1) * p / 2 <= w) ++p;
-      const int q = p + (w - (p * n - p * (p - 1) / 2));
-      const double lp = lam_s[p], lq = lam_s[q];
-      double2 tpq;
-      if (p == q || a.dt * fabs(lp - lq) < a.tau) {
-        double2 acc = make_double2(0.0, 0.0);
-        for (int r = 0; r < n; ++r) {
-          const double2 d = dd2(lp, lam_s[r], lq, a.dt);
-          const double mm = Mt[p * n + r] * Mt[r * n + q];
-          acc.x = fma(d.x, mm, acc.x);
-          acc.y = fma(d.y, mm, acc.y);
-        }
-        tpq = c_scale(acc, 2.0);
-      } else {
-        // Y_pq = -i dt h_p sum_r S_pr h_r Mt_rq
-        double2 ypq = make_double2(0.0, 0.0), yqp = make_double2(0.0, 0.0);
-        for (int r = 0; r < n; ++r) {
-          const double2 hr = h_s[r];
-          const double c1 = S[p * n + r] * Mt[r * n + q];
-          const double c2 = S[q * n + r] * Mt[r * n + p];
-          ypq.x = fma(c1, hr.x, ypq.x);
-          ypq.y = fma(c1, hr.y, ypq.y);
-          yqp.x = fma(c2, hr.x, yqp.x);
-          yqp.y = fma(c2, hr.y, yqp.y);
-        }
-        ypq = c_mul(h_s[p], ypq);
-        yqp = c_mul(h_s[q], yqp);
-        const double2 dif = c_sub(ypq, yqp);
-        // -i dt * dif * 2 / (lp - lq)
-        const double sc = 2.0 * a.dt / (lp - lq);
-        tpq = make_double2(sc * dif.y, -sc * dif.x);
+  double loc = 0.0;
+  for (int w = lane; w < npairs; w += 64) {
+    int p = (int)((2.0 * n + 1.0 - sqrt((2.0 * n + 1.0) * (2.0 * n + 1.0) - 8.0 * w)) * 0.5);
+    if (p < 0) p = 0;
+    while (p > 0 && p * n - p * (p - 1) / 2 > w) --p;
+    while ((p + 1) * n - (p + 1) * p / 2 <= w) ++p;
+    const int q = p + (w - (p * n - p * (p - 1) / 2));
+    const double lp = lam[p], lq = lam[q];
+    double2 tpq;
+    if (p == q || a.dt * fabs(lp - lq) < a.tau) {
+      double2 acc = make_double2(0.0, 0.0);
+      for (int r = 0; r < n; ++r) {
+        const double2 d = dd2(lp, lam[r], lq, a.dt);
+        const double mm = Mt[p * n + r] * Mt[r * n + q];
+        acc.x = fma(d.x, mm, acc.x);
+        acc.y = fma(d.y, mm, acc.y);
       }
-      // weight conj(mu_p) a_q (+ conj(mu_q) a_p for p != q)
-      double2 wgt = c_cmul(mu_s[p], at_s[q]);
-      if (p != q) wgt = c_add(wgt, c_cmul(mu_s[q], at_s[p]));
-      loc += wgt.x * tpq.x - wgt.y * tpq.y;
+      tpq = c_scale(acc, 2.0);
+    } else {
+      double2 ypq = make_double2(0.0, 0.0), yqp = make_double2(0.0, 0.0);
+      for (int r = 0; r < n; ++r) {
+        const double2 hr = phase(0.5 * lam[r], a.dt);
+        const double c1 = S[p * n + r] * Mt[r * n + q];
+        const double c2 = S[q * n + r] * Mt[r * n + p];
+        ypq.x = fma(c1, hr.x, ypq.x);
+        ypq.y = fma(c1, hr.y, ypq.y);
+        yqp.x = fma(c2, hr.x, yqp.x);
+        yqp.y = fma(c2, hr.y, yqp.y);
+      }
+      ypq = c_mul(phase(0.5 * lp, a.dt), ypq);
+      yqp = c_mul(phase(0.5 * lq, a.dt), yqp);
+      const double2 dif = c_sub(ypq, yqp);
+      const double sc = 2.0 * a.dt / (lp - lq);
+      tpq = make_double2(sc * dif.y, -sc * dif.x);
     }
-    const double tot = block_sum(loc, red);
-    if (tid == 0) a.s[step] = tot;
+    double2 wgt = c_cmul(mu[p], at[q]);
+    if (p != q) wgt = c_add(wgt, c_cmul(mu[q], at[p]));
+    loc += wgt.x * tpq.x - wgt.y * tpq.y;
+  }
+  return wave_sum(loc);
+}
+
+__global__ __launch_bounds__(kThreads) void k_sterm_wave(StermArgs a) {
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int n = a.n;
+  const size_t nn = (size_t)n * n;
+  const int wpb = kThreads / 64;
+  for (int task = blockIdx.x * wpb + wv; task < a.ntasks; task += gridDim.x * wpb) {
+    const size_t step = (size_t)task;
+    const double* lam = a.lam + step * n;
+    // per-lane copies of x, mu, a for rows lane and lane + 64
+    double lv[2];
+    double2 mv[2], av[2];
+    double lo = 1e300, hi = -1e300;
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int p = lane + 64 * e;
+      lv[e] = 0.0;
+      mv[e] = make_double2(0.0, 0.0);
+      av[e] = make_double2(0.0, 0.0);
+      if (p < n) {
+        lv[e] = lam[p];
+        mv[e] = a.mu[step * n + p];
+        av[e] = a.at[step * n + p];
+        lo = fmin(lo, lv[e]);
+        hi = fmax(hi, lv[e]);
+      }
+    }
+    lo = wave_min(lo);
+    hi = wave_max(hi);
+    const double m0 = 0.5 * (lo + hi);
+    const double del = 0.5 * a.dt * (hi - lo);
+    // number of terms: first omitted term bounded by (n+2)(n+3) del^(n+1) / (n+3)!
+    int nmax = -1;
+    {
+      double dp = del, fact = 6.0;
+      for (int k = 0; k <= kStermNmax; ++k) {
+        if ((k + 2.0) * (k + 3.0) * dp / fact < 1e-17) {
+          nmax = k;
+          break;
+        }
+        dp *= del;
+        fact *= (double)(k + 4);
+      }
+    }
+    double sval;
+    if (nmax < 0) {
+      sval = sterm_pairs_wave(a, step, lane);
+    } else {
+      // coefficients c^{k+2}/(k+2)!, c = -i dt
+      double2 coef[kStermNmax + 1];
+      {
+        double mag = 0.5 * a.dt * a.dt;
+#pragma unroll
+        for (int k = 0; k <= kStermNmax; ++k) {
+          // (-i)^(k+2): k%4 = 0:-1, 1:i, 2:1, 3:-i
+          const int r4 = k & 3;
+          coef[k] = r4 == 0 ? make_double2(-mag, 0.0)
+                  : r4 == 1 ? make_double2(0.0, mag)
+                  : r4 == 2 ? make_double2(mag, 0.0)
+                            : make_double2(0.0, -mag);
+          mag *= a.dt / (double)(k + 3);
+        }
+      }
+      const double x0 = lv[0] - m0, x1 = lv[1] - m0;
+      const double* Mt = a.mt + step * nn;
+      double2 contrib = make_double2(0.0, 0.0);
+      for (int rb = 0; rb * 64 < n; ++rb) {
+        const int p = lane + 64 * rb;
+        double2 P[kStermNmax + 1], Q[kStermNmax + 1];
+#pragma unroll
+        for (int k = 0; k <= kStermNmax; ++k) {
+          P[k] = make_double2(0.0, 0.0);
+          Q[k] = make_double2(0.0, 0.0);
+        }
+        for (int qi = 0; qi < n; ++qi) {
+          const int e = qi >> 6, ql = qi & 63;
+          const double xq = readlane_d(e ? x1 : x0, ql);
+          const double2 muq = make_double2(readlane_d(e ? mv[1].x : mv[0].x, ql), readlane_d(e ? mv[1].y : mv[0].y, ql));
+          const double2 atq = make_double2(readlane_d(e ? av[1].x : av[0].x, ql), readlane_d(e ? av[1].y : av[0].y, ql));
+          const double mt = p < n ? Mt[(size_t)qi * n + p] : 0.0;   // Mt symmetric: coalesced column read
+          double2 t1 = c_scale(muq, mt), t2 = c_scale(atq, mt);
+#pragma unroll
+          for (int k = 0; k <= kStermNmax; ++k) {
+            if (k <= nmax) {
+              P[k].x += t1.x;
+              P[k].y += t1.y;
+              Q[k].x += t2.x;
+              Q[k].y += t2.y;
+              t1 = c_scale(t1, xq);
+              t2 = c_scale(t2, xq);
+            }
+          }
+        }
+        if (p < n) {
+          const double xp = rb ? x1 : x0;
+#pragma unroll
+          for (int m = 0; m <= kStermNmax; ++m) {
+            if (m <= nmax) {
+              // R_m = sum_{a<=m} conj(P_a) Q_{m-a}
+              double2 R = make_double2(0.0, 0.0);
+#pragma unroll
+              for (int aa = 0; aa <= kStermNmax; ++aa) {
+                if (aa <= m) R = c_add(R, c_cmul(P[aa], Q[m - aa]));
+              }
+              // w_m = sum_{b <= nmax-m} coef_{m+b} xp^b   (Horner)
+              double2 wm = make_double2(0.0, 0.0);
+#pragma unroll
+              for (int bb = kStermNmax; bb >= 0; --bb) {
+                if (bb <= nmax - m) {
+                  wm = c_scale(wm, xp);
+                  wm = c_add(wm, coef[m + bb]);
+                }
+              }
+              contrib = c_add(contrib, c_mul(R, wm));
+            }
+          }
+        }
+      }
+      double2 tot = make_double2(wave_sum(contrib.x), wave_sum(contrib.y));
+      tot = c_mul(phase(m0, a.dt), tot);
+      sval = 2.0 * tot.x;
+    }
+    if (lane == 0) a.s[step] = sval;
   }
 }
 
@@ -741,18 +1240,21 @@ static size_t eig_lds_bytes(int np, bool lds_mats) {
 
 static bool eig_fits_lds(int np) { return eig_lds_bytes(np, true) <= 160 * 1024; }
 
+static bool sweep_stage(int n) { return n * n <= kPrefetch * kThreads; }
+
 static size_t sweep_lds_bytes(int n, int pg) {
-  return ((size_t)2 * n * (1 + pg) + 4 * n) * sizeof(double2);
+  const size_t mats = sweep_stage(n) ? (size_t)2 * n * n * sizeof(double) : 0;
+  return mats + ((size_t)2 * n * (1 + pg) + 5 * n) * sizeof(double2);
 }
 
 hipError_t configure_kernels() {
-  hipError_t e = hipFuncSetAttribute((const void*)k_eig_chunk, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     160 * 1024);
-  if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute((const void*)k_forward, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)k_backward, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             160 * 1024 - kThreads * 8);
+  const void* fns[] = {(const void*)k_eig_chunk, (const void*)k_eig_wave<36>, (const void*)k_forward<true>, (const void*)k_forward<false>,
+                       (const void*)k_backward<true>, (const void*)k_backward<false>};
+  for (const void* f : fns) {
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 size_t eig_scratch_doubles(int n, int nb, int nchunks) {
@@ -762,8 +1264,9 @@ size_t eig_scratch_doubles(int n, int nb, int nchunks) {
 }
 
 int choose_pg(int P, int nb) {
+  (void)nb;
   if (P <= 0) return 1;
-  int pg = nb >= 64 ? kMaxPg : 8;
+  int pg = 8;
   if (pg > P) pg = P;
   return pg;
 }
@@ -803,16 +1306,32 @@ hipError_t launch_eig(const SysDev& sy, const BasisDev& bs, Work& w, bool store_
   a.vlast = w.vlast;
   a.gscratch = w.gscratch;
   a.status = w.status;
+  a.stats = w.stats;
+  switch (w.np) {
+#define QOC_EIG_WAVE(NPV)                                                                               \
+  case NPV: {                                                                                          \
+    const size_t lds = ((size_t)3 * NPV * NPV + 2 * NPV + (NPV + 1) / 2) * sizeof(double);           \
+    hipLaunchKernelGGL(k_eig_wave<NPV>, dim3(w.nchunks, w.nb), dim3(64), lds, stream, a);              \
+    return hipGetLastError();                                                                          \
+  }
+    QOC_EIG_WAVE(4)
+    QOC_EIG_WAVE(8)
+    QOC_EIG_WAVE(16)
+    QOC_EIG_WAVE(36)
+#undef QOC_EIG_WAVE
+    default:
+      break;
+  }
   const size_t lds = eig_lds_bytes(w.np, a.lds_mats != 0);
   hipLaunchKernelGGL(k_eig_chunk, dim3(w.nchunks, w.nb), dim3(kThreads), lds, stream, a);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  if (w.nchunks > 1) {
-    hipLaunchKernelGGL(k_boundary_overlap, dim3(w.nchunks - 1, w.nb), dim3(kThreads), 0, stream, w.vfirst,
-                       w.vlast, w.ov, w.n, w.nt, w.chunk, w.nchunks);
-    e = hipGetLastError();
-  }
-  return e;
+  return hipGetLastError();
+}
+
+hipError_t launch_boundary(Work& w, hipStream_t stream) {
+  if (w.nchunks <= 1) return hipSuccess;
+  hipLaunchKernelGGL(k_boundary_overlap, dim3(w.nchunks - 1, w.nb), dim3(kThreads), 0, stream, w.vfirst, w.vlast,
+                     w.ov, w.n, w.nt, w.chunk, w.nchunks);
+  return hipGetLastError();
 }
 
 static SweepArgs sweep_args(const SysDev& sy, const BasisDev& bs, Work& w, Mode mode) {
@@ -861,7 +1380,10 @@ static SweepArgs sweep_args(const SysDev& sy, const BasisDev& bs, Work& w, Mode 
 hipError_t launch_forward(const SysDev& sy, const BasisDev& bs, Work& w, Mode mode, hipStream_t stream) {
   SweepArgs a = sweep_args(sy, bs, w, mode);
   const size_t lds = sweep_lds_bytes(w.n, a.P > 0 ? a.pg : 0);
-  hipLaunchKernelGGL(k_forward, dim3(a.ngroups, w.nb), dim3(kThreads), lds, stream, a);
+  if (sweep_stage(w.n))
+    hipLaunchKernelGGL(k_forward<true>, dim3(a.ngroups, w.nb), dim3(kThreads), lds, stream, a);
+  else
+    hipLaunchKernelGGL(k_forward<false>, dim3(a.ngroups, w.nb), dim3(kThreads), lds, stream, a);
   return hipGetLastError();
 }
 
@@ -875,8 +1397,11 @@ hipError_t launch_terminal(const SysDev& sy, const BasisDev& bs, Work& w, Mode m
 
 hipError_t launch_backward(const SysDev& sy, const BasisDev& bs, Work& w, Mode mode, hipStream_t stream) {
   SweepArgs a = sweep_args(sy, bs, w, mode);
-  const size_t lds = sweep_lds_bytes(w.n, a.P > 0 ? a.pg : 0) + 2 * w.n * sizeof(double2);
-  hipLaunchKernelGGL(k_backward, dim3(a.ngroups, w.nb), dim3(kThreads), lds, stream, a);
+  const size_t lds = sweep_lds_bytes(w.n, a.P > 0 ? a.pg : 0);
+  if (sweep_stage(w.n))
+    hipLaunchKernelGGL(k_backward<true>, dim3(a.ngroups, w.nb), dim3(kThreads), lds, stream, a);
+  else
+    hipLaunchKernelGGL(k_backward<false>, dim3(a.ngroups, w.nb), dim3(kThreads), lds, stream, a);
   return hipGetLastError();
 }
 
@@ -884,7 +1409,7 @@ hipError_t launch_sterm(const SysDev& sy, const BasisDev& bs, Work& w, hipStream
   StermArgs a;
   a.n = w.n;
   a.nt = w.nt;
-  a.jper = 8;
+  a.ntasks = w.nt * w.nb;
   a.dt = bs.dt;
   a.tau = 1e-3;
   a.mt = w.mt;
@@ -893,7 +1418,10 @@ hipError_t launch_sterm(const SysDev& sy, const BasisDev& bs, Work& w, hipStream
   a.mu = w.mu;
   a.at = w.at;
   a.s = w.s;
-  hipLaunchKernelGGL(k_sterm, dim3((w.nt + a.jper - 1) / a.jper, w.nb), dim3(kThreads), 0, stream, a);
+  const int wpb = kThreads / 64;
+  int blocks = (a.ntasks + wpb - 1) / wpb;
+  if (blocks > 256 * 64) blocks = 256 * 64;
+  hipLaunchKernelGGL(k_sterm_wave, dim3(blocks), dim3(kThreads), 0, stream, a);
   return hipGetLastError();
 }
 

@@ -69,6 +69,9 @@ SIGNATURES = {
     "qoc_batch_hess_unbatched": (_st, [_vp, ctypes.POINTER(_dp), ctypes.POINTER(_dp),
                                        ctypes.POINTER(_dp), ctypes.POINTER(_dp)]),
     "qoc_batch_last_error": (ctypes.c_char_p, [_vp]),
+    "qoc_profile_enable": (_st, [_vp, _i32]),
+    "qoc_profile_kernel_ms": (_st, [_vp, ctypes.c_char_p, _dp, ctypes.POINTER(_i32)]),
+    "qoc_jacobi_stats": (_st, [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64), _i32]),
     "qoc_status_string": (ctypes.c_char_p, [_st]),
     "qoc_last_error": (ctypes.c_char_p, [_vp]),
 }
@@ -256,6 +259,22 @@ class Problem:
 
     def sync(self):
         self._check(lib().qoc_sync(self._h))
+
+    # -- profiling
+    def profile_enable(self, on: bool = True):
+        self._check(lib().qoc_profile_enable(self._h, 1 if on else 0))
+
+    def profile_kernel_ms(self, kernel: str):
+        ms = np.zeros(1)
+        n = _i32()
+        self._check(lib().qoc_profile_kernel_ms(self._h, kernel.encode(), _ptr(ms), ctypes.byref(n)))
+        return float(ms[0]), int(n.value)
+
+    def jacobi_stats(self, reset: bool = True):
+        st = ctypes.c_int64()
+        sw = ctypes.c_int64()
+        self._check(lib().qoc_jacobi_stats(self._h, ctypes.byref(st), ctypes.byref(sw), 1 if reset else 0))
+        return int(st.value), int(sw.value)
 
     # -- inspection and solvers
     def step_propagators(self, theta, j: int):

@@ -47,6 +47,10 @@ CASES = [
     ("tiny-odd5-ragged", "tiny", dict(n=5, nt=37, k=3), 0.3),
     ("molecule-short", "molecule", dict(nt=300), 0.1),
     ("warm-short", "warm", dict(nt=60, k=8), 0.1),
+    # dt * spectral radius far beyond the moment-series range: pairwise U'' fallback
+    ("wide-spread-dt0.8", "tiny", dict(n=6, nt=20, dt=0.8, k=2), 0.5),
+    # n above the LDS staging limit of the sweeps, odd, ragged chunks
+    ("n67-unstaged", "tiny", dict(n=67, nt=21, k=2), 0.2),
 ]
 
 
