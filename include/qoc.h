@@ -100,6 +100,9 @@ qoc_status qoc_hess_many(qoc_problem* p, int32_t count, const double* thetas,
                          double* costs, double* grads, double* hess);
 qoc_status qoc_grad_many(qoc_problem* p, int32_t count, const double* thetas,
                          double* costs, double* grads);
+/* As qoc_hess_many with one target state per theta: targets is count x 2n doubles (complex). */
+qoc_status qoc_hess_many_targets(qoc_problem* p, int32_t count, const double* thetas, const double* targets,
+                                 double* costs, double* grads, double* hess);
 
 /* Device-pointer twins (same kernels, enqueue only, no synchronisation). */
 qoc_status qoc_cost_dev(qoc_problem* p, const double* theta, double* cost);
@@ -131,6 +134,14 @@ qoc_status qoc_memory_usage(const qoc_problem* p, int64_t* current_bytes, int64_
  * max_iter is reached. */
 qoc_status qoc_tr_solve(qoc_problem* p, const double* theta0, double gtol, int32_t max_iter,
                         double* theta_out, double* cost_out, int32_t* iters_out);
+/* `count` independent trust-region solves advanced in lockstep (one batched Hessian evaluation
+ * and one batched P x P eigendecomposition per iteration).  theta0: count x P; targets: NULL
+ * (handle's target for all) or count x 2n doubles; outputs count x P / count / count / count
+ * (any may be NULL except theta_out).  converged_out[i] = 1 if ||grad||_2 < gtol was reached.
+ * Returns QOC_OK even if some solves did not converge (see converged_out). */
+qoc_status qoc_tr_solve_many(qoc_problem* p, int32_t count, const double* theta0, const double* targets,
+                             double gtol, int32_t max_iter, double* theta_out, double* cost_out,
+                             int32_t* iters_out, int32_t* converged_out);
 
 /* Batched evaluation of independent problems of uneven (n, nt, P) in one persistent launch
  * sequence (captured as a HIP graph on first use).  problems: `count` configured handles on

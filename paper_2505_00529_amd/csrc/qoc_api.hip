@@ -19,7 +19,6 @@ using namespace qoc;
 namespace {
 
 constexpr double kJacobiTol = 1e-15;   // off-diagonal target relative to ||H_j||_F
-constexpr int kJacobiMaxSweeps = 40;
 
 std::mutex g_cfg_mu;
 bool g_cfg_done[64] = {false};
@@ -96,6 +95,7 @@ qoc_problem::~qoc_problem() {
   dfree(d_status, sizeof(int));
   dfree(d_stats, 2 * sizeof(unsigned long long));
   dfree(d_props, props_bytes);
+  dfree(d_tr, tr_bytes);
   (void)prof_collect();
   for (hipEvent_t e : prof_pool) (void)hipEventDestroy(e);
   if (own_stream && stream) (void)hipStreamDestroy(stream);
@@ -186,7 +186,7 @@ qoc_status qoc_problem::ready() {
 
 // Enqueue one evaluation of `nb` thetas (device pointers) on the handle's stream.
 qoc_status qoc_problem::enqueue(Mode mode, int nb, const double* d_theta, const double* d_v, double* d_cost,
-                                double* d_grad, double* d_out) {
+                                double* d_grad, double* d_out, const double* d_targets) {
   qoc_status st = ensure_work(nb);
   if (st != QOC_OK) return st;
   SysDev sy;
@@ -194,7 +194,8 @@ qoc_status qoc_problem::enqueue(Mode mode, int nb, const double* d_theta, const 
   sy.h0 = d_h0;
   sy.m = d_m;
   sy.psi0 = d_psi0;
-  sy.psit = d_psit;
+  sy.psit = d_targets ? d_targets : d_psit;
+  sy.psit_bstride = d_targets ? (size_t)2 * n : 0;
   BasisDev bs;
   bs.nt = nt;
   bs.P = P;
@@ -281,7 +282,7 @@ qoc_status qoc_problem::check_device_status() {
 
 // Host-pointer evaluation of `count` thetas: stage, enqueue, copy back, synchronise.
 qoc_status qoc_problem::run_host(Mode mode, int count, const double* theta, const double* v, double* cost,
-                                 double* grad, double* out) {
+                                 double* grad, double* out, const double* targets) {
   qoc_status st = ready();
   if (st != QOC_OK) return st;
   if (count < 1 || !theta) return fail(QOC_ERR_INVALID_ARG, "theta must be non-NULL and count >= 1");
@@ -290,20 +291,26 @@ qoc_status qoc_problem::run_host(Mode mode, int count, const double* theta, cons
     if (!v) return fail(QOC_ERR_INVALID_ARG, "v must be non-NULL");
     if (!all_finite(v, (size_t)count * P)) return fail(QOC_ERR_INVALID_ARG, "v has non-finite entries");
   }
+  if (targets && !all_finite(targets, (size_t)count * 2 * n))
+    return fail(QOC_ERR_INVALID_ARG, "targets have non-finite entries");
   const size_t nth = (size_t)count * P;
   const size_t nout = mode == Mode::Hess ? (size_t)count * P * P : (mode == Mode::Hvp ? nth : 0);
-  st = ensure_io(2 * nth + count + nth + nout);
+  const size_t ntg = targets ? (size_t)count * 2 * n : 0;
+  st = ensure_io(2 * nth + count + nth + nout + ntg);
   if (st != QOC_OK) return st;
   double* d_th = d_io;
   double* d_vv = d_th + nth;
   double* d_c = d_vv + nth;
   double* d_g = d_c + count;
   double* d_o = d_g + nth;
+  double* d_tg = d_o + nout;
   hipError_t e = hipMemcpyAsync(d_th, theta, nth * sizeof(double), hipMemcpyHostToDevice, stream);
   if (e == hipSuccess && mode == Mode::Hvp)
     e = hipMemcpyAsync(d_vv, v, nth * sizeof(double), hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess && targets) e = hipMemcpyAsync(d_tg, targets, ntg * sizeof(double), hipMemcpyHostToDevice, stream);
   if (e != hipSuccess) return hip_fail(e, "input upload");
-  st = enqueue(mode, count, d_th, d_vv, d_c, mode == Mode::Cost ? nullptr : d_g, nout ? d_o : nullptr);
+  st = enqueue(mode, count, d_th, d_vv, d_c, mode == Mode::Cost ? nullptr : d_g, nout ? d_o : nullptr,
+               targets ? d_tg : nullptr);
   if (st != QOC_OK) return st;
   std::vector<double> hc(count), hg(mode == Mode::Cost ? 0 : nth), ho(nout);
   e = hipMemcpyAsync(hc.data(), d_c, count * sizeof(double), hipMemcpyDeviceToHost, stream);
@@ -511,6 +518,7 @@ qoc_status qoc_set_control_basis(qoc_problem* p, qoc_basis_kind kind, int32_t nt
   p->dt = dt;
   p->P = P;
   p->kind = kind;
+  p->basis_version += 1;
   if (!p->weights_explicit) {
     p->gamma = 2.0 * dt;
     p->rho = 2.0;
@@ -564,6 +572,13 @@ qoc_status qoc_hess_many(qoc_problem* p, int32_t count, const double* thetas, do
                          double* hess) {
   if (!p) return QOC_ERR_INVALID_ARG;
   return p->run_host(Mode::Hess, count, thetas, nullptr, costs, grads, hess);
+}
+
+qoc_status qoc_hess_many_targets(qoc_problem* p, int32_t count, const double* thetas, const double* targets,
+                                 double* costs, double* grads, double* hess) {
+  if (!p) return QOC_ERR_INVALID_ARG;
+  if (!targets) return p->fail(QOC_ERR_INVALID_ARG, "NULL targets");
+  return p->run_host(Mode::Hess, count, thetas, nullptr, costs, grads, hess, targets);
 }
 
 qoc_status qoc_grad_many(qoc_problem* p, int32_t count, const double* thetas, double* costs, double* grads) {

@@ -76,8 +76,16 @@ struct qoc_problem {
   qoc_status ensure_io(size_t doubles);
   qoc_status ready();
   qoc_status enqueue(qoc::Mode mode, int nb, const double* d_theta, const double* d_v, double* d_cost,
-                     double* d_grad, double* d_out);
+                     double* d_grad, double* d_out, const double* d_targets = nullptr);
   qoc_status check_device_status();
+  // targets: NULL (handle's target) or count x 2n doubles (one complex target per theta)
   qoc_status run_host(qoc::Mode mode, int count, const double* theta, const double* v, double* cost, double* grad,
-                      double* out);
+                      double* out, const double* targets = nullptr);
+  // trust-region solver state
+  double* d_tr = nullptr;
+  size_t tr_bytes = 0;
+  std::vector<double> tr_whiten;   // P x rank whitening of the control-space trust region
+  int tr_rank = 0;
+  int tr_basis_version = -1;
+  int basis_version = 0;
 };

@@ -53,7 +53,8 @@ struct SysDev {
   const double* h0 = nullptr;     // [n][n]
   const double* m = nullptr;      // [n][n]
   const double* psi0 = nullptr;   // [n] complex
-  const double* psit = nullptr;   // [n] complex
+  const double* psit = nullptr;   // [n] complex, or [nb][n] complex when psit_bstride != 0
+  size_t psit_bstride = 0;        // doubles between consecutive thetas' targets (0: shared target)
 };
 
 struct BasisDev {
@@ -83,6 +84,12 @@ hipError_t launch_identity_basis(double* B, int nt, hipStream_t stream);
 hipError_t launch_step_props(const SysDev& sy, double fj, double dt, double* gs, double* u, double* u1,
                              double* u2, int* status, hipStream_t stream);
 size_t step_props_scratch_doubles(int n);
+// Batched symmetric eigendecomposition (parallel-order Jacobi, one workgroup per matrix):
+// h: count x P x P (symmetrised on the fly), evals: count x P, evecs: count x P x P (column i
+// is eigenvector i).  gs: device scratch of sym_eig_scratch_doubles(P, count) doubles.
+hipError_t launch_sym_eig(const double* h, int P, int count, double* evals, double* evecs, double* gs,
+                          int* status, hipStream_t stream);
+size_t sym_eig_scratch_doubles(int P, int count);
 
 // Largest dynamic LDS request of any kernel; set once per device.
 hipError_t configure_kernels();

@@ -655,11 +655,13 @@ __global__ __launch_bounds__(kThreads) void k_forward(SweepArgs a) {
 // r = a_J - beta in basis nt-1 (r^ = X_0 - V_{J-1}^T beta), |r|^2, lambda_J = rho r,
 // HVP: mu_J = rho a'_J; Hessian: rho Re(A'_J^H A'_J).
 __global__ __launch_bounds__(kThreads) void k_terminal(const double2* xf, const double* vlast,
-                                                       const double* psit, double2* binit, double* rr,
+                                                       const double* psit_all, size_t psit_bstride,
+                                                       double2* binit, double* rr,
                                                        double* aa, int n, int P, int nchunks, int mode,
                                                        double rho) {
   __shared__ double red[kThreads];
   const int b = blockIdx.x, tid = threadIdx.x;
+  const double* psit = psit_all + (size_t)b * psit_bstride;
   const size_t nn = (size_t)n * n;
   const double* V = vlast + ((size_t)b * nchunks + nchunks - 1) * nn;
   const double2* X = xf + (size_t)b * n * (1 + P);
@@ -1230,6 +1232,66 @@ __global__ __launch_bounds__(kThreads) void k_identity_basis(double* B, int nt) 
   B[idx] = (idx / nt == idx % nt) ? 1.0 : 0.0;
 }
 
+// ---------------------------------------------------------------- batched symmetric eigensolver
+
+// One workgroup per P x P symmetric matrix (trust-region subproblems): the same parallel-order
+// Jacobi as the propagator eigen-data, on (H + H^T)/2.  Matrices in LDS when they fit.
+__global__ __launch_bounds__(kThreads) void k_sym_eig(const double* h, int P, int np, double* evals,
+                                                      double* evecs, double* gs, int lds_mats, double tol_rel,
+                                                      int max_sweeps, int* status) {
+  extern __shared__ double smem[];
+  const int b = blockIdx.x, tid = threadIdx.x;
+  double* rot = smem;
+  double* red = rot + np;
+  int* prs = (int*)(red + kThreads);
+  double* A;
+  double* V;
+  if (lds_mats) {
+    A = smem + np + kThreads + (np + 1) / 2 + 1;
+  } else {
+    A = gs + (size_t)b * 2 * np * np;
+  }
+  V = A + (size_t)np * np;
+  const double* H = h + (size_t)b * P * P;
+  for (int idx = tid; idx < np * np; idx += kThreads) {
+    const int i = idx / np, k = idx - i * np;
+    A[idx] = (i < P && k < P) ? 0.5 * (H[i * P + k] + H[k * P + i]) : 0.0;
+    V[idx] = i == k ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  double loc = 0.0;
+  for (int idx = tid; idx < np * np; idx += kThreads) loc += A[idx] * A[idx];
+  const double fro = sqrt(block_sum(loc, red));
+  const bool ok = jacobi_eig(A, V, np, tol_rel * fro, max_sweeps, rot, prs, red, nullptr);
+  if (!ok && tid == 0) atomicOr(status, kStatusNoConv);
+  for (int i = tid; i < P; i += kThreads) evals[(size_t)b * P + i] = A[i * np + i];
+  for (int idx = tid; idx < P * P; idx += kThreads) {
+    const int i = idx / P, k = idx - i * P;
+    evecs[(size_t)b * P * P + idx] = V[i * np + k];
+  }
+}
+
+static size_t sym_eig_lds(int np, bool mats) {
+  size_t d = (size_t)np + kThreads + (np + 1) / 2 + 1;
+  if (mats) d += (size_t)2 * np * np;
+  return d * sizeof(double);
+}
+
+size_t sym_eig_scratch_doubles(int P, int count) {
+  const int np = pad_even(P);
+  if (sym_eig_lds(np, true) <= 160 * 1024) return 0;
+  return (size_t)count * 2 * np * np;
+}
+
+hipError_t launch_sym_eig(const double* h, int P, int count, double* evals, double* evecs, double* gs, int* status,
+                          hipStream_t stream) {
+  const int np = pad_even(P);
+  const bool mats = sym_eig_lds(np, true) <= 160 * 1024;
+  hipLaunchKernelGGL(k_sym_eig, dim3(count), dim3(kThreads), sym_eig_lds(np, mats), stream, h, P, np, evals, evecs,
+                     gs, mats ? 1 : 0, 1e-15, 60, status);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- launchers
 
 static size_t eig_lds_bytes(int np, bool lds_mats) {
@@ -1248,7 +1310,7 @@ static size_t sweep_lds_bytes(int n, int pg) {
 }
 
 hipError_t configure_kernels() {
-  const void* fns[] = {(const void*)k_eig_chunk, (const void*)k_eig_wave<36>, (const void*)k_forward<true>, (const void*)k_forward<false>,
+  const void* fns[] = {(const void*)k_eig_chunk, (const void*)k_eig_wave<36>, (const void*)k_sym_eig, (const void*)k_forward<true>, (const void*)k_forward<false>,
                        (const void*)k_backward<true>, (const void*)k_backward<false>};
   for (const void* f : fns) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
@@ -1390,7 +1452,8 @@ hipError_t launch_forward(const SysDev& sy, const BasisDev& bs, Work& w, Mode mo
 hipError_t launch_terminal(const SysDev& sy, const BasisDev& bs, Work& w, Mode mode, double rho,
                            hipStream_t stream) {
   const int P = mode == Mode::Hvp ? 1 : (mode == Mode::Hess ? w.P : 0);
-  hipLaunchKernelGGL(k_terminal, dim3(w.nb), dim3(kThreads), 0, stream, w.xf, w.vlast, sy.psit, w.binit, w.rr,
+  hipLaunchKernelGGL(k_terminal, dim3(w.nb), dim3(kThreads), 0, stream, w.xf, w.vlast, sy.psit, sy.psit_bstride,
+                     w.binit, w.rr,
                      w.aa, w.n, P, w.nchunks, (int)mode, rho);
   return hipGetLastError();
 }

@@ -1,16 +1,361 @@
-// Trust-region solver and batched multi-problem evaluation (filled in below the core path).
+// Exact-Hessian trust-region solver (the second-order optimizer step of Alg. 2, lines 27-28)
+// and the batched multi-problem evaluation.
+//
+// Trust region: Newton-type method with the exact subproblem
+//     min_p  g^T p + 1/2 p^T H p   s.t.  ||B p||_2 <= Delta,
+// i.e. the radius bounds the change of the sampled control f = B theta.  With the Gram matrix
+// G = B^T B = U diag(s) U^T restricted to its numerical range (s_i > 1e-14 max s), the
+// whitening p = W u, W = U diag(s^-1/2), turns the constraint into ||u|| <= Delta; the
+// directions of null(B) change neither f nor the cost and get no step.  The step is then
+// solved from the eigendecomposition W^T H W = Q diag(l) Q^T (Jacobi on the GPU) by the
+// More-Sorensen characterisation (p = -(H + s I)^{-1} g with H + s I >= 0, s (||p|| - Delta) = 0,
+// hard case handled with the lowest eigenvector).  Ratio test: rho = actual / predicted
+// reduction; accept when rho > 1e-4; shrink Delta by 1/4 when rho < 1/4; double it when
+// rho > 3/4 and the step reached the boundary.  When the predicted reduction falls below the
+// rounding level of the cost (|pred| < 1e3 eps |C|), a step is accepted iff it lowers ||g||.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <vector>
 
 #include "../../include/qoc.h"
 #include "qoc_api_internal.h"
+#include "qoc_internal.h"
+
+using namespace qoc;
+
+namespace {
+
+constexpr double kEps = std::numeric_limits<double>::epsilon();
+
+double norm2(const double* x, int n) {
+  double a = 0.0;
+  for (int i = 0; i < n; ++i) a += x[i] * x[i];
+  return std::sqrt(a);
+}
+
+struct SubproblemResult {
+  std::vector<double> p;   // step in the original coordinates
+  double pred = 0.0;       // predicted reduction  -(g^T p + 1/2 p^T H p)
+  bool boundary = false;
+};
+
+// Step of the subproblem in whitened coordinates from the eigen-decomposition of the
+// (transformed) Hessian: l (P), Q (P x P row-major, column i = eigenvector i).
+SubproblemResult tr_subproblem(int P, const double* g, const double* l, const double* Q, double delta) {
+  std::vector<double> gt(P, 0.0);
+  for (int i = 0; i < P; ++i) {
+    double acc = 0.0;
+    for (int r = 0; r < P; ++r) acc += Q[r * P + i] * g[r];
+    gt[i] = acc;
+  }
+  double lmax = 0.0;
+  for (int i = 0; i < P; ++i) lmax = std::max(lmax, std::fabs(l[i]));
+  std::vector<char> live(P, 1);
+  const int nlive = P;
+  double lmin = 0.0, gnorm = 0.0;
+  int imin = -1;
+  for (int i = 0; i < P; ++i) {
+    if (!live[i]) continue;
+    if (imin < 0 || l[i] < lmin) {
+      lmin = l[i];
+      imin = i;
+    }
+    gnorm += gt[i] * gt[i];
+  }
+  gnorm = std::sqrt(gnorm);
+  if (nlive == 0 || gnorm == 0.0) {
+    // no curvature information: steepest descent to the boundary
+    SubproblemResult res;
+    res.p.assign(P, 0.0);
+    const double gn = norm2(g, P);
+    if (gn > 0.0)
+      for (int r = 0; r < P; ++r) res.p[r] = -delta * g[r] / gn;
+    res.pred = delta * gn;
+    res.boundary = true;
+    return res;
+  }
+  auto pnorm2 = [&](double s) {
+    double acc = 0.0;
+    for (int i = 0; i < P; ++i) {
+      if (!live[i]) continue;
+      const double d = l[i] + s;
+      acc += gt[i] * gt[i] / (d * d);
+    }
+    return acc;
+  };
+  std::vector<double> pt(P, 0.0);
+  bool boundary = true;
+  const double tiny = 1e-14 * std::max(lmax, 1e-300);
+  if (lmin > tiny && pnorm2(0.0) <= delta * delta) {
+    for (int i = 0; i < P; ++i) pt[i] = live[i] ? -gt[i] / l[i] : 0.0;
+    boundary = false;
+  } else {
+    // components of g on the lowest eigenspace
+    double gmin2 = 0.0;
+    for (int i = 0; i < P; ++i)
+      if (live[i] && l[i] - lmin <= tiny) gmin2 += gt[i] * gt[i];
+    const double slo0 = std::max(0.0, -lmin);
+    bool hard = false;
+    if (gmin2 <= (1e-24) * std::max(gnorm * gnorm, 1e-300)) {
+      double acc = 0.0;
+      for (int i = 0; i < P; ++i) {
+        if (!live[i] || l[i] - lmin <= tiny) continue;
+        const double d = l[i] - lmin;
+        acc += gt[i] * gt[i] / (d * d);
+      }
+      if (acc < delta * delta) {
+        hard = true;
+        for (int i = 0; i < P; ++i) pt[i] = (!live[i] || l[i] - lmin <= tiny) ? 0.0 : -gt[i] / (l[i] - lmin);
+        const double tau = std::sqrt(std::max(0.0, delta * delta - acc));
+        pt[imin] += tau;
+      }
+    }
+    if (!hard) {
+      // safeguarded Newton on 1/||p(s)|| - 1/Delta over s in (slo, shi]
+      double slo = slo0, shi = slo0 + gnorm / delta + lmax + 1.0;
+      double s = slo0 + 1e-12 * std::max(lmax, 1.0);
+      for (int it = 0; it < 200; ++it) {
+        const double n2 = pnorm2(s);
+        const double pn = std::sqrt(n2);
+        if (std::fabs(pn - delta) <= 1e-12 * delta) break;
+        if (pn > delta) slo = s;
+        else shi = s;
+        double d3 = 0.0;
+        for (int i = 0; i < P; ++i) {
+          if (!live[i]) continue;
+          const double d = l[i] + s;
+          d3 += gt[i] * gt[i] / (d * d * d);
+        }
+        const double phi = 1.0 / pn - 1.0 / delta;
+        const double dphi = d3 / (pn * n2);
+        double sn = s - phi / dphi;
+        if (!(sn > slo && sn < shi)) sn = 0.5 * (slo + shi);
+        if (std::fabs(sn - s) <= 1e-16 * std::max(1.0, std::fabs(s))) {
+          s = sn;
+          break;
+        }
+        s = sn;
+      }
+      for (int i = 0; i < P; ++i) pt[i] = live[i] ? -gt[i] / (l[i] + s) : 0.0;
+    }
+  }
+  SubproblemResult res;
+  res.boundary = boundary;
+  res.p.assign(P, 0.0);
+  double m = 0.0;
+  for (int i = 0; i < P; ++i) m += gt[i] * pt[i] + 0.5 * l[i] * pt[i] * pt[i];
+  res.pred = -m;
+  for (int r = 0; r < P; ++r) {
+    double acc = 0.0;
+    for (int i = 0; i < P; ++i) acc += Q[r * P + i] * pt[i];
+    res.p[r] = acc;
+  }
+  return res;
+}
+
+}  // namespace
+
+// Batched eigendecomposition of `count` P x P host matrices on the handle's device.
+static qoc_status sym_eig_host(qoc_problem* p, int count, int P, const double* H, double* evals, double* evecs) {
+  const size_t mats = (size_t)count * P * P;
+  const size_t scratch = sym_eig_scratch_doubles(P, count);
+  const size_t need = (2 * mats + (size_t)count * P + scratch) * sizeof(double);
+  if (!p->d_tr || p->tr_bytes < need) {
+    p->dfree(p->d_tr, p->tr_bytes);
+    p->d_tr = nullptr;
+    p->tr_bytes = 0;
+    qoc_status st = p->dmalloc((void**)&p->d_tr, need, "trust-region scratch");
+    if (st != QOC_OK) return st;
+    p->tr_bytes = need;
+  }
+  double* d_h = p->d_tr;
+  double* d_v = d_h + mats;
+  double* d_l = d_v + mats;
+  double* d_s = d_l + (size_t)count * P;
+  hipError_t e = hipMemcpyAsync(d_h, H, mats * sizeof(double), hipMemcpyHostToDevice, p->stream);
+  if (e == hipSuccess) e = launch_sym_eig(d_h, P, count, d_l, d_v, d_s, p->d_status, p->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(evals, d_l, (size_t)count * P * sizeof(double), hipMemcpyDeviceToHost, p->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(evecs, d_v, mats * sizeof(double), hipMemcpyDeviceToHost, p->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+  if (e != hipSuccess) return p->hip_fail(e, "trust-region eigendecomposition");
+  return p->check_device_status();
+}
+
+// Whitening of the control-space trust region from G = B^T B (computed once per basis).
+static qoc_status ensure_whitening(qoc_problem* p) {
+  if (p->tr_rank > 0 && p->tr_basis_version == p->basis_version) return QOC_OK;
+  const int P = p->P, nt = p->nt;
+  std::vector<double> B((size_t)nt * P), Gm((size_t)P * P, 0.0);
+  hipError_t e = hipMemcpyAsync(B.data(), p->d_B, B.size() * sizeof(double), hipMemcpyDeviceToHost, p->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+  if (e != hipSuccess) return p->hip_fail(e, "basis download");
+  for (int j = 0; j < nt; ++j) {
+    const double* row = &B[(size_t)j * P];
+    for (int a = 0; a < P; ++a) {
+      const double ba = row[a];
+      if (ba == 0.0) continue;
+      for (int c = 0; c < P; ++c) Gm[(size_t)a * P + c] += ba * row[c];
+    }
+  }
+  std::vector<double> sv(P), U((size_t)P * P);
+  qoc_status st = sym_eig_host(p, 1, P, Gm.data(), sv.data(), U.data());
+  if (st != QOC_OK) return st;
+  double smax = 0.0;
+  for (int i = 0; i < P; ++i) smax = std::max(smax, sv[i]);
+  std::vector<int> keep;
+  for (int i = 0; i < P; ++i)
+    if (sv[i] > 1e-14 * smax) keep.push_back(i);
+  const int R = (int)keep.size();
+  if (R == 0) return p->fail(QOC_ERR_INVALID_ARG, "control basis is zero");
+  p->tr_whiten.assign((size_t)P * R, 0.0);
+  for (int a = 0; a < P; ++a)
+    for (int r = 0; r < R; ++r) p->tr_whiten[(size_t)a * R + r] = U[(size_t)a * P + keep[r]] / std::sqrt(sv[keep[r]]);
+  p->tr_rank = R;
+  p->tr_basis_version = p->basis_version;
+  return QOC_OK;
+}
 
 extern "C" {
 
+qoc_status qoc_tr_solve_many(qoc_problem* p, int32_t count, const double* theta0, const double* targets, double gtol,
+                             int32_t max_iter, double* theta_out, double* cost_out, int32_t* iters_out,
+                             int32_t* converged_out) {
+  if (!p) return QOC_ERR_INVALID_ARG;
+  qoc_status st = p->ready();
+  if (st != QOC_OK) return st;
+  if (count < 1 || !theta0 || !theta_out) return p->fail(QOC_ERR_INVALID_ARG, "theta0 / theta_out NULL or count < 1");
+  if (!(gtol > 0.0) || max_iter < 0) return p->fail(QOC_ERR_INVALID_ARG, "gtol must be > 0 and max_iter >= 0");
+  const int P = p->P, n = p->n;
+  const size_t PP = (size_t)P * P;
+  // whitening W (P x r) from the Gram matrix of the control model
+  st = ensure_whitening(p);
+  if (st != QOC_OK) return st;
+  const int R = p->tr_rank;
+  const double* W = p->tr_whiten.data();   // P x R row-major
+  const size_t RR = (size_t)R * R;
+  std::vector<double> th(theta0, theta0 + (size_t)count * P), C(count), G((size_t)count * P), H((size_t)count * PP);
+  st = p->run_host(Mode::Hess, count, th.data(), nullptr, C.data(), G.data(), H.data(), targets);
+  if (st != QOC_OK) return st;
+  std::vector<double> delta(count, 1.0);
+  std::vector<int> iters(count, 0), done(count, 0), conv(count, 0);
+  std::vector<double> l, Q, trial, tgt, tc, tg, th2, gw(R), tmp((size_t)P * R);
+  std::vector<int> act;
+  std::vector<SubproblemResult> steps;
+  for (;;) {
+    act.clear();
+    for (int i = 0; i < count; ++i) {
+      if (done[i]) continue;
+      if (norm2(&G[(size_t)i * P], P) < gtol) {
+        conv[i] = 1;
+        done[i] = 1;
+      } else if (iters[i] >= max_iter) {
+        done[i] = 1;
+      } else {
+        act.push_back(i);
+      }
+    }
+    if (act.empty()) break;
+    const int na = (int)act.size();
+    // whitened Hessians W^T H W
+    std::vector<double> Ha((size_t)na * RR);
+    for (int k = 0; k < na; ++k) {
+      const double* Hi = &H[(size_t)act[k] * PP];
+      for (int a = 0; a < P; ++a)
+        for (int c = 0; c < R; ++c) {
+          double acc = 0.0;
+          for (int b2 = 0; b2 < P; ++b2) acc += Hi[a * P + b2] * W[b2 * R + c];
+          tmp[(size_t)a * R + c] = acc;
+        }
+      double* Hw = &Ha[(size_t)k * RR];
+      for (int r = 0; r < R; ++r)
+        for (int c = 0; c < R; ++c) {
+          double acc = 0.0;
+          for (int a = 0; a < P; ++a) acc += W[a * R + r] * tmp[(size_t)a * R + c];
+          Hw[r * R + c] = acc;
+        }
+    }
+    l.assign((size_t)na * R, 0.0);
+    Q.assign((size_t)na * RR, 0.0);
+    st = sym_eig_host(p, na, R, Ha.data(), l.data(), Q.data());
+    if (st != QOC_OK) return st;
+    steps.assign(na, SubproblemResult());
+    trial.assign((size_t)na * P, 0.0);
+    if (targets) tgt.assign((size_t)na * 2 * n, 0.0);
+    std::vector<double> pnorm_f(na, 0.0);
+    for (int k = 0; k < na; ++k) {
+      const int i = act[k];
+      const double* gi = &G[(size_t)i * P];
+      for (int r = 0; r < R; ++r) {
+        double acc = 0.0;
+        for (int a = 0; a < P; ++a) acc += W[a * R + r] * gi[a];
+        gw[r] = acc;
+      }
+      SubproblemResult sr = tr_subproblem(R, gw.data(), &l[(size_t)k * R], &Q[(size_t)k * RR], delta[i]);
+      pnorm_f[k] = norm2(sr.p.data(), R);   // = ||B p||
+      steps[k].pred = sr.pred;
+      steps[k].boundary = sr.boundary;
+      steps[k].p.assign(P, 0.0);
+      for (int a = 0; a < P; ++a) {
+        double acc = 0.0;
+        for (int r = 0; r < R; ++r) acc += W[a * R + r] * sr.p[r];
+        steps[k].p[a] = acc;
+      }
+      for (int r = 0; r < P; ++r) trial[(size_t)k * P + r] = th[(size_t)i * P + r] + steps[k].p[r];
+      if (targets) std::memcpy(&tgt[(size_t)k * 2 * n], targets + (size_t)i * 2 * n, 2 * n * sizeof(double));
+    }
+    tc.assign(na, 0.0);
+    tg.assign((size_t)na * P, 0.0);
+    th2.assign((size_t)na * PP, 0.0);
+    st = p->run_host(Mode::Hess, na, trial.data(), nullptr, tc.data(), tg.data(), th2.data(),
+                     targets ? tgt.data() : nullptr);
+    if (st != QOC_OK) return st;
+    for (int k = 0; k < na; ++k) {
+      const int i = act[k];
+      const double pn = pnorm_f[k];
+      const double pred = steps[k].pred;
+      const double ared = C[i] - tc[k];
+      const double gcur = norm2(&G[(size_t)i * P], P), gnew = norm2(&tg[(size_t)k * P], P);
+      bool accept;
+      if (std::fabs(pred) < 1e3 * kEps * std::fabs(C[i])) {
+        accept = gnew < gcur;
+      } else {
+        const double rho = ared / pred;
+        if (rho < 0.25) delta[i] = 0.25 * std::min(delta[i], pn);
+        else if (rho > 0.75 && steps[k].boundary) delta[i] = std::min(2.0 * delta[i], 1e6);
+        accept = rho > 1e-4;
+      }
+      iters[i] += 1;
+      if (accept) {
+        std::memcpy(&th[(size_t)i * P], &trial[(size_t)k * P], P * sizeof(double));
+        C[i] = tc[k];
+        std::memcpy(&G[(size_t)i * P], &tg[(size_t)k * P], P * sizeof(double));
+        std::memcpy(&H[(size_t)i * PP], &th2[(size_t)k * PP], PP * sizeof(double));
+      }
+      const double thn = norm2(&th[(size_t)i * P], P);
+      if (norm2(steps[k].p.data(), P) < 1e-14 * (1.0 + thn) || delta[i] < 1e-300) done[i] = 1;
+    }
+  }
+  std::memcpy(theta_out, th.data(), (size_t)count * P * sizeof(double));
+  if (cost_out) std::memcpy(cost_out, C.data(), count * sizeof(double));
+  for (int i = 0; i < count; ++i) {
+    if (iters_out) iters_out[i] = iters[i];
+    if (converged_out) converged_out[i] = conv[i];
+  }
+  return QOC_OK;
+}
+
 qoc_status qoc_tr_solve(qoc_problem* p, const double* theta0, double gtol, int32_t max_iter, double* theta_out,
                         double* cost_out, int32_t* iters_out) {
-  (void)theta0; (void)gtol; (void)max_iter; (void)theta_out; (void)cost_out; (void)iters_out;
   if (!p) return QOC_ERR_INVALID_ARG;
-  return p->fail(QOC_ERR_UNSUPPORTED, "not built yet");
+  int32_t conv = 0;
+  qoc_status st = qoc_tr_solve_many(p, 1, theta0, nullptr, gtol, max_iter, theta_out, cost_out, iters_out, &conv);
+  if (st != QOC_OK) return st;
+  if (!conv) return p->fail(QOC_ERR_NOT_CONVERGED, "trust-region solve reached max_iter before ||grad|| < gtol");
+  return QOC_OK;
 }
 
 qoc_status qoc_batch_create(int device, int32_t count, qoc_problem* const* problems, qoc_batch** out) {

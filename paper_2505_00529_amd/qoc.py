@@ -62,6 +62,9 @@ SIGNATURES = {
     "qoc_set_checkpoint_interval": (_st, [_vp, _i32]),
     "qoc_memory_usage": (_st, [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
     "qoc_tr_solve": (_st, [_vp, _dp, ctypes.c_double, _i32, _dp, _dp, ctypes.POINTER(_i32)]),
+    "qoc_tr_solve_many": (_st, [_vp, _i32, _dp, _dp, ctypes.c_double, _i32, _dp, _dp, ctypes.POINTER(_i32),
+                                ctypes.POINTER(_i32)]),
+    "qoc_hess_many_targets": (_st, [_vp, _i32, _dp, _dp, _dp, _dp, _dp]),
     "qoc_batch_create": (_st, [ctypes.c_int, _i32, ctypes.POINTER(_vp), ctypes.POINTER(_vp)]),
     "qoc_batch_destroy": (None, [_vp]),
     "qoc_batch_hess": (_st, [_vp, ctypes.POINTER(_dp), ctypes.POINTER(_dp), ctypes.POINTER(_dp),
@@ -286,6 +289,32 @@ class Problem:
         self._check(lib().qoc_step_propagators(self._h, _ptr(th), j, _ptr(u.view(np.float64)),
                                                _ptr(u1.view(np.float64)), _ptr(u2.view(np.float64))))
         return u, u1, u2
+
+    def hess_many_targets(self, thetas, targets):
+        th = _f64(thetas)
+        count = th.size // self.P
+        tg = np.ascontiguousarray(np.asarray(targets, dtype=np.complex128).reshape(count, self.n)).view(np.float64)
+        c = np.zeros(count)
+        g = np.zeros((count, self.P))
+        h = np.zeros((count, self.P, self.P))
+        self._check(lib().qoc_hess_many_targets(self._h, count, _ptr(th), _ptr(tg), _ptr(c), _ptr(g), _ptr(h)))
+        return c, g, h
+
+    def tr_solve_many(self, theta0s, targets=None, gtol: float = 1e-8, max_iter: int = 10000):
+        th = _f64(theta0s)
+        count = th.size // self.P
+        th = th.reshape(count, self.P)
+        tg = None
+        if targets is not None:
+            tg = np.ascontiguousarray(np.asarray(targets, dtype=np.complex128).reshape(count, self.n)).view(np.float64)
+        out = np.zeros((count, self.P))
+        c = np.zeros(count)
+        its = np.zeros(count, dtype=np.int32)
+        conv = np.zeros(count, dtype=np.int32)
+        self._check(lib().qoc_tr_solve_many(self._h, count, _ptr(th), _ptr(tg), gtol, max_iter, _ptr(out), _ptr(c),
+                                            its.ctypes.data_as(ctypes.POINTER(_i32)),
+                                            conv.ctypes.data_as(ctypes.POINTER(_i32))))
+        return out, c, its, conv.astype(bool)
 
     def tr_solve(self, theta0, gtol: float = 1e-8, max_iter: int = 10000):
         th = _f64(theta0, self.P)
