@@ -70,6 +70,9 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--batch", type=int, default=256, help="independent theta per step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="after timing, run one device-to-device copy of this many MiB (a reference "
+                         "dispatch of known traffic for HBM byte counters)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -164,6 +167,15 @@ def main() -> int:
         "path_alg_flops_per_eval": f_alg,
         "path_roofline_frac": f_alg * value / PEAK_FP64,
     }
+    if args.calib_copy_mib > 0:
+        nel = args.calib_copy_mib * (1 << 20) // 8
+        src = torch.ones(nel, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["calib_copy_bytes"] = int(nel * 8)
+        del src, dst
     if not args.no_cpu_baseline:
         log("bench: timing the CPU oracle on one theta ...")
         out["cpu_baseline"] = cpu_baseline(w)
