@@ -63,7 +63,8 @@ typedef enum {
 qoc_status qoc_create(int device, void* hip_stream, qoc_problem** out);
 /* Release the handle and all device memory it owns.  NULL-safe. */
 void qoc_destroy(qoc_problem* p);
-/* Switch the stream later calls are enqueued on (NULL: library-owned stream). */
+/* Switch the stream later calls are enqueued on; NULL selects the device's null (default)
+ * stream, which is also what torch's default stream is.  Synchronises the previous stream. */
 qoc_status qoc_set_stream(qoc_problem* p, void* hip_stream);
 
 /* System of eq. matrixTDSE with one control (Sec. II): h0, m are n x n real symmetric

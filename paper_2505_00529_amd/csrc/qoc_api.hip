@@ -81,6 +81,7 @@ void qoc_problem::release_work() {
   work_bytes = 0;
   w = Work();
   work_key_nb = 0;
+  work_key_seg = -1;
 }
 
 qoc_problem::~qoc_problem() {
@@ -101,15 +102,18 @@ qoc_problem::~qoc_problem() {
   if (own_stream && stream) (void)hipStreamDestroy(stream);
 }
 
-// Lay out (and if needed grow) one evaluation workspace for nb thetas.
-qoc_status qoc_problem::ensure_work(int nb) {
+// Lay out (and if needed grow) one evaluation workspace for nb thetas.  seg > 0 sizes the
+// eigen-data for one checkpoint segment of seg steps instead of the whole horizon.
+qoc_status qoc_problem::ensure_work(int nb, int seg) {
   const int np = pad_even(n);
-  int nchunks_target = std::max(1, (2048 + nb - 1) / nb);
-  int chunk = std::max(8, (nt + nchunks_target - 1) / nchunks_target);
-  int nchunks = (nt + chunk - 1) / chunk;
-  if (work_mem && work_key_nb == nb && w.n == n && w.nt == nt && w.P == P && w.chunk == chunk) return QOC_OK;
+  const int eig_stride = seg > 0 ? std::min(seg, nt) : nt;
+  const int chunk = eig_chunk_len(eig_stride, nb);
+  const int nchunks = (eig_stride + chunk - 1) / chunk;
+  const int nseg = (nt + eig_stride - 1) / eig_stride;
+  if (work_mem && work_key_nb == nb && work_key_seg == seg && w.n == n && w.nt == nt && w.P == P) return QOC_OK;
   release_work();
   const size_t ntn = (size_t)nt * n, nn = (size_t)n * n;
+  const size_t en = (size_t)eig_stride * n, enn = (size_t)eig_stride * nn;
   struct Item {
     void** ptr;
     size_t bytes;
@@ -122,14 +126,19 @@ qoc_status qoc_problem::ensure_work(int nb) {
   nw.nb = nb;
   nw.nchunks = nchunks;
   nw.chunk = chunk;
+  nw.seg_begin = 0;
+  nw.seg_len = eig_stride;
+  nw.eig_stride = eig_stride;
+  nw.nseg = nseg;
   const size_t B8 = sizeof(double), B16 = sizeof(double2);
+  const bool ck = seg > 0 && nseg > 1;
   std::vector<Item> items = {
       {(void**)&nw.f, B8 * nb * nt},
       {(void**)&nw.u, B8 * nb * nt},
-      {(void**)&nw.lam, B8 * nb * ntn},
-      {(void**)&nw.mt, B8 * nb * nt * nn},
-      {(void**)&nw.sm, B8 * nb * nt * nn},
-      {(void**)&nw.ov, B8 * nb * nt * nn},
+      {(void**)&nw.lam, B8 * nb * en},
+      {(void**)&nw.mt, B8 * nb * enn},
+      {(void**)&nw.sm, B8 * nb * enn},
+      {(void**)&nw.ov, B8 * nb * enn},
       {(void**)&nw.vfirst, B8 * nb * nchunks * nn},
       {(void**)&nw.vlast, B8 * nb * nchunks * nn},
       {(void**)&nw.gscratch, B8 * eig_scratch_doubles(n, nb, nchunks)},
@@ -145,6 +154,11 @@ qoc_status qoc_problem::ensure_work(int nb) {
       {(void**)&nw.binit, B16 * nb * n * 2},
       {(void**)&nw.rr, B8 * nb},
       {(void**)&nw.aa, B8 * nb * P * P},
+      {(void**)&nw.obound, ck ? B8 * nseg * nb * nn : 0},
+      {(void**)&nw.vsave, ck ? B8 * nb * nn : 0},
+      {(void**)&nw.bcarry, ck ? B16 * nb * n * 2 : 0},
+      {(void**)&nw.bcarry2, ck ? B16 * nb * n * 2 : 0},
+      {(void**)&nw.xf2, ck ? B16 * nb * n * 2 : 0},
   };
   size_t total = 0;
   for (auto& it : items) total += (it.bytes + 255) & ~(size_t)255;
@@ -162,6 +176,7 @@ qoc_status qoc_problem::ensure_work(int nb) {
   work_mem = mem;
   work_bytes = total;
   work_key_nb = nb;
+  work_key_seg = seg;
   return QOC_OK;
 }
 
@@ -185,9 +200,14 @@ qoc_status qoc_problem::ready() {
 }
 
 // Enqueue one evaluation of `nb` thetas (device pointers) on the handle's stream.
+// Gradient and HVP evaluations with a checkpoint interval L (0 < L < nt) keep eigen-data for one
+// segment of L steps at a time: the forward pass computes segment after segment and keeps only
+// the per-step vectors, the overlaps joining segments and the carried state; the backward pass
+// recomputes each segment's eigen-data (same chunking, so bit-identical) newest first.
 qoc_status qoc_problem::enqueue(Mode mode, int nb, const double* d_theta, const double* d_v, double* d_cost,
                                 double* d_grad, double* d_out, const double* d_targets) {
-  qoc_status st = ensure_work(nb);
+  const bool ck = ckpt > 0 && ckpt < nt && (mode == Mode::Grad || mode == Mode::Hvp);
+  qoc_status st = ensure_work(nb, ck ? ckpt : 0);
   if (st != QOC_OK) return st;
   SysDev sy;
   sy.n = n;
@@ -210,14 +230,67 @@ qoc_status qoc_problem::enqueue(Mode mode, int nb, const double* d_theta, const 
     if (e != hipSuccess) return hip_fail(e, #call);       \
     prof_end(tag, ev);                                    \
   } while (0)
+  auto set_range = [&](int j0, int len) {
+    w.seg_begin = j0;
+    w.seg_len = len;
+    w.nchunks = (len + w.chunk - 1) / w.chunk;
+  };
+  const bool store_derivs = mode != Mode::Cost;
   QOC_LAUNCH("controls", launch_controls(bs, d_theta, w.f, nb, stream));
   if (mode == Mode::Hvp) QOC_LAUNCH("controls", launch_controls(bs, d_v, w.u, nb, stream));
-  QOC_LAUNCH("eig", launch_eig(sy, bs, w, mode != Mode::Cost, kJacobiTol, jacobi_max_sweeps, stream));
-  QOC_LAUNCH("boundary", launch_boundary(w, stream));
-  QOC_LAUNCH("forward", launch_forward(sy, bs, w, mode, stream));
-  QOC_LAUNCH("terminal", launch_terminal(sy, bs, w, mode, rho, stream));
-  if (mode != Mode::Cost) QOC_LAUNCH("backward", launch_backward(sy, bs, w, mode, stream));
-  if (mode == Mode::Hess || mode == Mode::Hvp) QOC_LAUNCH("sterm", launch_sterm(sy, bs, w, stream));
+  if (!ck) {
+    set_range(0, nt);
+    w.o_in = nullptr;
+    w.x_in = nullptr;
+    w.x_out = w.xf;
+    w.b_in = w.binit;
+    w.b_out = nullptr;
+    w.v_last_step = nullptr;
+    QOC_LAUNCH("eig", launch_eig(sy, bs, w, store_derivs, kJacobiTol, jacobi_max_sweeps, stream));
+    QOC_LAUNCH("boundary", launch_boundary(w, stream));
+    QOC_LAUNCH("forward", launch_forward(sy, bs, w, mode, stream));
+    QOC_LAUNCH("terminal", launch_terminal(sy, bs, w, mode, rho, stream));
+    if (mode != Mode::Cost) QOC_LAUNCH("backward", launch_backward(sy, bs, w, mode, stream));
+    if (mode == Mode::Hess || mode == Mode::Hvp) QOC_LAUNCH("sterm", launch_sterm(sy, bs, w, stream));
+  } else {
+    const int L = w.eig_stride, S = w.nseg;
+    const size_t nn = (size_t)n * n;
+    // forward pass over segments
+    for (int sgi = 0; sgi < S; ++sgi) {
+      const int j0 = sgi * L;
+      set_range(j0, std::min(L, nt - j0));
+      QOC_LAUNCH("eig", launch_eig(sy, bs, w, true, kJacobiTol, jacobi_max_sweeps, stream));
+      QOC_LAUNCH("boundary", launch_boundary(w, stream));
+      double* ob = w.obound + (size_t)sgi * nb * nn;
+      QOC_LAUNCH("boundary", launch_seg_join(w, ob, sgi > 0, stream));
+      w.o_in = sgi > 0 ? ob : nullptr;
+      w.x_in = sgi > 0 ? (((S - sgi) % 2 == 0) ? w.xf : w.xf2) : nullptr;   // previous segment's output
+      w.x_out = ((S - 1 - sgi) % 2 == 0) ? w.xf : w.xf2;                    // last segment writes xf
+      QOC_LAUNCH("forward", launch_forward(sy, bs, w, mode, stream));
+    }
+    w.v_last_step = w.vsave;
+    w.v_last_stride = nn;
+    QOC_LAUNCH("terminal", launch_terminal(sy, bs, w, mode, rho, stream));
+    w.v_last_step = nullptr;
+    // backward pass, newest segment first, recomputing each segment's eigen-data
+    for (int sgi = S - 1; sgi >= 0; --sgi) {
+      const int j0 = sgi * L;
+      const int k = S - 1 - sgi;
+      set_range(j0, std::min(L, nt - j0));
+      QOC_LAUNCH("eig", launch_eig(sy, bs, w, true, kJacobiTol, jacobi_max_sweeps, stream));
+      QOC_LAUNCH("boundary", launch_boundary(w, stream));
+      w.o_in = sgi > 0 ? w.obound + (size_t)sgi * nb * nn : nullptr;
+      w.b_in = k == 0 ? w.binit : ((k - 1) % 2 == 0 ? w.bcarry : w.bcarry2);
+      w.b_out = sgi > 0 ? (k % 2 == 0 ? w.bcarry : w.bcarry2) : nullptr;
+      QOC_LAUNCH("backward", launch_backward(sy, bs, w, mode, stream));
+      if (mode == Mode::Hvp) QOC_LAUNCH("sterm", launch_sterm(sy, bs, w, stream));
+    }
+    w.b_in = w.binit;
+    w.b_out = nullptr;
+    w.o_in = nullptr;
+    w.x_in = nullptr;
+    w.x_out = w.xf;
+  }
   QOC_LAUNCH("assemble", launch_assemble(bs, w, mode, gamma, rho, d_cost, d_grad, d_out, stream));
 #undef QOC_LAUNCH
   return QOC_OK;
@@ -392,15 +465,8 @@ qoc_status qoc_set_stream(qoc_problem* p, void* hip_stream) {
   if (p->own_stream) {
     (void)hipStreamDestroy(p->stream);
     p->own_stream = false;
-    p->stream = nullptr;
   }
-  if (hip_stream) {
-    p->stream = (hipStream_t)hip_stream;
-  } else {
-    e = hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking);
-    if (e != hipSuccess) return p->hip_fail(e, "stream create");
-    p->own_stream = true;
-  }
+  p->stream = (hipStream_t)hip_stream;   // NULL: the device's null stream
   return QOC_OK;
 }
 
@@ -626,7 +692,7 @@ qoc_status qoc_step_propagators(qoc_problem* p, const double* theta, int32_t j, 
   if (st != QOC_OK) return st;
   if (!theta) return p->fail(QOC_ERR_INVALID_ARG, "NULL theta");
   if (j < 0 || j >= p->nt) return p->fail(QOC_ERR_INVALID_ARG, "step index out of range");
-  st = p->ensure_work(1);
+  st = p->ensure_work(1, 0);
   if (st != QOC_OK) return st;
   st = p->ensure_io(p->P + 6 * (size_t)p->n * p->n);
   if (st != QOC_OK) return st;

@@ -42,6 +42,7 @@ struct qoc_problem {
   void* work_mem = nullptr;
   size_t work_bytes = 0;
   int work_key_nb = 0;
+  int work_key_seg = -1;
   double* d_io = nullptr;
   size_t io_bytes = 0;
   double* d_props = nullptr;
@@ -72,7 +73,7 @@ struct qoc_problem {
   qoc_status dmalloc(void** ptr, size_t bytes, const char* what);
   void dfree(void* ptr, size_t bytes);
   void release_work();
-  qoc_status ensure_work(int nb);
+  qoc_status ensure_work(int nb, int seg);
   qoc_status ensure_io(size_t doubles);
   qoc_status ready();
   qoc_status enqueue(qoc::Mode mode, int nb, const double* d_theta, const double* d_v, double* d_cost,

@@ -23,6 +23,26 @@ constexpr int kStatusNoConv = 1;
 struct Work {
   int n = 0, np = 0, nt = 0, P = 0, nb = 0;
   int nchunks = 0, chunk = 0;
+  // Step range of the current launches and layout of the eigen-data arrays (lam, mt, sm, ov):
+  // [nb][eig_stride] indexed by j - seg_begin.  Without checkpointing seg_begin = 0,
+  // seg_len = eig_stride = nt; with checkpointing they describe one segment.
+  int seg_begin = 0, seg_len = 0, eig_stride = 0;
+  // Checkpointed evaluation: O across segment boundaries, the previous segment's last V,
+  // the initial-state override, and the backward carry.
+  double* obound = nullptr;     // [nb][nseg][n][n]  O_{j0-1} at the start of segment s (s >= 1)
+  double* vsave = nullptr;      // [nb][n][n]        last V of the previous segment
+  double2* bcarry = nullptr;    // [nb][n][2]        backward state carried between segments
+  double2* bcarry2 = nullptr;   // [nb][n][2]        (ping-pong partner)
+  double2* xf2 = nullptr;       // [nb][n][1+P]      forward carry ping-pong partner of xf
+  int nseg = 1;
+  // per-launch wiring of the sweeps (set by the caller before each launch)
+  const double* o_in = nullptr;     // [nb][n][n] O_{seg_begin-1}
+  const double2* x_in = nullptr;    // forward carry in
+  double2* x_out = nullptr;         // forward carry out (xf for the last range)
+  const double2* b_in = nullptr;    // backward state in (binit for the last range)
+  double2* b_out = nullptr;         // backward state out
+  const double* v_last_step = nullptr;  // [nb] x n x n at stride v_last_stride: V_{J-1}
+  size_t v_last_stride = 0;
   double* f = nullptr;        // [nb][nt]          control samples f_j
   double* u = nullptr;        // [nb][nt]          u = B v (HVP forcing)
   double* lam = nullptr;      // [nb][nt][n]       eigenvalues of H_j
@@ -31,6 +51,7 @@ struct Work {
   double* ov = nullptr;       // [nb][nt][n][n]    O_j = V_{j+1}^T V_j   (j < nt-1)
   double* vfirst = nullptr;   // [nb][nchunks][n][n]  V at the first step of each chunk
   double* vlast = nullptr;    // [nb][nchunks][n][n]  V at the last step of each chunk
+                              // (chunk indices are local to the launch's step range)
   double* gscratch = nullptr; // eigen-kernel matrices when they do not fit in LDS
   double2* at = nullptr;      // [nb][nt][n]  state a_j in basis j
   double2* yt = nullptr;      // [nb][nt][n]  y_j = U'_j a_j in basis j
@@ -71,6 +92,9 @@ hipError_t launch_controls(const BasisDev& bs, const double* theta, double* f, i
 hipError_t launch_eig(const SysDev& sy, const BasisDev& bs, Work& w, bool store_derivs,
                       double tol_rel, int max_sweeps, hipStream_t stream);
 hipError_t launch_boundary(Work& w, hipStream_t stream);
+// Segment join for checkpointed sweeps: obound_s = V_first^T vsave (if do_overlap), vsave = V_last.
+hipError_t launch_seg_join(Work& w, double* obound_s, bool do_overlap, hipStream_t stream);
+int eig_chunk_len(int seg_len, int nb);
 hipError_t launch_forward(const SysDev& sy, const BasisDev& bs, Work& w, Mode mode, hipStream_t stream);
 hipError_t launch_terminal(const SysDev& sy, const BasisDev& bs, Work& w, Mode mode, double rho,
                            hipStream_t stream);

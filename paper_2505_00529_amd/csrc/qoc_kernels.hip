@@ -19,6 +19,8 @@
 // product with O_j (or O_j^T going backward) applied to complex columns.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "qoc_device.h"
 #include "qoc_internal.h"
 
@@ -56,6 +58,8 @@ __global__ __launch_bounds__(kThreads) void k_controls(const double* B, const do
 
 struct EigArgs {
   int n, np, nt, chunk, nchunks;
+  int j_base, nsteps;      // this launch covers global steps [j_base, j_base + nsteps)
+  int eig_stride;          // steps per theta in the eigen-data arrays (indexed by j - j_base)
   double dt, tol_rel;
   int max_sweeps, store_derivs, lds_mats;
   const double* h0;
@@ -83,8 +87,8 @@ __global__ __launch_bounds__(kThreads) void k_eig_chunk(EigArgs a) {
   extern __shared__ double smem[];
   const int c = blockIdx.x, b = blockIdx.y;
   const int np = a.np, n = a.n, nt = a.nt;
-  const int j0 = c * a.chunk;
-  const int j1 = min(nt, j0 + a.chunk);
+  const int j0 = a.j_base + c * a.chunk;
+  const int j1 = min(a.j_base + a.nsteps, j0 + a.chunk);
   if (j0 >= j1) return;
   const int tid = threadIdx.x;
   double* rot = smem;
@@ -149,7 +153,7 @@ __global__ __launch_bounds__(kThreads) void k_eig_chunk(EigArgs a) {
       __syncthreads();
     }
     // stores
-    const size_t step = (size_t)b * nt + j;
+    const size_t step = (size_t)b * a.eig_stride + (j - a.j_base);
     for (int i = tid; i < n; i += kThreads) a.lam[step * n + i] = lamv[i];
     for (int idx = tid; idx < (int)nn; idx += kThreads) {
       const int i = idx / n, k = idx - i * n;
@@ -180,15 +184,15 @@ __global__ __launch_bounds__(kThreads) void k_eig_chunk(EigArgs a) {
 
 // O_{j0-1} = V_{j0}^T V_{j0-1} across chunk boundaries (first V of chunk c, last V of c-1).
 __global__ __launch_bounds__(kThreads) void k_boundary_overlap(const double* vfirst, const double* vlast,
-                                                                double* ov, int n, int nt, int chunk,
-                                                                int nchunks) {
+                                                                double* ov, int n, int nsteps, int chunk,
+                                                                int nchunks, int eig_stride) {
   const int c = blockIdx.x + 1, b = blockIdx.y;
-  const int j0 = c * chunk;
-  if (j0 >= nt) return;
+  const int j0 = c * chunk;   // local step index within the launch
+  if (j0 >= nsteps) return;
   const size_t nn = (size_t)n * n;
   const double* Vn = vfirst + ((size_t)b * nchunks + c) * nn;
   const double* Vo = vlast + ((size_t)b * nchunks + c - 1) * nn;
-  double* dst = ov + ((size_t)b * nt + j0 - 1) * nn;
+  double* dst = ov + ((size_t)b * eig_stride + j0 - 1) * nn;
   for (int idx = threadIdx.x; idx < (int)nn; idx += kThreads) {
     const int i = idx / n, k = idx - i * n;
     double acc = 0.0;
@@ -244,8 +248,8 @@ __global__ __launch_bounds__(64, 2) void k_eig_wave(EigArgs a) {
   const int lane = threadIdx.x;
   const int c = blockIdx.x, b = blockIdx.y;
   const int n = a.n, nt = a.nt;
-  const int j0 = c * a.chunk;
-  const int j1 = min(nt, j0 + a.chunk);
+  const int j0 = a.j_base + c * a.chunk;
+  const int j1 = min(a.j_base + a.nsteps, j0 + a.chunk);
   if (j0 >= j1) return;
   const double* fb = a.f + (size_t)b * nt;
   const size_t nn = (size_t)n * n;
@@ -384,7 +388,7 @@ __global__ __launch_bounds__(64, 2) void k_eig_wave(EigArgs a) {
       for (int s = 0; s < NP; ++s) Bx[lane * NP + s] = v[s];
     }
     __syncthreads();
-    const size_t step = (size_t)b * nt + j;
+    const size_t step = (size_t)b * a.eig_stride + (j - a.j_base);
     double acc[NP];
     // O_{j-1} = V_j^T V_{j-1}: row `lane`
     if (j > j0) {
@@ -467,6 +471,9 @@ __global__ __launch_bounds__(64, 2) void k_eig_wave(EigArgs a) {
 
 struct SweepArgs {
   int n, nt, P, pg, ngroups, hvp, need_y;
+  int j_begin, j_end;     // step range of this launch
+  int eig_j0;             // eigen-data arrays are indexed by j - eig_j0 ...
+  size_t eig_stride;      // ... with this many steps per theta
   double dt;
   const double* ov;
   const double* sm;
@@ -484,8 +491,11 @@ struct SweepArgs {
   double* q;
   double* e;
   double* K;
-  double2* xf;
-  const double2* binit;
+  const double* o_in;     // [nb][n][n] O_{j_begin-1} joining the previous segment (j_begin > 0)
+  const double2* xin;     // forward state entering the range ([nb][n][1+P], j_begin > 0)
+  double2* xout;          // forward: X after the range's last step ([nb][n][1+P])
+  const double2* binit;   // backward state entering the range ([nb][n][2])
+  double2* bout;          // backward state leaving the range in basis j_begin-1 ([nb][n][2])
 };
 
 // Sweep kernels keep the current step's O, S and lambda in LDS (STAGE: n <= 64) and load the
@@ -499,10 +509,11 @@ struct StepStage {
 };
 
 // Forward sweep (Alg. 2 lines 1-5 and 13-19, eq. gradatheta) for one theta and one group of
-// tangent columns.  Column 0 carries the state a_j, columns 1..pg the tangents da_j/dtheta_l
-// of the group, all in the eigenbasis of step j:
+// tangent columns over steps [j_begin, j_end).  Column 0 carries the state a_j, columns 1..pg
+// the tangents da_j/dtheta_l of the group, all in the eigenbasis of step j:
 //   y_j = U'_j a_j = -i dt h o (S_j (h o a_j)),  h = exp(-i dt l_j / 2)
 //   X   = [phi o a_j | phi o A'_j + y_j F_j^T],  then [a_{j+1} | A'_{j+1}] = O_j X.
+// X after the last step of the range goes to xout (a_J, A'_J in basis J-1 when j_end = J).
 template <bool STAGE>
 __global__ __launch_bounds__(kThreads) void k_forward(SweepArgs a) {
   extern __shared__ double smem[];
@@ -520,19 +531,21 @@ __global__ __launch_bounds__(kThreads) void k_forward(SweepArgs a) {
   double2* ph = hh + n;             // [n]
   double2* yv = ph + n;             // [n]
   const double* Fb = a.F + (size_t)b * a.f_bstride;
-  const size_t sb0 = (size_t)b * nt;
+  const size_t vb0 = (size_t)b * nt;                 // per-step vectors
+  const size_t eb0 = (size_t)b * a.eig_stride;       // eigen-data
+  const int xw = 1 + a.P;
 
   auto load_step = [&](int j, StepStage& st) {
-    const size_t step = sb0 + j;
+    const size_t es = eb0 + (j - a.eig_j0);
     if (STAGE) {
 #pragma unroll
       for (int i = 0; i < kPrefetch; ++i) {
         const int idx = tid + i * kThreads;
-        st.po[i] = (idx < (int)nn && j + 1 < nt) ? a.ov[step * nn + idx] : 0.0;
-        st.ps[i] = (idx < (int)nn && a.need_y) ? a.sm[step * nn + idx] : 0.0;
+        st.po[i] = (idx < (int)nn && j + 1 < a.j_end) ? a.ov[es * nn + idx] : 0.0;
+        st.ps[i] = (idx < (int)nn && a.need_y) ? a.sm[es * nn + idx] : 0.0;
       }
     }
-    st.pl = tid < n ? a.lam[step * n + tid] : 0.0;
+    st.pl = tid < n ? a.lam[es * n + tid] : 0.0;
   };
   auto commit_step = [&](const StepStage& st) {
     if (STAGE) {
@@ -553,33 +566,52 @@ __global__ __launch_bounds__(kThreads) void k_forward(SweepArgs a) {
     }
   };
 
-  // a_0 = alpha in basis 0: V_0^T alpha
-  const double* V0 = a.vfirst + (size_t)b * a.nchunks * nn;
-  for (int idx = tid; idx < n * w; idx += kThreads) {
-    const int p = idx / w, col = idx - p * w;
-    double2 v = make_double2(0.0, 0.0);
-    if (col == 0) {
-      for (int r = 0; r < n; ++r) {
-        const double vr = V0[r * n + p];
-        v.x = fma(vr, a.psi0[2 * r], v.x);
-        v.y = fma(vr, a.psi0[2 * r + 1], v.y);
+  if (a.j_begin == 0) {
+    // a_0 = alpha in basis 0: V_0^T alpha
+    const double* V0 = a.vfirst + (size_t)b * a.nchunks * nn;
+    for (int idx = tid; idx < n * w; idx += kThreads) {
+      const int p = idx / w, col = idx - p * w;
+      double2 v = make_double2(0.0, 0.0);
+      if (col == 0) {
+        for (int r = 0; r < n; ++r) {
+          const double vr = V0[r * n + p];
+          v.x = fma(vr, a.psi0[2 * r], v.x);
+          v.y = fma(vr, a.psi0[2 * r + 1], v.y);
+        }
       }
+      cur[idx] = v;
     }
-    cur[idx] = v;
+  } else {
+    // carried X of the previous segment moved into basis j_begin by O_{j_begin-1}
+    const double* Oi = a.o_in + (size_t)b * nn;
+    const double2* xi = a.xin + (size_t)b * n * xw;
+    for (int idx = tid; idx < n * w; idx += kThreads) {
+      const int p = idx / w, col = idx - p * w;
+      const int xc = col == 0 ? 0 : c0 + col;
+      double2 acc = make_double2(0.0, 0.0);
+      for (int r = 0; r < n; ++r) {
+        const double o = Oi[p * n + r];
+        const double2 x = xi[r * xw + xc];
+        acc.x = fma(o, x.x, acc.x);
+        acc.y = fma(o, x.y, acc.y);
+      }
+      cur[idx] = acc;
+    }
   }
   {
     StepStage st;
-    load_step(0, st);
+    load_step(a.j_begin, st);
     commit_step(st);
   }
   __syncthreads();
 
   const int nrb = (n + 3) / 4;
-  for (int j = 0; j < nt; ++j) {
-    const size_t step = sb0 + j;
+  for (int j = a.j_begin; j < a.j_end; ++j) {
+    const size_t es = eb0 + (j - a.eig_j0);
+    const size_t vs = vb0 + j;
     StepStage nx;
-    if (j + 1 < nt) load_step(j + 1, nx);
-    const double* S = STAGE ? Sb : a.sm + step * nn;
+    if (j + 1 < a.j_end) load_step(j + 1, nx);
+    const double* S = STAGE ? Sb : a.sm + es * nn;
     if (a.need_y && tid < n) {
       const int p = tid;
       double2 acc = make_double2(0.0, 0.0);
@@ -594,9 +626,9 @@ __global__ __launch_bounds__(kThreads) void k_forward(SweepArgs a) {
     }
     __syncthreads();
     if (g == 0 && a.need_y && tid < n) {
-      a.at[step * n + tid] = cur[tid * w];
-      a.yt[step * n + tid] = yv[tid];
-      if (a.ah) a.ah[step * n + tid] = cur[tid * w + 1];
+      a.at[vs * n + tid] = cur[tid * w];
+      a.yt[vs * n + tid] = yv[tid];
+      if (a.ah) a.ah[vs * n + tid] = cur[tid * w + 1];
     }
     for (int idx = tid; idx < n * w; idx += kThreads) {
       const int p = idx / w, col = idx - p * w;
@@ -609,8 +641,8 @@ __global__ __launch_bounds__(kThreads) void k_forward(SweepArgs a) {
       X[idx] = v;
     }
     __syncthreads();
-    if (j + 1 < nt) {
-      const double* Og = a.ov + step * nn;
+    if (j + 1 < a.j_end) {
+      const double* Og = a.ov + es * nn;
       for (int t = tid; t < nrb * w; t += kThreads) {
         const int rb = t / w, col = t - rb * w;
         const int p0 = rb * 4;
@@ -632,19 +664,18 @@ __global__ __launch_bounds__(kThreads) void k_forward(SweepArgs a) {
           if (p0 + i < n) cur[(p0 + i) * w + col] = acc[i];
       }
     } else {
-      // X holds a_J and A'_J in basis nt-1
-      double2* dst = a.xf + (size_t)b * n * (1 + a.P);
+      double2* dst = a.xout + (size_t)b * n * xw;
       for (int idx = tid; idx < n * w; idx += kThreads) {
         const int p = idx / w, col = idx - p * w;
         if (col == 0) {
-          if (g == 0) dst[p * (1 + a.P)] = X[idx];
+          if (g == 0) dst[p * xw] = X[idx];
         } else {
-          dst[p * (1 + a.P) + c0 + col] = X[idx];
+          dst[p * xw + c0 + col] = X[idx];
         }
       }
     }
     __syncthreads();
-    if (j + 1 < nt) {
+    if (j + 1 < a.j_end) {
       commit_step(nx);
       __syncthreads();
     }
@@ -654,16 +685,14 @@ __global__ __launch_bounds__(kThreads) void k_forward(SweepArgs a) {
 // Terminal conditions (eq. discretecost, eq. lambdasys with the rho weight, eq. musys):
 // r = a_J - beta in basis nt-1 (r^ = X_0 - V_{J-1}^T beta), |r|^2, lambda_J = rho r,
 // HVP: mu_J = rho a'_J; Hessian: rho Re(A'_J^H A'_J).
-__global__ __launch_bounds__(kThreads) void k_terminal(const double2* xf, const double* vlast,
-                                                       const double* psit_all, size_t psit_bstride,
-                                                       double2* binit, double* rr,
-                                                       double* aa, int n, int P, int nchunks, int mode,
-                                                       double rho) {
+__global__ __launch_bounds__(kThreads) void k_terminal(const double2* xf, const double* vlast_step,
+                                                       size_t v_bstride, const double* psit_all,
+                                                       size_t psit_bstride, double2* binit, double* rr,
+                                                       double* aa, int n, int P, int mode, double rho) {
   __shared__ double red[kThreads];
   const int b = blockIdx.x, tid = threadIdx.x;
   const double* psit = psit_all + (size_t)b * psit_bstride;
-  const size_t nn = (size_t)n * n;
-  const double* V = vlast + ((size_t)b * nchunks + nchunks - 1) * nn;
+  const double* V = vlast_step + (size_t)b * v_bstride;   // V_{J-1}
   const double2* X = xf + (size_t)b * n * (1 + P);
   double loc = 0.0;
   for (int p = tid; p < n; p += kThreads) {
@@ -726,21 +755,29 @@ __global__ __launch_bounds__(kThreads) void k_backward(SweepArgs a) {
   double2* yv = zv + n;
   double2* av = yv + n;
   const double* Fb = a.F + (size_t)b * a.f_bstride;
-  const size_t sb0 = (size_t)b * nt;
+  const size_t vb0 = (size_t)b * nt;
+  const size_t eb0 = (size_t)b * a.eig_stride;
 
+  // O_{jj-1} for step jj >= 1: inside the range from the eigen-data, at the range start from o_in
+  auto o_prev = [&](int jj) -> const double* {
+    if (jj - 1 >= a.j_begin) return a.ov + (eb0 + (jj - 1 - a.eig_j0)) * nn;
+    return a.o_in ? a.o_in + (size_t)b * nn : nullptr;
+  };
   auto load_step = [&](int j, BwdStage& st) {
-    const size_t step = sb0 + j;
+    const size_t es = eb0 + (j - a.eig_j0);
+    const size_t vs = vb0 + j;
     if (STAGE) {
+      const double* Op = j >= 1 ? o_prev(j) : nullptr;
 #pragma unroll
       for (int i = 0; i < kPrefetch; ++i) {
         const int idx = tid + i * kThreads;
-        st.po[i] = (idx < (int)nn && j >= 1) ? a.ov[(step - 1) * nn + idx] : 0.0;
-        st.ps[i] = idx < (int)nn ? a.sm[step * nn + idx] : 0.0;
+        st.po[i] = (idx < (int)nn && Op) ? Op[idx] : 0.0;
+        st.ps[i] = idx < (int)nn ? a.sm[es * nn + idx] : 0.0;
       }
     }
-    st.pl = tid < n ? a.lam[step * n + tid] : 0.0;
-    st.py = tid < n ? a.yt[step * n + tid] : make_double2(0.0, 0.0);
-    st.pa = (tid < n && a.hvp) ? a.ah[step * n + tid] : make_double2(0.0, 0.0);
+    st.pl = tid < n ? a.lam[es * n + tid] : 0.0;
+    st.py = tid < n ? a.yt[vs * n + tid] : make_double2(0.0, 0.0);
+    st.pa = (tid < n && a.hvp) ? a.ah[vs * n + tid] : make_double2(0.0, 0.0);
   };
   auto commit_step = [&](const BwdStage& st) {
     if (STAGE) {
@@ -771,17 +808,18 @@ __global__ __launch_bounds__(kThreads) void k_backward(SweepArgs a) {
   }
   {
     BwdStage st;
-    load_step(nt - 1, st);
+    load_step(a.j_end - 1, st);
     commit_step(st);
   }
   __syncthreads();
 
   const int nrb = (n + 3) / 4;
-  for (int j = nt - 1; j >= 0; --j) {
-    const size_t step = sb0 + j;
+  for (int j = a.j_end - 1; j >= a.j_begin; --j) {
+    const size_t es = eb0 + (j - a.eig_j0);
+    const size_t vs = vb0 + j;
     BwdStage nx;
-    if (j >= 1) load_step(j - 1, nx);
-    const double* S = STAGE ? Sb : a.sm + step * nn;
+    if (j - 1 >= a.j_begin) load_step(j - 1, nx);
+    const double* S = STAGE ? Sb : a.sm + es * nn;
     if (tid < n) {
       const int p = tid;
       double2 acc = make_double2(0.0, 0.0);
@@ -801,7 +839,7 @@ __global__ __launch_bounds__(kThreads) void k_backward(SweepArgs a) {
       for (int p = lane; p < n; p += 64) {
         const double2 l = cur[p * w];
         lq += l.x * yv[p].x + l.y * yv[p].y;
-        a.mu[step * n + p] = l;
+        a.mu[vs * n + p] = l;
         if (a.hvp) {
           const double2 nu = cur[p * w + 1];
           le += nu.x * yv[p].x + nu.y * yv[p].y + zv[p].x * av[p].x + zv[p].y * av[p].y;
@@ -810,8 +848,8 @@ __global__ __launch_bounds__(kThreads) void k_backward(SweepArgs a) {
       lq = wave_sum(lq);
       if (a.hvp) le = wave_sum(le);
       if (lane == 0) {
-        a.q[step] = lq;
-        if (a.hvp) a.e[step] = le;
+        a.q[vs] = lq;
+        if (a.hvp) a.e[vs] = le;
       }
     }
     if (!a.hvp && a.K && tid >= 64 && tid - 64 < ncol) {
@@ -821,7 +859,7 @@ __global__ __launch_bounds__(kThreads) void k_backward(SweepArgs a) {
         const double2 xi = cur[p * w + 1 + col];
         acc += xi.x * yv[p].x + xi.y * yv[p].y;
       }
-      a.K[step * a.P + c0 + col] = acc;
+      a.K[vs * a.P + c0 + col] = acc;
     }
     if (j >= 1) {
       for (int idx = tid; idx < n * w; idx += kThreads) {
@@ -835,7 +873,7 @@ __global__ __launch_bounds__(kThreads) void k_backward(SweepArgs a) {
         X[idx] = v;
       }
       __syncthreads();
-      const double* Og = a.ov + (step - 1) * nn;   // O_{j-1}; apply its transpose
+      const double* Og = o_prev(j);   // apply its transpose
       for (int t = tid; t < nrb * w; t += kThreads) {
         const int rb = t / w, col = t - rb * w;
         const int p0 = rb * 4;
@@ -857,7 +895,15 @@ __global__ __launch_bounds__(kThreads) void k_backward(SweepArgs a) {
           if (p0 + i < n) cur[(p0 + i) * w + col] = acc[i];
       }
       __syncthreads();
-      commit_step(nx);
+      if (j > a.j_begin) {
+        commit_step(nx);
+      } else if (a.bout) {
+        // state leaving the range, in basis j_begin - 1
+        for (int idx = tid; idx < n * w; idx += kThreads) {
+          const int p = idx / w, col = idx - p * w;
+          a.bout[((size_t)b * n + p) * 2 + col] = cur[idx];
+        }
+      }
     }
     __syncthreads();
   }
@@ -878,6 +924,8 @@ __global__ __launch_bounds__(kThreads) void k_backward(SweepArgs a) {
 // spread is too wide for kStermNmax terms falls back to the pairwise form below.
 struct StermArgs {
   int n, nt, ntasks;
+  int j_begin, nsteps, eig_j0;   // tasks cover steps [j_begin, j_begin + nsteps) of every theta
+  size_t eig_stride;
   double dt, tau;
   const double* mt;
   const double* sm;
@@ -891,14 +939,14 @@ constexpr int kStermNmax = 10;
 
 // Pairwise fallback: T_pq = 2 (Y_pq - Y_qp)/(l_p - l_q), Y = (Phi o Mt) Mt for separated pairs,
 // the stable second divided difference term by term for close pairs and the diagonal.
-__device__ double sterm_pairs_wave(const StermArgs& a, size_t step, int lane) {
+__device__ double sterm_pairs_wave(const StermArgs& a, size_t es, size_t vs, int lane) {
   const int n = a.n;
   const size_t nn = (size_t)n * n;
-  const double* Mt = a.mt + step * nn;
-  const double* S = a.sm + step * nn;
-  const double* lam = a.lam + step * n;
-  const double2* mu = a.mu + step * n;
-  const double2* at = a.at + step * n;
+  const double* Mt = a.mt + es * nn;
+  const double* S = a.sm + es * nn;
+  const double* lam = a.lam + es * n;
+  const double2* mu = a.mu + vs * n;
+  const double2* at = a.at + vs * n;
   const int npairs = n * (n + 1) / 2;
   double loc = 0.0;
   for (int w = lane; w < npairs; w += 64) {
@@ -948,8 +996,10 @@ __global__ __launch_bounds__(kThreads) void k_sterm_wave(StermArgs a) {
   const size_t nn = (size_t)n * n;
   const int wpb = kThreads / 64;
   for (int task = blockIdx.x * wpb + wv; task < a.ntasks; task += gridDim.x * wpb) {
-    const size_t step = (size_t)task;
-    const double* lam = a.lam + step * n;
+    const int tb = task / a.nsteps, tj = a.j_begin + (task - tb * a.nsteps);
+    const size_t es = (size_t)tb * a.eig_stride + (tj - a.eig_j0);   // eigen-data index
+    const size_t vs = (size_t)tb * a.nt + tj;                         // per-step vector index
+    const double* lam = a.lam + es * n;
     // per-lane copies of x, mu, a for rows lane and lane + 64
     double lv[2];
     double2 mv[2], av[2];
@@ -962,8 +1012,8 @@ __global__ __launch_bounds__(kThreads) void k_sterm_wave(StermArgs a) {
       av[e] = make_double2(0.0, 0.0);
       if (p < n) {
         lv[e] = lam[p];
-        mv[e] = a.mu[step * n + p];
-        av[e] = a.at[step * n + p];
+        mv[e] = a.mu[vs * n + p];
+        av[e] = a.at[vs * n + p];
         lo = fmin(lo, lv[e]);
         hi = fmax(hi, lv[e]);
       }
@@ -987,7 +1037,7 @@ __global__ __launch_bounds__(kThreads) void k_sterm_wave(StermArgs a) {
     }
     double sval;
     if (nmax < 0) {
-      sval = sterm_pairs_wave(a, step, lane);
+      sval = sterm_pairs_wave(a, es, vs, lane);
     } else {
       // coefficients c^{k+2}/(k+2)!, c = -i dt
       double2 coef[kStermNmax + 1];
@@ -1005,7 +1055,7 @@ __global__ __launch_bounds__(kThreads) void k_sterm_wave(StermArgs a) {
         }
       }
       const double x0 = lv[0] - m0, x1 = lv[1] - m0;
-      const double* Mt = a.mt + step * nn;
+      const double* Mt = a.mt + es * nn;
       double2 contrib = make_double2(0.0, 0.0);
       for (int rb = 0; rb * 64 < n; ++rb) {
         const int p = lane + 64 * rb;
@@ -1063,7 +1113,7 @@ __global__ __launch_bounds__(kThreads) void k_sterm_wave(StermArgs a) {
       tot = c_mul(phase(m0, a.dt), tot);
       sval = 2.0 * tot.x;
     }
-    if (lane == 0) a.s[step] = sval;
+    if (lane == 0) a.s[vs] = sval;
   }
 }
 
@@ -1232,6 +1282,36 @@ __global__ __launch_bounds__(kThreads) void k_identity_basis(double* B, int nt) 
   B[idx] = (idx / nt == idx % nt) ? 1.0 : 0.0;
 }
 
+// ---------------------------------------------------------------- segment joins (checkpointing)
+
+// Between consecutive segments: O_{j0-1} = V_{j0}^T V_{j0-1} from the first V of this segment and
+// the saved last V of the previous one, then save this segment's last V.  One block per theta.
+__global__ __launch_bounds__(kThreads) void k_seg_join(const double* vfirst, const double* vlast, int nchunks,
+                                                       double* vsave, double* obound_s, int n, int do_overlap) {
+  const int b = blockIdx.x;
+  const size_t nn = (size_t)n * n;
+  const double* Vn = vfirst + (size_t)b * nchunks * nn;          // chunk 0 of this segment
+  const double* Vl = vlast + ((size_t)b * nchunks + nchunks - 1) * nn;
+  double* Vs = vsave + (size_t)b * nn;
+  if (do_overlap) {
+    double* dst = obound_s + (size_t)b * nn;
+    for (int idx = threadIdx.x; idx < (int)nn; idx += kThreads) {
+      const int i = idx / n, k = idx - i * n;
+      double acc = 0.0;
+      for (int r = 0; r < n; ++r) acc = fma(Vn[r * n + i], Vs[r * n + k], acc);
+      dst[idx] = acc;
+    }
+    __syncthreads();
+  }
+  for (int idx = threadIdx.x; idx < (int)nn; idx += kThreads) Vs[idx] = Vl[idx];
+}
+
+hipError_t launch_seg_join(Work& w, double* obound_s, bool do_overlap, hipStream_t stream) {
+  hipLaunchKernelGGL(k_seg_join, dim3(w.nb), dim3(kThreads), 0, stream, w.vfirst, w.vlast, w.nchunks, w.vsave,
+                     obound_s, w.n, do_overlap ? 1 : 0);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- batched symmetric eigensolver
 
 // One workgroup per P x P symmetric matrix (trust-region subproblems): the same parallel-order
@@ -1325,6 +1405,12 @@ size_t eig_scratch_doubles(int n, int nb, int nchunks) {
   return (size_t)nb * nchunks * 4 * np * np;
 }
 
+int eig_chunk_len(int seg_len, int nb) {
+  // enough chunks in flight to fill the device (about 2048 workgroups) but at least 8 steps each
+  const int target = std::max(1, (2048 + nb - 1) / nb);
+  return std::max(8, (seg_len + target - 1) / target);
+}
+
 int choose_pg(int P, int nb) {
   (void)nb;
   if (P <= 0) return 1;
@@ -1352,6 +1438,9 @@ hipError_t launch_eig(const SysDev& sy, const BasisDev& bs, Work& w, bool store_
   a.nt = w.nt;
   a.chunk = w.chunk;
   a.nchunks = w.nchunks;
+  a.j_base = w.seg_begin;
+  a.nsteps = w.seg_len;
+  a.eig_stride = w.eig_stride;
   a.dt = bs.dt;
   a.tol_rel = tol_rel;
   a.max_sweeps = max_sweeps;
@@ -1392,7 +1481,7 @@ hipError_t launch_eig(const SysDev& sy, const BasisDev& bs, Work& w, bool store_
 hipError_t launch_boundary(Work& w, hipStream_t stream) {
   if (w.nchunks <= 1) return hipSuccess;
   hipLaunchKernelGGL(k_boundary_overlap, dim3(w.nchunks - 1, w.nb), dim3(kThreads), 0, stream, w.vfirst, w.vlast,
-                     w.ov, w.n, w.nt, w.chunk, w.nchunks);
+                     w.ov, w.n, w.seg_len, w.chunk, w.nchunks, w.eig_stride);
   return hipGetLastError();
 }
 
@@ -1402,6 +1491,10 @@ static SweepArgs sweep_args(const SysDev& sy, const BasisDev& bs, Work& w, Mode 
   a.nt = w.nt;
   a.hvp = mode == Mode::Hvp ? 1 : 0;
   a.need_y = mode == Mode::Cost ? 0 : 1;
+  a.j_begin = w.seg_begin;
+  a.j_end = w.seg_begin + w.seg_len;
+  a.eig_j0 = w.seg_begin;
+  a.eig_stride = (size_t)w.eig_stride;
   a.dt = bs.dt;
   a.ov = w.ov;
   a.sm = w.sm;
@@ -1434,8 +1527,11 @@ static SweepArgs sweep_args(const SysDev& sy, const BasisDev& bs, Work& w, Mode 
   a.q = w.q;
   a.e = w.e;
   a.K = mode == Mode::Hess ? w.K : nullptr;
-  a.xf = w.xf;
-  a.binit = w.binit;
+  a.o_in = w.o_in;
+  a.xin = w.x_in;
+  a.xout = w.x_out ? w.x_out : w.xf;
+  a.binit = w.b_in ? w.b_in : w.binit;
+  a.bout = w.b_out;
   return a;
 }
 
@@ -1452,9 +1548,11 @@ hipError_t launch_forward(const SysDev& sy, const BasisDev& bs, Work& w, Mode mo
 hipError_t launch_terminal(const SysDev& sy, const BasisDev& bs, Work& w, Mode mode, double rho,
                            hipStream_t stream) {
   const int P = mode == Mode::Hvp ? 1 : (mode == Mode::Hess ? w.P : 0);
-  hipLaunchKernelGGL(k_terminal, dim3(w.nb), dim3(kThreads), 0, stream, w.xf, w.vlast, sy.psit, sy.psit_bstride,
-                     w.binit, w.rr,
-                     w.aa, w.n, P, w.nchunks, (int)mode, rho);
+  const size_t nn = (size_t)w.n * w.n;
+  const double* vl = w.v_last_step ? w.v_last_step : w.vlast + (size_t)(w.nchunks - 1) * nn;
+  const size_t vstride = w.v_last_step ? w.v_last_stride : (size_t)w.nchunks * nn;
+  hipLaunchKernelGGL(k_terminal, dim3(w.nb), dim3(kThreads), 0, stream, w.xf, vl, vstride, sy.psit, sy.psit_bstride,
+                     w.binit, w.rr, w.aa, w.n, P, (int)mode, rho);
   return hipGetLastError();
 }
 
@@ -1472,7 +1570,11 @@ hipError_t launch_sterm(const SysDev& sy, const BasisDev& bs, Work& w, hipStream
   StermArgs a;
   a.n = w.n;
   a.nt = w.nt;
-  a.ntasks = w.nt * w.nb;
+  a.ntasks = w.seg_len * w.nb;
+  a.j_begin = w.seg_begin;
+  a.nsteps = w.seg_len;
+  a.eig_j0 = w.seg_begin;
+  a.eig_stride = (size_t)w.eig_stride;
   a.dt = bs.dt;
   a.tau = 1e-3;
   a.mt = w.mt;

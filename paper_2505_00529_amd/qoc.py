@@ -156,6 +156,7 @@ class Problem:
 
     # -- configuration
     def set_stream(self, stream: Optional[int]):
+        """Enqueue later calls on this hipStream_t handle; 0 / None is the null stream."""
         self._check(lib().qoc_set_stream(self._h, _vp(stream) if stream else None))
 
     def set_system(self, h0, m, psi0, psi_target):

@@ -1,0 +1,98 @@
+"""torch.autograd layer and checkpointed gradient / HVP sweeps."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import qoc_oracle as O
+from paper_2505_00529_amd import inputs
+from paper_2505_00529_amd import qoc
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def test_autograd_cost_grad_hvp_against_oracle():
+    import torch
+    from paper_2505_00529_amd import autograd as QA
+
+    w = inputs.make_workload("tiny", nt=150)
+    s = w.system
+    basis = O.fourier_basis(w.nt, w.dt, w.k)
+    p = qoc.problem_from_workload(w)
+    th_np = inputs.draw_thetas(w.p, 1, 41, sigma=0.3)[0]
+    v_np = inputs.draw_directions(w.p, 1, 41)[0]
+    th = torch.tensor(th_np, dtype=torch.float64, device="cuda", requires_grad=True)
+    c = QA.cost(th, p)
+    (g,) = torch.autograd.grad(c, th, create_graph=True)
+    v = torch.tensor(v_np, dtype=torch.float64, device="cuda")
+    (hv,) = torch.autograd.grad(g, th, v)
+    p.sync()
+    cr, gr, hr = O.cost_grad_hess(s.h0, s.m, s.psi0, s.psi_target, basis, w.dt, th_np, w.gamma, w.rho)
+    assert _rel(c.item(), cr) < 1e-10
+    assert _rel(g.detach().cpu().numpy(), gr) < 1e-10
+    assert _rel(hv.cpu().numpy(), hr @ v_np) < 1e-10
+    p.close()
+
+
+def test_autograd_gradcheck_fp64():
+    import torch
+    from paper_2505_00529_amd import autograd as QA
+
+    w = inputs.make_workload("tiny", nt=60, k=2)
+    p = qoc.problem_from_workload(w)
+    th = torch.tensor(inputs.draw_thetas(w.p, 1, 43, sigma=0.3)[0], dtype=torch.float64, device="cuda",
+                      requires_grad=True)
+    assert torch.autograd.gradcheck(lambda x: QA.cost(x, p), (th,), eps=1e-6, atol=1e-7, rtol=1e-6)
+    assert torch.autograd.gradgradcheck(lambda x: QA.cost(x, p), (th,), eps=1e-6, atol=1e-6, rtol=1e-5)
+    p.close()
+
+
+@pytest.mark.parametrize("nt,ckpt", [(1000, 100), (1000, 64), (257, 50)])
+def test_checkpointed_matches_store_all(nt, ckpt):
+    w = inputs.make_workload("molecule", nt=nt)
+    p = qoc.problem_from_workload(w)
+    th = inputs.draw_thetas(w.p, 1, 45)[0]
+    v = inputs.draw_directions(w.p, 1, 45)[0]
+    c0, g0 = p.grad(th)
+    hv0, gh0 = p.hvp(th, v, with_grad=True)
+    _, peak0 = p.memory_usage()
+    p.close()
+    q = qoc.problem_from_workload(w)
+    q.set_checkpoint_interval(ckpt)
+    c1, g1 = q.grad(th)
+    hv1, gh1 = q.hvp(th, v, with_grad=True)
+    _, peak1 = q.memory_usage()
+    _say(f"nt={nt} ckpt={ckpt}: dC={_rel(c1, c0):.2e} dg={_rel(g1, g0):.2e} dHv={_rel(hv1, hv0):.2e} "
+         f"peak {peak0 / 2**20:.1f} -> {peak1 / 2**20:.1f} MiB")
+    assert _rel(c1, c0) < 1e-12 and _rel(g1, g0) < 1e-12 and _rel(hv1, hv0) < 1e-12
+    assert _rel(gh1, g0) < 1e-12
+    assert peak1 < peak0
+    q.close()
+
+
+def test_checkpointed_large_dimension_against_oracle():
+    """N=128 (unstaged sweeps, global-scratch eigen kernel) with checkpoints against the oracle."""
+    w = inputs.make_workload("diff", nt=24, k=3)
+    s = w.system
+    basis = O.fourier_basis(w.nt, w.dt, w.k)
+    p = qoc.problem_from_workload(w)
+    p.set_checkpoint_interval(10)
+    th = inputs.draw_thetas(w.p, 1, 47, sigma=0.3)[0]
+    v = inputs.draw_directions(w.p, 1, 47)[0]
+    c, g = p.grad(th)
+    hv = p.hvp(th, v)
+    cr, gr, hr = O.cost_grad_hess(s.h0, s.m, s.psi0, s.psi_target, basis, w.dt, th, w.gamma, w.rho)
+    _say(f"  dC={_rel(c, cr):.2e} dg={_rel(g, gr):.2e} dHv={_rel(hv, hr @ v):.2e}")
+    assert _rel(c, cr) < 1e-10 and _rel(g, gr) < 1e-10 and _rel(hv, hr @ v) < 1e-10
+    p.close()
