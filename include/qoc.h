@@ -121,7 +121,7 @@ qoc_status qoc_sync(qoc_problem* p);
 qoc_status qoc_step_propagators(qoc_problem* p, const double* theta, int32_t j,
                                 double* u, double* u1, double* u2);
 
-/* Checkpoint interval (steps) for the gradient / HVP paths: 0 stores every step's
+/* Checkpoint interval (steps) for the cost / gradient / HVP paths: 0 stores every step's
  * eigen-data; k > 0 keeps only states every k steps and recomputes one segment's
  * eigen-data at a time in the backward sweep (the memory reduction the paper names as
  * future work, Sec. V). */

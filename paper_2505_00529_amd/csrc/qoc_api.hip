@@ -200,13 +200,13 @@ qoc_status qoc_problem::ready() {
 }
 
 // Enqueue one evaluation of `nb` thetas (device pointers) on the handle's stream.
-// Gradient and HVP evaluations with a checkpoint interval L (0 < L < nt) keep eigen-data for one
+// Cost, gradient and HVP evaluations with a checkpoint interval L (0 < L < nt) keep eigen-data for one
 // segment of L steps at a time: the forward pass computes segment after segment and keeps only
 // the per-step vectors, the overlaps joining segments and the carried state; the backward pass
 // recomputes each segment's eigen-data (same chunking, so bit-identical) newest first.
 qoc_status qoc_problem::enqueue(Mode mode, int nb, const double* d_theta, const double* d_v, double* d_cost,
                                 double* d_grad, double* d_out, const double* d_targets) {
-  const bool ck = ckpt > 0 && ckpt < nt && (mode == Mode::Grad || mode == Mode::Hvp);
+  const bool ck = ckpt > 0 && ckpt < nt && mode != Mode::Hess;
   qoc_status st = ensure_work(nb, ck ? ckpt : 0);
   if (st != QOC_OK) return st;
   SysDev sy;
@@ -259,7 +259,7 @@ qoc_status qoc_problem::enqueue(Mode mode, int nb, const double* d_theta, const 
     for (int sgi = 0; sgi < S; ++sgi) {
       const int j0 = sgi * L;
       set_range(j0, std::min(L, nt - j0));
-      QOC_LAUNCH("eig", launch_eig(sy, bs, w, true, kJacobiTol, jacobi_max_sweeps, stream));
+      QOC_LAUNCH("eig", launch_eig(sy, bs, w, store_derivs, kJacobiTol, jacobi_max_sweeps, stream));
       QOC_LAUNCH("boundary", launch_boundary(w, stream));
       double* ob = w.obound + (size_t)sgi * nb * nn;
       QOC_LAUNCH("boundary", launch_seg_join(w, ob, sgi > 0, stream));
@@ -273,7 +273,7 @@ qoc_status qoc_problem::enqueue(Mode mode, int nb, const double* d_theta, const 
     QOC_LAUNCH("terminal", launch_terminal(sy, bs, w, mode, rho, stream));
     w.v_last_step = nullptr;
     // backward pass, newest segment first, recomputing each segment's eigen-data
-    for (int sgi = S - 1; sgi >= 0; --sgi) {
+    for (int sgi = S - 1; sgi >= 0 && mode != Mode::Cost; --sgi) {
       const int j0 = sgi * L;
       const int k = S - 1 - sgi;
       set_range(j0, std::min(L, nt - j0));

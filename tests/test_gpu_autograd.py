@@ -96,3 +96,42 @@ def test_checkpointed_large_dimension_against_oracle():
     _say(f"  dC={_rel(c, cr):.2e} dg={_rel(g, gr):.2e} dHv={_rel(hv, hr @ v):.2e}")
     assert _rel(c, cr) < 1e-10 and _rel(g, gr) < 1e-10 and _rel(hv, hr @ v) < 1e-10
     p.close()
+
+
+def test_differentiation_workload_fd_and_memory():
+    """N=128, J=10^4, K=64 (P=128), checkpoints every 100 steps: gradient and three HVPs through
+    torch.autograd, against central finite differences (h = 1e-6) of the store-all gradient;
+    peak device memory of the checkpointed handle against storing every step."""
+    import torch
+    from paper_2505_00529_amd import autograd as QA
+
+    w = inputs.make_workload("diff")
+    th_np = inputs.draw_thetas(w.p, 1, w.seed)[0]
+    vs = inputs.draw_directions(w.p, 3, w.seed)
+    full = qoc.problem_from_workload(w)
+    c_full, g_full = full.grad(th_np)
+    _, peak_full = full.memory_usage()
+    ck = qoc.problem_from_workload(w)
+    ck.set_checkpoint_interval(100)
+    th = torch.tensor(th_np, dtype=torch.float64, device="cuda", requires_grad=True)
+    c = QA.cost(th, ck)
+    (g,) = torch.autograd.grad(c, th, create_graph=True)
+    g_np = g.detach().cpu().numpy()
+    _say(f"diff: cost {c.item():.12f} dC={_rel(c.item(), c_full):.2e} dg={_rel(g_np, g_full):.2e}")
+    assert _rel(c.item(), c_full) < 1e-12 and _rel(g_np, g_full) < 1e-11
+    h = 1e-6
+    for i, v_np in enumerate(vs):
+        v = torch.tensor(v_np, dtype=torch.float64, device="cuda")
+        (hv,) = torch.autograd.grad(g, th, v, retain_graph=True)
+        gp = full.grad(th_np + h * v_np)[1]
+        gm = full.grad(th_np - h * v_np)[1]
+        fd = (gp - gm) / (2 * h)
+        err = _rel(hv.cpu().numpy(), fd)
+        _say(f"  hvp {i}: |Hv|={np.linalg.norm(fd):.4e} rel diff to central FD {err:.2e}")
+        assert err < 1e-6
+    ck.sync()
+    _, peak_ck = ck.memory_usage()
+    _say(f"  peak device memory: store-all {peak_full / 2**30:.3f} GiB, checkpointed {peak_ck / 2**30:.3f} GiB")
+    assert peak_ck < peak_full / 10
+    full.close()
+    ck.close()
