@@ -170,6 +170,30 @@ qoc_status qoc_profile_kernel_ms(qoc_problem* p, const char* kernel, double* tot
  * clears the counters after reading. */
 qoc_status qoc_jacobi_stats(qoc_problem* p, int64_t* steps, int64_t* sweeps, int32_t reset);
 
+/* ---- Learned warm start: 3-layer MLP n_in -> n_hidden -> n_hidden -> n_out with erf-GELU,
+ * BF16 matrix-core products with FP32 accumulation, FP32 master weights and Adam.
+ * Parameters are packed FP32 [W1 (hidden x in, row-major), b1, W2, b2, W3, b3].  All x / t / y
+ * / loss pointers are device pointers of FP32 row-major batches on the handle's stream.
+ * create: hip_stream is the stream every later call is enqueued on (NULL: the null stream);
+ * max_batch bounds `batch` in the calls below (activation buffers are sized for it). */
+typedef struct qoc_mlp qoc_mlp;
+qoc_status qoc_mlp_create(int device, void* hip_stream, int32_t n_in, int32_t n_hidden, int32_t n_out,
+                          int32_t max_batch, qoc_mlp** out);
+void       qoc_mlp_destroy(qoc_mlp* h);
+int64_t    qoc_mlp_num_params(const qoc_mlp* h);
+qoc_status qoc_mlp_set_params(qoc_mlp* h, const float* params_host);   /* also resets Adam state */
+qoc_status qoc_mlp_get_params(qoc_mlp* h, float* params_host);
+qoc_status qoc_mlp_get_grads(qoc_mlp* h, float* grads_host);           /* of the last loss_grad / train_step */
+/* y = MLP(x) for `batch` rows. */
+qoc_status qoc_mlp_forward(qoc_mlp* h, int32_t batch, const float* x_dev, float* y_dev);
+/* Mean-squared-error loss against t and its gradient with respect to every parameter. */
+qoc_status qoc_mlp_loss_grad(qoc_mlp* h, int32_t batch, const float* x_dev, const float* t_dev, float* loss_dev);
+/* loss_grad followed by one Adam step (bias-corrected) on the FP32 masters. */
+qoc_status qoc_mlp_train_step(qoc_mlp* h, int32_t batch, const float* x_dev, const float* t_dev, float lr,
+                              float beta1, float beta2, float eps, float* loss_dev);
+qoc_status qoc_mlp_sync(qoc_mlp* h);
+const char* qoc_mlp_last_error(const qoc_mlp* h);
+
 /* Static strings; never NULL. */
 const char* qoc_status_string(qoc_status s);
 const char* qoc_last_error(const qoc_problem* p);

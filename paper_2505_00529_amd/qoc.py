@@ -32,6 +32,7 @@ QOC_BASIS_DENSE = 2
 _lib = None
 
 _dp = ctypes.POINTER(ctypes.c_double)
+_fp = ctypes.POINTER(ctypes.c_float)
 _vp = ctypes.c_void_p
 _i32 = ctypes.c_int32
 _st = ctypes.c_int32
@@ -75,6 +76,18 @@ SIGNATURES = {
     "qoc_profile_enable": (_st, [_vp, _i32]),
     "qoc_profile_kernel_ms": (_st, [_vp, ctypes.c_char_p, _dp, ctypes.POINTER(_i32)]),
     "qoc_jacobi_stats": (_st, [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64), _i32]),
+    "qoc_mlp_create": (_st, [ctypes.c_int, _vp, _i32, _i32, _i32, _i32, ctypes.POINTER(_vp)]),
+    "qoc_mlp_destroy": (None, [_vp]),
+    "qoc_mlp_num_params": (ctypes.c_int64, [_vp]),
+    "qoc_mlp_set_params": (_st, [_vp, _fp]),
+    "qoc_mlp_get_params": (_st, [_vp, _fp]),
+    "qoc_mlp_get_grads": (_st, [_vp, _fp]),
+    "qoc_mlp_forward": (_st, [_vp, _i32, _vp, _vp]),
+    "qoc_mlp_loss_grad": (_st, [_vp, _i32, _vp, _vp, _vp]),
+    "qoc_mlp_train_step": (_st, [_vp, _i32, _vp, _vp, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                 ctypes.c_float, _vp]),
+    "qoc_mlp_sync": (_st, [_vp]),
+    "qoc_mlp_last_error": (ctypes.c_char_p, [_vp]),
     "qoc_status_string": (ctypes.c_char_p, [_st]),
     "qoc_last_error": (ctypes.c_char_p, [_vp]),
 }
@@ -326,6 +339,68 @@ class Problem:
         if st not in (QOC_OK, QOC_ERR_NOT_CONVERGED):
             self._check(st)
         return out, float(c[0]), int(it.value), st == QOC_OK
+
+
+class Mlp:
+    """Handle over the warm-start network (``qoc_mlp``).  Batches are device pointers of FP32
+    row-major arrays, enqueued on the handle's stream (``stream`` = 0 / None: the null stream,
+    which is torch's default stream)."""
+
+    def __init__(self, n_in: int, n_hidden: int, n_out: int, max_batch: int, device: int = 0,
+                 stream: Optional[int] = None):
+        self._h = _vp()
+        st = lib().qoc_mlp_create(device, _vp(stream) if stream else None, n_in, n_hidden, n_out, max_batch,
+                                  ctypes.byref(self._h))
+        if st != QOC_OK:
+            raise QocError(st, status_string(st))
+        self.n_in, self.n_hidden, self.n_out, self.max_batch = n_in, n_hidden, n_out, max_batch
+        self.num_params = int(lib().qoc_mlp_num_params(self._h))
+
+    def close(self):
+        if self._h:
+            lib().qoc_mlp_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st: int):
+        if st != QOC_OK:
+            raise QocError(st, lib().qoc_mlp_last_error(self._h).decode())
+
+    def set_params(self, params):
+        a = np.ascontiguousarray(np.asarray(params, dtype=np.float32))
+        if a.size != self.num_params:
+            raise ValueError(f"expected {self.num_params} parameters, got {a.size}")
+        self._check(lib().qoc_mlp_set_params(self._h, a.ctypes.data_as(_fp)))
+
+    def get_params(self) -> np.ndarray:
+        a = np.zeros(self.num_params, np.float32)
+        self._check(lib().qoc_mlp_get_params(self._h, a.ctypes.data_as(_fp)))
+        return a
+
+    def get_grads(self) -> np.ndarray:
+        a = np.zeros(self.num_params, np.float32)
+        self._check(lib().qoc_mlp_get_grads(self._h, a.ctypes.data_as(_fp)))
+        return a
+
+    def forward(self, batch: int, x_ptr: int, y_ptr: int):
+        self._check(lib().qoc_mlp_forward(self._h, batch, _vp(x_ptr), _vp(y_ptr)))
+
+    def loss_grad(self, batch: int, x_ptr: int, t_ptr: int, loss_ptr: Optional[int] = None):
+        self._check(lib().qoc_mlp_loss_grad(self._h, batch, _vp(x_ptr), _vp(t_ptr),
+                                            _vp(loss_ptr) if loss_ptr else None))
+
+    def train_step(self, batch: int, x_ptr: int, t_ptr: int, lr: float, beta1: float = 0.9,
+                   beta2: float = 0.999, eps: float = 1e-8, loss_ptr: Optional[int] = None):
+        self._check(lib().qoc_mlp_train_step(self._h, batch, _vp(x_ptr), _vp(t_ptr), lr, beta1, beta2, eps,
+                                             _vp(loss_ptr) if loss_ptr else None))
+
+    def sync(self):
+        self._check(lib().qoc_mlp_sync(self._h))
 
 
 def problem_from_workload(w, device: int = 0) -> Problem:
