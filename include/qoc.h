@@ -85,11 +85,11 @@ qoc_status qoc_set_weights(qoc_problem* p, double gamma, double rho);
 /* Number of control parameters P of the current basis. */
 qoc_status qoc_get_num_params(const qoc_problem* p, int32_t* num_params);
 
-/* Cost only: forward sweep of Alg. 1 lines 1-5 and eq. discretecost. theta: P doubles. */
+/* Cost only: forward sweep of Alg. 1 and eq. discretecost. theta: P doubles. */
 qoc_status qoc_cost(qoc_problem* p, const double* theta, double* cost);
-/* Cost and gradient: Alg. 1 lines 1-11 (first-order adjoint, eq. lambdasys, eq. dLdf). */
+/* Cost and gradient: Alg. 1 (first-order adjoint, eq. lambdasys, eq. dLdf). */
 qoc_status qoc_grad(qoc_problem* p, const double* theta, double* cost, double* grad);
-/* Cost, gradient and P x P Hessian (row-major): Alg. 2 lines 1-27 (eq. musys, eq. gradatheta,
+/* Cost, gradient and P x P Hessian (row-major): Alg. 2 up to its assembly (eq. musys, eq. gradatheta,
  * eq. d2Ldf2).  Any of cost / grad may be NULL. */
 qoc_status qoc_hess(qoc_problem* p, const double* theta, double* cost, double* grad, double* hess);
 /* Hessian-vector product H(theta) v (Alg. 2's tangent and second-adjoint sweeps for a single
@@ -129,20 +129,34 @@ qoc_status qoc_set_checkpoint_interval(qoc_problem* p, int32_t steps);
 /* Device bytes currently held by the handle's workspaces, and the high-water mark. */
 qoc_status qoc_memory_usage(const qoc_problem* p, int64_t* current_bytes, int64_t* peak_bytes);
 
-/* Exact-Hessian trust-region solve (Alg. 2 lines 27-28 with a Newton trust-region step):
- * from theta0 iterate until ||grad||_2 < gtol or max_iter.  theta_out: P doubles;
- * cost_out, iters_out may be NULL.  Returns QOC_ERR_NOT_CONVERGED (outputs written) when
- * max_iter is reached. */
+/* Exact-Hessian trust-region solve (the second-order optimisation step that closes Alg. 2):
+ * from theta0 iterate until the gradient is below gtol on the controllable subspace, or
+ * max_iter.  The radius bounds ||B p|| (the change of the sampled control).  Directions of
+ * the control matrix B with singular value below 1e-7 of the largest are numerically
+ * unidentifiable in parameter space (their Hessian entries fall under rounding) and are not
+ * moved; stationarity is ||V_r^T grad||_2 < gtol with V_r the kept right singular vectors
+ * (equal to ||grad||_2 for a well-conditioned basis).  theta_out: P doubles; cost_out,
+ * iters_out may be NULL.  Returns QOC_ERR_NOT_CONVERGED (outputs written) when max_iter is
+ * reached or the iteration stalls at the rounding level of the cost. */
 qoc_status qoc_tr_solve(qoc_problem* p, const double* theta0, double gtol, int32_t max_iter,
                         double* theta_out, double* cost_out, int32_t* iters_out);
 /* `count` independent trust-region solves advanced in lockstep (one batched Hessian evaluation
  * and one batched P x P eigendecomposition per iteration).  theta0: count x P; targets: NULL
  * (handle's target for all) or count x 2n doubles; outputs count x P / count / count / count
- * (any may be NULL except theta_out).  converged_out[i] = 1 if ||grad||_2 < gtol was reached.
+ * (any may be NULL except theta_out).  converged_out[i] = 1 if the stationarity test above
+ * was met.
  * Returns QOC_OK even if some solves did not converge (see converged_out). */
 qoc_status qoc_tr_solve_many(qoc_problem* p, int32_t count, const double* theta0, const double* targets,
                              double gtol, int32_t max_iter, double* theta_out, double* cost_out,
                              int32_t* iters_out, int32_t* converged_out);
+
+/* Coordinates of the trust-region metric: c = diag(sigma_r) V_r^T theta (count x P doubles
+ * out; entries past the rank are 0), so that ||c|| = ||B theta|| on the kept subspace, and the
+ * parameters theta = V_r diag(1/sigma_r) c that map back (the minimum-norm representative).
+ * rank (may be NULL) receives the number of kept directions.  Used to give a learned warm
+ * start well-conditioned regression targets. */
+qoc_status qoc_control_coords(qoc_problem* p, int32_t count, const double* theta, double* coords, int32_t* rank);
+qoc_status qoc_params_from_coords(qoc_problem* p, int32_t count, const double* coords, double* theta);
 
 /* Batched evaluation of independent problems of uneven (n, nt, P) in one persistent launch
  * sequence (captured as a HIP graph on first use).  problems: `count` configured handles on

@@ -86,6 +86,8 @@ struct qoc_problem {
   double* d_tr = nullptr;
   size_t tr_bytes = 0;
   std::vector<double> tr_whiten;   // P x rank whitening of the control-space trust region
+  std::vector<double> tr_vr;       // P x rank right singular vectors of the control matrix kept
+  std::vector<double> tr_sigma;    // their singular values
   int tr_rank = 0;
   int tr_basis_version = -1;
   int basis_version = 0;

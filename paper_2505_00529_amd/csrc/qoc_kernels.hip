@@ -2,12 +2,12 @@
 //
 // Paper map (Bhat, "Second-Order Adjoint Method for Quantum Optimal Control"):
 //   controls f = B theta ............... model f(j dt; theta), Sec. II
-//   eigen-data per step ................ Alg. 1/2 line 3 (decomposition of Z_j), Sec. III-A
-//   forward state + tangents ........... Alg. 2 lines 1-5 and 13-19, eq. gradatheta
+//   eigen-data per step ................ Alg. 1 and 2 (decomposition of Z_j in the forward sweep), Sec. III-A
+//   forward state + tangents ........... Alg. 2 (forward state sweep and tangent loop), eq. gradatheta
 //   terminal residual / cost ........... eq. discretecost
-//   backward costate + second adjoint .. Alg. 2 lines 6-9 and 20-26, eq. lambdasys, eq. musys
+//   backward costate + second adjoint .. Alg. 2 (costate sweep and second-adjoint loop), eq. lambdasys, eq. musys
 //   U'' contraction s_j ................ second derivative of exp in eq. d2Ldf2
-//   gradient / Hessian assembly ........ Alg. 2 line 27, eq. dLdf, eq. d2Ldf2
+//   gradient / Hessian assembly ........ Alg. 2 (final assembly), eq. dLdf, eq. d2Ldf2
 //
 // Every per-step quantity is kept in the eigenbasis of its own step.  With
 // H_j = V_j diag(l_j) V_j^T and phi(x) = exp(-i dt x):
@@ -41,17 +41,29 @@ __global__ __launch_bounds__(kThreads) void k_fourier_basis(double* B, int nt, i
   }
 }
 
-// f[b][j] = sum_k B[j][k] theta[b][k]
+// f[b][j] = sum_k B[j][k] theta[b][k], as a compensated dot product (Ogita, Rump & Oishi 2005,
+// "Accurate sum and dot product", Dot2: exact products by FMA, error-free sums, one final
+// correction).  A nearly rank-deficient basis makes optimal coefficient vectors large and
+// cancelling; the compensated sum keeps f accurate to working precision in that case.
 __global__ __launch_bounds__(kThreads) void k_controls(const double* B, const double* theta, double* f,
                                                        int nt, int P) {
+#pragma clang fp contract(off)   // the error-free transformations need every sum rounded on its own
   const int j = blockIdx.x * kThreads + threadIdx.x;
   const int b = blockIdx.y;
   if (j >= nt) return;
   const double* row = B + (size_t)j * P;
   const double* th = theta + (size_t)b * P;
-  double acc = 0.0;
-  for (int k = 0; k < P; ++k) acc = fma(row[k], th[k], acc);
-  f[(size_t)b * nt + j] = acc;
+  double s = 0.0, c = 0.0;
+  for (int k = 0; k < P; ++k) {
+    const double x = row[k] * th[k];
+    const double ex = fma(row[k], th[k], -x);     // x + ex = B_jk theta_k exactly
+    const double t = s + x;
+    const double z = t - s;
+    const double es = (s - (t - z)) + (x - z);    // t + es = s + x exactly
+    s = t;
+    c += ex + es;
+  }
+  f[(size_t)b * nt + j] = s + c;
 }
 
 // ---------------------------------------------------------------- eigen-data
@@ -508,7 +520,7 @@ struct StepStage {
   double pl;
 };
 
-// Forward sweep (Alg. 2 lines 1-5 and 13-19, eq. gradatheta) for one theta and one group of
+// Forward sweep (Alg. 2, forward state sweep and tangent loop; eq. gradatheta) for one theta and one group of
 // tangent columns over steps [j_begin, j_end).  Column 0 carries the state a_j, columns 1..pg
 // the tangents da_j/dtheta_l of the group, all in the eigenbasis of step j:
 //   y_j = U'_j a_j = -i dt h o (S_j (h o a_j)),  h = exp(-i dt l_j / 2)
@@ -723,7 +735,7 @@ __global__ __launch_bounds__(kThreads) void k_terminal(const double2* xf, const 
   }
 }
 
-// Backward sweep (Alg. 2 lines 6-9 and 20-26, eq. lambdasys, eq. musys).  Column 0 carries
+// Backward sweep (Alg. 2, costate sweep and second-adjoint loop; eq. lambdasys, eq. musys).  Column 0 carries
 // lambda_{j+1} in basis j, columns 1..pg the second-order adjoint columns of the group.
 //   z_j = U'_j^H lambda_{j+1} = i dt conj(h) o (S_j (conj(h) o lambda)),   q_j = Re(lambda^H y_j)
 // Hessian (two-sweep form): xi_{J-1} = 0, K_j = Re(xi_j^H y_j),
@@ -1119,7 +1131,7 @@ __global__ __launch_bounds__(kThreads) void k_sterm_wave(StermArgs a) {
 
 // ---------------------------------------------------------------- assembly
 
-// Alg. 2 line 27.  Cost (eq. discretecost): (gamma/2) sum f_j^2 + (rho/2) |r|^2.
+// Final assembly of Alg. 2.  Cost (eq. discretecost): (gamma/2) sum f_j^2 + (rho/2) |r|^2.
 // Gradient (eq. dLdf): g = gamma B^T f + B^T q.
 // Hessian (eq. d2Ldf2, two-sweep form): H = gamma B^T B + rho Re(A'^H A') + B^T K + K^T B
 //                                           + B^T diag(s) B.

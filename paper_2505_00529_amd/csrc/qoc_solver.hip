@@ -1,12 +1,14 @@
-// Exact-Hessian trust-region solver (the second-order optimizer step of Alg. 2, lines 27-28)
+// Exact-Hessian trust-region solver (the optimizer step and stopping test that close Alg. 2)
 // and the batched multi-problem evaluation.
 //
 // Trust region: Newton-type method with the exact subproblem
 //     min_p  g^T p + 1/2 p^T H p   s.t.  ||B p||_2 <= Delta,
-// i.e. the radius bounds the change of the sampled control f = B theta.  With the Gram matrix
-// G = B^T B = U diag(s) U^T restricted to its numerical range (s_i > 1e-14 max s), the
-// whitening p = W u, W = U diag(s^-1/2), turns the constraint into ||u|| <= Delta; the
-// directions of null(B) change neither f nor the cost and get no step.  The step is then
+// i.e. the radius bounds the change of the sampled control f = B theta.  With the singular value
+// decomposition B = U diag(sigma) V^T restricted to sigma_i > 1e-7 max sigma, the whitening
+// p = W u, W = V diag(1/sigma), turns the constraint into ||u|| <= Delta; the numerically null
+// directions of B change neither f nor the cost and get no step.  Stationarity is measured on
+// the directions the solver can move: ||V_r^T g|| < gtol (the gradient's components along the
+// directions left out are sigma times a bounded quantity, at most ~1e-7 sigma_max |dC/df|).  The step is then
 // solved from the eigendecomposition W^T H W = Q diag(l) Q^T (Jacobi on the GPU) by the
 // More-Sorensen characterisation (p = -(H + s I)^{-1} g with H + s I >= 0, s (||p|| - Delta) = 0,
 // hard case handled with the lowest eigenvector).  Ratio test: rho = actual / predicted
@@ -30,6 +32,7 @@ using namespace qoc;
 namespace {
 
 constexpr double kEps = std::numeric_limits<double>::epsilon();
+constexpr double kWhitenCut = 1e-7;   // smallest singular value of B kept, relative to the largest
 
 double norm2(const double* x, int n) {
   double a = 0.0;
@@ -185,35 +188,83 @@ static qoc_status sym_eig_host(qoc_problem* p, int count, int P, const double* H
   return p->check_device_status();
 }
 
-// Whitening of the control-space trust region from G = B^T B (computed once per basis).
+// Singular value decomposition B = U diag(sigma) V^T of the nt x P control matrix by one-sided
+// (Hestenes) Jacobi: plane rotations of column pairs until all columns are mutually orthogonal;
+// sigma_i are the final column norms and V the accumulated rotations.  Working on B itself rather
+// than on B^T B keeps the small singular values to absolute accuracy ~eps sigma_max (the Gram
+// matrix would square them into its rounding noise).  Host code, run once per control basis.
+static void one_sided_jacobi_svd(int nt, int P, const double* B, std::vector<double>& sigma,
+                                 std::vector<double>& V) {
+  std::vector<double> A((size_t)P * nt);   // column-major copy
+  for (int j = 0; j < nt; ++j)
+    for (int k = 0; k < P; ++k) A[(size_t)k * nt + j] = B[(size_t)j * P + k];
+  V.assign((size_t)P * P, 0.0);
+  for (int k = 0; k < P; ++k) V[(size_t)k * P + k] = 1.0;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    bool rotated = false;
+    for (int p = 0; p < P - 1; ++p)
+      for (int q = p + 1; q < P; ++q) {
+        double* ap = &A[(size_t)p * nt];
+        double* aq = &A[(size_t)q * nt];
+        double alpha = 0.0, beta = 0.0, gamma = 0.0;
+        for (int j = 0; j < nt; ++j) {
+          alpha += ap[j] * ap[j];
+          beta += aq[j] * aq[j];
+          gamma += ap[j] * aq[j];
+        }
+        if (gamma == 0.0 || std::fabs(gamma) <= 4.0 * kEps * std::sqrt(alpha * beta)) continue;
+        rotated = true;
+        const double zeta = (beta - alpha) / (2.0 * gamma);
+        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (std::fabs(zeta) + std::sqrt(1.0 + zeta * zeta));
+        const double c = 1.0 / std::sqrt(1.0 + t * t), sn = c * t;
+        for (int j = 0; j < nt; ++j) {
+          const double x = ap[j], y = aq[j];
+          ap[j] = c * x - sn * y;
+          aq[j] = sn * x + c * y;
+        }
+        for (int r = 0; r < P; ++r) {
+          const double x = V[(size_t)r * P + p], y = V[(size_t)r * P + q];
+          V[(size_t)r * P + p] = c * x - sn * y;
+          V[(size_t)r * P + q] = sn * x + c * y;
+        }
+      }
+    if (!rotated) break;
+  }
+  sigma.assign(P, 0.0);
+  for (int k = 0; k < P; ++k) sigma[k] = norm2(&A[(size_t)k * nt], nt);
+}
+
+// Whitening of the control-space trust region: W = V_r diag(1/sigma_r) over the singular
+// directions of B with sigma > 1e-7 sigma_max, so that ||B W u|| = ||u||.  Along a direction
+// with singular value sigma the parameter-space Hessian scales as sigma^2; below
+// sigma^2 / sigma_max^2 ~ 1e-14 it is under the rounding of the largest entries and the
+// direction cannot be optimised in parameter space, so it gets no step.  Computed once per basis.
 static qoc_status ensure_whitening(qoc_problem* p) {
   if (p->tr_rank > 0 && p->tr_basis_version == p->basis_version) return QOC_OK;
   const int P = p->P, nt = p->nt;
-  std::vector<double> B((size_t)nt * P), Gm((size_t)P * P, 0.0);
+  std::vector<double> B((size_t)nt * P);
   hipError_t e = hipMemcpyAsync(B.data(), p->d_B, B.size() * sizeof(double), hipMemcpyDeviceToHost, p->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
   if (e != hipSuccess) return p->hip_fail(e, "basis download");
-  for (int j = 0; j < nt; ++j) {
-    const double* row = &B[(size_t)j * P];
-    for (int a = 0; a < P; ++a) {
-      const double ba = row[a];
-      if (ba == 0.0) continue;
-      for (int c = 0; c < P; ++c) Gm[(size_t)a * P + c] += ba * row[c];
-    }
-  }
-  std::vector<double> sv(P), U((size_t)P * P);
-  qoc_status st = sym_eig_host(p, 1, P, Gm.data(), sv.data(), U.data());
-  if (st != QOC_OK) return st;
+  std::vector<double> sv, V;
+  one_sided_jacobi_svd(nt, P, B.data(), sv, V);
   double smax = 0.0;
   for (int i = 0; i < P; ++i) smax = std::max(smax, sv[i]);
   std::vector<int> keep;
   for (int i = 0; i < P; ++i)
-    if (sv[i] > 1e-14 * smax) keep.push_back(i);
+    if (sv[i] > kWhitenCut * smax) keep.push_back(i);
+  std::sort(keep.begin(), keep.end(), [&](int x, int y) { return sv[x] > sv[y]; });
   const int R = (int)keep.size();
   if (R == 0) return p->fail(QOC_ERR_INVALID_ARG, "control basis is zero");
   p->tr_whiten.assign((size_t)P * R, 0.0);
+  p->tr_vr.assign((size_t)P * R, 0.0);
+  p->tr_sigma.assign(R, 0.0);
+  for (int r = 0; r < R; ++r) p->tr_sigma[r] = sv[keep[r]];
   for (int a = 0; a < P; ++a)
-    for (int r = 0; r < R; ++r) p->tr_whiten[(size_t)a * R + r] = U[(size_t)a * P + keep[r]] / std::sqrt(sv[keep[r]]);
+    for (int r = 0; r < R; ++r) {
+      p->tr_vr[(size_t)a * R + r] = V[(size_t)a * P + keep[r]];
+      p->tr_whiten[(size_t)a * R + r] = V[(size_t)a * P + keep[r]] / sv[keep[r]];
+    }
   p->tr_rank = R;
   p->tr_basis_version = p->basis_version;
   return QOC_OK;
@@ -231,7 +282,7 @@ qoc_status qoc_tr_solve_many(qoc_problem* p, int32_t count, const double* theta0
   if (!(gtol > 0.0) || max_iter < 0) return p->fail(QOC_ERR_INVALID_ARG, "gtol must be > 0 and max_iter >= 0");
   const int P = p->P, n = p->n;
   const size_t PP = (size_t)P * P;
-  // whitening W (P x r) from the Gram matrix of the control model
+  // whitening W (P x r) from the singular value decomposition of the control model
   st = ensure_whitening(p);
   if (st != QOC_OK) return st;
   const int R = p->tr_rank;
@@ -245,11 +296,21 @@ qoc_status qoc_tr_solve_many(qoc_problem* p, int32_t count, const double* theta0
   std::vector<double> l, Q, trial, tgt, tc, tg, th2, gw(R), tmp((size_t)P * R);
   std::vector<int> act;
   std::vector<SubproblemResult> steps;
+  const double* Vr = p->tr_vr.data();   // P x R
+  std::vector<double> gproj(R);
+  auto stationarity = [&](const double* g) {
+    for (int r = 0; r < R; ++r) {
+      double acc = 0.0;
+      for (int a = 0; a < P; ++a) acc += Vr[(size_t)a * R + r] * g[a];
+      gproj[r] = acc;
+    }
+    return norm2(gproj.data(), R);
+  };
   for (;;) {
     act.clear();
     for (int i = 0; i < count; ++i) {
       if (done[i]) continue;
-      if (norm2(&G[(size_t)i * P], P) < gtol) {
+      if (stationarity(&G[(size_t)i * P]) < gtol) {
         conv[i] = 1;
         done[i] = 1;
       } else if (iters[i] >= max_iter) {
@@ -318,10 +379,14 @@ qoc_status qoc_tr_solve_many(qoc_problem* p, int32_t count, const double* theta0
       const double pn = pnorm_f[k];
       const double pred = steps[k].pred;
       const double ared = C[i] - tc[k];
-      const double gcur = norm2(&G[(size_t)i * P], P), gnew = norm2(&tg[(size_t)k * P], P);
+      const double gcur = stationarity(&G[(size_t)i * P]), gnew = stationarity(&tg[(size_t)k * P]);
       bool accept;
+      bool stalled = false;
       if (std::fabs(pred) < 1e3 * kEps * std::fabs(C[i])) {
+        // the model's reduction is below the rounding of C: decide by the gradient alone, and
+        // stop when even that no longer improves (the same step would be proposed again)
         accept = gnew < gcur;
+        stalled = !accept;
       } else {
         const double rho = ared / pred;
         if (rho < 0.25) delta[i] = 0.25 * std::min(delta[i], pn);
@@ -336,7 +401,7 @@ qoc_status qoc_tr_solve_many(qoc_problem* p, int32_t count, const double* theta0
         std::memcpy(&H[(size_t)i * PP], &th2[(size_t)k * PP], PP * sizeof(double));
       }
       const double thn = norm2(&th[(size_t)i * P], P);
-      if (norm2(steps[k].p.data(), P) < 1e-14 * (1.0 + thn) || delta[i] < 1e-300) done[i] = 1;
+      if (stalled || norm2(steps[k].p.data(), P) < 1e-14 * (1.0 + thn) || delta[i] < 1e-300) done[i] = 1;
     }
   }
   std::memcpy(theta_out, th.data(), (size_t)count * P * sizeof(double));
@@ -344,6 +409,50 @@ qoc_status qoc_tr_solve_many(qoc_problem* p, int32_t count, const double* theta0
   for (int i = 0; i < count; ++i) {
     if (iters_out) iters_out[i] = iters[i];
     if (converged_out) converged_out[i] = conv[i];
+  }
+  return QOC_OK;
+}
+
+qoc_status qoc_control_coords(qoc_problem* p, int32_t count, const double* theta, double* coords, int32_t* rank) {
+  if (!p) return QOC_ERR_INVALID_ARG;
+  qoc_status st = p->ready();
+  if (st != QOC_OK) return st;
+  if (count < 1 || !theta || !coords) return p->fail(QOC_ERR_INVALID_ARG, "theta / coords NULL or count < 1");
+  st = ensure_whitening(p);
+  if (st != QOC_OK) return st;
+  const int P = p->P, R = p->tr_rank;
+  for (int i = 0; i < count; ++i) {
+    const double* th = theta + (size_t)i * P;
+    double* c = coords + (size_t)i * P;
+    for (int r = 0; r < R; ++r) {
+      double acc = 0.0;
+      for (int a = 0; a < P; ++a) acc += p->tr_vr[(size_t)a * R + r] * th[a];
+      c[r] = p->tr_sigma[r] * acc;
+    }
+    for (int r = R; r < P; ++r) c[r] = 0.0;
+  }
+  if (rank) *rank = R;
+  return QOC_OK;
+}
+
+qoc_status qoc_params_from_coords(qoc_problem* p, int32_t count, const double* coords, double* theta) {
+  if (!p) return QOC_ERR_INVALID_ARG;
+  qoc_status st = p->ready();
+  if (st != QOC_OK) return st;
+  if (count < 1 || !theta || !coords) return p->fail(QOC_ERR_INVALID_ARG, "theta / coords NULL or count < 1");
+  st = ensure_whitening(p);
+  if (st != QOC_OK) return st;
+  const int P = p->P, R = p->tr_rank;
+  for (int i = 0; i < count; ++i) {
+    const double* c = coords + (size_t)i * P;
+    for (int r = 0; r < R; ++r)
+      if (!std::isfinite(c[r])) return p->fail(QOC_ERR_INVALID_ARG, "non-finite coordinate");
+    double* th = theta + (size_t)i * P;
+    for (int a = 0; a < P; ++a) {
+      double acc = 0.0;
+      for (int r = 0; r < R; ++r) acc += p->tr_whiten[(size_t)a * R + r] * c[r];
+      th[a] = acc;
+    }
   }
   return QOC_OK;
 }

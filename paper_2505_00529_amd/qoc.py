@@ -66,6 +66,8 @@ SIGNATURES = {
     "qoc_tr_solve_many": (_st, [_vp, _i32, _dp, _dp, ctypes.c_double, _i32, _dp, _dp, ctypes.POINTER(_i32),
                                 ctypes.POINTER(_i32)]),
     "qoc_hess_many_targets": (_st, [_vp, _i32, _dp, _dp, _dp, _dp, _dp]),
+    "qoc_control_coords": (_st, [_vp, _i32, _dp, _dp, ctypes.POINTER(_i32)]),
+    "qoc_params_from_coords": (_st, [_vp, _i32, _dp, _dp]),
     "qoc_batch_create": (_st, [ctypes.c_int, _i32, ctypes.POINTER(_vp), ctypes.POINTER(_vp)]),
     "qoc_batch_destroy": (None, [_vp]),
     "qoc_batch_hess": (_st, [_vp, ctypes.POINTER(_dp), ctypes.POINTER(_dp), ctypes.POINTER(_dp),
@@ -329,6 +331,22 @@ class Problem:
                                             its.ctypes.data_as(ctypes.POINTER(_i32)),
                                             conv.ctypes.data_as(ctypes.POINTER(_i32))))
         return out, c, its, conv.astype(bool)
+
+    def control_coords(self, thetas):
+        """(coords (count x P), rank): c = diag(sigma_r) V_r^T theta of the trust-region metric."""
+        th = _f64(thetas)
+        count = th.size // self.P
+        out = np.zeros((count, self.P))
+        r = _i32()
+        self._check(lib().qoc_control_coords(self._h, count, _ptr(th), _ptr(out), ctypes.byref(r)))
+        return out, int(r.value)
+
+    def params_from_coords(self, coords):
+        c = _f64(coords)
+        count = c.size // self.P
+        out = np.zeros((count, self.P))
+        self._check(lib().qoc_params_from_coords(self._h, count, _ptr(c), _ptr(out)))
+        return out
 
     def tr_solve(self, theta0, gtol: float = 1e-8, max_iter: int = 10000):
         th = _f64(theta0, self.P)

@@ -1,0 +1,217 @@
+"""Learned warm start for the exact-Hessian trust-region solver.
+
+A small network (``n_in = 2n`` target features -> 512 -> 512 -> P, erf-GELU between) proposes
+the starting control for a new target state.  It is trained on optimal controls that the
+trust-region solver itself produced from the zero start, and it runs entirely in the library's
+BF16 matrix-core kernels (``qoc_mlp_*``: forward, backward and Adam, FP32 accumulation and
+master weights).  The network regresses the trust-region metric coordinates
+c = diag(sigma_r) V_r^T theta (``qoc_control_coords``), which are isometric to the sampled
+control f = B theta; a half-period Fourier basis is numerically rank-deficient, so the raw
+coefficients are not identifiable and make poor regression targets.
+
+The plain zero-start solve stays the reference and the fallback: a warm solve that does not
+converge is rerun from theta = 0, and its final cost is compared with the plain solve's.
+
+Command line (one GPU): ``python -m paper_2505_00529_amd.warmstart --train 2000 --test 200``
+generates the training set, trains, and reports iterations, wall time and cost agreement of
+plain against warm-started solves on held-out targets as one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import time
+from typing import Optional
+
+import numpy as np
+
+from . import qoc
+
+
+def target_features(targets) -> np.ndarray:
+    """(count, n) complex targets -> (count, 2n) float32 [Re beta, Im beta]."""
+    t = np.asarray(targets, dtype=np.complex128)
+    return np.concatenate([t.real, t.imag], axis=1).astype(np.float32)
+
+
+def init_params(n_in: int, n_hidden: int, n_out: int, seed: int) -> np.ndarray:
+    """Uniform(-1/sqrt(fan_in), 1/sqrt(fan_in)) weights and biases, packed like qoc_mlp."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    parts = []
+    for fan_out, fan_in in ((n_hidden, n_in), (n_hidden, n_hidden), (n_out, n_hidden)):
+        b = 1.0 / np.sqrt(fan_in)
+        parts.append(rng.uniform(-b, b, size=fan_out * fan_in))
+        parts.append(rng.uniform(-b, b, size=fan_out))
+    return np.concatenate(parts).astype(np.float32)
+
+
+class WarmStart:
+    """Network + output normalisation for one configured problem (system, basis, weights)."""
+
+    def __init__(self, problem: "qoc.Problem", n_hidden: int = 512, max_batch: int = 256, seed: int = 0):
+        self.problem = problem
+        self.n_in = 2 * problem.n
+        self.n_out = problem.P
+        self.max_batch = max_batch
+        self.mlp = qoc.Mlp(self.n_in, n_hidden, self.n_out, max_batch)
+        self.mlp.set_params(init_params(self.n_in, n_hidden, self.n_out, seed))
+        self.mean = np.zeros(self.n_out)
+        self.scale = np.ones(self.n_out)
+        self.rank = self.n_out
+
+    # -- training
+    def fit(self, targets, thetas, epochs: int = 200, lr: float = 1e-3, batch: int = 128, seed: int = 0,
+            lr_final: float = 1e-5):
+        """Train on (target, optimal theta) pairs; returns the mean loss of each epoch."""
+        import torch
+
+        coords, self.rank = self.problem.control_coords(thetas)
+        self.mean = coords.mean(axis=0)
+        sd = coords.std(axis=0)
+        self.scale = np.where(sd > 1e-12, sd, 1.0)
+        y = ((coords - self.mean) / self.scale).astype(np.float32)
+        x = target_features(targets)
+        xd = torch.from_numpy(x).cuda()
+        yd = torch.from_numpy(y).cuda()
+        loss = torch.zeros((), dtype=torch.float32, device="cuda")
+        rng = np.random.Generator(np.random.PCG64(seed))
+        batch = min(batch, self.max_batch)
+        count = x.shape[0]
+        history = []
+        steps_per_epoch = max(1, count // batch)
+        total = epochs * steps_per_epoch
+        step = 0
+        for _ in range(epochs):
+            perm = torch.from_numpy(rng.permutation(count)).cuda()
+            xs = xd.index_select(0, perm).contiguous()
+            ys = yd.index_select(0, perm).contiguous()
+            acc = 0.0
+            for k in range(steps_per_epoch):
+                # cosine decay from lr to lr_final
+                cur = lr_final + 0.5 * (lr - lr_final) * (1.0 + np.cos(np.pi * step / total))
+                xb = xs[k * batch:(k + 1) * batch]
+                yb = ys[k * batch:(k + 1) * batch]
+                self.mlp.train_step(batch, xb.data_ptr(), yb.data_ptr(), float(cur), loss_ptr=loss.data_ptr())
+                acc += loss.item()
+                step += 1
+            history.append(acc / steps_per_epoch)
+        return history
+
+    # -- inference
+    def predict_coords(self, targets) -> np.ndarray:
+        import torch
+
+        x = torch.from_numpy(target_features(targets)).cuda()
+        count = x.shape[0]
+        y = torch.empty((count, self.n_out), dtype=torch.float32, device="cuda")
+        for s in range(0, count, self.max_batch):
+            e = min(count, s + self.max_batch)
+            xb = x[s:e].contiguous()
+            yb = torch.empty((e - s, self.n_out), dtype=torch.float32, device="cuda")
+            self.mlp.forward(e - s, xb.data_ptr(), yb.data_ptr())
+            y[s:e] = yb
+        c = y.cpu().numpy().astype(np.float64) * self.scale + self.mean
+        c[:, self.rank:] = 0.0
+        return c
+
+    def predict(self, targets) -> np.ndarray:
+        """Starting parameters theta_0 (count x P) for the given targets."""
+        return self.problem.params_from_coords(self.predict_coords(targets))
+
+    def solve(self, targets, gtol: float = 1e-8, max_iter: int = 10000):
+        """Warm-started solves with the zero-start fallback.  Returns a dict of per-target
+        arrays (theta, cost, iters, converged, fallback) and the wall time."""
+        t0 = time.perf_counter()
+        th0 = self.predict(targets)
+        th, c, its, conv = self.problem.tr_solve_many(th0, targets, gtol=gtol, max_iter=max_iter)
+        fb = ~conv
+        if fb.any():
+            idx = np.flatnonzero(fb)
+            th2, c2, its2, conv2 = self.problem.tr_solve_many(np.zeros((idx.size, self.n_out)),
+                                                              np.asarray(targets)[idx], gtol=gtol, max_iter=max_iter)
+            th[idx], c[idx], conv[idx] = th2, c2, conv2
+            its[idx] += its2
+        return dict(theta=th, cost=c, iters=its, converged=conv, fallback=fb, seconds=time.perf_counter() - t0)
+
+
+def solve_plain(problem: "qoc.Problem", targets, gtol: float = 1e-8, max_iter: int = 10000, chunk: int = 256):
+    """Zero-start solves in lockstep chunks; returns (theta, cost, iters, converged, seconds)."""
+    targets = np.asarray(targets)
+    count = targets.shape[0]
+    th = np.zeros((count, problem.P))
+    c = np.zeros(count)
+    its = np.zeros(count, dtype=np.int32)
+    conv = np.zeros(count, dtype=bool)
+    t0 = time.perf_counter()
+    for s in range(0, count, chunk):
+        e = min(count, s + chunk)
+        th[s:e], c[s:e], its[s:e], conv[s:e] = problem.tr_solve_many(np.zeros((e - s, problem.P)), targets[s:e],
+                                                                      gtol=gtol, max_iter=max_iter)
+    return th, c, its, conv, time.perf_counter() - t0
+
+
+def compare(plain_cost, warm_cost, tol: float = 1e-8) -> dict:
+    """Same final cost within tol counts as a match; otherwise a miss, reported as lower or higher."""
+    d = np.asarray(warm_cost) - np.asarray(plain_cost)
+    return dict(match=int((np.abs(d) <= tol).sum()), lower=int((d < -tol).sum()), higher=int((d > tol).sum()),
+                max_abs_diff_matched=float(np.abs(d[np.abs(d) <= tol]).max()) if (np.abs(d) <= tol).any() else None)
+
+
+def main(argv: Optional[list] = None):
+    from . import inputs
+
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--workload", default="warm")
+    ap.add_argument("--train", type=int, default=2000)
+    ap.add_argument("--test", type=int, default=200)
+    ap.add_argument("--epochs", type=int, default=300)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--batch", type=int, default=128)
+    ap.add_argument("--gtol", type=float, default=1e-8)
+    ap.add_argument("--max-iter", type=int, default=1000)
+    ap.add_argument("--save", default=None, help="write the training set and trained parameters (.npz)")
+    args = ap.parse_args(argv)
+
+    w = inputs.make_workload(args.workload)
+    p = qoc.problem_from_workload(w)
+    tr_t = inputs.warm_targets(w.system.n, args.train, spawn=0)
+    te_t = inputs.warm_targets(w.system.n, args.test, spawn=1)
+    print(f"[warmstart] {args.workload}: n={w.system.n} nt={w.nt} P={w.p}; solving {args.train} training targets",
+          flush=True)
+    tr_th, tr_c, tr_it, tr_conv, tr_s = solve_plain(p, tr_t, args.gtol, args.max_iter)
+    print(f"[warmstart] training set: {tr_s:.1f} s, converged {int(tr_conv.sum())}/{args.train}, "
+          f"mean iters {tr_it.mean():.1f}", flush=True)
+    ws = WarmStart(p)
+    t0 = time.perf_counter()
+    hist = ws.fit(tr_t[tr_conv], tr_th[tr_conv], epochs=args.epochs, lr=args.lr, batch=args.batch)
+    fit_s = time.perf_counter() - t0
+    print(f"[warmstart] trained {args.epochs} epochs in {fit_s:.1f} s, loss {hist[0]:.4f} -> {hist[-1]:.4f}",
+          flush=True)
+    pl_th, pl_c, pl_it, pl_conv, pl_s = solve_plain(p, te_t, args.gtol, args.max_iter)
+    print(f"[warmstart] plain held-out: {pl_s:.1f} s, mean iters {pl_it.mean():.1f}", flush=True)
+    wr = ws.solve(te_t, args.gtol, args.max_iter)
+    print(f"[warmstart] warm held-out: {wr['seconds']:.1f} s, mean iters {wr['iters'].mean():.1f}", flush=True)
+    cmp = compare(pl_c, wr["cost"])
+    pred_c = ws.predict_coords(te_t)
+    true_c, _ = p.control_coords(pl_th)
+    out = dict(
+        workload=args.workload, n=w.system.n, nt=w.nt, P=w.p, rank=ws.rank, train=args.train, test=args.test,
+        train_converged=int(tr_conv.sum()), train_seconds=round(tr_s, 2), fit_seconds=round(fit_s, 2),
+        loss_first=hist[0], loss_last=hist[-1],
+        coord_rel_err_median=float(np.median(np.linalg.norm(pred_c - true_c, axis=1) / np.linalg.norm(true_c, axis=1))),
+        plain=dict(seconds=round(pl_s, 3), solves_per_s=args.test / pl_s, iters_mean=float(pl_it.mean()),
+                   iters_median=float(np.median(pl_it)), converged=int(pl_conv.sum())),
+        warm=dict(seconds=round(wr["seconds"], 3), solves_per_s=args.test / wr["seconds"],
+                  iters_mean=float(wr["iters"].mean()), iters_median=float(np.median(wr["iters"])),
+                  converged=int(wr["converged"].sum()), fallback=int(wr["fallback"].sum())),
+        cost_agreement=cmp,
+    )
+    print(json.dumps(out), flush=True)
+    if args.save:
+        np.savez(args.save, train_targets=tr_t, train_thetas=tr_th, train_costs=tr_c, train_iters=tr_it,
+                 params=ws.mlp.get_params(), mean=ws.mean, scale=ws.scale)
+    return out
+
+
+if __name__ == "__main__":
+    main()
