@@ -158,17 +158,38 @@ qoc_status qoc_tr_solve_many(qoc_problem* p, int32_t count, const double* theta0
 qoc_status qoc_control_coords(qoc_problem* p, int32_t count, const double* theta, double* coords, int32_t* rank);
 qoc_status qoc_params_from_coords(qoc_problem* p, int32_t count, const double* coords, double* theta);
 
-/* Batched evaluation of independent problems of uneven (n, nt, P) in one persistent launch
- * sequence (captured as a HIP graph on first use).  problems: `count` configured handles on
- * the same device; the batch copies their systems and bases. */
+/* Batched evaluation of independent problems of uneven (n, nt, P): cost, gradient and Hessian
+ * of every problem at its own theta.  Problems are grouped by n; each group runs as a chain of
+ * persistent queue launches (one per phase of the evaluation: controls, eigen-data, chunk
+ * joins, forward sweep, terminal, backward sweep, U'' contraction, assembly) whose workgroups
+ * pull (problem, block) items longest first.  The chains run concurrently on their own streams
+ * and the whole sequence is captured as one HIP graph on first use and replayed afterwards.
+ * problems: `count` configured handles on `device`; the batch copies their systems, bases and
+ * weights (later changes to the handles do not affect it) and owns one workspace per problem
+ * (every step's eigen-data is stored: about 24 n^2 nt bytes per problem).
+ * Errors: QOC_ERR_INVALID_ARG (NULL, count < 1, a handle on another device), QOC_ERR_STATE (a
+ * handle without system or basis), QOC_ERR_OOM / QOC_ERR_DEVICE. */
 qoc_status qoc_batch_create(int device, int32_t count, qoc_problem* const* problems, qoc_batch** out);
-void       qoc_batch_destroy(qoc_batch* b);
-/* thetas[i], costs[i], grads[i], hessians[i]: host pointers for problem i (outputs may be NULL). */
+void       qoc_batch_destroy(qoc_batch* b);   /* NULL-safe */
+/* thetas[i]: P_i doubles (host); costs[i] (1), grads[i] (P_i), hessians[i] (P_i x P_i row-major)
+ * are host outputs, any may be NULL (hessians itself may be NULL).  Synchronous. */
 qoc_status qoc_batch_hess(qoc_batch* b, const double* const* thetas, double* const* costs,
                           double* const* grads, double* const* hessians);
-/* Same work as separate per-problem launches (the reference point of the batched path). */
+/* Same results through one launch sequence per problem (the reference point of the batched
+ * launch; same kernels, same tuning). */
 qoc_status qoc_batch_hess_unbatched(qoc_batch* b, const double* const* thetas, double* const* costs,
                                     double* const* grads, double* const* hessians);
+/* Autotuner: times each group's eigen phase over candidate chunk lengths {16..256} and each
+ * (n, P) group's sweeps over candidate tangent columns per workgroup {2..32} at these thetas,
+ * keeps the fastest, and rebuilds the launch plan (the graph is recaptured on the next call). */
+qoc_status qoc_batch_autotune(qoc_batch* b, const double* const* thetas);
+/* Tuning in use for problem i (columns per sweep workgroup, eigen chunk length); set overrides
+ * it (pg in [1, 32], chunk >= 16, or >= 64 for n > 64). */
+qoc_status qoc_batch_get_config(const qoc_batch* b, int32_t i, int32_t* pg, int32_t* chunk);
+qoc_status qoc_batch_set_config(qoc_batch* b, int32_t i, int32_t pg, int32_t chunk);
+/* Device time (HIP events) of the last qoc_batch_hess / _unbatched call's launches, in ms. */
+qoc_status qoc_batch_last_ms(const qoc_batch* b, double* ms);
+qoc_status qoc_batch_memory(const qoc_batch* b, int64_t* bytes);
 const char* qoc_batch_last_error(const qoc_batch* b);
 
 /* Per-kernel timing with HIP events recorded around every launch on the handle's stream.

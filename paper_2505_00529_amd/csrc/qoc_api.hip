@@ -102,23 +102,21 @@ qoc_problem::~qoc_problem() {
   if (own_stream && stream) (void)hipStreamDestroy(stream);
 }
 
-// Lay out (and if needed grow) one evaluation workspace for nb thetas.  seg > 0 sizes the
-// eigen-data for one checkpoint segment of seg steps instead of the whole horizon.
-qoc_status qoc_problem::ensure_work(int nb, int seg) {
+namespace qoc {
+
+size_t layout_work(Work& nw, int n, int nt, int P, int nb, int seg, int chunk_req, void* base) {
   const int np = pad_even(n);
   const int eig_stride = seg > 0 ? std::min(seg, nt) : nt;
-  const int chunk = eig_chunk_len(eig_stride, nb);
+  const int chunk = chunk_req > 0 ? std::min(chunk_req, eig_stride) : eig_chunk_len(eig_stride, nb);
   const int nchunks = (eig_stride + chunk - 1) / chunk;
   const int nseg = (nt + eig_stride - 1) / eig_stride;
-  if (work_mem && work_key_nb == nb && work_key_seg == seg && w.n == n && w.nt == nt && w.P == P) return QOC_OK;
-  release_work();
   const size_t ntn = (size_t)nt * n, nn = (size_t)n * n;
   const size_t en = (size_t)eig_stride * n, enn = (size_t)eig_stride * nn;
   struct Item {
     void** ptr;
     size_t bytes;
   };
-  Work nw;
+  nw = Work();
   nw.n = n;
   nw.np = np;
   nw.nt = nt;
@@ -132,7 +130,7 @@ qoc_status qoc_problem::ensure_work(int nb, int seg) {
   nw.nseg = nseg;
   const size_t B8 = sizeof(double), B16 = sizeof(double2);
   const bool ck = seg > 0 && nseg > 1;
-  std::vector<Item> items = {
+  const Item items[] = {
       {(void**)&nw.f, B8 * nb * nt},
       {(void**)&nw.u, B8 * nb * nt},
       {(void**)&nw.lam, B8 * nb * en},
@@ -161,15 +159,29 @@ qoc_status qoc_problem::ensure_work(int nb, int seg) {
       {(void**)&nw.xf2, ck ? B16 * nb * n * 2 : 0},
   };
   size_t total = 0;
-  for (auto& it : items) total += (it.bytes + 255) & ~(size_t)255;
+  char* cur = (char*)base;
+  for (const auto& it : items) {
+    const size_t b = (it.bytes + 255) & ~(size_t)255;
+    *it.ptr = (base && it.bytes) ? (void*)cur : nullptr;
+    if (base) cur += b;
+    total += b;
+  }
+  return total;
+}
+
+}  // namespace qoc
+
+// Lay out (and if needed grow) one evaluation workspace for nb thetas.  seg > 0 sizes the
+// eigen-data for one checkpoint segment of seg steps instead of the whole horizon.
+qoc_status qoc_problem::ensure_work(int nb, int seg) {
+  if (work_mem && work_key_nb == nb && work_key_seg == seg && w.n == n && w.nt == nt && w.P == P) return QOC_OK;
+  release_work();
+  Work nw;
+  const size_t total = layout_work(nw, n, nt, P, nb, seg, 0, nullptr);
   void* mem = nullptr;
   qoc_status st = dmalloc(&mem, total, "workspace allocation");
   if (st != QOC_OK) return st;
-  char* cur = (char*)mem;
-  for (auto& it : items) {
-    *it.ptr = it.bytes ? (void*)cur : nullptr;
-    cur += (it.bytes + 255) & ~(size_t)255;
-  }
+  layout_work(nw, n, nt, P, nb, seg, 0, mem);
   nw.status = d_status;
   nw.stats = d_stats;
   w = nw;

@@ -86,6 +86,124 @@ struct BasisDev {
 
 enum class Mode { Cost = 0, Grad = 1, Hess = 2, Hvp = 3 };
 
+// ---------------------------------------------------------------- kernel arguments
+// Each kernel is a device body over (argument block, block coordinates).  The single-problem
+// kernels take their block coordinates from the grid; the multi-problem kernels pull work
+// items (argument index, block coordinates) from a queue, so one launch covers many problems.
+
+struct CtlArgs {
+  int nt, P;
+  const double* B;
+  const double* theta;
+  double* f;
+};
+
+struct EigArgs {
+  int n, np, nt, chunk, nchunks;
+  int j_base, nsteps;      // this launch covers global steps [j_base, j_base + nsteps)
+  int eig_stride;          // steps per theta in the eigen-data arrays (indexed by j - j_base)
+  double dt, tol_rel;
+  int max_sweeps, store_derivs, lds_mats;
+  const double* h0;
+  const double* m;
+  const double* f;
+  double* lam;
+  double* mt;
+  double* sm;
+  double* ov;
+  double* vfirst;
+  double* vlast;
+  double* gscratch;
+  int* status;
+  unsigned long long* stats;
+};
+
+struct BndArgs {
+  int n, nsteps, chunk, nchunks, eig_stride;
+  const double* vfirst;
+  const double* vlast;
+  double* ov;
+};
+
+struct SweepArgs {
+  int n, nt, P, pg, ngroups, hvp, need_y;
+  int j_begin, j_end;     // step range of this launch
+  int eig_j0;             // eigen-data arrays are indexed by j - eig_j0 ...
+  size_t eig_stride;      // ... with this many steps per theta
+  double dt;
+  const double* ov;
+  const double* sm;
+  const double* lam;
+  const double* F;        // forcing: [nt][fcols] (shared) or [nb][nt] (HVP)
+  int fcols;
+  size_t f_bstride;
+  const double* vfirst;
+  int nchunks;
+  const double* psi0;     // complex n
+  double2* at;
+  double2* yt;
+  double2* ah;
+  double2* mu;
+  double* q;
+  double* e;
+  double* K;
+  const double* o_in;     // [nb][n][n] O_{j_begin-1} joining the previous segment (j_begin > 0)
+  const double2* xin;     // forward state entering the range ([nb][n][1+P], j_begin > 0)
+  double2* xout;          // forward: X after the range's last step ([nb][n][1+P])
+  const double2* binit;   // backward state entering the range ([nb][n][2])
+  double2* bout;          // backward state leaving the range in basis j_begin-1 ([nb][n][2])
+};
+
+struct TermArgs {
+  int n, P, mode;
+  double rho;
+  const double2* xf;
+  const double* vlast_step;
+  size_t v_bstride;
+  const double* psit;
+  size_t psit_bstride;
+  double2* binit;
+  double* rr;
+  double* aa;
+};
+
+struct StermArgs {
+  int n, nt, ntasks;
+  int j_begin, nsteps, eig_j0;   // tasks cover steps [j_begin, j_begin + nsteps) of every theta
+  size_t eig_stride;
+  double dt, tau;
+  const double* mt;
+  const double* sm;
+  const double* lam;
+  const double2* mu;
+  const double2* at;
+  double* s;
+};
+
+struct AsmArgs {
+  int nt, P, mode, gx;   // gx: blocks sharing one theta's P x P outputs
+  double gamma, rho;
+  const double* B;
+  const double* f;
+  const double* u;
+  const double* q;
+  const double* s;
+  const double* e;
+  const double* K;
+  const double* rr;
+  const double* aa;
+  double* cost;
+  double* grad;
+  double* out;
+};
+
+// One queue entry of a multi-problem launch.
+struct Item {
+  int arg;      // index into the launch's argument array
+  int bx, by;   // block coordinates within that problem's grid
+  int pad;
+};
+
 // Launchers (all enqueue on `stream`; return hipSuccess or the first launch error).
 hipError_t launch_fourier_basis(double* B, int nt, int K, hipStream_t stream);
 hipError_t launch_controls(const BasisDev& bs, const double* theta, double* f, int nb, hipStream_t stream);
@@ -114,6 +232,42 @@ size_t step_props_scratch_doubles(int n);
 hipError_t launch_sym_eig(const double* h, int P, int count, double* evals, double* evecs, double* gs,
                           int* status, hipStream_t stream);
 size_t sym_eig_scratch_doubles(int P, int count);
+
+// Argument blocks of the kernels (the single-problem launchers build theirs the same way).
+CtlArgs controls_args(const BasisDev& bs, const double* theta, double* f);
+EigArgs eig_args(const SysDev& sy, const BasisDev& bs, const Work& w, bool store_derivs, double tol_rel,
+                 int max_sweeps);
+BndArgs boundary_args(const Work& w);
+// pg > 0 overrides the tangent columns per workgroup of the Hessian sweeps (clamped to P).
+SweepArgs sweep_args(const SysDev& sy, const BasisDev& bs, const Work& w, Mode mode, int pg);
+TermArgs terminal_args(const SysDev& sy, const Work& w, Mode mode, double rho);
+StermArgs sterm_args(const BasisDev& bs, const Work& w);
+AsmArgs assemble_args(const BasisDev& bs, const Work& w, Mode mode, double gamma, double rho, double* cost,
+                      double* grad, double* out);
+
+// Multi-problem (queue) launches: one launch per kernel variant covers many problems.
+enum class MultiKind {
+  Controls, EigWave4, EigWave8, EigWave16, EigWave36, EigChunk, Boundary, ForwardStaged, ForwardGlobal,
+  Terminal, BackwardStaged, BackwardGlobal, Sterm, Assemble, Count
+};
+MultiKind eig_kind(int np);
+MultiKind forward_kind(int n);
+MultiKind backward_kind(int n);
+int multi_threads(MultiKind k);
+size_t eig_launch_lds(int np);
+size_t sweep_launch_lds(int n, int pg);
+hipError_t configure_multi_kernels();
+// Sweep launches from prepared arguments (grid: column groups x nb thetas).
+hipError_t launch_forward_args(const SweepArgs& a, int nb, hipStream_t stream);
+hipError_t launch_backward_args(const SweepArgs& a, int nb, hipStream_t stream);
+int multi_grid(MultiKind k, size_t lds, int nitems, int num_cus);
+hipError_t launch_multi(MultiKind k, const void* d_args, const Item* d_items, int nitems, int* d_counter,
+                        size_t lds, int grid, hipStream_t stream);
+hipError_t launch_fill_int(int* p, int count, int v, hipStream_t stream);
+// Workspace layout for nb thetas, checkpoint segment seg (0: whole horizon) and eigen chunk length
+// chunk (0: default); assigns w's pointers inside base (may be null to size only) and returns
+// the bytes needed.
+size_t layout_work(Work& w, int n, int nt, int P, int nb, int seg, int chunk, void* base);
 
 // Largest dynamic LDS request of any kernel; set once per device.
 hipError_t configure_kernels();

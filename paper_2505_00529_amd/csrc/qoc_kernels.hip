@@ -45,14 +45,14 @@ __global__ __launch_bounds__(kThreads) void k_fourier_basis(double* B, int nt, i
 // "Accurate sum and dot product", Dot2: exact products by FMA, error-free sums, one final
 // correction).  A nearly rank-deficient basis makes optimal coefficient vectors large and
 // cancelling; the compensated sum keeps f accurate to working precision in that case.
-__global__ __launch_bounds__(kThreads) void k_controls(const double* B, const double* theta, double* f,
-                                                       int nt, int P) {
+__device__ __forceinline__ void body_controls(const CtlArgs& a, int bx, int b) {
 #pragma clang fp contract(off)   // the error-free transformations need every sum rounded on its own
-  const int j = blockIdx.x * kThreads + threadIdx.x;
-  const int b = blockIdx.y;
+  const int j = bx * kThreads + threadIdx.x;
+  const int nt = a.nt, P = a.P;
   if (j >= nt) return;
-  const double* row = B + (size_t)j * P;
-  const double* th = theta + (size_t)b * P;
+  const double* row = a.B + (size_t)j * P;
+  const double* th = a.theta + (size_t)b * P;
+  double* f = a.f;
   double s = 0.0, c = 0.0;
   for (int k = 0; k < P; ++k) {
     const double x = row[k] * th[k];
@@ -66,27 +66,10 @@ __global__ __launch_bounds__(kThreads) void k_controls(const double* B, const do
   f[(size_t)b * nt + j] = s + c;
 }
 
+__global__ __launch_bounds__(kThreads) void k_controls(CtlArgs a) { body_controls(a, blockIdx.x, blockIdx.y); }
+
 // ---------------------------------------------------------------- eigen-data
 
-struct EigArgs {
-  int n, np, nt, chunk, nchunks;
-  int j_base, nsteps;      // this launch covers global steps [j_base, j_base + nsteps)
-  int eig_stride;          // steps per theta in the eigen-data arrays (indexed by j - j_base)
-  double dt, tol_rel;
-  int max_sweeps, store_derivs, lds_mats;
-  const double* h0;
-  const double* m;
-  const double* f;
-  double* lam;
-  double* mt;
-  double* sm;
-  double* ov;
-  double* vfirst;
-  double* vlast;
-  double* gscratch;
-  int* status;
-  unsigned long long* stats;
-};
 
 __host__ __device__ inline size_t eig_small_doubles(int np) { return (size_t)2 * np + kThreads + np; }
 
@@ -95,9 +78,8 @@ __host__ __device__ inline size_t eig_small_doubles(int np) { return (size_t)2 *
 // step's basis:  V_{j-1}^T H_j V_{j-1} = diag(l_{j-1}) + (f_j - f_{j-1}) Mt_{j-1},
 // which is nearly diagonal for a smooth control, so the Jacobi sweeps converge in a few
 // passes and the rotations accumulate into V_j = V_{j-1} Q_j.
-__global__ __launch_bounds__(kThreads) void k_eig_chunk(EigArgs a) {
+__device__ __forceinline__ void body_eig_chunk(const EigArgs& a, int c, int b) {
   extern __shared__ double smem[];
-  const int c = blockIdx.x, b = blockIdx.y;
   const int np = a.np, n = a.n, nt = a.nt;
   const int j0 = a.j_base + c * a.chunk;
   const int j1 = min(a.j_base + a.nsteps, j0 + a.chunk);
@@ -111,7 +93,7 @@ __global__ __launch_bounds__(kThreads) void k_eig_chunk(EigArgs a) {
   if (a.lds_mats) {
     mats = smem + eig_small_doubles(np) + (np + 1) / 2;  // ints of prs take np/2 doubles
   } else {
-    mats = a.gscratch + ((size_t)b * gridDim.x + c) * 4 * (size_t)np * np;
+    mats = a.gscratch + ((size_t)b * a.nchunks + c) * 4 * (size_t)np * np;
   }
   double* A = mats;
   double* V = A + (size_t)np * np;
@@ -194,13 +176,17 @@ __global__ __launch_bounds__(kThreads) void k_eig_chunk(EigArgs a) {
   }
 }
 
+__global__ __launch_bounds__(kThreads) void k_eig_chunk(EigArgs a) { body_eig_chunk(a, blockIdx.x, blockIdx.y); }
+
 // O_{j0-1} = V_{j0}^T V_{j0-1} across chunk boundaries (first V of chunk c, last V of c-1).
-__global__ __launch_bounds__(kThreads) void k_boundary_overlap(const double* vfirst, const double* vlast,
-                                                                double* ov, int n, int nsteps, int chunk,
-                                                                int nchunks, int eig_stride) {
-  const int c = blockIdx.x + 1, b = blockIdx.y;
+__device__ __forceinline__ void body_boundary(const BndArgs& a, int bx, int b) {
+  const double* vfirst = a.vfirst;
+  const double* vlast = a.vlast;
+  double* ov = a.ov;
+  const int n = a.n, chunk = a.chunk, nchunks = a.nchunks, eig_stride = a.eig_stride;
+  const int c = bx + 1;
   const int j0 = c * chunk;   // local step index within the launch
-  if (j0 >= nsteps) return;
+  if (j0 >= a.nsteps) return;
   const size_t nn = (size_t)n * n;
   const double* Vn = vfirst + ((size_t)b * nchunks + c) * nn;
   const double* Vo = vlast + ((size_t)b * nchunks + c - 1) * nn;
@@ -212,6 +198,8 @@ __global__ __launch_bounds__(kThreads) void k_boundary_overlap(const double* vfi
     dst[idx] = acc;
   }
 }
+
+__global__ __launch_bounds__(kThreads) void k_boundary_overlap(BndArgs a) { body_boundary(a, blockIdx.x, blockIdx.y); }
 
 // ---------------------------------------------------------------- eigen-data, one wave per problem
 
@@ -246,7 +234,7 @@ __device__ __forceinline__ void circ_advance(double (&v)[NP]) {
 // row i of V in registers (slot order = column order at sweep boundaries), and the basis products
 // O_{j-1} = V_j^T V_{j-1}, X = M V_j, Mt_j = V_j^T X use three rotating LDS buffers.
 template <int NP>
-__global__ __launch_bounds__(64, 2) void k_eig_wave(EigArgs a) {
+__device__ __forceinline__ void body_eig_wave(const EigArgs& a, int c, int b) {
   constexpr int H = NP / 2;
   constexpr int NBLK = H * (H + 1) / 2;
   constexpr int BPL = (NBLK + 63) / 64;    // 2x2 blocks per lane
@@ -258,7 +246,6 @@ __global__ __launch_bounds__(64, 2) void k_eig_wave(EigArgs a) {
   double* lamv = rot + NP;                 // eigenvalues
   int* prs = (int*)(lamv + NP);            // players of each pair
   const int lane = threadIdx.x;
-  const int c = blockIdx.x, b = blockIdx.y;
   const int n = a.n, nt = a.nt;
   const int j0 = a.j_base + c * a.chunk;
   const int j1 = min(a.j_base + a.nsteps, j0 + a.chunk);
@@ -479,36 +466,11 @@ __global__ __launch_bounds__(64, 2) void k_eig_wave(EigArgs a) {
   }
 }
 
+template <int NP>
+__global__ __launch_bounds__(64, 2) void k_eig_wave(EigArgs a) { body_eig_wave<NP>(a, blockIdx.x, blockIdx.y); }
+
 // ---------------------------------------------------------------- sweeps
 
-struct SweepArgs {
-  int n, nt, P, pg, ngroups, hvp, need_y;
-  int j_begin, j_end;     // step range of this launch
-  int eig_j0;             // eigen-data arrays are indexed by j - eig_j0 ...
-  size_t eig_stride;      // ... with this many steps per theta
-  double dt;
-  const double* ov;
-  const double* sm;
-  const double* lam;
-  const double* F;        // forcing: [nt][fcols] (shared) or [nb][nt] (HVP)
-  int fcols;
-  size_t f_bstride;
-  const double* vfirst;
-  int nchunks;
-  const double* psi0;     // complex n
-  double2* at;
-  double2* yt;
-  double2* ah;
-  double2* mu;
-  double* q;
-  double* e;
-  double* K;
-  const double* o_in;     // [nb][n][n] O_{j_begin-1} joining the previous segment (j_begin > 0)
-  const double2* xin;     // forward state entering the range ([nb][n][1+P], j_begin > 0)
-  double2* xout;          // forward: X after the range's last step ([nb][n][1+P])
-  const double2* binit;   // backward state entering the range ([nb][n][2])
-  double2* bout;          // backward state leaving the range in basis j_begin-1 ([nb][n][2])
-};
 
 // Sweep kernels keep the current step's O, S and lambda in LDS (STAGE: n <= 64) and load the
 // next step's into registers while the current step computes, so the dependent chain of
@@ -527,9 +489,8 @@ struct StepStage {
 //   X   = [phi o a_j | phi o A'_j + y_j F_j^T],  then [a_{j+1} | A'_{j+1}] = O_j X.
 // X after the last step of the range goes to xout (a_J, A'_J in basis J-1 when j_end = J).
 template <bool STAGE>
-__global__ __launch_bounds__(kThreads) void k_forward(SweepArgs a) {
+__device__ __forceinline__ void body_forward(const SweepArgs& a, int g, int b) {
   extern __shared__ double smem[];
-  const int g = blockIdx.x, b = blockIdx.y;
   const int n = a.n, nt = a.nt, tid = threadIdx.x;
   const int c0 = g * a.pg;
   const int ncol = max(0, min(a.pg, a.P - c0));
@@ -694,15 +655,25 @@ __global__ __launch_bounds__(kThreads) void k_forward(SweepArgs a) {
   }
 }
 
+template <bool STAGE>
+__global__ __launch_bounds__(kThreads) void k_forward(SweepArgs a) { body_forward<STAGE>(a, blockIdx.x, blockIdx.y); }
+
 // Terminal conditions (eq. discretecost, eq. lambdasys with the rho weight, eq. musys):
 // r = a_J - beta in basis nt-1 (r^ = X_0 - V_{J-1}^T beta), |r|^2, lambda_J = rho r,
 // HVP: mu_J = rho a'_J; Hessian: rho Re(A'_J^H A'_J).
-__global__ __launch_bounds__(kThreads) void k_terminal(const double2* xf, const double* vlast_step,
-                                                       size_t v_bstride, const double* psit_all,
-                                                       size_t psit_bstride, double2* binit, double* rr,
-                                                       double* aa, int n, int P, int mode, double rho) {
+__device__ __forceinline__ void body_terminal(const TermArgs& ta, int b, int) {
   __shared__ double red[kThreads];
-  const int b = blockIdx.x, tid = threadIdx.x;
+  const double2* xf = ta.xf;
+  const double* vlast_step = ta.vlast_step;
+  const size_t v_bstride = ta.v_bstride;
+  const double* psit_all = ta.psit;
+  const size_t psit_bstride = ta.psit_bstride;
+  double2* binit = ta.binit;
+  double* rr = ta.rr;
+  double* aa = ta.aa;
+  const int n = ta.n, P = ta.P, mode = ta.mode;
+  const double rho = ta.rho;
+  const int tid = threadIdx.x;
   const double* psit = psit_all + (size_t)b * psit_bstride;
   const double* V = vlast_step + (size_t)b * v_bstride;   // V_{J-1}
   const double2* X = xf + (size_t)b * n * (1 + P);
@@ -735,6 +706,8 @@ __global__ __launch_bounds__(kThreads) void k_terminal(const double2* xf, const 
   }
 }
 
+__global__ __launch_bounds__(kThreads) void k_terminal(TermArgs a) { body_terminal(a, blockIdx.x, 0); }
+
 // Backward sweep (Alg. 2, costate sweep and second-adjoint loop; eq. lambdasys, eq. musys).  Column 0 carries
 // lambda_{j+1} in basis j, columns 1..pg the second-order adjoint columns of the group.
 //   z_j = U'_j^H lambda_{j+1} = i dt conj(h) o (S_j (conj(h) o lambda)),   q_j = Re(lambda^H y_j)
@@ -748,9 +721,8 @@ struct BwdStage {
 };
 
 template <bool STAGE>
-__global__ __launch_bounds__(kThreads) void k_backward(SweepArgs a) {
+__device__ __forceinline__ void body_backward(const SweepArgs& a, int g, int b) {
   extern __shared__ double smem[];
-  const int g = blockIdx.x, b = blockIdx.y;
   const int n = a.n, nt = a.nt, tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
   const int c0 = g * a.pg;
@@ -921,6 +893,9 @@ __global__ __launch_bounds__(kThreads) void k_backward(SweepArgs a) {
   }
 }
 
+template <bool STAGE>
+__global__ __launch_bounds__(kThreads) void k_backward(SweepArgs a) { body_backward<STAGE>(a, blockIdx.x, blockIdx.y); }
+
 // ---------------------------------------------------------------- U'' contraction
 
 // s_j = Re(lambda_{j+1}^H U''_j a_j) = Re(mu^H T_j a) in basis j (second derivative of exp in
@@ -934,18 +909,6 @@ __global__ __launch_bounds__(kThreads) void k_backward(SweepArgs a) {
 //   P_a = Mt (x^a o mu),  Q_d = Mt (x^d o a).
 // The series is truncated by the bound |h_n| <= C(n+2,2) (dt r)^n, r = max |x|; a step whose
 // spread is too wide for kStermNmax terms falls back to the pairwise form below.
-struct StermArgs {
-  int n, nt, ntasks;
-  int j_begin, nsteps, eig_j0;   // tasks cover steps [j_begin, j_begin + nsteps) of every theta
-  size_t eig_stride;
-  double dt, tau;
-  const double* mt;
-  const double* sm;
-  const double* lam;
-  const double2* mu;
-  const double2* at;
-  double* s;
-};
 
 constexpr int kStermNmax = 10;
 
@@ -1002,12 +965,13 @@ __device__ double sterm_pairs_wave(const StermArgs& a, size_t es, size_t vs, int
   return wave_sum(loc);
 }
 
-__global__ __launch_bounds__(kThreads) void k_sterm_wave(StermArgs a) {
+// Tasks bx * waves + wave, stepping nblk * waves: block bx of nblk covering all tasks.
+__device__ __forceinline__ void body_sterm(const StermArgs& a, int bx, int nblk) {
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int n = a.n;
   const size_t nn = (size_t)n * n;
   const int wpb = kThreads / 64;
-  for (int task = blockIdx.x * wpb + wv; task < a.ntasks; task += gridDim.x * wpb) {
+  for (int task = bx * wpb + wv; task < a.ntasks; task += nblk * wpb) {
     const int tb = task / a.nsteps, tj = a.j_begin + (task - tb * a.nsteps);
     const size_t es = (size_t)tb * a.eig_stride + (tj - a.eig_j0);   // eigen-data index
     const size_t vs = (size_t)tb * a.nt + tj;                         // per-step vector index
@@ -1129,6 +1093,8 @@ __global__ __launch_bounds__(kThreads) void k_sterm_wave(StermArgs a) {
   }
 }
 
+__global__ __launch_bounds__(kThreads) void k_sterm_wave(StermArgs a) { body_sterm(a, blockIdx.x, gridDim.x); }
+
 // ---------------------------------------------------------------- assembly
 
 // Final assembly of Alg. 2.  Cost (eq. discretecost): (gamma/2) sum f_j^2 + (rho/2) |r|^2.
@@ -1136,31 +1102,15 @@ __global__ __launch_bounds__(kThreads) void k_sterm_wave(StermArgs a) {
 // Hessian (eq. d2Ldf2, two-sweep form): H = gamma B^T B + rho Re(A'^H A') + B^T K + K^T B
 //                                           + B^T diag(s) B.
 // HVP: Hv = gamma B^T u + B^T (e + s o u).
-struct AsmArgs {
-  int nt, P, mode;
-  double gamma, rho;
-  const double* B;
-  const double* f;
-  const double* u;
-  const double* q;
-  const double* s;
-  const double* e;
-  const double* K;
-  const double* rr;
-  const double* aa;
-  double* cost;
-  double* grad;
-  double* out;
-};
 
-__global__ __launch_bounds__(kThreads) void k_assemble(AsmArgs a) {
+__device__ __forceinline__ void body_assemble(const AsmArgs& a, int bx, int b) {
   __shared__ double red[kThreads];
-  const int b = blockIdx.y, tid = threadIdx.x;
+  const int tid = threadIdx.x;
   const int nt = a.nt, P = a.P;
   const double* f = a.f + (size_t)b * nt;
   const double* q = a.q ? a.q + (size_t)b * nt : nullptr;
-  // blockIdx.x == 0 does cost and gradient; all blocks share the P x P (or P) outputs
-  if (blockIdx.x == 0) {
+  // block 0 does cost and gradient; all a.gx blocks share the P x P (or P) outputs
+  if (bx == 0) {
     double loc = 0.0;
     for (int j = tid; j < nt; j += kThreads) loc += f[j] * f[j];
     const double ff = block_sum(loc, red);
@@ -1176,8 +1126,8 @@ __global__ __launch_bounds__(kThreads) void k_assemble(AsmArgs a) {
   if (a.mode == (int)Mode::Hess) {
     const double* s = a.s + (size_t)b * nt;
     const double* K = a.K + (size_t)b * nt * P;
-    const int per = (P * P + gridDim.x - 1) / gridDim.x;
-    const int i0 = blockIdx.x * per, i1 = min(P * P, i0 + per);
+    const int per = (P * P + a.gx - 1) / a.gx;
+    const int i0 = bx * per, i1 = min(P * P, i0 + per);
     for (int idx = i0 + tid; idx < i1; idx += kThreads) {
       const int l = idx / P, m = idx - l * P;
       double acc = 0.0;
@@ -1188,7 +1138,7 @@ __global__ __launch_bounds__(kThreads) void k_assemble(AsmArgs a) {
       }
       a.out[(size_t)b * P * P + idx] = acc + a.aa[(size_t)b * P * P + idx];
     }
-  } else if (a.mode == (int)Mode::Hvp && blockIdx.x == 0) {
+  } else if (a.mode == (int)Mode::Hvp && bx == 0) {
     const double* s = a.s + (size_t)b * nt;
     const double* e = a.e + (size_t)b * nt;
     const double* u = a.u + (size_t)b * nt;
@@ -1200,6 +1150,8 @@ __global__ __launch_bounds__(kThreads) void k_assemble(AsmArgs a) {
     }
   }
 }
+
+__global__ __launch_bounds__(kThreads) void k_assemble(AsmArgs a) { body_assemble(a, blockIdx.x, blockIdx.y); }
 
 // ---------------------------------------------------------------- inspection kernel
 
@@ -1408,7 +1360,7 @@ hipError_t configure_kernels() {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
   }
-  return hipSuccess;
+  return configure_multi_kernels();
 }
 
 size_t eig_scratch_doubles(int n, int nb, int nchunks) {
@@ -1436,14 +1388,24 @@ hipError_t launch_fourier_basis(double* B, int nt, int K, hipStream_t stream) {
   return hipGetLastError();
 }
 
+CtlArgs controls_args(const BasisDev& bs, const double* theta, double* f) {
+  CtlArgs a;
+  a.nt = bs.nt;
+  a.P = bs.P;
+  a.B = bs.B;
+  a.theta = theta;
+  a.f = f;
+  return a;
+}
+
 hipError_t launch_controls(const BasisDev& bs, const double* theta, double* f, int nb, hipStream_t stream) {
-  hipLaunchKernelGGL(k_controls, dim3((bs.nt + kThreads - 1) / kThreads, nb), dim3(kThreads), 0, stream, bs.B,
-                     theta, f, bs.nt, bs.P);
+  hipLaunchKernelGGL(k_controls, dim3((bs.nt + kThreads - 1) / kThreads, nb), dim3(kThreads), 0, stream,
+                     controls_args(bs, theta, f));
   return hipGetLastError();
 }
 
-hipError_t launch_eig(const SysDev& sy, const BasisDev& bs, Work& w, bool store_derivs, double tol_rel,
-                      int max_sweeps, hipStream_t stream) {
+EigArgs eig_args(const SysDev& sy, const BasisDev& bs, const Work& w, bool store_derivs, double tol_rel,
+                 int max_sweeps) {
   EigArgs a;
   a.n = w.n;
   a.np = w.np;
@@ -1470,6 +1432,24 @@ hipError_t launch_eig(const SysDev& sy, const BasisDev& bs, Work& w, bool store_
   a.gscratch = w.gscratch;
   a.status = w.status;
   a.stats = w.stats;
+  return a;
+}
+
+size_t eig_launch_lds(int np) {
+  switch (np) {
+    case 4:
+    case 8:
+    case 16:
+    case 36:
+      return ((size_t)3 * np * np + 2 * np + (np + 1) / 2) * sizeof(double);
+    default:
+      return eig_lds_bytes(np, eig_fits_lds(np));
+  }
+}
+
+hipError_t launch_eig(const SysDev& sy, const BasisDev& bs, Work& w, bool store_derivs, double tol_rel,
+                      int max_sweeps, hipStream_t stream) {
+  const EigArgs a = eig_args(sy, bs, w, store_derivs, tol_rel, max_sweeps);
   switch (w.np) {
 #define QOC_EIG_WAVE(NPV)                                                                               \
   case NPV: {                                                                                          \
@@ -1490,14 +1470,26 @@ hipError_t launch_eig(const SysDev& sy, const BasisDev& bs, Work& w, bool store_
   return hipGetLastError();
 }
 
+BndArgs boundary_args(const Work& w) {
+  BndArgs a;
+  a.n = w.n;
+  a.nsteps = w.seg_len;
+  a.chunk = w.chunk;
+  a.nchunks = w.nchunks;
+  a.eig_stride = w.eig_stride;
+  a.vfirst = w.vfirst;
+  a.vlast = w.vlast;
+  a.ov = w.ov;
+  return a;
+}
+
 hipError_t launch_boundary(Work& w, hipStream_t stream) {
   if (w.nchunks <= 1) return hipSuccess;
-  hipLaunchKernelGGL(k_boundary_overlap, dim3(w.nchunks - 1, w.nb), dim3(kThreads), 0, stream, w.vfirst, w.vlast,
-                     w.ov, w.n, w.seg_len, w.chunk, w.nchunks, w.eig_stride);
+  hipLaunchKernelGGL(k_boundary_overlap, dim3(w.nchunks - 1, w.nb), dim3(kThreads), 0, stream, boundary_args(w));
   return hipGetLastError();
 }
 
-static SweepArgs sweep_args(const SysDev& sy, const BasisDev& bs, Work& w, Mode mode) {
+SweepArgs sweep_args(const SysDev& sy, const BasisDev& bs, const Work& w, Mode mode, int pg) {
   SweepArgs a;
   a.n = w.n;
   a.nt = w.nt;
@@ -1527,7 +1519,7 @@ static SweepArgs sweep_args(const SysDev& sy, const BasisDev& bs, Work& w, Mode 
     a.fcols = w.P;
     a.f_bstride = 0;
   }
-  a.pg = mode == Mode::Hess ? choose_pg(w.P, w.nb) : 1;
+  a.pg = mode == Mode::Hess ? (pg > 0 ? std::min(pg, w.P) : choose_pg(w.P, w.nb)) : 1;
   a.ngroups = a.P > 0 ? (a.P + a.pg - 1) / a.pg : 1;
   a.vfirst = w.vfirst;
   a.nchunks = w.nchunks;
@@ -1547,38 +1539,58 @@ static SweepArgs sweep_args(const SysDev& sy, const BasisDev& bs, Work& w, Mode 
   return a;
 }
 
-hipError_t launch_forward(const SysDev& sy, const BasisDev& bs, Work& w, Mode mode, hipStream_t stream) {
-  SweepArgs a = sweep_args(sy, bs, w, mode);
-  const size_t lds = sweep_lds_bytes(w.n, a.P > 0 ? a.pg : 0);
-  if (sweep_stage(w.n))
-    hipLaunchKernelGGL(k_forward<true>, dim3(a.ngroups, w.nb), dim3(kThreads), lds, stream, a);
+hipError_t launch_forward_args(const SweepArgs& a, int nb, hipStream_t stream) {
+  const size_t lds = sweep_lds_bytes(a.n, a.P > 0 ? a.pg : 0);
+  if (sweep_stage(a.n))
+    hipLaunchKernelGGL(k_forward<true>, dim3(a.ngroups, nb), dim3(kThreads), lds, stream, a);
   else
-    hipLaunchKernelGGL(k_forward<false>, dim3(a.ngroups, w.nb), dim3(kThreads), lds, stream, a);
+    hipLaunchKernelGGL(k_forward<false>, dim3(a.ngroups, nb), dim3(kThreads), lds, stream, a);
   return hipGetLastError();
+}
+
+hipError_t launch_forward(const SysDev& sy, const BasisDev& bs, Work& w, Mode mode, hipStream_t stream) {
+  return launch_forward_args(sweep_args(sy, bs, w, mode, 0), w.nb, stream);
+}
+
+TermArgs terminal_args(const SysDev& sy, const Work& w, Mode mode, double rho) {
+  TermArgs a;
+  const size_t nn = (size_t)w.n * w.n;
+  a.n = w.n;
+  a.P = mode == Mode::Hvp ? 1 : (mode == Mode::Hess ? w.P : 0);
+  a.mode = (int)mode;
+  a.rho = rho;
+  a.xf = w.xf;
+  a.vlast_step = w.v_last_step ? w.v_last_step : w.vlast + (size_t)(w.nchunks - 1) * nn;
+  a.v_bstride = w.v_last_step ? w.v_last_stride : (size_t)w.nchunks * nn;
+  a.psit = sy.psit;
+  a.psit_bstride = sy.psit_bstride;
+  a.binit = w.binit;
+  a.rr = w.rr;
+  a.aa = w.aa;
+  return a;
 }
 
 hipError_t launch_terminal(const SysDev& sy, const BasisDev& bs, Work& w, Mode mode, double rho,
                            hipStream_t stream) {
-  const int P = mode == Mode::Hvp ? 1 : (mode == Mode::Hess ? w.P : 0);
-  const size_t nn = (size_t)w.n * w.n;
-  const double* vl = w.v_last_step ? w.v_last_step : w.vlast + (size_t)(w.nchunks - 1) * nn;
-  const size_t vstride = w.v_last_step ? w.v_last_stride : (size_t)w.nchunks * nn;
-  hipLaunchKernelGGL(k_terminal, dim3(w.nb), dim3(kThreads), 0, stream, w.xf, vl, vstride, sy.psit, sy.psit_bstride,
-                     w.binit, w.rr, w.aa, w.n, P, (int)mode, rho);
+  (void)bs;
+  hipLaunchKernelGGL(k_terminal, dim3(w.nb), dim3(kThreads), 0, stream, terminal_args(sy, w, mode, rho));
+  return hipGetLastError();
+}
+
+hipError_t launch_backward_args(const SweepArgs& a, int nb, hipStream_t stream) {
+  const size_t lds = sweep_lds_bytes(a.n, a.P > 0 ? a.pg : 0);
+  if (sweep_stage(a.n))
+    hipLaunchKernelGGL(k_backward<true>, dim3(a.ngroups, nb), dim3(kThreads), lds, stream, a);
+  else
+    hipLaunchKernelGGL(k_backward<false>, dim3(a.ngroups, nb), dim3(kThreads), lds, stream, a);
   return hipGetLastError();
 }
 
 hipError_t launch_backward(const SysDev& sy, const BasisDev& bs, Work& w, Mode mode, hipStream_t stream) {
-  SweepArgs a = sweep_args(sy, bs, w, mode);
-  const size_t lds = sweep_lds_bytes(w.n, a.P > 0 ? a.pg : 0);
-  if (sweep_stage(w.n))
-    hipLaunchKernelGGL(k_backward<true>, dim3(a.ngroups, w.nb), dim3(kThreads), lds, stream, a);
-  else
-    hipLaunchKernelGGL(k_backward<false>, dim3(a.ngroups, w.nb), dim3(kThreads), lds, stream, a);
-  return hipGetLastError();
+  return launch_backward_args(sweep_args(sy, bs, w, mode, 0), w.nb, stream);
 }
 
-hipError_t launch_sterm(const SysDev& sy, const BasisDev& bs, Work& w, hipStream_t stream) {
+StermArgs sterm_args(const BasisDev& bs, const Work& w) {
   StermArgs a;
   a.n = w.n;
   a.nt = w.nt;
@@ -1595,6 +1607,12 @@ hipError_t launch_sterm(const SysDev& sy, const BasisDev& bs, Work& w, hipStream
   a.mu = w.mu;
   a.at = w.at;
   a.s = w.s;
+  return a;
+}
+
+hipError_t launch_sterm(const SysDev& sy, const BasisDev& bs, Work& w, hipStream_t stream) {
+  (void)sy;
+  const StermArgs a = sterm_args(bs, w);
   const int wpb = kThreads / 64;
   int blocks = (a.ntasks + wpb - 1) / wpb;
   if (blocks > 256 * 64) blocks = 256 * 64;
@@ -1602,8 +1620,8 @@ hipError_t launch_sterm(const SysDev& sy, const BasisDev& bs, Work& w, hipStream
   return hipGetLastError();
 }
 
-hipError_t launch_assemble(const BasisDev& bs, Work& w, Mode mode, double gamma, double rho, double* cost,
-                           double* grad, double* out, hipStream_t stream) {
+AsmArgs assemble_args(const BasisDev& bs, const Work& w, Mode mode, double gamma, double rho, double* cost,
+                      double* grad, double* out) {
   AsmArgs a;
   a.nt = w.nt;
   a.P = w.P;
@@ -1622,9 +1640,14 @@ hipError_t launch_assemble(const BasisDev& bs, Work& w, Mode mode, double gamma,
   a.cost = cost;
   a.grad = grad;
   a.out = out;
-  int gx = 1;
-  if (mode == Mode::Hess) gx = (w.P * w.P + kThreads - 1) / kThreads;
-  hipLaunchKernelGGL(k_assemble, dim3(gx, w.nb), dim3(kThreads), 0, stream, a);
+  a.gx = mode == Mode::Hess ? (w.P * w.P + kThreads - 1) / kThreads : 1;
+  return a;
+}
+
+hipError_t launch_assemble(const BasisDev& bs, Work& w, Mode mode, double gamma, double rho, double* cost,
+                           double* grad, double* out, hipStream_t stream) {
+  const AsmArgs a = assemble_args(bs, w, mode, gamma, rho, cost, grad, out);
+  hipLaunchKernelGGL(k_assemble, dim3(a.gx, w.nb), dim3(kThreads), 0, stream, a);
   return hipGetLastError();
 }
 
@@ -1645,6 +1668,157 @@ hipError_t launch_identity_basis(double* B, int nt, hipStream_t stream) {
   const size_t tot = (size_t)nt * nt;
   hipLaunchKernelGGL(k_identity_basis, dim3((unsigned)((tot + kThreads - 1) / kThreads)), dim3(kThreads), 0,
                      stream, B, nt);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- multi-problem queue launches
+
+// Next item of a launch's work queue for the whole workgroup (uniform across the group).
+__device__ __forceinline__ int queue_next(int* counter) {
+  __shared__ int s_next;
+  if (threadIdx.x == 0) s_next = atomicAdd(counter, 1);
+  __syncthreads();
+  const int it = __builtin_amdgcn_readfirstlane(s_next);
+  __syncthreads();
+  return it;
+}
+
+// Persistent workgroups drain a queue of (argument, block) items ordered longest first, so one
+// launch runs every problem of a batch that uses this kernel variant, load-balanced on the fly.
+#define QOC_MULTI_KERNEL(NAME, THREADS, WAVES, ARGT, BODY)                                                    \
+  __global__ __launch_bounds__(THREADS, WAVES) void NAME(const ARGT* __restrict__ args,                      \
+                                                          const Item* __restrict__ items, int nitems,          \
+                                                          int* counter) {                                      \
+    for (;;) {                                                                                                 \
+      const int it = queue_next(counter);                                                                      \
+      if (it >= nitems) break;                                                                                 \
+      const Item w = items[it];                                                                                \
+      const ARGT a = args[w.arg];                                                                              \
+      BODY(a, w.bx, w.by);                                                                                     \
+      __syncthreads();                                                                                         \
+    }                                                                                                          \
+  }
+
+QOC_MULTI_KERNEL(km_controls, kThreads, 1, CtlArgs, body_controls)
+QOC_MULTI_KERNEL(km_eig_wave4, 64, 2, EigArgs, body_eig_wave<4>)
+QOC_MULTI_KERNEL(km_eig_wave8, 64, 2, EigArgs, body_eig_wave<8>)
+QOC_MULTI_KERNEL(km_eig_wave16, 64, 2, EigArgs, body_eig_wave<16>)
+QOC_MULTI_KERNEL(km_eig_wave36, 64, 2, EigArgs, body_eig_wave<36>)
+QOC_MULTI_KERNEL(km_eig_chunk, kThreads, 1, EigArgs, body_eig_chunk)
+QOC_MULTI_KERNEL(km_boundary, kThreads, 1, BndArgs, body_boundary)
+QOC_MULTI_KERNEL(km_forward_staged, kThreads, 1, SweepArgs, body_forward<true>)
+QOC_MULTI_KERNEL(km_forward_global, kThreads, 1, SweepArgs, body_forward<false>)
+QOC_MULTI_KERNEL(km_terminal, kThreads, 1, TermArgs, body_terminal)
+QOC_MULTI_KERNEL(km_backward_staged, kThreads, 1, SweepArgs, body_backward<true>)
+QOC_MULTI_KERNEL(km_backward_global, kThreads, 1, SweepArgs, body_backward<false>)
+QOC_MULTI_KERNEL(km_sterm, kThreads, 1, StermArgs, body_sterm)
+QOC_MULTI_KERNEL(km_assemble, kThreads, 1, AsmArgs, body_assemble)
+#undef QOC_MULTI_KERNEL
+
+__global__ __launch_bounds__(kThreads) void k_fill_int(int* p, int count, int v) {
+  const int i = blockIdx.x * kThreads + threadIdx.x;
+  if (i < count) p[i] = v;
+}
+
+static const void* multi_fn(MultiKind k) {
+  switch (k) {
+    case MultiKind::Controls: return (const void*)km_controls;
+    case MultiKind::EigWave4: return (const void*)km_eig_wave4;
+    case MultiKind::EigWave8: return (const void*)km_eig_wave8;
+    case MultiKind::EigWave16: return (const void*)km_eig_wave16;
+    case MultiKind::EigWave36: return (const void*)km_eig_wave36;
+    case MultiKind::EigChunk: return (const void*)km_eig_chunk;
+    case MultiKind::Boundary: return (const void*)km_boundary;
+    case MultiKind::ForwardStaged: return (const void*)km_forward_staged;
+    case MultiKind::ForwardGlobal: return (const void*)km_forward_global;
+    case MultiKind::Terminal: return (const void*)km_terminal;
+    case MultiKind::BackwardStaged: return (const void*)km_backward_staged;
+    case MultiKind::BackwardGlobal: return (const void*)km_backward_global;
+    case MultiKind::Sterm: return (const void*)km_sterm;
+    case MultiKind::Assemble: return (const void*)km_assemble;
+    default: return nullptr;
+  }
+}
+
+int multi_threads(MultiKind k) {
+  switch (k) {
+    case MultiKind::EigWave4:
+    case MultiKind::EigWave8:
+    case MultiKind::EigWave16:
+    case MultiKind::EigWave36:
+      return 64;
+    default:
+      return kThreads;
+  }
+}
+
+MultiKind eig_kind(int np) {
+  switch (np) {
+    case 4: return MultiKind::EigWave4;
+    case 8: return MultiKind::EigWave8;
+    case 16: return MultiKind::EigWave16;
+    case 36: return MultiKind::EigWave36;
+    default: return MultiKind::EigChunk;
+  }
+}
+
+MultiKind forward_kind(int n) { return sweep_stage(n) ? MultiKind::ForwardStaged : MultiKind::ForwardGlobal; }
+MultiKind backward_kind(int n) { return sweep_stage(n) ? MultiKind::BackwardStaged : MultiKind::BackwardGlobal; }
+size_t sweep_launch_lds(int n, int pg) { return sweep_lds_bytes(n, pg); }
+
+hipError_t configure_multi_kernels() {
+  for (int k = 0; k < (int)MultiKind::Count; ++k) {
+    // room for the kernels' static LDS (queue slot, reduction scratch: at most 2 KiB + 4 B)
+    hipError_t e = hipFuncSetAttribute(multi_fn((MultiKind)k), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       160 * 1024 - 4096);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// Persistent grid: as many workgroups as can be resident at once (capped by the item count).
+int multi_grid(MultiKind k, size_t lds, int nitems, int num_cus) {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, multi_fn(k), multi_threads(k), lds) != hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  const long long g = (long long)per_cu * std::max(1, num_cus);
+  return (int)std::max(1LL, std::min<long long>(g, nitems));
+}
+
+hipError_t launch_multi(MultiKind k, const void* d_args, const Item* d_items, int nitems, int* d_counter,
+                        size_t lds, int grid, hipStream_t stream) {
+  if (nitems <= 0) return hipSuccess;
+  const dim3 gd(grid), bd(multi_threads(k));
+  switch (k) {
+#define QOC_MULTI_CASE(KIND, FN, ARGT)                                                                    \
+  case MultiKind::KIND:                                                                                  \
+    hipLaunchKernelGGL(FN, gd, bd, lds, stream, (const ARGT*)d_args, d_items, nitems, d_counter);        \
+    break;
+    QOC_MULTI_CASE(Controls, km_controls, CtlArgs)
+    QOC_MULTI_CASE(EigWave4, km_eig_wave4, EigArgs)
+    QOC_MULTI_CASE(EigWave8, km_eig_wave8, EigArgs)
+    QOC_MULTI_CASE(EigWave16, km_eig_wave16, EigArgs)
+    QOC_MULTI_CASE(EigWave36, km_eig_wave36, EigArgs)
+    QOC_MULTI_CASE(EigChunk, km_eig_chunk, EigArgs)
+    QOC_MULTI_CASE(Boundary, km_boundary, BndArgs)
+    QOC_MULTI_CASE(ForwardStaged, km_forward_staged, SweepArgs)
+    QOC_MULTI_CASE(ForwardGlobal, km_forward_global, SweepArgs)
+    QOC_MULTI_CASE(Terminal, km_terminal, TermArgs)
+    QOC_MULTI_CASE(BackwardStaged, km_backward_staged, SweepArgs)
+    QOC_MULTI_CASE(BackwardGlobal, km_backward_global, SweepArgs)
+    QOC_MULTI_CASE(Sterm, km_sterm, StermArgs)
+    QOC_MULTI_CASE(Assemble, km_assemble, AsmArgs)
+#undef QOC_MULTI_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_int(int* p, int count, int v, hipStream_t stream) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_int, dim3((count + kThreads - 1) / kThreads), dim3(kThreads), 0, stream, p, count, v);
   return hipGetLastError();
 }
 

@@ -1,5 +1,4 @@
-// Exact-Hessian trust-region solver (the optimizer step and stopping test that close Alg. 2)
-// and the batched multi-problem evaluation.
+// Exact-Hessian trust-region solver (the optimizer step and stopping test that close Alg. 2).
 //
 // Trust region: Newton-type method with the exact subproblem
 //     min_p  g^T p + 1/2 p^T H p   s.t.  ||B p||_2 <= Delta,
@@ -466,22 +465,5 @@ qoc_status qoc_tr_solve(qoc_problem* p, const double* theta0, double gtol, int32
   if (!conv) return p->fail(QOC_ERR_NOT_CONVERGED, "trust-region solve reached max_iter before ||grad|| < gtol");
   return QOC_OK;
 }
-
-qoc_status qoc_batch_create(int device, int32_t count, qoc_problem* const* problems, qoc_batch** out) {
-  (void)device; (void)count; (void)problems; (void)out;
-  return QOC_ERR_UNSUPPORTED;
-}
-void qoc_batch_destroy(qoc_batch* b) { (void)b; }
-qoc_status qoc_batch_hess(qoc_batch* b, const double* const* thetas, double* const* costs, double* const* grads,
-                          double* const* hessians) {
-  (void)b; (void)thetas; (void)costs; (void)grads; (void)hessians;
-  return QOC_ERR_UNSUPPORTED;
-}
-qoc_status qoc_batch_hess_unbatched(qoc_batch* b, const double* const* thetas, double* const* costs,
-                                    double* const* grads, double* const* hessians) {
-  (void)b; (void)thetas; (void)costs; (void)grads; (void)hessians;
-  return QOC_ERR_UNSUPPORTED;
-}
-const char* qoc_batch_last_error(const qoc_batch* b) { (void)b; return "not built yet"; }
 
 }  // extern "C"

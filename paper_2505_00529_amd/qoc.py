@@ -75,6 +75,11 @@ SIGNATURES = {
     "qoc_batch_hess_unbatched": (_st, [_vp, ctypes.POINTER(_dp), ctypes.POINTER(_dp),
                                        ctypes.POINTER(_dp), ctypes.POINTER(_dp)]),
     "qoc_batch_last_error": (ctypes.c_char_p, [_vp]),
+    "qoc_batch_autotune": (_st, [_vp, ctypes.POINTER(_dp)]),
+    "qoc_batch_get_config": (_st, [_vp, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
+    "qoc_batch_set_config": (_st, [_vp, _i32, _i32, _i32]),
+    "qoc_batch_last_ms": (_st, [_vp, _dp]),
+    "qoc_batch_memory": (_st, [_vp, ctypes.POINTER(ctypes.c_int64)]),
     "qoc_profile_enable": (_st, [_vp, _i32]),
     "qoc_profile_kernel_ms": (_st, [_vp, ctypes.c_char_p, _dp, ctypes.POINTER(_i32)]),
     "qoc_jacobi_stats": (_st, [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64), _i32]),
@@ -419,6 +424,82 @@ class Mlp:
 
     def sync(self):
         self._check(lib().qoc_mlp_sync(self._h))
+
+
+class Batch:
+    """Handle over many independent problems evaluated together (``qoc_batch``)."""
+
+    def __init__(self, problems, device: int = 0):
+        self.problems = list(problems)
+        self.P = [p.P for p in self.problems]
+        self._h = _vp()
+        arr = (_vp * len(self.problems))(*[p.handle for p in self.problems])
+        st = lib().qoc_batch_create(device, len(self.problems), arr, ctypes.byref(self._h))
+        if st != QOC_OK:
+            raise QocError(st, status_string(st))
+
+    def close(self):
+        if self._h:
+            lib().qoc_batch_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st: int):
+        if st != QOC_OK:
+            raise QocError(st, lib().qoc_batch_last_error(self._h).decode())
+
+    def _thetas(self, thetas):
+        th = [_f64(t, P) for t, P in zip(thetas, self.P)]
+        if len(th) != len(self.P):
+            raise ValueError("one theta per problem")
+        return th, (_dp * len(th))(*[_ptr(t) for t in th])
+
+    def _run(self, fn, thetas, with_hessian=True):
+        th, tp = self._thetas(thetas)
+        c = [np.zeros(1) for _ in self.P]
+        g = [np.zeros(P) for P in self.P]
+        h = [np.zeros((P, P)) for P in self.P] if with_hessian else None
+        cp = (_dp * len(c))(*[_ptr(x) for x in c])
+        gp = (_dp * len(g))(*[_ptr(x) for x in g])
+        hp = (_dp * len(h))(*[_ptr(x) for x in h]) if with_hessian else None
+        self._check(fn(self._h, tp, cp, gp, hp))
+        return np.array([x[0] for x in c]), g, h
+
+    def hess(self, thetas, with_hessian: bool = True):
+        """Batched launch (graph replay): (costs, [grad_i], [hess_i])."""
+        return self._run(lib().qoc_batch_hess, thetas, with_hessian)
+
+    def hess_unbatched(self, thetas, with_hessian: bool = True):
+        """Same results from one launch sequence per problem."""
+        return self._run(lib().qoc_batch_hess_unbatched, thetas, with_hessian)
+
+    def autotune(self, thetas):
+        th, tp = self._thetas(thetas)
+        self._check(lib().qoc_batch_autotune(self._h, tp))
+
+    def config(self, i: int):
+        pg = _i32()
+        ch = _i32()
+        self._check(lib().qoc_batch_get_config(self._h, i, ctypes.byref(pg), ctypes.byref(ch)))
+        return int(pg.value), int(ch.value)
+
+    def set_config(self, i: int, pg: int, chunk: int):
+        self._check(lib().qoc_batch_set_config(self._h, i, pg, chunk))
+
+    def last_ms(self) -> float:
+        ms = np.zeros(1)
+        self._check(lib().qoc_batch_last_ms(self._h, _ptr(ms)))
+        return float(ms[0])
+
+    def memory(self) -> int:
+        b = ctypes.c_int64()
+        self._check(lib().qoc_batch_memory(self._h, ctypes.byref(b)))
+        return int(b.value)
 
 
 def problem_from_workload(w, device: int = 0) -> Problem:
