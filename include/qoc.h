@@ -179,9 +179,10 @@ qoc_status qoc_batch_hess(qoc_batch* b, const double* const* thetas, double* con
  * launch; same kernels, same tuning). */
 qoc_status qoc_batch_hess_unbatched(qoc_batch* b, const double* const* thetas, double* const* costs,
                                     double* const* grads, double* const* hessians);
-/* Autotuner: times each group's eigen phase over candidate chunk lengths {16..256} and each
- * (n, P) group's sweeps over candidate tangent columns per workgroup {2..32} at these thetas,
- * keeps the fastest, and rebuilds the launch plan (the graph is recaptured on the next call). */
+/* Autotuner: on a sample of each (n, P) group (its 4 longest problems) it times the group's
+ * eigen phase over candidate chunk lengths {16..256} and its sweeps over candidate tangent
+ * columns per workgroup {2..32} at these thetas, keeps the fastest for the whole group, and
+ * rebuilds the launch plan (the graph is recaptured on the next call). */
 qoc_status qoc_batch_autotune(qoc_batch* b, const double* const* thetas);
 /* Tuning in use for problem i (columns per sweep workgroup, eigen chunk length); set overrides
  * it (pg in [1, 32], chunk >= 16, or >= 64 for n > 64). */

@@ -37,6 +37,7 @@ constexpr int kBatchMaxSweeps = 40;
 constexpr int kStermItemsPerBlock = 16;   // sterm items: each covers 16 waves' worth of tasks
 constexpr int kChunkCandidates[] = {16, 32, 64, 128, 256};
 constexpr int kPgCandidates[] = {2, 4, 8, 16, 32};
+constexpr int kTuneSample = 4;   // problems per (n, P) group timed by the autotuner
 
 struct Prob {
   int n = 0, nt = 0, P = 0;
@@ -74,6 +75,7 @@ struct qoc_batch {
   std::vector<Prob> pr;
   std::vector<int> cls_of;        // problem -> class
   std::vector<int> cls_n;         // class -> N
+  std::vector<char> active;       // problems given queue items (all, except while tuning)
   int64_t total_p = 0, total_pp = 0;
   // device memory
   void* sys_mem = nullptr;
@@ -220,6 +222,7 @@ qoc_status qoc_batch::build_plan() {
     lds_of[k] = std::max(lds_of[k], lds);
   };
   for (int i = 0; i < count; ++i) {
+    if (!active[i]) continue;
     const Prob& q = pr[i];
     const double n = q.n, nt = q.nt;
     for (int bxi = 0; bxi < (q.nt + kThreads - 1) / kThreads; ++bxi) add(i, kCtl, MultiKind::Controls, bxi, 0, q.P, 0);
@@ -489,6 +492,7 @@ qoc_status qoc_batch_create(int device, int32_t count, qoc_problem* const* probl
   std::vector<int> per_cls(cls_index.size(), 0);
   b->pr.resize(count);
   b->cls_of.resize(count);
+  b->active.assign(count, 1);
   size_t sys_doubles = 0;
   for (int i = 0; i < count; ++i) {
     const qoc_problem* p = problems[i];
@@ -642,6 +646,21 @@ qoc_status qoc_batch_autotune(qoc_batch* b, const double* const* thetas) {
   if (st != QOC_OK) return st;
   const int count = (int)b->pr.size();
   const int ncls = (int)b->cls_n.size();
+  // time a sample of each group: its longest problems, at most kTuneSample per (n, P)
+  {
+    std::map<std::pair<int, int>, std::vector<int>> groups;
+    for (int i = 0; i < count; ++i) groups[{b->pr[i].n, b->pr[i].P}].push_back(i);
+    std::fill(b->active.begin(), b->active.end(), 0);
+    for (auto& kv : groups) {
+      auto& v = kv.second;
+      std::stable_sort(v.begin(), v.end(), [&](int x, int y) { return b->pr[x].nt > b->pr[y].nt; });
+      for (size_t k = 0; k < v.size() && k < (size_t)kTuneSample; ++k) b->active[v[k]] = 1;
+    }
+  }
+  struct ActiveReset {
+    qoc_batch* b;
+    ~ActiveReset() { std::fill(b->active.begin(), b->active.end(), 1); }
+  } active_reset{b};
   // eigen chunk per class (the eigen phase and the chunk joins)
   for (int c = 0; c < ncls; ++c) {
     int best = -1;
@@ -650,17 +669,15 @@ qoc_status qoc_batch_autotune(qoc_batch* b, const double* const* thetas) {
       bool any = false;
       for (int i = 0; i < count; ++i)
         if (b->cls_of[i] == c) {
-          any = any || cand >= b->pr[i].chunk_min;
+          any = any || (b->active[i] && cand >= b->pr[i].chunk_min);
           b->set_chunk(i, cand);
         }
       if (!any) continue;
       st = b->build_plan();
       if (st != QOC_OK) return st;
-      float ms = 0.f, ms2 = 0.f;
+      float ms = 0.f;
       st = b->time_class_phases(c, {kCtl, kEig, kBnd}, &ms);
-      if (st == QOC_OK) st = b->time_class_phases(c, {kCtl, kEig, kBnd}, &ms2);
       if (st != QOC_OK) return st;
-      ms = std::min(ms, ms2);
       if (best < 0 || ms < best_ms) {
         best = cand;
         best_ms = ms;
@@ -693,11 +710,9 @@ qoc_status qoc_batch_autotune(qoc_batch* b, const double* const* thetas) {
           if (b->cls_of[i] == c && b->pr[i].P == P) b->pr[i].pg = std::min(cand, P);
         st = b->build_plan();
         if (st != QOC_OK) return st;
-        float ms = 0.f, ms2 = 0.f;
+        float ms = 0.f;
         st = b->time_class_phases(c, {kFwd, kTerm, kBwd}, &ms);
-        if (st == QOC_OK) st = b->time_class_phases(c, {kFwd, kTerm, kBwd}, &ms2);
         if (st != QOC_OK) return st;
-        ms = std::min(ms, ms2);
         if (best < 0 || ms < best_ms) {
           best = std::min(cand, P);
           best_ms = ms;
@@ -707,6 +722,7 @@ qoc_status qoc_batch_autotune(qoc_batch* b, const double* const* thetas) {
         if (b->cls_of[i] == c && b->pr[i].P == P) b->pr[i].pg = best;
     }
   }
+  std::fill(b->active.begin(), b->active.end(), 1);
   st = b->build_plan();
   if (st != QOC_OK) return st;
   return b->check_status();

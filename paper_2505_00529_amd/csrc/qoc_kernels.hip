@@ -469,17 +469,368 @@ __device__ __forceinline__ void body_eig_wave(const EigArgs& a, int c, int b) {
 template <int NP>
 __global__ __launch_bounds__(64, 2) void k_eig_wave(EigArgs a) { body_eig_wave<NP>(a, blockIdx.x, blockIdx.y); }
 
+// ---------------------------------------------------------------- eigen-data, one workgroup per problem
+
+// Workgroup (4 waves) variant for NP in {36, 64}: the four waves share one problem's LDS
+// (A and V, plus V_{j-1} when it fits), so a compute unit keeps several problems' waves resident
+// and the dependent chain of each Jacobi round is hidden.  Per round: the H = NP/2 rotations of
+// a round-robin pairing are formed by the first H threads, then every thread updates its fixed
+// 2x2 blocks of A (A <- J^T A J) and its fixed (pair, row) items of V (V <- V J).  V is kept
+// column-major so that one pair's items touch consecutive words.  Products at the end of a
+// step use register tiles.  Without LDS room for V_{j-1} (NP = 64) it goes through
+// a global scratch of NP x NP doubles per (theta, chunk).
+template <int NP>
+struct EigWgShape;
+template <>
+struct EigWgShape<36> {
+  static constexpr int TPB = 256;        // threads per workgroup
+  static constexpr int RT = 2, CT = 3;   // 18 x 12 output tiles
+  static constexpr bool VP_LDS = true;
+};
+template <>
+struct EigWgShape<64> {
+  static constexpr int TPB = 512;        // eight waves share the 66 KB of LDS
+  static constexpr int RT = 4, CT = 2;   // 16 x 32 output tiles
+  static constexpr bool VP_LDS = false;
+};
+
+template <int NP>
+__host__ __device__ constexpr size_t eig_wg_lds_doubles() {
+  return (size_t)(EigWgShape<NP>::VP_LDS ? 3 : 2) * NP * NP + 2 * (NP / 2) + (NP / 2) + NP +
+         EigWgShape<NP>::TPB / 64;
+}
+
+// Sum / max over a workgroup of TPB threads from the wave partials (red: TPB/64 doubles of LDS).
+template <int TPB>
+__device__ __forceinline__ double wg_sum(double v, double* red) {
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = 0.0;
+#pragma unroll
+  for (int w = 0; w < TPB / 64; ++w) r += red[w];
+  __syncthreads();
+  return r;
+}
+template <int TPB>
+__device__ __forceinline__ double wg_max(double v, double* red) {
+  v = wave_max(v);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = red[0];
+#pragma unroll
+  for (int w = 1; w < TPB / 64; ++w) r = fmax(r, red[w]);
+  __syncthreads();
+  return r;
+}
+
+template <int NP>
+__device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
+  constexpr int H = NP / 2;
+  constexpr int NBLK = H * (H + 1) / 2;
+  constexpr int TPB = EigWgShape<NP>::TPB;
+  constexpr int BPT = (NBLK + TPB - 1) / TPB;
+  constexpr int NVI = NP * H;
+  constexpr int VPT = (NVI + TPB - 1) / TPB;
+  constexpr int RT = EigWgShape<NP>::RT, CT = EigWgShape<NP>::CT;
+  constexpr int TCOLS = NP / CT;                  // tiles per output row
+  constexpr int NTILE = (NP / RT) * TCOLS;
+  constexpr bool VP_LDS = EigWgShape<NP>::VP_LDS;
+  static_assert(NP % RT == 0 && NP % CT == 0 && NTILE <= TPB, "tile shape");
+  extern __shared__ double smem[];
+  double* A = smem;                              // NP x NP
+  double* Vt = A + NP * NP;                      // NP x NP, column-major: Vt[k * NP + i] = V[i][k]
+  double* Vp = VP_LDS ? Vt + NP * NP : nullptr;  // V_{j-1}, same layout
+  double2* rot = (double2*)(Vt + (VP_LDS ? 2 : 1) * NP * NP);  // (c, s) per pair
+  int2* prs = (int2*)(rot + H);                  // (p, q) per pair
+  double* lamv = (double*)rot + 3 * H;           // eigenvalues
+  double* red = lamv + NP;                       // wave partials
+  const int tid = threadIdx.x;
+  const int n = a.n, nt = a.nt;
+  const int j0 = a.j_base + c * a.chunk;
+  const int j1 = min(a.j_base + a.nsteps, j0 + a.chunk);
+  if (j0 >= j1) return;
+  const double* fb = a.f + (size_t)b * nt;
+  const size_t nn = (size_t)n * n;
+  double* vpg = VP_LDS ? nullptr : a.gscratch + ((size_t)b * a.nchunks + c) * NP * NP;
+
+  // fixed work of this thread: 2x2 blocks (I <= K) and V items (row, pair)
+  int bI[BPT], bK[BPT];
+#pragma unroll
+  for (int t = 0; t < BPT; ++t) {
+    const int w = tid + TPB * t;
+    int I = -1, K = 0;
+    if (w < NBLK) {
+      I = 0;
+      int rem = w;
+      while (rem >= H - I) {
+        rem -= H - I;
+        ++I;
+      }
+      K = I + rem;
+    }
+    bI[t] = I;
+    bK[t] = K;
+  }
+  // V items u = tid + TPB t: pair u / NP, row u % NP, so consecutive threads take consecutive
+  // rows of one pair (conflict-free columns of Vt, one broadcast of the pair's rotation)
+  // output tile of this thread
+  const int tr = tid / TCOLS, tc = tid - (tid / TCOLS) * TCOLS;
+  const bool has_tile = tid < NTILE;
+  const int i0 = tr * RT, k0 = tc * CT;
+
+  for (int j = j0; j < j1; ++j) {
+    const double fj = fb[j];
+    if (j == j0) {
+      for (int idx = tid; idx < NP * NP; idx += TPB) {
+        const int i = idx / NP, k = idx - (idx / NP) * NP;
+        A[idx] = (i < n && k < n) ? a.h0[i * n + k] + fj * a.m[i * n + k] : 0.0;
+        Vt[idx] = i == k ? 1.0 : 0.0;
+      }
+    } else {
+      const double df = fj - fb[j - 1];
+      for (int idx = tid; idx < NP * NP; idx += TPB) {
+        const int i = idx / NP, k = idx - (idx / NP) * NP;
+        A[idx] = df * A[idx] + (i == k ? lamv[i] : 0.0);   // A held Mt_{j-1}
+        if (VP_LDS) Vp[idx] = Vt[idx];
+      }
+    }
+    __syncthreads();
+    double loc = 0.0;
+    for (int idx = tid; idx < NP * NP; idx += TPB) loc = fma(A[idx], A[idx], loc);
+    const double tol = a.tol_rel * sqrt(wg_sum<TPB>(loc, red));
+#pragma unroll 1
+    for (int sweep = 0;; ++sweep) {
+      double off = 0.0;
+      for (int idx = tid; idx < NP * NP; idx += TPB) {
+        const int i = idx / NP, k = idx - (idx / NP) * NP;
+        if (i < k) off = fmax(off, fabs(A[idx]));
+      }
+      off = wg_max<TPB>(off, red);
+      if (off <= tol) {
+        if (tid == 0 && a.stats) {
+          atomicAdd(a.stats, 1ull);
+          atomicAdd(a.stats + 1, (unsigned long long)sweep);
+        }
+        break;
+      }
+      if (sweep >= a.max_sweeps) {
+        if (tid == 0) atomicOr(a.status, kStatusNoConv);
+        break;
+      }
+#pragma unroll 1
+      for (int r = 0; r < NP - 1; ++r) {
+        if (tid < H) {
+          int p, q;
+          rr_pair(r, tid, NP, p, q);
+          const double app = A[p * NP + p], aqq = A[q * NP + q], apq = A[p * NP + q];
+          double cc = 1.0, ss = 0.0;
+          if (apq != 0.0) {
+            // tan of the rotation angle: t = sign(d) e / (|d| + sqrt(d^2 + e^2)), d = aqq - app,
+            // e = 2 apq (the smaller root of t^2 + 2 (d/e) t - 1 = 0)
+            const double d = aqq - app, e = 2.0 * apq;
+            const double den = fabs(d) + sqrt(fma(d, d, e * e));
+            const double t = den > 0.0 ? (d >= 0.0 ? e : -e) / den : 1.0;
+            cc = 1.0 / sqrt(fma(t, t, 1.0));
+            ss = t * cc;
+          }
+          rot[tid] = make_double2(cc, ss);
+          prs[tid] = make_int2(p, q);
+        }
+        __syncthreads();
+#pragma unroll 1
+        for (int t = 0; t < BPT; ++t) {
+          const int I = bI[t];
+          if (I >= 0) {
+            const int K = bK[t];
+            const int2 PI = prs[I], PK = prs[K];
+            const double2 RI = rot[I], RK = rot[K];
+            const int pI = PI.x, qI = PI.y, pK = PK.x, qK = PK.y;
+            const double cI = RI.x, sI = RI.y, cK = RK.x, sK = RK.y;
+            const double a00 = A[pI * NP + pK], a01 = A[pI * NP + qK];
+            const double a10 = A[qI * NP + pK], a11 = A[qI * NP + qK];
+            const double t00 = a00 * cK - a01 * sK, t01 = a00 * sK + a01 * cK;
+            const double t10 = a10 * cK - a11 * sK, t11 = a10 * sK + a11 * cK;
+            const double b00 = cI * t00 - sI * t10, b01 = cI * t01 - sI * t11;
+            const double b10 = sI * t00 + cI * t10, b11 = sI * t01 + cI * t11;
+            if (I == K) {
+              A[pI * NP + pI] = b00;
+              A[pI * NP + qI] = 0.0;
+              A[qI * NP + pI] = 0.0;
+              A[qI * NP + qI] = b11;
+            } else {
+              A[pI * NP + pK] = b00;
+              A[pI * NP + qK] = b01;
+              A[qI * NP + pK] = b10;
+              A[qI * NP + qK] = b11;
+              A[pK * NP + pI] = b00;
+              A[qK * NP + pI] = b01;
+              A[pK * NP + qI] = b10;
+              A[qK * NP + qI] = b11;
+            }
+          }
+        }
+#pragma unroll 2
+        for (int t = 0; t < VPT; ++t) {
+          const int u = tid + TPB * t;
+          if (u < NVI) {
+            const int K = u / NP, i = u - (u / NP) * NP;
+            const int2 PQ = prs[K];
+            const double2 R = rot[K];
+            const double vp = Vt[PQ.x * NP + i], vq = Vt[PQ.y * NP + i];
+            Vt[PQ.x * NP + i] = R.x * vp - R.y * vq;
+            Vt[PQ.y * NP + i] = R.y * vp + R.x * vq;
+          }
+        }
+        __syncthreads();
+      }
+    }
+    if (tid < NP) lamv[tid] = A[tid * NP + tid];
+    __syncthreads();
+    const size_t step = (size_t)b * a.eig_stride + (j - a.j_base);
+    double acc[RT][CT];
+    // O_{j-1} = V_j^T V_{j-1}
+    if (j > j0 && has_tile) {
+#pragma unroll
+      for (int x = 0; x < RT; ++x)
+#pragma unroll
+        for (int y = 0; y < CT; ++y) acc[x][y] = 0.0;
+      const double* Vprev = VP_LDS ? Vp : vpg;
+#pragma unroll 2
+      for (int r = 0; r < n; ++r) {
+        double u[RT], w[CT];
+#pragma unroll
+        for (int x = 0; x < RT; ++x) u[x] = Vt[(i0 + x) * NP + r];
+#pragma unroll
+        for (int y = 0; y < CT; ++y) w[y] = Vprev[(k0 + y) * NP + r];
+#pragma unroll
+        for (int x = 0; x < RT; ++x)
+#pragma unroll
+          for (int y = 0; y < CT; ++y) acc[x][y] = fma(u[x], w[y], acc[x][y]);
+      }
+      double* dst = a.ov + (step - 1) * nn;
+#pragma unroll
+      for (int x = 0; x < RT; ++x)
+#pragma unroll
+        for (int y = 0; y < CT; ++y)
+          if (i0 + x < n && k0 + y < n) dst[(size_t)(i0 + x) * n + k0 + y] = acc[x][y];
+    }
+    // X = M V_j into A (M symmetric: row r of M is column r)
+    if (has_tile) {
+#pragma unroll
+      for (int x = 0; x < RT; ++x)
+#pragma unroll
+        for (int y = 0; y < CT; ++y) acc[x][y] = 0.0;
+#pragma unroll 2
+      for (int r = 0; r < n; ++r) {
+        double u[RT], w[CT];
+#pragma unroll
+        for (int x = 0; x < RT; ++x) u[x] = i0 + x < n ? a.m[r * n + i0 + x] : 0.0;
+#pragma unroll
+        for (int y = 0; y < CT; ++y) w[y] = Vt[(k0 + y) * NP + r];
+#pragma unroll
+        for (int x = 0; x < RT; ++x)
+#pragma unroll
+          for (int y = 0; y < CT; ++y) acc[x][y] = fma(u[x], w[y], acc[x][y]);
+      }
+#pragma unroll
+      for (int x = 0; x < RT; ++x)
+#pragma unroll
+        for (int y = 0; y < CT; ++y) A[(i0 + x) * NP + k0 + y] = acc[x][y];
+    }
+    __syncthreads();
+    // Mt_j = V_j^T X, kept in A for the next step's warm start and written out with S_j
+    if (has_tile) {
+#pragma unroll
+      for (int x = 0; x < RT; ++x)
+#pragma unroll
+        for (int y = 0; y < CT; ++y) acc[x][y] = 0.0;
+#pragma unroll 2
+      for (int r = 0; r < n; ++r) {
+        double u[RT], w[CT];
+#pragma unroll
+        for (int x = 0; x < RT; ++x) u[x] = Vt[(i0 + x) * NP + r];
+#pragma unroll
+        for (int y = 0; y < CT; ++y) w[y] = A[r * NP + k0 + y];
+#pragma unroll
+        for (int x = 0; x < RT; ++x)
+#pragma unroll
+          for (int y = 0; y < CT; ++y) acc[x][y] = fma(u[x], w[y], acc[x][y]);
+      }
+    }
+    __syncthreads();
+    if (has_tile) {
+#pragma unroll
+      for (int x = 0; x < RT; ++x)
+#pragma unroll
+        for (int y = 0; y < CT; ++y) {
+          const int i = i0 + x, k = k0 + y;
+          A[i * NP + k] = acc[x][y];
+          if (i < n && k < n) {
+            if (a.store_derivs) {
+              a.mt[step * nn + (size_t)i * n + k] = acc[x][y];
+              a.sm[step * nn + (size_t)i * n + k] = sinc(0.5 * a.dt * (lamv[i] - lamv[k])) * acc[x][y];
+            }
+          }
+        }
+    }
+    // eigenvalues, V_j for the next step's overlap, and the chunk ends
+    if (tid < n) a.lam[step * n + tid] = lamv[tid];
+    for (int idx = tid; idx < NP * NP; idx += TPB) {
+      if (!VP_LDS) vpg[idx] = Vt[idx];
+      const int k = idx / NP, i = idx - (idx / NP) * NP;   // Vt[idx] = V[i][k]
+      if (i < n && k < n) {
+        if (j == j0) a.vfirst[((size_t)b * a.nchunks + c) * nn + (size_t)i * n + k] = Vt[idx];
+        if (j == j1 - 1) a.vlast[((size_t)b * a.nchunks + c) * nn + (size_t)i * n + k] = Vt[idx];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <int NP>
+__global__ __launch_bounds__(EigWgShape<NP>::TPB, 4) void k_eig_wg(EigArgs a) {
+  body_eig_wg<NP>(a, blockIdx.x, blockIdx.y);
+}
+
 // ---------------------------------------------------------------- sweeps
 
 
 // Sweep kernels keep the current step's O, S and lambda in LDS (STAGE: n <= 64) and load the
 // next step's into registers while the current step computes, so the dependent chain of
-// steps never waits on HBM.  Product tiles are 4 rows x 1 complex column per thread.
+// steps never waits on HBM.  Product tiles are 4 rows x 1 complex column per thread, and the
+// length-n inner loops are unrolled so that their LDS reads overlap.
 constexpr int kPrefetch = 16;   // doubles per thread per staged n x n matrix (n*n <= 16*256)
+constexpr int kPrefetchSmall = 8;   // n*n <= 8*256: O and S double-buffered in LDS instead
+constexpr int kTileRows = 4;    // rows of the O product per thread (x 1 complex column)
 
+// Sweep variants: kSweepGlobal reads O and S from global memory inside the step (n > 64);
+// kSweepRegs stages them in LDS from registers loaded one step ahead (n <= 64); kSweepAsync
+// double-buffers them in LDS with direct global-to-LDS loads issued one step ahead (n <= 45).
+constexpr int kSweepGlobal = 0, kSweepRegs = 1, kSweepAsync = 2;
+
+// Copy `count` doubles from global memory to LDS with direct global-to-LDS dword loads (each
+// lane moves one dword; wave w takes every (waves)-th 64-dword segment).  The caller waits for
+// completion (vmcnt) and synchronises the workgroup before the data is read.
+__device__ __forceinline__ void lds_copy_async(double* dst, const double* src, int count) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int dwords = 2 * count;
+  for (int seg = wv * 64; seg < dwords; seg += kThreads) {
+    const int d = seg + lane;
+    if (d < dwords)
+      __builtin_amdgcn_global_load_lds((const void*)((const unsigned*)src + d),
+                                       (__attribute__((address_space(3))) void*)((unsigned*)dst + seg), 4, 0, 0);
+  }
+}
+// s_waitcnt vmcnt(0) (expcnt and lgkmcnt left at their maxima)
+__device__ __forceinline__ void wait_vm_all() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+template <int MODE>
 struct StepStage {
-  double po[kPrefetch], ps[kPrefetch];
+  static constexpr int PF = MODE == kSweepRegs ? kPrefetch : 1;
+  double po[PF], ps[PF];
   double pl;
+  double pf;   // forcing value of column tid + 1 (tid < columns of the group)
 };
 
 // Forward sweep (Alg. 2, forward state sweep and tangent loop; eq. gradatheta) for one theta and one group of
@@ -488,7 +839,27 @@ struct StepStage {
 //   y_j = U'_j a_j = -i dt h o (S_j (h o a_j)),  h = exp(-i dt l_j / 2)
 //   X   = [phi o a_j | phi o A'_j + y_j F_j^T],  then [a_{j+1} | A'_{j+1}] = O_j X.
 // X after the last step of the range goes to xout (a_J, A'_J in basis J-1 when j_end = J).
-template <bool STAGE>
+// Item coordinates (row, column) of idx = tid + k * kThreads over an n x w array, advanced
+// without divisions.
+struct ItemWalk {
+  int p, col, dp, dc, w;
+  __device__ ItemWalk(int tid, int w_) : w(w_) {
+    p = tid / w_;
+    col = tid - p * w_;
+    dp = kThreads / w_;
+    dc = kThreads - dp * w_;
+  }
+  __device__ void next() {
+    p += dp;
+    col += dc;
+    if (col >= w) {
+      col -= w;
+      ++p;
+    }
+  }
+};
+
+template <int MODE>
 __device__ __forceinline__ void body_forward(const SweepArgs& a, int g, int b) {
   extern __shared__ double smem[];
   const int n = a.n, nt = a.nt, tid = threadIdx.x;
@@ -496,34 +867,44 @@ __device__ __forceinline__ void body_forward(const SweepArgs& a, int g, int b) {
   const int ncol = max(0, min(a.pg, a.P - c0));
   const int w = 1 + ncol;           // columns carried
   const size_t nn = (size_t)n * n;
-  double* Ob = smem;                // O_j^T: Ob[r*n + p] = O_j[p][r]
-  double* Sb = Ob + (STAGE ? nn : 0);
-  double2* cur = (double2*)(Sb + (STAGE ? nn : 0));   // [n][w]
+  constexpr bool STAGE = MODE != kSweepGlobal;
+  constexpr bool ASYNC = MODE == kSweepAsync;
+  // kSweepRegs: Ob[r*n + p] = O_j[p][r] (transposed); kSweepAsync: two buffers each of O_j
+  // (row-major, as stored) and S_j
+  double* Ob = smem;
+  double* Sb = Ob + (STAGE ? nn : 0) * (ASYNC ? 2 : 1);
+  double2* cur = (double2*)(Sb + (STAGE ? nn : 0) * (ASYNC ? 2 : 1));   // [n][w]
   double2* X = cur + n * w;         // [n][w]
   double2* hh = X + n * w;          // [n]
   double2* ph = hh + n;             // [n]
   double2* yv = ph + n;             // [n]
+  double* fv = (double*)(yv + n);   // [pg] forcing values of the step
   const double* Fb = a.F + (size_t)b * a.f_bstride;
   const size_t vb0 = (size_t)b * nt;                 // per-step vectors
   const size_t eb0 = (size_t)b * a.eig_stride;       // eigen-data
   const int xw = 1 + a.P;
+  const int ph_t = tid - (kThreads - 128);           // waves 2 and 3 evaluate the step's phases
 
-  auto load_step = [&](int j, StepStage& st) {
+  auto load_step = [&](int j, StepStage<MODE>& st, int buf) {
     const size_t es = eb0 + (j - a.eig_j0);
-    if (STAGE) {
+    if (ASYNC) {
+      if (j + 1 < a.j_end) lds_copy_async(Ob + buf * nn, a.ov + es * nn, (int)nn);
+      if (a.need_y) lds_copy_async(Sb + buf * nn, a.sm + es * nn, (int)nn);
+    } else if (STAGE) {
 #pragma unroll
-      for (int i = 0; i < kPrefetch; ++i) {
+      for (int i = 0; i < StepStage<MODE>::PF; ++i) {
         const int idx = tid + i * kThreads;
         st.po[i] = (idx < (int)nn && j + 1 < a.j_end) ? a.ov[es * nn + idx] : 0.0;
         st.ps[i] = (idx < (int)nn && a.need_y) ? a.sm[es * nn + idx] : 0.0;
       }
     }
-    st.pl = tid < n ? a.lam[es * n + tid] : 0.0;
+    st.pl = (ph_t >= 0 && ph_t < n) ? a.lam[es * n + ph_t] : 0.0;
+    st.pf = tid < ncol ? Fb[(size_t)j * a.fcols + c0 + tid] : 0.0;
   };
-  auto commit_step = [&](const StepStage& st) {
-    if (STAGE) {
+  auto commit_step = [&](const StepStage<MODE>& st) {
+    if (STAGE && !ASYNC) {
 #pragma unroll
-      for (int i = 0; i < kPrefetch; ++i) {
+      for (int i = 0; i < StepStage<MODE>::PF; ++i) {
         const int idx = tid + i * kThreads;
         if (idx < (int)nn) {
           const int pr = idx / n, rr = idx - pr * n;
@@ -532,11 +913,12 @@ __device__ __forceinline__ void body_forward(const SweepArgs& a, int g, int b) {
         }
       }
     }
-    if (tid < n) {
+    if (ph_t >= 0 && ph_t < n) {
       const double2 h = phase(0.5 * st.pl, a.dt);
-      hh[tid] = h;
-      ph[tid] = c_mul(h, h);
+      hh[ph_t] = h;
+      ph[ph_t] = c_mul(h, h);
     }
+    if (tid < ncol) fv[tid] = st.pf;
   };
 
   if (a.j_begin == 0) {
@@ -572,30 +954,41 @@ __device__ __forceinline__ void body_forward(const SweepArgs& a, int g, int b) {
     }
   }
   {
-    StepStage st;
-    load_step(a.j_begin, st);
+    StepStage<MODE> st;
+    load_step(a.j_begin, st, 0);
+    if (ASYNC) wait_vm_all();
     commit_step(st);
   }
   __syncthreads();
 
-  const int nrb = (n + 3) / 4;
+  const int nrb = (n + kTileRows - 1) / kTileRows;
   for (int j = a.j_begin; j < a.j_end; ++j) {
     const size_t es = eb0 + (j - a.eig_j0);
     const size_t vs = vb0 + j;
-    StepStage nx;
-    if (j + 1 < a.j_end) load_step(j + 1, nx);
-    const double* S = STAGE ? Sb : a.sm + es * nn;
-    if (a.need_y && tid < n) {
-      const int p = tid;
-      double2 acc = make_double2(0.0, 0.0);
-      for (int r = 0; r < n; ++r) {
-        const double2 t = c_mul(hh[r], cur[r * w]);
-        const double sv = S[r * n + p];   // S symmetric
-        acc.x = fma(sv, t.x, acc.x);
-        acc.y = fma(sv, t.y, acc.y);
+    const int cb = ASYNC ? ((j - a.j_begin) & 1) : 0;
+    StepStage<MODE> nx;
+    if (j + 1 < a.j_end) load_step(j + 1, nx, cb ^ 1);
+    const double* S = STAGE ? Sb + cb * nn : a.sm + es * nn;
+    if (a.need_y) {
+      // four adjacent lanes per output row, each summing every fourth r
+      for (int t4 = tid; t4 < 4 * n; t4 += kThreads) {
+        const int p = t4 >> 2, part = t4 & 3;
+        double2 acc = make_double2(0.0, 0.0);
+        for (int r = part; r < n; r += 4) {
+          const double2 t = c_mul(hh[r], cur[r * w]);
+          const double sv = S[r * n + p];   // S symmetric
+          acc.x = fma(sv, t.x, acc.x);
+          acc.y = fma(sv, t.y, acc.y);
+        }
+        acc.x += __shfl_xor(acc.x, 1);
+        acc.y += __shfl_xor(acc.y, 1);
+        acc.x += __shfl_xor(acc.x, 2);
+        acc.y += __shfl_xor(acc.y, 2);
+        if (part == 0) {
+          const double2 hp = c_mul(hh[p], acc);
+          yv[p] = make_double2(a.dt * hp.y, -a.dt * hp.x);   // -i dt * hp
+        }
       }
-      const double2 hp = c_mul(hh[p], acc);
-      yv[p] = make_double2(a.dt * hp.y, -a.dt * hp.x);   // -i dt * hp
     }
     __syncthreads();
     if (g == 0 && a.need_y && tid < n) {
@@ -603,37 +996,44 @@ __device__ __forceinline__ void body_forward(const SweepArgs& a, int g, int b) {
       a.yt[vs * n + tid] = yv[tid];
       if (a.ah) a.ah[vs * n + tid] = cur[tid * w + 1];
     }
-    for (int idx = tid; idx < n * w; idx += kThreads) {
-      const int p = idx / w, col = idx - p * w;
-      double2 v = c_mul(ph[p], cur[idx]);
-      if (col > 0) {
-        const double fv = Fb[(size_t)j * a.fcols + c0 + col - 1];
-        v.x = fma(yv[p].x, fv, v.x);
-        v.y = fma(yv[p].y, fv, v.y);
+    {
+      ItemWalk it(tid, w);
+      for (int idx = tid; idx < n * w; idx += kThreads, it.next()) {
+        const int p = it.p, col = it.col;
+        double2 v = c_mul(ph[p], cur[idx]);
+        if (col > 0) {
+          const double f = fv[col - 1];
+          v.x = fma(yv[p].x, f, v.x);
+          v.y = fma(yv[p].y, f, v.y);
+        }
+        X[idx] = v;
       }
-      X[idx] = v;
     }
     __syncthreads();
     if (j + 1 < a.j_end) {
       const double* Og = a.ov + es * nn;
-      for (int t = tid; t < nrb * w; t += kThreads) {
-        const int rb = t / w, col = t - rb * w;
-        const int p0 = rb * 4;
-        double2 acc[4];
+      ItemWalk it(tid, w);
+      for (int t = tid; t < nrb * w; t += kThreads, it.next()) {
+        const int rb = it.p, col = it.col;
+        const int p0 = rb * kTileRows;
+        double2 acc[kTileRows];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) acc[i] = make_double2(0.0, 0.0);
+        for (int i = 0; i < kTileRows; ++i) acc[i] = make_double2(0.0, 0.0);
+#pragma unroll(MODE == kSweepRegs ? 1 : 4)
         for (int r = 0; r < n; ++r) {
           const double2 x = X[r * w + col];
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
+          for (int i = 0; i < kTileRows; ++i) {
             const int p = p0 + i;
-            const double o = p < n ? (STAGE ? Ob[r * n + p] : Og[(size_t)p * n + r]) : 0.0;
+            const double o = p < n ? (ASYNC ? Ob[cb * nn + (size_t)p * n + r]
+                                            : (STAGE ? Ob[r * n + p] : Og[(size_t)p * n + r]))
+                                   : 0.0;
             acc[i].x = fma(o, x.x, acc[i].x);
             acc[i].y = fma(o, x.y, acc[i].y);
           }
         }
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < kTileRows; ++i)
           if (p0 + i < n) cur[(p0 + i) * w + col] = acc[i];
       }
     } else {
@@ -649,14 +1049,17 @@ __device__ __forceinline__ void body_forward(const SweepArgs& a, int g, int b) {
     }
     __syncthreads();
     if (j + 1 < a.j_end) {
+      if (ASYNC) wait_vm_all();
       commit_step(nx);
       __syncthreads();
     }
   }
 }
 
-template <bool STAGE>
-__global__ __launch_bounds__(kThreads) void k_forward(SweepArgs a) { body_forward<STAGE>(a, blockIdx.x, blockIdx.y); }
+template <int MODE>
+__global__ __launch_bounds__(kThreads, MODE == kSweepRegs ? 2 : 3) void k_forward(SweepArgs a) {
+  body_forward<MODE>(a, blockIdx.x, blockIdx.y);
+}
 
 // Terminal conditions (eq. discretecost, eq. lambdasys with the rho weight, eq. musys):
 // r = a_J - beta in basis nt-1 (r^ = X_0 - V_{J-1}^T beta), |r|^2, lambda_J = rho r,
@@ -714,13 +1117,16 @@ __global__ __launch_bounds__(kThreads) void k_terminal(TermArgs a) { body_termin
 // Hessian (two-sweep form): xi_{J-1} = 0, K_j = Re(xi_j^H y_j),
 //   xi_{j-1} = U_j^H xi_j + z_j b_j^T.
 // HVP: mu_J = rho a'_J, mu_j = U_j^H mu_{j+1} + z_j u_j, e_j = Re(mu^H y_j) + Re(z_j^H a'_j).
+template <int MODE>
 struct BwdStage {
-  double po[kPrefetch], ps[kPrefetch];
+  static constexpr int PF = MODE == kSweepRegs ? kPrefetch : 1;
+  double po[PF], ps[PF];
   double pl;
   double2 py, pa;
+  double pf;   // forcing value of column tid + 1 (tid < columns of the group)
 };
 
-template <bool STAGE>
+template <int MODE>
 __device__ __forceinline__ void body_backward(const SweepArgs& a, int g, int b) {
   extern __shared__ double smem[];
   const int n = a.n, nt = a.nt, tid = threadIdx.x;
@@ -729,44 +1135,53 @@ __device__ __forceinline__ void body_backward(const SweepArgs& a, int g, int b) 
   const int ncol = max(0, min(a.pg, a.P - c0));
   const int w = 1 + ncol;
   const size_t nn = (size_t)n * n;
-  double* Ob = smem;                // O_{j-1} as stored: Ob[r*n + p] = O_{j-1}[r][p]
-  double* Sb = Ob + (STAGE ? nn : 0);
-  double2* cur = (double2*)(Sb + (STAGE ? nn : 0));
+  constexpr bool STAGE = MODE != kSweepGlobal;
+  constexpr bool ASYNC = MODE == kSweepAsync;
+  double* Ob = smem;                // O_{j-1} as stored: Ob[r*n + p] = O_{j-1}[r][p] (two buffers if ASYNC)
+  double* Sb = Ob + (STAGE ? nn : 0) * (ASYNC ? 2 : 1);
+  double2* cur = (double2*)(Sb + (STAGE ? nn : 0) * (ASYNC ? 2 : 1));
   double2* X = cur + n * w;
   double2* hh = X + n * w;
   double2* ph = hh + n;
   double2* zv = ph + n;
   double2* yv = zv + n;
   double2* av = yv + n;
+  double* fv = (double*)(av + n);   // [pg] forcing values of the step
   const double* Fb = a.F + (size_t)b * a.f_bstride;
   const size_t vb0 = (size_t)b * nt;
   const size_t eb0 = (size_t)b * a.eig_stride;
+  const int ph_t = tid - (kThreads - 128);   // waves 2 and 3 evaluate the step's phases
 
   // O_{jj-1} for step jj >= 1: inside the range from the eigen-data, at the range start from o_in
   auto o_prev = [&](int jj) -> const double* {
     if (jj - 1 >= a.j_begin) return a.ov + (eb0 + (jj - 1 - a.eig_j0)) * nn;
     return a.o_in ? a.o_in + (size_t)b * nn : nullptr;
   };
-  auto load_step = [&](int j, BwdStage& st) {
+  auto load_step = [&](int j, BwdStage<MODE>& st, int buf) {
     const size_t es = eb0 + (j - a.eig_j0);
     const size_t vs = vb0 + j;
-    if (STAGE) {
+    if (ASYNC) {
+      const double* Op = j >= 1 ? o_prev(j) : nullptr;
+      if (Op) lds_copy_async(Ob + buf * nn, Op, (int)nn);
+      lds_copy_async(Sb + buf * nn, a.sm + es * nn, (int)nn);
+    } else if (STAGE) {
       const double* Op = j >= 1 ? o_prev(j) : nullptr;
 #pragma unroll
-      for (int i = 0; i < kPrefetch; ++i) {
+      for (int i = 0; i < BwdStage<MODE>::PF; ++i) {
         const int idx = tid + i * kThreads;
         st.po[i] = (idx < (int)nn && Op) ? Op[idx] : 0.0;
         st.ps[i] = idx < (int)nn ? a.sm[es * nn + idx] : 0.0;
       }
     }
-    st.pl = tid < n ? a.lam[es * n + tid] : 0.0;
+    st.pl = (ph_t >= 0 && ph_t < n) ? a.lam[es * n + ph_t] : 0.0;
     st.py = tid < n ? a.yt[vs * n + tid] : make_double2(0.0, 0.0);
     st.pa = (tid < n && a.hvp) ? a.ah[vs * n + tid] : make_double2(0.0, 0.0);
+    st.pf = tid < ncol ? Fb[(size_t)j * a.fcols + c0 + tid] : 0.0;
   };
-  auto commit_step = [&](const BwdStage& st) {
-    if (STAGE) {
+  auto commit_step = [&](const BwdStage<MODE>& st) {
+    if (STAGE && !ASYNC) {
 #pragma unroll
-      for (int i = 0; i < kPrefetch; ++i) {
+      for (int i = 0; i < BwdStage<MODE>::PF; ++i) {
         const int idx = tid + i * kThreads;
         if (idx < (int)nn) {
           Ob[idx] = st.po[i];
@@ -774,13 +1189,16 @@ __device__ __forceinline__ void body_backward(const SweepArgs& a, int g, int b) 
         }
       }
     }
-    if (tid < n) {
+    if (ph_t >= 0 && ph_t < n) {
       const double2 h = c_conj(phase(0.5 * st.pl, a.dt));   // conj(h)
-      hh[tid] = h;
-      ph[tid] = c_mul(h, h);                                  // conj(phi)
+      hh[ph_t] = h;
+      ph[ph_t] = c_mul(h, h);                                 // conj(phi)
+    }
+    if (tid < n) {
       yv[tid] = st.py;
       av[tid] = st.pa;
     }
+    if (tid < ncol) fv[tid] = st.pf;
   };
 
   for (int idx = tid; idx < n * w; idx += kThreads) {
@@ -791,30 +1209,39 @@ __device__ __forceinline__ void body_backward(const SweepArgs& a, int g, int b) 
     cur[idx] = v;
   }
   {
-    BwdStage st;
-    load_step(a.j_end - 1, st);
+    BwdStage<MODE> st;
+    load_step(a.j_end - 1, st, 0);
+    if (ASYNC) wait_vm_all();
     commit_step(st);
   }
   __syncthreads();
 
-  const int nrb = (n + 3) / 4;
+  const int nrb = (n + kTileRows - 1) / kTileRows;
   for (int j = a.j_end - 1; j >= a.j_begin; --j) {
     const size_t es = eb0 + (j - a.eig_j0);
     const size_t vs = vb0 + j;
-    BwdStage nx;
-    if (j - 1 >= a.j_begin) load_step(j - 1, nx);
-    const double* S = STAGE ? Sb : a.sm + es * nn;
-    if (tid < n) {
-      const int p = tid;
+    const int cb = ASYNC ? ((a.j_end - 1 - j) & 1) : 0;
+    BwdStage<MODE> nx;
+    if (j - 1 >= a.j_begin) load_step(j - 1, nx, cb ^ 1);
+    const double* S = STAGE ? Sb + cb * nn : a.sm + es * nn;
+    for (int t4 = tid; t4 < 4 * n; t4 += kThreads) {
+      // four adjacent lanes per output row, each summing every fourth r
+      const int p = t4 >> 2, part = t4 & 3;
       double2 acc = make_double2(0.0, 0.0);
-      for (int r = 0; r < n; ++r) {
+      for (int r = part; r < n; r += 4) {
         const double2 t = c_mul(hh[r], cur[r * w]);
         const double sv = S[r * n + p];
         acc.x = fma(sv, t.x, acc.x);
         acc.y = fma(sv, t.y, acc.y);
       }
-      const double2 hp = c_mul(hh[p], acc);
-      zv[p] = make_double2(-a.dt * hp.y, a.dt * hp.x);   // i dt * hp
+      acc.x += __shfl_xor(acc.x, 1);
+      acc.y += __shfl_xor(acc.y, 1);
+      acc.x += __shfl_xor(acc.x, 2);
+      acc.y += __shfl_xor(acc.y, 2);
+      if (part == 0) {
+        const double2 hp = c_mul(hh[p], acc);
+        zv[p] = make_double2(-a.dt * hp.y, a.dt * hp.x);   // i dt * hp
+      }
     }
     __syncthreads();
     // per-step reductions (wave 0) and K_j (one thread per column)
@@ -839,6 +1266,7 @@ __device__ __forceinline__ void body_backward(const SweepArgs& a, int g, int b) 
     if (!a.hvp && a.K && tid >= 64 && tid - 64 < ncol) {
       const int col = tid - 64;
       double acc = 0.0;
+#pragma unroll(MODE == kSweepRegs ? 1 : 4)
       for (int p = 0; p < n; ++p) {
         const double2 xi = cur[p * w + 1 + col];
         acc += xi.x * yv[p].x + xi.y * yv[p].y;
@@ -846,40 +1274,46 @@ __device__ __forceinline__ void body_backward(const SweepArgs& a, int g, int b) 
       a.K[vs * a.P + c0 + col] = acc;
     }
     if (j >= 1) {
-      for (int idx = tid; idx < n * w; idx += kThreads) {
-        const int p = idx / w, col = idx - p * w;
-        double2 v = c_mul(ph[p], cur[idx]);
-        if (col > 0) {
-          const double fv = Fb[(size_t)j * a.fcols + c0 + col - 1];
-          v.x = fma(zv[p].x, fv, v.x);
-          v.y = fma(zv[p].y, fv, v.y);
+      {
+        ItemWalk it(tid, w);
+        for (int idx = tid; idx < n * w; idx += kThreads, it.next()) {
+          const int p = it.p, col = it.col;
+          double2 v = c_mul(ph[p], cur[idx]);
+          if (col > 0) {
+            const double f = fv[col - 1];
+            v.x = fma(zv[p].x, f, v.x);
+            v.y = fma(zv[p].y, f, v.y);
+          }
+          X[idx] = v;
         }
-        X[idx] = v;
       }
       __syncthreads();
       const double* Og = o_prev(j);   // apply its transpose
-      for (int t = tid; t < nrb * w; t += kThreads) {
-        const int rb = t / w, col = t - rb * w;
-        const int p0 = rb * 4;
-        double2 acc[4];
+      ItemWalk it(tid, w);
+      for (int t = tid; t < nrb * w; t += kThreads, it.next()) {
+        const int rb = it.p, col = it.col;
+        const int p0 = rb * kTileRows;
+        double2 acc[kTileRows];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) acc[i] = make_double2(0.0, 0.0);
+        for (int i = 0; i < kTileRows; ++i) acc[i] = make_double2(0.0, 0.0);
+#pragma unroll(MODE == kSweepRegs ? 1 : 4)
         for (int r = 0; r < n; ++r) {
           const double2 x = X[r * w + col];
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
+          for (int i = 0; i < kTileRows; ++i) {
             const int p = p0 + i;
-            const double o = p < n ? (STAGE ? Ob[r * n + p] : Og[(size_t)r * n + p]) : 0.0;
+            const double o = p < n ? (STAGE ? Ob[cb * nn + (size_t)r * n + p] : Og[(size_t)r * n + p]) : 0.0;
             acc[i].x = fma(o, x.x, acc[i].x);
             acc[i].y = fma(o, x.y, acc[i].y);
           }
         }
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < kTileRows; ++i)
           if (p0 + i < n) cur[(p0 + i) * w + col] = acc[i];
       }
       __syncthreads();
       if (j > a.j_begin) {
+        if (ASYNC) wait_vm_all();
         commit_step(nx);
       } else if (a.bout) {
         // state leaving the range, in basis j_begin - 1
@@ -893,8 +1327,10 @@ __device__ __forceinline__ void body_backward(const SweepArgs& a, int g, int b) 
   }
 }
 
-template <bool STAGE>
-__global__ __launch_bounds__(kThreads) void k_backward(SweepArgs a) { body_backward<STAGE>(a, blockIdx.x, blockIdx.y); }
+template <int MODE>
+__global__ __launch_bounds__(kThreads, MODE == kSweepRegs ? 2 : 3) void k_backward(SweepArgs a) {
+  body_backward<MODE>(a, blockIdx.x, blockIdx.y);
+}
 
 // ---------------------------------------------------------------- U'' contraction
 
@@ -1347,15 +1783,17 @@ static size_t eig_lds_bytes(int np, bool lds_mats) {
 static bool eig_fits_lds(int np) { return eig_lds_bytes(np, true) <= 160 * 1024; }
 
 static bool sweep_stage(int n) { return n * n <= kPrefetch * kThreads; }
+static bool sweep_small(int n) { return n * n <= kPrefetchSmall * kThreads; }   // async LDS double buffer
 
 static size_t sweep_lds_bytes(int n, int pg) {
-  const size_t mats = sweep_stage(n) ? (size_t)2 * n * n * sizeof(double) : 0;
-  return mats + ((size_t)2 * n * (1 + pg) + 5 * n) * sizeof(double2);
+  const size_t mats = (sweep_small(n) ? 4 : (sweep_stage(n) ? 2 : 0)) * (size_t)n * n * sizeof(double);
+  return mats + ((size_t)2 * n * (1 + pg) + 5 * n) * sizeof(double2) + (size_t)kMaxPg * sizeof(double);
 }
 
 hipError_t configure_kernels() {
-  const void* fns[] = {(const void*)k_eig_chunk, (const void*)k_eig_wave<36>, (const void*)k_sym_eig, (const void*)k_forward<true>, (const void*)k_forward<false>,
-                       (const void*)k_backward<true>, (const void*)k_backward<false>};
+  const void* fns[] = {(const void*)k_eig_chunk, (const void*)k_eig_wg<36>, (const void*)k_eig_wg<64>, (const void*)k_sym_eig, (const void*)k_forward<kSweepRegs>, (const void*)k_forward<kSweepAsync>,
+                       (const void*)k_forward<kSweepGlobal>, (const void*)k_backward<kSweepRegs>,
+                       (const void*)k_backward<kSweepAsync>, (const void*)k_backward<kSweepGlobal>};
   for (const void* f : fns) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
@@ -1365,6 +1803,7 @@ hipError_t configure_kernels() {
 
 size_t eig_scratch_doubles(int n, int nb, int nchunks) {
   const int np = pad_even(n);
+  if (np == 64) return (size_t)nb * nchunks * np * np;   // workgroup kernel: V_{j-1} per chunk
   if (eig_fits_lds(np)) return 0;
   return (size_t)nb * nchunks * 4 * np * np;
 }
@@ -1437,10 +1876,13 @@ EigArgs eig_args(const SysDev& sy, const BasisDev& bs, const Work& w, bool store
 
 size_t eig_launch_lds(int np) {
   switch (np) {
+    case 36:
+      return eig_wg_lds_doubles<36>() * sizeof(double);
+    case 64:
+      return eig_wg_lds_doubles<64>() * sizeof(double);
     case 4:
     case 8:
     case 16:
-    case 36:
       return ((size_t)3 * np * np + 2 * np + (np + 1) / 2) * sizeof(double);
     default:
       return eig_lds_bytes(np, eig_fits_lds(np));
@@ -1450,6 +1892,14 @@ size_t eig_launch_lds(int np) {
 hipError_t launch_eig(const SysDev& sy, const BasisDev& bs, Work& w, bool store_derivs, double tol_rel,
                       int max_sweeps, hipStream_t stream) {
   const EigArgs a = eig_args(sy, bs, w, store_derivs, tol_rel, max_sweeps);
+  if (w.np == 36) {
+    hipLaunchKernelGGL(k_eig_wg<36>, dim3(w.nchunks, w.nb), dim3(EigWgShape<36>::TPB), eig_launch_lds(36), stream, a);
+    return hipGetLastError();
+  }
+  if (w.np == 64) {
+    hipLaunchKernelGGL(k_eig_wg<64>, dim3(w.nchunks, w.nb), dim3(EigWgShape<64>::TPB), eig_launch_lds(64), stream, a);
+    return hipGetLastError();
+  }
   switch (w.np) {
 #define QOC_EIG_WAVE(NPV)                                                                               \
   case NPV: {                                                                                          \
@@ -1460,7 +1910,6 @@ hipError_t launch_eig(const SysDev& sy, const BasisDev& bs, Work& w, bool store_
     QOC_EIG_WAVE(4)
     QOC_EIG_WAVE(8)
     QOC_EIG_WAVE(16)
-    QOC_EIG_WAVE(36)
 #undef QOC_EIG_WAVE
     default:
       break;
@@ -1541,10 +1990,12 @@ SweepArgs sweep_args(const SysDev& sy, const BasisDev& bs, const Work& w, Mode m
 
 hipError_t launch_forward_args(const SweepArgs& a, int nb, hipStream_t stream) {
   const size_t lds = sweep_lds_bytes(a.n, a.P > 0 ? a.pg : 0);
-  if (sweep_stage(a.n))
-    hipLaunchKernelGGL(k_forward<true>, dim3(a.ngroups, nb), dim3(kThreads), lds, stream, a);
+  if (sweep_small(a.n))
+    hipLaunchKernelGGL(k_forward<kSweepAsync>, dim3(a.ngroups, nb), dim3(kThreads), lds, stream, a);
+  else if (sweep_stage(a.n))
+    hipLaunchKernelGGL(k_forward<kSweepRegs>, dim3(a.ngroups, nb), dim3(kThreads), lds, stream, a);
   else
-    hipLaunchKernelGGL(k_forward<false>, dim3(a.ngroups, nb), dim3(kThreads), lds, stream, a);
+    hipLaunchKernelGGL(k_forward<kSweepGlobal>, dim3(a.ngroups, nb), dim3(kThreads), lds, stream, a);
   return hipGetLastError();
 }
 
@@ -1579,10 +2030,12 @@ hipError_t launch_terminal(const SysDev& sy, const BasisDev& bs, Work& w, Mode m
 
 hipError_t launch_backward_args(const SweepArgs& a, int nb, hipStream_t stream) {
   const size_t lds = sweep_lds_bytes(a.n, a.P > 0 ? a.pg : 0);
-  if (sweep_stage(a.n))
-    hipLaunchKernelGGL(k_backward<true>, dim3(a.ngroups, nb), dim3(kThreads), lds, stream, a);
+  if (sweep_small(a.n))
+    hipLaunchKernelGGL(k_backward<kSweepAsync>, dim3(a.ngroups, nb), dim3(kThreads), lds, stream, a);
+  else if (sweep_stage(a.n))
+    hipLaunchKernelGGL(k_backward<kSweepRegs>, dim3(a.ngroups, nb), dim3(kThreads), lds, stream, a);
   else
-    hipLaunchKernelGGL(k_backward<false>, dim3(a.ngroups, nb), dim3(kThreads), lds, stream, a);
+    hipLaunchKernelGGL(k_backward<kSweepGlobal>, dim3(a.ngroups, nb), dim3(kThreads), lds, stream, a);
   return hipGetLastError();
 }
 
@@ -1703,14 +2156,17 @@ QOC_MULTI_KERNEL(km_controls, kThreads, 1, CtlArgs, body_controls)
 QOC_MULTI_KERNEL(km_eig_wave4, 64, 2, EigArgs, body_eig_wave<4>)
 QOC_MULTI_KERNEL(km_eig_wave8, 64, 2, EigArgs, body_eig_wave<8>)
 QOC_MULTI_KERNEL(km_eig_wave16, 64, 2, EigArgs, body_eig_wave<16>)
-QOC_MULTI_KERNEL(km_eig_wave36, 64, 2, EigArgs, body_eig_wave<36>)
+QOC_MULTI_KERNEL(km_eig_wg36, kThreads, 4, EigArgs, body_eig_wg<36>)
+QOC_MULTI_KERNEL(km_eig_wg64, 512, 4, EigArgs, body_eig_wg<64>)
 QOC_MULTI_KERNEL(km_eig_chunk, kThreads, 1, EigArgs, body_eig_chunk)
 QOC_MULTI_KERNEL(km_boundary, kThreads, 1, BndArgs, body_boundary)
-QOC_MULTI_KERNEL(km_forward_staged, kThreads, 1, SweepArgs, body_forward<true>)
-QOC_MULTI_KERNEL(km_forward_global, kThreads, 1, SweepArgs, body_forward<false>)
+QOC_MULTI_KERNEL(km_forward_staged, kThreads, 2, SweepArgs, body_forward<kSweepRegs>)
+QOC_MULTI_KERNEL(km_forward_small, kThreads, 3, SweepArgs, body_forward<kSweepAsync>)
+QOC_MULTI_KERNEL(km_forward_global, kThreads, 3, SweepArgs, body_forward<kSweepGlobal>)
 QOC_MULTI_KERNEL(km_terminal, kThreads, 1, TermArgs, body_terminal)
-QOC_MULTI_KERNEL(km_backward_staged, kThreads, 1, SweepArgs, body_backward<true>)
-QOC_MULTI_KERNEL(km_backward_global, kThreads, 1, SweepArgs, body_backward<false>)
+QOC_MULTI_KERNEL(km_backward_staged, kThreads, 2, SweepArgs, body_backward<kSweepRegs>)
+QOC_MULTI_KERNEL(km_backward_small, kThreads, 3, SweepArgs, body_backward<kSweepAsync>)
+QOC_MULTI_KERNEL(km_backward_global, kThreads, 3, SweepArgs, body_backward<kSweepGlobal>)
 QOC_MULTI_KERNEL(km_sterm, kThreads, 1, StermArgs, body_sterm)
 QOC_MULTI_KERNEL(km_assemble, kThreads, 1, AsmArgs, body_assemble)
 #undef QOC_MULTI_KERNEL
@@ -1726,13 +2182,16 @@ static const void* multi_fn(MultiKind k) {
     case MultiKind::EigWave4: return (const void*)km_eig_wave4;
     case MultiKind::EigWave8: return (const void*)km_eig_wave8;
     case MultiKind::EigWave16: return (const void*)km_eig_wave16;
-    case MultiKind::EigWave36: return (const void*)km_eig_wave36;
+    case MultiKind::EigWg36: return (const void*)km_eig_wg36;
+    case MultiKind::EigWg64: return (const void*)km_eig_wg64;
     case MultiKind::EigChunk: return (const void*)km_eig_chunk;
     case MultiKind::Boundary: return (const void*)km_boundary;
     case MultiKind::ForwardStaged: return (const void*)km_forward_staged;
+    case MultiKind::ForwardSmall: return (const void*)km_forward_small;
     case MultiKind::ForwardGlobal: return (const void*)km_forward_global;
     case MultiKind::Terminal: return (const void*)km_terminal;
     case MultiKind::BackwardStaged: return (const void*)km_backward_staged;
+    case MultiKind::BackwardSmall: return (const void*)km_backward_small;
     case MultiKind::BackwardGlobal: return (const void*)km_backward_global;
     case MultiKind::Sterm: return (const void*)km_sterm;
     case MultiKind::Assemble: return (const void*)km_assemble;
@@ -1745,8 +2204,9 @@ int multi_threads(MultiKind k) {
     case MultiKind::EigWave4:
     case MultiKind::EigWave8:
     case MultiKind::EigWave16:
-    case MultiKind::EigWave36:
       return 64;
+    case MultiKind::EigWg64:
+      return EigWgShape<64>::TPB;
     default:
       return kThreads;
   }
@@ -1757,13 +2217,19 @@ MultiKind eig_kind(int np) {
     case 4: return MultiKind::EigWave4;
     case 8: return MultiKind::EigWave8;
     case 16: return MultiKind::EigWave16;
-    case 36: return MultiKind::EigWave36;
+    case 36: return MultiKind::EigWg36;
+    case 64: return MultiKind::EigWg64;
     default: return MultiKind::EigChunk;
   }
 }
 
-MultiKind forward_kind(int n) { return sweep_stage(n) ? MultiKind::ForwardStaged : MultiKind::ForwardGlobal; }
-MultiKind backward_kind(int n) { return sweep_stage(n) ? MultiKind::BackwardStaged : MultiKind::BackwardGlobal; }
+MultiKind forward_kind(int n) {
+  return sweep_small(n) ? MultiKind::ForwardSmall : (sweep_stage(n) ? MultiKind::ForwardStaged : MultiKind::ForwardGlobal);
+}
+MultiKind backward_kind(int n) {
+  return sweep_small(n) ? MultiKind::BackwardSmall
+                        : (sweep_stage(n) ? MultiKind::BackwardStaged : MultiKind::BackwardGlobal);
+}
 size_t sweep_launch_lds(int n, int pg) { return sweep_lds_bytes(n, pg); }
 
 hipError_t configure_multi_kernels() {
@@ -1799,13 +2265,16 @@ hipError_t launch_multi(MultiKind k, const void* d_args, const Item* d_items, in
     QOC_MULTI_CASE(EigWave4, km_eig_wave4, EigArgs)
     QOC_MULTI_CASE(EigWave8, km_eig_wave8, EigArgs)
     QOC_MULTI_CASE(EigWave16, km_eig_wave16, EigArgs)
-    QOC_MULTI_CASE(EigWave36, km_eig_wave36, EigArgs)
+    QOC_MULTI_CASE(EigWg36, km_eig_wg36, EigArgs)
+    QOC_MULTI_CASE(EigWg64, km_eig_wg64, EigArgs)
     QOC_MULTI_CASE(EigChunk, km_eig_chunk, EigArgs)
     QOC_MULTI_CASE(Boundary, km_boundary, BndArgs)
     QOC_MULTI_CASE(ForwardStaged, km_forward_staged, SweepArgs)
+    QOC_MULTI_CASE(ForwardSmall, km_forward_small, SweepArgs)
     QOC_MULTI_CASE(ForwardGlobal, km_forward_global, SweepArgs)
     QOC_MULTI_CASE(Terminal, km_terminal, TermArgs)
     QOC_MULTI_CASE(BackwardStaged, km_backward_staged, SweepArgs)
+    QOC_MULTI_CASE(BackwardSmall, km_backward_small, SweepArgs)
     QOC_MULTI_CASE(BackwardGlobal, km_backward_global, SweepArgs)
     QOC_MULTI_CASE(Sterm, km_sterm, StermArgs)
     QOC_MULTI_CASE(Assemble, km_assemble, AsmArgs)
