@@ -27,13 +27,54 @@ __device__ __forceinline__ double2 phase(double x, double dt) {
   return make_double2(c, -s);
 }
 
-// sin(u)/u, accurate for all u (no cancellation for u != 0; series near 0).
+// sin(u)/u, accurate for all u.  |u| < 1/4: the even Taylor series through u^12 (the first
+// omitted term is below 3e-21); otherwise sin(u)/u.
 __device__ __forceinline__ double sinc(double u) {
-  if (fabs(u) < 1e-3) {
+  if (fabs(u) < 0.25) {
     const double u2 = u * u;
-    return 1.0 - u2 * (1.0 / 6.0) + u2 * u2 * (1.0 / 120.0);
+    double r = 1.0 / 6227020800.0;              // 1/13!
+    r = fma(r, -u2, 1.0 / 39916800.0);          // 1/11!
+    r = fma(r, -u2, 1.0 / 362880.0);            // 1/9!
+    r = fma(r, -u2, 1.0 / 5040.0);              // 1/7!
+    r = fma(r, -u2, 1.0 / 120.0);               // 1/5!
+    r = fma(r, -u2, 1.0 / 6.0);                 // 1/3!
+    return fma(r, -u2, 1.0);
   }
   return sin(u) / u;
+}
+
+// 1/sqrt(x) and 1/x for positive normal x from the hardware estimates refined by two Newton
+// steps (to within about one ulp).
+__device__ __forceinline__ double rsqrt_refined(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  y = fma(y, fma(-0.5 * x * y, y, 0.5), y);
+  y = fma(y, fma(-0.5 * x * y, y, 0.5), y);
+  return y;
+}
+__device__ __forceinline__ double rcp_refined(double x) {
+  double q = __builtin_amdgcn_rcp(x);
+  q = fma(q, fma(-x, q, 1.0), q);
+  q = fma(q, fma(-x, q, 1.0), q);
+  return q;
+}
+
+// Jacobi rotation (c, s) annihilating the off-diagonal of [[app, apq], [apq, aqq]] with the
+// smaller angle: t = sign(d) e / (|d| + sqrt(d^2 + e^2)), d = aqq - app, e = 2 apq (the root of
+// t^2 + 2 (d/e) t - 1 = 0 of modulus <= 1), c = 1/sqrt(1 + t^2), s = t c.  c is accurate to
+// about one ulp, so c^2 + s^2 = 1 to working accuracy; t only steers how completely apq is
+// removed.  |apq| <= 1e-150 is left alone (far below any tolerance for O(1) matrices).
+__device__ __forceinline__ void jacobi_rotation(double app, double aqq, double apq, double& c, double& s) {
+  c = 1.0;
+  s = 0.0;
+  if (fabs(apq) > 1e-150) {
+    const double d = aqq - app, e = 2.0 * apq;
+    const double x = fma(d, d, e * e);
+    const double h = x * rsqrt_refined(x);   // sqrt(d^2 + e^2)
+    const double t = (d >= 0.0 ? e : -e) * rcp_refined(fabs(d) + h);
+    const double r = rsqrt_refined(fma(t, t, 1.0));
+    c = r;
+    s = t * r;
+  }
 }
 
 // First divided difference phi[x, y] of phi(t) = exp(-i dt t):
@@ -187,20 +228,8 @@ __device__ bool jacobi_eig(double* A, double* V, int np, double tol_abs, int max
       if (tid < half) {
         int p, q;
         rr_pair(r, tid, np, p, q);
-        const double app = A[p * np + p], aqq = A[q * np + q], apq = A[p * np + q];
-        double c = 1.0, s = 0.0;
-        if (apq != 0.0) {
-          // symmetric Schur decomposition of [[app, apq], [apq, aqq]]
-          const double tau = (aqq - app) / (2.0 * apq);
-          double t;
-          if (fabs(tau) > 1e150) {
-            t = 0.5 / tau;
-          } else {
-            t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-          }
-          c = 1.0 / sqrt(1.0 + t * t);
-          s = t * c;
-        }
+        double c, s;
+        jacobi_rotation(A[p * np + p], A[q * np + q], A[p * np + q], c, s);
         rot[2 * tid] = c;
         rot[2 * tid + 1] = s;
         prs[2 * tid] = p;

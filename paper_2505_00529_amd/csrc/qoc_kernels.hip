@@ -320,16 +320,8 @@ __device__ __forceinline__ void body_eig_wave(const EigArgs& a, int c, int b) {
       for (int r = 0; r < NP - 1; ++r) {
         if (lane < H) {
           const int p = circ_player(2 * lane, r, NP), q = circ_player(2 * lane + 1, r, NP);
-          const double app = Bm[p * NP + p], aqq = Bm[q * NP + q], apq = Bm[p * NP + q];
-          double cc = 1.0, ss = 0.0;
-          if (apq != 0.0) {
-            const double tau = (aqq - app) / (2.0 * apq);
-            double t;
-            if (fabs(tau) > 1e150) t = 0.5 / tau;
-            else t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-            cc = 1.0 / sqrt(1.0 + t * t);
-            ss = t * cc;
-          }
+          double cc, ss;
+          jacobi_rotation(Bm[p * NP + p], Bm[q * NP + q], Bm[p * NP + q], cc, ss);
           rot[2 * lane] = cc;
           rot[2 * lane + 1] = ss;
           prs[2 * lane] = p;
@@ -623,17 +615,8 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
         if (tid < H) {
           int p, q;
           rr_pair(r, tid, NP, p, q);
-          const double app = A[p * NP + p], aqq = A[q * NP + q], apq = A[p * NP + q];
-          double cc = 1.0, ss = 0.0;
-          if (apq != 0.0) {
-            // tan of the rotation angle: t = sign(d) e / (|d| + sqrt(d^2 + e^2)), d = aqq - app,
-            // e = 2 apq (the smaller root of t^2 + 2 (d/e) t - 1 = 0)
-            const double d = aqq - app, e = 2.0 * apq;
-            const double den = fabs(d) + sqrt(fma(d, d, e * e));
-            const double t = den > 0.0 ? (d >= 0.0 ? e : -e) / den : 1.0;
-            cc = 1.0 / sqrt(fma(t, t, 1.0));
-            ss = t * cc;
-          }
+          double cc, ss;
+          jacobi_rotation(A[p * NP + p], A[q * NP + q], A[p * NP + q], cc, ss);
           rot[tid] = make_double2(cc, ss);
           prs[tid] = make_int2(p, q);
         }
@@ -1814,10 +1797,12 @@ int eig_chunk_len(int seg_len, int nb) {
   return std::max(8, (seg_len + target - 1) / target);
 }
 
+// Tangent columns per sweep workgroup: wider groups amortise each step's fixed chain (state
+// column, phases, forcing, barriers) over more columns; narrower groups give more workgroups
+// when there are few thetas.  16 columns once there are enough thetas to fill the device.
 int choose_pg(int P, int nb) {
-  (void)nb;
   if (P <= 0) return 1;
-  int pg = 8;
+  int pg = nb >= 128 ? 16 : 8;
   if (pg > P) pg = P;
   return pg;
 }
