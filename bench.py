@@ -39,6 +39,36 @@ def alg_flops_per_step(kernel: str, n: int, p: int) -> float:
     }.get(kernel, 0.0)
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_molecule_b256.json")
+
+
+def kernel_source_digest() -> str:
+    """SHA-256 over the library's kernel sources (ties a counter measurement to the code)."""
+    import hashlib
+
+    csrc = os.path.join(ROOT, "paper_2505_00529_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".h")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str, batch: int):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE / WRITE_SIZE counter runs,
+    each scaled by the factor a reference copy of known size gave; None when the kernel sources
+    have changed since, or the measurement was for another kernel or batch."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel") != kernel or t.get("batch") != batch or t.get("source_sha256") != kernel_source_digest():
+        return None
+    return 1024.0 * (t["fetch_kib_per_dispatch"] * t["fetch_scale"] + t["write_kib_per_dispatch"] * t["write_scale"])
+
+
 def log(msg: str) -> None:
     sys.stderr.write(msg + "\n")
     sys.stderr.flush()
@@ -146,7 +176,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after timing, run one device-to-device copy of this many MiB (a reference "
-                         "dispatch of known traffic for HBM byte counters)")
+                         "dispatch of known traffic for HBM byte counters; use more than the last-level "
+                         "cache so that its source is read from HBM)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -237,7 +268,7 @@ def main() -> int:
             "peak": peak,
             "unit": "TFLOP/s",
             "frac": achieved / peak,
-            "traffic": None,
+            "traffic": measured_traffic(dom, B),
         },
         "kernel_ms": {k: round(v[0], 4) for k, v in ktimes.items()},
         "jacobi_sweeps_per_step": eig_sweeps / max(eig_steps, 1),

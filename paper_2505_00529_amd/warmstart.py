@@ -134,7 +134,8 @@ class WarmStart:
         return dict(theta=th, cost=c, iters=its, converged=conv, fallback=fb, seconds=time.perf_counter() - t0)
 
 
-def solve_plain(problem: "qoc.Problem", targets, gtol: float = 1e-8, max_iter: int = 10000, chunk: int = 256):
+def solve_plain(problem: "qoc.Problem", targets, gtol: float = 1e-8, max_iter: int = 10000, chunk: int = 256,
+                verbose: bool = False):
     """Zero-start solves in lockstep chunks; returns (theta, cost, iters, converged, seconds)."""
     targets = np.asarray(targets)
     count = targets.shape[0]
@@ -147,6 +148,8 @@ def solve_plain(problem: "qoc.Problem", targets, gtol: float = 1e-8, max_iter: i
         e = min(count, s + chunk)
         th[s:e], c[s:e], its[s:e], conv[s:e] = problem.tr_solve_many(np.zeros((e - s, problem.P)), targets[s:e],
                                                                       gtol=gtol, max_iter=max_iter)
+        if verbose:
+            print(f"[warmstart]   solved {e}/{count} ({time.perf_counter() - t0:.1f} s)", flush=True)
     return th, c, its, conv, time.perf_counter() - t0
 
 
@@ -162,23 +165,33 @@ def main(argv: Optional[list] = None):
 
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--workload", default="warm")
+    ap.add_argument("--n", type=int, default=None, help="override the system dimension of the workload")
     ap.add_argument("--train", type=int, default=2000)
     ap.add_argument("--test", type=int, default=200)
-    ap.add_argument("--epochs", type=int, default=300)
+    ap.add_argument("--epochs", type=int, default=400)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--batch", type=int, default=128)
     ap.add_argument("--gtol", type=float, default=1e-8)
     ap.add_argument("--max-iter", type=int, default=1000)
     ap.add_argument("--save", default=None, help="write the training set and trained parameters (.npz)")
+    ap.add_argument("--load", default=None, help="training set from an earlier --save instead of solving")
     args = ap.parse_args(argv)
 
-    w = inputs.make_workload(args.workload)
+    w = inputs.make_workload(args.workload, n=args.n)
     p = qoc.problem_from_workload(w)
     tr_t = inputs.warm_targets(w.system.n, args.train, spawn=0)
     te_t = inputs.warm_targets(w.system.n, args.test, spawn=1)
-    print(f"[warmstart] {args.workload}: n={w.system.n} nt={w.nt} P={w.p}; solving {args.train} training targets",
-          flush=True)
-    tr_th, tr_c, tr_it, tr_conv, tr_s = solve_plain(p, tr_t, args.gtol, args.max_iter)
+    if args.load:
+        d = np.load(args.load)
+        tr_t, tr_th, tr_c, tr_it = d["train_targets"], d["train_thetas"], d["train_costs"], d["train_iters"]
+        tr_conv = d["train_converged"].astype(bool) if "train_converged" in d else np.ones(len(tr_t), bool)
+        tr_s = float(d["train_seconds"]) if "train_seconds" in d else 0.0
+        args.train = len(tr_t)
+        print(f"[warmstart] loaded {args.train} training pairs from {args.load}", flush=True)
+    else:
+        print(f"[warmstart] {args.workload}: n={w.system.n} nt={w.nt} P={w.p}; solving {args.train} training "
+              "targets", flush=True)
+        tr_th, tr_c, tr_it, tr_conv, tr_s = solve_plain(p, tr_t, args.gtol, args.max_iter, verbose=True)
     print(f"[warmstart] training set: {tr_s:.1f} s, converged {int(tr_conv.sum())}/{args.train}, "
           f"mean iters {tr_it.mean():.1f}", flush=True)
     ws = WarmStart(p)
@@ -209,7 +222,8 @@ def main(argv: Optional[list] = None):
     print(json.dumps(out), flush=True)
     if args.save:
         np.savez(args.save, train_targets=tr_t, train_thetas=tr_th, train_costs=tr_c, train_iters=tr_it,
-                 params=ws.mlp.get_params(), mean=ws.mean, scale=ws.scale)
+                 train_converged=tr_conv, train_seconds=tr_s, params=ws.mlp.get_params(), mean=ws.mean,
+                 scale=ws.scale)
     return out
 
 
