@@ -170,10 +170,11 @@ def main() -> int:
     ap.add_argument("--count", type=int, default=256, help="problems in the batched workload")
     ap.add_argument("--unbatched-steps", type=int, default=1)
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--batch", type=int, default=256, help="independent theta per step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tr-solves", type=int, default=32, help="plain trust-region solves timed after the steps")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after timing, run one device-to-device copy of this many MiB (a reference "
                          "dispatch of known traffic for HBM byte counters; use more than the last-level "
@@ -214,13 +215,17 @@ def main() -> int:
     prob.sync()
     prob.jacobi_stats(reset=True)
     prob.profile_enable(True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    ev[0].record(stream)
+    for i in range(args.steps):
         step()
+        ev[i + 1].record(stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prob.sync()
+    step_ms = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps)])
     log(f"bench: {args.steps} timed steps in {t1 - t0:.3f} s")
 
     kernels = ["controls", "eig", "boundary", "forward", "terminal", "backward", "sterm", "assemble"]
@@ -239,6 +244,28 @@ def main() -> int:
 
     h = hess.cpu().numpy()
     assert np.all(np.isfinite(h)) and np.all(np.isfinite(costs.cpu().numpy()))
+
+    # gradient only (cost + adjoint gradient, same thetas): the Hessian-to-gradient time ratio
+    th_host = thetas.cpu().numpy()
+    prob.grad_many(th_host)
+    g_steps = max(1, min(args.steps, 3))
+    tg0 = time.perf_counter()
+    for _ in range(g_steps):
+        prob.grad_many(th_host)
+    tg = (time.perf_counter() - tg0) / g_steps
+    log(f"bench: gradient-only {tg * 1e3:.1f} ms per batch")
+
+    # plain trust-region solves from theta = 0 on per-theta targets of the same system
+    tr = None
+    if args.tr_solves > 0:
+        tgs = inputs.warm_targets(n, args.tr_solves, spawn=2, dim=6)
+        tt0 = time.perf_counter()
+        _, _, its, conv = prob.tr_solve_many(np.zeros((args.tr_solves, P)), tgs, gtol=1e-8, max_iter=1000)
+        tt = time.perf_counter() - tt0
+        tr = {"solves": args.tr_solves, "seconds": tt, "solves_per_s": args.tr_solves / tt,
+              "iters_mean": float(its.mean()), "converged": int(conv.sum()),
+              "note": "zero start, gradient norm < 1e-8 on the controllable subspace, lockstep batch"}
+        log(f"bench: {args.tr_solves} trust-region solves in {tt:.1f} s")
 
     elapsed = t1 - t0
     value = B * args.steps / elapsed
@@ -271,6 +298,11 @@ def main() -> int:
             "traffic": measured_traffic(dom, B),
         },
         "kernel_ms": {k: round(v[0], 4) for k, v in ktimes.items()},
+        "step_ms_median": float(np.median(step_ms)),
+        "step_ms_iqr": [float(np.percentile(step_ms, 25)), float(np.percentile(step_ms, 75))],
+        "grad_only_evals_per_s": B / tg,
+        "hess_to_grad_time_ratio": (elapsed / args.steps) / tg,
+        "tr_plain": tr,
         "jacobi_sweeps_per_step": eig_sweeps / max(eig_steps, 1),
         "path_alg_flops_per_eval": f_alg,
         "path_roofline_frac": f_alg * value / PEAK_FP64,
