@@ -478,13 +478,25 @@ struct EigWgShape<36> {
   static constexpr int TPB = 256;        // threads per workgroup
   static constexpr int RT = 2, CT = 3;   // 18 x 12 output tiles
   static constexpr bool VP_LDS = true;
+  static constexpr bool REGV = true;     // V in registers during the sweeps
 };
 template <>
 struct EigWgShape<64> {
   static constexpr int TPB = 512;        // eight waves share the 66 KB of LDS
   static constexpr int RT = 4, CT = 2;   // 16 x 32 output tiles
   static constexpr bool VP_LDS = false;
+  static constexpr bool REGV = true;
 };
+
+// Cross-lane moves within a wave by DPP (no LDS traffic): the value of lane + 1 and of lane - 1
+// (wave_shl:1 / wave_shr:1; lanes whose source is outside the wave keep `x`).
+constexpr int kDppFromNext = 0x130, kDppFromPrev = 0x138;
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(__double2loint(x), __double2loint(x), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(__double2hiint(x), __double2hiint(x), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
 
 template <int NP>
 __host__ __device__ constexpr size_t eig_wg_lds_doubles() {
@@ -528,7 +540,16 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
   constexpr int TCOLS = NP / CT;                  // tiles per output row
   constexpr int NTILE = (NP / RT) * TCOLS;
   constexpr bool VP_LDS = EigWgShape<NP>::VP_LDS;
+  constexpr bool REGV = EigWgShape<NP>::REGV;
   static_assert(NP % RT == 0 && NP % CT == 0 && NTILE <= TPB, "tile shape");
+  // Register-resident V (REGV): lane (row group g, pair K) of wave w holds columns 2K, 2K+1 of
+  // rows w*RPW + g + NGRP*m, m < MI, in circle-slot order; a round rotates them in place and
+  // the circle shift moves one value to each neighbour lane (DPP).  At sweep boundaries the
+  // slot order is the player order again.
+  constexpr int RPW = 64 / H;                    // row groups per wave
+  constexpr int NGRP = (TPB / 64) * RPW;
+  constexpr int MI = NP / NGRP;                  // rows per lane
+  static_assert(!REGV || (RPW >= 1 && NP % NGRP == 0), "register V layout");
   extern __shared__ double smem[];
   double* A = smem;                              // NP x NP
   double* Vt = A + NP * NP;                      // NP x NP, column-major: Vt[k * NP + i] = V[i][k]
@@ -566,6 +587,11 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
   }
   // V items u = tid + TPB t: pair u / NP, row u % NP, so consecutive threads take consecutive
   // rows of one pair (conflict-free columns of Vt, one broadcast of the pair's rotation)
+  const int lane = tid & 63;
+  const int vK = lane % H, vg = lane / H;        // pair and row group of this lane (REGV)
+  const bool v_on = vg < RPW;
+  const int vrow0 = (tid >> 6) * RPW + vg;
+  double ve[REGV ? MI : 1], vo[REGV ? MI : 1];
   // output tile of this thread
   const int tr = tid / TCOLS, tc = tid - (tid / TCOLS) * TCOLS;
   const bool has_tile = tid < NTILE;
@@ -579,12 +605,29 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
         A[idx] = (i < n && k < n) ? a.h0[i * n + k] + fj * a.m[i * n + k] : 0.0;
         Vt[idx] = i == k ? 1.0 : 0.0;
       }
+      if (REGV) {
+#pragma unroll
+        for (int m = 0; m < MI; ++m) {
+          const int i = vrow0 + NGRP * m;
+          ve[m] = (v_on && i == 2 * vK) ? 1.0 : 0.0;
+          vo[m] = (v_on && i == 2 * vK + 1) ? 1.0 : 0.0;
+        }
+      }
     } else {
       const double df = fj - fb[j - 1];
       for (int idx = tid; idx < NP * NP; idx += TPB) {
         const int i = idx / NP, k = idx - (idx / NP) * NP;
         A[idx] = df * A[idx] + (i == k ? lamv[i] : 0.0);   // A held Mt_{j-1}
         if (VP_LDS) Vp[idx] = Vt[idx];
+      }
+      if (REGV) {
+        // V_{j-1} back into registers (not kept live through the basis products)
+#pragma unroll
+        for (int m = 0; m < MI; ++m) {
+          const int i = vrow0 + NGRP * m;
+          ve[m] = v_on ? Vt[(2 * vK) * NP + i] : 0.0;
+          vo[m] = v_on ? Vt[(2 * vK + 1) * NP + i] : 0.0;
+        }
       }
     }
     __syncthreads();
@@ -614,7 +657,12 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
       for (int r = 0; r < NP - 1; ++r) {
         if (tid < H) {
           int p, q;
-          rr_pair(r, tid, NP, p, q);
+          if (REGV) {
+            p = circ_player(2 * tid, r, NP);
+            q = circ_player(2 * tid + 1, r, NP);
+          } else {
+            rr_pair(r, tid, NP, p, q);
+          }
           double cc, ss;
           jacobi_rotation(A[p * NP + p], A[q * NP + q], A[p * NP + q], cc, ss);
           rot[tid] = make_double2(cc, ss);
@@ -653,8 +701,20 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
             }
           }
         }
+        if (REGV) {
+          const double2 R = rot[vK];
+#pragma unroll
+          for (int m = 0; m < MI; ++m) {
+            const double e = R.x * ve[m] - R.y * vo[m];
+            const double o = R.y * ve[m] + R.x * vo[m];
+            const double e_next = dpp_move<kDppFromNext>(e);   // pair vK+1's rotated even column
+            const double o_prev = dpp_move<kDppFromPrev>(o);   // pair vK-1's rotated odd column
+            ve[m] = vK == 0 ? e : (vK == H - 1 ? o : e_next);
+            vo[m] = vK == 0 ? e_next : o_prev;
+          }
+        }
 #pragma unroll 2
-        for (int t = 0; t < VPT; ++t) {
+        for (int t = 0; t < (REGV ? 0 : VPT); ++t) {
           const int u = tid + TPB * t;
           if (u < NVI) {
             const int K = u / NP, i = u - (u / NP) * NP;
@@ -669,6 +729,15 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
       }
     }
     if (tid < NP) lamv[tid] = A[tid * NP + tid];
+    if (REGV && v_on) {
+      // sweep boundary: slot order is the player (column) order
+#pragma unroll
+      for (int m = 0; m < MI; ++m) {
+        const int i = vrow0 + NGRP * m;
+        Vt[(2 * vK) * NP + i] = ve[m];
+        Vt[(2 * vK + 1) * NP + i] = vo[m];
+      }
+    }
     __syncthreads();
     const size_t step = (size_t)b * a.eig_stride + (j - a.j_base);
     double acc[RT][CT];
