@@ -463,14 +463,26 @@ __global__ __launch_bounds__(64, 2) void k_eig_wave(EigArgs a) { body_eig_wave<N
 
 // ---------------------------------------------------------------- eigen-data, one workgroup per problem
 
-// Workgroup (4 waves) variant for NP in {36, 64}: the four waves share one problem's LDS
-// (A and V, plus V_{j-1} when it fits), so a compute unit keeps several problems' waves resident
-// and the dependent chain of each Jacobi round is hidden.  Per round: the H = NP/2 rotations of
-// a round-robin pairing are formed by the first H threads, then every thread updates its fixed
-// 2x2 blocks of A (A <- J^T A J) and its fixed (pair, row) items of V (V <- V J).  V is kept
-// column-major so that one pair's items touch consecutive words.  Products at the end of a
-// step use register tiles.  Without LDS room for V_{j-1} (NP = 64) it goes through
-// a global scratch of NP x NP doubles per (theta, chunk).
+// Workgroup variant for NP in {36, 64}: several waves share one problem's LDS, so a compute
+// unit keeps several problems resident and the dependent chain of each Jacobi round is hidden.
+//
+// Everything is kept in circle-slot order: in every round the pairs are slots (2K, 2K+1), and
+// after the round the circle shift moves slot x to slot_next(x) (slot 0 stays, the even slots
+// walk down and the odd ones up); after NP-1 rounds (one sweep) slot order is the index order
+// again and every pair of indices has met once.
+//   A: upper triangle in slot space, ping-ponged between two LDS buffers.  The thread that owns
+//      2x2 block (I, K), I <= K, reads it from the current buffer (two 16-byte reads), applies
+//      J_I^T . J_K and writes each element to its shifted place in the other buffer, so no
+//      thread reads what another writes within a round.
+//   Rotations: double-buffered; those of round r+1 are formed during round r by H threads of
+//      the last wave, from the current buffer and the round-r rotations (the two new diagonal
+//      entries and the new off-diagonal entry of each next pair are single elements of round-r
+//      blocks), so a round needs one barrier.
+//   V: registers; lane (row group g, pair K) of wave w holds columns 2K, 2K+1 of rows
+//      w*RPW + g + NGRP*m, rotates them in place and passes one value to each neighbour lane
+//      (DPP) for the shift.  V goes through LDS only at step ends, for the basis products.
+// Without LDS room for V_{j-1} (NP = 64) it goes through a global scratch of NP x NP doubles
+// per (theta, chunk).
 template <int NP>
 struct EigWgShape;
 template <>
@@ -478,14 +490,12 @@ struct EigWgShape<36> {
   static constexpr int TPB = 256;        // threads per workgroup
   static constexpr int RT = 2, CT = 3;   // 18 x 12 output tiles
   static constexpr bool VP_LDS = true;
-  static constexpr bool REGV = true;     // V in registers during the sweeps
 };
 template <>
 struct EigWgShape<64> {
   static constexpr int TPB = 512;        // eight waves share the 66 KB of LDS
   static constexpr int RT = 4, CT = 2;   // 16 x 32 output tiles
   static constexpr bool VP_LDS = false;
-  static constexpr bool REGV = true;
 };
 
 // Cross-lane moves within a wave by DPP (no LDS traffic): the value of lane + 1 and of lane - 1
@@ -498,10 +508,31 @@ __device__ __forceinline__ double dpp_move(double x) {
   return __hiloint2double(hi, lo);
 }
 
+// Slot that slot x moves to in the circle shift after a round.
+template <int NP>
+__host__ __device__ constexpr int slot_next(int x) {
+  return x == 0 ? 0 : ((x & 1) == 0 ? (x == 2 ? 1 : x - 2) : (x == NP - 1 ? NP - 2 : x + 2));
+}
+// Slot that moves into slot x.
+template <int NP>
+__host__ __device__ constexpr int slot_prev(int x) {
+  return x == 0 ? 0 : ((x & 1) == 0 ? (x == NP - 2 ? NP - 1 : x + 2) : (x == 1 ? 2 : x - 2));
+}
+
+// B = J_I^T [a00 a01; a10 a11] J_K for the rotations RI = (c_I, s_I), RK = (c_K, s_K).
+__device__ __forceinline__ void rotate_block(double a00, double a01, double a10, double a11, double2 RI, double2 RK,
+                                             double& b00, double& b01, double& b10, double& b11) {
+  const double t00 = a00 * RK.x - a01 * RK.y, t01 = a00 * RK.y + a01 * RK.x;
+  const double t10 = a10 * RK.x - a11 * RK.y, t11 = a10 * RK.y + a11 * RK.x;
+  b00 = RI.x * t00 - RI.y * t10;
+  b01 = RI.x * t01 - RI.y * t11;
+  b10 = RI.y * t00 + RI.x * t10;
+  b11 = RI.y * t01 + RI.x * t11;
+}
+
 template <int NP>
 __host__ __device__ constexpr size_t eig_wg_lds_doubles() {
-  return (size_t)(EigWgShape<NP>::VP_LDS ? 3 : 2) * NP * NP + 2 * (NP / 2) + (NP / 2) + NP +
-         EigWgShape<NP>::TPB / 64;
+  return (size_t)(EigWgShape<NP>::VP_LDS ? 3 : 2) * NP * NP + 4 * (NP / 2) + NP + EigWgShape<NP>::TPB / 64;
 }
 
 // Sum / max over a workgroup of TPB threads from the wave partials (red: TPB/64 doubles of LDS).
@@ -534,29 +565,22 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
   constexpr int NBLK = H * (H + 1) / 2;
   constexpr int TPB = EigWgShape<NP>::TPB;
   constexpr int BPT = (NBLK + TPB - 1) / TPB;
-  constexpr int NVI = NP * H;
-  constexpr int VPT = (NVI + TPB - 1) / TPB;
   constexpr int RT = EigWgShape<NP>::RT, CT = EigWgShape<NP>::CT;
   constexpr int TCOLS = NP / CT;                  // tiles per output row
   constexpr int NTILE = (NP / RT) * TCOLS;
   constexpr bool VP_LDS = EigWgShape<NP>::VP_LDS;
-  constexpr bool REGV = EigWgShape<NP>::REGV;
-  static_assert(NP % RT == 0 && NP % CT == 0 && NTILE <= TPB, "tile shape");
-  // Register-resident V (REGV): lane (row group g, pair K) of wave w holds columns 2K, 2K+1 of
-  // rows w*RPW + g + NGRP*m, m < MI, in circle-slot order; a round rotates them in place and
-  // the circle shift moves one value to each neighbour lane (DPP).  At sweep boundaries the
-  // slot order is the player order again.
-  constexpr int RPW = 64 / H;                    // row groups per wave
+  constexpr int RPW = 64 / H;                    // V row groups per wave
   constexpr int NGRP = (TPB / 64) * RPW;
-  constexpr int MI = NP / NGRP;                  // rows per lane
-  static_assert(!REGV || (RPW >= 1 && NP % NGRP == 0), "register V layout");
+  constexpr int MI = NP / NGRP;                  // V rows per lane
+  constexpr int ROT0 = TPB - 64;                 // first thread forming the next rotations
+  static_assert(NP % RT == 0 && NP % CT == 0 && NTILE <= TPB, "tile shape");
+  static_assert(RPW >= 1 && NP % NGRP == 0 && H <= 64, "register V layout");
   extern __shared__ double smem[];
-  double* A = smem;                              // NP x NP
-  double* Vt = A + NP * NP;                      // NP x NP, column-major: Vt[k * NP + i] = V[i][k]
+  double* A = smem;                              // NP x NP; also A buffer 0 during the sweeps
+  double* Vt = A + NP * NP;                      // NP x NP, column-major: Vt[k * NP + i] = V[i][k]; A buffer 1
   double* Vp = VP_LDS ? Vt + NP * NP : nullptr;  // V_{j-1}, same layout
-  double2* rot = (double2*)(Vt + (VP_LDS ? 2 : 1) * NP * NP);  // (c, s) per pair
-  int2* prs = (int2*)(rot + H);                  // (p, q) per pair
-  double* lamv = (double*)rot + 3 * H;           // eigenvalues
+  double2* rot = (double2*)(Vt + (VP_LDS ? 2 : 1) * NP * NP);  // 2 x H rotations (c, s)
+  double* lamv = (double*)(rot + 2 * H);         // eigenvalues
   double* red = lamv + NP;                       // wave partials
   const int tid = threadIdx.x;
   const int n = a.n, nt = a.nt;
@@ -567,8 +591,9 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
   const size_t nn = (size_t)n * n;
   double* vpg = VP_LDS ? nullptr : a.gscratch + ((size_t)b * a.nchunks + c) * NP * NP;
 
-  // fixed work of this thread: 2x2 blocks (I <= K) and V items (row, pair)
-  int bI[BPT], bK[BPT];
+  // fixed 2x2 blocks (I <= K) of this thread: read offset in the current buffer and the four
+  // write offsets (upper triangle of the shifted slots) in the other one
+  int bI[BPT], bK[BPT], bw[BPT][4];
 #pragma unroll
   for (int t = 0; t < BPT; ++t) {
     const int w = tid + TPB * t;
@@ -584,14 +609,26 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
     }
     bI[t] = I;
     bK[t] = K;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int x = slot_next<NP>(2 * max(I, 0) + (e >> 1)), y = slot_next<NP>(2 * K + (e & 1));
+      bw[t][e] = min(x, y) * NP + max(x, y);
+    }
   }
-  // V items u = tid + TPB t: pair u / NP, row u % NP, so consecutive threads take consecutive
-  // rows of one pair (conflict-free columns of Vt, one broadcast of the pair's rotation)
+  // next-round rotation formed by this thread (pair kr of the next round): its even slot comes
+  // from slot es, its odd slot from slot os; the off-diagonal entry is element (ep, op) of the
+  // round's block (I0, K0)
+  const int kr = tid - ROT0;
+  const bool has_rot = kr >= 0 && kr < H;
+  const int es = slot_prev<NP>(2 * kr), os = slot_prev<NP>(2 * kr + 1);
+  const int I0 = min(es, os) >> 1, K0 = max(es, os) >> 1;
+  const int rpar = (es < os ? es : os) & 1, cpar = (es < os ? os : es) & 1;
+  // V registers
   const int lane = tid & 63;
-  const int vK = lane % H, vg = lane / H;        // pair and row group of this lane (REGV)
+  const int vK = lane % H, vg = lane / H;
   const bool v_on = vg < RPW;
   const int vrow0 = (tid >> 6) * RPW + vg;
-  double ve[REGV ? MI : 1], vo[REGV ? MI : 1];
+  double ve[MI], vo[MI];
   // output tile of this thread
   const int tr = tid / TCOLS, tc = tid - (tid / TCOLS) * TCOLS;
   const bool has_tile = tid < NTILE;
@@ -603,15 +640,12 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
       for (int idx = tid; idx < NP * NP; idx += TPB) {
         const int i = idx / NP, k = idx - (idx / NP) * NP;
         A[idx] = (i < n && k < n) ? a.h0[i * n + k] + fj * a.m[i * n + k] : 0.0;
-        Vt[idx] = i == k ? 1.0 : 0.0;
       }
-      if (REGV) {
 #pragma unroll
-        for (int m = 0; m < MI; ++m) {
-          const int i = vrow0 + NGRP * m;
-          ve[m] = (v_on && i == 2 * vK) ? 1.0 : 0.0;
-          vo[m] = (v_on && i == 2 * vK + 1) ? 1.0 : 0.0;
-        }
+      for (int m = 0; m < MI; ++m) {
+        const int i = vrow0 + NGRP * m;
+        ve[m] = (v_on && i == 2 * vK) ? 1.0 : 0.0;
+        vo[m] = (v_on && i == 2 * vK + 1) ? 1.0 : 0.0;
       }
     } else {
       const double df = fj - fb[j - 1];
@@ -620,26 +654,26 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
         A[idx] = df * A[idx] + (i == k ? lamv[i] : 0.0);   // A held Mt_{j-1}
         if (VP_LDS) Vp[idx] = Vt[idx];
       }
-      if (REGV) {
-        // V_{j-1} back into registers (not kept live through the basis products)
+      // V_{j-1} back into registers (not kept live through the basis products)
 #pragma unroll
-        for (int m = 0; m < MI; ++m) {
-          const int i = vrow0 + NGRP * m;
-          ve[m] = v_on ? Vt[(2 * vK) * NP + i] : 0.0;
-          vo[m] = v_on ? Vt[(2 * vK + 1) * NP + i] : 0.0;
-        }
+      for (int m = 0; m < MI; ++m) {
+        const int i = vrow0 + NGRP * m;
+        ve[m] = v_on ? Vt[(2 * vK) * NP + i] : 0.0;
+        vo[m] = v_on ? Vt[(2 * vK + 1) * NP + i] : 0.0;
       }
     }
     __syncthreads();
     double loc = 0.0;
     for (int idx = tid; idx < NP * NP; idx += TPB) loc = fma(A[idx], A[idx], loc);
     const double tol = a.tol_rel * sqrt(wg_sum<TPB>(loc, red));
+    int cur = 0, rb = 0;                           // current A buffer and rotation buffer
 #pragma unroll 1
     for (int sweep = 0;; ++sweep) {
+      const double* Ac = cur ? Vt : A;
       double off = 0.0;
       for (int idx = tid; idx < NP * NP; idx += TPB) {
         const int i = idx / NP, k = idx - (idx / NP) * NP;
-        if (i < k) off = fmax(off, fabs(A[idx]));
+        if (i < k) off = fmax(off, fabs(Ac[idx]));
       }
       off = wg_max<TPB>(off, red);
       if (off <= tol) {
@@ -653,84 +687,89 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
         if (tid == 0) atomicOr(a.status, kStatusNoConv);
         break;
       }
-#pragma unroll 1
-      for (int r = 0; r < NP - 1; ++r) {
-        if (tid < H) {
-          int p, q;
-          if (REGV) {
-            p = circ_player(2 * tid, r, NP);
-            q = circ_player(2 * tid + 1, r, NP);
-          } else {
-            rr_pair(r, tid, NP, p, q);
-          }
+      if (sweep == 0) {
+        // first rotations of the step; later sweeps get theirs from the last round before
+        if (has_rot) {
           double cc, ss;
-          jacobi_rotation(A[p * NP + p], A[q * NP + q], A[p * NP + q], cc, ss);
-          rot[tid] = make_double2(cc, ss);
-          prs[tid] = make_int2(p, q);
+          jacobi_rotation(Ac[(2 * kr) * NP + 2 * kr], Ac[(2 * kr + 1) * NP + 2 * kr + 1], Ac[(2 * kr) * NP + 2 * kr + 1],
+                          cc, ss);
+          rot[rb * H + kr] = make_double2(cc, ss);
         }
         __syncthreads();
+      }
 #pragma unroll 1
+      for (int r = 0; r < NP - 1; ++r) {
+        const double* Ar = cur ? Vt : A;
+        double* An = cur ? A : Vt;
+        const double2* R = rot + rb * H;
+#pragma unroll
         for (int t = 0; t < BPT; ++t) {
           const int I = bI[t];
           if (I >= 0) {
             const int K = bK[t];
-            const int2 PI = prs[I], PK = prs[K];
-            const double2 RI = rot[I], RK = rot[K];
-            const int pI = PI.x, qI = PI.y, pK = PK.x, qK = PK.y;
-            const double cI = RI.x, sI = RI.y, cK = RK.x, sK = RK.y;
-            const double a00 = A[pI * NP + pK], a01 = A[pI * NP + qK];
-            const double a10 = A[qI * NP + pK], a11 = A[qI * NP + qK];
-            const double t00 = a00 * cK - a01 * sK, t01 = a00 * sK + a01 * cK;
-            const double t10 = a10 * cK - a11 * sK, t11 = a10 * sK + a11 * cK;
-            const double b00 = cI * t00 - sI * t10, b01 = cI * t01 - sI * t11;
-            const double b10 = sI * t00 + cI * t10, b11 = sI * t01 + cI * t11;
+            const double2 RI = R[I], RK = R[K];
+            const double2 r0 = *(const double2*)(Ar + (2 * I) * NP + 2 * K);
+            double b00, b01, b10, b11;
             if (I == K) {
-              A[pI * NP + pI] = b00;
-              A[pI * NP + qI] = 0.0;
-              A[qI * NP + pI] = 0.0;
-              A[qI * NP + qI] = b11;
+              const double a11 = Ar[(2 * I + 1) * NP + 2 * I + 1];
+              rotate_block(r0.x, r0.y, r0.y, a11, RI, RI, b00, b01, b10, b11);
+              An[bw[t][0]] = b00;
+              An[bw[t][1]] = 0.0;
+              An[bw[t][3]] = b11;
             } else {
-              A[pI * NP + pK] = b00;
-              A[pI * NP + qK] = b01;
-              A[qI * NP + pK] = b10;
-              A[qI * NP + qK] = b11;
-              A[pK * NP + pI] = b00;
-              A[qK * NP + pI] = b01;
-              A[pK * NP + qI] = b10;
-              A[qK * NP + qI] = b11;
+              const double2 r1 = *(const double2*)(Ar + (2 * I + 1) * NP + 2 * K);
+              rotate_block(r0.x, r0.y, r1.x, r1.y, RI, RK, b00, b01, b10, b11);
+              An[bw[t][0]] = b00;
+              An[bw[t][1]] = b01;
+              An[bw[t][2]] = b10;
+              An[bw[t][3]] = b11;
             }
           }
         }
-        if (REGV) {
-          const double2 R = rot[vK];
+        if (has_rot) {
+          // the next round's pair kr: new diagonal entries of slots es and os (each from its
+          // round-r diagonal block) and the new entry (es, os) (from block (I0, K0))
+          double d[2];
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const int x = h ? os : es, P = x >> 1;
+            const double2 RP = R[P];
+            const double2 r0 = *(const double2*)(Ar + (2 * P) * NP + 2 * P);
+            const double a11 = Ar[(2 * P + 1) * NP + 2 * P + 1];
+            double b00, b01, b10, b11;
+            rotate_block(r0.x, r0.y, r0.y, a11, RP, RP, b00, b01, b10, b11);
+            d[h] = (x & 1) ? b11 : b00;
+          }
+          const double2 r0 = *(const double2*)(Ar + (2 * I0) * NP + 2 * K0);
+          const double2 r1 = *(const double2*)(Ar + (2 * I0 + 1) * NP + 2 * K0);
+          double b00, b01, b10, b11;
+          rotate_block(r0.x, r0.y, r1.x, r1.y, R[I0], R[K0], b00, b01, b10, b11);
+          const double e = rpar ? (cpar ? b11 : b10) : (cpar ? b01 : b00);
+          double cc, ss;
+          jacobi_rotation(d[0], d[1], e, cc, ss);
+          rot[(rb ^ 1) * H + kr] = make_double2(cc, ss);
+        }
+        {
+          const double2 RV = R[vK];
 #pragma unroll
           for (int m = 0; m < MI; ++m) {
-            const double e = R.x * ve[m] - R.y * vo[m];
-            const double o = R.y * ve[m] + R.x * vo[m];
+            const double e = RV.x * ve[m] - RV.y * vo[m];
+            const double o = RV.y * ve[m] + RV.x * vo[m];
             const double e_next = dpp_move<kDppFromNext>(e);   // pair vK+1's rotated even column
             const double o_prev = dpp_move<kDppFromPrev>(o);   // pair vK-1's rotated odd column
             ve[m] = vK == 0 ? e : (vK == H - 1 ? o : e_next);
             vo[m] = vK == 0 ? e_next : o_prev;
           }
         }
-#pragma unroll 2
-        for (int t = 0; t < (REGV ? 0 : VPT); ++t) {
-          const int u = tid + TPB * t;
-          if (u < NVI) {
-            const int K = u / NP, i = u - (u / NP) * NP;
-            const int2 PQ = prs[K];
-            const double2 R = rot[K];
-            const double vp = Vt[PQ.x * NP + i], vq = Vt[PQ.y * NP + i];
-            Vt[PQ.x * NP + i] = R.x * vp - R.y * vq;
-            Vt[PQ.y * NP + i] = R.y * vp + R.x * vq;
-          }
-        }
+        cur ^= 1;
+        rb ^= 1;
         __syncthreads();
       }
     }
-    if (tid < NP) lamv[tid] = A[tid * NP + tid];
-    if (REGV && v_on) {
-      // sweep boundary: slot order is the player (column) order
+    // sweep boundary: slot order is the index order
+    if (tid < NP) lamv[tid] = (cur ? Vt : A)[tid * NP + tid];
+    __syncthreads();
+    if (v_on) {
 #pragma unroll
       for (int m = 0; m < MI; ++m) {
         const int i = vrow0 + NGRP * m;
