@@ -77,6 +77,19 @@ __device__ __forceinline__ void jacobi_rotation(double app, double aqq, double a
   }
 }
 
+// The same rotation without a branch (both outcomes evaluated, then selected), so that the
+// loads feeding it can all be issued up front.
+__device__ __forceinline__ void jacobi_rotation_nobranch(double app, double aqq, double apq, double& c, double& s) {
+  const double d = aqq - app, e = 2.0 * apq;
+  const double x = fma(d, d, e * e);
+  const double h = x * rsqrt_refined(x);
+  const double t = (d >= 0.0 ? e : -e) * rcp_refined(fabs(d) + h);
+  const double r = rsqrt_refined(fma(t, t, 1.0));
+  const bool rotate = fabs(apq) > 1e-150;
+  c = rotate ? r : 1.0;
+  s = rotate ? t * r : 0.0;
+}
+
 // First divided difference phi[x, y] of phi(t) = exp(-i dt t):
 //   phi[x, y] = -i dt exp(-i dt (x + y)/2) sinc(dt (x - y)/2),
 // an identity valid for every gap, confluent case (phi'(x)) included.

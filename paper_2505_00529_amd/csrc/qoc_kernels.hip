@@ -490,12 +490,14 @@ struct EigWgShape<36> {
   static constexpr int TPB = 256;        // threads per workgroup
   static constexpr int RT = 2, CT = 3;   // 18 x 12 output tiles
   static constexpr bool VP_LDS = true;
+  static constexpr int VW = 3;           // waves holding V (the last one forms the rotations)
 };
 template <>
 struct EigWgShape<64> {
   static constexpr int TPB = 512;        // eight waves share the 66 KB of LDS
   static constexpr int RT = 4, CT = 2;   // 16 x 32 output tiles
   static constexpr bool VP_LDS = false;
+  static constexpr int VW = 8;
 };
 
 // Cross-lane moves within a wave by DPP (no LDS traffic): the value of lane + 1 and of lane - 1
@@ -517,6 +519,16 @@ __host__ __device__ constexpr int slot_next(int x) {
 template <int NP>
 __host__ __device__ constexpr int slot_prev(int x) {
   return x == 0 ? 0 : ((x & 1) == 0 ? (x == NP - 2 ? NP - 1 : x + 2) : (x == 1 ? 2 : x - 2));
+}
+
+// Column x of the rotation J for (c, s): (c, -s) for the first index of the pair, (s, c) for
+// the second.
+__device__ __forceinline__ double2 rot_col(double2 R, int second) {
+  return second ? make_double2(R.y, R.x) : make_double2(R.x, -R.y);
+}
+// One entry u^T [a00 a01; a10 a11] w of a rotated 2x2 block.
+__device__ __forceinline__ double rotate_entry(double a00, double a01, double a10, double a11, double2 u, double2 w) {
+  return u.x * fma(a01, w.y, a00 * w.x) + u.y * fma(a11, w.y, a10 * w.x);
 }
 
 // B = J_I^T [a00 a01; a10 a11] J_K for the rotations RI = (c_I, s_I), RK = (c_K, s_K).
@@ -570,7 +582,8 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
   constexpr int NTILE = (NP / RT) * TCOLS;
   constexpr bool VP_LDS = EigWgShape<NP>::VP_LDS;
   constexpr int RPW = 64 / H;                    // V row groups per wave
-  constexpr int NGRP = (TPB / 64) * RPW;
+  constexpr int VW = EigWgShape<NP>::VW;
+  constexpr int NGRP = VW * RPW;
   constexpr int MI = NP / NGRP;                  // V rows per lane
   constexpr int ROT0 = TPB - 64;                 // first thread forming the next rotations
   static_assert(NP % RT == 0 && NP % CT == 0 && NTILE <= TPB, "tile shape");
@@ -626,7 +639,8 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
   // V registers
   const int lane = tid & 63;
   const int vK = lane % H, vg = lane / H;
-  const bool v_on = vg < RPW;
+  const bool v_wave = (tid >> 6) < VW;
+  const bool v_on = v_wave && vg < RPW;
   const int vrow0 = (tid >> 6) * RPW + vg;
   double ve[MI], vo[MI];
   // output tile of this thread
@@ -709,47 +723,37 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
             const int K = bK[t];
             const double2 RI = R[I], RK = R[K];
             const double2 r0 = *(const double2*)(Ar + (2 * I) * NP + 2 * K);
+            const double2 r1 = *(const double2*)(Ar + (2 * I + 1) * NP + 2 * K);
+            // a diagonal block (I == K) is symmetric: its lower entry is not stored, and the
+            // rotation annihilates its off-diagonal pair (both writes go to one place)
+            const bool dg = I == K;
             double b00, b01, b10, b11;
-            if (I == K) {
-              const double a11 = Ar[(2 * I + 1) * NP + 2 * I + 1];
-              rotate_block(r0.x, r0.y, r0.y, a11, RI, RI, b00, b01, b10, b11);
-              An[bw[t][0]] = b00;
-              An[bw[t][1]] = 0.0;
-              An[bw[t][3]] = b11;
-            } else {
-              const double2 r1 = *(const double2*)(Ar + (2 * I + 1) * NP + 2 * K);
-              rotate_block(r0.x, r0.y, r1.x, r1.y, RI, RK, b00, b01, b10, b11);
-              An[bw[t][0]] = b00;
-              An[bw[t][1]] = b01;
-              An[bw[t][2]] = b10;
-              An[bw[t][3]] = b11;
-            }
+            rotate_block(r0.x, r0.y, dg ? r0.y : r1.x, r1.y, RI, RK, b00, b01, b10, b11);
+            An[bw[t][0]] = b00;
+            An[bw[t][1]] = dg ? 0.0 : b01;
+            An[bw[t][2]] = dg ? 0.0 : b10;
+            An[bw[t][3]] = b11;
           }
         }
         if (has_rot) {
           // the next round's pair kr: new diagonal entries of slots es and os (each from its
           // round-r diagonal block) and the new entry (es, os) (from block (I0, K0))
-          double d[2];
-#pragma unroll
-          for (int h = 0; h < 2; ++h) {
-            const int x = h ? os : es, P = x >> 1;
-            const double2 RP = R[P];
-            const double2 r0 = *(const double2*)(Ar + (2 * P) * NP + 2 * P);
-            const double a11 = Ar[(2 * P + 1) * NP + 2 * P + 1];
-            double b00, b01, b10, b11;
-            rotate_block(r0.x, r0.y, r0.y, a11, RP, RP, b00, b01, b10, b11);
-            d[h] = (x & 1) ? b11 : b00;
-          }
+          // (the two slots lie in pairs I0 < K0, whose diagonal blocks give the diagonal entries)
+          const double2 uI = rot_col(R[I0], rpar), uK = rot_col(R[K0], cpar);
+          const double2 gI = *(const double2*)(Ar + (2 * I0) * NP + 2 * I0);
+          const double gI11 = Ar[(2 * I0 + 1) * NP + 2 * I0 + 1];
+          const double2 gK = *(const double2*)(Ar + (2 * K0) * NP + 2 * K0);
+          const double gK11 = Ar[(2 * K0 + 1) * NP + 2 * K0 + 1];
           const double2 r0 = *(const double2*)(Ar + (2 * I0) * NP + 2 * K0);
           const double2 r1 = *(const double2*)(Ar + (2 * I0 + 1) * NP + 2 * K0);
-          double b00, b01, b10, b11;
-          rotate_block(r0.x, r0.y, r1.x, r1.y, R[I0], R[K0], b00, b01, b10, b11);
-          const double e = rpar ? (cpar ? b11 : b10) : (cpar ? b01 : b00);
+          const double dI = rotate_entry(gI.x, gI.y, gI.y, gI11, uI, uI);
+          const double dK = rotate_entry(gK.x, gK.y, gK.y, gK11, uK, uK);
+          const double e = rotate_entry(r0.x, r0.y, r1.x, r1.y, uI, uK);
           double cc, ss;
-          jacobi_rotation(d[0], d[1], e, cc, ss);
+          jacobi_rotation_nobranch(es < os ? dI : dK, es < os ? dK : dI, e, cc, ss);
           rot[(rb ^ 1) * H + kr] = make_double2(cc, ss);
         }
-        {
+        if (v_wave) {
           const double2 RV = R[vK];
 #pragma unroll
           for (int m = 0; m < MI; ++m) {
