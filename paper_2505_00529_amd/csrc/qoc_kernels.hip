@@ -478,9 +478,10 @@ __global__ __launch_bounds__(64, 2) void k_eig_wave(EigArgs a) { body_eig_wave<N
 //      the last wave, from the current buffer and the round-r rotations (the two new diagonal
 //      entries and the new off-diagonal entry of each next pair are single elements of round-r
 //      blocks), so a round needs one barrier.
-//   V: registers; lane (row group g, pair K) of wave w holds columns 2K, 2K+1 of rows
-//      w*RPW + g + NGRP*m, rotates them in place and passes one value to each neighbour lane
-//      (DPP) for the shift.  V goes through LDS only at step ends, for the basis products.
+//   V: registers; a lane holds one row's columns for S consecutive pairs (a segment, G = H/S
+//      segments per row), applies their rotations in place and shifts them within the segment;
+//      only the segment ends cross lanes (one DPP move each way).  V goes through LDS only at
+//      step ends, for the basis products.
 // Without LDS room for V_{j-1} (NP = 64) it goes through a global scratch of NP x NP doubles
 // per (theta, chunk).
 template <int NP>
@@ -490,14 +491,16 @@ struct EigWgShape<36> {
   static constexpr int TPB = 256;        // threads per workgroup
   static constexpr int RT = 2, CT = 3;   // 18 x 12 output tiles
   static constexpr bool VP_LDS = true;
-  static constexpr int VW = 3;           // waves holding V (the last one forms the rotations)
+  static constexpr int VW0 = 1, VW = 2;  // waves VW0 .. VW0+VW-1 hold V
+  static constexpr int VS = 6;           // pairs per V segment
 };
 template <>
 struct EigWgShape<64> {
   static constexpr int TPB = 512;        // eight waves share the 66 KB of LDS
   static constexpr int RT = 4, CT = 2;   // 16 x 32 output tiles
   static constexpr bool VP_LDS = false;
-  static constexpr int VW = 8;
+  static constexpr int VW0 = 1, VW = 4;
+  static constexpr int VS = 8;
 };
 
 // Cross-lane moves within a wave by DPP (no LDS traffic): the value of lane + 1 and of lane - 1
@@ -581,13 +584,14 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
   constexpr int TCOLS = NP / CT;                  // tiles per output row
   constexpr int NTILE = (NP / RT) * TCOLS;
   constexpr bool VP_LDS = EigWgShape<NP>::VP_LDS;
-  constexpr int RPW = 64 / H;                    // V row groups per wave
-  constexpr int VW = EigWgShape<NP>::VW;
-  constexpr int NGRP = VW * RPW;
-  constexpr int MI = NP / NGRP;                  // V rows per lane
+  constexpr int VW0 = EigWgShape<NP>::VW0, VW = EigWgShape<NP>::VW;
+  constexpr int S = EigWgShape<NP>::VS;          // pairs per V segment
+  constexpr int G = H / S;                       // segments per row
+  constexpr int VRW = NP / VW;                   // V rows per wave
   constexpr int ROT0 = TPB - 64;                 // first thread forming the next rotations
   static_assert(NP % RT == 0 && NP % CT == 0 && NTILE <= TPB, "tile shape");
-  static_assert(RPW >= 1 && NP % NGRP == 0 && H <= 64, "register V layout");
+  static_assert(H % S == 0 && S >= 2 && NP % VW == 0 && VRW * G <= 64 && VW0 + VW <= TPB / 64 - 1,
+                "register V layout");
   extern __shared__ double smem[];
   double* A = smem;                              // NP x NP; also A buffer 0 during the sweeps
   double* Vt = A + NP * NP;                      // NP x NP, column-major: Vt[k * NP + i] = V[i][k]; A buffer 1
@@ -638,11 +642,11 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
   const int rpar = (es < os ? es : os) & 1, cpar = (es < os ? os : es) & 1;
   // V registers
   const int lane = tid & 63;
-  const int vK = lane % H, vg = lane / H;
-  const bool v_wave = (tid >> 6) < VW;
-  const bool v_on = v_wave && vg < RPW;
-  const int vrow0 = (tid >> 6) * RPW + vg;
-  double ve[MI], vo[MI];
+  const int vseg = lane % G;                     // segment: pairs vseg*S .. vseg*S+S-1
+  const bool v_wave = (tid >> 6) >= VW0 && (tid >> 6) < VW0 + VW;
+  const bool v_on = v_wave && lane < VRW * G;
+  const int vrow = ((tid >> 6) - VW0) * VRW + lane / G;
+  double ve[S], vo[S];
   // output tile of this thread
   const int tr = tid / TCOLS, tc = tid - (tid / TCOLS) * TCOLS;
   const bool has_tile = tid < NTILE;
@@ -656,10 +660,10 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
         A[idx] = (i < n && k < n) ? a.h0[i * n + k] + fj * a.m[i * n + k] : 0.0;
       }
 #pragma unroll
-      for (int m = 0; m < MI; ++m) {
-        const int i = vrow0 + NGRP * m;
-        ve[m] = (v_on && i == 2 * vK) ? 1.0 : 0.0;
-        vo[m] = (v_on && i == 2 * vK + 1) ? 1.0 : 0.0;
+      for (int k = 0; k < S; ++k) {
+        const int K = vseg * S + k;
+        ve[k] = (v_on && vrow == 2 * K) ? 1.0 : 0.0;
+        vo[k] = (v_on && vrow == 2 * K + 1) ? 1.0 : 0.0;
       }
     } else {
       const double df = fj - fb[j - 1];
@@ -670,10 +674,10 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
       }
       // V_{j-1} back into registers (not kept live through the basis products)
 #pragma unroll
-      for (int m = 0; m < MI; ++m) {
-        const int i = vrow0 + NGRP * m;
-        ve[m] = v_on ? Vt[(2 * vK) * NP + i] : 0.0;
-        vo[m] = v_on ? Vt[(2 * vK + 1) * NP + i] : 0.0;
+      for (int k = 0; k < S; ++k) {
+        const int K = vseg * S + k;
+        ve[k] = v_on ? Vt[(2 * K) * NP + vrow] : 0.0;
+        vo[k] = v_on ? Vt[(2 * K + 1) * NP + vrow] : 0.0;
       }
     }
     __syncthreads();
@@ -754,16 +758,24 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
           rot[(rb ^ 1) * H + kr] = make_double2(cc, ss);
         }
         if (v_wave) {
-          const double2 RV = R[vK];
+          double e[S], o[S];
 #pragma unroll
-          for (int m = 0; m < MI; ++m) {
-            const double e = RV.x * ve[m] - RV.y * vo[m];
-            const double o = RV.y * ve[m] + RV.x * vo[m];
-            const double e_next = dpp_move<kDppFromNext>(e);   // pair vK+1's rotated even column
-            const double o_prev = dpp_move<kDppFromPrev>(o);   // pair vK-1's rotated odd column
-            ve[m] = vK == 0 ? e : (vK == H - 1 ? o : e_next);
-            vo[m] = vK == 0 ? e_next : o_prev;
+          for (int k = 0; k < S; ++k) {
+            const double2 RV = R[vseg * S + k];
+            e[k] = RV.x * ve[k] - RV.y * vo[k];
+            o[k] = RV.y * ve[k] + RV.x * vo[k];
           }
+          const double e_next = dpp_move<kDppFromNext>(e[0]);       // next segment's first even
+          const double o_prev = dpp_move<kDppFromPrev>(o[S - 1]);   // previous segment's last odd
+          // circle shift: even columns move down one pair, odd ones up; pair 0's even stays,
+          // its odd takes pair 1's even, and pair H-1's even takes its own odd
+          ve[0] = vseg == 0 ? e[0] : e[1];
+#pragma unroll
+          for (int k = 1; k < S - 1; ++k) ve[k] = e[k + 1];
+          ve[S - 1] = vseg == G - 1 ? o[S - 1] : e_next;
+          vo[0] = vseg == 0 ? e[1] : o_prev;
+#pragma unroll
+          for (int k = 1; k < S; ++k) vo[k] = o[k - 1];
         }
         cur ^= 1;
         rb ^= 1;
@@ -775,10 +787,10 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
     __syncthreads();
     if (v_on) {
 #pragma unroll
-      for (int m = 0; m < MI; ++m) {
-        const int i = vrow0 + NGRP * m;
-        Vt[(2 * vK) * NP + i] = ve[m];
-        Vt[(2 * vK + 1) * NP + i] = vo[m];
+      for (int k = 0; k < S; ++k) {
+        const int K = vseg * S + k;
+        Vt[(2 * K) * NP + vrow] = ve[k];
+        Vt[(2 * K + 1) * NP + vrow] = vo[k];
       }
     }
     __syncthreads();
