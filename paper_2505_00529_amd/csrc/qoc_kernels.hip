@@ -493,6 +493,7 @@ struct EigWgShape<36> {
   static constexpr bool VP_LDS = true;
   static constexpr int VW0 = 1, VW = 2;  // waves VW0 .. VW0+VW-1 hold V
   static constexpr int VS = 6;           // pairs per V segment
+  static constexpr int WAVES = 4;        // waves per SIMD (five spill more than they hide)
 };
 template <>
 struct EigWgShape<64> {
@@ -501,6 +502,7 @@ struct EigWgShape<64> {
   static constexpr bool VP_LDS = false;
   static constexpr int VW0 = 1, VW = 4;
   static constexpr int VS = 8;
+  static constexpr int WAVES = 4;
 };
 
 // Cross-lane moves within a wave by DPP (no LDS traffic): the value of lane + 1 and of lane - 1
@@ -796,6 +798,9 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
     __syncthreads();
     const size_t step = (size_t)b * a.eig_stride + (j - a.j_base);
     double acc[RT][CT];
+    // Basis products on register tiles.  Their inner index r runs over all NP (V and X vanish
+    // in the padding rows), two values per 16-byte load: column-major V, and X stored
+    // transposed.
     // O_{j-1} = V_j^T V_{j-1}
     if (j > j0 && has_tile) {
 #pragma unroll
@@ -804,16 +809,16 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
         for (int y = 0; y < CT; ++y) acc[x][y] = 0.0;
       const double* Vprev = VP_LDS ? Vp : vpg;
 #pragma unroll 2
-      for (int r = 0; r < n; ++r) {
-        double u[RT], w[CT];
+      for (int r = 0; r < NP; r += 2) {
+        double2 u[RT], w[CT];
 #pragma unroll
-        for (int x = 0; x < RT; ++x) u[x] = Vt[(i0 + x) * NP + r];
+        for (int x = 0; x < RT; ++x) u[x] = *(const double2*)(Vt + (i0 + x) * NP + r);
 #pragma unroll
-        for (int y = 0; y < CT; ++y) w[y] = Vprev[(k0 + y) * NP + r];
+        for (int y = 0; y < CT; ++y) w[y] = *(const double2*)(Vprev + (k0 + y) * NP + r);
 #pragma unroll
         for (int x = 0; x < RT; ++x)
 #pragma unroll
-          for (int y = 0; y < CT; ++y) acc[x][y] = fma(u[x], w[y], acc[x][y]);
+          for (int y = 0; y < CT; ++y) acc[x][y] = fma(u[x].y, w[y].y, fma(u[x].x, w[y].x, acc[x][y]));
       }
       double* dst = a.ov + (step - 1) * nn;
 #pragma unroll
@@ -822,28 +827,32 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
         for (int y = 0; y < CT; ++y)
           if (i0 + x < n && k0 + y < n) dst[(size_t)(i0 + x) * n + k0 + y] = acc[x][y];
     }
-    // X = M V_j into A (M symmetric: row r of M is column r)
+    // X = M V_j into A, transposed (A[k][i] = X[i][k]; M symmetric: row i of M is column i)
     if (has_tile) {
 #pragma unroll
       for (int x = 0; x < RT; ++x)
 #pragma unroll
         for (int y = 0; y < CT; ++y) acc[x][y] = 0.0;
 #pragma unroll 2
-      for (int r = 0; r < n; ++r) {
-        double u[RT], w[CT];
+      for (int r = 0; r < n; r += 2) {
+        double2 u[RT], w[CT];
 #pragma unroll
-        for (int x = 0; x < RT; ++x) u[x] = i0 + x < n ? a.m[r * n + i0 + x] : 0.0;
+        for (int x = 0; x < RT; ++x) {
+          const bool row = i0 + x < n;
+          u[x].x = row ? a.m[(i0 + x) * n + r] : 0.0;
+          u[x].y = row && r + 1 < n ? a.m[(i0 + x) * n + r + 1] : 0.0;
+        }
 #pragma unroll
-        for (int y = 0; y < CT; ++y) w[y] = Vt[(k0 + y) * NP + r];
+        for (int y = 0; y < CT; ++y) w[y] = *(const double2*)(Vt + (k0 + y) * NP + r);
 #pragma unroll
         for (int x = 0; x < RT; ++x)
 #pragma unroll
-          for (int y = 0; y < CT; ++y) acc[x][y] = fma(u[x], w[y], acc[x][y]);
+          for (int y = 0; y < CT; ++y) acc[x][y] = fma(u[x].y, w[y].y, fma(u[x].x, w[y].x, acc[x][y]));
       }
 #pragma unroll
-      for (int x = 0; x < RT; ++x)
+      for (int y = 0; y < CT; ++y)
 #pragma unroll
-        for (int y = 0; y < CT; ++y) A[(i0 + x) * NP + k0 + y] = acc[x][y];
+        for (int x = 0; x < RT; ++x) A[(k0 + y) * NP + i0 + x] = acc[x][y];
     }
     __syncthreads();
     // Mt_j = V_j^T X, kept in A for the next step's warm start and written out with S_j
@@ -853,16 +862,16 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
 #pragma unroll
         for (int y = 0; y < CT; ++y) acc[x][y] = 0.0;
 #pragma unroll 2
-      for (int r = 0; r < n; ++r) {
-        double u[RT], w[CT];
+      for (int r = 0; r < NP; r += 2) {
+        double2 u[RT], w[CT];
 #pragma unroll
-        for (int x = 0; x < RT; ++x) u[x] = Vt[(i0 + x) * NP + r];
+        for (int x = 0; x < RT; ++x) u[x] = *(const double2*)(Vt + (i0 + x) * NP + r);
 #pragma unroll
-        for (int y = 0; y < CT; ++y) w[y] = A[r * NP + k0 + y];
+        for (int y = 0; y < CT; ++y) w[y] = *(const double2*)(A + (k0 + y) * NP + r);
 #pragma unroll
         for (int x = 0; x < RT; ++x)
 #pragma unroll
-          for (int y = 0; y < CT; ++y) acc[x][y] = fma(u[x], w[y], acc[x][y]);
+          for (int y = 0; y < CT; ++y) acc[x][y] = fma(u[x].y, w[y].y, fma(u[x].x, w[y].x, acc[x][y]));
       }
     }
     __syncthreads();
@@ -896,7 +905,7 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
 }
 
 template <int NP>
-__global__ __launch_bounds__(EigWgShape<NP>::TPB, 4) void k_eig_wg(EigArgs a) {
+__global__ __launch_bounds__(EigWgShape<NP>::TPB, EigWgShape<NP>::WAVES) void k_eig_wg(EigArgs a) {
   body_eig_wg<NP>(a, blockIdx.x, blockIdx.y);
 }
 
@@ -2265,8 +2274,8 @@ QOC_MULTI_KERNEL(km_controls, kThreads, 1, CtlArgs, body_controls)
 QOC_MULTI_KERNEL(km_eig_wave4, 64, 2, EigArgs, body_eig_wave<4>)
 QOC_MULTI_KERNEL(km_eig_wave8, 64, 2, EigArgs, body_eig_wave<8>)
 QOC_MULTI_KERNEL(km_eig_wave16, 64, 2, EigArgs, body_eig_wave<16>)
-QOC_MULTI_KERNEL(km_eig_wg36, kThreads, 4, EigArgs, body_eig_wg<36>)
-QOC_MULTI_KERNEL(km_eig_wg64, 512, 4, EigArgs, body_eig_wg<64>)
+QOC_MULTI_KERNEL(km_eig_wg36, kThreads, EigWgShape<36>::WAVES, EigArgs, body_eig_wg<36>)
+QOC_MULTI_KERNEL(km_eig_wg64, 512, EigWgShape<64>::WAVES, EigArgs, body_eig_wg<64>)
 QOC_MULTI_KERNEL(km_eig_chunk, kThreads, 1, EigArgs, body_eig_chunk)
 QOC_MULTI_KERNEL(km_boundary, kThreads, 1, BndArgs, body_boundary)
 QOC_MULTI_KERNEL(km_forward_staged, kThreads, 2, SweepArgs, body_forward<kSweepRegs>)
