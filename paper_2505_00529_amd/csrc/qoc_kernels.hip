@@ -1135,17 +1135,49 @@ __device__ __forceinline__ void body_forward(const SweepArgs& a, int g, int b) {
         double2 acc[kTileRows];
 #pragma unroll
         for (int i = 0; i < kTileRows; ++i) acc[i] = make_double2(0.0, 0.0);
-#pragma unroll(MODE == kSweepRegs ? 1 : 4)
-        for (int r = 0; r < n; ++r) {
-          const double2 x = X[r * w + col];
+        if (ASYNC && (n & 1) == 0) {
+          // row-major O in LDS: two consecutive r of a row per 16-byte load
+          const double* Oc = Ob + cb * nn;
+#pragma unroll 2
+          for (int r = 0; r < n; r += 2) {
+            const double2 x0 = X[r * w + col], x1 = X[(r + 1) * w + col];
 #pragma unroll
-          for (int i = 0; i < kTileRows; ++i) {
-            const int p = p0 + i;
-            const double o = p < n ? (ASYNC ? Ob[cb * nn + (size_t)p * n + r]
-                                            : (STAGE ? Ob[r * n + p] : Og[(size_t)p * n + r]))
-                                   : 0.0;
-            acc[i].x = fma(o, x.x, acc[i].x);
-            acc[i].y = fma(o, x.y, acc[i].y);
+            for (int i = 0; i < kTileRows; ++i) {
+              const int p = p0 + i;
+              const double2 o = p < n ? *(const double2*)(Oc + p * n + r) : make_double2(0.0, 0.0);
+              acc[i].x = fma(o.x, x0.x, acc[i].x);
+              acc[i].y = fma(o.x, x0.y, acc[i].y);
+              acc[i].x = fma(o.y, x1.x, acc[i].x);
+              acc[i].y = fma(o.y, x1.y, acc[i].y);
+            }
+          }
+        } else if (MODE == kSweepRegs && (n & 3) == 0) {
+          // transposed O in LDS: the tile's four rows p0..p0+3 in two 16-byte loads
+#pragma unroll 2
+          for (int r = 0; r < n; ++r) {
+            const double2 x = X[r * w + col];
+            const double2 o01 = *(const double2*)(Ob + r * n + p0);
+            const double2 o23 = *(const double2*)(Ob + r * n + p0 + 2);
+            const double o[4] = {o01.x, o01.y, o23.x, o23.y};
+#pragma unroll
+            for (int i = 0; i < kTileRows; ++i) {
+              acc[i].x = fma(o[i], x.x, acc[i].x);
+              acc[i].y = fma(o[i], x.y, acc[i].y);
+            }
+          }
+        } else {
+#pragma unroll(MODE == kSweepRegs ? 1 : 4)
+          for (int r = 0; r < n; ++r) {
+            const double2 x = X[r * w + col];
+#pragma unroll
+            for (int i = 0; i < kTileRows; ++i) {
+              const int p = p0 + i;
+              const double o = p < n ? (ASYNC ? Ob[cb * nn + (size_t)p * n + r]
+                                              : (STAGE ? Ob[r * n + p] : Og[(size_t)p * n + r]))
+                                     : 0.0;
+              acc[i].x = fma(o, x.x, acc[i].x);
+              acc[i].y = fma(o, x.y, acc[i].y);
+            }
           }
         }
 #pragma unroll
@@ -1412,15 +1444,32 @@ __device__ __forceinline__ void body_backward(const SweepArgs& a, int g, int b) 
         double2 acc[kTileRows];
 #pragma unroll
         for (int i = 0; i < kTileRows; ++i) acc[i] = make_double2(0.0, 0.0);
-#pragma unroll(MODE == kSweepRegs ? 1 : 4)
-        for (int r = 0; r < n; ++r) {
-          const double2 x = X[r * w + col];
+        if (STAGE && (n & 3) == 0) {
+          // the tile's four rows p0..p0+3 of O^T (row r of O) in two 16-byte loads
+          const double* Oc = Ob + cb * nn;
+#pragma unroll 2
+          for (int r = 0; r < n; ++r) {
+            const double2 x = X[r * w + col];
+            const double2 o01 = *(const double2*)(Oc + r * n + p0);
+            const double2 o23 = *(const double2*)(Oc + r * n + p0 + 2);
+            const double o[4] = {o01.x, o01.y, o23.x, o23.y};
 #pragma unroll
-          for (int i = 0; i < kTileRows; ++i) {
-            const int p = p0 + i;
-            const double o = p < n ? (STAGE ? Ob[cb * nn + (size_t)r * n + p] : Og[(size_t)r * n + p]) : 0.0;
-            acc[i].x = fma(o, x.x, acc[i].x);
-            acc[i].y = fma(o, x.y, acc[i].y);
+            for (int i = 0; i < kTileRows; ++i) {
+              acc[i].x = fma(o[i], x.x, acc[i].x);
+              acc[i].y = fma(o[i], x.y, acc[i].y);
+            }
+          }
+        } else {
+#pragma unroll(MODE == kSweepRegs ? 1 : 4)
+          for (int r = 0; r < n; ++r) {
+            const double2 x = X[r * w + col];
+#pragma unroll
+            for (int i = 0; i < kTileRows; ++i) {
+              const int p = p0 + i;
+              const double o = p < n ? (STAGE ? Ob[cb * nn + (size_t)r * n + p] : Og[(size_t)r * n + p]) : 0.0;
+              acc[i].x = fma(o, x.x, acc[i].x);
+              acc[i].y = fma(o, x.y, acc[i].y);
+            }
           }
         }
 #pragma unroll
