@@ -505,8 +505,9 @@ struct EigWgShape<64> {
   static constexpr int WAVES = 4;
 };
 
-// Cross-lane moves within a wave by DPP (no LDS traffic): the value of lane + 1 and of lane - 1
-// (wave_shl:1 / wave_shr:1; lanes whose source is outside the wave keep `x`).
+// Cross-lane move within a wave by DPP control CTRL (no LDS traffic).  kDppFromNext and
+// kDppFromPrev give lane i the value of lane i + 1 and of lane i - 1 (wave_shl:1 / wave_shr:1;
+// lanes whose source is outside the wave keep `x`).
 constexpr int kDppFromNext = 0x130, kDppFromPrev = 0x138;
 template <int CTRL>
 __device__ __forceinline__ double dpp_move(double x) {
@@ -920,6 +921,17 @@ constexpr int kPrefetch = 16;   // doubles per thread per staged n x n matrix (n
 constexpr int kPrefetchSmall = 8;   // n*n <= 8*256: O and S double-buffered in LDS instead
 constexpr int kTileRows = 4;    // rows of the O product per thread (x 1 complex column)
 
+// Sum over each aligned group of four lanes (DPP quad permutations, no LDS traffic); every lane
+// of a group must be active.
+constexpr int kDppQuadXor1 = 0xB1, kDppQuadXor2 = 0x4E;   // quad_perm [1,0,3,2] and [2,3,0,1]
+__device__ __forceinline__ double2 quad_sum(double2 v) {
+  v.x += dpp_move<kDppQuadXor1>(v.x);
+  v.y += dpp_move<kDppQuadXor1>(v.y);
+  v.x += dpp_move<kDppQuadXor2>(v.x);
+  v.y += dpp_move<kDppQuadXor2>(v.y);
+  return v;
+}
+
 // Sweep variants: kSweepGlobal reads O and S from global memory inside the step (n > 64);
 // kSweepRegs stages them in LDS from registers loaded one step ahead (n <= 64); kSweepAsync
 // double-buffers them in LDS with direct global-to-LDS loads issued one step ahead (n <= 45).
@@ -1096,10 +1108,7 @@ __device__ __forceinline__ void body_forward(const SweepArgs& a, int g, int b) {
           acc.x = fma(sv, t.x, acc.x);
           acc.y = fma(sv, t.y, acc.y);
         }
-        acc.x += __shfl_xor(acc.x, 1);
-        acc.y += __shfl_xor(acc.y, 1);
-        acc.x += __shfl_xor(acc.x, 2);
-        acc.y += __shfl_xor(acc.y, 2);
+        acc = quad_sum(acc);
         if (part == 0) {
           const double2 hp = c_mul(hh[p], acc);
           yv[p] = make_double2(a.dt * hp.y, -a.dt * hp.x);   // -i dt * hp
@@ -1382,10 +1391,7 @@ __device__ __forceinline__ void body_backward(const SweepArgs& a, int g, int b) 
         acc.x = fma(sv, t.x, acc.x);
         acc.y = fma(sv, t.y, acc.y);
       }
-      acc.x += __shfl_xor(acc.x, 1);
-      acc.y += __shfl_xor(acc.y, 1);
-      acc.x += __shfl_xor(acc.x, 2);
-      acc.y += __shfl_xor(acc.y, 2);
+      acc = quad_sum(acc);
       if (part == 0) {
         const double2 hp = c_mul(hh[p], acc);
         zv[p] = make_double2(-a.dt * hp.y, a.dt * hp.x);   // i dt * hp
