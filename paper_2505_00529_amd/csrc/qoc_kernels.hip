@@ -937,11 +937,23 @@ __device__ __forceinline__ double2 quad_sum(double2 v) {
 // double-buffers them in LDS with direct global-to-LDS loads issued one step ahead (n <= 45).
 constexpr int kSweepGlobal = 0, kSweepRegs = 1, kSweepAsync = 2;
 
-// Copy `count` doubles from global memory to LDS with direct global-to-LDS dword loads (each
-// lane moves one dword; wave w takes every (waves)-th 64-dword segment).  The caller waits for
-// completion (vmcnt) and synchronises the workgroup before the data is read.
+// Copy `count` doubles from global memory to LDS with direct global-to-LDS loads: 16 bytes per
+// lane when both ends are 16-byte aligned and count is even (lane l of a load fills bytes
+// 16 l .. 16 l + 15 after the load's LDS base), otherwise one dword per lane.  Wave w takes
+// every (waves)-th 64-lane segment.  The caller waits for completion (vmcnt) and synchronises
+// the workgroup before the data is read.
 __device__ __forceinline__ void lds_copy_async(double* dst, const double* src, int count) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (((count & 1) | (((uintptr_t)src | (uintptr_t)dst) & 15)) == 0) {
+    const int chunks = count / 2;
+    for (int seg = wv * 64; seg < chunks; seg += kThreads) {
+      const int d = seg + lane;
+      if (d < chunks)
+        __builtin_amdgcn_global_load_lds((const void*)(src + 2 * d),
+                                         (__attribute__((address_space(3))) void*)(dst + 2 * seg), 16, 0, 0);
+    }
+    return;
+  }
   const int dwords = 2 * count;
   for (int seg = wv * 64; seg < dwords; seg += kThreads) {
     const int d = seg + lane;
@@ -1144,16 +1156,16 @@ __device__ __forceinline__ void body_forward(const SweepArgs& a, int g, int b) {
         double2 acc[kTileRows];
 #pragma unroll
         for (int i = 0; i < kTileRows; ++i) acc[i] = make_double2(0.0, 0.0);
-        if (ASYNC && (n & 1) == 0) {
-          // row-major O in LDS: two consecutive r of a row per 16-byte load
-          const double* Oc = Ob + cb * nn;
+        if (ASYNC && (n & 3) == 0) {
+          // row-major O in LDS: two consecutive r of a row per 16-byte load (every tile row
+          // exists when n is a multiple of the tile height)
+          const double* Oc = Ob + cb * nn + p0 * n;
 #pragma unroll 2
           for (int r = 0; r < n; r += 2) {
             const double2 x0 = X[r * w + col], x1 = X[(r + 1) * w + col];
 #pragma unroll
             for (int i = 0; i < kTileRows; ++i) {
-              const int p = p0 + i;
-              const double2 o = p < n ? *(const double2*)(Oc + p * n + r) : make_double2(0.0, 0.0);
+              const double2 o = *(const double2*)(Oc + i * n + r);
               acc[i].x = fma(o.x, x0.x, acc[i].x);
               acc[i].y = fma(o.x, x0.y, acc[i].y);
               acc[i].x = fma(o.y, x1.x, acc[i].x);
