@@ -175,18 +175,19 @@ __device__ __forceinline__ double block_max(double v, double* red) {
   return r;
 }
 
-// Wave-level (64-lane) reductions.
-__device__ __forceinline__ double wave_sum(double v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-__device__ __forceinline__ double wave_max(double v) {
-  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
-  return v;
-}
-__device__ __forceinline__ double wave_min(double v) {
-  for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
-  return v;
+// Cross-lane move within a wave by DPP control CTRL (no LDS traffic).  kDppFromNext and
+// kDppFromPrev give lane i the value of lane i + 1 and of lane i - 1 (wave_shl:1 / wave_shr:1;
+// lanes whose source is outside the wave keep `x`); the quad permutations exchange lanes
+// i ^ 1 and i ^ 2 within groups of four; the mirrors reverse each half row (8 lanes) and each
+// row (16 lanes).
+constexpr int kDppFromNext = 0x130, kDppFromPrev = 0x138;
+constexpr int kDppQuadXor1 = 0xB1, kDppQuadXor2 = 0x4E;   // quad_perm [1,0,3,2] and [2,3,0,1]
+constexpr int kDppRowHalfMirror = 0x141, kDppRowMirror = 0x140;
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(__double2loint(x), __double2loint(x), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(__double2hiint(x), __double2hiint(x), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
 }
 // Broadcast lane `src` (wave-uniform) of a double.
 __device__ __forceinline__ double readlane_d(double v, int src) {
@@ -194,6 +195,33 @@ __device__ __forceinline__ double readlane_d(double v, int src) {
   const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
   return __hiloint2double(hi, lo);
 }
+
+// Wave-level (64-lane) reductions, every lane receiving the result: DPP butterflies within
+// each row of 16 lanes, then the four row results read out.  All 64 lanes must be active.
+template <typename Op>
+__device__ __forceinline__ double wave_reduce(double v, Op op) {
+  v = op(v, dpp_move<kDppQuadXor1>(v));
+  v = op(v, dpp_move<kDppQuadXor2>(v));
+  v = op(v, dpp_move<kDppRowHalfMirror>(v));
+  v = op(v, dpp_move<kDppRowMirror>(v));
+  return op(op(readlane_d(v, 0), readlane_d(v, 16)), op(readlane_d(v, 32), readlane_d(v, 48)));
+}
+__device__ __forceinline__ double wave_sum(double v) {
+  return wave_reduce(v, [](double x, double y) { return x + y; });
+}
+__device__ __forceinline__ double wave_max(double v) {
+  return wave_reduce(v, [](double x, double y) { return fmax(x, y); });
+}
+__device__ __forceinline__ double wave_min(double v) {
+  return wave_reduce(v, [](double x, double y) { return fmin(x, y); });
+}
+// Sum over each aligned group of four lanes (all four active).
+__device__ __forceinline__ double quad_sum(double v) {
+  v += dpp_move<kDppQuadXor1>(v);
+  v += dpp_move<kDppQuadXor2>(v);
+  return v;
+}
+__device__ __forceinline__ double2 quad_sum(double2 v) { return make_double2(quad_sum(v.x), quad_sum(v.y)); }
 
 // Round-robin ("circle") pairing of np players (np even) in round r of np-1: player np-1
 // meets r; the others pair as (r+k, r-k) mod (np-1).  Every unordered pair meets once per

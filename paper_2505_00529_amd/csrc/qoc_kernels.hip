@@ -505,17 +505,6 @@ struct EigWgShape<64> {
   static constexpr int WAVES = 4;
 };
 
-// Cross-lane move within a wave by DPP control CTRL (no LDS traffic).  kDppFromNext and
-// kDppFromPrev give lane i the value of lane i + 1 and of lane i - 1 (wave_shl:1 / wave_shr:1;
-// lanes whose source is outside the wave keep `x`).
-constexpr int kDppFromNext = 0x130, kDppFromPrev = 0x138;
-template <int CTRL>
-__device__ __forceinline__ double dpp_move(double x) {
-  const int lo = __builtin_amdgcn_update_dpp(__double2loint(x), __double2loint(x), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(__double2hiint(x), __double2hiint(x), CTRL, 0xF, 0xF, false);
-  return __hiloint2double(hi, lo);
-}
-
 // Slot that slot x moves to in the circle shift after a round.
 template <int NP>
 __host__ __device__ constexpr int slot_next(int x) {
@@ -920,17 +909,6 @@ __global__ __launch_bounds__(EigWgShape<NP>::TPB, EigWgShape<NP>::WAVES) void k_
 constexpr int kPrefetch = 16;   // doubles per thread per staged n x n matrix (n*n <= 16*256)
 constexpr int kPrefetchSmall = 8;   // n*n <= 8*256: O and S double-buffered in LDS instead
 constexpr int kTileRows = 4;    // rows of the O product per thread (x 1 complex column)
-
-// Sum over each aligned group of four lanes (DPP quad permutations, no LDS traffic); every lane
-// of a group must be active.
-constexpr int kDppQuadXor1 = 0xB1, kDppQuadXor2 = 0x4E;   // quad_perm [1,0,3,2] and [2,3,0,1]
-__device__ __forceinline__ double2 quad_sum(double2 v) {
-  v.x += dpp_move<kDppQuadXor1>(v.x);
-  v.y += dpp_move<kDppQuadXor1>(v.y);
-  v.x += dpp_move<kDppQuadXor2>(v.x);
-  v.y += dpp_move<kDppQuadXor2>(v.y);
-  return v;
-}
 
 // Sweep variants: kSweepGlobal reads O and S from global memory inside the step (n > 64);
 // kSweepRegs stages them in LDS from registers loaded one step ahead (n <= 64); kSweepAsync
@@ -1429,15 +1407,18 @@ __device__ __forceinline__ void body_backward(const SweepArgs& a, int g, int b) 
         if (a.hvp) a.e[vs] = le;
       }
     }
-    if (!a.hvp && a.K && tid >= 64 && tid - 64 < ncol) {
-      const int col = tid - 64;
-      double acc = 0.0;
-#pragma unroll(MODE == kSweepRegs ? 1 : 4)
-      for (int p = 0; p < n; ++p) {
-        const double2 xi = cur[p * w + 1 + col];
-        acc += xi.x * yv[p].x + xi.y * yv[p].y;
+    if (!a.hvp && a.K) {
+      // waves 1.. : four lanes per column, each summing every fourth p
+      for (int t = tid - 64; t >= 0 && t < 4 * ncol; t += kThreads - 64) {
+        const int col = t >> 2, part = t & 3;
+        double acc = 0.0;
+        for (int p = part; p < n; p += 4) {
+          const double2 xi = cur[p * w + 1 + col];
+          acc += xi.x * yv[p].x + xi.y * yv[p].y;
+        }
+        acc = quad_sum(acc);
+        if (part == 0) a.K[vs * a.P + c0 + col] = acc;
       }
-      a.K[vs * a.P + c0 + col] = acc;
     }
     if (j >= 1) {
       {
@@ -1712,7 +1693,7 @@ __device__ __forceinline__ void body_sterm(const StermArgs& a, int bx, int nblk)
   }
 }
 
-__global__ __launch_bounds__(kThreads) void k_sterm_wave(StermArgs a) { body_sterm(a, blockIdx.x, gridDim.x); }
+__global__ __launch_bounds__(kThreads, 2) void k_sterm_wave(StermArgs a) { body_sterm(a, blockIdx.x, gridDim.x); }
 
 // ---------------------------------------------------------------- assembly
 
@@ -2352,7 +2333,7 @@ QOC_MULTI_KERNEL(km_terminal, kThreads, 1, TermArgs, body_terminal)
 QOC_MULTI_KERNEL(km_backward_staged, kThreads, 2, SweepArgs, body_backward<kSweepRegs>)
 QOC_MULTI_KERNEL(km_backward_small, kThreads, 3, SweepArgs, body_backward<kSweepAsync>)
 QOC_MULTI_KERNEL(km_backward_global, kThreads, 3, SweepArgs, body_backward<kSweepGlobal>)
-QOC_MULTI_KERNEL(km_sterm, kThreads, 1, StermArgs, body_sterm)
+QOC_MULTI_KERNEL(km_sterm, kThreads, 2, StermArgs, body_sterm)
 QOC_MULTI_KERNEL(km_assemble, kThreads, 1, AsmArgs, body_assemble)
 #undef QOC_MULTI_KERNEL
 
