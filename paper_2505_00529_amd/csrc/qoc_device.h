@@ -27,6 +27,28 @@ __device__ __forceinline__ double2 phase(double x, double dt) {
   return make_double2(c, -s);
 }
 
+// sin(u)/u for |u| >= 1/4, out of line: its constants then stay out of the register budget of
+// the (unrolled) loops that call sinc, where this branch is rare.
+__device__ __attribute__((noinline)) double sinc_wide(double u) { return sin(u) / u; }
+
+// Coefficients of the even Taylor series of sin(u)/u in -u^2, highest first: 1/13!, 1/11!, ...,
+// 1/3!, 1.
+constexpr int kSincTerms = 7;
+__device__ constexpr double kSincCoef[kSincTerms] = {1.0 / 6227020800.0, 1.0 / 39916800.0, 1.0 / 362880.0,
+                                                     1.0 / 5040.0, 1.0 / 120.0, 1.0 / 6.0, 1.0};
+// sinc with the series coefficients read from `coef` (a copy of kSincCoef, e.g. in LDS): keeps
+// the constants out of the registers of kernels whose loops would otherwise hold them.
+__device__ __forceinline__ double sinc_table(double u, const double* coef) {
+  if (fabs(u) < 0.25) {
+    const double u2 = u * u;
+    double r = coef[0];
+#pragma unroll
+    for (int k = 1; k < kSincTerms; ++k) r = fma(r, -u2, coef[k]);
+    return r;
+  }
+  return sinc_wide(u);
+}
+
 // sin(u)/u, accurate for all u.  |u| < 1/4: the even Taylor series through u^12 (the first
 // omitted term is below 3e-21); otherwise sin(u)/u.
 __device__ __forceinline__ double sinc(double u) {
@@ -40,7 +62,7 @@ __device__ __forceinline__ double sinc(double u) {
     r = fma(r, -u2, 1.0 / 6.0);                 // 1/3!
     return fma(r, -u2, 1.0);
   }
-  return sin(u) / u;
+  return sinc_wide(u);
 }
 
 // 1/sqrt(x) and 1/x for positive normal x from the hardware estimates refined by two Newton
@@ -214,6 +236,20 @@ __device__ __forceinline__ double wave_max(double v) {
 }
 __device__ __forceinline__ double wave_min(double v) {
   return wave_reduce(v, [](double x, double y) { return fmin(x, y); });
+}
+// The same reductions through LDS permutes (fewer registers; for kernels whose reductions are
+// off the critical path and whose register budget is tight).
+__device__ __forceinline__ double wave_sum_lds(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max_lds(double v) {
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
+__device__ __forceinline__ double wave_min_lds(double v) {
+  for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
+  return v;
 }
 // Sum over each aligned group of four lanes (all four active).
 __device__ __forceinline__ double quad_sum(double v) {

@@ -505,6 +505,10 @@ struct EigWgShape<64> {
   static constexpr int WAVES = 4;
 };
 
+// Largest |F_ik| / |d_k - d_i| over the off-diagonal part F of the current A = diag(d) + F at
+// which the remaining Jacobi sweeps are replaced by the first-order eigenvector correction.
+constexpr double kJacobiFinishRatio = 1e-8;
+
 // Slot that slot x moves to in the circle shift after a round.
 template <int NP>
 __host__ __device__ constexpr int slot_next(int x) {
@@ -539,7 +543,8 @@ __device__ __forceinline__ void rotate_block(double a00, double a01, double a10,
 
 template <int NP>
 __host__ __device__ constexpr size_t eig_wg_lds_doubles() {
-  return (size_t)(EigWgShape<NP>::VP_LDS ? 3 : 2) * NP * NP + 4 * (NP / 2) + NP + EigWgShape<NP>::TPB / 64;
+  return (size_t)(EigWgShape<NP>::VP_LDS ? 3 : 2) * NP * NP + 4 * (NP / 2) + NP + EigWgShape<NP>::TPB / 64 +
+         kSincTerms;
 }
 
 // Sum / max over a workgroup of TPB threads from the wave partials (red: TPB/64 doubles of LDS).
@@ -591,11 +596,13 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
   double2* rot = (double2*)(Vt + (VP_LDS ? 2 : 1) * NP * NP);  // 2 x H rotations (c, s)
   double* lamv = (double*)(rot + 2 * H);         // eigenvalues
   double* red = lamv + NP;                       // wave partials
+  double* sinc_c = red + TPB / 64;               // sinc series coefficients
   const int tid = threadIdx.x;
   const int n = a.n, nt = a.nt;
   const int j0 = a.j_base + c * a.chunk;
   const int j1 = min(a.j_base + a.nsteps, j0 + a.chunk);
   if (j0 >= j1) return;
+  if (tid < kSincTerms) sinc_c[tid] = kSincCoef[tid];
   const double* fb = a.f + (size_t)b * nt;
   const size_t nn = (size_t)n * n;
   double* vpg = VP_LDS ? nullptr : a.gscratch + ((size_t)b * a.nchunks + c) * NP * NP;
@@ -677,13 +684,21 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
     for (int idx = tid; idx < NP * NP; idx += TPB) loc = fma(A[idx], A[idx], loc);
     const double tol = a.tol_rel * sqrt(wg_sum<TPB>(loc, red));
     int cur = 0, rb = 0;                           // current A buffer and rotation buffer
+    bool finished = false;                         // V_j already in Vt (first-order finish)
 #pragma unroll 1
     for (int sweep = 0;; ++sweep) {
-      const double* Ac = cur ? Vt : A;
-      double off = 0.0;
+      double* Ac = cur ? Vt : A;
+      // sweep boundary: slot order is the index order
+      if (tid < NP) lamv[tid] = Ac[tid * NP + tid];
+      __syncthreads();
+      double off = 0.0, rat = 0.0;
       for (int idx = tid; idx < NP * NP; idx += TPB) {
         const int i = idx / NP, k = idx - (idx / NP) * NP;
-        if (i < k) off = fmax(off, fabs(Ac[idx]));
+        if (i < k) {
+          const double v = fabs(Ac[idx]);
+          off = fmax(off, v);
+          if (v != 0.0) rat = fmax(rat, v / fabs(lamv[k] - lamv[i]));   // inf for equal diagonals
+        }
       }
       off = wg_max<TPB>(off, red);
       if (off <= tol) {
@@ -695,6 +710,68 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
       }
       if (sweep >= a.max_sweeps) {
         if (tid == 0) atomicOr(a.status, kStatusNoConv);
+        break;
+      }
+      rat = wg_max<TPB>(rat, red);
+      if (rat <= kJacobiFinishRatio) {
+        // First-order finish: with A = diag(d) + F and every |F_ik| <= 1e-8 |d_k - d_i|, the
+        // eigenvectors are the columns of I + E, E_ik = F_ik / (d_k - d_i) (antisymmetric), to
+        // within terms of order |E|^2, and the eigenvalues are d to within |F| |E|.  So
+        // V_j = V (I + E) and lambda_j = d replace the remaining sweeps.
+        // E^T goes into A's buffer in place (Ac[k][i] = E_ik), V into the other one.
+        for (int idx = tid; idx < NP * NP; idx += TPB) {
+          const int i = idx / NP, k = idx - (idx / NP) * NP;
+          if (i < k) {
+            const double f = Ac[idx];
+            const double e = f == 0.0 ? 0.0 : f / (lamv[k] - lamv[i]);
+            Ac[k * NP + i] = e;
+            Ac[idx] = -e;
+          } else if (i == k) {
+            Ac[idx] = 0.0;
+          }
+        }
+        double* Vo = cur ? A : Vt;
+        if (v_on) {
+#pragma unroll
+          for (int k = 0; k < S; ++k) {
+            const int K = vseg * S + k;
+            Vo[(2 * K) * NP + vrow] = ve[k];
+            Vo[(2 * K + 1) * NP + vrow] = vo[k];
+          }
+        }
+        __syncthreads();
+        // tile (x, y): column k = i0 + x, row i = k0 + y of V_j = V + V E
+        double acc[RT][CT];
+        if (has_tile) {
+#pragma unroll
+          for (int x = 0; x < RT; ++x)
+#pragma unroll
+            for (int y = 0; y < CT; ++y) acc[x][y] = Vo[(i0 + x) * NP + k0 + y];
+#pragma unroll 2
+          for (int r = 0; r < NP; r += 2) {
+            double2 u[RT], w[CT];
+#pragma unroll
+            for (int x = 0; x < RT; ++x) u[x] = *(const double2*)(Ac + (i0 + x) * NP + r);   // E_{r,k}, E_{r+1,k}
+#pragma unroll
+            for (int y = 0; y < CT; ++y) w[y] = make_double2(Vo[r * NP + k0 + y], Vo[(r + 1) * NP + k0 + y]);
+#pragma unroll
+            for (int x = 0; x < RT; ++x)
+#pragma unroll
+              for (int y = 0; y < CT; ++y) acc[x][y] = fma(u[x].y, w[y].y, fma(u[x].x, w[y].x, acc[x][y]));
+          }
+        }
+        __syncthreads();
+        if (has_tile) {
+#pragma unroll
+          for (int x = 0; x < RT; ++x)
+#pragma unroll
+            for (int y = 0; y < CT; ++y) Vt[(i0 + x) * NP + k0 + y] = acc[x][y];
+        }
+        if (tid == 0 && a.stats) {
+          atomicAdd(a.stats, 1ull);
+          atomicAdd(a.stats + 1, (unsigned long long)sweep);
+        }
+        finished = true;
         break;
       }
       if (sweep == 0) {
@@ -774,10 +851,8 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
         __syncthreads();
       }
     }
-    // sweep boundary: slot order is the index order
-    if (tid < NP) lamv[tid] = (cur ? Vt : A)[tid * NP + tid];
-    __syncthreads();
-    if (v_on) {
+    // lambda_j is in lamv (set at the last sweep boundary); V_j to Vt
+    if (!finished && v_on) {
 #pragma unroll
       for (int k = 0; k < S; ++k) {
         const int K = vseg * S + k;
@@ -875,7 +950,7 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
           if (i < n && k < n) {
             if (a.store_derivs) {
               a.mt[step * nn + (size_t)i * n + k] = acc[x][y];
-              a.sm[step * nn + (size_t)i * n + k] = sinc(0.5 * a.dt * (lamv[i] - lamv[k])) * acc[x][y];
+              a.sm[step * nn + (size_t)i * n + k] = sinc_table(0.5 * a.dt * (lamv[i] - lamv[k]), sinc_c) * acc[x][y];
             }
           }
         }
@@ -1562,7 +1637,7 @@ __device__ double sterm_pairs_wave(const StermArgs& a, size_t es, size_t vs, int
     if (p != q) wgt = c_add(wgt, c_cmul(mu[q], at[p]));
     loc += wgt.x * tpq.x - wgt.y * tpq.y;
   }
-  return wave_sum(loc);
+  return wave_sum_lds(loc);
 }
 
 // Tasks bx * waves + wave, stepping nblk * waves: block bx of nblk covering all tasks.
@@ -1594,8 +1669,8 @@ __device__ __forceinline__ void body_sterm(const StermArgs& a, int bx, int nblk)
         hi = fmax(hi, lv[e]);
       }
     }
-    lo = wave_min(lo);
-    hi = wave_max(hi);
+    lo = wave_min_lds(lo);
+    hi = wave_max_lds(hi);
     const double m0 = 0.5 * (lo + hi);
     const double del = 0.5 * a.dt * (hi - lo);
     // number of terms: first omitted term bounded by (n+2)(n+3) del^(n+1) / (n+3)!
@@ -1685,7 +1760,7 @@ __device__ __forceinline__ void body_sterm(const StermArgs& a, int bx, int nblk)
           }
         }
       }
-      double2 tot = make_double2(wave_sum(contrib.x), wave_sum(contrib.y));
+      double2 tot = make_double2(wave_sum_lds(contrib.x), wave_sum_lds(contrib.y));
       tot = c_mul(phase(m0, a.dt), tot);
       sval = 2.0 * tot.x;
     }
