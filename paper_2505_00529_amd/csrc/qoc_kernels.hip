@@ -691,13 +691,15 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
       // sweep boundary: slot order is the index order
       if (tid < NP) lamv[tid] = Ac[tid * NP + tid];
       __syncthreads();
-      double off = 0.0, rat = 0.0;
+      // largest off-diagonal entry, and (after the first sweep) largest excess of |F_ik| over the
+      // finish bound
+      double off = 0.0, excess = -1.0;
       for (int idx = tid; idx < NP * NP; idx += TPB) {
         const int i = idx / NP, k = idx - (idx / NP) * NP;
         if (i < k) {
           const double v = fabs(Ac[idx]);
           off = fmax(off, v);
-          if (v != 0.0) rat = fmax(rat, v / fabs(lamv[k] - lamv[i]));   // inf for equal diagonals
+          if (sweep > 0) excess = fmax(excess, v - kJacobiFinishRatio * fabs(lamv[k] - lamv[i]));
         }
       }
       off = wg_max<TPB>(off, red);
@@ -712,8 +714,7 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
         if (tid == 0) atomicOr(a.status, kStatusNoConv);
         break;
       }
-      rat = wg_max<TPB>(rat, red);
-      if (rat <= kJacobiFinishRatio) {
+      if (sweep > 0 && wg_max<TPB>(excess, red) <= 0.0) {
         // First-order finish: with A = diag(d) + F and every |F_ik| <= 1e-8 |d_k - d_i|, the
         // eigenvectors are the columns of I + E, E_ik = F_ik / (d_k - d_i) (antisymmetric), to
         // within terms of order |E|^2, and the eigenvalues are d to within |F| |E|.  So
