@@ -740,34 +740,6 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
             Vo[(2 * K + 1) * NP + vrow] = vo[k];
           }
         }
-        __syncthreads();
-        // tile (x, y): column k = i0 + x, row i = k0 + y of V_j = V + V E
-        double acc[RT][CT];
-        if (has_tile) {
-#pragma unroll
-          for (int x = 0; x < RT; ++x)
-#pragma unroll
-            for (int y = 0; y < CT; ++y) acc[x][y] = Vo[(i0 + x) * NP + k0 + y];
-#pragma unroll 2
-          for (int r = 0; r < NP; r += 2) {
-            double2 u[RT], w[CT];
-#pragma unroll
-            for (int x = 0; x < RT; ++x) u[x] = *(const double2*)(Ac + (i0 + x) * NP + r);   // E_{r,k}, E_{r+1,k}
-#pragma unroll
-            for (int y = 0; y < CT; ++y) w[y] = make_double2(Vo[r * NP + k0 + y], Vo[(r + 1) * NP + k0 + y]);
-#pragma unroll
-            for (int x = 0; x < RT; ++x)
-#pragma unroll
-              for (int y = 0; y < CT; ++y) acc[x][y] = fma(u[x].y, w[y].y, fma(u[x].x, w[y].x, acc[x][y]));
-          }
-        }
-        __syncthreads();
-        if (has_tile) {
-#pragma unroll
-          for (int x = 0; x < RT; ++x)
-#pragma unroll
-            for (int y = 0; y < CT; ++y) Vt[(i0 + x) * NP + k0 + y] = acc[x][y];
-        }
         if (tid == 0 && a.stats) {
           atomicAdd(a.stats, 1ull);
           atomicAdd(a.stats + 1, (unsigned long long)sweep);
@@ -853,7 +825,39 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
       }
     }
     // lambda_j is in lamv (set at the last sweep boundary); V_j to Vt
-    if (!finished && v_on) {
+    if (finished) {
+      // V_j = V + V E from V (in Vo) and E^T (in Ac): tile (x, y) is column k = i0 + x, row
+      // i = k0 + y
+      const double* Ac = cur ? Vt : A;
+      const double* Vo = cur ? A : Vt;
+      __syncthreads();
+      double acc[RT][CT];
+      if (has_tile) {
+#pragma unroll
+        for (int x = 0; x < RT; ++x)
+#pragma unroll
+          for (int y = 0; y < CT; ++y) acc[x][y] = Vo[(i0 + x) * NP + k0 + y];
+#pragma unroll 2
+        for (int r = 0; r < NP; r += 2) {
+          double2 u[RT], w[CT];
+#pragma unroll
+          for (int x = 0; x < RT; ++x) u[x] = *(const double2*)(Ac + (i0 + x) * NP + r);   // E_{r,k}, E_{r+1,k}
+#pragma unroll
+          for (int y = 0; y < CT; ++y) w[y] = make_double2(Vo[r * NP + k0 + y], Vo[(r + 1) * NP + k0 + y]);
+#pragma unroll
+          for (int x = 0; x < RT; ++x)
+#pragma unroll
+            for (int y = 0; y < CT; ++y) acc[x][y] = fma(u[x].y, w[y].y, fma(u[x].x, w[y].x, acc[x][y]));
+        }
+      }
+      __syncthreads();
+      if (has_tile) {
+#pragma unroll
+        for (int x = 0; x < RT; ++x)
+#pragma unroll
+          for (int y = 0; y < CT; ++y) Vt[(i0 + x) * NP + k0 + y] = acc[x][y];
+      }
+    } else if (v_on) {
 #pragma unroll
       for (int k = 0; k < S; ++k) {
         const int K = vseg * S + k;
