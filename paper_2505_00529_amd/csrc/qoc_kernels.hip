@@ -1081,7 +1081,10 @@ __device__ __forceinline__ void body_forward(const SweepArgs& a, int g, int b) {
   const size_t vb0 = (size_t)b * nt;                 // per-step vectors
   const size_t eb0 = (size_t)b * a.eig_stride;       // eigen-data
   const int xw = 1 + a.P;
-  const int ph_t = tid - (kThreads - 128);           // waves 2 and 3 evaluate the step's phases
+  // the step's phases are evaluated by the last wave (n <= 64) or the last two
+  const int ph_t = tid - (kThreads - (n <= 64 ? 64 : 128));
+  // FOLD: the next step's staged data goes in during the O X product, which reads none of it
+  constexpr bool FOLD = MODE != kSweepRegs;
 
   auto load_step = [&](int j, StepStage<MODE>& st, int buf) {
     const size_t es = eb0 + (j - a.eig_j0);
@@ -1274,9 +1277,12 @@ __device__ __forceinline__ void body_forward(const SweepArgs& a, int g, int b) {
         }
       }
     }
-    __syncthreads();
-    if (j + 1 < a.j_end) {
+    if (FOLD && j + 1 < a.j_end) {
       if (ASYNC) wait_vm_all();
+      commit_step(nx);
+    }
+    __syncthreads();
+    if (!FOLD && j + 1 < a.j_end) {
       commit_step(nx);
       __syncthreads();
     }
@@ -1377,7 +1383,10 @@ __device__ __forceinline__ void body_backward(const SweepArgs& a, int g, int b) 
   const double* Fb = a.F + (size_t)b * a.f_bstride;
   const size_t vb0 = (size_t)b * nt;
   const size_t eb0 = (size_t)b * a.eig_stride;
-  const int ph_t = tid - (kThreads - 128);   // waves 2 and 3 evaluate the step's phases
+  // the step's phases are evaluated by the last wave (n <= 64) or the last two
+  const int ph_t = tid - (kThreads - (n <= 64 ? 64 : 128));
+  // FOLD: the next step's staged data goes in during the O^T X product, which reads none of it
+  constexpr bool FOLD = MODE != kSweepRegs;
 
   // O_{jj-1} for step jj >= 1: inside the range from the eigen-data, at the range start from o_in
   auto o_prev = [&](int jj) -> const double* {
@@ -1555,11 +1564,14 @@ __device__ __forceinline__ void body_backward(const SweepArgs& a, int g, int b) 
         for (int i = 0; i < kTileRows; ++i)
           if (p0 + i < n) cur[(p0 + i) * w + col] = acc[i];
       }
-      __syncthreads();
-      if (j > a.j_begin) {
+      if (FOLD && j > a.j_begin) {
         if (ASYNC) wait_vm_all();
         commit_step(nx);
-      } else if (a.bout) {
+      }
+      __syncthreads();
+      if (!FOLD && j > a.j_begin) {
+        commit_step(nx);
+      } else if (j == a.j_begin && a.bout) {
         // state leaving the range, in basis j_begin - 1
         for (int idx = tid; idx < n * w; idx += kThreads) {
           const int p = idx / w, col = idx - p * w;
@@ -1567,7 +1579,9 @@ __device__ __forceinline__ void body_backward(const SweepArgs& a, int g, int b) 
         }
       }
     }
-    __syncthreads();
+    // (with FOLD the barrier after the product already orders this step's reads before the
+    // next step's writes)
+    if (!FOLD || j < 1) __syncthreads();
   }
 }
 
