@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "qoc_device.h"
 #include "qoc_internal.h"
@@ -757,11 +758,13 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
         }
         __syncthreads();
       }
-#pragma unroll 1
-      for (int r = 0; r < NP - 1; ++r) {
-        const double* Ar = cur ? Vt : A;
-        double* An = cur ? A : Vt;
-        const double2* R = rot + rb * H;
+      // One round with the current A buffer and rotation buffer PAR (they flip together every
+      // round); instantiated for both parities so that every LDS address is a fixed offset.
+      auto round = [&](auto par) {
+        constexpr int PAR = decltype(par)::value;
+        const double* Ar = PAR ? Vt : A;
+        double* An = PAR ? A : Vt;
+        const double2* R = rot + PAR * H;
 #pragma unroll
         for (int t = 0; t < BPT; ++t) {
           const int I = bI[t];
@@ -797,7 +800,7 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
           const double e = rotate_entry(r0.x, r0.y, r1.x, r1.y, uI, uK);
           double cc, ss;
           jacobi_rotation_nobranch(es < os ? dI : dK, es < os ? dK : dI, e, cc, ss);
-          rot[(rb ^ 1) * H + kr] = make_double2(cc, ss);
+          rot[(PAR ^ 1) * H + kr] = make_double2(cc, ss);
         }
         if (v_wave) {
           double e[S], o[S];
@@ -819,10 +822,28 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
 #pragma unroll
           for (int k = 1; k < S; ++k) vo[k] = o[k - 1];
         }
-        cur ^= 1;
-        rb ^= 1;
         __syncthreads();
+      };
+      const std::integral_constant<int, 0> par0;
+      const std::integral_constant<int, 1> par1;
+      // NP - 1 (odd) rounds: the parity flips over a sweep
+      if (cur == 0) {
+#pragma unroll 1
+        for (int r = 0; r + 1 < NP - 1; r += 2) {
+          round(par0);
+          round(par1);
+        }
+        round(par0);
+      } else {
+#pragma unroll 1
+        for (int r = 0; r + 1 < NP - 1; r += 2) {
+          round(par1);
+          round(par0);
+        }
+        round(par1);
       }
+      cur ^= 1;
+      rb ^= 1;
     }
     // lambda_j is in lamv (set at the last sweep boundary); V_j to Vt
     if (finished) {
