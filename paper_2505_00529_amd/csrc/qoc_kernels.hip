@@ -970,16 +970,28 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
 #pragma unroll
       for (int x = 0; x < RT; ++x)
 #pragma unroll
-        for (int y = 0; y < CT; ++y) {
-          const int i = i0 + x, k = k0 + y;
-          A[i * NP + k] = acc[x][y];
-          if (i < n && k < n) {
-            if (a.store_derivs) {
-              a.mt[step * nn + (size_t)i * n + k] = acc[x][y];
-              a.sm[step * nn + (size_t)i * n + k] = sinc_table(0.5 * a.dt * (lamv[i] - lamv[k]), sinc_c) * acc[x][y];
-            }
-          }
+        for (int y = 0; y < CT; ++y) A[(i0 + x) * NP + k0 + y] = acc[x][y];
+    }
+    if (a.store_derivs) {
+      // M~_j and S_j from LDS in one coalesced pass (row i, column k of entry idx, stepped
+      // without divisions)
+      __syncthreads();
+      double* mt = a.mt + step * nn;
+      double* sm = a.sm + step * nn;
+      const int dr = TPB / n, dc = TPB - (TPB / n) * n;
+      int i = tid / n, k = tid - (tid / n) * n;
+#pragma unroll 1
+      for (int idx = tid; idx < (int)nn; idx += TPB) {
+        const double v = A[i * NP + k];
+        mt[idx] = v;
+        sm[idx] = sinc_table(0.5 * a.dt * (lamv[i] - lamv[k]), sinc_c) * v;
+        i += dr;
+        k += dc;
+        if (k >= n) {
+          k -= n;
+          ++i;
         }
+      }
     }
     // eigenvalues, V_j for the next step's overlap, and the chunk ends
     if (tid < n) a.lam[step * n + tid] = lamv[tid];
