@@ -47,6 +47,10 @@ CASES = [
     ("tiny-odd5-ragged", "tiny", dict(n=5, nt=37, k=3), 0.3),
     ("molecule-short", "molecule", dict(nt=300), 0.1),
     ("warm-short", "warm", dict(nt=60, k=8), 0.1),
+    # odd n padded to the workgroup eigen kernels' sizes (36 and 64): the padding must stay
+    # decoupled through the rotations and the first-order finish
+    ("molecule-odd35-padded", "molecule", dict(n=35, nt=200), 0.1),
+    ("warm-odd63-padded", "warm", dict(n=63, nt=50, k=8), 0.1),
     # dt * spectral radius far beyond the moment-series range: pairwise U'' fallback
     ("wide-spread-dt0.8", "tiny", dict(n=6, nt=20, dt=0.8, k=2), 0.5),
     # n above the LDS staging limit of the sweeps, odd, ragged chunks
