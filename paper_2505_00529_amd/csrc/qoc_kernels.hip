@@ -1851,19 +1851,91 @@ __device__ __forceinline__ void body_assemble(const AsmArgs& a, int bx, int b) {
     }
   }
   if (a.mode == (int)Mode::Hess) {
+    // H_lm = sum_j B_jl ((gamma + s_j) B_jm + K_jm) + B_jm K_jl + aa_lm on 4 x 4 register
+    // tiles.  This block owns tpb tiles, laid out on ts >= tpb (a power of two) lane slots;
+    // each tile is summed over j by the kThreads / ts threads of its slot (every nslice-th j),
+    // and the slices are added in a fixed order (shuffles within a wave, LDS across waves).
     const double* s = a.s + (size_t)b * nt;
     const double* K = a.K + (size_t)b * nt * P;
-    const int per = (P * P + a.gx - 1) / a.gx;
-    const int i0 = bx * per, i1 = min(P * P, i0 + per);
-    for (int idx = i0 + tid; idx < i1; idx += kThreads) {
-      const int l = idx / P, m = idx - l * P;
-      double acc = 0.0;
-      for (int j = 0; j < nt; ++j) {
-        const double bl = a.B[(size_t)j * P + l], bm = a.B[(size_t)j * P + m];
-        acc = fma(bl, (a.gamma + s[j]) * bm + K[(size_t)j * P + m], acc);
-        acc = fma(bm, K[(size_t)j * P + l], acc);
+    const int tp = (P + 3) / 4, ntile = tp * tp;
+    const int tpb = (ntile + a.gx - 1) / a.gx;
+    int ts = 1;
+    while (ts < tpb) ts <<= 1;   // at most 32 for every P, given gx = ceil(P^2 / 256)
+    const int nslice = kThreads / ts;
+    const int tl = tid % ts, slice = tid / ts;
+    const int tile = bx * tpb + tl;
+    const bool active = tl < tpb && tile < ntile;
+    const int l0 = (active ? tile / tp : 0) * 4, m0 = (active ? tile % tp : 0) * 4;
+    double acc[4][4];
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+      for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
+    if (active) {
+      const bool full = (P & 3) == 0;
+      for (int j = slice; j < nt; j += nslice) {
+        const double* Bj = a.B + (size_t)j * P;
+        const double* Kj = K + (size_t)j * P;
+        double bl[4], bm[4], kl[4], km[4];
+        if (full) {
+          const double2 b0 = *(const double2*)(Bj + l0), b1 = *(const double2*)(Bj + l0 + 2);
+          const double2 b2 = *(const double2*)(Bj + m0), b3 = *(const double2*)(Bj + m0 + 2);
+          const double2 k0 = *(const double2*)(Kj + l0), k1 = *(const double2*)(Kj + l0 + 2);
+          const double2 k2 = *(const double2*)(Kj + m0), k3 = *(const double2*)(Kj + m0 + 2);
+          bl[0] = b0.x; bl[1] = b0.y; bl[2] = b1.x; bl[3] = b1.y;
+          bm[0] = b2.x; bm[1] = b2.y; bm[2] = b3.x; bm[3] = b3.y;
+          kl[0] = k0.x; kl[1] = k0.y; kl[2] = k1.x; kl[3] = k1.y;
+          km[0] = k2.x; km[1] = k2.y; km[2] = k3.x; km[3] = k3.y;
+        } else {
+#pragma unroll
+          for (int x = 0; x < 4; ++x) {
+            bl[x] = l0 + x < P ? Bj[l0 + x] : 0.0;
+            kl[x] = l0 + x < P ? Kj[l0 + x] : 0.0;
+            bm[x] = m0 + x < P ? Bj[m0 + x] : 0.0;
+            km[x] = m0 + x < P ? Kj[m0 + x] : 0.0;
+          }
+        }
+        const double gs = a.gamma + s[j];
+#pragma unroll
+        for (int y = 0; y < 4; ++y) {
+          const double cm = fma(gs, bm[y], km[y]);
+#pragma unroll
+          for (int x = 0; x < 4; ++x) acc[x][y] = fma(bm[y], kl[x], fma(bl[x], cm, acc[x][y]));
+        }
       }
-      a.out[(size_t)b * P * P + idx] = acc + a.aa[(size_t)b * P * P + idx];
+    }
+    // within a wave, the slices of a slot are ts lanes apart (ts < 64): fold them onto lanes < ts
+    __shared__ double part[kThreads / 64][64][16];
+    const int wv = tid >> 6, lane = tid & 63;
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+      for (int y = 0; y < 4; ++y) {
+        double v = acc[x][y];
+        for (int off = 32; off >= ts; off >>= 1) v += __shfl_down(v, off, 64);
+        acc[x][y] = v;
+      }
+    if (lane < ts) {
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) part[wv][lane][4 * x + y] = acc[x][y];
+    }
+    __syncthreads();
+    // one thread per (slot, tile entry): add the four waves' partial sums (every wave holds all
+    // ts slots)
+    for (int t = tid; t < ts * 16; t += kThreads) {
+      const int tt = t / 16, el = t % 16;
+      const int gtile = bx * tpb + tt;
+      if (tt >= tpb || gtile >= ntile) continue;
+      double v = 0.0;
+#pragma unroll
+      for (int w2 = 0; w2 < kThreads / 64; ++w2) v += part[w2][tt][el];
+      const int l = (gtile / tp) * 4 + el / 4, m = (gtile % tp) * 4 + el % 4;
+      if (l < P && m < P) {
+        const size_t o = (size_t)b * P * P + (size_t)l * P + m;
+        a.out[o] = v + a.aa[o];
+      }
     }
   } else if (a.mode == (int)Mode::Hvp && bx == 0) {
     const double* s = a.s + (size_t)b * nt;
@@ -2527,9 +2599,12 @@ size_t sweep_launch_lds(int n, int pg) { return sweep_lds_bytes(n, pg); }
 
 hipError_t configure_multi_kernels() {
   for (int k = 0; k < (int)MultiKind::Count; ++k) {
-    // room for the kernels' static LDS (queue slot, reduction scratch: at most 2 KiB + 4 B)
-    hipError_t e = hipFuncSetAttribute(multi_fn((MultiKind)k), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       160 * 1024 - 4096);
+    // dynamic LDS up to what the kernel's static LDS (queue slot, reduction scratch) leaves
+    hipFuncAttributes attr;
+    hipError_t e = hipFuncGetAttributes(&attr, multi_fn((MultiKind)k));
+    if (e != hipSuccess) return e;
+    const size_t room = (size_t)160 * 1024 - ((attr.sharedSizeBytes + 1023) / 1024) * 1024;
+    e = hipFuncSetAttribute(multi_fn((MultiKind)k), hipFuncAttributeMaxDynamicSharedMemorySize, (int)room);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
