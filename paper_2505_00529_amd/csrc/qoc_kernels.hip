@@ -1692,6 +1692,61 @@ __device__ double sterm_pairs_wave(const StermArgs& a, size_t es, size_t vs, int
   return wave_sum_lds(loc);
 }
 
+// Moment form of the U'' contraction with NT series terms (one wave, lane = row p): the moments
+// P_k[p] = sum_q M~_pq mu_q x_q^k and Q_k[p] = sum_q M~_pq a_q x_q^k, then
+// sum_p sum_m R_m[p] w_m[p] with R_m = sum_{a<=m} conj(P_a) Q_{m-a} and
+// w_m = sum_b coef_{m+b} x_p^b.  Instantiated per NT so that the term loops have fixed length;
+// x_q, mu_q and a_q are read at wave-uniform addresses.
+template <int NT>
+__device__ __forceinline__ double2 sterm_moments(const double* Mt, const double* lam, const double2* mu,
+                                                 const double2* at, const double2* coef, double m0, double x0,
+                                                 double x1, int lane, int n) {
+  double2 contrib = make_double2(0.0, 0.0);
+  for (int rb = 0; rb * 64 < n; ++rb) {
+    const int p = lane + 64 * rb;
+    double2 P[NT], Q[NT];
+#pragma unroll
+    for (int k = 0; k < NT; ++k) {
+      P[k] = make_double2(0.0, 0.0);
+      Q[k] = make_double2(0.0, 0.0);
+    }
+    for (int qi = 0; qi < n; ++qi) {
+      const double xq = lam[qi] - m0;
+      const double2 muq = mu[qi], atq = at[qi];
+      const double mt = p < n ? Mt[(size_t)qi * n + p] : 0.0;   // Mt symmetric: coalesced column read
+      double2 t1 = c_scale(muq, mt), t2 = c_scale(atq, mt);
+#pragma unroll
+      for (int k = 0; k < NT; ++k) {
+        P[k].x += t1.x;
+        P[k].y += t1.y;
+        Q[k].x += t2.x;
+        Q[k].y += t2.y;
+        if (k + 1 < NT) {
+          t1 = c_scale(t1, xq);
+          t2 = c_scale(t2, xq);
+        }
+      }
+    }
+    if (p < n) {
+      const double xp = rb ? x1 : x0;
+#pragma unroll
+      for (int m = 0; m < NT; ++m) {
+        double2 R = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int aa = 0; aa <= m; ++aa) R = c_add(R, c_cmul(P[aa], Q[m - aa]));
+        double2 wm = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int bb = NT - 1 - m; bb >= 0; --bb) {
+          wm = c_scale(wm, xp);
+          wm = c_add(wm, coef[m + bb]);
+        }
+        contrib = c_add(contrib, c_mul(R, wm));
+      }
+    }
+  }
+  return contrib;
+}
+
 // Tasks bx * waves + wave, stepping nblk * waves: block bx of nblk covering all tasks.
 __device__ __forceinline__ void body_sterm(const StermArgs& a, int bx, int nblk) {
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -1738,6 +1793,7 @@ __device__ __forceinline__ void body_sterm(const StermArgs& a, int bx, int nblk)
         fact *= (double)(k + 4);
       }
     }
+    nmax = __builtin_amdgcn_readfirstlane(nmax);   // the same in every lane
     double sval;
     if (nmax < 0) {
       sval = sterm_pairs_wave(a, es, vs, lane);
@@ -1759,58 +1815,17 @@ __device__ __forceinline__ void body_sterm(const StermArgs& a, int bx, int nblk)
       }
       const double x0 = lv[0] - m0, x1 = lv[1] - m0;
       const double* Mt = a.mt + es * nn;
+      const double2* mu = a.mu + vs * n;
+      const double2* at = a.at + vs * n;
       double2 contrib = make_double2(0.0, 0.0);
-      for (int rb = 0; rb * 64 < n; ++rb) {
-        const int p = lane + 64 * rb;
-        double2 P[kStermNmax + 1], Q[kStermNmax + 1];
-#pragma unroll
-        for (int k = 0; k <= kStermNmax; ++k) {
-          P[k] = make_double2(0.0, 0.0);
-          Q[k] = make_double2(0.0, 0.0);
-        }
-        for (int qi = 0; qi < n; ++qi) {
-          const int e = qi >> 6, ql = qi & 63;
-          const double xq = readlane_d(e ? x1 : x0, ql);
-          const double2 muq = make_double2(readlane_d(e ? mv[1].x : mv[0].x, ql), readlane_d(e ? mv[1].y : mv[0].y, ql));
-          const double2 atq = make_double2(readlane_d(e ? av[1].x : av[0].x, ql), readlane_d(e ? av[1].y : av[0].y, ql));
-          const double mt = p < n ? Mt[(size_t)qi * n + p] : 0.0;   // Mt symmetric: coalesced column read
-          double2 t1 = c_scale(muq, mt), t2 = c_scale(atq, mt);
-#pragma unroll
-          for (int k = 0; k <= kStermNmax; ++k) {
-            if (k <= nmax) {
-              P[k].x += t1.x;
-              P[k].y += t1.y;
-              Q[k].x += t2.x;
-              Q[k].y += t2.y;
-              t1 = c_scale(t1, xq);
-              t2 = c_scale(t2, xq);
-            }
-          }
-        }
-        if (p < n) {
-          const double xp = rb ? x1 : x0;
-#pragma unroll
-          for (int m = 0; m <= kStermNmax; ++m) {
-            if (m <= nmax) {
-              // R_m = sum_{a<=m} conj(P_a) Q_{m-a}
-              double2 R = make_double2(0.0, 0.0);
-#pragma unroll
-              for (int aa = 0; aa <= kStermNmax; ++aa) {
-                if (aa <= m) R = c_add(R, c_cmul(P[aa], Q[m - aa]));
-              }
-              // w_m = sum_{b <= nmax-m} coef_{m+b} xp^b   (Horner)
-              double2 wm = make_double2(0.0, 0.0);
-#pragma unroll
-              for (int bb = kStermNmax; bb >= 0; --bb) {
-                if (bb <= nmax - m) {
-                  wm = c_scale(wm, xp);
-                  wm = c_add(wm, coef[m + bb]);
-                }
-              }
-              contrib = c_add(contrib, c_mul(R, wm));
-            }
-          }
-        }
+      switch (nmax) {   // wave-uniform
+#define QOC_STERM_CASE(T) \
+  case T - 1: contrib = sterm_moments<T>(Mt, lam, mu, at, coef, m0, x0, x1, lane, n); break;
+        QOC_STERM_CASE(1) QOC_STERM_CASE(2) QOC_STERM_CASE(3) QOC_STERM_CASE(4) QOC_STERM_CASE(5)
+        QOC_STERM_CASE(6) QOC_STERM_CASE(7) QOC_STERM_CASE(8) QOC_STERM_CASE(9) QOC_STERM_CASE(10)
+        QOC_STERM_CASE(11)
+#undef QOC_STERM_CASE
+        default: break;
       }
       double2 tot = make_double2(wave_sum_lds(contrib.x), wave_sum_lds(contrib.y));
       tot = c_mul(phase(m0, a.dt), tot);
