@@ -1637,7 +1637,7 @@ __global__ __launch_bounds__(kThreads, MODE == kSweepRegs ? 2 : 3) void k_backwa
 // The series is truncated by the bound |h_n| <= C(n+2,2) (dt r)^n, r = max |x|; a step whose
 // spread is too wide for kStermNmax terms falls back to the pairwise form below.
 
-constexpr int kStermNmax = 10;
+constexpr int kStermNmax = 14;
 
 // Pairwise fallback: T_pq = 2 (Y_pq - Y_qp)/(l_p - l_q), Y = (Phi o Mt) Mt for separated pairs,
 // the stable second divided difference term by term for close pairs and the diagonal.
@@ -1823,7 +1823,7 @@ __device__ __forceinline__ void body_sterm(const StermArgs& a, int bx, int nblk)
   case T - 1: contrib = sterm_moments<T>(Mt, lam, mu, at, coef, m0, x0, x1, lane, n); break;
         QOC_STERM_CASE(1) QOC_STERM_CASE(2) QOC_STERM_CASE(3) QOC_STERM_CASE(4) QOC_STERM_CASE(5)
         QOC_STERM_CASE(6) QOC_STERM_CASE(7) QOC_STERM_CASE(8) QOC_STERM_CASE(9) QOC_STERM_CASE(10)
-        QOC_STERM_CASE(11)
+        QOC_STERM_CASE(11) QOC_STERM_CASE(12) QOC_STERM_CASE(13) QOC_STERM_CASE(14) QOC_STERM_CASE(15)
 #undef QOC_STERM_CASE
         default: break;
       }
