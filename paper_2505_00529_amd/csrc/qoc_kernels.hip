@@ -80,7 +80,7 @@ __host__ __device__ inline size_t eig_small_doubles(int np) { return (size_t)2 *
 // which is nearly diagonal for a smooth control, so the Jacobi sweeps converge in a few
 // passes and the rotations accumulate into V_j = V_{j-1} Q_j.
 __device__ __forceinline__ void body_eig_chunk(const EigArgs& a, int c, int b) {
-  extern __shared__ double smem[];
+  extern __shared__ __attribute__((aligned(16))) double smem[];
   const int np = a.np, n = a.n, nt = a.nt;
   const int j0 = a.j_base + c * a.chunk;
   const int j1 = min(a.j_base + a.nsteps, j0 + a.chunk);
@@ -239,7 +239,7 @@ __device__ __forceinline__ void body_eig_wave(const EigArgs& a, int c, int b) {
   constexpr int H = NP / 2;
   constexpr int NBLK = H * (H + 1) / 2;
   constexpr int BPL = (NBLK + 63) / 64;    // 2x2 blocks per lane
-  extern __shared__ double smem[];
+  extern __shared__ __attribute__((aligned(16))) double smem[];
   double* buf0 = smem;
   double* buf1 = buf0 + NP * NP;
   double* buf2 = buf1 + NP * NP;
@@ -590,7 +590,7 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
   static_assert(NP % RT == 0 && NP % CT == 0 && NTILE <= TPB, "tile shape");
   static_assert(H % S == 0 && S >= 2 && NP % VW == 0 && VRW * G <= 64 && VW0 + VW <= TPB / 64 - 1,
                 "register V layout");
-  extern __shared__ double smem[];
+  extern __shared__ __attribute__((aligned(16))) double smem[];
   double* A = smem;                              // NP x NP; also A buffer 0 during the sweeps
   double* Vt = A + NP * NP;                      // NP x NP, column-major: Vt[k * NP + i] = V[i][k]; A buffer 1
   double* Vp = VP_LDS ? Vt + NP * NP : nullptr;  // V_{j-1}, same layout
@@ -1024,41 +1024,52 @@ constexpr int kPrefetchSmall = 8;   // n*n <= 8*256: O and S double-buffered in 
 constexpr int kTileRows = 4;    // rows of the O product per thread (x 1 complex column)
 
 // Sweep variants: kSweepGlobal reads O and S from global memory inside the step (n > 64);
-// kSweepRegs stages them in LDS from registers loaded one step ahead (n <= 64); kSweepAsync
-// double-buffers them in LDS with direct global-to-LDS loads issued one step ahead (n <= 45).
-constexpr int kSweepGlobal = 0, kSweepRegs = 1, kSweepAsync = 2;
+// kSweepRegs stages them in LDS from registers loaded one step ahead (n <= 64); kSweepDbuf
+// double-buffers them in LDS, written from registers loaded one step ahead (even n <= 45).
+constexpr int kSweepGlobal = 0, kSweepRegs = 1, kSweepDbuf = 2;
 
-// Copy `count` doubles from global memory to LDS with direct global-to-LDS loads: 16 bytes per
-// lane when both ends are 16-byte aligned and count is even (lane l of a load fills bytes
-// 16 l .. 16 l + 15 after the load's LDS base), otherwise one dword per lane.  Wave w takes
-// every (waves)-th 64-lane segment.  The caller waits for completion (vmcnt) and synchronises
-// the workgroup before the data is read.
-__device__ __forceinline__ void lds_copy_async(double* dst, const double* src, int count) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  if (((count & 1) | (((uintptr_t)src | (uintptr_t)dst) & 15)) == 0) {
-    const int chunks = count / 2;
-    for (int seg = wv * 64; seg < chunks; seg += kThreads) {
-      const int d = seg + lane;
-      if (d < chunks)
-        __builtin_amdgcn_global_load_lds((const void*)(src + 2 * d),
-                                         (__attribute__((address_space(3))) void*)(dst + 2 * seg), 16, 0, 0);
+// Staging of the next step's n x n matrices in the double-buffered mode: each thread loads its
+// share into registers at the start of a step and writes it to the idle LDS buffer during the
+// product phase, so the loads' latency overlaps the whole step.  Thread t holds the 16-byte pairs
+// t + k*kThreads; count is even, at most kPrefetchSmall * kThreads, and both ends are 16-byte
+// aligned (n even, eigen-data in 256-byte aligned arrays).  One fixed register layout: a choice
+// between layouts at run time makes the compiler copy, and so wait for, the loaded registers.
+// (Direct global-to-LDS loads would need no registers, but the compiler waits for them before
+// the first LDS read that follows.)
+__device__ __forceinline__ void stage_load(double (&v)[kPrefetchSmall], const double* src, int count) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < kPrefetchSmall / 2; ++k) {
+    const int c = tid + k * kThreads;
+    if (c < count / 2) {
+      const double2 x = ((const double2*)src)[c];
+      v[2 * k] = x.x;
+      v[2 * k + 1] = x.y;
     }
-    return;
-  }
-  const int dwords = 2 * count;
-  for (int seg = wv * 64; seg < dwords; seg += kThreads) {
-    const int d = seg + lane;
-    if (d < dwords)
-      __builtin_amdgcn_global_load_lds((const void*)((const unsigned*)src + d),
-                                       (__attribute__((address_space(3))) void*)((unsigned*)dst + seg), 4, 0, 0);
   }
 }
-// s_waitcnt vmcnt(0) (expcnt and lgkmcnt left at their maxima)
-__device__ __forceinline__ void wait_vm_all() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+__device__ __forceinline__ void stage_store(double* dst, const double (&v)[kPrefetchSmall], int count) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < kPrefetchSmall / 2; ++k) {
+    const int c = tid + k * kThreads;
+    if (c < count / 2) ((double2*)dst)[c] = make_double2(v[2 * k], v[2 * k + 1]);
+  }
+}
+
+// An empty use of v on every path.  Registers loaded one step ahead are consumed under
+// conditions (lanes, ranges) that the compiler's wait insertion cannot follow across the step
+// loop; unless every path reads them at the commit, it waits for them (and, with stores in
+// flight, for all memory operations) before the next step's loads into the same registers.
+__device__ __forceinline__ void reg_use(double v) { asm volatile("" ::"v"(v)); }
+__device__ __forceinline__ void reg_use(double2 v) {
+  reg_use(v.x);
+  reg_use(v.y);
+}
 
 template <int MODE>
 struct StepStage {
-  static constexpr int PF = MODE == kSweepRegs ? kPrefetch : 1;
+  static constexpr int PF = MODE == kSweepRegs ? kPrefetch : (MODE == kSweepDbuf ? kPrefetchSmall : 1);
   double po[PF], ps[PF];
   double pl;
   double pf;   // forcing value of column tid + 1 (tid < columns of the group)
@@ -1092,19 +1103,19 @@ struct ItemWalk {
 
 template <int MODE>
 __device__ __forceinline__ void body_forward(const SweepArgs& a, int g, int b) {
-  extern __shared__ double smem[];
+  extern __shared__ __attribute__((aligned(16))) double smem[];
   const int n = a.n, nt = a.nt, tid = threadIdx.x;
   const int c0 = g * a.pg;
   const int ncol = max(0, min(a.pg, a.P - c0));
   const int w = 1 + ncol;           // columns carried
   const size_t nn = (size_t)n * n;
   constexpr bool STAGE = MODE != kSweepGlobal;
-  constexpr bool ASYNC = MODE == kSweepAsync;
-  // kSweepRegs: Ob[r*n + p] = O_j[p][r] (transposed); kSweepAsync: two buffers each of O_j
+  constexpr bool DBUF = MODE == kSweepDbuf;
+  // kSweepRegs: Ob[r*n + p] = O_j[p][r] (transposed); kSweepDbuf: two buffers each of O_j
   // (row-major, as stored) and S_j
   double* Ob = smem;
-  double* Sb = Ob + (STAGE ? nn : 0) * (ASYNC ? 2 : 1);
-  double2* cur = (double2*)(Sb + (STAGE ? nn : 0) * (ASYNC ? 2 : 1));   // [n][w]
+  double* Sb = Ob + (STAGE ? nn : 0) * (DBUF ? 2 : 1);
+  double2* cur = (double2*)(Sb + (STAGE ? nn : 0) * (DBUF ? 2 : 1));   // [n][w]
   double2* X = cur + n * w;         // [n][w]
   double2* hh = X + n * w;          // [n]
   double2* ph = hh + n;             // [n]
@@ -1119,11 +1130,11 @@ __device__ __forceinline__ void body_forward(const SweepArgs& a, int g, int b) {
   // FOLD: the next step's staged data goes in during the O X product, which reads none of it
   constexpr bool FOLD = MODE != kSweepRegs;
 
-  auto load_step = [&](int j, StepStage<MODE>& st, int buf) {
+  auto load_step = [&](int j, StepStage<MODE>& st) {
     const size_t es = eb0 + (j - a.eig_j0);
-    if (ASYNC) {
-      if (j + 1 < a.j_end) lds_copy_async(Ob + buf * nn, a.ov + es * nn, (int)nn);
-      if (a.need_y) lds_copy_async(Sb + buf * nn, a.sm + es * nn, (int)nn);
+    if constexpr (DBUF) {
+      if (j + 1 < a.j_end) stage_load(st.po, a.ov + es * nn, (int)nn);
+      if (a.need_y) stage_load(st.ps, a.sm + es * nn, (int)nn);
     } else if (STAGE) {
 #pragma unroll
       for (int i = 0; i < StepStage<MODE>::PF; ++i) {
@@ -1135,8 +1146,12 @@ __device__ __forceinline__ void body_forward(const SweepArgs& a, int g, int b) {
     st.pl = (ph_t >= 0 && ph_t < n) ? a.lam[es * n + ph_t] : 0.0;
     st.pf = tid < ncol ? Fb[(size_t)j * a.fcols + c0 + tid] : 0.0;
   };
-  auto commit_step = [&](const StepStage<MODE>& st) {
-    if (STAGE && !ASYNC) {
+  // j: the step whose data st holds; buf: its LDS buffer (double-buffered mode)
+  auto commit_step = [&](const StepStage<MODE>& st, int j, int buf) {
+    if constexpr (DBUF) {
+      if (j + 1 < a.j_end) stage_store(Ob + buf * nn, st.po, (int)nn);
+      if (a.need_y) stage_store(Sb + buf * nn, st.ps, (int)nn);
+    } else if (STAGE) {
 #pragma unroll
       for (int i = 0; i < StepStage<MODE>::PF; ++i) {
         const int idx = tid + i * kThreads;
@@ -1153,6 +1168,18 @@ __device__ __forceinline__ void body_forward(const SweepArgs& a, int g, int b) {
       ph[ph_t] = c_mul(h, h);
     }
     if (tid < ncol) fv[tid] = st.pf;
+  };
+  // on every path through the step, whether or not it loaded or committed st
+  auto settle = [&](const StepStage<MODE>& st) {
+    if constexpr (DBUF) {
+#pragma unroll
+      for (int i = 0; i < StepStage<MODE>::PF; ++i) {
+        reg_use(st.po[i]);
+        reg_use(st.ps[i]);
+      }
+      reg_use(st.pl);
+      reg_use(st.pf);
+    }
   };
 
   if (a.j_begin == 0) {
@@ -1189,9 +1216,9 @@ __device__ __forceinline__ void body_forward(const SweepArgs& a, int g, int b) {
   }
   {
     StepStage<MODE> st;
-    load_step(a.j_begin, st, 0);
-    if (ASYNC) wait_vm_all();
-    commit_step(st);
+    load_step(a.j_begin, st);
+    commit_step(st, a.j_begin, 0);
+    settle(st);
   }
   __syncthreads();
 
@@ -1199,9 +1226,9 @@ __device__ __forceinline__ void body_forward(const SweepArgs& a, int g, int b) {
   for (int j = a.j_begin; j < a.j_end; ++j) {
     const size_t es = eb0 + (j - a.eig_j0);
     const size_t vs = vb0 + j;
-    const int cb = ASYNC ? ((j - a.j_begin) & 1) : 0;
+    const int cb = DBUF ? ((j - a.j_begin) & 1) : 0;
     StepStage<MODE> nx;
-    if (j + 1 < a.j_end) load_step(j + 1, nx, cb ^ 1);
+    if (j + 1 < a.j_end) load_step(j + 1, nx);
     const double* S = STAGE ? Sb + cb * nn : a.sm + es * nn;
     if (a.need_y) {
       // four adjacent lanes per output row, each summing every fourth r
@@ -1250,7 +1277,7 @@ __device__ __forceinline__ void body_forward(const SweepArgs& a, int g, int b) {
         double2 acc[kTileRows];
 #pragma unroll
         for (int i = 0; i < kTileRows; ++i) acc[i] = make_double2(0.0, 0.0);
-        if (ASYNC && (n & 3) == 0) {
+        if (DBUF && (n & 3) == 0) {
           // row-major O in LDS: two consecutive r of a row per 16-byte load (every tile row
           // exists when n is a multiple of the tile height)
           const double* Oc = Ob + cb * nn + p0 * n;
@@ -1287,7 +1314,7 @@ __device__ __forceinline__ void body_forward(const SweepArgs& a, int g, int b) {
 #pragma unroll
             for (int i = 0; i < kTileRows; ++i) {
               const int p = p0 + i;
-              const double o = p < n ? (ASYNC ? Ob[cb * nn + (size_t)p * n + r]
+              const double o = p < n ? (DBUF ? Ob[cb * nn + (size_t)p * n + r]
                                               : (STAGE ? Ob[r * n + p] : Og[(size_t)p * n + r]))
                                      : 0.0;
               acc[i].x = fma(o, x.x, acc[i].x);
@@ -1310,20 +1337,18 @@ __device__ __forceinline__ void body_forward(const SweepArgs& a, int g, int b) {
         }
       }
     }
-    if (FOLD && j + 1 < a.j_end) {
-      if (ASYNC) wait_vm_all();
-      commit_step(nx);
-    }
+    if (FOLD && j + 1 < a.j_end) commit_step(nx, j + 1, cb ^ 1);
+    settle(nx);
     __syncthreads();
     if (!FOLD && j + 1 < a.j_end) {
-      commit_step(nx);
+      commit_step(nx, j + 1, 0);
       __syncthreads();
     }
   }
 }
 
 template <int MODE>
-__global__ __launch_bounds__(kThreads, MODE == kSweepRegs ? 2 : 3) void k_forward(SweepArgs a) {
+__global__ __launch_bounds__(kThreads, MODE == kSweepGlobal ? 3 : 2) void k_forward(SweepArgs a) {
   body_forward<MODE>(a, blockIdx.x, blockIdx.y);
 }
 
@@ -1385,7 +1410,7 @@ __global__ __launch_bounds__(kThreads) void k_terminal(TermArgs a) { body_termin
 // HVP: mu_J = rho a'_J, mu_j = U_j^H mu_{j+1} + z_j u_j, e_j = Re(mu^H y_j) + Re(z_j^H a'_j).
 template <int MODE>
 struct BwdStage {
-  static constexpr int PF = MODE == kSweepRegs ? kPrefetch : 1;
+  static constexpr int PF = MODE == kSweepRegs ? kPrefetch : (MODE == kSweepDbuf ? kPrefetchSmall : 1);
   double po[PF], ps[PF];
   double pl;
   double2 py, pa;
@@ -1394,7 +1419,7 @@ struct BwdStage {
 
 template <int MODE>
 __device__ __forceinline__ void body_backward(const SweepArgs& a, int g, int b) {
-  extern __shared__ double smem[];
+  extern __shared__ __attribute__((aligned(16))) double smem[];
   const int n = a.n, nt = a.nt, tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
   const int c0 = g * a.pg;
@@ -1402,10 +1427,10 @@ __device__ __forceinline__ void body_backward(const SweepArgs& a, int g, int b) 
   const int w = 1 + ncol;
   const size_t nn = (size_t)n * n;
   constexpr bool STAGE = MODE != kSweepGlobal;
-  constexpr bool ASYNC = MODE == kSweepAsync;
-  double* Ob = smem;                // O_{j-1} as stored: Ob[r*n + p] = O_{j-1}[r][p] (two buffers if ASYNC)
-  double* Sb = Ob + (STAGE ? nn : 0) * (ASYNC ? 2 : 1);
-  double2* cur = (double2*)(Sb + (STAGE ? nn : 0) * (ASYNC ? 2 : 1));
+  constexpr bool DBUF = MODE == kSweepDbuf;
+  double* Ob = smem;                // O_{j-1} as stored: Ob[r*n + p] = O_{j-1}[r][p] (two buffers if DBUF)
+  double* Sb = Ob + (STAGE ? nn : 0) * (DBUF ? 2 : 1);
+  double2* cur = (double2*)(Sb + (STAGE ? nn : 0) * (DBUF ? 2 : 1));
   double2* X = cur + n * w;
   double2* hh = X + n * w;
   double2* ph = hh + n;
@@ -1426,13 +1451,13 @@ __device__ __forceinline__ void body_backward(const SweepArgs& a, int g, int b) 
     if (jj - 1 >= a.j_begin) return a.ov + (eb0 + (jj - 1 - a.eig_j0)) * nn;
     return a.o_in ? a.o_in + (size_t)b * nn : nullptr;
   };
-  auto load_step = [&](int j, BwdStage<MODE>& st, int buf) {
+  auto load_step = [&](int j, BwdStage<MODE>& st) {
     const size_t es = eb0 + (j - a.eig_j0);
     const size_t vs = vb0 + j;
-    if (ASYNC) {
+    if constexpr (DBUF) {
       const double* Op = j >= 1 ? o_prev(j) : nullptr;
-      if (Op) lds_copy_async(Ob + buf * nn, Op, (int)nn);
-      lds_copy_async(Sb + buf * nn, a.sm + es * nn, (int)nn);
+      if (Op) stage_load(st.po, Op, (int)nn);
+      stage_load(st.ps, a.sm + es * nn, (int)nn);
     } else if (STAGE) {
       const double* Op = j >= 1 ? o_prev(j) : nullptr;
 #pragma unroll
@@ -1447,8 +1472,12 @@ __device__ __forceinline__ void body_backward(const SweepArgs& a, int g, int b) 
     st.pa = (tid < n && a.hvp) ? a.ah[vs * n + tid] : make_double2(0.0, 0.0);
     st.pf = tid < ncol ? Fb[(size_t)j * a.fcols + c0 + tid] : 0.0;
   };
-  auto commit_step = [&](const BwdStage<MODE>& st) {
-    if (STAGE && !ASYNC) {
+  // j: the step whose data st holds; buf: its LDS buffer (double-buffered mode)
+  auto commit_step = [&](const BwdStage<MODE>& st, int j, int buf) {
+    if constexpr (DBUF) {
+      if (j >= 1 && o_prev(j)) stage_store(Ob + buf * nn, st.po, (int)nn);
+      stage_store(Sb + buf * nn, st.ps, (int)nn);
+    } else if (STAGE) {
 #pragma unroll
       for (int i = 0; i < BwdStage<MODE>::PF; ++i) {
         const int idx = tid + i * kThreads;
@@ -1469,6 +1498,20 @@ __device__ __forceinline__ void body_backward(const SweepArgs& a, int g, int b) 
     }
     if (tid < ncol) fv[tid] = st.pf;
   };
+  // on every path through the step, whether or not it loaded or committed st
+  auto settle = [&](const BwdStage<MODE>& st) {
+    if constexpr (DBUF) {
+#pragma unroll
+      for (int i = 0; i < BwdStage<MODE>::PF; ++i) {
+        reg_use(st.po[i]);
+        reg_use(st.ps[i]);
+      }
+      reg_use(st.pl);
+      reg_use(st.pf);
+      reg_use(st.py);
+      reg_use(st.pa);
+    }
+  };
 
   for (int idx = tid; idx < n * w; idx += kThreads) {
     const int p = idx / w, col = idx - p * w;
@@ -1479,9 +1522,9 @@ __device__ __forceinline__ void body_backward(const SweepArgs& a, int g, int b) 
   }
   {
     BwdStage<MODE> st;
-    load_step(a.j_end - 1, st, 0);
-    if (ASYNC) wait_vm_all();
-    commit_step(st);
+    load_step(a.j_end - 1, st);
+    commit_step(st, a.j_end - 1, 0);
+    settle(st);
   }
   __syncthreads();
 
@@ -1489,9 +1532,9 @@ __device__ __forceinline__ void body_backward(const SweepArgs& a, int g, int b) 
   for (int j = a.j_end - 1; j >= a.j_begin; --j) {
     const size_t es = eb0 + (j - a.eig_j0);
     const size_t vs = vb0 + j;
-    const int cb = ASYNC ? ((a.j_end - 1 - j) & 1) : 0;
+    const int cb = DBUF ? ((a.j_end - 1 - j) & 1) : 0;
     BwdStage<MODE> nx;
-    if (j - 1 >= a.j_begin) load_step(j - 1, nx, cb ^ 1);
+    if (j - 1 >= a.j_begin) load_step(j - 1, nx);
     const double* S = STAGE ? Sb + cb * nn : a.sm + es * nn;
     for (int t4 = tid; t4 < 4 * n; t4 += kThreads) {
       // four adjacent lanes per output row, each summing every fourth r
@@ -1597,13 +1640,10 @@ __device__ __forceinline__ void body_backward(const SweepArgs& a, int g, int b) 
         for (int i = 0; i < kTileRows; ++i)
           if (p0 + i < n) cur[(p0 + i) * w + col] = acc[i];
       }
-      if (FOLD && j > a.j_begin) {
-        if (ASYNC) wait_vm_all();
-        commit_step(nx);
-      }
+      if (FOLD && j > a.j_begin) commit_step(nx, j - 1, cb ^ 1);
       __syncthreads();
       if (!FOLD && j > a.j_begin) {
-        commit_step(nx);
+        commit_step(nx, j - 1, 0);
       } else if (j == a.j_begin && a.bout) {
         // state leaving the range, in basis j_begin - 1
         for (int idx = tid; idx < n * w; idx += kThreads) {
@@ -1612,6 +1652,7 @@ __device__ __forceinline__ void body_backward(const SweepArgs& a, int g, int b) 
         }
       }
     }
+    settle(nx);
     // (with FOLD the barrier after the product already orders this step's reads before the
     // next step's writes)
     if (!FOLD || j < 1) __syncthreads();
@@ -1619,7 +1660,7 @@ __device__ __forceinline__ void body_backward(const SweepArgs& a, int g, int b) 
 }
 
 template <int MODE>
-__global__ __launch_bounds__(kThreads, MODE == kSweepRegs ? 2 : 3) void k_backward(SweepArgs a) {
+__global__ __launch_bounds__(kThreads, MODE == kSweepGlobal ? 3 : 2) void k_backward(SweepArgs a) {
   body_backward<MODE>(a, blockIdx.x, blockIdx.y);
 }
 
@@ -2097,7 +2138,7 @@ hipError_t launch_seg_join(Work& w, double* obound_s, bool do_overlap, hipStream
 __global__ __launch_bounds__(kThreads) void k_sym_eig(const double* h, int P, int np, double* evals,
                                                       double* evecs, double* gs, int lds_mats, double tol_rel,
                                                       int max_sweeps, int* status) {
-  extern __shared__ double smem[];
+  extern __shared__ __attribute__((aligned(16))) double smem[];
   const int b = blockIdx.x, tid = threadIdx.x;
   double* rot = smem;
   double* red = rot + np;
@@ -2161,7 +2202,8 @@ static size_t eig_lds_bytes(int np, bool lds_mats) {
 static bool eig_fits_lds(int np) { return eig_lds_bytes(np, true) <= 160 * 1024; }
 
 static bool sweep_stage(int n) { return n * n <= kPrefetch * kThreads; }
-static bool sweep_small(int n) { return n * n <= kPrefetchSmall * kThreads; }   // async LDS double buffer
+// LDS double buffer with 16-byte staging (even n)
+static bool sweep_small(int n) { return (n & 1) == 0 && n * n <= kPrefetchSmall * kThreads; }
 
 static size_t sweep_lds_bytes(int n, int pg) {
   const size_t mats = (sweep_small(n) ? 4 : (sweep_stage(n) ? 2 : 0)) * (size_t)n * n * sizeof(double);
@@ -2169,9 +2211,9 @@ static size_t sweep_lds_bytes(int n, int pg) {
 }
 
 hipError_t configure_kernels() {
-  const void* fns[] = {(const void*)k_eig_chunk, (const void*)k_eig_wg<36>, (const void*)k_eig_wg<64>, (const void*)k_sym_eig, (const void*)k_forward<kSweepRegs>, (const void*)k_forward<kSweepAsync>,
+  const void* fns[] = {(const void*)k_eig_chunk, (const void*)k_eig_wg<36>, (const void*)k_eig_wg<64>, (const void*)k_sym_eig, (const void*)k_forward<kSweepRegs>, (const void*)k_forward<kSweepDbuf>,
                        (const void*)k_forward<kSweepGlobal>, (const void*)k_backward<kSweepRegs>,
-                       (const void*)k_backward<kSweepAsync>, (const void*)k_backward<kSweepGlobal>};
+                       (const void*)k_backward<kSweepDbuf>, (const void*)k_backward<kSweepGlobal>};
   for (const void* f : fns) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
@@ -2371,7 +2413,7 @@ SweepArgs sweep_args(const SysDev& sy, const BasisDev& bs, const Work& w, Mode m
 hipError_t launch_forward_args(const SweepArgs& a, int nb, hipStream_t stream) {
   const size_t lds = sweep_lds_bytes(a.n, a.P > 0 ? a.pg : 0);
   if (sweep_small(a.n))
-    hipLaunchKernelGGL(k_forward<kSweepAsync>, dim3(a.ngroups, nb), dim3(kThreads), lds, stream, a);
+    hipLaunchKernelGGL(k_forward<kSweepDbuf>, dim3(a.ngroups, nb), dim3(kThreads), lds, stream, a);
   else if (sweep_stage(a.n))
     hipLaunchKernelGGL(k_forward<kSweepRegs>, dim3(a.ngroups, nb), dim3(kThreads), lds, stream, a);
   else
@@ -2411,7 +2453,7 @@ hipError_t launch_terminal(const SysDev& sy, const BasisDev& bs, Work& w, Mode m
 hipError_t launch_backward_args(const SweepArgs& a, int nb, hipStream_t stream) {
   const size_t lds = sweep_lds_bytes(a.n, a.P > 0 ? a.pg : 0);
   if (sweep_small(a.n))
-    hipLaunchKernelGGL(k_backward<kSweepAsync>, dim3(a.ngroups, nb), dim3(kThreads), lds, stream, a);
+    hipLaunchKernelGGL(k_backward<kSweepDbuf>, dim3(a.ngroups, nb), dim3(kThreads), lds, stream, a);
   else if (sweep_stage(a.n))
     hipLaunchKernelGGL(k_backward<kSweepRegs>, dim3(a.ngroups, nb), dim3(kThreads), lds, stream, a);
   else
@@ -2541,11 +2583,11 @@ QOC_MULTI_KERNEL(km_eig_wg64, 512, EigWgShape<64>::WAVES, EigArgs, body_eig_wg<6
 QOC_MULTI_KERNEL(km_eig_chunk, kThreads, 1, EigArgs, body_eig_chunk)
 QOC_MULTI_KERNEL(km_boundary, kThreads, 1, BndArgs, body_boundary)
 QOC_MULTI_KERNEL(km_forward_staged, kThreads, 2, SweepArgs, body_forward<kSweepRegs>)
-QOC_MULTI_KERNEL(km_forward_small, kThreads, 3, SweepArgs, body_forward<kSweepAsync>)
+QOC_MULTI_KERNEL(km_forward_small, kThreads, 2, SweepArgs, body_forward<kSweepDbuf>)
 QOC_MULTI_KERNEL(km_forward_global, kThreads, 3, SweepArgs, body_forward<kSweepGlobal>)
 QOC_MULTI_KERNEL(km_terminal, kThreads, 1, TermArgs, body_terminal)
 QOC_MULTI_KERNEL(km_backward_staged, kThreads, 2, SweepArgs, body_backward<kSweepRegs>)
-QOC_MULTI_KERNEL(km_backward_small, kThreads, 3, SweepArgs, body_backward<kSweepAsync>)
+QOC_MULTI_KERNEL(km_backward_small, kThreads, 2, SweepArgs, body_backward<kSweepDbuf>)
 QOC_MULTI_KERNEL(km_backward_global, kThreads, 3, SweepArgs, body_backward<kSweepGlobal>)
 QOC_MULTI_KERNEL(km_sterm, kThreads, 2, StermArgs, body_sterm)
 QOC_MULTI_KERNEL(km_assemble, kThreads, 1, AsmArgs, body_assemble)
