@@ -1222,7 +1222,6 @@ __device__ __forceinline__ void body_forward(const SweepArgs& a, int g, int b) {
   }
   __syncthreads();
 
-  const int nrb = (n + kTileRows - 1) / kTileRows;
   for (int j = a.j_begin; j < a.j_end; ++j) {
     const size_t es = eb0 + (j - a.eig_j0);
     const size_t vs = vb0 + j;
@@ -1270,62 +1269,71 @@ __device__ __forceinline__ void body_forward(const SweepArgs& a, int g, int b) {
     __syncthreads();
     if (j + 1 < a.j_end) {
       const double* Og = a.ov + es * nn;
-      ItemWalk it(tid, w);
-      for (int t = tid; t < nrb * w; t += kThreads, it.next()) {
-        const int rb = it.p, col = it.col;
-        const int p0 = rb * kTileRows;
-        double2 acc[kTileRows];
+      // [a_{j+1} | A'_{j+1}] = O_j X on tiles of TR rows x 1 column
+      auto product = [&](auto tile_rows) {
+        constexpr int TR = decltype(tile_rows)::value;
+        const int nrb = (n + TR - 1) / TR;
+        ItemWalk it(tid, w);
+        for (int t = tid; t < nrb * w; t += kThreads, it.next()) {
+          const int rb = it.p, col = it.col;
+          const int p0 = rb * TR;
+          double2 acc[TR];
 #pragma unroll
-        for (int i = 0; i < kTileRows; ++i) acc[i] = make_double2(0.0, 0.0);
-        if (DBUF && (n & 3) == 0) {
-          // row-major O in LDS: two consecutive r of a row per 16-byte load (every tile row
-          // exists when n is a multiple of the tile height)
-          const double* Oc = Ob + cb * nn + p0 * n;
+          for (int i = 0; i < TR; ++i) acc[i] = make_double2(0.0, 0.0);
+          if (DBUF && (n & 1) == 0 && n % TR == 0) {
+            // row-major O in LDS: two consecutive r of a row per 16-byte load (every tile row
+            // exists when n is a multiple of the tile height)
+            const double* Oc = Ob + cb * nn + p0 * n;
 #pragma unroll 2
-          for (int r = 0; r < n; r += 2) {
-            const double2 x0 = X[r * w + col], x1 = X[(r + 1) * w + col];
+            for (int r = 0; r < n; r += 2) {
+              const double2 x0 = X[r * w + col], x1 = X[(r + 1) * w + col];
 #pragma unroll
-            for (int i = 0; i < kTileRows; ++i) {
-              const double2 o = *(const double2*)(Oc + i * n + r);
-              acc[i].x = fma(o.x, x0.x, acc[i].x);
-              acc[i].y = fma(o.x, x0.y, acc[i].y);
-              acc[i].x = fma(o.y, x1.x, acc[i].x);
-              acc[i].y = fma(o.y, x1.y, acc[i].y);
+              for (int i = 0; i < TR; ++i) {
+                const double2 o = *(const double2*)(Oc + i * n + r);
+                acc[i].x = fma(o.x, x0.x, acc[i].x);
+                acc[i].y = fma(o.x, x0.y, acc[i].y);
+                acc[i].x = fma(o.y, x1.x, acc[i].x);
+                acc[i].y = fma(o.y, x1.y, acc[i].y);
+              }
             }
-          }
-        } else if (MODE == kSweepRegs && (n & 3) == 0) {
-          // transposed O in LDS: the tile's four rows p0..p0+3 in two 16-byte loads
+          } else if (MODE == kSweepRegs && TR == 4 && (n & 3) == 0) {
+            // transposed O in LDS: the tile's four rows p0..p0+3 in two 16-byte loads
 #pragma unroll 2
-          for (int r = 0; r < n; ++r) {
-            const double2 x = X[r * w + col];
-            const double2 o01 = *(const double2*)(Ob + r * n + p0);
-            const double2 o23 = *(const double2*)(Ob + r * n + p0 + 2);
-            const double o[4] = {o01.x, o01.y, o23.x, o23.y};
+            for (int r = 0; r < n; ++r) {
+              const double2 x = X[r * w + col];
+              const double2 o01 = *(const double2*)(Ob + r * n + p0);
+              const double2 o23 = *(const double2*)(Ob + r * n + p0 + 2);
+              const double o[4] = {o01.x, o01.y, o23.x, o23.y};
 #pragma unroll
-            for (int i = 0; i < kTileRows; ++i) {
-              acc[i].x = fma(o[i], x.x, acc[i].x);
-              acc[i].y = fma(o[i], x.y, acc[i].y);
+              for (int i = 0; i < TR; ++i) {
+                acc[i].x = fma(o[i], x.x, acc[i].x);
+                acc[i].y = fma(o[i], x.y, acc[i].y);
+              }
             }
-          }
-        } else {
+          } else {
 #pragma unroll(MODE == kSweepRegs ? 1 : 4)
-          for (int r = 0; r < n; ++r) {
-            const double2 x = X[r * w + col];
+            for (int r = 0; r < n; ++r) {
+              const double2 x = X[r * w + col];
 #pragma unroll
-            for (int i = 0; i < kTileRows; ++i) {
-              const int p = p0 + i;
-              const double o = p < n ? (DBUF ? Ob[cb * nn + (size_t)p * n + r]
-                                              : (STAGE ? Ob[r * n + p] : Og[(size_t)p * n + r]))
-                                     : 0.0;
-              acc[i].x = fma(o, x.x, acc[i].x);
-              acc[i].y = fma(o, x.y, acc[i].y);
+              for (int i = 0; i < TR; ++i) {
+                const int p = p0 + i;
+                const double o = p < n ? (DBUF ? Ob[cb * nn + (size_t)p * n + r]
+                                                : (STAGE ? Ob[r * n + p] : Og[(size_t)p * n + r]))
+                                       : 0.0;
+                acc[i].x = fma(o, x.x, acc[i].x);
+                acc[i].y = fma(o, x.y, acc[i].y);
+              }
             }
           }
-        }
 #pragma unroll
-        for (int i = 0; i < kTileRows; ++i)
-          if (p0 + i < n) cur[(p0 + i) * w + col] = acc[i];
-      }
+          for (int i = 0; i < TR; ++i)
+            if (p0 + i < n) cur[(p0 + i) * w + col] = acc[i];
+        }
+      };
+      // three-row tiles spread the items over more of the workgroup (n = 36: 12 x 17 instead
+      // of 9 x 17 items on 256 threads)
+      if (DBUF && n % 6 == 0) product(std::integral_constant<int, 3>{});
+      else product(std::integral_constant<int, kTileRows>{});
     } else {
       double2* dst = a.xout + (size_t)b * n * xw;
       for (int idx = tid; idx < n * w; idx += kThreads) {
@@ -1528,7 +1536,6 @@ __device__ __forceinline__ void body_backward(const SweepArgs& a, int g, int b) 
   }
   __syncthreads();
 
-  const int nrb = (n + kTileRows - 1) / kTileRows;
   for (int j = a.j_end - 1; j >= a.j_begin; --j) {
     const size_t es = eb0 + (j - a.eig_j0);
     const size_t vs = vb0 + j;
@@ -1601,45 +1608,52 @@ __device__ __forceinline__ void body_backward(const SweepArgs& a, int g, int b) 
       }
       __syncthreads();
       const double* Og = o_prev(j);   // apply its transpose
-      ItemWalk it(tid, w);
-      for (int t = tid; t < nrb * w; t += kThreads, it.next()) {
-        const int rb = it.p, col = it.col;
-        const int p0 = rb * kTileRows;
-        double2 acc[kTileRows];
+      // [lambda_j | Xi_j] = O_{j-1}^T X on tiles of TR rows x 1 column
+      auto product = [&](auto tile_rows) {
+        constexpr int TR = decltype(tile_rows)::value;
+        const int nrb = (n + TR - 1) / TR;
+        ItemWalk it(tid, w);
+        for (int t = tid; t < nrb * w; t += kThreads, it.next()) {
+          const int rb = it.p, col = it.col;
+          const int p0 = rb * TR;
+          double2 acc[TR];
 #pragma unroll
-        for (int i = 0; i < kTileRows; ++i) acc[i] = make_double2(0.0, 0.0);
-        if (STAGE && (n & 3) == 0) {
-          // the tile's four rows p0..p0+3 of O^T (row r of O) in two 16-byte loads
-          const double* Oc = Ob + cb * nn;
+          for (int i = 0; i < TR; ++i) acc[i] = make_double2(0.0, 0.0);
+          if (STAGE && TR == 4 && (n & 3) == 0) {
+            // the tile's four rows p0..p0+3 of O^T (row r of O) in two 16-byte loads
+            const double* Oc = Ob + cb * nn;
 #pragma unroll 2
-          for (int r = 0; r < n; ++r) {
-            const double2 x = X[r * w + col];
-            const double2 o01 = *(const double2*)(Oc + r * n + p0);
-            const double2 o23 = *(const double2*)(Oc + r * n + p0 + 2);
-            const double o[4] = {o01.x, o01.y, o23.x, o23.y};
+            for (int r = 0; r < n; ++r) {
+              const double2 x = X[r * w + col];
+              const double2 o01 = *(const double2*)(Oc + r * n + p0);
+              const double2 o23 = *(const double2*)(Oc + r * n + p0 + 2);
+              const double o[4] = {o01.x, o01.y, o23.x, o23.y};
 #pragma unroll
-            for (int i = 0; i < kTileRows; ++i) {
-              acc[i].x = fma(o[i], x.x, acc[i].x);
-              acc[i].y = fma(o[i], x.y, acc[i].y);
+              for (int i = 0; i < TR; ++i) {
+                acc[i].x = fma(o[i], x.x, acc[i].x);
+                acc[i].y = fma(o[i], x.y, acc[i].y);
+              }
             }
-          }
-        } else {
+          } else {
 #pragma unroll(MODE == kSweepRegs ? 1 : 4)
-          for (int r = 0; r < n; ++r) {
-            const double2 x = X[r * w + col];
+            for (int r = 0; r < n; ++r) {
+              const double2 x = X[r * w + col];
 #pragma unroll
-            for (int i = 0; i < kTileRows; ++i) {
-              const int p = p0 + i;
-              const double o = p < n ? (STAGE ? Ob[cb * nn + (size_t)r * n + p] : Og[(size_t)r * n + p]) : 0.0;
-              acc[i].x = fma(o, x.x, acc[i].x);
-              acc[i].y = fma(o, x.y, acc[i].y);
+              for (int i = 0; i < TR; ++i) {
+                const int p = p0 + i;
+                const double o = p < n ? (STAGE ? Ob[cb * nn + (size_t)r * n + p] : Og[(size_t)r * n + p]) : 0.0;
+                acc[i].x = fma(o, x.x, acc[i].x);
+                acc[i].y = fma(o, x.y, acc[i].y);
+              }
             }
           }
-        }
 #pragma unroll
-        for (int i = 0; i < kTileRows; ++i)
-          if (p0 + i < n) cur[(p0 + i) * w + col] = acc[i];
-      }
+          for (int i = 0; i < TR; ++i)
+            if (p0 + i < n) cur[(p0 + i) * w + col] = acc[i];
+        }
+      };
+      // (three-row tiles with single-element loads of O were measured slower here)
+      product(std::integral_constant<int, kTileRows>{});
       if (FOLD && j > a.j_begin) commit_step(nx, j - 1, cb ^ 1);
       __syncthreads();
       if (!FOLD && j > a.j_begin) {
