@@ -258,6 +258,12 @@ __device__ __forceinline__ double quad_sum(double v) {
   return v;
 }
 __device__ __forceinline__ double2 quad_sum(double2 v) { return make_double2(quad_sum(v.x), quad_sum(v.y)); }
+// Sum over each aligned group of eight lanes (all eight active): the quad sums of the two halves
+// meet through the half-row mirror (lane i of eight reads lane 7 - i).
+__device__ __forceinline__ double oct_sum(double v) {
+  v = quad_sum(v);
+  return v + dpp_move<kDppRowHalfMirror>(v);
+}
 
 // Round-robin ("circle") pairing of np players (np even) in round r of np-1: player np-1
 // meets r; the others pair as (r+k, r-k) mod (np-1).  Every unordered pair meets once per

@@ -1580,15 +1580,15 @@ __device__ __forceinline__ void body_backward(const SweepArgs& a, int g, int b) 
       }
     }
     if (!a.hvp && a.K) {
-      // waves 1.. : four lanes per column, each summing every fourth p
-      for (int t = tid - 64; t >= 0 && t < 4 * ncol; t += kThreads - 64) {
-        const int col = t >> 2, part = t & 3;
+      // waves 1.. : eight lanes per column, each summing every eighth p
+      for (int t = tid - 64; t >= 0 && t < 8 * ncol; t += kThreads - 64) {
+        const int col = t >> 3, part = t & 7;
         double acc = 0.0;
-        for (int p = part; p < n; p += 4) {
+        for (int p = part; p < n; p += 8) {
           const double2 xi = cur[p * w + 1 + col];
           acc += xi.x * yv[p].x + xi.y * yv[p].y;
         }
-        acc = quad_sum(acc);
+        acc = oct_sum(acc);
         if (part == 0) a.K[vs * a.P + c0 + col] = acc;
       }
     }
