@@ -1021,6 +1021,9 @@ __global__ __launch_bounds__(EigWgShape<NP>::TPB, EigWgShape<NP>::WAVES) void k_
 // length-n inner loops are unrolled so that their LDS reads overlap.
 constexpr int kPrefetch = 16;   // doubles per thread per staged n x n matrix (n*n <= 16*256)
 constexpr int kPrefetchSmall = 8;   // n*n <= 8*256: O and S double-buffered in LDS instead
+// register-staged mode: S_j stays in registers of the y / z phase thread (row p, part):
+// S_j[part + 4k][p], k < kSRegs (n <= 64)
+constexpr int kSRegs = 16;
 constexpr int kTileRows = 4;    // rows of the O product per thread (x 1 complex column)
 
 // Sweep variants: kSweepGlobal reads O and S from global memory inside the step (n > 64);
@@ -1070,7 +1073,8 @@ __device__ __forceinline__ void reg_use(double2 v) {
 template <int MODE>
 struct StepStage {
   static constexpr int PF = MODE == kSweepRegs ? kPrefetch : (MODE == kSweepDbuf ? kPrefetchSmall : 1);
-  double po[PF], ps[PF];
+  static constexpr int PS = MODE == kSweepDbuf ? kPrefetchSmall : 1;
+  double po[PF], ps[PS];
   double pl;
   double pf;   // forcing value of column tid + 1 (tid < columns of the group)
 };
@@ -1111,11 +1115,11 @@ __device__ __forceinline__ void body_forward(const SweepArgs& a, int g, int b) {
   const size_t nn = (size_t)n * n;
   constexpr bool STAGE = MODE != kSweepGlobal;
   constexpr bool DBUF = MODE == kSweepDbuf;
-  // kSweepRegs: Ob[r*n + p] = O_j[p][r] (transposed); kSweepDbuf: two buffers each of O_j
-  // (row-major, as stored) and S_j
+  // kSweepRegs: Ob[r*n + p] = O_j[p][r] (transposed), S_j in registers (sreg below);
+  // kSweepDbuf: two buffers each of O_j (row-major, as stored) and S_j
   double* Ob = smem;
   double* Sb = Ob + (STAGE ? nn : 0) * (DBUF ? 2 : 1);
-  double2* cur = (double2*)(Sb + (STAGE ? nn : 0) * (DBUF ? 2 : 1));   // [n][w]
+  double2* cur = (double2*)(Sb + (DBUF ? 2 * nn : 0));   // [n][w]
   double2* X = cur + n * w;         // [n][w]
   double2* hh = X + n * w;          // [n]
   double2* ph = hh + n;             // [n]
@@ -1129,6 +1133,24 @@ __device__ __forceinline__ void body_forward(const SweepArgs& a, int g, int b) {
   const int ph_t = tid - (kThreads - (n <= 64 ? 64 : 128));
   // FOLD: the next step's staged data goes in during the O X product, which reads none of it
   constexpr bool FOLD = MODE != kSweepRegs;
+  // register-staged mode (n <= 64): the y-phase thread for row yp, part ypart keeps
+  // S_j[ypart + 4k][yp] (S symmetric) in sreg[k], loaded after the previous step's y phase; S_j
+  // then needs no LDS, which leaves room for two workgroups per CU at n = 64
+  constexpr bool SREG = MODE == kSweepRegs;
+  constexpr int SR = SREG ? kSRegs : 1;
+  double sreg[SR];
+  const int yp = tid >> 2, ypart = tid & 3;
+  const bool ythread = tid < 4 * n;
+  auto load_s = [&](int j) {
+    if (SREG && a.need_y && ythread) {
+      const double* Sg = a.sm + (eb0 + (j - a.eig_j0)) * nn;
+#pragma unroll
+      for (int k = 0; k < SR; ++k) {
+        const int r = ypart + 4 * k;
+        if (r < n) sreg[k] = Sg[(size_t)r * n + yp];
+      }
+    }
+  };
 
   auto load_step = [&](int j, StepStage<MODE>& st) {
     const size_t es = eb0 + (j - a.eig_j0);
@@ -1140,7 +1162,6 @@ __device__ __forceinline__ void body_forward(const SweepArgs& a, int g, int b) {
       for (int i = 0; i < StepStage<MODE>::PF; ++i) {
         const int idx = tid + i * kThreads;
         st.po[i] = (idx < (int)nn && j + 1 < a.j_end) ? a.ov[es * nn + idx] : 0.0;
-        st.ps[i] = (idx < (int)nn && a.need_y) ? a.sm[es * nn + idx] : 0.0;
       }
     }
     st.pl = (ph_t >= 0 && ph_t < n) ? a.lam[es * n + ph_t] : 0.0;
@@ -1158,7 +1179,6 @@ __device__ __forceinline__ void body_forward(const SweepArgs& a, int g, int b) {
         if (idx < (int)nn) {
           const int pr = idx / n, rr = idx - pr * n;
           Ob[rr * n + pr] = st.po[i];
-          Sb[idx] = st.ps[i];
         }
       }
     }
@@ -1171,11 +1191,16 @@ __device__ __forceinline__ void body_forward(const SweepArgs& a, int g, int b) {
   };
   // on every path through the step, whether or not it loaded or committed st
   auto settle = [&](const StepStage<MODE>& st) {
-    if constexpr (DBUF) {
+    if constexpr (STAGE) {
 #pragma unroll
-      for (int i = 0; i < StepStage<MODE>::PF; ++i) {
-        reg_use(st.po[i]);
-        reg_use(st.ps[i]);
+      for (int i = 0; i < StepStage<MODE>::PF; ++i) reg_use(st.po[i]);
+      if constexpr (DBUF) {
+#pragma unroll
+        for (int i = 0; i < StepStage<MODE>::PS; ++i) reg_use(st.ps[i]);
+      }
+      if constexpr (SREG) {
+#pragma unroll
+        for (int k = 0; k < SR; ++k) reg_use(sreg[k]);
       }
       reg_use(st.pl);
       reg_use(st.pf);
@@ -1217,6 +1242,7 @@ __device__ __forceinline__ void body_forward(const SweepArgs& a, int g, int b) {
   {
     StepStage<MODE> st;
     load_step(a.j_begin, st);
+    load_s(a.j_begin);
     commit_step(st, a.j_begin, 0);
     settle(st);
   }
@@ -1228,8 +1254,30 @@ __device__ __forceinline__ void body_forward(const SweepArgs& a, int g, int b) {
     const int cb = DBUF ? ((j - a.j_begin) & 1) : 0;
     StepStage<MODE> nx;
     if (j + 1 < a.j_end) load_step(j + 1, nx);
-    const double* S = STAGE ? Sb + cb * nn : a.sm + es * nn;
-    if (a.need_y) {
+    if (SREG && a.need_y) {
+      // four adjacent lanes per output row, each summing every fourth r (one pass: 4n <= 256)
+      if (ythread) {
+        double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int k = 0; k < SR; ++k) {
+          const int r = ypart + 4 * k;
+          if (r < n) {
+            const double2 t = c_mul(hh[r], cur[r * w]);
+            acc.x = fma(sreg[k], t.x, acc.x);
+            acc.y = fma(sreg[k], t.y, acc.y);
+          }
+          // at most four r in flight: the hoisted LDS loads would otherwise hold 4 SR registers
+          if ((k & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+        }
+        acc = quad_sum(acc);
+        if (ypart == 0) {
+          const double2 hp = c_mul(hh[yp], acc);
+          yv[yp] = make_double2(a.dt * hp.y, -a.dt * hp.x);   // -i dt * hp
+        }
+      }
+      if (j + 1 < a.j_end) load_s(j + 1);
+    } else if (a.need_y) {
+      const double* S = DBUF ? Sb + cb * nn : a.sm + es * nn;
       // four adjacent lanes per output row, each summing every fourth r
       for (int t4 = tid; t4 < 4 * n; t4 += kThreads) {
         const int p = t4 >> 2, part = t4 & 3;
@@ -1419,7 +1467,8 @@ __global__ __launch_bounds__(kThreads) void k_terminal(TermArgs a) { body_termin
 template <int MODE>
 struct BwdStage {
   static constexpr int PF = MODE == kSweepRegs ? kPrefetch : (MODE == kSweepDbuf ? kPrefetchSmall : 1);
-  double po[PF], ps[PF];
+  static constexpr int PS = MODE == kSweepDbuf ? kPrefetchSmall : 1;
+  double po[PF], ps[PS];
   double pl;
   double2 py, pa;
   double pf;   // forcing value of column tid + 1 (tid < columns of the group)
@@ -1437,8 +1486,8 @@ __device__ __forceinline__ void body_backward(const SweepArgs& a, int g, int b) 
   constexpr bool STAGE = MODE != kSweepGlobal;
   constexpr bool DBUF = MODE == kSweepDbuf;
   double* Ob = smem;                // O_{j-1} as stored: Ob[r*n + p] = O_{j-1}[r][p] (two buffers if DBUF)
-  double* Sb = Ob + (STAGE ? nn : 0) * (DBUF ? 2 : 1);
-  double2* cur = (double2*)(Sb + (STAGE ? nn : 0) * (DBUF ? 2 : 1));
+  double* Sb = Ob + (STAGE ? nn : 0) * (DBUF ? 2 : 1);   // S_j (two buffers if DBUF; none if SREG)
+  double2* cur = (double2*)(Sb + (DBUF ? 2 * nn : 0));
   double2* X = cur + n * w;
   double2* hh = X + n * w;
   double2* ph = hh + n;
@@ -1453,6 +1502,23 @@ __device__ __forceinline__ void body_backward(const SweepArgs& a, int g, int b) 
   const int ph_t = tid - (kThreads - (n <= 64 ? 64 : 128));
   // FOLD: the next step's staged data goes in during the O^T X product, which reads none of it
   constexpr bool FOLD = MODE != kSweepRegs;
+  // register-staged mode (n <= 64): the z-phase thread for row yp, part ypart keeps
+  // S_j[ypart + 4k][yp] (S symmetric) in sreg[k], loaded after the previous step's z phase
+  constexpr bool SREG = MODE == kSweepRegs;
+  constexpr int SR = SREG ? kSRegs : 1;
+  double sreg[SR];
+  const int yp = tid >> 2, ypart = tid & 3;
+  const bool ythread = tid < 4 * n;
+  auto load_s = [&](int j) {
+    if (SREG && ythread) {
+      const double* Sg = a.sm + (eb0 + (j - a.eig_j0)) * nn;
+#pragma unroll
+      for (int k = 0; k < SR; ++k) {
+        const int r = ypart + 4 * k;
+        if (r < n) sreg[k] = Sg[(size_t)r * n + yp];
+      }
+    }
+  };
 
   // O_{jj-1} for step jj >= 1: inside the range from the eigen-data, at the range start from o_in
   auto o_prev = [&](int jj) -> const double* {
@@ -1472,7 +1538,6 @@ __device__ __forceinline__ void body_backward(const SweepArgs& a, int g, int b) 
       for (int i = 0; i < BwdStage<MODE>::PF; ++i) {
         const int idx = tid + i * kThreads;
         st.po[i] = (idx < (int)nn && Op) ? Op[idx] : 0.0;
-        st.ps[i] = idx < (int)nn ? a.sm[es * nn + idx] : 0.0;
       }
     }
     st.pl = (ph_t >= 0 && ph_t < n) ? a.lam[es * n + ph_t] : 0.0;
@@ -1489,10 +1554,7 @@ __device__ __forceinline__ void body_backward(const SweepArgs& a, int g, int b) 
 #pragma unroll
       for (int i = 0; i < BwdStage<MODE>::PF; ++i) {
         const int idx = tid + i * kThreads;
-        if (idx < (int)nn) {
-          Ob[idx] = st.po[i];
-          Sb[idx] = st.ps[i];
-        }
+        if (idx < (int)nn) Ob[idx] = st.po[i];
       }
     }
     if (ph_t >= 0 && ph_t < n) {
@@ -1508,11 +1570,16 @@ __device__ __forceinline__ void body_backward(const SweepArgs& a, int g, int b) 
   };
   // on every path through the step, whether or not it loaded or committed st
   auto settle = [&](const BwdStage<MODE>& st) {
-    if constexpr (DBUF) {
+    if constexpr (STAGE) {
 #pragma unroll
-      for (int i = 0; i < BwdStage<MODE>::PF; ++i) {
-        reg_use(st.po[i]);
-        reg_use(st.ps[i]);
+      for (int i = 0; i < BwdStage<MODE>::PF; ++i) reg_use(st.po[i]);
+      if constexpr (DBUF) {
+#pragma unroll
+        for (int i = 0; i < BwdStage<MODE>::PS; ++i) reg_use(st.ps[i]);
+      }
+      if constexpr (SREG) {
+#pragma unroll
+        for (int k = 0; k < SR; ++k) reg_use(sreg[k]);
       }
       reg_use(st.pl);
       reg_use(st.pf);
@@ -1531,6 +1598,7 @@ __device__ __forceinline__ void body_backward(const SweepArgs& a, int g, int b) 
   {
     BwdStage<MODE> st;
     load_step(a.j_end - 1, st);
+    load_s(a.j_end - 1);
     commit_step(st, a.j_end - 1, 0);
     settle(st);
   }
@@ -1542,21 +1610,45 @@ __device__ __forceinline__ void body_backward(const SweepArgs& a, int g, int b) 
     const int cb = DBUF ? ((a.j_end - 1 - j) & 1) : 0;
     BwdStage<MODE> nx;
     if (j - 1 >= a.j_begin) load_step(j - 1, nx);
-    const double* S = STAGE ? Sb + cb * nn : a.sm + es * nn;
-    for (int t4 = tid; t4 < 4 * n; t4 += kThreads) {
-      // four adjacent lanes per output row, each summing every fourth r
-      const int p = t4 >> 2, part = t4 & 3;
-      double2 acc = make_double2(0.0, 0.0);
-      for (int r = part; r < n; r += 4) {
-        const double2 t = c_mul(hh[r], cur[r * w]);
-        const double sv = S[r * n + p];
-        acc.x = fma(sv, t.x, acc.x);
-        acc.y = fma(sv, t.y, acc.y);
+    if (SREG) {
+      // four adjacent lanes per output row, each summing every fourth r (one pass: 4n <= 256)
+      if (ythread) {
+        double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int k = 0; k < SR; ++k) {
+          const int r = ypart + 4 * k;
+          if (r < n) {
+            const double2 t = c_mul(hh[r], cur[r * w]);
+            acc.x = fma(sreg[k], t.x, acc.x);
+            acc.y = fma(sreg[k], t.y, acc.y);
+          }
+          // at most four r in flight: the hoisted LDS loads would otherwise hold 4 SR registers
+          if ((k & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+        }
+        acc = quad_sum(acc);
+        if (ypart == 0) {
+          const double2 hp = c_mul(hh[yp], acc);
+          zv[yp] = make_double2(-a.dt * hp.y, a.dt * hp.x);   // i dt * hp
+        }
       }
-      acc = quad_sum(acc);
-      if (part == 0) {
-        const double2 hp = c_mul(hh[p], acc);
-        zv[p] = make_double2(-a.dt * hp.y, a.dt * hp.x);   // i dt * hp
+      if (j - 1 >= a.j_begin) load_s(j - 1);
+    } else {
+      const double* S = DBUF ? Sb + cb * nn : a.sm + es * nn;
+      for (int t4 = tid; t4 < 4 * n; t4 += kThreads) {
+        // four adjacent lanes per output row, each summing every fourth r
+        const int p = t4 >> 2, part = t4 & 3;
+        double2 acc = make_double2(0.0, 0.0);
+        for (int r = part; r < n; r += 4) {
+          const double2 t = c_mul(hh[r], cur[r * w]);
+          const double sv = S[r * n + p];
+          acc.x = fma(sv, t.x, acc.x);
+          acc.y = fma(sv, t.y, acc.y);
+        }
+        acc = quad_sum(acc);
+        if (part == 0) {
+          const double2 hp = c_mul(hh[p], acc);
+          zv[p] = make_double2(-a.dt * hp.y, a.dt * hp.x);   // i dt * hp
+        }
       }
     }
     __syncthreads();
@@ -2220,7 +2312,9 @@ static bool sweep_stage(int n) { return n * n <= kPrefetch * kThreads; }
 static bool sweep_small(int n) { return (n & 1) == 0 && n * n <= kPrefetchSmall * kThreads; }
 
 static size_t sweep_lds_bytes(int n, int pg) {
-  const size_t mats = (sweep_small(n) ? 4 : (sweep_stage(n) ? 2 : 0)) * (size_t)n * n * sizeof(double);
+  // double-buffered mode: O_j and S_j, two buffers each; register-staged mode: O_j only (S_j
+  // stays in registers)
+  const size_t mats = (sweep_small(n) ? 4 : (sweep_stage(n) ? 1 : 0)) * (size_t)n * n * sizeof(double);
   return mats + ((size_t)2 * n * (1 + pg) + 5 * n) * sizeof(double2) + (size_t)kMaxPg * sizeof(double);
 }
 
