@@ -503,7 +503,9 @@ struct EigWgShape<64> {
   static constexpr bool VP_LDS = false;
   static constexpr int VW0 = 1, VW = 4;
   static constexpr int VS = 8;
-  static constexpr int WAVES = 4;
+  // one problem per CU without spills (256 VGPRs) beats two per CU at 128 VGPRs with about 130
+  // spilled registers per thread (683 against 754 ms for 256 theta x 4000 steps)
+  static constexpr int WAVES = 2;
 };
 
 // Largest |F_ik| / |d_k - d_i| over the off-diagonal part F of the current A = diag(d) + F at
