@@ -55,6 +55,13 @@ CASES = [
     ("wide-spread-dt0.8", "tiny", dict(n=6, nt=20, dt=0.8, k=2), 0.5),
     # n above the LDS staging limit of the sweeps, odd, ragged chunks
     ("n67-unstaged", "tiny", dict(n=67, nt=21, k=2), 0.2),
+    # sweep product and staging paths by n: three-row tiles with n = 2 mod 4 (18), four-row
+    # paired tiles with a partly filled last staging slot (44), the generic tile path (22), and
+    # the register-staged mode with even n (50)
+    ("dbuf-n18-tiles3", "tiny", dict(n=18, nt=40, k=3), 0.2),
+    ("dbuf-n44-pairs", "tiny", dict(n=44, nt=30, k=2), 0.2),
+    ("dbuf-n22-generic", "tiny", dict(n=22, nt=30, k=2), 0.2),
+    ("regs-n50-even", "tiny", dict(n=50, nt=25, k=2), 0.2),
 ]
 
 
