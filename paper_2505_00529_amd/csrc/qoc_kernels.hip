@@ -1140,7 +1140,7 @@ __device__ __forceinline__ void body_forward(const SweepArgs& a, int g, int b) {
   // then needs no LDS, which leaves room for two workgroups per CU at n = 64
   constexpr bool SREG = MODE == kSweepRegs;
   constexpr int SR = SREG ? kSRegs : 1;
-  double sreg[SR];
+  double sreg[SR] = {};
   const int yp = tid >> 2, ypart = tid & 3;
   const bool ythread = tid < 4 * n;
   auto load_s = [&](int j) {
@@ -1242,7 +1242,7 @@ __device__ __forceinline__ void body_forward(const SweepArgs& a, int g, int b) {
     }
   }
   {
-    StepStage<MODE> st;
+    StepStage<MODE> st{};
     load_step(a.j_begin, st);
     load_s(a.j_begin);
     commit_step(st, a.j_begin, 0);
@@ -1250,11 +1250,12 @@ __device__ __forceinline__ void body_forward(const SweepArgs& a, int g, int b) {
   }
   __syncthreads();
 
+  // the next step's registers live across the loop (settle reads all of them every step)
+  StepStage<MODE> nx{};
   for (int j = a.j_begin; j < a.j_end; ++j) {
     const size_t es = eb0 + (j - a.eig_j0);
     const size_t vs = vb0 + j;
     const int cb = DBUF ? ((j - a.j_begin) & 1) : 0;
-    StepStage<MODE> nx;
     if (j + 1 < a.j_end) load_step(j + 1, nx);
     if (SREG && a.need_y) {
       // four adjacent lanes per output row, each summing every fourth r (one pass: 4n <= 256)
@@ -1508,7 +1509,7 @@ __device__ __forceinline__ void body_backward(const SweepArgs& a, int g, int b) 
   // S_j[ypart + 4k][yp] (S symmetric) in sreg[k], loaded after the previous step's z phase
   constexpr bool SREG = MODE == kSweepRegs;
   constexpr int SR = SREG ? kSRegs : 1;
-  double sreg[SR];
+  double sreg[SR] = {};
   const int yp = tid >> 2, ypart = tid & 3;
   const bool ythread = tid < 4 * n;
   auto load_s = [&](int j) {
@@ -1598,7 +1599,7 @@ __device__ __forceinline__ void body_backward(const SweepArgs& a, int g, int b) 
     cur[idx] = v;
   }
   {
-    BwdStage<MODE> st;
+    BwdStage<MODE> st{};
     load_step(a.j_end - 1, st);
     load_s(a.j_end - 1);
     commit_step(st, a.j_end - 1, 0);
@@ -1606,11 +1607,12 @@ __device__ __forceinline__ void body_backward(const SweepArgs& a, int g, int b) 
   }
   __syncthreads();
 
+  // the next step's registers live across the loop (settle reads all of them every step)
+  BwdStage<MODE> nx{};
   for (int j = a.j_end - 1; j >= a.j_begin; --j) {
     const size_t es = eb0 + (j - a.eig_j0);
     const size_t vs = vb0 + j;
     const int cb = DBUF ? ((a.j_end - 1 - j) & 1) : 0;
-    BwdStage<MODE> nx;
     if (j - 1 >= a.j_begin) load_step(j - 1, nx);
     if (SREG) {
       // four adjacent lanes per output row, each summing every fourth r (one pass: 4n <= 256)
