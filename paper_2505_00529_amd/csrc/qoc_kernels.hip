@@ -509,8 +509,9 @@ struct EigWgShape<64> {
 };
 
 // Largest |F_ik| / |d_k - d_i| over the off-diagonal part F of the current A = diag(d) + F at
-// which the remaining Jacobi sweeps are replaced by the first-order eigenvector correction.
-constexpr double kJacobiFinishRatio = 1e-8;
+// which the remaining Jacobi sweeps are replaced by the second-order perturbative finish (its
+// errors are of third order in this ratio: below 1e-15 relative at 1e-5).
+constexpr double kJacobiFinishRatio = 1e-5;
 
 // Slot that slot x moves to in the circle shift after a round.
 template <int NP>
@@ -718,11 +719,15 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
         break;
       }
       if (sweep > 0 && wg_max<TPB>(excess, red) <= 0.0) {
-        // First-order finish: with A = diag(d) + F and every |F_ik| <= 1e-8 |d_k - d_i|, the
-        // eigenvectors are the columns of I + E, E_ik = F_ik / (d_k - d_i) (antisymmetric), to
-        // within terms of order |E|^2, and the eigenvalues are d to within |F| |E|.  So
-        // V_j = V (I + E) and lambda_j = d replace the remaining sweeps.
-        // E^T goes into A's buffer in place (Ac[k][i] = E_ik), V into the other one.
+        // Perturbative finish: with A = diag(d) + F and every |F_ik| <= 1e-5 |d_k - d_i|, the
+        // eigenvectors are the columns of W = I + E + E2 and the eigenvalues are
+        // d_k + sum_i F_ik E_ik, to within terms of third order in E, where
+        //   E_ik = F_ik / (d_k - d_i)                       (first order, antisymmetric),
+        //   E2_ik = (F E)_ik / (d_k - d_i) (i != k),  E2_kk = -1/2 sum_i E_ik^2
+        // (Rayleigh-Schroedinger perturbation theory about diag(d); F has a zero diagonal).
+        // So V_j = V W and those eigenvalues replace the remaining sweeps.  E^T goes into A's
+        // buffer in place (Ac[k][i] = E_ik), V into the other one; the second-order terms are
+        // formed below from E alone.
         for (int idx = tid; idx < NP * NP; idx += TPB) {
           const int i = idx / NP, k = idx - (idx / NP) * NP;
           if (i < k) {
@@ -849,11 +854,71 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
     }
     // lambda_j is in lamv (set at the last sweep boundary); V_j to Vt
     if (finished) {
-      // V_j = V + V E from V (in Vo) and E^T (in Ac): tile (x, y) is column k = i0 + x, row
-      // i = k0 + y
-      const double* Ac = cur ? Vt : A;
+      double* Ac = cur ? Vt : A;
       const double* Vo = cur ? A : Vt;
       __syncthreads();
+      // Second-order terms from E alone.  F_im = E_im (d_m - d_i) and E is antisymmetric, so
+      // rows of Ac serve both factors of (F E)_ik = sum_m E_im (d_m - d_i) E_mk, with
+      // E_im (d_m - d_i) = Ac[i][m] (d_i - d_m) and E_mk = Ac[k][m].  The diagonal needs only
+      // column sums: E2_kk = -s1_k / 2 and lambda_k = d_k + d_k s1_k - s2_k with
+      // s1_k = sum_i E_ik^2, s2_k = sum_i E_ik^2 d_i.
+      // Tile (x, y) is column k = i0 + x, row i = k0 + y, as in the product below.
+      double lam_new = 0.0;
+      {
+        double fe[RT][CT];
+        if (has_tile) {
+          double di[CT];
+#pragma unroll
+          for (int y = 0; y < CT; ++y) di[y] = lamv[k0 + y];
+#pragma unroll
+          for (int x = 0; x < RT; ++x)
+#pragma unroll
+            for (int y = 0; y < CT; ++y) fe[x][y] = 0.0;
+#pragma unroll 2
+          for (int r = 0; r < NP; r += 2) {
+            double2 u[RT], w[CT];
+#pragma unroll
+            for (int x = 0; x < RT; ++x) u[x] = *(const double2*)(Ac + (i0 + x) * NP + r);   // E_{r,k}, E_{r+1,k}
+            const double d0 = lamv[r], d1 = lamv[r + 1];
+#pragma unroll
+            for (int y = 0; y < CT; ++y) {
+              const double2 q = *(const double2*)(Ac + (k0 + y) * NP + r);   // -E_{i,r}, -E_{i,r+1}
+              w[y] = make_double2(q.x * (di[y] - d0), q.y * (di[y] - d1));   // F_{i,r}, F_{i,r+1}
+            }
+#pragma unroll
+            for (int x = 0; x < RT; ++x)
+#pragma unroll
+              for (int y = 0; y < CT; ++y) fe[x][y] = fma(u[x].y, w[y].y, fma(u[x].x, w[y].x, fe[x][y]));
+          }
+        }
+        double s1 = 0.0, s2 = 0.0;
+        if (tid < NP) {
+          for (int i = 0; i < NP; i += 2) {
+            const double2 q = *(const double2*)(Ac + tid * NP + i);   // E_{i,k}, E_{i+1,k}, k = tid
+            const double q0 = q.x * q.x, q1 = q.y * q.y;
+            s1 += q0 + q1;
+            s2 = fma(q0, lamv[i], fma(q1, lamv[i + 1], s2));
+          }
+        }
+        __syncthreads();   // every row of Ac read
+        if (has_tile) {
+#pragma unroll
+          for (int x = 0; x < RT; ++x)
+#pragma unroll
+            for (int y = 0; y < CT; ++y) {
+              const int k = i0 + x, i = k0 + y;
+              const double den = lamv[k] - lamv[i];
+              if (i != k && den != 0.0) Ac[k * NP + i] += fe[x][y] / den;   // (E + E2)^T
+            }
+        }
+        if (tid < NP) {
+          Ac[tid * NP + tid] = -0.5 * s1;
+          lam_new = lamv[tid] + lamv[tid] * s1 - s2;   // written to lamv once no thread reads it
+        }
+      }
+      // V_j = V + V (W - I) from V (in Vo) and (W - I)^T (in Ac)
+      __syncthreads();
+      if (tid < NP) lamv[tid] = lam_new;   // the product below reads only Ac and Vo
       double acc[RT][CT];
       if (has_tile) {
 #pragma unroll
