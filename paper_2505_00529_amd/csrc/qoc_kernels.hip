@@ -1926,6 +1926,8 @@ __device__ __forceinline__ double2 sterm_moments(const double* Mt, const double*
       P[k] = make_double2(0.0, 0.0);
       Q[k] = make_double2(0.0, 0.0);
     }
+    // unrolled so that several rows' M~ loads are in flight at once
+#pragma unroll 4
     for (int qi = 0; qi < n; ++qi) {
       const double xq = lam[qi] - m0;
       const double2 muq = mu[qi], atq = at[qi];
