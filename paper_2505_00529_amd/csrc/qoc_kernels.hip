@@ -1350,6 +1350,7 @@ __device__ __forceinline__ void body_forward(const SweepArgs& a, int g, int b) {
       for (int t4 = tid; t4 < 4 * n; t4 += kThreads) {
         const int p = t4 >> 2, part = t4 & 3;
         double2 acc = make_double2(0.0, 0.0);
+#pragma unroll(MODE == kSweepGlobal ? 4 : 1)   // S_j from global memory: loads in flight
         for (int r = part; r < n; r += 4) {
           const double2 t = c_mul(hh[r], cur[r * w]);
           const double sv = S[r * n + p];   // S symmetric
@@ -1707,6 +1708,7 @@ __device__ __forceinline__ void body_backward(const SweepArgs& a, int g, int b) 
         // four adjacent lanes per output row, each summing every fourth r
         const int p = t4 >> 2, part = t4 & 3;
         double2 acc = make_double2(0.0, 0.0);
+#pragma unroll(MODE == kSweepGlobal ? 4 : 1)   // S_j from global memory: loads in flight
         for (int r = part; r < n; r += 4) {
           const double2 t = c_mul(hh[r], cur[r * w]);
           const double sv = S[r * n + p];
