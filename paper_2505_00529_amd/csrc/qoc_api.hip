@@ -107,7 +107,7 @@ namespace qoc {
 size_t layout_work(Work& nw, int n, int nt, int P, int nb, int seg, int chunk_req, void* base) {
   const int np = pad_even(n);
   const int eig_stride = seg > 0 ? std::min(seg, nt) : nt;
-  const int chunk = chunk_req > 0 ? std::min(chunk_req, eig_stride) : eig_chunk_len(eig_stride, nb);
+  const int chunk = chunk_req > 0 ? std::min(chunk_req, eig_stride) : eig_chunk_len(eig_stride, nb, np);
   const int nchunks = (eig_stride + chunk - 1) / chunk;
   const int nseg = (nt + eig_stride - 1) / eig_stride;
   const size_t ntn = (size_t)nt * n, nn = (size_t)n * n;

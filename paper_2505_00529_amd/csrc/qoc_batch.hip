@@ -582,7 +582,7 @@ qoc_status qoc_batch_create(int device, int32_t count, qoc_problem* const* probl
     q.w.status = b->d_status;
     q.w.stats = nullptr;
     // defaults: about 2048 eigen chunks in flight per class, 8 tangent columns per workgroup
-    b->set_chunk(i, eig_chunk_len(q.nt, per_cls[b->cls_of[i]]));
+    b->set_chunk(i, eig_chunk_len(q.nt, per_cls[b->cls_of[i]], pad_even(q.n)));
     q.pg = std::min(8, std::max(1, q.P));
   }
   if (e == hipSuccess) e = hipStreamSynchronize(b->stream);

@@ -212,7 +212,7 @@ hipError_t launch_eig(const SysDev& sy, const BasisDev& bs, Work& w, bool store_
 hipError_t launch_boundary(Work& w, hipStream_t stream);
 // Segment join for checkpointed sweeps: obound_s = V_first^T vsave (if do_overlap), vsave = V_last.
 hipError_t launch_seg_join(Work& w, double* obound_s, bool do_overlap, hipStream_t stream);
-int eig_chunk_len(int seg_len, int nb);
+int eig_chunk_len(int seg_len, int nb, int np);
 hipError_t launch_forward(const SysDev& sy, const BasisDev& bs, Work& w, Mode mode, hipStream_t stream);
 hipError_t launch_terminal(const SysDev& sy, const BasisDev& bs, Work& w, Mode mode, double rho,
                            hipStream_t stream);

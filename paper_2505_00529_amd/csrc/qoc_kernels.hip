@@ -2409,9 +2409,14 @@ size_t eig_scratch_doubles(int n, int nb, int nchunks) {
   return (size_t)nb * nchunks * 4 * np * np;
 }
 
-int eig_chunk_len(int seg_len, int nb) {
-  // enough chunks in flight to fill the device (about 2048 workgroups) but at least 8 steps each
-  const int target = std::max(1, (2048 + nb - 1) / nb);
+int eig_chunk_len(int seg_len, int nb, int np) {
+  // enough chunks to fill the device, at least 8 steps each.  NP = 36 (four workgroups per
+  // CU): about 6144, whose smaller granules balance the uneven sweep counts of the chunks
+  // better than 2048 (molecule workload, 256 theta: eig 79.5 -> 76.4 ms) and outweigh the extra
+  // cold starts; at NP = 64 (one workgroup per CU) the extra cold starts cost more (680 -> 697
+  // ms), so 2048 there and for the other kernels.
+  const int total = np == 36 ? 6144 : 2048;
+  const int target = std::max(1, (total + nb - 1) / nb);
   return std::max(8, (seg_len + target - 1) / target);
 }
 
