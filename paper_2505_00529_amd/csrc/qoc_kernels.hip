@@ -688,7 +688,7 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
     for (int idx = tid; idx < NP * NP; idx += TPB) loc = fma(A[idx], A[idx], loc);
     const double tol = a.tol_rel * sqrt(wg_sum<TPB>(loc, red));
     int cur = 0, rb = 0;                           // current A buffer and rotation buffer
-    bool finished = false;                         // V_j already in Vt (first-order finish)
+    bool finished = false;                         // perturbative finish taken (V_j formed below)
 #pragma unroll 1
     for (int sweep = 0;; ++sweep) {
       double* Ac = cur ? Vt : A;
@@ -1082,10 +1082,10 @@ __global__ __launch_bounds__(EigWgShape<NP>::TPB, EigWgShape<NP>::WAVES) void k_
 // ---------------------------------------------------------------- sweeps
 
 
-// Sweep kernels keep the current step's O, S and lambda in LDS (STAGE: n <= 64) and load the
-// next step's into registers while the current step computes, so the dependent chain of
-// steps never waits on HBM.  Product tiles are 4 rows x 1 complex column per thread, and the
-// length-n inner loops are unrolled so that their LDS reads overlap.
+// Sweep kernels (n <= 64) keep the current step's O (and, double-buffered, S) in LDS and load
+// the next step's into registers while the current step computes, so the dependent chain of
+// steps never waits on HBM.  Product tiles are 4 (or 3) rows x 1 complex column per thread, and
+// the length-n inner loops are unrolled so that their LDS reads overlap.
 constexpr int kPrefetch = 16;   // doubles per thread per staged n x n matrix (n*n <= 16*256)
 constexpr int kPrefetchSmall = 8;   // n*n <= 8*256: O and S double-buffered in LDS instead
 // register-staged mode: S_j stays in registers of the y / z phase thread (row p, part):
