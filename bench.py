@@ -74,23 +74,70 @@ def log(msg: str) -> None:
     sys.stderr.flush()
 
 
-def cpu_baseline(w) -> dict:
-    """The CPU oracle timed on one theta of the same workload (full cost + grad + Hessian)."""
-    from oracle import qoc_oracle as O
+def cpu_model() -> str:
     try:
-        from threadpoolctl import threadpool_info
-        threads = max([int(x.get("num_threads", 1)) for x in threadpool_info()] or [1])
-    except Exception:  # pragma: no cover
-        threads = os.cpu_count() or 1
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(w, single_thread_steps: int = 1000) -> dict:
+    """The CPU oracle timed on the host cores: one theta of the same workload (full cost + grad +
+    Hessian) with every BLAS thread, and the first `single_thread_steps` steps of it on one
+    thread (the oracle's time is linear in the steps; the rate is scaled to the full horizon)."""
+    from oracle import qoc_oracle as O
+    from threadpoolctl import threadpool_info, threadpool_limits
+
+    threads = max([int(x.get("num_threads", 1)) for x in threadpool_info()] or [1])
     s = w.system
     basis = O.fourier_basis(w.nt, w.dt, w.k)
     th = inputs.draw_thetas(w.p, 1, w.seed)[0]
     t0 = time.perf_counter()
     O.cost_grad_hess(s.h0, s.m, s.psi0, s.psi_target, basis, w.dt, th, w.gamma, w.rho)
     dt = time.perf_counter() - t0
+    ns = min(single_thread_steps, w.nt)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        O.cost_grad_hess(s.h0, s.m, s.psi0, s.psi_target, basis[:ns], w.dt, th, w.gamma, w.rho)
+        dt1 = (time.perf_counter() - t0) * w.nt / ns
     return {"value": 1.0 / dt, "unit": "evals/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(),
             "sample": f"1 theta of the same workload (N={s.n}, J={w.nt}, P={w.p}), full cost+grad+Hessian, "
-                      f"{dt:.1f} s; forward-over-forward oracle with block-triangular exponentials"}
+                      f"{dt:.1f} s on {threads} BLAS threads; forward-over-forward oracle with "
+                      "block-triangular exponentials",
+            "single_thread": {"value": 1.0 / dt1, "unit": "evals/s", "cores": 1,
+                              "sample": f"the first {ns} of the {w.nt} steps of the same theta on one thread, "
+                                        f"{dt1 * ns / w.nt:.1f} s, scaled to the full horizon"}}
+
+
+GOLDEN = os.path.join(ROOT, "tests", "golden", "molecule_oracle.json")
+PARITY_TOL = 1e-10
+
+
+def parity_vs_oracle(costs, grads, hess) -> dict:
+    """Normwise relative error of the timed batch's thetas 0 and 1 (the benchmark draws the
+    stored oracle cases first) against the CPU oracle's values for them."""
+    with open(GOLDEN) as f:
+        doc = json.load(f)
+
+    def rel(a, b):
+        b = np.asarray(b)
+        return float(np.linalg.norm(np.asarray(a) - b) / max(np.linalg.norm(b), 1e-300))
+
+    errs = {}
+    for case in doc["cases"]:
+        i = case["theta_index"]
+        errs[f"theta{i}"] = {"cost": rel(costs[i], case["cost"]), "grad": rel(grads[i], case["grad"]),
+                             "hess": rel(hess[i], case["hess"])}
+    worst = max(v for e in errs.values() for v in e.values())
+    return {"max_rel_err": worst, "tolerance": PARITY_TOL, "ok": worst < PARITY_TOL, "per_theta": errs,
+            "reference": "oracle values of thetas 0 and 1 (tests/golden/molecule_oracle.json)"}
 
 
 def run_batched(args) -> int:
@@ -174,6 +221,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--batch", type=int, default=256, help="independent theta per step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--latency-calls", type=int, default=30, help="single-theta calls timed for the latency")
     ap.add_argument("--tr-solves", type=int, default=32, help="plain trust-region solves timed after the steps")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after timing, run one device-to-device copy of this many MiB (a reference "
@@ -243,7 +291,44 @@ def main() -> int:
     peak = PEAK_FP64 / 1e12
 
     h = hess.cpu().numpy()
-    assert np.all(np.isfinite(h)) and np.all(np.isfinite(costs.cpu().numpy()))
+    c_np = costs.cpu().numpy()
+    g_np = grads.cpu().numpy()
+    assert np.all(np.isfinite(h)) and np.all(np.isfinite(c_np))
+    parity = parity_vs_oracle(c_np, g_np, h)
+    log(f"bench: parity of the timed batch against the oracle: max rel err {parity['max_rel_err']:.2e}")
+
+    # single-problem latency (B = 1) on its own handle, so the batch workspace stays in place
+    single = qoc.problem_from_workload(w, device=0)
+    single.set_stream(stream.cuda_stream)
+    th1 = thetas[:1].clone()
+    c1 = torch.empty(1, dtype=torch.float64, device="cuda")
+    g1 = torch.empty(1, P, dtype=torch.float64, device="cuda")
+    h1 = torch.empty(1, P, P, dtype=torch.float64, device="cuda")
+    n_lat = max(args.latency_calls, 1)
+    for _ in range(3):
+        single.hess_many_dev(1, th1.data_ptr(), c1.data_ptr(), g1.data_ptr(), h1.data_ptr())
+    single.sync()
+    lev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * n_lat)]
+    for i in range(n_lat):
+        lev[2 * i].record(stream)
+        single.hess_many_dev(1, th1.data_ptr(), c1.data_ptr(), g1.data_ptr(), h1.data_ptr())
+        lev[2 * i + 1].record(stream)
+    single.sync()
+    lat_ms = np.array([lev[2 * i].elapsed_time(lev[2 * i + 1]) for i in range(n_lat)])
+    th1_host = th1.cpu().numpy()[0]
+    hw = []
+    for _ in range(5):
+        ta = time.perf_counter()
+        single.hess(th1_host)
+        hw.append(time.perf_counter() - ta)
+    single.close()
+    latency = {"ms_median": float(np.median(lat_ms)),
+               "ms_iqr": [float(np.percentile(lat_ms, 25)), float(np.percentile(lat_ms, 75))],
+               "calls": n_lat, "evals_per_s": 1e3 / float(np.median(lat_ms)),
+               "path_roofline_frac": None,
+               "host_wall_ms_per_abi_call": 1e3 * float(np.median(hw))}
+    log(f"bench: single-theta latency {latency['ms_median']:.2f} ms (device), "
+        f"{latency['host_wall_ms_per_abi_call']:.2f} ms per host ABI call")
 
     # gradient only (cost + adjoint gradient, same thetas): the Hessian-to-gradient time ratio
     th_host = thetas.cpu().numpy()
@@ -260,11 +345,20 @@ def main() -> int:
     if args.tr_solves > 0:
         tgs = inputs.warm_targets(n, args.tr_solves, spawn=2, dim=6)
         tt0 = time.perf_counter()
-        _, _, its, conv = prob.tr_solve_many(np.zeros((args.tr_solves, P)), tgs, gtol=1e-8, max_iter=1000)
+        th_out, _, its, conv = prob.tr_solve_many(np.zeros((args.tr_solves, P)), tgs, gtol=1e-8, max_iter=1000)
         tt = time.perf_counter() - tt0
+        _, g_out, _ = prob.hess_many_targets(th_out, tgs)
+        gn, pn = prob.gradient_norms(g_out)
         tr = {"solves": args.tr_solves, "seconds": tt, "solves_per_s": args.tr_solves / tt,
-              "iters_mean": float(its.mean()), "converged": int(conv.sum()),
-              "note": "zero start, gradient norm < 1e-8 on the controllable subspace, lockstep batch"}
+              "iters_mean": float(its.mean()), "iters_median": float(np.median(its)),
+              "converged": int(conv.sum()),
+              "grad_norm_max": float(gn.max()), "grad_norm_median": float(np.median(gn)),
+              "projected_grad_norm_max": float(pn.max()),
+              "below_1e-8_grad_norm": int((gn < 1e-8).sum()),
+              "below_1e-8_projected": int((pn < 1e-8).sum()),
+              "note": "zero start; 'converged' counts ||V_r^T g||_2 < 1e-8 (the directions of the control "
+                      "basis with singular value above 1e-7 of the largest); ||g||_2 reported beside it; "
+                      "lockstep batch"}
         log(f"bench: {args.tr_solves} trust-region solves in {tt:.1f} s")
 
     elapsed = t1 - t0
@@ -306,7 +400,10 @@ def main() -> int:
         "jacobi_sweeps_per_step": eig_sweeps / max(eig_steps, 1),
         "path_alg_flops_per_eval": f_alg,
         "path_roofline_frac": f_alg * value / PEAK_FP64,
+        "parity": parity,
+        "single_theta_latency": latency,
     }
+    latency["path_roofline_frac"] = f_alg * latency["evals_per_s"] / PEAK_FP64
     if args.calib_copy_mib > 0:
         nel = args.calib_copy_mib * (1 << 20) // 8
         src = torch.ones(nel, dtype=torch.float64, device="cuda")
@@ -321,6 +418,9 @@ def main() -> int:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)
     prob.close()
+    if not parity["ok"]:
+        log(f"bench: PARITY FAILURE: max rel err {parity['max_rel_err']:.3e} above {PARITY_TOL:g}")
+        return 1
     return 0
 
 

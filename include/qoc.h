@@ -23,7 +23,8 @@
  *  - *_dev entry points take device pointers valid on the handle's stream and only
  *    enqueue work on that stream; the caller keeps the buffers alive until the stream
  *    has passed them.  Device-side failures of a *_dev call (Jacobi non-convergence)
- *    are reported by qoc_sync(handle).
+ *    are reported by qoc_sync(handle); every evaluation clears the handle's device status
+ *    word when it starts, so qoc_sync reports the most recent evaluation enqueued.
  *  - A handle is not thread-safe; separate handles are independent.
  *  - psi0 and psi_target are used as given (not normalised).  The Hessian is returned
  *    symmetric by construction (the two-sweep form of the second-order adjoint).
@@ -121,6 +122,12 @@ qoc_status qoc_sync(qoc_problem* p);
 qoc_status qoc_step_propagators(qoc_problem* p, const double* theta, int32_t j,
                                 double* u, double* u1, double* u2);
 
+/* Cap on the cyclic Jacobi sweeps per step's eigendecomposition (default 40; 0..1000).  A step
+ * that is not diagonal to the stopping tolerance within the cap ends the kernel normally with its
+ * current rotation and raises QOC_ERR_NOCONV for the call (host-pointer calls: returned, outputs
+ * untouched; *_dev calls: reported by qoc_sync).  A low cap is a way to exercise that path. */
+qoc_status qoc_set_jacobi_sweep_cap(qoc_problem* p, int32_t max_sweeps);
+
 /* Checkpoint interval (steps) for the cost / gradient / HVP paths: 0 stores every step's
  * eigen-data; k > 0 keeps only states every k steps and recomputes one segment's
  * eigen-data at a time in the backward sweep (the memory reduction the paper names as
@@ -149,6 +156,12 @@ qoc_status qoc_tr_solve(qoc_problem* p, const double* theta0, double gtol, int32
 qoc_status qoc_tr_solve_many(qoc_problem* p, int32_t count, const double* theta0, const double* targets,
                              double gtol, int32_t max_iter, double* theta_out, double* cost_out,
                              int32_t* iters_out, int32_t* converged_out);
+
+/* Both stationarity measures of `count` gradients (count x P): gnorm_out[i] = ||g_i||_2 and
+ * proj_out[i] = ||V_r^T g_i||_2, the measure the trust-region solve stops on (either output may
+ * be NULL).  They agree for a well-conditioned control basis. */
+qoc_status qoc_tr_gradient_norms(qoc_problem* p, int32_t count, const double* grads, double* gnorm_out,
+                                 double* proj_out);
 
 /* Coordinates of the trust-region metric: c = diag(sigma_r) V_r^T theta (count x P doubles
  * out; entries past the rank are 0), so that ||c|| = ||B theta|| on the kept subspace, and the

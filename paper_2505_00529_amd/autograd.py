@@ -12,6 +12,11 @@ stream).
 
 With ``problem.set_checkpoint_interval(k)`` both the gradient and the HVP keep eigen-data for
 k steps at a time and recompute it segment by segment in their backward sweeps.
+
+Every forward and backward waits for its evaluation and checks the handle's device status
+(``problem.sync()``), so that a device-side failure (a Jacobi step that reached the sweep cap,
+``QOC_ERR_NOCONV``) raises ``qoc.QocError`` in the call that produced it instead of returning a
+tensor.
 """
 from __future__ import annotations
 
@@ -40,6 +45,7 @@ class QocGrad(torch.autograd.Function):
         th = _prepare(theta, problem)
         g = torch.empty_like(th)
         problem.grad_dev(th.data_ptr(), None, g.data_ptr())
+        problem.sync()
         ctx.problem = problem
         ctx.save_for_backward(th)
         return g
@@ -51,6 +57,7 @@ class QocGrad(torch.autograd.Function):
         vv = _prepare(v.to(torch.float64), problem)
         hv = torch.empty_like(th)
         problem.hvp_dev(th.data_ptr(), vv.data_ptr(), hv.data_ptr())
+        problem.sync()
         return hv, None
 
 
@@ -60,6 +67,7 @@ class QocCost(torch.autograd.Function):
         th = _prepare(theta, problem)
         c = torch.empty((), dtype=torch.float64, device=th.device)
         problem.cost_dev(th.data_ptr(), c.data_ptr())
+        problem.sync()
         ctx.problem = problem
         ctx.save_for_backward(theta)
         return c

@@ -221,6 +221,10 @@ qoc_status qoc_problem::enqueue(Mode mode, int nb, const double* d_theta, const 
   const bool ck = ckpt > 0 && ckpt < nt && mode != Mode::Hess;
   qoc_status st = ensure_work(nb, ck ? ckpt : 0);
   if (st != QOC_OK) return st;
+  // The status word reports this evaluation only: clear it first, with a kernel rather than a
+  // memset node, so that the sequence stays valid under stream capture.
+  hipError_t e0 = launch_fill_int(d_status, 1, 0, stream);
+  if (e0 != hipSuccess) return hip_fail(e0, "status reset");
   SysDev sy;
   sy.n = n;
   sy.h0 = d_h0;
@@ -748,6 +752,13 @@ qoc_status qoc_step_propagators(qoc_problem* p, const double* theta, int32_t j, 
   if (u) std::memcpy(u, h.data(), sizeof(double) * nn2);
   if (u1) std::memcpy(u1, h.data() + nn2, sizeof(double) * nn2);
   if (u2) std::memcpy(u2, h.data() + 2 * nn2, sizeof(double) * nn2);
+  return QOC_OK;
+}
+
+qoc_status qoc_set_jacobi_sweep_cap(qoc_problem* p, int32_t max_sweeps) {
+  if (!p) return QOC_ERR_INVALID_ARG;
+  if (max_sweeps < 0 || max_sweeps > 1000) return p->fail(QOC_ERR_INVALID_ARG, "sweep cap must be in [0, 1000]");
+  p->jacobi_max_sweeps = max_sweeps;
   return QOC_OK;
 }
 

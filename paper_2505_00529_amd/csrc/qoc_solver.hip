@@ -456,6 +456,31 @@ qoc_status qoc_params_from_coords(qoc_problem* p, int32_t count, const double* c
   return QOC_OK;
 }
 
+qoc_status qoc_tr_gradient_norms(qoc_problem* p, int32_t count, const double* grads, double* gnorm_out,
+                                 double* proj_out) {
+  if (!p) return QOC_ERR_INVALID_ARG;
+  qoc_status st = p->ready();
+  if (st != QOC_OK) return st;
+  if (count < 1 || !grads) return p->fail(QOC_ERR_INVALID_ARG, "grads NULL or count < 1");
+  st = ensure_whitening(p);
+  if (st != QOC_OK) return st;
+  const int P = p->P, R = p->tr_rank;
+  for (int i = 0; i < count; ++i) {
+    const double* g = grads + (size_t)i * P;
+    if (gnorm_out) gnorm_out[i] = norm2(g, P);
+    if (proj_out) {
+      double acc2 = 0.0;
+      for (int r = 0; r < R; ++r) {
+        double acc = 0.0;
+        for (int a = 0; a < P; ++a) acc += p->tr_vr[(size_t)a * R + r] * g[a];
+        acc2 += acc * acc;
+      }
+      proj_out[i] = std::sqrt(acc2);
+    }
+  }
+  return QOC_OK;
+}
+
 qoc_status qoc_tr_solve(qoc_problem* p, const double* theta0, double gtol, int32_t max_iter, double* theta_out,
                         double* cost_out, int32_t* iters_out) {
   if (!p) return QOC_ERR_INVALID_ARG;

@@ -38,6 +38,8 @@ __all__ = [
     "draw_directions",
     "batched_workloads",
     "warm_targets",
+    "degenerate_system",
+    "DEGENERATE_KINDS",
     "WORKLOADS",
 ]
 
@@ -192,3 +194,51 @@ def warm_targets(n: int, count: int, spawn: int, seed: int = 5, dim: int = 8) ->
     z = np.zeros((count, n), dtype=np.complex128)
     z[:, :dim] = rng.normal(size=(count, dim)) + 1j * rng.normal(size=(count, dim))
     return z / np.linalg.norm(z, axis=1, keepdims=True)
+
+
+DEGENERATE_KINDS = ("h0zero", "doubled", "near_crossing")
+
+
+def degenerate_system(kind: str, n: int, seed: int = 11) -> System:
+    """Systems whose step Hamiltonians H0 + f M have confluent or nearly confluent spectra.
+
+    * ``h0zero``: H0 = 0 and M dense symmetric N(0, 0.3^2).  Every eigenvalue of f M passes
+      through 0 together when the field changes sign, and all coincide at f = 0 (theta = 0).
+    * ``doubled`` (n even): H0 = diag(e, e) with e the sorted U[-1.5, 0] draw of size n/2, so
+      every level is exactly doubly degenerate, and M = R^T blockdiag(m, m) R with R a product
+      of plane rotations by random angles on the pairs (i, i + n/2).  R commutes with H0, so
+      every H0 + f M keeps an exactly doubly degenerate spectrum, in a basis that mixes the
+      copies.
+    * ``near_crossing``: the molecule recipe's spectrum with level 1 moved to 1e-9 above level 0;
+      with a weak field the pair stays within about |f| of a crossing.
+
+    psi0 = e0; the target is e1 (a unit vector), as in the tiny recipe.
+    """
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, n, DEGENERATE_KINDS.index(kind)])))
+    if kind == "h0zero":
+        h0 = np.zeros((n, n))
+        m = _sym_normal(rng, n, 0.3, zero_diag=False)
+    elif kind == "doubled":
+        if n % 2:
+            raise ValueError("doubled system needs an even n")
+        k = n // 2
+        e = np.sort(rng.uniform(-1.5, 0.0, size=k))
+        h0 = np.diag(np.concatenate([e, e]))
+        mb = _sym_normal(rng, k, 0.5, zero_diag=True)
+        m2 = np.zeros((n, n))
+        m2[:k, :k] = mb
+        m2[k:, k:] = mb
+        r = np.eye(n)
+        for i, ang in enumerate(rng.uniform(0.0, np.pi, size=k)):
+            c, sn = np.cos(ang), np.sin(ang)
+            r[i, i], r[i, i + k], r[i + k, i], r[i + k, i + k] = c, -sn, sn, c
+        m = r.T @ m2 @ r
+        m = 0.5 * (m + m.T)
+    elif kind == "near_crossing":
+        e = spectrum_with_gap(rng, n, -3.0, 1e-3)
+        e[1] = e[0] + 1e-9
+        h0 = np.diag(e)
+        m = _sym_normal(rng, n, 0.3, zero_diag=False)
+    else:
+        raise ValueError(f"unknown degenerate kind {kind!r}")
+    return System(h0, m, _unit(n, 0), _unit(n, 1))

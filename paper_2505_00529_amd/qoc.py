@@ -61,12 +61,14 @@ SIGNATURES = {
     "qoc_sync": (_st, [_vp]),
     "qoc_step_propagators": (_st, [_vp, _dp, _i32, _dp, _dp, _dp]),
     "qoc_set_checkpoint_interval": (_st, [_vp, _i32]),
+    "qoc_set_jacobi_sweep_cap": (_st, [_vp, _i32]),
     "qoc_memory_usage": (_st, [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
     "qoc_tr_solve": (_st, [_vp, _dp, ctypes.c_double, _i32, _dp, _dp, ctypes.POINTER(_i32)]),
     "qoc_tr_solve_many": (_st, [_vp, _i32, _dp, _dp, ctypes.c_double, _i32, _dp, _dp, ctypes.POINTER(_i32),
                                 ctypes.POINTER(_i32)]),
     "qoc_hess_many_targets": (_st, [_vp, _i32, _dp, _dp, _dp, _dp, _dp]),
     "qoc_control_coords": (_st, [_vp, _i32, _dp, _dp, ctypes.POINTER(_i32)]),
+    "qoc_tr_gradient_norms": (_st, [_vp, _i32, _dp, _dp, _dp]),
     "qoc_params_from_coords": (_st, [_vp, _i32, _dp, _dp]),
     "qoc_batch_create": (_st, [ctypes.c_int, _i32, ctypes.POINTER(_vp), ctypes.POINTER(_vp)]),
     "qoc_batch_destroy": (None, [_vp]),
@@ -204,6 +206,9 @@ class Problem:
     def set_checkpoint_interval(self, steps: int):
         self._check(lib().qoc_set_checkpoint_interval(self._h, steps))
 
+    def set_jacobi_sweep_cap(self, max_sweeps: int):
+        self._check(lib().qoc_set_jacobi_sweep_cap(self._h, max_sweeps))
+
     def memory_usage(self) -> Tuple[int, int]:
         c = ctypes.c_int64()
         pk = ctypes.c_int64()
@@ -336,6 +341,15 @@ class Problem:
                                             its.ctypes.data_as(ctypes.POINTER(_i32)),
                                             conv.ctypes.data_as(ctypes.POINTER(_i32))))
         return out, c, its, conv.astype(bool)
+
+    def gradient_norms(self, grads):
+        """(||g||_2, ||V_r^T g||_2) per row of grads (count x P)."""
+        g = _f64(grads)
+        count = g.size // self.P
+        gn = np.zeros(count)
+        pn = np.zeros(count)
+        self._check(lib().qoc_tr_gradient_norms(self._h, count, _ptr(g), _ptr(gn), _ptr(pn)))
+        return gn, pn
 
     def control_coords(self, thetas):
         """(coords (count x P), rank): c = diag(sigma_r) V_r^T theta of the trust-region metric."""

@@ -52,3 +52,44 @@ def test_create_without_device_fails_cleanly():
     st = qoc.lib().qoc_create(0, None, ctypes.byref(h))
     assert st in (qoc.QOC_ERR_DEVICE, qoc.QOC_ERR_INVALID_ARG)
     assert not h.value
+
+
+def _device_disassembly():
+    """Disassembly of every gfx950 code object in the built library (each translation unit's
+    offload bundle in the .hip_fatbin section)."""
+    import subprocess
+    import tempfile
+
+    llvm = "/opt/rocm/llvm/bin"
+    for tool in ("clang-offload-bundler", "llvm-objdump"):
+        if not os.path.exists(os.path.join(llvm, tool)):
+            pytest.skip(f"{tool} not available")
+    with tempfile.TemporaryDirectory() as tmp:
+        fat = os.path.join(tmp, "fatbin")
+        subprocess.run(["objcopy", "--dump-section", f".hip_fatbin={fat}", qoc.LIB_PATH], check=True)
+        data = open(fat, "rb").read()
+        magic = b"__CLANG_OFFLOAD_BUNDLE__"
+        starts = [m.start() for m in re.finditer(re.escape(magic), data)]
+        assert starts, "no offload bundle in the library"
+        text = []
+        for k, a in enumerate(starts):
+            b = starts[k + 1] if k + 1 < len(starts) else len(data)
+            part = os.path.join(tmp, f"b{k}")
+            elf = os.path.join(tmp, f"c{k}.elf")
+            open(part, "wb").write(data[a:b])
+            subprocess.run([os.path.join(llvm, "clang-offload-bundler"), "--unbundle", "--type=o", f"--input={part}",
+                            "--targets=hipv4-amdgcn-amd-amdhsa--gfx950", f"--output={elf}"], check=True)
+            out = subprocess.run([os.path.join(llvm, "llvm-objdump"), "-d", "--mcpu=gfx950", elf],
+                                 check=True, capture_output=True, text=True).stdout
+            text.append(out)
+        return text
+
+
+def test_device_code_has_no_packed_fp32_arithmetic():
+    """The library is built with the packed-FP32 target feature off for the device pass: no
+    v_pk_add_f32 / v_pk_mul_f32 / v_pk_fma_f32 anywhere in its gfx950 code."""
+    texts = _device_disassembly()
+    assert sum(t.count("\n") for t in texts) > 10000
+    for t in texts:
+        for op in ("v_pk_add_f32", "v_pk_mul_f32", "v_pk_fma_f32"):
+            assert op not in t, op

@@ -1,4 +1,6 @@
 """torch.autograd layer and checkpointed gradient / HVP sweeps."""
+import json
+import os
 import sys
 
 import numpy as np
@@ -98,14 +100,20 @@ def test_checkpointed_large_dimension_against_oracle():
     p.close()
 
 
-def test_differentiation_workload_fd_and_memory():
+GOLDEN_DIFF = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "diff_oracle.json")
+
+
+def test_differentiation_workload_fd_oracle_and_memory():
     """N=128, J=10^4, K=64 (P=128), checkpoints every 100 steps: gradient and three HVPs through
-    torch.autograd, against central finite differences (h = 1e-6) of the store-all gradient;
-    peak device memory of the checkpointed handle against storing every step."""
+    torch.autograd, against the stored oracle values (1e-10 relative) and central finite
+    differences (h = 1e-6) of the store-all gradient; peak device memory of the checkpointed
+    handle against storing every step."""
     import torch
     from paper_2505_00529_amd import autograd as QA
 
+    doc = json.load(open(GOLDEN_DIFF))
     w = inputs.make_workload("diff")
+    assert (doc["n"], doc["nt"], doc["k"], doc["seed"]) == (w.system.n, w.nt, w.k, w.seed)
     th_np = inputs.draw_thetas(w.p, 1, w.seed)[0]
     vs = inputs.draw_directions(w.p, 3, w.seed)
     full = qoc.problem_from_workload(w)
@@ -119,15 +127,22 @@ def test_differentiation_workload_fd_and_memory():
     g_np = g.detach().cpu().numpy()
     _say(f"diff: cost {c.item():.12f} dC={_rel(c.item(), c_full):.2e} dg={_rel(g_np, g_full):.2e}")
     assert _rel(c.item(), c_full) < 1e-12 and _rel(g_np, g_full) < 1e-11
+    _say(f"  against the oracle: dC={_rel(c.item(), doc['cost']):.2e} dg={_rel(g_np, doc['grad']):.2e}")
+    assert _rel(c.item(), doc["cost"]) < 1e-10 and _rel(g_np, doc["grad"]) < 1e-10
     h = 1e-6
     for i, v_np in enumerate(vs):
         v = torch.tensor(v_np, dtype=torch.float64, device="cuda")
         (hv,) = torch.autograd.grad(g, th, v, retain_graph=True)
+        hv_np = hv.cpu().numpy()
         gp = full.grad(th_np + h * v_np)[1]
         gm = full.grad(th_np - h * v_np)[1]
         fd = (gp - gm) / (2 * h)
-        err = _rel(hv.cpu().numpy(), fd)
-        _say(f"  hvp {i}: |Hv|={np.linalg.norm(fd):.4e} rel diff to central FD {err:.2e}")
+        err = _rel(hv_np, fd)
+        ref = doc["hvps"][i]
+        assert ref["v_index"] == i
+        err_o = _rel(hv_np, ref["hvp"])
+        _say(f"  hvp {i}: |Hv|={np.linalg.norm(fd):.4e} rel diff to the oracle {err_o:.2e}, to central FD {err:.2e}")
+        assert err_o < 1e-10
         assert err < 1e-6
     ck.sync()
     _, peak_ck = ck.memory_usage()

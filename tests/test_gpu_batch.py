@@ -49,8 +49,6 @@ def test_batched_matches_per_problem_and_oracle():
         assert _rel(c[i], ci) < 1e-10 and _rel(g[i], gi) < 1e-10 and _rel(h[i], hi) < 1e-10, i
     for i in range(len(ws)):
         w = ws[i]
-        if w.system.n > 36:
-            continue
         s = w.system
         basis = O.fourier_basis(w.nt, w.dt, w.k)
         cr, gr, hr = O.cost_grad_hess(s.h0, s.m, s.psi0, s.psi_target, basis, w.dt, th[i], w.gamma, w.rho)

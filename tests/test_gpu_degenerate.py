@@ -1,0 +1,107 @@
+"""GPU parity on confluent and nearly confluent spectra, end to end through the hot-path kernels.
+
+The eigen kernels are chosen by n: the one-wave kernel at n = 8 and 16, the workgroup kernels at
+n = 36 and 64.  Each system (inputs.degenerate_system) makes the divided differences of the
+propagator's derivatives confluent or nearly so:
+
+* H0 = 0: all eigenvalues of f M meet at 0 where the field changes sign, and coincide on every
+  step at theta = 0 (U = I, U' = -i dt M, U'' = -dt^2 M^2);
+* an exactly doubly degenerate spectrum on every step, in a basis that mixes the two copies;
+* a level pair 1e-9 apart, under a weak field (the pair stays nearly degenerate on every step)
+  and under a moderate one (the pair crosses where the field is small).
+
+Tolerance: 1e-10 normwise relative for cost, gradient and Hessian against the CPU oracle.
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import qoc_oracle as O
+from paper_2505_00529_amd import inputs
+from paper_2505_00529_amd import qoc
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "degenerate_oracle.json")
+
+
+def _rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _handle(s, nt, dt, k):
+    p = qoc.Problem(0)
+    p.set_system(s.h0, s.m, s.psi0, s.psi_target)
+    p.set_control_basis(qoc.QOC_BASIS_FOURIER, nt, dt, k)
+    p.set_weights(2.0 * dt, 2.0)
+    return p
+
+
+# kind, theta scale (0: theta = 0)
+FAMILIES = [("h0zero", 0.3), ("h0zero", 0.0), ("doubled", 0.3), ("near_crossing", 1e-8),
+            ("near_crossing", 0.3)]
+SIZES = [8, 16, 36, 64]
+CASES = [(k, s, n) for k, s in FAMILIES for n in SIZES]
+
+
+@pytest.mark.parametrize("kind,sigma,n", CASES, ids=[f"{k}-s{s:g}-n{n}" for k, s, n in CASES])
+def test_degenerate_spectra_against_oracle(kind, sigma, n):
+    nt, dt, k = 48, 0.05, 2
+    s = inputs.degenerate_system(kind, n)
+    _say(f"case {kind} sigma={sigma:g} n={n} nt={nt}")
+    p = _handle(s, nt, dt, k)
+    if sigma > 0:
+        thetas = inputs.draw_thetas(2 * k, 2, 300 + n, sigma=sigma)
+    else:
+        thetas = np.zeros((2, 2 * k))
+    costs, grads, hess = p.hess_many(thetas)
+    basis = O.fourier_basis(nt, dt, k)
+    for i, th in enumerate(thetas):
+        cr, gr, hr = O.cost_grad_hess(s.h0, s.m, s.psi0, s.psi_target, basis, dt, th, 2.0 * dt, 2.0)
+        _say(f"  theta {i}: dC={_rel(costs[i], cr):.2e} dg={_rel(grads[i], gr):.2e} dH={_rel(hess[i], hr):.2e}")
+        assert _rel(costs[i], cr) < TOL
+        assert _rel(grads[i], gr) < TOL
+        assert _rel(hess[i], hr) < TOL
+    v = inputs.draw_directions(2 * k, 1, 400 + n)[0]
+    hv = p.hvp(thetas[0], v)
+    hr0 = O.cost_grad_hess(s.h0, s.m, s.psi0, s.psi_target, basis, dt, thetas[0], 2.0 * dt, 2.0)[2]
+    _say(f"  hvp: {_rel(hv, hr0 @ v):.2e}")
+    assert _rel(hv, hr0 @ v) < TOL
+    p.close()
+
+
+def test_degenerate_spectra_in_the_benchmark_configuration():
+    """n = 36, J = 4000, K = 16 evaluated as a batch of 256 thetas: the launch configuration of the
+    throughput benchmark (16 tangent columns per sweep workgroup, 167-step eigen chunks), with
+    the first two thetas compared against stored oracle values."""
+    doc = json.load(open(GOLDEN))
+    n, nt, dt, k, batch = doc["n"], doc["nt"], doc["dt"], doc["k"], doc["batch"]
+    by_kind = {}
+    for case in doc["cases"]:
+        by_kind.setdefault((case["kind"], case["sigma"], case["seed"]), []).append(case)
+    for (kind, sigma, seed), cases in by_kind.items():
+        s = inputs.degenerate_system(kind, n)
+        p = _handle(s, nt, dt, k)
+        thetas = inputs.draw_thetas(2 * k, batch, seed, sigma=sigma)
+        costs, grads, hess = p.hess_many(thetas)
+        assert np.all(np.isfinite(hess))
+        for case in cases:
+            i = case["theta_index"]
+            _say(f"  {kind}: theta {i}: dC={_rel(costs[i], case['cost']):.2e} "
+                 f"dg={_rel(grads[i], case['grad']):.2e} dH={_rel(hess[i], case['hess']):.2e}")
+            assert _rel(costs[i], case["cost"]) < TOL
+            assert _rel(grads[i], case["grad"]) < TOL
+            assert _rel(hess[i], case["hess"]) < TOL
+        p.close()

@@ -52,3 +52,22 @@ def test_adam_first_step_is_signed_learning_rate():
     p1, m, v = R.adam_step(np.zeros(3), g, np.zeros(3), np.zeros(3), 1, 0.01)
     assert np.allclose(p1, [-0.01, 0.01, 0.0], rtol=1e-4, atol=0)
     assert np.allclose(m, 0.1 * g) and np.allclose(v, 0.001 * g * g)
+
+
+def test_adam_bias_correction_over_several_steps():
+    # A constant gradient g gives m_t = (1 - b1^t) g and v_t = (1 - b2^t) g^2, so with the bias
+    # correction every step moves by -lr * sign(g) (up to eps), not only the first.
+    g = np.array([2.0, -0.5, 1e-3])
+    lr, b1, b2 = 0.01, 0.9, 0.999
+    p, m, v = np.zeros(3), np.zeros(3), np.zeros(3)
+    for t in range(1, 8):
+        p_new, m, v = R.adam_step(p, g, m, v, t, lr, b1, b2)
+        assert np.allclose(p_new - p, -lr * np.sign(g), rtol=1e-4, atol=0), t
+        assert np.allclose(m, (1 - b1 ** t) * g) and np.allclose(v, (1 - b2 ** t) * g * g)
+        p = p_new
+    # a sign flip at the second step: m_2 = -(1 - b1)^2 g, bias-corrected -(1 - b1)/(1 + b1) g,
+    # and v_2 = (1 - b2)(1 + b2) g^2, bias-corrected g^2: the second step is
+    # +lr (1 - b1)/(1 + b1) sign(g)
+    p1, m, v = R.adam_step(np.zeros(3), g, np.zeros(3), np.zeros(3), 1, lr, b1, b2)
+    p2, m, v = R.adam_step(p1, -g, m, v, 2, lr, b1, b2)
+    assert np.allclose(p2 - p1, lr * (1 - b1) / (1 + b1) * np.sign(g), rtol=1e-4, atol=0)
