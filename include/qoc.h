@@ -127,6 +127,10 @@ qoc_status qoc_step_propagators(qoc_problem* p, const double* theta, int32_t j,
  * current rotation and raises QOC_ERR_NOCONV for the call (host-pointer calls: returned, outputs
  * untouched; *_dev calls: reported by qoc_sync).  A low cap is a way to exercise that path. */
 qoc_status qoc_set_jacobi_sweep_cap(qoc_problem* p, int32_t max_sweeps);
+/* Stopping tolerance of the per-step Jacobi eigendecomposition: a step is converged when its
+ * largest off-diagonal entry is at most tol_rel * ||H_j||_F (default 1e-15; 0 <= tol_rel <= 1e-6).
+ * A tolerance of 0 runs the sweeps until the off-diagonal part is exactly zero or the cap. */
+qoc_status qoc_set_jacobi_tolerance(qoc_problem* p, double tol_rel);
 
 /* Checkpoint interval (steps) for the cost / gradient / HVP paths: 0 stores every step's
  * eigen-data; k > 0 keeps only states every k steps and recomputes one segment's
@@ -193,12 +197,13 @@ qoc_status qoc_batch_hess(qoc_batch* b, const double* const* thetas, double* con
 qoc_status qoc_batch_hess_unbatched(qoc_batch* b, const double* const* thetas, double* const* costs,
                                     double* const* grads, double* const* hessians);
 /* Autotuner: on a sample of each (n, P) group (its 4 longest problems) it times the group's
- * eigen phase over candidate chunk lengths {16..256} and its sweeps over candidate tangent
+ * eigen phase over candidate chunk lengths {8, 16, 32} and its sweeps over candidate tangent
  * columns per workgroup {2..32} at these thetas, keeps the fastest for the whole group, and
  * rebuilds the launch plan (the graph is recaptured on the next call). */
 qoc_status qoc_batch_autotune(qoc_batch* b, const double* const* thetas);
 /* Tuning in use for problem i (columns per sweep workgroup, eigen chunk length); set overrides
- * it (pg in [1, 32], chunk >= 16, or >= 64 for n > 64). */
+ * it (pg in [1, 32]; chunk in [8, 32], or [16, 32] for n > 64: the longest chain of warm-started
+ * eigendecompositions is 32 steps, after which a chunk restarts cold). */
 qoc_status qoc_batch_get_config(const qoc_batch* b, int32_t i, int32_t* pg, int32_t* chunk);
 qoc_status qoc_batch_set_config(qoc_batch* b, int32_t i, int32_t pg, int32_t chunk);
 /* Device time (HIP events) of the last qoc_batch_hess / _unbatched call's launches, in ms. */

@@ -18,8 +18,6 @@ using namespace qoc;
 
 namespace {
 
-constexpr double kJacobiTol = 1e-15;   // off-diagonal target relative to ||H_j||_F
-
 std::mutex g_cfg_mu;
 bool g_cfg_done[64] = {false};
 
@@ -107,7 +105,8 @@ namespace qoc {
 size_t layout_work(Work& nw, int n, int nt, int P, int nb, int seg, int chunk_req, void* base) {
   const int np = pad_even(n);
   const int eig_stride = seg > 0 ? std::min(seg, nt) : nt;
-  const int chunk = chunk_req > 0 ? std::min(chunk_req, eig_stride) : eig_chunk_len(eig_stride, nb, np);
+  const int chunk = chunk_req > 0 ? std::min(std::min(chunk_req, kMaxWarmChain), eig_stride)
+                                  : eig_chunk_len(eig_stride, nb, np);
   const int nchunks = (eig_stride + chunk - 1) / chunk;
   const int nseg = (nt + eig_stride - 1) / eig_stride;
   const size_t ntn = (size_t)nt * n, nn = (size_t)n * n;
@@ -262,7 +261,7 @@ qoc_status qoc_problem::enqueue(Mode mode, int nb, const double* d_theta, const 
     w.b_in = w.binit;
     w.b_out = nullptr;
     w.v_last_step = nullptr;
-    QOC_LAUNCH("eig", launch_eig(sy, bs, w, store_derivs, kJacobiTol, jacobi_max_sweeps, stream));
+    QOC_LAUNCH("eig", launch_eig(sy, bs, w, store_derivs, jacobi_tol, jacobi_max_sweeps, stream));
     QOC_LAUNCH("boundary", launch_boundary(w, stream));
     QOC_LAUNCH("forward", launch_forward(sy, bs, w, mode, stream));
     QOC_LAUNCH("terminal", launch_terminal(sy, bs, w, mode, rho, stream));
@@ -275,7 +274,7 @@ qoc_status qoc_problem::enqueue(Mode mode, int nb, const double* d_theta, const 
     for (int sgi = 0; sgi < S; ++sgi) {
       const int j0 = sgi * L;
       set_range(j0, std::min(L, nt - j0));
-      QOC_LAUNCH("eig", launch_eig(sy, bs, w, store_derivs, kJacobiTol, jacobi_max_sweeps, stream));
+      QOC_LAUNCH("eig", launch_eig(sy, bs, w, store_derivs, jacobi_tol, jacobi_max_sweeps, stream));
       QOC_LAUNCH("boundary", launch_boundary(w, stream));
       double* ob = w.obound + (size_t)sgi * nb * nn;
       QOC_LAUNCH("boundary", launch_seg_join(w, ob, sgi > 0, stream));
@@ -293,7 +292,7 @@ qoc_status qoc_problem::enqueue(Mode mode, int nb, const double* d_theta, const 
       const int j0 = sgi * L;
       const int k = S - 1 - sgi;
       set_range(j0, std::min(L, nt - j0));
-      QOC_LAUNCH("eig", launch_eig(sy, bs, w, true, kJacobiTol, jacobi_max_sweeps, stream));
+      QOC_LAUNCH("eig", launch_eig(sy, bs, w, true, jacobi_tol, jacobi_max_sweeps, stream));
       QOC_LAUNCH("boundary", launch_boundary(w, stream));
       w.o_in = sgi > 0 ? w.obound + (size_t)sgi * nb * nn : nullptr;
       w.b_in = k == 0 ? w.binit : ((k - 1) % 2 == 0 ? w.bcarry : w.bcarry2);
@@ -759,6 +758,14 @@ qoc_status qoc_set_jacobi_sweep_cap(qoc_problem* p, int32_t max_sweeps) {
   if (!p) return QOC_ERR_INVALID_ARG;
   if (max_sweeps < 0 || max_sweeps > 1000) return p->fail(QOC_ERR_INVALID_ARG, "sweep cap must be in [0, 1000]");
   p->jacobi_max_sweeps = max_sweeps;
+  return QOC_OK;
+}
+
+qoc_status qoc_set_jacobi_tolerance(qoc_problem* p, double tol_rel) {
+  if (!p) return QOC_ERR_INVALID_ARG;
+  if (!std::isfinite(tol_rel) || tol_rel < 0.0 || tol_rel > 1e-6)
+    return p->fail(QOC_ERR_INVALID_ARG, "tolerance must be in [0, 1e-6]");
+  p->jacobi_tol = tol_rel;
   return QOC_OK;
 }
 

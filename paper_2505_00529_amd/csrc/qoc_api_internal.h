@@ -36,6 +36,7 @@ struct qoc_problem {
   bool weights_explicit = false;
   int ckpt = 0;
   int jacobi_max_sweeps = 40;
+  double jacobi_tol = 1e-15;   // largest off-diagonal entry at convergence, relative to ||H_j||_F
 
   // workspace
   qoc::Work w;

@@ -35,7 +35,7 @@ namespace {
 constexpr double kBatchJacobiTol = 1e-15;
 constexpr int kBatchMaxSweeps = 40;
 constexpr int kStermItemsPerBlock = 16;   // sterm items: each covers 16 waves' worth of tasks
-constexpr int kChunkCandidates[] = {16, 32, 64, 128, 256};
+constexpr int kChunkCandidates[] = {8, 16, 32};   // at most kMaxWarmChain
 constexpr int kPgCandidates[] = {2, 4, 8, 16, 32};
 constexpr int kTuneSample = 4;   // problems per (n, P) group timed by the autotuner
 
@@ -147,7 +147,7 @@ struct qoc_batch {
   // Sets the eigen chunk of problem i (>= the layout's minimum) and the derived chunk count.
   void set_chunk(int i, int chunk) {
     Prob& q = pr[i];
-    q.chunk = std::max(q.chunk_min, std::min(chunk, q.nt));
+    q.chunk = std::max(q.chunk_min, std::min(std::min(chunk, kMaxWarmChain), q.nt));
     q.w.chunk = q.chunk;
     q.w.nchunks = (q.nt + q.chunk - 1) / q.chunk;
   }
@@ -556,7 +556,7 @@ qoc_status qoc_batch_create(int device, int32_t count, qoc_problem* const* probl
   std::vector<size_t> work_off(count);
   for (int i = 0; i < count; ++i) {
     Prob& q = b->pr[i];
-    q.chunk_min = std::min(q.nt, pad_even(q.n) > 64 ? 64 : kChunkCandidates[0]);
+    q.chunk_min = std::min(q.nt, pad_even(q.n) > 64 ? 16 : kChunkCandidates[0]);
     work_off[i] = work_total;
     work_total += layout_work(q.w, q.n, q.nt, q.P, 1, 0, q.chunk_min, nullptr);
   }
@@ -739,6 +739,7 @@ qoc_status qoc_batch_set_config(qoc_batch* b, int32_t i, int32_t pg, int32_t chu
   if (!b || i < 0 || i >= (int)b->pr.size()) return QOC_ERR_INVALID_ARG;
   if (pg < 1 || pg > kMaxPg) return b->fail(QOC_ERR_INVALID_ARG, "pg outside [1, 32]");
   if (chunk < b->pr[i].chunk_min) return b->fail(QOC_ERR_INVALID_ARG, "chunk below the workspace layout's minimum");
+  if (chunk > kMaxWarmChain) return b->fail(QOC_ERR_INVALID_ARG, "chunk above the longest warm-started chain (32)");
   b->pr[i].pg = std::min(pg, b->pr[i].P);
   b->set_chunk(i, chunk);
   b->release_plan();

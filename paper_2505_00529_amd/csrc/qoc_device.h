@@ -80,6 +80,41 @@ __device__ __forceinline__ double rcp_refined(double x) {
   return q;
 }
 
+// Rescale one column of a warm-started eigenvector matrix to unit Euclidean norm.  A rotation
+// with |t| below about 1e-8 has c = 1/sqrt(1 + t^2) rounded to exactly 1 and s = t, so it
+// scales the norms of its column pair by 1 + t^2: always up.  Such rotations are the rule in
+// the second sweep of a warm start (the angles are about the square of the first sweep's), so
+// without a correction the column norms of V drift up along a chain of warm-started steps and
+// V_{j+1}^T V_j stops being orthogonal in the same direction at every step (the state norm then
+// grows by about 1e-13 per step at n = 128).  The rotations' effect on orthogonality between
+// columns is unbiased (exactly zero for a pair of equal norms), so renormalising the columns
+// once per step leaves only unbiased rounding.
+__device__ __forceinline__ void normalize_column(double* v, int rows, int stride) {
+  double ss = 0.0;
+  for (int i = 0; i < rows; ++i) ss = fma(v[i * stride], v[i * stride], ss);
+  if (ss > 0.0) {
+    const double r = rsqrt_refined(ss);
+    for (int i = 0; i < rows; ++i) v[i * stride] *= r;
+  }
+}
+// The same for a contiguous, 16-byte aligned column of even length.
+__device__ __forceinline__ void normalize_column_contig(double* v, int rows) {
+  double ss0 = 0.0, ss1 = 0.0;
+  for (int i = 0; i < rows; i += 2) {
+    const double2 x = *(const double2*)(v + i);
+    ss0 = fma(x.x, x.x, ss0);
+    ss1 = fma(x.y, x.y, ss1);
+  }
+  const double ss = ss0 + ss1;
+  if (ss > 0.0) {
+    const double r = rsqrt_refined(ss);
+    for (int i = 0; i < rows; i += 2) {
+      const double2 x = *(const double2*)(v + i);
+      *(double2*)(v + i) = make_double2(x.x * r, x.y * r);
+    }
+  }
+}
+
 // Jacobi rotation (c, s) annihilating the off-diagonal of [[app, apq], [apq, aqq]] with the
 // smaller angle: t = sign(d) e / (|d| + sqrt(d^2 + e^2)), d = aqq - app, e = 2 apq (the root of
 // t^2 + 2 (d/e) t - 1 = 0 of modulus <= 1), c = 1/sqrt(1 + t^2), s = t c.  c is accurate to

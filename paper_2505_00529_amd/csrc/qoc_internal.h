@@ -12,6 +12,13 @@ constexpr int kMaxP = 4096;      // largest supported parameter count
 constexpr int kThreads = 256;    // threads per workgroup of every kernel
 constexpr int kMaxPg = 32;       // tangent / second-adjoint columns carried per workgroup
 
+// Longest chain of warm-started eigendecompositions (an eigen chunk).  Along a chain, the warm
+// start diag(lambda_{j-1}) + (f_j - f_{j-1}) Mt_{j-1} leaves out each step's rounding residue
+// and the rotated eigenvector matrix loses orthogonality by unbiased rounding, both growing with
+// the chain (about 4e-15 relative per step in the backward error ||V diag(l) V^T - H_j|| at
+// n = 36).  Chunks therefore restart cold at least every 32 steps.
+constexpr int kMaxWarmChain = 32;
+
 // Pad n to an even count of Jacobi "players" (a dummy index when n is odd).
 inline int pad_even(int n) { return (n + 1) & ~1; }
 

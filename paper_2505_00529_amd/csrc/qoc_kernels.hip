@@ -136,6 +136,8 @@ __device__ __forceinline__ void body_eig_chunk(const EigArgs& a, int c, int b) {
       atomicAdd(a.stats + 1, (unsigned long long)sweeps);
     }
     for (int i = tid; i < np; i += kThreads) lamv[i] = A[i * np + i];
+    // V_j carries into the next step: unit columns (each thread owns whole columns)
+    for (int k = tid; k < np; k += kThreads) normalize_column(V + k, np, np);
     __syncthreads();
     // X = M V ; A = V^T X = Mt_j
     gemm_global_left(a.m, n, V, X, np);
@@ -374,11 +376,13 @@ __device__ __forceinline__ void body_eig_wave(const EigArgs& a, int c, int b) {
       }
     }
     if (lane < NP) lamv[lane] = Bm[lane * NP + lane];
-    // stage V_j
+    // stage V_j, with unit columns (it carries into the next step)
     if (lane < NP) {
 #pragma unroll
       for (int s = 0; s < NP; ++s) Bx[lane * NP + s] = v[s];
     }
+    __syncthreads();
+    if (lane < NP) normalize_column(Bx + lane, NP, NP);
     __syncthreads();
     const size_t step = (size_t)b * a.eig_stride + (j - a.j_base);
     double acc[NP];
@@ -953,6 +957,9 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
         Vt[(2 * K + 1) * NP + vrow] = vo[k];
       }
     }
+    __syncthreads();
+    // V_j carries into the next step: unit columns (column k of V is row k of Vt)
+    if (tid < NP) normalize_column_contig(Vt + tid * NP, NP);
     __syncthreads();
     const size_t step = (size_t)b * a.eig_stride + (j - a.j_base);
     double acc[RT][CT];
@@ -2417,7 +2424,7 @@ int eig_chunk_len(int seg_len, int nb, int np) {
   // ms), so 2048 there and for the other kernels.
   const int total = np == 36 ? 6144 : 2048;
   const int target = std::max(1, (total + nb - 1) / nb);
-  return std::max(8, (seg_len + target - 1) / target);
+  return std::min(kMaxWarmChain, std::max(8, (seg_len + target - 1) / target));
 }
 
 // Tangent columns per sweep workgroup: wider groups amortise each step's fixed chain (state

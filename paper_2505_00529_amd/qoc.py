@@ -62,6 +62,7 @@ SIGNATURES = {
     "qoc_step_propagators": (_st, [_vp, _dp, _i32, _dp, _dp, _dp]),
     "qoc_set_checkpoint_interval": (_st, [_vp, _i32]),
     "qoc_set_jacobi_sweep_cap": (_st, [_vp, _i32]),
+    "qoc_set_jacobi_tolerance": (_st, [_vp, ctypes.c_double]),
     "qoc_memory_usage": (_st, [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
     "qoc_tr_solve": (_st, [_vp, _dp, ctypes.c_double, _i32, _dp, _dp, ctypes.POINTER(_i32)]),
     "qoc_tr_solve_many": (_st, [_vp, _i32, _dp, _dp, ctypes.c_double, _i32, _dp, _dp, ctypes.POINTER(_i32),
@@ -208,6 +209,9 @@ class Problem:
 
     def set_jacobi_sweep_cap(self, max_sweeps: int):
         self._check(lib().qoc_set_jacobi_sweep_cap(self._h, max_sweeps))
+
+    def set_jacobi_tolerance(self, tol_rel: float):
+        self._check(lib().qoc_set_jacobi_tolerance(self._h, tol_rel))
 
     def memory_usage(self) -> Tuple[int, int]:
         c = ctypes.c_int64()

@@ -86,15 +86,17 @@ def test_autotune_changes_nothing_but_speed():
     c1, g1, h1 = b.hess(th)
     for i in range(len(ws)):
         pg, chunk = cfg[i]
-        assert 1 <= pg <= max(1, ws[i].p) and chunk >= 16
+        assert 1 <= pg <= max(1, ws[i].p) and 8 <= chunk <= 32
         # a different chunking changes rounding only
         assert _rel(c1[i], c0[i]) < 1e-12 and _rel(g1[i], g0[i]) < 1e-10 and _rel(h1[i], h0[i]) < 1e-10
-    b.set_config(0, 1, 64)
+    b.set_config(0, 1, 32)
     assert b.config(0)[0] == 1
     c2, g2, h2 = b.hess(th)
     assert _rel(h2[0], h0[0]) < 1e-10
     with pytest.raises(qoc.QocError):
-        b.set_config(0, 0, 64)
+        b.set_config(0, 0, 32)
+    with pytest.raises(qoc.QocError):
+        b.set_config(0, 1, 64)
     b.close()
     for p in probs:
         p.close()

@@ -84,7 +84,7 @@ def test_degenerate_spectra_against_oracle(kind, sigma, n):
 
 def test_degenerate_spectra_in_the_benchmark_configuration():
     """n = 36, J = 4000, K = 16 evaluated as a batch of 256 thetas: the launch configuration of the
-    throughput benchmark (16 tangent columns per sweep workgroup, 167-step eigen chunks), with
+    throughput benchmark (16 tangent columns per sweep workgroup, 32-step eigen chunks), with
     the first two thetas compared against stored oracle values."""
     doc = json.load(open(GOLDEN))
     n, nt, dt, k, batch = doc["n"], doc["nt"], doc["dt"], doc["k"], doc["batch"]
