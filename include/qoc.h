@@ -113,6 +113,19 @@ qoc_status qoc_hess_dev(qoc_problem* p, const double* theta, double* cost, doubl
 qoc_status qoc_hvp_dev(qoc_problem* p, const double* theta, const double* v, double* hv, double* grad);
 qoc_status qoc_hess_many_dev(qoc_problem* p, int32_t count, const double* thetas,
                              double* costs, double* grads, double* hess);
+/* Allocation-free twin of qoc_hess_many_dev, for callers that cannot allocate device memory
+ * (code under HIP stream/graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments, kernels and results; it allocates nothing (no hipMalloc, hipFree, event or
+ * library allocation): its workspace is a static 256 MiB device array that each GPU the library
+ * runs on holds from the first qoc_create on that device until the process ends.  The caller
+ * still passes the device inputs and outputs.  Every step's eigen-data must fit: about
+ * 24 n^2 nt bytes per theta plus lower-order terms (n = 36, nt = 4000: 135 MB for one theta);
+ * a larger request returns QOC_ERR_UNSUPPORTED with nothing enqueued.  All handles on one GPU
+ * share that array, so calls that overlap in time on one GPU (other streams, other threads)
+ * race and must be serialised by the caller; each call fully rewrites what it reads, so no
+ * state carries from one call to the next.  Device-side failures are reported by qoc_sync. */
+qoc_status qoc_hess_many_dev_noalloc(qoc_problem* p, int32_t count, const double* thetas,
+                                     double* costs, double* grads, double* hess);
 /* Wait for the handle's stream and report device-side failures of earlier *_dev calls. */
 qoc_status qoc_sync(qoc_problem* p);
 

@@ -21,6 +21,15 @@ namespace {
 std::mutex g_cfg_mu;
 bool g_cfg_done[64] = {false};
 
+// Workspace of qoc_hess_many_dev_noalloc: a file-scope device array, so that the call allocates
+// nothing.  Every GPU the library runs on holds its own copy until the process ends.  Host code
+// never passes `scratch` itself to a kernel (in host code the name is a host-side stand-in):
+// qoc_create looks up each device's copy once with hipGetSymbolAddress, and the entry point
+// uses that address.
+constexpr size_t kStaticScratchBytes = (size_t)256 << 20;
+static __device__ __align__(256) double scratch[kStaticScratchBytes / sizeof(double)];
+double* g_scratch_dev[64] = {nullptr};
+
 const char* status_text(qoc_status s) {
   switch (s) {
     case QOC_OK: return "ok";
@@ -220,6 +229,13 @@ qoc_status qoc_problem::enqueue(Mode mode, int nb, const double* d_theta, const 
   const bool ck = ckpt > 0 && ckpt < nt && mode != Mode::Hess;
   qoc_status st = ensure_work(nb, ck ? ckpt : 0);
   if (st != QOC_OK) return st;
+  return enqueue_into(w, ck, mode, nb, d_theta, d_v, d_cost, d_grad, d_out, d_targets);
+}
+
+// The launch sequence of one evaluation on the workspace w (laid out for nb thetas and, when ck,
+// for the handle's checkpoint segment).  Launches kernels only: no allocation, no host wait.
+qoc_status qoc_problem::enqueue_into(Work& w, bool ck, Mode mode, int nb, const double* d_theta, const double* d_v,
+                                     double* d_cost, double* d_grad, double* d_out, const double* d_targets) {
   // The status word reports this evaluation only: clear it first, with a kernel rather than a
   // memset node, so that the sequence stays valid under stream capture.
   hipError_t e0 = launch_fill_int(d_status, 1, 0, stream);
@@ -442,6 +458,13 @@ qoc_status qoc_create(int device, void* hip_stream, qoc_problem** out) {
     if (device < 64 && !g_cfg_done[device]) {
       e = configure_kernels();
       if (e != hipSuccess) return QOC_ERR_DEVICE;
+      void* sp = nullptr;
+      e = hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !sp) {
+        (void)hipGetLastError();
+        return QOC_ERR_DEVICE;
+      }
+      g_scratch_dev[device] = (double*)sp;
       g_cfg_done[device] = true;
     }
   }
@@ -692,6 +715,33 @@ qoc_status qoc_hvp_dev(qoc_problem* p, const double* theta, const double* v, dou
 qoc_status qoc_hess_many_dev(qoc_problem* p, int32_t count, const double* thetas, double* costs, double* grads,
                              double* hess) {
   return run_dev(p, Mode::Hess, count, thetas, nullptr, costs, grads, hess);
+}
+
+qoc_status qoc_hess_many_dev_noalloc(qoc_problem* p, int32_t count, const double* thetas, double* costs,
+                                     double* grads, double* hess) {
+  if (!p) return QOC_ERR_INVALID_ARG;
+  qoc_status st = p->ready();
+  if (st != QOC_OK) return st;
+  if (count < 1 || !thetas) return p->fail(QOC_ERR_INVALID_ARG, "theta must be non-NULL and count >= 1");
+  double* base = p->device < 64 ? g_scratch_dev[p->device] : nullptr;
+  if (!base) return p->fail(QOC_ERR_STATE, "no static workspace on this device");
+  Work sw;
+  const size_t need = layout_work(sw, p->n, p->nt, p->P, count, 0, 0, nullptr);
+  if (need > kStaticScratchBytes) {
+    char msg[160];
+    std::snprintf(msg, sizeof msg, "workspace of %zu bytes exceeds the %zu-byte static scratch", need,
+                  kStaticScratchBytes);
+    return p->fail(QOC_ERR_UNSUPPORTED, msg);
+  }
+  layout_work(sw, p->n, p->nt, p->P, count, 0, 0, base);
+  sw.status = p->d_status;
+  sw.stats = p->d_stats;
+  // no timing events either (creating one is a library allocation)
+  const bool prof = p->profiling;
+  p->profiling = false;
+  st = p->enqueue_into(sw, false, Mode::Hess, count, thetas, nullptr, costs, grads, hess, nullptr);
+  p->profiling = prof;
+  return st;
 }
 
 qoc_status qoc_sync(qoc_problem* p) {

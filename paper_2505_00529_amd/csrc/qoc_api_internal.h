@@ -79,6 +79,8 @@ struct qoc_problem {
   qoc_status ready();
   qoc_status enqueue(qoc::Mode mode, int nb, const double* d_theta, const double* d_v, double* d_cost,
                      double* d_grad, double* d_out, const double* d_targets = nullptr);
+  qoc_status enqueue_into(qoc::Work& w, bool ck, qoc::Mode mode, int nb, const double* d_theta, const double* d_v,
+                          double* d_cost, double* d_grad, double* d_out, const double* d_targets);
   qoc_status check_device_status();
   // targets: NULL (handle's target) or count x 2n doubles (one complex target per theta)
   qoc_status run_host(qoc::Mode mode, int count, const double* theta, const double* v, double* cost, double* grad,

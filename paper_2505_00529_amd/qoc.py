@@ -58,6 +58,7 @@ SIGNATURES = {
     "qoc_hess_dev": (_st, [_vp, _vp, _vp, _vp, _vp]),
     "qoc_hvp_dev": (_st, [_vp, _vp, _vp, _vp, _vp]),
     "qoc_hess_many_dev": (_st, [_vp, _i32, _vp, _vp, _vp, _vp]),
+    "qoc_hess_many_dev_noalloc": (_st, [_vp, _i32, _vp, _vp, _vp, _vp]),
     "qoc_sync": (_st, [_vp]),
     "qoc_step_propagators": (_st, [_vp, _dp, _i32, _dp, _dp, _dp]),
     "qoc_set_checkpoint_interval": (_st, [_vp, _i32]),
@@ -289,6 +290,12 @@ class Problem:
                                             _vp(costs_ptr) if costs_ptr else None,
                                             _vp(grads_ptr) if grads_ptr else None,
                                             _vp(hess_ptr) if hess_ptr else None))
+
+    def hess_many_dev_noalloc(self, count, thetas_ptr, costs_ptr, grads_ptr, hess_ptr):
+        self._check(lib().qoc_hess_many_dev_noalloc(self._h, count, _vp(thetas_ptr),
+                                                    _vp(costs_ptr) if costs_ptr else None,
+                                                    _vp(grads_ptr) if grads_ptr else None,
+                                                    _vp(hess_ptr) if hess_ptr else None))
 
     def sync(self):
         self._check(lib().qoc_sync(self._h))
