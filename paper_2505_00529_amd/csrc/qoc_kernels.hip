@@ -992,32 +992,58 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
         for (int y = 0; y < CT; ++y)
           if (i0 + x < n && k0 + y < n) dst[(size_t)(i0 + x) * n + k0 + y] = acc[x][y];
     }
-    // X = M V_j into A, transposed (A[k][i] = X[i][k]; M symmetric: row i of M is column i)
+    // X = M V_j, transposed (X^T[k][i] = X[i][k]; M symmetric: row i of M is column i).  With
+    // V_{j-1} in LDS (NP = 36), M is staged into A (free after the sweeps) and X goes to Vp
+    // (free after the O product); without that room (NP = 64) X reads M from global memory and
+    // goes to A.
+    double* Xt = VP_LDS ? Vp : A;
+    if (VP_LDS) {
+      for (int idx = tid; idx < NP * NP; idx += TPB) {
+        const int i = idx / NP, k = idx - (idx / NP) * NP;
+        A[idx] = (i < n && k < n) ? a.m[i * n + k] : 0.0;
+      }
+      __syncthreads();
+    }
     if (has_tile) {
 #pragma unroll
       for (int x = 0; x < RT; ++x)
 #pragma unroll
         for (int y = 0; y < CT; ++y) acc[x][y] = 0.0;
+      if (VP_LDS) {
 #pragma unroll 2
-      for (int r = 0; r < n; r += 2) {
-        double2 u[RT], w[CT];
+        for (int r = 0; r < NP; r += 2) {
+          double2 u[RT], w[CT];
 #pragma unroll
-        for (int x = 0; x < RT; ++x) {
-          const bool row = i0 + x < n;
-          u[x].x = row ? a.m[(i0 + x) * n + r] : 0.0;
-          u[x].y = row && r + 1 < n ? a.m[(i0 + x) * n + r + 1] : 0.0;
+          for (int x = 0; x < RT; ++x) u[x] = *(const double2*)(A + (i0 + x) * NP + r);
+#pragma unroll
+          for (int y = 0; y < CT; ++y) w[y] = *(const double2*)(Vt + (k0 + y) * NP + r);
+#pragma unroll
+          for (int x = 0; x < RT; ++x)
+#pragma unroll
+            for (int y = 0; y < CT; ++y) acc[x][y] = fma(u[x].y, w[y].y, fma(u[x].x, w[y].x, acc[x][y]));
         }
+      } else {
+#pragma unroll 2
+        for (int r = 0; r < n; r += 2) {
+          double2 u[RT], w[CT];
 #pragma unroll
-        for (int y = 0; y < CT; ++y) w[y] = *(const double2*)(Vt + (k0 + y) * NP + r);
+          for (int x = 0; x < RT; ++x) {
+            const bool row = i0 + x < n;
+            u[x].x = row ? a.m[(i0 + x) * n + r] : 0.0;
+            u[x].y = row && r + 1 < n ? a.m[(i0 + x) * n + r + 1] : 0.0;
+          }
 #pragma unroll
-        for (int x = 0; x < RT; ++x)
+          for (int y = 0; y < CT; ++y) w[y] = *(const double2*)(Vt + (k0 + y) * NP + r);
 #pragma unroll
-          for (int y = 0; y < CT; ++y) acc[x][y] = fma(u[x].y, w[y].y, fma(u[x].x, w[y].x, acc[x][y]));
+          for (int x = 0; x < RT; ++x)
+#pragma unroll
+            for (int y = 0; y < CT; ++y) acc[x][y] = fma(u[x].y, w[y].y, fma(u[x].x, w[y].x, acc[x][y]));
+        }
       }
 #pragma unroll
       for (int y = 0; y < CT; ++y)
 #pragma unroll
-        for (int x = 0; x < RT; ++x) A[(k0 + y) * NP + i0 + x] = acc[x][y];
+        for (int x = 0; x < RT; ++x) Xt[(k0 + y) * NP + i0 + x] = acc[x][y];
     }
     __syncthreads();
     // Mt_j = V_j^T X, kept in A for the next step's warm start and written out with S_j
@@ -1032,14 +1058,15 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
 #pragma unroll
         for (int x = 0; x < RT; ++x) u[x] = *(const double2*)(Vt + (i0 + x) * NP + r);
 #pragma unroll
-        for (int y = 0; y < CT; ++y) w[y] = *(const double2*)(A + (k0 + y) * NP + r);
+        for (int y = 0; y < CT; ++y) w[y] = *(const double2*)(Xt + (k0 + y) * NP + r);
 #pragma unroll
         for (int x = 0; x < RT; ++x)
 #pragma unroll
           for (int y = 0; y < CT; ++y) acc[x][y] = fma(u[x].y, w[y].y, fma(u[x].x, w[y].x, acc[x][y]));
       }
     }
-    __syncthreads();
+    // (NP = 36: A held M, whose last reads were before the barrier above)
+    if (!VP_LDS) __syncthreads();
     if (has_tile) {
 #pragma unroll
       for (int x = 0; x < RT; ++x)
