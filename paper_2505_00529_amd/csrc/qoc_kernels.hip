@@ -551,8 +551,8 @@ __device__ __forceinline__ void rotate_block(double a00, double a01, double a10,
 
 template <int NP>
 __host__ __device__ constexpr size_t eig_wg_lds_doubles() {
-  return (size_t)(EigWgShape<NP>::VP_LDS ? 3 : 2) * NP * NP + 4 * (NP / 2) + NP + EigWgShape<NP>::TPB / 64 +
-         kSincTerms;
+  return (size_t)(EigWgShape<NP>::VP_LDS ? 3 : 2) * NP * NP + 4 * (NP / 2) + NP + 2 * (EigWgShape<NP>::TPB / 64) +
+         kSincTerms + 4;
 }
 
 // Sum / max over a workgroup of TPB threads from the wave partials (red: TPB/64 doubles of LDS).
@@ -564,6 +564,23 @@ __device__ __forceinline__ double wg_sum(double v, double* red) {
   double r = 0.0;
 #pragma unroll
   for (int w = 0; w < TPB / 64; ++w) r += red[w];
+  __syncthreads();
+  return r;
+}
+// Both maxima of a pair over a workgroup in one exchange (red: 2 TPB/64 doubles of LDS).
+template <int TPB>
+__device__ __forceinline__ double2 wg_max2(double2 v, double* red) {
+  v.x = wave_max(v.x);
+  v.y = wave_max(v.y);
+  if ((threadIdx.x & 63) == 0) *(double2*)(red + 2 * (threadIdx.x >> 6)) = v;
+  __syncthreads();
+  double2 r = *(const double2*)red;
+#pragma unroll
+  for (int w = 1; w < TPB / 64; ++w) {
+    const double2 q = *(const double2*)(red + 2 * w);
+    r.x = fmax(r.x, q.x);
+    r.y = fmax(r.y, q.y);
+  }
   __syncthreads();
   return r;
 }
@@ -603,8 +620,9 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
   double* Vp = VP_LDS ? Vt + NP * NP : nullptr;  // V_{j-1}, same layout
   double2* rot = (double2*)(Vt + (VP_LDS ? 2 : 1) * NP * NP);  // 2 x H rotations (c, s)
   double* lamv = (double*)(rot + 2 * H);         // eigenvalues
-  double* red = lamv + NP;                       // wave partials
-  double* sinc_c = red + TPB / 64;               // sinc series coefficients
+  double* red = lamv + NP;                       // wave partials (pairs)
+  double* sinc_c = red + 2 * (TPB / 64);         // sinc series coefficients
+  double* hnorm = sinc_c + kSincTerms;           // ||H0||_F^2, <H0, M>, ||M||_F^2
   const int tid = threadIdx.x;
   const int n = a.n, nt = a.nt;
   const int j0 = a.j_base + c * a.chunk;
@@ -614,6 +632,25 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
   const double* fb = a.f + (size_t)b * nt;
   const size_t nn = (size_t)n * n;
   double* vpg = VP_LDS ? nullptr : a.gscratch + ((size_t)b * a.nchunks + c) * NP * NP;
+  {
+    // ||H_j||_F^2 = ||H0||^2 + 2 f_j <H0, M> + f_j^2 ||M||^2 sets each step's stopping tolerance
+    // (the Frobenius norm is invariant under the rotations), so no step needs a reduction for it
+    double hh = 0.0, hm = 0.0, mm = 0.0;
+    for (int idx = tid; idx < (int)nn; idx += TPB) {
+      const double h = a.h0[idx], m = a.m[idx];
+      hh = fma(h, h, hh);
+      hm = fma(h, m, hm);
+      mm = fma(m, m, mm);
+    }
+    hh = wg_sum<TPB>(hh, red);
+    hm = wg_sum<TPB>(hm, red);
+    mm = wg_sum<TPB>(mm, red);
+    if (tid == 0) {
+      hnorm[0] = hh;
+      hnorm[1] = hm;
+      hnorm[2] = mm;
+    }
+  }
 
   // fixed 2x2 blocks (I <= K) of this thread: read offset in the current buffer and the four
   // write offsets (upper triangle of the shifted slots) in the other one
@@ -688,9 +725,7 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
       }
     }
     __syncthreads();
-    double loc = 0.0;
-    for (int idx = tid; idx < NP * NP; idx += TPB) loc = fma(A[idx], A[idx], loc);
-    const double tol = a.tol_rel * sqrt(wg_sum<TPB>(loc, red));
+    const double tol = a.tol_rel * sqrt(fmax(fma(fj, fma(fj, hnorm[2], 2.0 * hnorm[1]), hnorm[0]), 0.0));
     int cur = 0, rb = 0;                           // current A buffer and rotation buffer
     bool finished = false;                         // perturbative finish taken (V_j formed below)
 #pragma unroll 1
@@ -710,7 +745,8 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
           if (sweep > 0) excess = fmax(excess, v - kJacobiFinishRatio * fabs(lamv[k] - lamv[i]));
         }
       }
-      off = wg_max<TPB>(off, red);
+      const double2 oe = wg_max2<TPB>(make_double2(off, excess), red);
+      off = oe.x;
       if (off <= tol) {
         if (tid == 0 && a.stats) {
           atomicAdd(a.stats, 1ull);
@@ -722,7 +758,7 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
         if (tid == 0) atomicOr(a.status, kStatusNoConv);
         break;
       }
-      if (sweep > 0 && wg_max<TPB>(excess, red) <= 0.0) {
+      if (sweep > 0 && oe.y <= 0.0) {
         // Perturbative finish: with A = diag(d) + F and every |F_ik| <= 1e-5 |d_k - d_i|, the
         // eigenvectors are the columns of W = I + E + E2 and the eigenvalues are
         // d_k + sum_i F_ik E_ik, to within terms of third order in E, where
