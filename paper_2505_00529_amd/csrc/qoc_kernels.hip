@@ -487,8 +487,7 @@ __global__ __launch_bounds__(64, 2) void k_eig_wave(EigArgs a) { body_eig_wave<N
 //      segments per row), applies their rotations in place and shifts them within the segment;
 //      only the segment ends cross lanes (one DPP move each way).  V goes through LDS only at
 //      step ends, for the basis products.
-// Without LDS room for V_{j-1} (NP = 64) it goes through a global scratch of NP x NP doubles
-// per (theta, chunk).
+// Three NP x NP buffers (A / V ping-pong and V_{j-1}) live in LDS at a row stride LD.
 template <int NP>
 struct EigWgShape;
 template <>
@@ -499,17 +498,21 @@ struct EigWgShape<36> {
   static constexpr int VW0 = 1, VW = 2;  // waves VW0 .. VW0+VW-1 hold V
   static constexpr int VS = 6;           // pairs per V segment
   static constexpr int WAVES = 4;        // waves per SIMD (five spill more than they hide)
+  static constexpr int LD = 36;          // row stride of the NP x NP LDS buffers
 };
 template <>
 struct EigWgShape<64> {
-  static constexpr int TPB = 512;        // eight waves share the 66 KB of LDS
+  static constexpr int TPB = 512;        // eight waves share the 101 KB of LDS
   static constexpr int RT = 4, CT = 2;   // 16 x 32 output tiles
-  static constexpr bool VP_LDS = false;
+  static constexpr bool VP_LDS = true;   // 3 buffers of 64 x 66 doubles: 101 KB, one problem per CU
   static constexpr int VW0 = 1, VW = 4;
   static constexpr int VS = 8;
   // one problem per CU without spills (256 VGPRs) beats two per CU at 128 VGPRs with about 130
   // spilled registers per thread (683 against 754 ms for 256 theta x 4000 steps)
   static constexpr int WAVES = 2;
+  // row stride 66: rows 132 dwords apart fall on distinct banks for the products' 16-byte loads
+  // (a stride of 64 puts every row of a column on the same bank)
+  static constexpr int LD = 66;
 };
 
 // Largest |F_ik| / |d_k - d_i| over the off-diagonal part F of the current A = diag(d) + F at
@@ -551,8 +554,8 @@ __device__ __forceinline__ void rotate_block(double a00, double a01, double a10,
 
 template <int NP>
 __host__ __device__ constexpr size_t eig_wg_lds_doubles() {
-  return (size_t)(EigWgShape<NP>::VP_LDS ? 3 : 2) * NP * NP + 4 * (NP / 2) + NP + 2 * (EigWgShape<NP>::TPB / 64) +
-         kSincTerms + 4;
+  return (size_t)(EigWgShape<NP>::VP_LDS ? 3 : 2) * NP * EigWgShape<NP>::LD + 4 * (NP / 2) + NP +
+         2 * (EigWgShape<NP>::TPB / 64) + kSincTerms + 4;
 }
 
 // Sum / max over a workgroup of TPB threads from the wave partials (red: TPB/64 doubles of LDS).
@@ -611,14 +614,15 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
   constexpr int G = H / S;                       // segments per row
   constexpr int VRW = NP / VW;                   // V rows per wave
   constexpr int ROT0 = TPB - 64;                 // first thread forming the next rotations
+  constexpr int LD = EigWgShape<NP>::LD;         // row stride of the NP x NP buffers in LDS
   static_assert(NP % RT == 0 && NP % CT == 0 && NTILE <= TPB, "tile shape");
   static_assert(H % S == 0 && S >= 2 && NP % VW == 0 && VRW * G <= 64 && VW0 + VW <= TPB / 64 - 1,
                 "register V layout");
   extern __shared__ __attribute__((aligned(16))) double smem[];
   double* A = smem;                              // NP x NP; also A buffer 0 during the sweeps
-  double* Vt = A + NP * NP;                      // NP x NP, column-major: Vt[k * NP + i] = V[i][k]; A buffer 1
-  double* Vp = VP_LDS ? Vt + NP * NP : nullptr;  // V_{j-1}, same layout
-  double2* rot = (double2*)(Vt + (VP_LDS ? 2 : 1) * NP * NP);  // 2 x H rotations (c, s)
+  double* Vt = A + NP * LD;                      // NP x NP, column-major: Vt[k * LD + i] = V[i][k]; A buffer 1
+  double* Vp = VP_LDS ? Vt + NP * LD : nullptr;  // V_{j-1}, same layout
+  double2* rot = (double2*)(Vt + (VP_LDS ? 2 : 1) * NP * LD);  // 2 x H rotations (c, s)
   double* lamv = (double*)(rot + 2 * H);         // eigenvalues
   double* red = lamv + NP;                       // wave partials (pairs)
   double* sinc_c = red + 2 * (TPB / 64);         // sinc series coefficients
@@ -631,7 +635,7 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
   if (tid < kSincTerms) sinc_c[tid] = kSincCoef[tid];
   const double* fb = a.f + (size_t)b * nt;
   const size_t nn = (size_t)n * n;
-  double* vpg = VP_LDS ? nullptr : a.gscratch + ((size_t)b * a.nchunks + c) * NP * NP;
+  double* vpg = VP_LDS ? nullptr : a.gscratch + ((size_t)b * a.nchunks + c) * NP * LD;
   {
     // ||H_j||_F^2 = ||H0||^2 + 2 f_j <H0, M> + f_j^2 ||M||^2 sets each step's stopping tolerance
     // (the Frobenius norm is invariant under the rotations), so no step needs a reduction for it
@@ -673,7 +677,7 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int x = slot_next<NP>(2 * max(I, 0) + (e >> 1)), y = slot_next<NP>(2 * K + (e & 1));
-      bw[t][e] = min(x, y) * NP + max(x, y);
+      bw[t][e] = min(x, y) * LD + max(x, y);
     }
   }
   // next-round rotation formed by this thread (pair kr of the next round): its even slot comes
@@ -701,7 +705,7 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
     if (j == j0) {
       for (int idx = tid; idx < NP * NP; idx += TPB) {
         const int i = idx / NP, k = idx - (idx / NP) * NP;
-        A[idx] = (i < n && k < n) ? a.h0[i * n + k] + fj * a.m[i * n + k] : 0.0;
+        A[i * LD + k] = (i < n && k < n) ? a.h0[i * n + k] + fj * a.m[i * n + k] : 0.0;
       }
 #pragma unroll
       for (int k = 0; k < S; ++k) {
@@ -713,15 +717,15 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
       const double df = fj - fb[j - 1];
       for (int idx = tid; idx < NP * NP; idx += TPB) {
         const int i = idx / NP, k = idx - (idx / NP) * NP;
-        A[idx] = df * A[idx] + (i == k ? lamv[i] : 0.0);   // A held Mt_{j-1}
-        if (VP_LDS) Vp[idx] = Vt[idx];
+        A[i * LD + k] = df * A[i * LD + k] + (i == k ? lamv[i] : 0.0);   // A held Mt_{j-1}
+        if (VP_LDS) Vp[i * LD + k] = Vt[i * LD + k];
       }
       // V_{j-1} back into registers (not kept live through the basis products)
 #pragma unroll
       for (int k = 0; k < S; ++k) {
         const int K = vseg * S + k;
-        ve[k] = v_on ? Vt[(2 * K) * NP + vrow] : 0.0;
-        vo[k] = v_on ? Vt[(2 * K + 1) * NP + vrow] : 0.0;
+        ve[k] = v_on ? Vt[(2 * K) * LD + vrow] : 0.0;
+        vo[k] = v_on ? Vt[(2 * K + 1) * LD + vrow] : 0.0;
       }
     }
     __syncthreads();
@@ -732,7 +736,7 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
     for (int sweep = 0;; ++sweep) {
       double* Ac = cur ? Vt : A;
       // sweep boundary: slot order is the index order
-      if (tid < NP) lamv[tid] = Ac[tid * NP + tid];
+      if (tid < NP) lamv[tid] = Ac[tid * LD + tid];
       __syncthreads();
       // largest off-diagonal entry, and (after the first sweep) largest excess of |F_ik| over the
       // finish bound
@@ -740,7 +744,7 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
       for (int idx = tid; idx < NP * NP; idx += TPB) {
         const int i = idx / NP, k = idx - (idx / NP) * NP;
         if (i < k) {
-          const double v = fabs(Ac[idx]);
+          const double v = fabs(Ac[i * LD + k]);
           off = fmax(off, v);
           if (sweep > 0) excess = fmax(excess, v - kJacobiFinishRatio * fabs(lamv[k] - lamv[i]));
         }
@@ -771,12 +775,12 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
         for (int idx = tid; idx < NP * NP; idx += TPB) {
           const int i = idx / NP, k = idx - (idx / NP) * NP;
           if (i < k) {
-            const double f = Ac[idx];
+            const double f = Ac[i * LD + k];
             const double e = f == 0.0 ? 0.0 : f / (lamv[k] - lamv[i]);
-            Ac[k * NP + i] = e;
-            Ac[idx] = -e;
+            Ac[k * LD + i] = e;
+            Ac[i * LD + k] = -e;
           } else if (i == k) {
-            Ac[idx] = 0.0;
+            Ac[i * LD + k] = 0.0;
           }
         }
         double* Vo = cur ? A : Vt;
@@ -784,8 +788,8 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
 #pragma unroll
           for (int k = 0; k < S; ++k) {
             const int K = vseg * S + k;
-            Vo[(2 * K) * NP + vrow] = ve[k];
-            Vo[(2 * K + 1) * NP + vrow] = vo[k];
+            Vo[(2 * K) * LD + vrow] = ve[k];
+            Vo[(2 * K + 1) * LD + vrow] = vo[k];
           }
         }
         if (tid == 0 && a.stats) {
@@ -799,7 +803,7 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
         // first rotations of the step; later sweeps get theirs from the last round before
         if (has_rot) {
           double cc, ss;
-          jacobi_rotation(Ac[(2 * kr) * NP + 2 * kr], Ac[(2 * kr + 1) * NP + 2 * kr + 1], Ac[(2 * kr) * NP + 2 * kr + 1],
+          jacobi_rotation(Ac[(2 * kr) * LD + 2 * kr], Ac[(2 * kr + 1) * LD + 2 * kr + 1], Ac[(2 * kr) * LD + 2 * kr + 1],
                           cc, ss);
           rot[rb * H + kr] = make_double2(cc, ss);
         }
@@ -818,8 +822,8 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
           if (I >= 0) {
             const int K = bK[t];
             const double2 RI = R[I], RK = R[K];
-            const double2 r0 = *(const double2*)(Ar + (2 * I) * NP + 2 * K);
-            const double2 r1 = *(const double2*)(Ar + (2 * I + 1) * NP + 2 * K);
+            const double2 r0 = *(const double2*)(Ar + (2 * I) * LD + 2 * K);
+            const double2 r1 = *(const double2*)(Ar + (2 * I + 1) * LD + 2 * K);
             // a diagonal block (I == K) is symmetric: its lower entry is not stored, and the
             // rotation annihilates its off-diagonal pair (both writes go to one place)
             const bool dg = I == K;
@@ -836,12 +840,12 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
           // round-r diagonal block) and the new entry (es, os) (from block (I0, K0))
           // (the two slots lie in pairs I0 < K0, whose diagonal blocks give the diagonal entries)
           const double2 uI = rot_col(R[I0], rpar), uK = rot_col(R[K0], cpar);
-          const double2 gI = *(const double2*)(Ar + (2 * I0) * NP + 2 * I0);
-          const double gI11 = Ar[(2 * I0 + 1) * NP + 2 * I0 + 1];
-          const double2 gK = *(const double2*)(Ar + (2 * K0) * NP + 2 * K0);
-          const double gK11 = Ar[(2 * K0 + 1) * NP + 2 * K0 + 1];
-          const double2 r0 = *(const double2*)(Ar + (2 * I0) * NP + 2 * K0);
-          const double2 r1 = *(const double2*)(Ar + (2 * I0 + 1) * NP + 2 * K0);
+          const double2 gI = *(const double2*)(Ar + (2 * I0) * LD + 2 * I0);
+          const double gI11 = Ar[(2 * I0 + 1) * LD + 2 * I0 + 1];
+          const double2 gK = *(const double2*)(Ar + (2 * K0) * LD + 2 * K0);
+          const double gK11 = Ar[(2 * K0 + 1) * LD + 2 * K0 + 1];
+          const double2 r0 = *(const double2*)(Ar + (2 * I0) * LD + 2 * K0);
+          const double2 r1 = *(const double2*)(Ar + (2 * I0 + 1) * LD + 2 * K0);
           const double dI = rotate_entry(gI.x, gI.y, gI.y, gI11, uI, uI);
           const double dK = rotate_entry(gK.x, gK.y, gK.y, gK11, uK, uK);
           const double e = rotate_entry(r0.x, r0.y, r1.x, r1.y, uI, uK);
@@ -918,11 +922,11 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
           for (int r = 0; r < NP; r += 2) {
             double2 u[RT], w[CT];
 #pragma unroll
-            for (int x = 0; x < RT; ++x) u[x] = *(const double2*)(Ac + (i0 + x) * NP + r);   // E_{r,k}, E_{r+1,k}
+            for (int x = 0; x < RT; ++x) u[x] = *(const double2*)(Ac + (i0 + x) * LD + r);   // E_{r,k}, E_{r+1,k}
             const double d0 = lamv[r], d1 = lamv[r + 1];
 #pragma unroll
             for (int y = 0; y < CT; ++y) {
-              const double2 q = *(const double2*)(Ac + (k0 + y) * NP + r);   // -E_{i,r}, -E_{i,r+1}
+              const double2 q = *(const double2*)(Ac + (k0 + y) * LD + r);   // -E_{i,r}, -E_{i,r+1}
               w[y] = make_double2(q.x * (di[y] - d0), q.y * (di[y] - d1));   // F_{i,r}, F_{i,r+1}
             }
 #pragma unroll
@@ -934,7 +938,7 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
         double s1 = 0.0, s2 = 0.0;
         if (tid < NP) {
           for (int i = 0; i < NP; i += 2) {
-            const double2 q = *(const double2*)(Ac + tid * NP + i);   // E_{i,k}, E_{i+1,k}, k = tid
+            const double2 q = *(const double2*)(Ac + tid * LD + i);   // E_{i,k}, E_{i+1,k}, k = tid
             const double q0 = q.x * q.x, q1 = q.y * q.y;
             s1 += q0 + q1;
             s2 = fma(q0, lamv[i], fma(q1, lamv[i + 1], s2));
@@ -948,11 +952,11 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
             for (int y = 0; y < CT; ++y) {
               const int k = i0 + x, i = k0 + y;
               const double den = lamv[k] - lamv[i];
-              if (i != k && den != 0.0) Ac[k * NP + i] += fe[x][y] / den;   // (E + E2)^T
+              if (i != k && den != 0.0) Ac[k * LD + i] += fe[x][y] / den;   // (E + E2)^T
             }
         }
         if (tid < NP) {
-          Ac[tid * NP + tid] = -0.5 * s1;
+          Ac[tid * LD + tid] = -0.5 * s1;
           lam_new = lamv[tid] + lamv[tid] * s1 - s2;   // written to lamv once no thread reads it
         }
       }
@@ -964,14 +968,14 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
 #pragma unroll
         for (int x = 0; x < RT; ++x)
 #pragma unroll
-          for (int y = 0; y < CT; ++y) acc[x][y] = Vo[(i0 + x) * NP + k0 + y];
+          for (int y = 0; y < CT; ++y) acc[x][y] = Vo[(i0 + x) * LD + k0 + y];
 #pragma unroll 2
         for (int r = 0; r < NP; r += 2) {
           double2 u[RT], w[CT];
 #pragma unroll
-          for (int x = 0; x < RT; ++x) u[x] = *(const double2*)(Ac + (i0 + x) * NP + r);   // E_{r,k}, E_{r+1,k}
+          for (int x = 0; x < RT; ++x) u[x] = *(const double2*)(Ac + (i0 + x) * LD + r);   // E_{r,k}, E_{r+1,k}
 #pragma unroll
-          for (int y = 0; y < CT; ++y) w[y] = make_double2(Vo[r * NP + k0 + y], Vo[(r + 1) * NP + k0 + y]);
+          for (int y = 0; y < CT; ++y) w[y] = make_double2(Vo[r * LD + k0 + y], Vo[(r + 1) * LD + k0 + y]);
 #pragma unroll
           for (int x = 0; x < RT; ++x)
 #pragma unroll
@@ -983,19 +987,19 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
 #pragma unroll
         for (int x = 0; x < RT; ++x)
 #pragma unroll
-          for (int y = 0; y < CT; ++y) Vt[(i0 + x) * NP + k0 + y] = acc[x][y];
+          for (int y = 0; y < CT; ++y) Vt[(i0 + x) * LD + k0 + y] = acc[x][y];
       }
     } else if (v_on) {
 #pragma unroll
       for (int k = 0; k < S; ++k) {
         const int K = vseg * S + k;
-        Vt[(2 * K) * NP + vrow] = ve[k];
-        Vt[(2 * K + 1) * NP + vrow] = vo[k];
+        Vt[(2 * K) * LD + vrow] = ve[k];
+        Vt[(2 * K + 1) * LD + vrow] = vo[k];
       }
     }
     __syncthreads();
     // V_j carries into the next step: unit columns (column k of V is row k of Vt)
-    if (tid < NP) normalize_column_contig(Vt + tid * NP, NP);
+    if (tid < NP) normalize_column_contig(Vt + tid * LD, NP);
     __syncthreads();
     const size_t step = (size_t)b * a.eig_stride + (j - a.j_base);
     double acc[RT][CT];
@@ -1013,9 +1017,9 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
       for (int r = 0; r < NP; r += 2) {
         double2 u[RT], w[CT];
 #pragma unroll
-        for (int x = 0; x < RT; ++x) u[x] = *(const double2*)(Vt + (i0 + x) * NP + r);
+        for (int x = 0; x < RT; ++x) u[x] = *(const double2*)(Vt + (i0 + x) * LD + r);
 #pragma unroll
-        for (int y = 0; y < CT; ++y) w[y] = *(const double2*)(Vprev + (k0 + y) * NP + r);
+        for (int y = 0; y < CT; ++y) w[y] = *(const double2*)(Vprev + (k0 + y) * LD + r);
 #pragma unroll
         for (int x = 0; x < RT; ++x)
 #pragma unroll
@@ -1036,7 +1040,7 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
     if (VP_LDS) {
       for (int idx = tid; idx < NP * NP; idx += TPB) {
         const int i = idx / NP, k = idx - (idx / NP) * NP;
-        A[idx] = (i < n && k < n) ? a.m[i * n + k] : 0.0;
+        A[i * LD + k] = (i < n && k < n) ? a.m[i * n + k] : 0.0;
       }
       __syncthreads();
     }
@@ -1050,9 +1054,9 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
         for (int r = 0; r < NP; r += 2) {
           double2 u[RT], w[CT];
 #pragma unroll
-          for (int x = 0; x < RT; ++x) u[x] = *(const double2*)(A + (i0 + x) * NP + r);
+          for (int x = 0; x < RT; ++x) u[x] = *(const double2*)(A + (i0 + x) * LD + r);
 #pragma unroll
-          for (int y = 0; y < CT; ++y) w[y] = *(const double2*)(Vt + (k0 + y) * NP + r);
+          for (int y = 0; y < CT; ++y) w[y] = *(const double2*)(Vt + (k0 + y) * LD + r);
 #pragma unroll
           for (int x = 0; x < RT; ++x)
 #pragma unroll
@@ -1069,7 +1073,7 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
             u[x].y = row && r + 1 < n ? a.m[(i0 + x) * n + r + 1] : 0.0;
           }
 #pragma unroll
-          for (int y = 0; y < CT; ++y) w[y] = *(const double2*)(Vt + (k0 + y) * NP + r);
+          for (int y = 0; y < CT; ++y) w[y] = *(const double2*)(Vt + (k0 + y) * LD + r);
 #pragma unroll
           for (int x = 0; x < RT; ++x)
 #pragma unroll
@@ -1079,7 +1083,7 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
 #pragma unroll
       for (int y = 0; y < CT; ++y)
 #pragma unroll
-        for (int x = 0; x < RT; ++x) Xt[(k0 + y) * NP + i0 + x] = acc[x][y];
+        for (int x = 0; x < RT; ++x) Xt[(k0 + y) * LD + i0 + x] = acc[x][y];
     }
     __syncthreads();
     // Mt_j = V_j^T X, kept in A for the next step's warm start and written out with S_j
@@ -1092,9 +1096,9 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
       for (int r = 0; r < NP; r += 2) {
         double2 u[RT], w[CT];
 #pragma unroll
-        for (int x = 0; x < RT; ++x) u[x] = *(const double2*)(Vt + (i0 + x) * NP + r);
+        for (int x = 0; x < RT; ++x) u[x] = *(const double2*)(Vt + (i0 + x) * LD + r);
 #pragma unroll
-        for (int y = 0; y < CT; ++y) w[y] = *(const double2*)(Xt + (k0 + y) * NP + r);
+        for (int y = 0; y < CT; ++y) w[y] = *(const double2*)(Xt + (k0 + y) * LD + r);
 #pragma unroll
         for (int x = 0; x < RT; ++x)
 #pragma unroll
@@ -1107,7 +1111,7 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
 #pragma unroll
       for (int x = 0; x < RT; ++x)
 #pragma unroll
-        for (int y = 0; y < CT; ++y) A[(i0 + x) * NP + k0 + y] = acc[x][y];
+        for (int y = 0; y < CT; ++y) A[(i0 + x) * LD + k0 + y] = acc[x][y];
     }
     if (a.store_derivs) {
       // M~_j and S_j from LDS in one coalesced pass (row i, column k of entry idx, stepped
@@ -1119,7 +1123,7 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
       int i = tid / n, k = tid - (tid / n) * n;
 #pragma unroll 1
       for (int idx = tid; idx < (int)nn; idx += TPB) {
-        const double v = A[i * NP + k];
+        const double v = A[i * LD + k];
         mt[idx] = v;
         sm[idx] = sinc_table(0.5 * a.dt * (lamv[i] - lamv[k]), sinc_c) * v;
         i += dr;
@@ -1133,11 +1137,12 @@ __device__ __forceinline__ void body_eig_wg(const EigArgs& a, int c, int b) {
     // eigenvalues, V_j for the next step's overlap, and the chunk ends
     if (tid < n) a.lam[step * n + tid] = lamv[tid];
     for (int idx = tid; idx < NP * NP; idx += TPB) {
-      if (!VP_LDS) vpg[idx] = Vt[idx];
-      const int k = idx / NP, i = idx - (idx / NP) * NP;   // Vt[idx] = V[i][k]
+      const int k = idx / NP, i = idx - (idx / NP) * NP;   // Vt[k * LD + i] = V[i][k]
+      const double v = Vt[k * LD + i];
+      if (!VP_LDS) vpg[k * LD + i] = v;
       if (i < n && k < n) {
-        if (j == j0) a.vfirst[((size_t)b * a.nchunks + c) * nn + (size_t)i * n + k] = Vt[idx];
-        if (j == j1 - 1) a.vlast[((size_t)b * a.nchunks + c) * nn + (size_t)i * n + k] = Vt[idx];
+        if (j == j0) a.vfirst[((size_t)b * a.nchunks + c) * nn + (size_t)i * n + k] = v;
+        if (j == j1 - 1) a.vlast[((size_t)b * a.nchunks + c) * nn + (size_t)i * n + k] = v;
       }
     }
     __syncthreads();
@@ -2474,7 +2479,7 @@ hipError_t configure_kernels() {
 
 size_t eig_scratch_doubles(int n, int nb, int nchunks) {
   const int np = pad_even(n);
-  if (np == 64) return (size_t)nb * nchunks * np * np;   // workgroup kernel: V_{j-1} per chunk
+  if (np == 36 || np == 64) return 0;   // workgroup kernels: everything in LDS
   if (eig_fits_lds(np)) return 0;
   return (size_t)nb * nchunks * 4 * np * np;
 }
