@@ -116,14 +116,15 @@ def cpu_baseline(w, single_thread_steps: int = 1000) -> dict:
                                         f"{dt1 * ns / w.nt:.1f} s, scaled to the full horizon"}}
 
 
-GOLDEN = os.path.join(ROOT, "tests", "golden", "molecule_oracle.json")
+GOLDEN_DIR = os.path.join(ROOT, "tests", "golden")
 PARITY_TOL = 1e-10
 
 
-def parity_vs_oracle(costs, grads, hess) -> dict:
+def parity_vs_oracle(workload: str, costs, grads, hess) -> dict:
     """Normwise relative error of the timed batch's thetas 0 and 1 (the benchmark draws the
     stored oracle cases first) against the CPU oracle's values for them."""
-    with open(GOLDEN) as f:
+    path = os.path.join(GOLDEN_DIR, f"{workload}_oracle.json")
+    with open(path) as f:
         doc = json.load(f)
 
     def rel(a, b):
@@ -137,7 +138,120 @@ def parity_vs_oracle(costs, grads, hess) -> dict:
                              "hess": rel(hess[i], case["hess"])}
     worst = max(v for e in errs.values() for v in e.values())
     return {"max_rel_err": worst, "tolerance": PARITY_TOL, "ok": worst < PARITY_TOL, "per_theta": errs,
-            "reference": "oracle values of thetas 0 and 1 (tests/golden/molecule_oracle.json)"}
+            "reference": f"oracle values of thetas 0 and 1 (tests/golden/{workload}_oracle.json)"}
+
+
+KERNELS = ["controls", "eig", "boundary", "forward", "terminal", "backward", "sterm", "assemble"]
+
+
+def timed_batch(prob, thetas, steps: int, warmup: int, stream, label: str):
+    """Warm up, then time `steps` Hessian evaluations of the batch `thetas` (device tensor) with
+    HIP events on `stream`; per-kernel averages from the library's own events on the same stream."""
+    import torch
+
+    B, P = thetas.shape
+    costs = torch.empty(B, dtype=torch.float64, device="cuda")
+    grads = torch.empty(B, P, dtype=torch.float64, device="cuda")
+    hess = torch.empty(B, P, P, dtype=torch.float64, device="cuda")
+
+    def step():
+        prob.hess_many_dev(B, thetas.data_ptr(), costs.data_ptr(), grads.data_ptr(), hess.data_ptr())
+
+    for i in range(warmup):
+        step()
+        torch.cuda.synchronize()
+        log(f"bench: {label} warmup {i + 1}/{warmup} done")
+    prob.sync()
+    prob.jacobi_stats(reset=True)
+    prob.profile_enable(True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for i in range(steps):
+        step()
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prob.sync()
+    step_ms = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(steps)])
+    log(f"bench: {label}: {steps} timed steps in {t1 - t0:.3f} s")
+    ktimes = {}
+    for k in KERNELS:
+        ms, cnt = prob.profile_kernel_ms(k)
+        if cnt:
+            ktimes[k] = (ms / cnt, cnt)
+    prob.profile_enable(False)
+    eig_steps, eig_sweeps = prob.jacobi_stats(reset=True)
+    return {"elapsed": t1 - t0, "step_ms": step_ms, "ktimes": ktimes,
+            "sweeps_per_step": eig_sweeps / max(eig_steps, 1),
+            "costs": costs.cpu().numpy(), "grads": grads.cpu().numpy(), "hess": hess.cpu().numpy()}
+
+
+def eig_roofline(ktimes, n, P, nt, B):
+    avg_ms = ktimes["eig"][0]
+    achieved = alg_flops_per_step("eig", n, P) * nt * B / (avg_ms * 1e-3) / 1e12
+    return achieved, achieved / (PEAK_FP64 / 1e12)
+
+
+def secondary_system(name: str, B: int, steps: int, stream) -> dict:
+    """Throughput of a second system (same measurement, fewer steps), reported beside the
+    headline line."""
+    import torch
+
+    w = inputs.make_workload(name)
+    n, P, nt = w.system.n, w.p, w.nt
+    log(f"bench: secondary workload {name} n={n} nt={nt} P={P} batch={B}")
+    prob = qoc.problem_from_workload(w, device=0)
+    prob.set_stream(stream.cuda_stream)
+    thetas = torch.tensor(inputs.draw_thetas(P, B, w.seed), dtype=torch.float64, device="cuda")
+    r = timed_batch(prob, thetas, steps, 1, stream, name)
+    prob.close()
+    value = B * steps / r["elapsed"]
+    f_alg = sum(alg_flops_per_step(k, n, P) for k in ("eig", "forward", "backward", "sterm")) * nt
+    ach, frac = eig_roofline(r["ktimes"], n, P, nt, B)
+    par = parity_vs_oracle(name, r["costs"], r["grads"], r["hess"])
+    log(f"bench: {name}: {value:.1f} evals/s, parity {par['max_rel_err']:.2e}")
+    return {"workload": f"{name}: N={n}, J={nt}, dt={w.dt}, Fourier K={w.k} (P={P}), {B} theta ~ N(0, 0.1^2)",
+            "evals_per_s": value, "steps": steps, "ms_per_step": 1e3 * r["elapsed"] / steps,
+            "kernel_ms": {k: round(v[0], 3) for k, v in r["ktimes"].items()},
+            "path_alg_flops_per_eval": f_alg, "path_roofline_frac": f_alg * value / PEAK_FP64,
+            "eig_roofline": {"achieved": ach, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s", "frac": frac,
+                             "bound": "alu"},
+            "jacobi_sweeps_per_step": r["sweeps_per_step"], "parity": par}
+
+
+WARM_MODEL = os.path.join(ROOT, "paper_2505_00529_amd", "data", "warm_c5_mlp.npz")
+
+
+def tr_plain_vs_warm(count: int) -> dict:
+    """Trust-region solves per second on the 64-level system (N=64, J=4000, K=32) for `count`
+    held-out targets: from theta = 0 (plain) and from the learned warm start (network inference
+    included), with the plain solve judging the final cost (same minimum within 1e-8)."""
+    from paper_2505_00529_amd import warmstart as W
+
+    w = inputs.make_workload("warm")
+    prob = qoc.problem_from_workload(w, device=0)
+    targets = inputs.warm_targets(w.system.n, count, spawn=1)
+    ws = W.WarmStart.load(prob, WARM_MODEL)
+    log(f"bench: {count} trust-region solves on the 64-level system, plain and warm-started ...")
+    th, c, its, conv, ps = W.solve_plain(prob, targets, 1e-8, 1000)
+    wr = ws.solve(targets, 1e-8, 1000)
+    cmp = W.compare(c, wr["cost"])
+    meta = np.load(WARM_MODEL)
+    prob.close()
+    log(f"bench: plain {count / ps:.2f} solves/s, warm {count / wr['seconds']:.2f} solves/s")
+    return {"workload": "warm: N=64, J=4000, dt=0.02, Fourier K=32 (P=64); held-out targets in the lowest-8 "
+                        "eigenspace", "solves": count,
+            "plain": {"solves_per_s": count / ps, "seconds": ps, "iters_mean": float(its.mean()),
+                      "converged": int(conv.sum())},
+            "warm": {"solves_per_s": count / wr["seconds"], "seconds": wr["seconds"],
+                     "iters_mean": float(wr["iters"].mean()), "converged": int(wr["converged"].sum()),
+                     "fallback": int(wr["fallback"].sum())},
+            "same_final_cost_1e-8": cmp["match"], "warm_lower": cmp["lower"], "warm_higher": cmp["higher"],
+            "network": f"trained on the zero-start iterate after {int(meta['target_iters'])} iterations of "
+                       f"{int(meta['train'])} training targets (paper_2505_00529_amd/data/warm_c5_mlp.npz)",
+            "note": "gradient norm < 1e-8 on the controllable subspace; lockstep batches of 256"}
 
 
 def run_batched(args) -> int:
@@ -212,8 +326,12 @@ def run_batched(args) -> int:
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=["molecule", "batched"], default="molecule",
-                    help="molecule: the headline evals/s line; batched: 256 uneven problems")
+    ap.add_argument("--workload", choices=["molecule", "warm", "batched"], default="molecule",
+                    help="molecule: the headline evals/s line (N=36, P=32); warm: the 64-level system "
+                         "(N=64, P=64); batched: 256 uneven problems")
+    ap.add_argument("--n64-steps", type=int, default=4,
+                    help="with the molecule workload, also time this many steps of the 64-level system "
+                         "(256 theta) and report them beside the headline (0: skip)")
     ap.add_argument("--count", type=int, default=256, help="problems in the batched workload")
     ap.add_argument("--unbatched-steps", type=int, default=1)
     ap.add_argument("--no-autotune", action="store_true")
@@ -223,6 +341,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--latency-calls", type=int, default=30, help="single-theta calls timed for the latency")
     ap.add_argument("--tr-solves", type=int, default=32, help="plain trust-region solves timed after the steps")
+    ap.add_argument("--tr-warm", type=int, default=128,
+                    help="held-out targets of the 64-level system solved plain and warm-started (0: skip)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after timing, run one device-to-device copy of this many MiB (a reference "
                          "dispatch of known traffic for HBM byte counters; use more than the last-level "
@@ -241,60 +361,28 @@ def main() -> int:
     import torch
 
     torch.cuda.set_device(0)
-    w = inputs.make_workload("molecule")
+    wl = args.workload
+    w = inputs.make_workload(wl)
     n, P, nt, B = w.system.n, w.p, w.nt, args.batch
-    log(f"bench: workload molecule n={n} nt={nt} P={P} batch={B}")
+    log(f"bench: workload {wl} n={n} nt={nt} P={P} batch={B}")
     prob = qoc.problem_from_workload(w, device=0)
     stream = torch.cuda.current_stream()
     prob.set_stream(stream.cuda_stream)
 
     thetas = torch.tensor(inputs.draw_thetas(P, B, w.seed), dtype=torch.float64, device="cuda")
-    costs = torch.empty(B, dtype=torch.float64, device="cuda")
-    grads = torch.empty(B, P, dtype=torch.float64, device="cuda")
-    hess = torch.empty(B, P, P, dtype=torch.float64, device="cuda")
-
-    def step():
-        prob.hess_many_dev(B, thetas.data_ptr(), costs.data_ptr(), grads.data_ptr(), hess.data_ptr())
-
-    for i in range(args.warmup):
-        step()
-        torch.cuda.synchronize()
-        log(f"bench: warmup {i + 1}/{args.warmup} done")
-    prob.sync()
-    prob.jacobi_stats(reset=True)
-    prob.profile_enable(True)
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev[0].record(stream)
-    for i in range(args.steps):
-        step()
-        ev[i + 1].record(stream)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    prob.sync()
-    step_ms = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps)])
-    log(f"bench: {args.steps} timed steps in {t1 - t0:.3f} s")
-
-    kernels = ["controls", "eig", "boundary", "forward", "terminal", "backward", "sterm", "assemble"]
-    ktimes = {}
-    for k in kernels:
-        ms, cnt = prob.profile_kernel_ms(k)
-        if cnt:
-            ktimes[k] = (ms / cnt, cnt)
-    prob.profile_enable(False)
-    eig_steps, eig_sweeps = prob.jacobi_stats(reset=True)
+    r = timed_batch(prob, thetas, args.steps, args.warmup, stream, wl)
+    t0, t1 = 0.0, r["elapsed"]
+    step_ms, ktimes = r["step_ms"], r["ktimes"]
+    eig_sweeps_per_step = r["sweeps_per_step"]
     dom = max(ktimes, key=lambda k: ktimes[k][0])
     avg_ms = ktimes[dom][0]
     flops_launch = alg_flops_per_step(dom, n, P) * nt * B
     achieved = flops_launch / (avg_ms * 1e-3) / 1e12
     peak = PEAK_FP64 / 1e12
 
-    h = hess.cpu().numpy()
-    c_np = costs.cpu().numpy()
-    g_np = grads.cpu().numpy()
+    h, c_np, g_np = r["hess"], r["costs"], r["grads"]
     assert np.all(np.isfinite(h)) and np.all(np.isfinite(c_np))
-    parity = parity_vs_oracle(c_np, g_np, h)
+    parity = parity_vs_oracle(wl, c_np, g_np, h)
     log(f"bench: parity of the timed batch against the oracle: max rel err {parity['max_rel_err']:.2e}")
 
     # single-problem latency (B = 1) on its own handle, so the batch workspace stays in place
@@ -365,7 +453,7 @@ def main() -> int:
     value = B * args.steps / elapsed
     f_alg = sum(alg_flops_per_step(k, n, P) for k in ("eig", "forward", "backward", "sterm")) * nt
     out = {
-        "metric": "grad+Hessian evals/s (FP64, N=36, P=32)",
+        "metric": f"grad+Hessian evals/s (FP64, N={n}, P={P})",
         "value": value,
         "unit": "evals/s",
         "n_gpus": 1,
@@ -378,7 +466,7 @@ def main() -> int:
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": "molecule: N=36, J=4000, dt=0.02, Fourier K=16 (P=32), "
+            "workload": f"{wl}: N={n}, J={nt}, dt={w.dt}, Fourier K={w.k} (P={P}), "
                         f"{B} independent theta ~ N(0, 0.1^2) per step",
             "n": n, "nt": nt, "P": P, "batch": B, "parallelism": "single GPU",
         },
@@ -397,7 +485,7 @@ def main() -> int:
         "grad_only_evals_per_s": B / tg,
         "hess_to_grad_time_ratio": (elapsed / args.steps) / tg,
         "tr_plain": tr,
-        "jacobi_sweeps_per_step": eig_sweeps / max(eig_steps, 1),
+        "jacobi_sweeps_per_step": eig_sweeps_per_step,
         "path_alg_flops_per_eval": f_alg,
         "path_roofline_frac": f_alg * value / PEAK_FP64,
         "parity": parity,
@@ -413,11 +501,17 @@ def main() -> int:
         torch.cuda.synchronize()
         out["calib_copy_bytes"] = int(nel * 8)
         del src, dst
+    prob.close()
+    if wl == "molecule" and args.n64_steps > 0:
+        out["n64_system"] = secondary_system("warm", 256, args.n64_steps, stream)
+        if not out["n64_system"]["parity"]["ok"]:
+            parity["ok"] = False
+    if args.tr_warm > 0:
+        out["tr_solves_per_s_plain_vs_warm"] = tr_plain_vs_warm(args.tr_warm)
     if not args.no_cpu_baseline:
         log("bench: timing the CPU oracle on one theta ...")
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)
-    prob.close()
     if not parity["ok"]:
         log(f"bench: PARITY FAILURE: max rel err {parity['max_rel_err']:.3e} above {PARITY_TOL:g}")
         return 1

@@ -9,6 +9,14 @@ c = diag(sigma_r) V_r^T theta (``qoc_control_coords``), which are isometric to t
 control f = B theta; a half-period Fourier basis is numerically rank-deficient, so the raw
 coefficients are not identifiable and make poor regression targets.
 
+The regression target is the zero-start solver's own iterate after k iterations (k =
+``target_iters``; 0 means the final optimum).  The optimum reached from theta = 0 is a
+discontinuous function of the target (the plain solve lands in one of many nearby local
+minima), so it cannot be learned from a few thousand samples; the early iterate is a smooth
+function of the target away from the few targets where a ratio test decides differently, and a
+warm solve started close to it continues along the plain solve's path into the same minimum,
+skipping about k iterations.
+
 The plain zero-start solve stays the reference and the fallback: a warm solve that does not
 converge is rerun from theta = 0, and its final cost is compared with the plain solve's.
 
@@ -97,6 +105,20 @@ class WarmStart:
             history.append(acc / steps_per_epoch)
         return history
 
+    # -- persistence
+    def save(self, path: str, **extra):
+        """Trained parameters and output normalisation (.npz)."""
+        np.savez_compressed(path, params=self.mlp.get_params(), mean=self.mean, scale=self.scale,
+                            rank=np.int64(self.rank), n_hidden=np.int64(self.mlp.n_hidden), **extra)
+
+    @classmethod
+    def load(cls, problem: "qoc.Problem", path: str, max_batch: int = 256) -> "WarmStart":
+        d = np.load(path)
+        ws = cls(problem, n_hidden=int(d["n_hidden"]), max_batch=max_batch)
+        ws.mlp.set_params(d["params"])
+        ws.mean, ws.scale, ws.rank = d["mean"], d["scale"], int(d["rank"])
+        return ws
+
     # -- inference
     def predict_coords(self, targets) -> np.ndarray:
         import torch
@@ -118,20 +140,38 @@ class WarmStart:
         """Starting parameters theta_0 (count x P) for the given targets."""
         return self.problem.params_from_coords(self.predict_coords(targets))
 
-    def solve(self, targets, gtol: float = 1e-8, max_iter: int = 10000):
-        """Warm-started solves with the zero-start fallback.  Returns a dict of per-target
-        arrays (theta, cost, iters, converged, fallback) and the wall time."""
+    def solve(self, targets, gtol: float = 1e-8, max_iter: int = 10000, chunk: int = 256, verbose: bool = False):
+        """Warm-started solves with the zero-start fallback, in lockstep chunks of `chunk` targets.
+        Returns a dict of per-target arrays (theta, cost, iters, converged, fallback) and the wall
+        time (network inference included)."""
+        targets = np.asarray(targets)
+        count = targets.shape[0]
         t0 = time.perf_counter()
         th0 = self.predict(targets)
-        th, c, its, conv = self.problem.tr_solve_many(th0, targets, gtol=gtol, max_iter=max_iter)
+        th = np.zeros((count, self.n_out))
+        c = np.zeros(count)
+        its = np.zeros(count, dtype=np.int32)
+        conv = np.zeros(count, dtype=bool)
+        for s in range(0, count, chunk):
+            e = min(count, s + chunk)
+            th[s:e], c[s:e], its[s:e], conv[s:e] = self.problem.tr_solve_many(th0[s:e], targets[s:e], gtol=gtol,
+                                                                              max_iter=max_iter)
+            if verbose:
+                print(f"[warmstart]   warm solved {e}/{count} ({time.perf_counter() - t0:.1f} s)", flush=True)
         fb = ~conv
         if fb.any():
             idx = np.flatnonzero(fb)
-            th2, c2, its2, conv2 = self.problem.tr_solve_many(np.zeros((idx.size, self.n_out)),
-                                                              np.asarray(targets)[idx], gtol=gtol, max_iter=max_iter)
+            th2, c2, its2, conv2 = solve_plain(self.problem, targets[idx], gtol, max_iter, chunk)[:4]
             th[idx], c[idx], conv[idx] = th2, c2, conv2
             its[idx] += its2
         return dict(theta=th, cost=c, iters=its, converged=conv, fallback=fb, seconds=time.perf_counter() - t0)
+
+
+def early_iterates(problem: "qoc.Problem", targets, k: int, gtol: float = 1e-8, chunk: int = 256):
+    """The zero-start trust-region iterate after k iterations for every target (the solver is
+    deterministic, so this is the plain solve's own path; a solve that converges earlier gives
+    its optimum)."""
+    return solve_plain(problem, targets, gtol, k, chunk)
 
 
 def solve_plain(problem: "qoc.Problem", targets, gtol: float = 1e-8, max_iter: int = 10000, chunk: int = 256,
@@ -151,6 +191,39 @@ def solve_plain(problem: "qoc.Problem", targets, gtol: float = 1e-8, max_iter: i
         if verbose:
             print(f"[warmstart]   solved {e}/{count} ({time.perf_counter() - t0:.1f} s)", flush=True)
     return th, c, its, conv, time.perf_counter() - t0
+
+
+def regression_baselines(problem: "qoc.Problem", train_targets, train_thetas, test_targets, test_thetas) -> dict:
+    """How well plain regressors predict the network's regression target from the target state,
+    in the same metric coordinates: median relative error on the held-out targets of the
+    training mean, ridge regression (linear and quadratic features) and k-nearest neighbours.
+    A map no better than the mean is not learnable from that many samples."""
+    from sklearn.linear_model import Ridge
+    from sklearn.neighbors import KNeighborsRegressor
+
+    def feats(t):
+        return target_features(t).astype(np.float64)
+
+    def quad(x):
+        iu = np.triu_indices(x.shape[1])
+        return np.concatenate([x, (x[:, :, None] * x[:, None, :])[:, iu[0], iu[1]]], axis=1)
+
+    ctr, r = problem.control_coords(train_thetas)
+    cte, _ = problem.control_coords(test_thetas)
+    ctr, cte = ctr[:, :r], cte[:, :r]
+    xtr, xte = feats(train_targets), feats(test_targets)
+    keep = np.abs(xtr).max(axis=0) > 0   # the target's nonzero components
+    xtr, xte = xtr[:, keep], xte[:, keep]
+
+    def err(pred):
+        return float(np.median(np.linalg.norm(pred - cte, axis=1) / np.linalg.norm(cte, axis=1)))
+
+    out = {"mean": err(np.tile(ctr.mean(axis=0), (cte.shape[0], 1))),
+           "ridge": err(Ridge(alpha=1e-3).fit(xtr, ctr).predict(xte)),
+           "ridge_quadratic": err(Ridge(alpha=1e-3).fit(quad(xtr), ctr).predict(quad(xte)))}
+    for k in (1, 5, 20):
+        out[f"knn{k}"] = err(KNeighborsRegressor(k).fit(xtr, ctr).predict(xte))
+    return out
 
 
 def compare(plain_cost, warm_cost, tol: float = 1e-8) -> dict:
@@ -173,8 +246,11 @@ def main(argv: Optional[list] = None):
     ap.add_argument("--batch", type=int, default=128)
     ap.add_argument("--gtol", type=float, default=1e-8)
     ap.add_argument("--max-iter", type=int, default=1000)
+    ap.add_argument("--target-iters", type=int, default=8,
+                    help="regress the zero-start iterate after this many iterations (0: the final optimum)")
     ap.add_argument("--save", default=None, help="write the training set and trained parameters (.npz)")
     ap.add_argument("--load", default=None, help="training set from an earlier --save instead of solving")
+    ap.add_argument("--save-model", default=None, help="write only the trained network (.npz, for WarmStart.load)")
     args = ap.parse_args(argv)
 
     w = inputs.make_workload(args.workload, n=args.n)
@@ -189,26 +265,35 @@ def main(argv: Optional[list] = None):
         args.train = len(tr_t)
         print(f"[warmstart] loaded {args.train} training pairs from {args.load}", flush=True)
     else:
-        print(f"[warmstart] {args.workload}: n={w.system.n} nt={w.nt} P={w.p}; solving {args.train} training "
-              "targets", flush=True)
-        tr_th, tr_c, tr_it, tr_conv, tr_s = solve_plain(p, tr_t, args.gtol, args.max_iter, verbose=True)
-    print(f"[warmstart] training set: {tr_s:.1f} s, converged {int(tr_conv.sum())}/{args.train}, "
-          f"mean iters {tr_it.mean():.1f}", flush=True)
+        k = args.target_iters
+        print(f"[warmstart] {args.workload}: n={w.system.n} nt={w.nt} P={w.p}; "
+              + (f"zero-start iterates after {k} iterations for" if k > 0 else "solving")
+              + f" {args.train} training targets", flush=True)
+        tr_th, tr_c, tr_it, tr_conv, tr_s = solve_plain(p, tr_t, args.gtol, k if k > 0 else args.max_iter,
+                                                        verbose=True)
+        if k > 0:
+            tr_conv = np.ones(args.train, dtype=bool)   # an early iterate is a target whether or not converged
+    print(f"[warmstart] training set: {tr_s:.1f} s, mean iters {tr_it.mean():.1f}", flush=True)
     ws = WarmStart(p)
     t0 = time.perf_counter()
     hist = ws.fit(tr_t[tr_conv], tr_th[tr_conv], epochs=args.epochs, lr=args.lr, batch=args.batch)
     fit_s = time.perf_counter() - t0
     print(f"[warmstart] trained {args.epochs} epochs in {fit_s:.1f} s, loss {hist[0]:.4f} -> {hist[-1]:.4f}",
           flush=True)
-    pl_th, pl_c, pl_it, pl_conv, pl_s = solve_plain(p, te_t, args.gtol, args.max_iter)
+    pl_th, pl_c, pl_it, pl_conv, pl_s = solve_plain(p, te_t, args.gtol, args.max_iter, verbose=True)
     print(f"[warmstart] plain held-out: {pl_s:.1f} s, mean iters {pl_it.mean():.1f}", flush=True)
-    wr = ws.solve(te_t, args.gtol, args.max_iter)
+    wr = ws.solve(te_t, args.gtol, args.max_iter, verbose=True)
     print(f"[warmstart] warm held-out: {wr['seconds']:.1f} s, mean iters {wr['iters'].mean():.1f}", flush=True)
     cmp = compare(pl_c, wr["cost"])
+    # the held-out values of the regression target: early iterates, or the plain optima
+    ref_th = early_iterates(p, te_t, args.target_iters, args.gtol)[0] if args.target_iters > 0 else pl_th
+    print("[warmstart] regression baselines ...", flush=True)
+    base = regression_baselines(p, tr_t[tr_conv], tr_th[tr_conv], te_t, ref_th)
     pred_c = ws.predict_coords(te_t)
-    true_c, _ = p.control_coords(pl_th)
+    true_c, _ = p.control_coords(ref_th)
     out = dict(
         workload=args.workload, n=w.system.n, nt=w.nt, P=w.p, rank=ws.rank, train=args.train, test=args.test,
+        target_iters=args.target_iters,
         train_converged=int(tr_conv.sum()), train_seconds=round(tr_s, 2), fit_seconds=round(fit_s, 2),
         loss_first=hist[0], loss_last=hist[-1],
         coord_rel_err_median=float(np.median(np.linalg.norm(pred_c - true_c, axis=1) / np.linalg.norm(true_c, axis=1))),
@@ -218,12 +303,15 @@ def main(argv: Optional[list] = None):
                   iters_mean=float(wr["iters"].mean()), iters_median=float(np.median(wr["iters"])),
                   converged=int(wr["converged"].sum()), fallback=int(wr["fallback"].sum())),
         cost_agreement=cmp,
+        regression_baselines_rel_err=base,
     )
     print(json.dumps(out), flush=True)
     if args.save:
         np.savez(args.save, train_targets=tr_t, train_thetas=tr_th, train_costs=tr_c, train_iters=tr_it,
                  train_converged=tr_conv, train_seconds=tr_s, params=ws.mlp.get_params(), mean=ws.mean,
-                 scale=ws.scale)
+                 scale=ws.scale, rank=ws.rank, target_iters=args.target_iters)
+    if args.save_model:
+        ws.save(args.save_model, target_iters=np.int64(args.target_iters), train=np.int64(args.train))
     return out
 
 

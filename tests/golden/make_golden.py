@@ -1,7 +1,10 @@
-"""Write oracle reference values for the full-size molecule workload (N=36, J=4000, K=16).
+"""Write oracle reference values for a full-size workload: the molecule workload (N=36,
+J=4000, K=16) by default, or the 64-level warm-start system (N=64, J=4000, K=32) with
+argument "warm".  Two thetas (the first rows of the benchmark's batch) with cost, gradient
+and Hessian, and one HVP for the first.
 
 Calls only the CPU oracle (oracle/) and the seeded input generators; run from the repo
-root:  python tests/golden/make_golden.py
+root:  python tests/golden/make_golden.py [molecule|warm]
 """
 import json
 import os
@@ -16,11 +19,12 @@ import numpy as np  # noqa: E402
 from oracle import qoc_oracle as O  # noqa: E402
 from paper_2505_00529_amd import inputs  # noqa: E402
 
-OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "molecule_oracle.json")
+HERE = os.path.dirname(os.path.abspath(__file__))
 
 
-def main():
-    w = inputs.make_workload("molecule")
+def main(name="molecule"):
+    out = os.path.join(HERE, f"{name}_oracle.json")
+    w = inputs.make_workload(name)
     s = w.system
     basis = O.fourier_basis(w.nt, w.dt, w.k)
     args = (s.h0, s.m, s.psi0, s.psi_target, basis, w.dt)
@@ -38,16 +42,16 @@ def main():
         cases.append(case)
         print(f"theta {i}: {time.time() - t0:.1f} s", flush=True)
     doc = {
-        "workload": "molecule", "n": w.system.n, "nt": w.nt, "dt": w.dt, "k": w.k,
+        "workload": name, "n": w.system.n, "nt": w.nt, "dt": w.dt, "k": w.k,
         "gamma": w.gamma, "rho": w.rho, "seed": w.seed,
         "source": "oracle/qoc_oracle.py cost_grad_hess and hvp; thetas = inputs.draw_thetas(P, 2, seed), "
                   "v = inputs.draw_directions(P, 1, seed)",
         "cases": cases,
     }
-    with open(OUT, "w") as fh:
+    with open(out, "w") as fh:
         json.dump(doc, fh, indent=1)
-    print("wrote", OUT)
+    print("wrote", out)
 
 
 if __name__ == "__main__":
-    main()
+    main(sys.argv[1] if len(sys.argv) > 1 else "molecule")
