@@ -174,6 +174,39 @@ qoc_status qoc_tr_solve_many(qoc_problem* p, int32_t count, const double* theta0
                              double gtol, int32_t max_iter, double* theta_out, double* cost_out,
                              int32_t* iters_out, int32_t* converged_out);
 
+/* Subproblem solver of both trust-region solvers.  DEFAULT: the exact solver minimises the
+ * model on the ball through an eigendecomposition of the (whitened) Hessian on the device, the
+ * BFGS solver takes the dogleg step.  CG: both take the Steihaug-Toint truncated conjugate-
+ * gradient step (Nocedal & Wright 2006, Alg. 7.2), which needs matrix-vector products only, so
+ * the two solvers differ in nothing but the Hessian they are given. */
+typedef enum {
+  QOC_TR_SUBPROBLEM_DEFAULT = 0,
+  QOC_TR_SUBPROBLEM_CG = 1,
+} qoc_tr_subproblem;
+qoc_status qoc_set_tr_subproblem(qoc_problem* p, int32_t kind);
+
+/* Step tolerance of both trust-region solvers (the paper's delta test on the parameter change,
+ * Alg. 1 and Alg. 2 stopping rules): a solve also stops, unconverged unless the gradient test
+ * holds, once the step it just evaluated is shorter than xtol (theta 2-norm) or its radius has
+ * shrunk below xtol.  Default 0 (off).  QOC_ERR_INVALID_ARG unless xtol is finite and >= 0. */
+qoc_status qoc_set_tr_step_tolerance(qoc_problem* p, double xtol);
+
+/* Quasi-Newton twin of qoc_tr_solve_many for the paper's comparison of Alg. 1 (gradient by the
+ * first-order adjoint) with Alg. 2 (exact Hessian) (Sec. IV-B): the same trust region, ratio
+ * test, radius rules and stopping test, with the Hessian replaced by a BFGS approximation
+ * (first update scaled by y^T y / y^T s; updates without positive curvature skipped) and the
+ * subproblem solved by the dogleg path.  Each iteration costs one gradient evaluation per active
+ * solve.  Arguments, outputs and return value as qoc_tr_solve_many; iters_out counts evaluated
+ * trial points (accepted or not). */
+qoc_status qoc_tr_solve_bfgs_many(qoc_problem* p, int32_t count, const double* theta0, const double* targets,
+                                  double gtol, int32_t max_iter, double* theta_out, double* cost_out,
+                                  int32_t* iters_out, int32_t* converged_out);
+/* The BFGS update used by qoc_tr_solve_bfgs_many (host arithmetic, no device): with s^T y > 0,
+ * b <- b - (b s)(b s)^T / (s^T b s) + y y^T / (y^T s) and h <- its inverse update (r x r row-major,
+ * h = b^{-1} on entry); rescale != 0 first resets b = (y^T y / y^T s) I and h = b^{-1}.
+ * QOC_ERR_INVALID_ARG if s^T y <= 0 or a pointer is NULL. */
+qoc_status qoc_bfgs_update(int32_t r, double* b, double* h, const double* s, const double* y, int32_t rescale);
+
 /* Both stationarity measures of `count` gradients (count x P): gnorm_out[i] = ||g_i||_2 and
  * proj_out[i] = ||V_r^T g_i||_2, the measure the trust-region solve stops on (either output may
  * be NULL).  They agree for a well-conditioned control basis. */

@@ -819,6 +819,21 @@ qoc_status qoc_set_jacobi_tolerance(qoc_problem* p, double tol_rel) {
   return QOC_OK;
 }
 
+qoc_status qoc_set_tr_subproblem(qoc_problem* p, int32_t kind) {
+  if (!p) return QOC_ERR_INVALID_ARG;
+  if (kind != QOC_TR_SUBPROBLEM_DEFAULT && kind != QOC_TR_SUBPROBLEM_CG)
+    return p->fail(QOC_ERR_INVALID_ARG, "unknown trust-region subproblem solver");
+  p->tr_subproblem = kind;
+  return QOC_OK;
+}
+
+qoc_status qoc_set_tr_step_tolerance(qoc_problem* p, double xtol) {
+  if (!p) return QOC_ERR_INVALID_ARG;
+  if (!std::isfinite(xtol) || xtol < 0.0) return p->fail(QOC_ERR_INVALID_ARG, "step tolerance must be finite and >= 0");
+  p->tr_xtol = xtol;
+  return QOC_OK;
+}
+
 qoc_status qoc_set_checkpoint_interval(qoc_problem* p, int32_t steps) {
   if (!p) return QOC_ERR_INVALID_ARG;
   if (steps < 0) return p->fail(QOC_ERR_INVALID_ARG, "interval must be >= 0");

@@ -92,6 +92,9 @@ struct qoc_problem {
   std::vector<double> tr_vr;       // P x rank right singular vectors of the control matrix kept
   std::vector<double> tr_sigma;    // their singular values
   int tr_rank = 0;
+  bool tr_whiten_identity = false; // W = I (orthonormal control basis)
+  int tr_subproblem = QOC_TR_SUBPROBLEM_DEFAULT;
+  double tr_xtol = 0.0;             // trust-region step / radius stopping tolerance (0: off)
   int tr_basis_version = -1;
   int basis_version = 0;
 };

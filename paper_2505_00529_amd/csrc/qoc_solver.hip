@@ -20,6 +20,7 @@
 #include <cmath>
 #include <cstring>
 #include <limits>
+#include <thread>
 #include <vector>
 
 #include "../../include/qoc.h"
@@ -37,6 +38,134 @@ double norm2(const double* x, int n) {
   double a = 0.0;
   for (int i = 0; i < n; ++i) a += x[i] * x[i];
   return std::sqrt(a);
+}
+
+// y = A x for a symmetric R x R row-major A, accumulated as the sum over c of x_c times row c
+// (= column c): contiguous, independent updates that vectorise, where the row-dot form is one
+// dependent chain of additions per entry.
+void symv(int R, const double* A, const double* x, double* y) {
+  for (int a = 0; a < R; ++a) y[a] = 0.0;
+  for (int c = 0; c < R; ++c) {
+    const double xc = x[c];
+    const double* row = A + (size_t)c * R;
+    for (int a = 0; a < R; ++a) y[a] += xc * row[a];
+  }
+}
+
+// BFGS update of the Hessian approximation B and its inverse H (R x R, row-major) from the step s
+// and gradient change y with s^T y > 0 (Nocedal & Wright 2006, eqs. 6.17 and 6.19):
+//   B <- B - (B s)(B s)^T / (s^T B s) + y y^T / (y^T s),
+//   H <- (I - r s y^T) H (I - r y s^T) + r s s^T,  r = 1 / (y^T s),
+// with H expanded as H - r (s (H y)^T + (H y) s^T) + (r^2 y^T H y + r) s s^T.  With `rescale`
+// (the first update), B and H are first reset to (y^T y / y^T s) I and its inverse (eq. 6.20).
+void bfgs_update(int R, double* B, double* H, const double* s, const double* y, bool rescale) {
+  double sy = 0.0, yy = 0.0;
+  for (int r = 0; r < R; ++r) {
+    sy += s[r] * y[r];
+    yy += y[r] * y[r];
+  }
+  if (rescale) {
+    const double sc = yy / sy;
+    for (size_t e = 0; e < (size_t)R * R; ++e) {
+      B[e] = 0.0;
+      H[e] = 0.0;
+    }
+    for (int r = 0; r < R; ++r) {
+      B[(size_t)r * R + r] = sc;
+      H[(size_t)r * R + r] = 1.0 / sc;
+    }
+  }
+  std::vector<double> bs(R), hy(R);
+  symv(R, B, s, bs.data());
+  symv(R, H, y, hy.data());
+  double sbs = 0.0, yhy = 0.0;
+  for (int r = 0; r < R; ++r) {
+    sbs += s[r] * bs[r];
+    yhy += y[r] * hy[r];
+  }
+  const double rh = 1.0 / sy;
+  for (int r = 0; r < R; ++r)
+    for (int c = 0; c < R; ++c) {
+      B[(size_t)r * R + c] += y[r] * y[c] * rh - bs[r] * bs[c] / sbs;
+      H[(size_t)r * R + c] += -rh * (s[r] * hy[c] + hy[r] * s[c]) + (rh * rh * yhy + rh) * s[r] * s[c];
+    }
+}
+
+// fn(k) for k in [0, count) on up to 16 host threads (independent trials of a lockstep batch).
+template <class F>
+void parallel_for(int count, F fn) {
+  const int nt = std::max(1, std::min({count / 4, 16, (int)std::thread::hardware_concurrency()}));
+  if (nt <= 1) {
+    for (int k = 0; k < count; ++k) fn(k);
+    return;
+  }
+  std::vector<std::thread> pool;
+  for (int t = 0; t < nt; ++t)
+    pool.emplace_back([&, t] {
+      for (int k = t; k < count; k += nt) fn(k);
+    });
+  for (auto& th : pool) th.join();
+}
+
+// Steihaug-Toint truncated conjugate gradients for min g^T u + u^T B u / 2 over |u| <= delta
+// (Nocedal & Wright 2006, Alg. 7.2; forcing tolerance min(0.5, sqrt|g|) |g|, their eq. 7.3):
+// CG from u = 0 until the residual meets the tolerance, a direction of non-positive curvature
+// appears (then the boundary point along it with the lower model value), or an iterate would
+// leave the region (then the boundary crossing).  B: R x R row-major symmetric.  Writes u;
+// returns whether u lies on the boundary.  Matrix-vector products only: O(R^2) per CG step.
+bool steihaug_cg(int R, const double* B, const double* g, double delta, double* u) {
+  std::vector<double> r(g, g + R), d(R), bd(R);
+  for (int a = 0; a < R; ++a) {
+    u[a] = 0.0;
+    d[a] = -g[a];
+  }
+  double rr = 0.0;
+  for (int a = 0; a < R; ++a) rr += r[a] * r[a];
+  const double gn = std::sqrt(rr), eps = std::min(0.5, std::sqrt(gn)) * gn;
+  if (!(gn > 0.0)) return false;
+  // the root tau >= 0 (or both roots) of |u + tau d| = delta
+  auto to_boundary = [&](bool both) {
+    double dd = 0.0, ud = 0.0, uu = 0.0, rd = 0.0, dbd = 0.0;
+    for (int a = 0; a < R; ++a) {
+      dd += d[a] * d[a];
+      ud += u[a] * d[a];
+      uu += u[a] * u[a];
+      rd += r[a] * d[a];
+      dbd += d[a] * bd[a];
+    }
+    const double disc = std::sqrt(std::max(0.0, ud * ud - dd * (uu - delta * delta)));
+    double tau = (-ud + disc) / dd;
+    if (both) {
+      const double t2 = (-ud - disc) / dd;
+      if (t2 * rd + 0.5 * t2 * t2 * dbd < tau * rd + 0.5 * tau * tau * dbd) tau = t2;
+    }
+    for (int a = 0; a < R; ++a) u[a] += tau * d[a];
+    return true;
+  };
+  for (int it = 0; it < 2 * R; ++it) {
+    symv(R, B, d.data(), bd.data());
+    double dbd = 0.0;
+    for (int a = 0; a < R; ++a) dbd += d[a] * bd[a];
+    if (!(dbd > 0.0)) return to_boundary(true);
+    const double alpha = rr / dbd;
+    double un = 0.0;
+    for (int a = 0; a < R; ++a) {
+      const double v = u[a] + alpha * d[a];
+      un += v * v;
+    }
+    if (un >= delta * delta) return to_boundary(false);
+    double rr2 = 0.0;
+    for (int a = 0; a < R; ++a) {
+      u[a] += alpha * d[a];
+      r[a] += alpha * bd[a];
+      rr2 += r[a] * r[a];
+    }
+    if (std::sqrt(rr2) < eps) return false;
+    const double beta = rr2 / rr;
+    rr = rr2;
+    for (int a = 0; a < R; ++a) d[a] = -r[a] + beta * d[a];
+  }
+  return false;
 }
 
 struct SubproblemResult {
@@ -266,6 +395,11 @@ static qoc_status ensure_whitening(qoc_problem* p) {
     }
   p->tr_rank = R;
   p->tr_basis_version = p->basis_version;
+  // an orthonormal basis (the maximal model f_j = theta_j) leaves W = I: no whitening products
+  bool ident = R == P;
+  for (int a = 0; a < P && ident; ++a)
+    for (int r = 0; r < R && ident; ++r) ident = p->tr_whiten[(size_t)a * R + r] == (a == r ? 1.0 : 0.0);
+  p->tr_whiten_identity = ident;
   return QOC_OK;
 }
 
@@ -292,18 +426,20 @@ qoc_status qoc_tr_solve_many(qoc_problem* p, int32_t count, const double* theta0
   if (st != QOC_OK) return st;
   std::vector<double> delta(count, 1.0);
   std::vector<int> iters(count, 0), done(count, 0), conv(count, 0);
-  std::vector<double> l, Q, trial, tgt, tc, tg, th2, gw(R), tmp((size_t)P * R);
+  std::vector<double> l, Q, trial, tgt, tc, tg, th2;
   std::vector<int> act;
   std::vector<SubproblemResult> steps;
   const double* Vr = p->tr_vr.data();   // P x R
-  std::vector<double> gproj(R);
-  auto stationarity = [&](const double* g) {
+  const bool ident = p->tr_whiten_identity;
+  auto stationarity = [&](const double* g) {   // ||V_r^T g||_2; safe to call from parallel_for
+    if (ident) return norm2(g, P);
+    double a2 = 0.0;
     for (int r = 0; r < R; ++r) {
       double acc = 0.0;
       for (int a = 0; a < P; ++a) acc += Vr[(size_t)a * R + r] * g[a];
-      gproj[r] = acc;
+      a2 += acc * acc;
     }
-    return norm2(gproj.data(), R);
+    return std::sqrt(a2);
   };
   for (;;) {
     act.clear();
@@ -322,39 +458,63 @@ qoc_status qoc_tr_solve_many(qoc_problem* p, int32_t count, const double* theta0
     const int na = (int)act.size();
     // whitened Hessians W^T H W
     std::vector<double> Ha((size_t)na * RR);
-    for (int k = 0; k < na; ++k) {
+    parallel_for(na, [&](int k) {
       const double* Hi = &H[(size_t)act[k] * PP];
+      double* Hw = &Ha[(size_t)k * RR];
+      if (ident) {
+        std::memcpy(Hw, Hi, PP * sizeof(double));
+        return;
+      }
+      std::vector<double> t((size_t)P * R);
       for (int a = 0; a < P; ++a)
         for (int c = 0; c < R; ++c) {
           double acc = 0.0;
           for (int b2 = 0; b2 < P; ++b2) acc += Hi[a * P + b2] * W[b2 * R + c];
-          tmp[(size_t)a * R + c] = acc;
+          t[(size_t)a * R + c] = acc;
         }
-      double* Hw = &Ha[(size_t)k * RR];
       for (int r = 0; r < R; ++r)
         for (int c = 0; c < R; ++c) {
           double acc = 0.0;
-          for (int a = 0; a < P; ++a) acc += W[a * R + r] * tmp[(size_t)a * R + c];
+          for (int a = 0; a < P; ++a) acc += W[a * R + r] * t[(size_t)a * R + c];
           Hw[r * R + c] = acc;
         }
+    });
+    const bool cg = p->tr_subproblem == QOC_TR_SUBPROBLEM_CG;
+    if (!cg) {
+      l.assign((size_t)na * R, 0.0);
+      Q.assign((size_t)na * RR, 0.0);
+      st = sym_eig_host(p, na, R, Ha.data(), l.data(), Q.data());
+      if (st != QOC_OK) return st;
     }
-    l.assign((size_t)na * R, 0.0);
-    Q.assign((size_t)na * RR, 0.0);
-    st = sym_eig_host(p, na, R, Ha.data(), l.data(), Q.data());
-    if (st != QOC_OK) return st;
     steps.assign(na, SubproblemResult());
     trial.assign((size_t)na * P, 0.0);
     if (targets) tgt.assign((size_t)na * 2 * n, 0.0);
     std::vector<double> pnorm_f(na, 0.0);
-    for (int k = 0; k < na; ++k) {
+    parallel_for(na, [&](int k) {
       const int i = act[k];
       const double* gi = &G[(size_t)i * P];
+      std::vector<double> gw(R);
       for (int r = 0; r < R; ++r) {
         double acc = 0.0;
         for (int a = 0; a < P; ++a) acc += W[a * R + r] * gi[a];
         gw[r] = acc;
       }
-      SubproblemResult sr = tr_subproblem(R, gw.data(), &l[(size_t)k * R], &Q[(size_t)k * RR], delta[i]);
+      SubproblemResult sr;
+      if (cg) {
+        const double* Hw = &Ha[(size_t)k * RR];
+        sr.p.assign(R, 0.0);
+        sr.boundary = steihaug_cg(R, Hw, gw.data(), delta[i], sr.p.data());
+        std::vector<double> hu(R);
+        symv(R, Hw, sr.p.data(), hu.data());
+        double gu = 0.0, uhu = 0.0;
+        for (int a = 0; a < R; ++a) {
+          gu += gw[a] * sr.p[a];
+          uhu += sr.p[a] * hu[a];
+        }
+        sr.pred = -(gu + 0.5 * uhu);
+      } else {
+        sr = tr_subproblem(R, gw.data(), &l[(size_t)k * R], &Q[(size_t)k * RR], delta[i]);
+      }
       pnorm_f[k] = norm2(sr.p.data(), R);   // = ||B p||
       steps[k].pred = sr.pred;
       steps[k].boundary = sr.boundary;
@@ -366,14 +526,14 @@ qoc_status qoc_tr_solve_many(qoc_problem* p, int32_t count, const double* theta0
       }
       for (int r = 0; r < P; ++r) trial[(size_t)k * P + r] = th[(size_t)i * P + r] + steps[k].p[r];
       if (targets) std::memcpy(&tgt[(size_t)k * 2 * n], targets + (size_t)i * 2 * n, 2 * n * sizeof(double));
-    }
+    });
     tc.assign(na, 0.0);
     tg.assign((size_t)na * P, 0.0);
     th2.assign((size_t)na * PP, 0.0);
     st = p->run_host(Mode::Hess, na, trial.data(), nullptr, tc.data(), tg.data(), th2.data(),
                      targets ? tgt.data() : nullptr);
     if (st != QOC_OK) return st;
-    for (int k = 0; k < na; ++k) {
+    parallel_for(na, [&](int k) {
       const int i = act[k];
       const double pn = pnorm_f[k];
       const double pred = steps[k].pred;
@@ -399,16 +559,238 @@ qoc_status qoc_tr_solve_many(qoc_problem* p, int32_t count, const double* theta0
         std::memcpy(&G[(size_t)i * P], &tg[(size_t)k * P], P * sizeof(double));
         std::memcpy(&H[(size_t)i * PP], &th2[(size_t)k * PP], PP * sizeof(double));
       }
-      const double thn = norm2(&th[(size_t)i * P], P);
-      if (stalled || norm2(steps[k].p.data(), P) < 1e-14 * (1.0 + thn) || delta[i] < 1e-300) done[i] = 1;
-    }
+      const double thn = norm2(&th[(size_t)i * P], P), stn = norm2(steps[k].p.data(), P);
+      if (stalled || stn < 1e-14 * (1.0 + thn) || stn < p->tr_xtol || delta[i] < std::max(p->tr_xtol, 1e-300))
+        done[i] = 1;
+    });
   }
   std::memcpy(theta_out, th.data(), (size_t)count * P * sizeof(double));
   if (cost_out) std::memcpy(cost_out, C.data(), count * sizeof(double));
   for (int i = 0; i < count; ++i) {
     if (iters_out) iters_out[i] = iters[i];
-    if (converged_out) converged_out[i] = conv[i];
+    if (converged_out) converged_out[i] = conv[i] || stationarity(&G[(size_t)i * P]) < gtol;
   }
+  return QOC_OK;
+}
+
+// Quasi-Newton trust region driven by the first-order adjoint gradient alone (the optimiser
+// coupled to Alg. 1 for the paper's comparison, Sec. IV-B): the same control-space trust region,
+// ratio test, radius rules and stopping test as qoc_tr_solve_many, with the Hessian replaced by a
+// BFGS approximation B in whitened coordinates (Nocedal & Wright 2006, eq. 6.19; the first
+// update starts from (y^T y / y^T s) I, eq. 6.20; an update whose curvature s^T y is not positive
+// is skipped) and the subproblem solved by the dogleg path between the Cauchy point and the
+// quasi-Newton step -B^{-1} g (Nocedal & Wright, Sec. 4.1).  The inverse H = B^{-1} is updated
+// alongside (eq. 6.17), so an iteration costs O(R^2) per solve besides one gradient evaluation.
+// Curvature pairs come from every evaluated trial point, accepted or not.
+qoc_status qoc_tr_solve_bfgs_many(qoc_problem* p, int32_t count, const double* theta0, const double* targets,
+                                  double gtol, int32_t max_iter, double* theta_out, double* cost_out,
+                                  int32_t* iters_out, int32_t* converged_out) {
+  if (!p) return QOC_ERR_INVALID_ARG;
+  qoc_status st = p->ready();
+  if (st != QOC_OK) return st;
+  if (count < 1 || !theta0 || !theta_out) return p->fail(QOC_ERR_INVALID_ARG, "theta0 / theta_out NULL or count < 1");
+  if (!(gtol > 0.0) || max_iter < 0) return p->fail(QOC_ERR_INVALID_ARG, "gtol must be > 0 and max_iter >= 0");
+  if (targets && !std::all_of(targets, targets + (size_t)count * 2 * p->n, [](double x) { return std::isfinite(x); }))
+    return p->fail(QOC_ERR_INVALID_ARG, "targets have non-finite entries");
+  const int P = p->P, n = p->n;
+  st = ensure_whitening(p);
+  if (st != QOC_OK) return st;
+  const int R = p->tr_rank;
+  const size_t RR = (size_t)R * R;
+  const double* W = p->tr_whiten.data();   // P x R
+  const double* Vr = p->tr_vr.data();      // P x R
+  std::vector<double> th(theta0, theta0 + (size_t)count * P), C(count), G((size_t)count * P);
+  st = p->run_host(Mode::Grad, count, th.data(), nullptr, C.data(), G.data(), nullptr, targets);
+  if (st != QOC_OK) return st;
+  const bool ident = p->tr_whiten_identity;
+  auto whiten = [&](const double* g, double* gw) {   // gw = W^T g
+    if (ident) {
+      std::memcpy(gw, g, R * sizeof(double));
+      return;
+    }
+    for (int r = 0; r < R; ++r) {
+      double acc = 0.0;
+      for (int a = 0; a < P; ++a) acc += W[(size_t)a * R + r] * g[a];
+      gw[r] = acc;
+    }
+  };
+  auto stationarity = [&](const double* g) {   // ||V_r^T g||_2
+    if (ident) return norm2(g, P);
+    double a2 = 0.0;
+    for (int r = 0; r < R; ++r) {
+      double acc = 0.0;
+      for (int a = 0; a < P; ++a) acc += Vr[(size_t)a * R + r] * g[a];
+      a2 += acc * acc;
+    }
+    return std::sqrt(a2);
+  };
+  std::vector<double> Bm((size_t)count * RR, 0.0), Hm((size_t)count * RR, 0.0), GW((size_t)count * R);
+  for (int i = 0; i < count; ++i)
+    for (int r = 0; r < R; ++r) {
+      Bm[(size_t)i * RR + (size_t)r * R + r] = 1.0;
+      Hm[(size_t)i * RR + (size_t)r * R + r] = 1.0;
+    }
+  parallel_for(count, [&](int i) { whiten(&G[(size_t)i * P], &GW[(size_t)i * R]); });
+  std::vector<double> delta(count, 1.0), gnorm(count);
+  std::vector<int> iters(count, 0), done(count, 0), conv(count, 0), scaled(count, 0);
+  std::vector<int> act;
+  std::vector<double> U, pred, trial, tgt, tc, tg;
+  std::vector<char> boundary;
+  parallel_for(count, [&](int i) { gnorm[i] = stationarity(&G[(size_t)i * P]); });
+  for (;;) {
+    act.clear();
+    for (int i = 0; i < count; ++i) {
+      if (done[i]) continue;
+      if (gnorm[i] < gtol) {
+        conv[i] = 1;
+        done[i] = 1;
+      } else if (iters[i] >= max_iter) {
+        done[i] = 1;
+      } else {
+        act.push_back(i);
+      }
+    }
+    if (act.empty()) break;
+    const int na = (int)act.size();
+    U.assign((size_t)na * R, 0.0);
+    pred.assign(na, 0.0);
+    boundary.assign(na, 0);
+    trial.assign((size_t)na * P, 0.0);
+    if (targets) tgt.assign((size_t)na * 2 * n, 0.0);
+    // dogleg steps
+    parallel_for(na, [&](int k) {
+      const int i = act[k];
+      const double* g = &GW[(size_t)i * R];
+      const double* B = &Bm[(size_t)i * RR];
+      const double* H = &Hm[(size_t)i * RR];
+      double* u = &U[(size_t)k * R];
+      const double dl = delta[i];
+      std::vector<double> pb(R), bg(R), bu(R);
+      symv(R, H, g, pb.data());
+      symv(R, B, g, bg.data());
+      double pbn = 0.0, gg = 0.0, gbg = 0.0;
+      for (int r = 0; r < R; ++r) {
+        pb[r] = -pb[r];
+        pbn += pb[r] * pb[r];
+        gg += g[r] * g[r];
+        gbg += g[r] * bg[r];
+      }
+      pbn = std::sqrt(pbn);
+      const double gn = std::sqrt(gg);
+      if (p->tr_subproblem == QOC_TR_SUBPROBLEM_CG) {
+        boundary[k] = steihaug_cg(R, B, g, dl, u);
+      } else if (pbn <= dl) {
+        for (int r = 0; r < R; ++r) u[r] = pb[r];
+      } else if (!(gbg > 0.0) || gg / gbg * gn >= dl) {
+        for (int r = 0; r < R; ++r) u[r] = -dl * g[r] / gn;   // steepest descent to the boundary
+        boundary[k] = 1;
+      } else {
+        // p = pu + tau (pb - pu) with |p| = delta, pu the Cauchy point
+        const double cu = gg / gbg;
+        double a = 0.0, b = 0.0, cc = 0.0;
+        for (int r = 0; r < R; ++r) {
+          const double pu = -cu * g[r], d = pb[r] - pu;
+          a += d * d;
+          b += 2.0 * pu * d;
+          cc += pu * pu;
+        }
+        cc -= dl * dl;
+        const double tau = (-b + std::sqrt(std::max(0.0, b * b - 4.0 * a * cc))) / (2.0 * a);
+        for (int r = 0; r < R; ++r) {
+          const double pu = -cu * g[r];
+          u[r] = pu + tau * (pb[r] - pu);
+        }
+        boundary[k] = 1;
+      }
+      symv(R, B, u, bu.data());
+      double gu = 0.0, ubu = 0.0;
+      for (int r = 0; r < R; ++r) {
+        gu += g[r] * u[r];
+        ubu += u[r] * bu[r];
+      }
+      pred[k] = -(gu + 0.5 * ubu);
+      for (int a = 0; a < P; ++a) {
+        double acc = 0.0;
+        if (ident) {
+          acc = u[a];
+        } else {
+          for (int r = 0; r < R; ++r) acc += W[(size_t)a * R + r] * u[r];
+        }
+        trial[(size_t)k * P + a] = th[(size_t)i * P + a] + acc;
+      }
+      if (targets) std::memcpy(&tgt[(size_t)k * 2 * n], targets + (size_t)i * 2 * n, 2 * n * sizeof(double));
+    });
+    tc.assign(na, 0.0);
+    tg.assign((size_t)na * P, 0.0);
+    st = p->run_host(Mode::Grad, na, trial.data(), nullptr, tc.data(), tg.data(), nullptr,
+                     targets ? tgt.data() : nullptr);
+    if (st != QOC_OK) return st;
+    parallel_for(na, [&](int k) {
+      const int i = act[k];
+      double* B = &Bm[(size_t)i * RR];
+      double* H = &Hm[(size_t)i * RR];
+      const double* u = &U[(size_t)k * R];
+      const double* g = &GW[(size_t)i * R];
+      std::vector<double> gnew(R), y(R);
+      whiten(&tg[(size_t)k * P], gnew.data());
+      const double gcur = gnorm[i], gtr = stationarity(&tg[(size_t)k * P]);
+      // radius and acceptance
+      const double pn = norm2(u, R), pr = pred[k], ared = C[i] - tc[k];
+      bool accept, stalled = false;
+      if (std::fabs(pr) < 1e3 * kEps * std::fabs(C[i])) {
+        accept = gtr < gcur;
+        stalled = !accept;
+      } else {
+        const double rho = ared / pr;
+        if (rho < 0.25) delta[i] = 0.25 * std::min(delta[i], pn);
+        else if (rho > 0.75 && boundary[k]) delta[i] = std::min(2.0 * delta[i], 1e6);
+        accept = rho > 1e-4;
+      }
+      // BFGS update from the pair (s, y) = (u, W^T (g_trial - g))
+      double sy = 0.0, yy = 0.0;
+      for (int r = 0; r < R; ++r) {
+        y[r] = gnew[r] - g[r];
+        sy += u[r] * y[r];
+        yy += y[r] * y[r];
+      }
+      if (sy > 1e-12 * pn * std::sqrt(yy) && std::isfinite(sy)) {
+        bfgs_update(R, B, H, u, y.data(), !scaled[i]);
+        scaled[i] = 1;
+      }
+      double stn = 0.0;   // |theta step|, for the same stopping test as the exact solver
+      for (int a = 0; a < P; ++a) {
+        const double d = trial[(size_t)k * P + a] - th[(size_t)i * P + a];
+        stn += d * d;
+      }
+      iters[i] += 1;
+      if (accept) {
+        std::memcpy(&th[(size_t)i * P], &trial[(size_t)k * P], P * sizeof(double));
+        C[i] = tc[k];
+        std::memcpy(&G[(size_t)i * P], &tg[(size_t)k * P], P * sizeof(double));
+        std::memcpy(&GW[(size_t)i * R], gnew.data(), R * sizeof(double));
+        gnorm[i] = gtr;
+      }
+      const double thn = norm2(&th[(size_t)i * P], P);
+      stn = std::sqrt(stn);
+      if (stalled || stn < 1e-14 * (1.0 + thn) || stn < p->tr_xtol || delta[i] < std::max(p->tr_xtol, 1e-300))
+        done[i] = 1;
+    });
+  }
+  std::memcpy(theta_out, th.data(), (size_t)count * P * sizeof(double));
+  if (cost_out) std::memcpy(cost_out, C.data(), count * sizeof(double));
+  for (int i = 0; i < count; ++i) {
+    if (iters_out) iters_out[i] = iters[i];
+    if (converged_out) converged_out[i] = conv[i] || gnorm[i] < gtol;
+  }
+  return QOC_OK;
+}
+
+qoc_status qoc_bfgs_update(int32_t r, double* b, double* h, const double* s, const double* y, int32_t rescale) {
+  if (r < 1 || !b || !h || !s || !y) return QOC_ERR_INVALID_ARG;
+  double sy = 0.0;
+  for (int k = 0; k < r; ++k) sy += s[k] * y[k];
+  if (!(sy > 0.0) || !std::isfinite(sy)) return QOC_ERR_INVALID_ARG;
+  bfgs_update(r, b, h, s, y, rescale != 0);
   return QOC_OK;
 }
 

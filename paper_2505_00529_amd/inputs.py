@@ -40,6 +40,7 @@ __all__ = [
     "warm_targets",
     "degenerate_system",
     "DEGENERATE_KINDS",
+    "transfer_system",
     "WORKLOADS",
 ]
 
@@ -125,6 +126,16 @@ def molecule_system(rng: np.random.Generator, n: int = 36, target_dim: int = 6) 
     h0 = np.diag(e)
     m = _sym_normal(rng, n, 0.3, zero_diag=False)
     return System(h0, m, _unit(n, 0), _random_unit_in_span(rng, n, min(target_dim, n)))
+
+
+def transfer_system(n: int, seed: int = 12) -> System:
+    """Stand-in for the paper's optimiser-comparison molecules (Sec. IV-B): the molecule recipe
+    (spectrum U[-3, 0] with gap >= 1e-3, dense M ~ N(0, 0.3^2)) driven from the lowest
+    state e_0 to the highest e_{n-1}, the paper's alpha and beta."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, n])))
+    e = spectrum_with_gap(rng, n, -3.0, 1e-3)
+    m = _sym_normal(rng, n, 0.3, zero_diag=False)
+    return System(np.diag(e), m, _unit(n, 0), _unit(n, n - 1))
 
 
 def _default_weights(dt: float):

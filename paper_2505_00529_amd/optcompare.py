@@ -1,0 +1,185 @@
+"""Gradient-only versus exact-Hessian trust region on the paper's optimiser-comparison protocol
+(Sec. IV-B, Tables I and II), on synthetic stand-in systems.
+
+Protocol: maximal model f_j = theta_j (eq. maximal, P = J = 200), dt = 0.1, cost weights 1 on the
+field energy and rho = 1e6 on the target miss (eq. discretecost), alpha = e_0 and beta = e_{N-1},
+stopping tolerances delta = epsilon = 1e-10 and at most 1e4 iterations, theta_0 ~ N(0, I).  Each
+trial solves from the same theta_0 twice: with the BFGS trust region fed by first-order adjoint
+gradients (Alg. 1) and with the exact trust region fed by gradients and Hessians (Alg. 2).  Both
+take Steihaug-Toint truncated-CG subproblem steps by default (--subproblem cg), so that the two
+runs differ only in the Hessian the model is built on; --subproblem default gives the exact solver
+its eigen-exact steps and the BFGS solver dogleg steps.
+
+The trials run as lockstep batches (one batched gradient or Hessian evaluation per iteration for
+every unfinished trial), so the batch wall time is reported as an amortised time per solve; the
+per-trial wall time of Table II comes from the first --single trials solved one at a time.
+
+Reported, per system and algorithm: the Table I means (iterations, wall time, final cost, final
+||grad||_2, ||a_J - beta||_2), and the Table II per-trial ratios Alg. 1 / Alg. 2 (mean and 0.05 /
+0.95 quantiles).  ||a_J - beta|| follows from the cost: with f = theta,
+C = ||theta||^2 / 2 + (rho / 2) ||a_J - beta||^2.
+
+    python -m paper_2505_00529_amd.optcompare [--n 4 16] [--trials 1000] [--chunk 250]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+
+from . import inputs
+from . import qoc
+
+NT, DT, RHO, TOL, MAX_ITER = 200, 0.1, 1e6, 1e-10, 10000
+
+
+def _say(msg: str) -> None:
+    print(f"[optcompare] {msg}", flush=True)
+
+
+SUBPROBLEMS = {"cg": qoc.QOC_TR_SUBPROBLEM_CG, "default": qoc.QOC_TR_SUBPROBLEM_DEFAULT}
+
+
+def make_problem(n: int, seed: int, subproblem: str = "cg", device: int = 0) -> qoc.Problem:
+    s = inputs.transfer_system(n, seed)
+    p = qoc.Problem(device)
+    p.set_system(s.h0, s.m, s.psi0, s.psi_target)
+    p.set_control_basis(qoc.QOC_BASIS_IDENTITY, NT, DT, 0)
+    p.set_weights(1.0, RHO)
+    p.set_tr_step_tolerance(TOL)
+    p.set_tr_subproblem(SUBPROBLEMS[subproblem])
+    return p
+
+
+def evaluation_latency(p: qoc.Problem, theta: np.ndarray, reps: int = 20) -> dict:
+    """Wall time of one gradient and of one gradient + Hessian evaluation (one theta)."""
+    out = {}
+    for name, fn in (("grad_ms", lambda: p.grad_many(theta[None, :])),
+                     ("hess_ms", lambda: p.hess_many(theta[None, :]))):
+        fn()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        out[name] = (time.perf_counter() - t0) / reps * 1e3
+    return out
+
+
+def draw_starts(trials: int, seed: int) -> np.ndarray:
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 4243])))
+    return rng.normal(0.0, 1.0, size=(trials, NT))
+
+
+def _solve(p: qoc.Problem, algo: str, th0: np.ndarray):
+    if algo == "bfgs":
+        return p.tr_solve_bfgs_many(th0, gtol=TOL, max_iter=MAX_ITER)
+    return p.tr_solve_many(th0, gtol=TOL, max_iter=MAX_ITER)
+
+
+def run_algorithm(p: qoc.Problem, algo: str, starts: np.ndarray, chunk: int) -> dict:
+    trials = len(starts)
+    th = np.zeros_like(starts)
+    cost = np.zeros(trials)
+    iters = np.zeros(trials, dtype=np.int64)
+    conv = np.zeros(trials, dtype=bool)
+    t0 = time.perf_counter()
+    for a in range(0, trials, chunk):
+        b = min(trials, a + chunk)
+        th[a:b], cost[a:b], iters[a:b], conv[a:b] = _solve(p, algo, starts[a:b])
+        _say(f"  {algo}: {b}/{trials} trials, {time.perf_counter() - t0:.1f} s, "
+             f"mean iters so far {iters[:b].mean():.1f}")
+    wall = time.perf_counter() - t0
+    _, grads = p.grad_many(th)
+    gnorm = np.linalg.norm(grads, axis=1)
+    miss2 = np.maximum(0.0, 2.0 * (cost - 0.5 * np.einsum("ij,ij->i", th, th)) / RHO)
+    return {"theta": th, "cost": cost, "iters": iters, "converged": conv, "gnorm": gnorm,
+            "target_viol": np.sqrt(miss2), "wall": wall}
+
+
+def single_walls(p: qoc.Problem, algo: str, starts: np.ndarray) -> np.ndarray:
+    out = np.zeros(len(starts))
+    for i, th0 in enumerate(starts):
+        t0 = time.perf_counter()
+        _solve(p, algo, th0[None, :])
+        out[i] = time.perf_counter() - t0
+        _say(f"  {algo} single solve {i}: {out[i]:.2f} s")
+    return out
+
+
+def _ratio_stats(num: np.ndarray, den: np.ndarray) -> dict:
+    ok = den > 0
+    r = num[ok] / den[ok]
+    if r.size == 0:
+        return {"mean": None, "q05": None, "q95": None, "count": 0}
+    return {"mean": float(r.mean()), "q05": float(np.quantile(r, 0.05)),
+            "q95": float(np.quantile(r, 0.95)), "count": int(r.size)}
+
+
+def compare(n: int, trials: int, chunk: int, single: int, seed: int, subproblem: str) -> dict:
+    p = make_problem(n, seed, subproblem)
+    starts = draw_starts(trials, seed)
+    _say(f"N={n}: J={NT} dt={DT} rho={RHO:g} P={p.P} trials={trials} subproblem={subproblem}")
+    lat = evaluation_latency(p, starts[0])
+    _say(f"  one evaluation: gradient {lat['grad_ms']:.3f} ms, gradient + Hessian {lat['hess_ms']:.3f} ms")
+    res = {}
+    for algo in ("bfgs", "exact"):
+        res[algo] = run_algorithm(p, algo, starts, chunk)
+    walls = {algo: single_walls(p, algo, starts[:single]) for algo in ("bfgs", "exact")}
+    p.close()
+    table1 = {}
+    for algo, label in (("bfgs", "alg1_bfgs"), ("exact", "alg2_exact")):
+        r = res[algo]
+        table1[label] = {
+            "iterations": float(r["iters"].mean()),
+            "batch_seconds_per_solve": r["wall"] / trials,
+            "single_solve_seconds": float(walls[algo].mean()) if single else None,
+            "final_cost": float(r["cost"].mean()),
+            "final_grad_norm": float(r["gnorm"].mean()),
+            "target_viol": float(r["target_viol"].mean()),
+            "gradient_test_met": int(r["converged"].sum()),
+            "iteration_cap_reached": int((r["iters"] >= MAX_ITER).sum()),
+        }
+    a, b = res["bfgs"], res["exact"]
+    table2 = {
+        "iterations": _ratio_stats(a["iters"].astype(float), b["iters"].astype(float)),
+        "single_solve_wall": _ratio_stats(walls["bfgs"], walls["exact"]) if single else None,
+        "final_cost": _ratio_stats(a["cost"], b["cost"]),
+        "final_grad_norm": _ratio_stats(a["gnorm"], b["gnorm"]),
+        "target_viol": _ratio_stats(a["target_viol"], b["target_viol"]),
+    }
+    within = np.mean((np.abs(np.log10(a["cost"] / b["cost"])) <= 1.0)
+                     & (np.abs(np.log10(np.maximum(a["target_viol"], 1e-300)
+                                        / np.maximum(b["target_viol"], 1e-300))) <= 1.0))
+    best = int(np.argmin(b["cost"]))
+    return {"n": n, "nt": NT, "dt": DT, "rho": RHO, "tol": TOL, "max_iter": MAX_ITER, "P": NT,
+            "trials": trials, "single_trials": single, "seed": seed, "subproblem": subproblem,
+            "evaluation_latency": lat,
+            "table1_means": table1, "table2_ratios_alg1_over_alg2": table2,
+            "fraction_cost_and_viol_within_10x": float(within),
+            "best_exact_trial": {"index": best, "cost": float(b["cost"][best]),
+                                 "target_viol": float(b["target_viol"][best])}}
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--n", type=int, nargs="+", default=[4, 16])
+    ap.add_argument("--trials", type=int, default=1000)
+    ap.add_argument("--chunk", type=int, default=250)
+    ap.add_argument("--single", type=int, default=8, help="trials also solved one at a time for wall ratios")
+    ap.add_argument("--seed", type=int, default=12)
+    ap.add_argument("--subproblem", choices=sorted(SUBPROBLEMS), default="cg")
+    ap.add_argument("--out", default=None, help="write the JSON here as well")
+    a = ap.parse_args(argv)
+    results = [compare(n, a.trials, a.chunk, min(a.single, a.trials), a.seed, a.subproblem) for n in a.n]
+    line = json.dumps({"protocol": "optimiser comparison, maximal model", "systems": results})
+    print(line, flush=True)
+    if a.out:
+        with open(a.out, "w") as fh:
+            fh.write(line + "\n")
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -28,6 +28,8 @@ QOC_ERR_NOT_CONVERGED = -8
 QOC_BASIS_FOURIER = 0
 QOC_BASIS_IDENTITY = 1
 QOC_BASIS_DENSE = 2
+QOC_TR_SUBPROBLEM_DEFAULT = 0
+QOC_TR_SUBPROBLEM_CG = 1
 
 _lib = None
 
@@ -71,6 +73,11 @@ SIGNATURES = {
     "qoc_hess_many_targets": (_st, [_vp, _i32, _dp, _dp, _dp, _dp, _dp]),
     "qoc_control_coords": (_st, [_vp, _i32, _dp, _dp, ctypes.POINTER(_i32)]),
     "qoc_tr_gradient_norms": (_st, [_vp, _i32, _dp, _dp, _dp]),
+    "qoc_set_tr_step_tolerance": (_st, [_vp, ctypes.c_double]),
+    "qoc_set_tr_subproblem": (_st, [_vp, _i32]),
+    "qoc_tr_solve_bfgs_many": (_st, [_vp, _i32, _dp, _dp, ctypes.c_double, _i32, _dp, _dp, ctypes.POINTER(_i32),
+                                     ctypes.POINTER(_i32)]),
+    "qoc_bfgs_update": (_st, [_i32, _dp, _dp, _dp, _dp, _i32]),
     "qoc_params_from_coords": (_st, [_vp, _i32, _dp, _dp]),
     "qoc_batch_create": (_st, [ctypes.c_int, _i32, ctypes.POINTER(_vp), ctypes.POINTER(_vp)]),
     "qoc_batch_destroy": (None, [_vp]),
@@ -362,6 +369,31 @@ class Problem:
         self._check(lib().qoc_tr_gradient_norms(self._h, count, _ptr(g), _ptr(gn), _ptr(pn)))
         return gn, pn
 
+    def set_tr_subproblem(self, kind: int):
+        """QOC_TR_SUBPROBLEM_DEFAULT (eigen-exact / dogleg) or QOC_TR_SUBPROBLEM_CG (Steihaug CG)."""
+        self._check(lib().qoc_set_tr_subproblem(self._h, int(kind)))
+
+    def set_tr_step_tolerance(self, xtol: float):
+        """Stop trust-region solves once a step or the radius is shorter than xtol (0: off)."""
+        self._check(lib().qoc_set_tr_step_tolerance(self._h, float(xtol)))
+
+    def tr_solve_bfgs_many(self, theta0s, targets=None, gtol: float = 1e-8, max_iter: int = 10000):
+        """BFGS trust-region solves (gradient evaluations only): (theta, cost, iters, converged)."""
+        th = _f64(theta0s)
+        count = th.size // self.P
+        th = th.reshape(count, self.P)
+        tg = None
+        if targets is not None:
+            tg = np.ascontiguousarray(np.asarray(targets, dtype=np.complex128).reshape(count, self.n)).view(np.float64)
+        out = np.zeros((count, self.P))
+        c = np.zeros(count)
+        its = np.zeros(count, dtype=np.int32)
+        conv = np.zeros(count, dtype=np.int32)
+        self._check(lib().qoc_tr_solve_bfgs_many(self._h, count, _ptr(th), _ptr(tg), gtol, max_iter, _ptr(out),
+                                                 _ptr(c), its.ctypes.data_as(ctypes.POINTER(_i32)),
+                                                 conv.ctypes.data_as(ctypes.POINTER(_i32))))
+        return out, c, its, conv.astype(bool)
+
     def control_coords(self, thetas):
         """(coords (count x P), rank): c = diag(sigma_r) V_r^T theta of the trust-region metric."""
         th = _f64(thetas)
@@ -525,6 +557,18 @@ class Batch:
         b = ctypes.c_int64()
         self._check(lib().qoc_batch_memory(self._h, ctypes.byref(b)))
         return int(b.value)
+
+
+def bfgs_update(b, h, s, y, rescale: bool = False):
+    """In-place BFGS update of (b, h = b^-1) from step s and gradient change y (qoc_bfgs_update)."""
+    r = len(s)
+    for a in (b, h):
+        if not (isinstance(a, np.ndarray) and a.dtype == np.float64 and a.flags.c_contiguous and a.size == r * r):
+            raise ValueError("b and h must be C-contiguous float64 arrays of r x r")
+    sv, yv = _f64(s, r), _f64(y, r)   # held for the duration of the call
+    st = lib().qoc_bfgs_update(r, _ptr(b), _ptr(h), _ptr(sv), _ptr(yv), 1 if rescale else 0)
+    if st != QOC_OK:
+        raise QocError(st, status_string(st))
 
 
 def problem_from_workload(w, device: int = 0) -> Problem:

@@ -66,7 +66,10 @@ def _device_disassembly():
             pytest.skip(f"{tool} not available")
     with tempfile.TemporaryDirectory() as tmp:
         fat = os.path.join(tmp, "fatbin")
-        subprocess.run(["objcopy", "--dump-section", f".hip_fatbin={fat}", qoc.LIB_PATH], check=True)
+        # with no output operand objcopy would rewrite the library in place (under a process that
+        # may have it mapped); write its copy to a scratch file instead
+        subprocess.run(["objcopy", "--dump-section", f".hip_fatbin={fat}", qoc.LIB_PATH,
+                        os.path.join(tmp, "copy.so")], check=True)
         data = open(fat, "rb").read()
         magic = b"__CLANG_OFFLOAD_BUNDLE__"
         starts = [m.start() for m in re.finditer(re.escape(magic), data)]

@@ -109,3 +109,76 @@ def test_tr_max_iter_reports_not_converged():
     th, c, iters, ok = p.tr_solve(np.zeros(w.p), gtol=1e-12, max_iter=1)
     assert not ok and iters == 1
     p.close()
+
+
+def _transfer_problem(n, nt, rho):
+    s = inputs.transfer_system(n)
+    p = qoc.Problem(0)
+    p.set_system(s.h0, s.m, s.psi0, s.psi_target)
+    p.set_control_basis(qoc.QOC_BASIS_IDENTITY, nt, 0.1, 0)
+    p.set_weights(1.0, rho)
+    return s, p
+
+
+def test_bfgs_trust_region_reaches_oracle_stationary_points():
+    """Gradient-only (BFGS) trust region on the maximal model from theta_0 ~ N(0, I): every solve
+    meets the gradient test, the oracle's gradient vanishes at the result and its Hessian is
+    positive semi-definite there; the exact-Hessian solver from the same starts needs fewer
+    iterations in total."""
+    nt, rho = 40, 1e2
+    s, p = _transfer_problem(4, nt, rho)
+    rng = np.random.default_rng(5)
+    th0 = rng.normal(size=(4, nt))
+    th, c, its, conv = p.tr_solve_bfgs_many(th0, gtol=1e-8, max_iter=5000)
+    th2, c2, its2, conv2 = p.tr_solve_many(th0, gtol=1e-8, max_iter=500)
+    _say(f"bfgs iters {its.tolist()} costs {c.tolist()}")
+    _say(f"exact iters {its2.tolist()} costs {c2.tolist()}")
+    assert conv.all() and conv2.all()
+    basis = np.eye(nt)
+    for i in range(4):
+        cr, gr, hr = O.cost_grad_hess(s.h0, s.m, s.psi0, s.psi_target, basis, 0.1, th[i], 1.0, rho)
+        ev = np.linalg.eigvalsh(hr)
+        _say(f"  trial {i}: oracle |g|={np.linalg.norm(gr):.2e} min eig={ev.min():.3e}")
+        assert abs(c[i] - cr) < 1e-12 * abs(cr)
+        assert np.linalg.norm(gr) < 1e-7
+        assert ev.min() > -1e-8 * ev.max()
+    assert its2.sum() < its.sum()
+    p.close()
+
+
+def test_step_tolerance_stops_both_solvers_early():
+    nt = 40
+    _, p = _transfer_problem(4, nt, 1e2)
+    th0 = np.random.default_rng(6).normal(size=(2, nt))
+    _, _, its_b, _ = p.tr_solve_bfgs_many(th0, gtol=1e-8, max_iter=5000)
+    _, _, its_e, _ = p.tr_solve_many(th0, gtol=1e-8, max_iter=500)
+    p.set_tr_step_tolerance(1e-1)
+    _, _, its_b2, conv_b2 = p.tr_solve_bfgs_many(th0, gtol=1e-8, max_iter=5000)
+    _, _, its_e2, conv_e2 = p.tr_solve_many(th0, gtol=1e-8, max_iter=500)
+    _say(f"bfgs {its_b.tolist()} -> {its_b2.tolist()}; exact {its_e.tolist()} -> {its_e2.tolist()}")
+    assert (its_b2 < its_b).all() and (its_e2 <= its_e).all()
+    assert not conv_b2.any()
+    with pytest.raises(qoc.QocError):
+        p.set_tr_step_tolerance(-1.0)
+    p.close()
+
+
+def test_truncated_cg_subproblem_for_both_solvers():
+    """Steihaug-Toint CG steps in place of the eigen-exact and dogleg steps: both solvers still
+    meet the gradient test at points where the oracle's gradient vanishes."""
+    nt, rho = 40, 1e2
+    s, p = _transfer_problem(4, nt, rho)
+    th0 = np.random.default_rng(8).normal(size=(3, nt))
+    _, _, its_d, _ = p.tr_solve_many(th0, gtol=1e-8, max_iter=500)
+    p.set_tr_subproblem(qoc.QOC_TR_SUBPROBLEM_CG)
+    th_e, c_e, its_e, conv_e = p.tr_solve_many(th0, gtol=1e-8, max_iter=500)
+    th_b, c_b, its_b, conv_b = p.tr_solve_bfgs_many(th0, gtol=1e-8, max_iter=5000)
+    _say(f"exact: eigen {its_d.tolist()} cg {its_e.tolist()}; bfgs cg {its_b.tolist()}")
+    assert conv_e.all() and conv_b.all()
+    basis = np.eye(nt)
+    for th in list(th_e) + list(th_b):
+        _, gr = O.cost_grad(s.h0, s.m, s.psi0, s.psi_target, basis, 0.1, th, 1.0, rho)
+        assert np.linalg.norm(gr) < 1e-7
+    with pytest.raises(qoc.QocError):
+        p.set_tr_subproblem(7)
+    p.close()
