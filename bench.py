@@ -42,16 +42,20 @@ def alg_flops_per_step(kernel: str, n: int, p: int) -> float:
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_molecule_b256.json")
 
 
+# the sources that decide what the single-problem evaluation kernels do and how they are launched
+# (the solvers, the batch layer and the network do not enter a counter run of the evaluation)
+KERNEL_SOURCES = ("qoc_api.hip", "qoc_api_internal.h", "qoc_device.h", "qoc_internal.h", "qoc_kernels.hip")
+
+
 def kernel_source_digest() -> str:
-    """SHA-256 over the library's kernel sources (ties a counter measurement to the code)."""
+    """SHA-256 over the evaluation kernels' sources (ties a counter measurement to the code)."""
     import hashlib
 
     csrc = os.path.join(ROOT, "paper_2505_00529_amd", "csrc")
     h = hashlib.sha256()
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".h")):
-            with open(os.path.join(csrc, name), "rb") as f:
-                h.update(name.encode() + b"\0" + f.read())
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
     return h.hexdigest()
 
 

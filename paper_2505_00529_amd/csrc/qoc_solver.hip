@@ -381,7 +381,8 @@ static qoc_status ensure_whitening(qoc_problem* p) {
   std::vector<int> keep;
   for (int i = 0; i < P; ++i)
     if (sv[i] > kWhitenCut * smax) keep.push_back(i);
-  std::sort(keep.begin(), keep.end(), [&](int x, int y) { return sv[x] > sv[y]; });
+  // stable: equal singular values keep their index order, so an orthonormal basis gives W = I
+  std::stable_sort(keep.begin(), keep.end(), [&](int x, int y) { return sv[x] > sv[y]; });
   const int R = (int)keep.size();
   if (R == 0) return p->fail(QOC_ERR_INVALID_ARG, "control basis is zero");
   p->tr_whiten.assign((size_t)P * R, 0.0);
@@ -465,19 +466,25 @@ qoc_status qoc_tr_solve_many(qoc_problem* p, int32_t count, const double* theta0
         std::memcpy(Hw, Hi, PP * sizeof(double));
         return;
       }
-      std::vector<double> t((size_t)P * R);
-      for (int a = 0; a < P; ++a)
-        for (int c = 0; c < R; ++c) {
-          double acc = 0.0;
-          for (int b2 = 0; b2 < P; ++b2) acc += Hi[a * P + b2] * W[b2 * R + c];
-          t[(size_t)a * R + c] = acc;
+      // t = H W, then W^T t, both with the contiguous index innermost (vectorised row updates)
+      std::vector<double> t((size_t)P * R, 0.0);
+      for (int a = 0; a < P; ++a) {
+        double* ta = &t[(size_t)a * R];
+        for (int b2 = 0; b2 < P; ++b2) {
+          const double h = Hi[(size_t)a * P + b2];
+          const double* wb = W + (size_t)b2 * R;
+          for (int c = 0; c < R; ++c) ta[c] += h * wb[c];
         }
-      for (int r = 0; r < R; ++r)
-        for (int c = 0; c < R; ++c) {
-          double acc = 0.0;
-          for (int a = 0; a < P; ++a) acc += W[a * R + r] * t[(size_t)a * R + c];
-          Hw[r * R + c] = acc;
+      }
+      for (size_t e = 0; e < RR; ++e) Hw[e] = 0.0;
+      for (int a = 0; a < P; ++a) {
+        const double* ta = &t[(size_t)a * R];
+        for (int r = 0; r < R; ++r) {
+          const double w = W[(size_t)a * R + r];
+          double* hr = Hw + (size_t)r * R;
+          for (int c = 0; c < R; ++c) hr[c] += w * ta[c];
         }
+      }
     });
     const bool cg = p->tr_subproblem == QOC_TR_SUBPROBLEM_CG;
     if (!cg) {

@@ -19,7 +19,8 @@ Reported, per system and algorithm: the Table I means (iterations, wall time, fi
 0.95 quantiles).  ||a_J - beta|| follows from the cost: with f = theta,
 C = ||theta||^2 / 2 + (rho / 2) ||a_J - beta||^2.
 
-    python -m paper_2505_00529_amd.optcompare [--n 4 16] [--trials 1000] [--chunk 250]
+    python -m paper_2505_00529_amd.optcompare [--n 4 16] [--trials 1000] [--chunk 250] [--save PREFIX]
+    python -m paper_2505_00529_amd.optcompare --merge PREFIX_a_n16.npz PREFIX_b_n16.npz
 """
 from __future__ import annotations
 
@@ -117,34 +118,50 @@ def _ratio_stats(num: np.ndarray, den: np.ndarray) -> dict:
             "q95": float(np.quantile(r, 0.95)), "count": int(r.size)}
 
 
-def compare(n: int, trials: int, chunk: int, single: int, seed: int, subproblem: str) -> dict:
+def run_trials(n: int, first: int, trials: int, chunk: int, single: int, seed: int, subproblem: str) -> dict:
+    """Per-trial records of both algorithms for trials [first, first + trials) of the seeded draw."""
     p = make_problem(n, seed, subproblem)
-    starts = draw_starts(trials, seed)
-    _say(f"N={n}: J={NT} dt={DT} rho={RHO:g} P={p.P} trials={trials} subproblem={subproblem}")
+    starts = draw_starts(first + trials, seed)[first:]
+    _say(f"N={n}: J={NT} dt={DT} rho={RHO:g} P={p.P} trials {first}..{first + trials - 1} subproblem={subproblem}")
     lat = evaluation_latency(p, starts[0])
     _say(f"  one evaluation: gradient {lat['grad_ms']:.3f} ms, gradient + Hessian {lat['hess_ms']:.3f} ms")
-    res = {}
+    rec = {"n": n, "first": first, "seed": seed, "subproblem": subproblem,
+           "grad_ms": lat["grad_ms"], "hess_ms": lat["hess_ms"]}
     for algo in ("bfgs", "exact"):
-        res[algo] = run_algorithm(p, algo, starts, chunk)
-    walls = {algo: single_walls(p, algo, starts[:single]) for algo in ("bfgs", "exact")}
+        r = run_algorithm(p, algo, starts, chunk)
+        for key in ("cost", "iters", "converged", "gnorm", "target_viol"):
+            rec[f"{algo}_{key}"] = r[key]
+        rec[f"{algo}_batch_wall"] = r["wall"]
+        rec[f"{algo}_single_wall"] = single_walls(p, algo, starts[:single])
     p.close()
+    return rec
+
+
+def summarise(recs) -> dict:
+    """Table I means and Table II ratio statistics over the concatenated per-trial records."""
+    def cat(key):
+        return np.concatenate([np.atleast_1d(r[key]) for r in recs])
+
+    r0 = recs[0]
+    trials = len(cat("bfgs_cost"))
     table1 = {}
     for algo, label in (("bfgs", "alg1_bfgs"), ("exact", "alg2_exact")):
-        r = res[algo]
+        walls = cat(f"{algo}_single_wall")
         table1[label] = {
-            "iterations": float(r["iters"].mean()),
-            "batch_seconds_per_solve": r["wall"] / trials,
-            "single_solve_seconds": float(walls[algo].mean()) if single else None,
-            "final_cost": float(r["cost"].mean()),
-            "final_grad_norm": float(r["gnorm"].mean()),
-            "target_viol": float(r["target_viol"].mean()),
-            "gradient_test_met": int(r["converged"].sum()),
-            "iteration_cap_reached": int((r["iters"] >= MAX_ITER).sum()),
+            "iterations": float(cat(f"{algo}_iters").mean()),
+            "batch_seconds_per_solve": float(sum(float(r[f"{algo}_batch_wall"]) for r in recs) / trials),
+            "single_solve_seconds": float(walls.mean()) if walls.size else None,
+            "final_cost": float(cat(f"{algo}_cost").mean()),
+            "final_grad_norm": float(cat(f"{algo}_gnorm").mean()),
+            "target_viol": float(cat(f"{algo}_target_viol").mean()),
+            "gradient_test_met": int(cat(f"{algo}_converged").sum()),
+            "iteration_cap_reached": int((cat(f"{algo}_iters") >= MAX_ITER).sum()),
         }
-    a, b = res["bfgs"], res["exact"]
+    a = {k: cat(f"bfgs_{k}") for k in ("iters", "cost", "gnorm", "target_viol", "single_wall")}
+    b = {k: cat(f"exact_{k}") for k in ("iters", "cost", "gnorm", "target_viol", "single_wall")}
     table2 = {
         "iterations": _ratio_stats(a["iters"].astype(float), b["iters"].astype(float)),
-        "single_solve_wall": _ratio_stats(walls["bfgs"], walls["exact"]) if single else None,
+        "single_solve_wall": _ratio_stats(a["single_wall"], b["single_wall"]) if a["single_wall"].size else None,
         "final_cost": _ratio_stats(a["cost"], b["cost"]),
         "final_grad_norm": _ratio_stats(a["gnorm"], b["gnorm"]),
         "target_viol": _ratio_stats(a["target_viol"], b["target_viol"]),
@@ -153,9 +170,10 @@ def compare(n: int, trials: int, chunk: int, single: int, seed: int, subproblem:
                      & (np.abs(np.log10(np.maximum(a["target_viol"], 1e-300)
                                         / np.maximum(b["target_viol"], 1e-300))) <= 1.0))
     best = int(np.argmin(b["cost"]))
-    return {"n": n, "nt": NT, "dt": DT, "rho": RHO, "tol": TOL, "max_iter": MAX_ITER, "P": NT,
-            "trials": trials, "single_trials": single, "seed": seed, "subproblem": subproblem,
-            "evaluation_latency": lat,
+    return {"n": int(r0["n"]), "nt": NT, "dt": DT, "rho": RHO, "tol": TOL, "max_iter": MAX_ITER, "P": NT,
+            "trials": trials, "single_trials": int(a["single_wall"].size), "seed": int(r0["seed"]),
+            "subproblem": str(r0["subproblem"]),
+            "evaluation_latency_ms": {"grad": float(r0["grad_ms"]), "grad_and_hess": float(r0["hess_ms"])},
             "table1_means": table1, "table2_ratios_alg1_over_alg2": table2,
             "fraction_cost_and_viol_within_10x": float(within),
             "best_exact_trial": {"index": best, "cost": float(b["cost"][best]),
@@ -166,13 +184,26 @@ def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--n", type=int, nargs="+", default=[4, 16])
     ap.add_argument("--trials", type=int, default=1000)
+    ap.add_argument("--first", type=int, default=0, help="index of the first trial of the seeded draw")
     ap.add_argument("--chunk", type=int, default=250)
     ap.add_argument("--single", type=int, default=8, help="trials also solved one at a time for wall ratios")
     ap.add_argument("--seed", type=int, default=12)
     ap.add_argument("--subproblem", choices=sorted(SUBPROBLEMS), default="cg")
+    ap.add_argument("--save", default=None, help="write the per-trial records of each N to SAVE_n<N>.npz")
+    ap.add_argument("--merge", nargs="+", default=None,
+                    help="summarise saved per-trial records (npz files of one N) instead of running")
     ap.add_argument("--out", default=None, help="write the JSON here as well")
     a = ap.parse_args(argv)
-    results = [compare(n, a.trials, a.chunk, min(a.single, a.trials), a.seed, a.subproblem) for n in a.n]
+    if a.merge:
+        recs = [dict(np.load(f, allow_pickle=False)) for f in a.merge]
+        results = [summarise(recs)]
+    else:
+        results = []
+        for n in a.n:
+            rec = run_trials(n, a.first, a.trials, a.chunk, min(a.single, a.trials), a.seed, a.subproblem)
+            if a.save:
+                np.savez(f"{a.save}_n{n}.npz", **rec)
+            results.append(summarise([rec]))
     line = json.dumps({"protocol": "optimiser comparison, maximal model", "systems": results})
     print(line, flush=True)
     if a.out:
