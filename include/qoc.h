@@ -72,6 +72,18 @@ qoc_status qoc_set_stream(qoc_problem* p, void* hip_stream);
  * (symmetry checked to 1e-12 relative); psi0, psi_target are n complex (2n doubles). */
 qoc_status qoc_set_system(qoc_problem* p, int32_t n, const double* h0, const double* m,
                           const double* psi0, const double* psi_target);
+/* Complex Hermitian H0 and M (the random Hermitian dipole matrices of the paper's timing runs,
+ * Sec. IV-A): n x n complex, row-major, interleaved (re, im), 2 n^2 doubles each, Hermitian to
+ * 1e-12 relative (QOC_ERR_NOT_SYMMETRIC otherwise; the Hermitian part (X + X^H) / 2 is used);
+ * psi0, psi_target: n complex.  n <= 64.  The system is evaluated exactly through its real
+ * embedding E(X) = [[Re X, -Im X], [Im X, Re X]] of size 2n: the states phi(a) = [a; -i a] / sqrt(2)
+ * span an invariant subspace on which E(H0 + f M) acts as H0 + f M, and |phi(a) - phi(b)| = |a - b|,
+ * so cost, gradient and Hessian are those of the complex system (every eigenvalue of the embedding
+ * is doubled, which the eigen-data path handles exactly).  Targets passed later (qoc_set_target,
+ * per-theta targets) have n complex entries and are mapped the same way.  qoc_step_propagators
+ * returns QOC_ERR_UNSUPPORTED for such a system. */
+qoc_status qoc_set_system_hermitian(qoc_problem* p, int32_t n, const double* h0, const double* m,
+                                    const double* psi0, const double* psi_target);
 /* Replace only the target state (2n doubles); cheap, keeps all other settings. */
 qoc_status qoc_set_target(qoc_problem* p, const double* psi_target);
 

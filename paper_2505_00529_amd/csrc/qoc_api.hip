@@ -395,8 +395,14 @@ qoc_status qoc_problem::run_host(Mode mode, int count, const double* theta, cons
     if (!v) return fail(QOC_ERR_INVALID_ARG, "v must be non-NULL");
     if (!all_finite(v, (size_t)count * P)) return fail(QOC_ERR_INVALID_ARG, "v has non-finite entries");
   }
-  if (targets && !all_finite(targets, (size_t)count * 2 * n))
+  if (targets && !all_finite(targets, (size_t)count * 2 * target_n()))
     return fail(QOC_ERR_INVALID_ARG, "targets have non-finite entries");
+  std::vector<double> mapped;
+  if (targets && embed) {
+    mapped.resize((size_t)count * 2 * n);
+    for (int i = 0; i < count; ++i) embed_state(n_user, targets + (size_t)i * 2 * n_user, &mapped[(size_t)i * 2 * n]);
+    targets = mapped.data();
+  }
   const size_t nth = (size_t)count * P;
   const size_t nout = mode == Mode::Hess ? (size_t)count * P * P : (mode == Mode::Hvp ? nth : 0);
   const size_t ntg = targets ? (size_t)count * 2 * n : 0;
@@ -432,6 +438,19 @@ qoc_status qoc_problem::run_host(Mode mode, int count, const double* theta, cons
 }
 
 // ------------------------------------------------------------------------ C ABI
+
+// phi(a) = [a; -i a] / sqrt(2): the embedding of a state of the complex system into the
+// invariant subspace of the real embedded system that evolves exactly as the complex one.
+void embed_state(int n, const double* a, double* out) {
+  const double r = std::sqrt(0.5);
+  for (int k = 0; k < n; ++k) {
+    const double re = a[2 * k], im = a[2 * k + 1];
+    out[2 * k] = r * re;
+    out[2 * k + 1] = r * im;
+    out[2 * (n + k)] = r * im;        // -i (re + i im) = im - i re
+    out[2 * (n + k) + 1] = -r * re;
+  }
+}
 
 extern "C" {
 
@@ -563,6 +582,54 @@ qoc_status qoc_set_system(qoc_problem* p, int32_t n, const double* h0, const dou
   p->h_psi0.assign(psi0, psi0 + 2 * n);
   p->h_psit.assign(psi_target, psi_target + 2 * n);
   p->has_system = true;
+  p->embed = false;
+  p->n_user = n;
+  return QOC_OK;
+}
+
+qoc_status qoc_set_system_hermitian(qoc_problem* p, int32_t n, const double* h0, const double* m, const double* psi0,
+                                    const double* psi_target) {
+  if (!p) return QOC_ERR_INVALID_ARG;
+  if (!h0 || !m || !psi0 || !psi_target) return p->fail(QOC_ERR_INVALID_ARG, "NULL system pointer");
+  if (n < 1) return p->fail(QOC_ERR_INVALID_ARG, "n must be >= 1");
+  if (2 * n > kMaxN) return p->fail(QOC_ERR_UNSUPPORTED, "complex n above the build limit (64)");
+  const size_t nn = (size_t)n * n;
+  if (!all_finite(h0, 2 * nn) || !all_finite(m, 2 * nn) || !all_finite(psi0, 2 * (size_t)n) ||
+      !all_finite(psi_target, 2 * (size_t)n))
+    return p->fail(QOC_ERR_INVALID_ARG, "non-finite system entry");
+  const int n2 = 2 * n;
+  std::vector<double> he((size_t)n2 * n2), me((size_t)n2 * n2);
+  for (int which = 0; which < 2; ++which) {
+    const double* x = which == 0 ? h0 : m;
+    double nrm = 0.0, dev = 0.0;
+    for (size_t i = 0; i < 2 * nn; ++i) nrm += x[i] * x[i];
+    for (int i = 0; i < n; ++i)
+      for (int k = i; k < n; ++k) {
+        const double dr = x[2 * (i * n + k)] - x[2 * (k * n + i)];           // Re h_ik - Re h_ki
+        const double di = x[2 * (i * n + k) + 1] + x[2 * (k * n + i) + 1];   // Im h_ik + Im h_ki
+        dev += (i == k ? 1.0 : 2.0) * (dr * dr + di * di);
+      }
+    if (std::sqrt(dev) > 1e-12 * std::sqrt(nrm))
+      return p->fail(QOC_ERR_NOT_SYMMETRIC, which == 0 ? "H0 is not Hermitian" : "M is not Hermitian");
+    // E(X) = [[Re X, -Im X], [Im X, Re X]] of the exactly Hermitian part (X + X^H) / 2
+    double* e = which == 0 ? he.data() : me.data();
+    for (int i = 0; i < n; ++i)
+      for (int k = 0; k < n; ++k) {
+        const double re = 0.5 * (x[2 * (i * n + k)] + x[2 * (k * n + i)]);
+        const double im = 0.5 * (x[2 * (i * n + k) + 1] - x[2 * (k * n + i) + 1]);
+        e[(size_t)i * n2 + k] = re;
+        e[(size_t)(n + i) * n2 + n + k] = re;
+        e[(size_t)i * n2 + n + k] = -im;
+        e[(size_t)(n + i) * n2 + k] = im;
+      }
+  }
+  std::vector<double> a0(2 * (size_t)n2), bt(2 * (size_t)n2);
+  embed_state(n, psi0, a0.data());
+  embed_state(n, psi_target, bt.data());
+  qoc_status st = qoc_set_system(p, n2, he.data(), me.data(), a0.data(), bt.data());
+  if (st != QOC_OK) return st;
+  p->embed = true;
+  p->n_user = n;
   return QOC_OK;
 }
 
@@ -570,7 +637,13 @@ qoc_status qoc_set_target(qoc_problem* p, const double* psi_target) {
   if (!p) return QOC_ERR_INVALID_ARG;
   if (!p->has_system) return p->fail(QOC_ERR_STATE, "set_system first");
   if (!psi_target) return p->fail(QOC_ERR_INVALID_ARG, "NULL target");
-  if (!all_finite(psi_target, 2 * (size_t)p->n)) return p->fail(QOC_ERR_INVALID_ARG, "non-finite target");
+  if (!all_finite(psi_target, 2 * (size_t)p->target_n())) return p->fail(QOC_ERR_INVALID_ARG, "non-finite target");
+  std::vector<double> mapped;
+  if (p->embed) {
+    mapped.resize(2 * (size_t)p->n);
+    embed_state(p->n_user, psi_target, mapped.data());
+    psi_target = mapped.data();
+  }
   hipError_t e = hipMemcpyAsync(p->d_psit, psi_target, sizeof(double) * 2 * p->n, hipMemcpyHostToDevice, p->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
   if (e != hipSuccess) return p->hip_fail(e, "target upload");
@@ -757,6 +830,7 @@ qoc_status qoc_step_propagators(qoc_problem* p, const double* theta, int32_t j, 
   if (st != QOC_OK) return st;
   if (!theta) return p->fail(QOC_ERR_INVALID_ARG, "NULL theta");
   if (j < 0 || j >= p->nt) return p->fail(QOC_ERR_INVALID_ARG, "step index out of range");
+  if (p->embed) return p->fail(QOC_ERR_UNSUPPORTED, "step propagators of a Hermitian system are not available");
   st = p->ensure_work(1, 0);
   if (st != QOC_OK) return st;
   st = p->ensure_io(p->P + 6 * (size_t)p->n * p->n);

@@ -19,6 +19,11 @@ struct qoc_problem {
   // system (device copies, and host copies for solvers built on top)
   int n = 0;
   bool has_system = false;
+  // complex Hermitian system held as its real embedding of size n = 2 n_user; caller-facing
+  // states and targets have n_user complex entries and are mapped by embed_state
+  bool embed = false;
+  int n_user = 0;
+  int target_n() const { return embed ? n_user : n; }
   double* d_h0 = nullptr;
   double* d_m = nullptr;
   double* d_psi0 = nullptr;
@@ -98,3 +103,6 @@ struct qoc_problem {
   int tr_basis_version = -1;
   int basis_version = 0;
 };
+
+// phi(a) = [a; -i a] / sqrt(2) for a state of n complex entries (2n doubles in, 4n out).
+void embed_state(int n, const double* a, double* out);

@@ -181,6 +181,7 @@ __device__ __forceinline__ void body_eig_chunk(const EigArgs& a, int c, int b) {
 
 __global__ __launch_bounds__(kThreads) void k_eig_chunk(EigArgs a) { body_eig_chunk(a, blockIdx.x, blockIdx.y); }
 
+
 // O_{j0-1} = V_{j0}^T V_{j0-1} across chunk boundaries (first V of chunk c, last V of c-1).
 __device__ __forceinline__ void body_boundary(const BndArgs& a, int bx, int b) {
   const double* vfirst = a.vfirst;
@@ -1153,6 +1154,296 @@ template <int NP>
 __global__ __launch_bounds__(EigWgShape<NP>::TPB, EigWgShape<NP>::WAVES) void k_eig_wg(EigArgs a) {
   body_eig_wg<NP>(a, blockIdx.x, blockIdx.y);
 }
+
+// ---------------------------------------------------------------- eigen-data, sizes past one LDS tile
+
+// For NP whose four NP x NP work matrices do not fit the 160 KB of LDS (NP > 70, up to 128): one
+// workgroup of kBigTPB threads per (theta, chunk).  A stays in LDS (row stride NP, 128 KB at
+// NP = 128); V, V_{j-1} and X = M V live in the chunk's global scratch, column-major
+// (Vc[k * NP + i] = V[i][k]), so that a rotation of columns p, q touches two contiguous columns
+// and consecutive threads (consecutive rows i) coalesce.  The parallel-order cyclic Jacobi uses
+// the round-robin pairing; every thread owns at most three fixed 2x2 blocks of A and at most
+// eight (row, pair) entries of V per round, and issues all of their loads before any update.
+constexpr int kBigTPB = 1024;
+constexpr int kBigBlk = 3;   // >= ceil((64 * 65 / 2) / kBigTPB): blocks per thread at NP = 128
+constexpr int kBigV = 8;     // >= 128 * 64 / kBigTPB: V entries per thread at NP = 128
+
+__host__ __device__ inline size_t eig_big_lds_doubles(int np) {
+  return (size_t)np + kBigTPB / 64 + np + (np + 1) / 2 + (size_t)np * np;
+}
+
+// Round r of the circle pairing of np players (np - 1 rounds): player np-1 meets r, the others
+// pair as (r + k, r - k) mod (np - 1).  Ordered p < q.
+__device__ __forceinline__ void rr_pair_fast(int r, int k, int np, int& p, int& q) {
+  const int m = np - 1;
+  int a = m, b = r;
+  if (k != 0) {
+    a = r + k;
+    if (a >= m) a -= m;
+    b = r - k;
+    if (b < 0) b += m;
+  }
+  p = a < b ? a : b;
+  q = a < b ? b : a;
+}
+
+// C (LDS, row-major, stride np) or Cc (global, column-major) = L^T R over the inner index r for
+// column-major L and R (Lc[i * np + r] = L[r][i]); 2 x 2 register tiles.
+__device__ __forceinline__ void big_product_tile(const double* Lc, const double* Rc, int np, int i0, int k0,
+                                                 double& c00, double& c01, double& c10, double& c11) {
+  c00 = c01 = c10 = c11 = 0.0;
+  const double* l0 = Lc + (size_t)i0 * np;
+  const double* l1 = l0 + np;
+  const double* r0 = Rc + (size_t)k0 * np;
+  const double* r1 = r0 + np;
+#pragma unroll 2
+  for (int r = 0; r < np; r += 2) {
+    const double2 a0 = *(const double2*)(l0 + r), a1 = *(const double2*)(l1 + r);
+    const double2 b0 = *(const double2*)(r0 + r), b1 = *(const double2*)(r1 + r);
+    c00 = fma(a0.y, b0.y, fma(a0.x, b0.x, c00));
+    c01 = fma(a0.y, b1.y, fma(a0.x, b1.x, c01));
+    c10 = fma(a1.y, b0.y, fma(a1.x, b0.x, c10));
+    c11 = fma(a1.y, b1.y, fma(a1.x, b1.x, c11));
+  }
+}
+
+__device__ __forceinline__ void body_eig_big(const EigArgs& a, int c, int b) {
+  constexpr int TPB = kBigTPB;
+  extern __shared__ __attribute__((aligned(16))) double smem[];
+  const int np = a.np, n = a.n, nt = a.nt;
+  const int j0 = a.j_base + c * a.chunk;
+  const int j1 = min(a.j_base + a.nsteps, j0 + a.chunk);
+  if (j0 >= j1) return;
+  const int tid = threadIdx.x;
+  const int half = np / 2, nblk = half * (half + 1) / 2, npp = np * np;
+  double2* rot2 = (double2*)smem;             // np / 2: (c, s) per pair of the round
+  double* red = smem + np;                    // TPB / 64
+  double* lamv = red + TPB / 64;              // np
+  double* A = lamv + np + (np + 1) / 2;       // np x np, row-major
+  double* Vc = a.gscratch + ((size_t)b * a.nchunks + c) * 3 * (size_t)npp;   // V_j, column-major
+  double* Vpc = Vc + npp;                     // V_{j-1}
+  double* Xc = Vpc + npp;                     // X = M V_j, then O_{j-1}, column-major
+  const double* fb = a.f + (size_t)b * nt;
+  const size_t nn = (size_t)n * n;
+  // this thread's V entries: row vi of V for the pairs vg, vg + vG, ... (vG = TPB / np groups
+  // of np threads, consecutive threads on consecutive rows)
+  const int vG = TPB / np, vg = tid / np, vi = tid - (tid / np) * np;
+  const bool v_on = vg < vG;
+  // this thread's fixed blocks (I, K), I <= K, of the pair-by-pair partition of A
+  int bI[kBigBlk], bK[kBigBlk];
+#pragma unroll
+  for (int t = 0; t < kBigBlk; ++t) {
+    const int w = tid + TPB * t;
+    int I = -1, K = 0;
+    if (w < nblk) {
+      I = 0;
+      int rem = w;
+      while (rem >= half - I) {
+        rem -= half - I;
+        ++I;
+      }
+      K = I + rem;
+    }
+    bI[t] = I;
+    bK[t] = K;
+  }
+
+  for (int j = j0; j < j1; ++j) {
+    const double fj = fb[j];
+    if (j == j0) {
+      for (int idx = tid; idx < npp; idx += TPB) {
+        const int i = idx / np, k = idx - (idx / np) * np;
+        A[idx] = (i < n && k < n) ? a.h0[i * n + k] + fj * a.m[i * n + k] : 0.0;
+        Vc[idx] = (i == k) ? 1.0 : 0.0;
+      }
+    } else {
+      const double df = fj - fb[j - 1];
+      for (int idx = tid; idx < npp; idx += TPB) {
+        const int i = idx / np, k = idx - (idx / np) * np;
+        A[idx] = df * A[idx] + (i == k ? lamv[i] : 0.0);   // A held Mt_{j-1}
+        Vpc[idx] = Vc[idx];
+      }
+    }
+    __syncthreads();
+    double loc = 0.0;
+    for (int idx = tid; idx < npp; idx += TPB) loc = fma(A[idx], A[idx], loc);
+    const double tol = a.tol_rel * sqrt(wg_sum<TPB>(loc, red));
+    int sweep = 0;
+    bool conv = false;
+#pragma unroll 1
+    for (;; ++sweep) {
+      double off = 0.0;
+      for (int idx = tid; idx < npp; idx += TPB) {
+        const int i = idx / np, k = idx - (idx / np) * np;
+        if (i < k) off = fmax(off, fabs(A[idx]));
+      }
+      off = wg_max<TPB>(off, red);
+      if (off <= tol) {
+        conv = true;
+        break;
+      }
+      if (sweep >= a.max_sweeps) {
+        if (tid == 0) atomicOr(a.status, kStatusNoConv);
+        break;
+      }
+#pragma unroll 1
+      for (int r = 0; r < np - 1; ++r) {
+        // The pairs of round r are known to every thread (rr_pair_fast), and A and V hold the
+        // previous round's results since its closing barrier, so each thread loads its block
+        // entries and V entries before the rotations are formed: the loads' latency overlaps
+        // the rotation formation and the barrier, and only (c, s) waits for it.
+        double x00[kBigBlk], x01[kBigBlk], x10[kBigBlk], x11[kBigBlk];
+#pragma unroll
+        for (int t = 0; t < kBigBlk; ++t) {
+          if (bI[t] >= 0) {
+            int pI, qI, pK, qK;
+            rr_pair_fast(r, bI[t], np, pI, qI);
+            rr_pair_fast(r, bK[t], np, pK, qK);
+            x00[t] = A[pI * np + pK];
+            x01[t] = A[pI * np + qK];
+            x10[t] = A[qI * np + pK];
+            x11[t] = A[qI * np + qK];
+          }
+        }
+        double vp[kBigV], vq[kBigV];
+#pragma unroll
+        for (int v = 0; v < kBigV; ++v) {
+          const int K = vg + v * vG;
+          if (v_on && K < half) {
+            int pp, qq;
+            rr_pair_fast(r, K, np, pp, qq);
+            vp[v] = Vc[pp * np + vi];
+            vq[v] = Vc[qq * np + vi];
+          }
+        }
+        if (tid < half) {
+          int pp, qq;
+          rr_pair_fast(r, tid, np, pp, qq);
+          double cc, ss;
+          jacobi_rotation(A[pp * np + pp], A[qq * np + qq], A[pp * np + qq], cc, ss);
+          rot2[tid] = make_double2(cc, ss);
+        }
+        __syncthreads();
+        // A <- J^T A J on this thread's blocks; block (K, I) is the transpose of (I, K), so no
+        // thread reads an entry another one writes within the round
+#pragma unroll
+        for (int t = 0; t < kBigBlk; ++t) {
+          if (bI[t] >= 0) {
+            const int I = bI[t], K = bK[t];
+            int pI, qI, pK, qK;
+            rr_pair_fast(r, I, np, pI, qI);
+            rr_pair_fast(r, K, np, pK, qK);
+            const double2 RI = rot2[I], RK = rot2[K];
+            const double t00 = x00[t] * RK.x - x01[t] * RK.y, t01 = x00[t] * RK.y + x01[t] * RK.x;
+            const double t10 = x10[t] * RK.x - x11[t] * RK.y, t11 = x10[t] * RK.y + x11[t] * RK.x;
+            const double b00 = RI.x * t00 - RI.y * t10, b01 = RI.x * t01 - RI.y * t11;
+            const double b10 = RI.y * t00 + RI.x * t10, b11 = RI.y * t01 + RI.x * t11;
+            if (I == K) {
+              A[pI * np + pI] = b00;
+              A[pI * np + qI] = 0.0;
+              A[qI * np + pI] = 0.0;
+              A[qI * np + qI] = b11;
+            } else {
+              A[pI * np + pK] = b00;
+              A[pI * np + qK] = b01;
+              A[qI * np + pK] = b10;
+              A[qI * np + qK] = b11;
+              A[pK * np + pI] = b00;
+              A[qK * np + pI] = b01;
+              A[pK * np + qI] = b10;
+              A[qK * np + qI] = b11;
+            }
+          }
+        }
+        // V <- V J on this thread's (row, pair) entries
+#pragma unroll
+        for (int v = 0; v < kBigV; ++v) {
+          const int K = vg + v * vG;
+          if (v_on && K < half) {
+            int pp, qq;
+            rr_pair_fast(r, K, np, pp, qq);
+            const double2 R = rot2[K];
+            Vc[pp * np + vi] = R.x * vp[v] - R.y * vq[v];
+            Vc[qq * np + vi] = R.y * vp[v] + R.x * vq[v];
+          }
+        }
+        __syncthreads();
+      }
+    }
+    if (tid == 0 && a.stats && conv) {
+      atomicAdd(a.stats, 1ull);
+      atomicAdd(a.stats + 1, (unsigned long long)sweep);
+    }
+    for (int i = tid; i < np; i += TPB) lamv[i] = A[i * np + i];
+    // V_j carries into the next step: unit columns
+    if (tid < np) normalize_column_contig(Vc + (size_t)tid * np, np);
+    __syncthreads();
+    // X = M V_j (column-major; M symmetric, so row i of M is its column i)
+    for (int w = tid; w < half * half; w += TPB) {
+      const int ti = w / half, tk = w - (w / half) * half;   // rows i0, i0 + 1 of X; columns k0, k0 + 1
+      const int i0 = 2 * ti, k0 = 2 * tk;
+      double c00 = 0.0, c01 = 0.0, c10 = 0.0, c11 = 0.0;
+      const double* v0 = Vc + (size_t)k0 * np;
+      const double* v1 = v0 + np;
+#pragma unroll 2
+      for (int r = 0; r < n; ++r) {
+        const double m0 = i0 < n ? a.m[(size_t)r * n + i0] : 0.0;
+        const double m1 = i0 + 1 < n ? a.m[(size_t)r * n + i0 + 1] : 0.0;
+        c00 = fma(m0, v0[r], c00);
+        c01 = fma(m0, v1[r], c01);
+        c10 = fma(m1, v0[r], c10);
+        c11 = fma(m1, v1[r], c11);
+      }
+      Xc[(size_t)k0 * np + i0] = c00;
+      Xc[(size_t)k0 * np + i0 + 1] = c10;
+      Xc[(size_t)(k0 + 1) * np + i0] = c01;
+      Xc[(size_t)(k0 + 1) * np + i0 + 1] = c11;
+    }
+    __syncthreads();
+    // Mt_j = V_j^T X into A (kept for the next step's warm start)
+    for (int w = tid; w < half * half; w += TPB) {
+      const int ti = w / half, tk = w - (w / half) * half;
+      const int i0 = 2 * ti, k0 = 2 * tk;
+      double c00, c01, c10, c11;
+      big_product_tile(Vc, Xc, np, i0, k0, c00, c01, c10, c11);
+      A[i0 * np + k0] = c00;
+      A[i0 * np + k0 + 1] = c01;
+      A[(i0 + 1) * np + k0] = c10;
+      A[(i0 + 1) * np + k0 + 1] = c11;
+    }
+    __syncthreads();
+    const size_t step = (size_t)b * a.eig_stride + (j - a.j_base);
+    // O_{j-1} = V_j^T V_{j-1}, straight to the output
+    if (j > j0) {
+      double* dst = a.ov + (step - 1) * nn;
+      for (int w = tid; w < half * half; w += TPB) {
+        const int ti = w / half, tk = w - (w / half) * half;
+        const int i0 = 2 * ti, k0 = 2 * tk;
+        double c00, c01, c10, c11;
+        big_product_tile(Vc, Vpc, np, i0, k0, c00, c01, c10, c11);
+        if (i0 < n && k0 < n) dst[(size_t)i0 * n + k0] = c00;
+        if (i0 < n && k0 + 1 < n) dst[(size_t)i0 * n + k0 + 1] = c01;
+        if (i0 + 1 < n && k0 < n) dst[(size_t)(i0 + 1) * n + k0] = c10;
+        if (i0 + 1 < n && k0 + 1 < n) dst[(size_t)(i0 + 1) * n + k0 + 1] = c11;
+      }
+    }
+    if (tid < n) a.lam[step * n + tid] = lamv[tid];
+    for (int idx = tid; idx < (int)nn; idx += TPB) {
+      const int i = idx / n, k = idx - (idx / n) * n;
+      if (a.store_derivs) {
+        const double mtv = A[i * np + k];
+        a.mt[step * nn + idx] = mtv;
+        a.sm[step * nn + idx] = sinc(0.5 * a.dt * (lamv[i] - lamv[k])) * mtv;
+      }
+      const double v = Vc[(size_t)k * np + i];
+      if (j == j0) a.vfirst[((size_t)b * a.nchunks + c) * nn + idx] = v;
+      if (j == j1 - 1) a.vlast[((size_t)b * a.nchunks + c) * nn + idx] = v;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kBigTPB, 1) void k_eig_big(EigArgs a) { body_eig_big(a, blockIdx.x, blockIdx.y); }
 
 // ---------------------------------------------------------------- sweeps
 
@@ -2454,6 +2745,8 @@ static size_t eig_lds_bytes(int np, bool lds_mats) {
 }
 
 static bool eig_fits_lds(int np) { return eig_lds_bytes(np, true) <= 160 * 1024; }
+// sizes served by the large-N kernel (its LDS holds A alone)
+static bool eig_big(int np) { return np != 36 && np != 64 && !eig_fits_lds(np); }
 
 static bool sweep_stage(int n) { return n * n <= kPrefetch * kThreads; }
 // LDS double buffer with 16-byte staging (even n)
@@ -2467,7 +2760,7 @@ static size_t sweep_lds_bytes(int n, int pg) {
 }
 
 hipError_t configure_kernels() {
-  const void* fns[] = {(const void*)k_eig_chunk, (const void*)k_eig_wg<36>, (const void*)k_eig_wg<64>, (const void*)k_sym_eig, (const void*)k_forward<kSweepRegs>, (const void*)k_forward<kSweepDbuf>,
+  const void* fns[] = {(const void*)k_eig_chunk, (const void*)k_eig_big, (const void*)k_eig_wg<36>, (const void*)k_eig_wg<64>, (const void*)k_sym_eig, (const void*)k_forward<kSweepRegs>, (const void*)k_forward<kSweepDbuf>,
                        (const void*)k_forward<kSweepGlobal>, (const void*)k_backward<kSweepRegs>,
                        (const void*)k_backward<kSweepDbuf>, (const void*)k_backward<kSweepGlobal>};
   for (const void* f : fns) {
@@ -2481,7 +2774,7 @@ size_t eig_scratch_doubles(int n, int nb, int nchunks) {
   const int np = pad_even(n);
   if (np == 36 || np == 64) return 0;   // workgroup kernels: everything in LDS
   if (eig_fits_lds(np)) return 0;
-  return (size_t)nb * nchunks * 4 * np * np;
+  return (size_t)nb * nchunks * 3 * np * np;   // large-N kernel: V, V_{j-1}, X
 }
 
 int eig_chunk_len(int seg_len, int nb, int np) {
@@ -2568,6 +2861,7 @@ size_t eig_launch_lds(int np) {
     case 16:
       return ((size_t)3 * np * np + 2 * np + (np + 1) / 2) * sizeof(double);
     default:
+      if (eig_big(np)) return eig_big_lds_doubles(np) * sizeof(double);
       return eig_lds_bytes(np, eig_fits_lds(np));
   }
 }
@@ -2596,6 +2890,11 @@ hipError_t launch_eig(const SysDev& sy, const BasisDev& bs, Work& w, bool store_
 #undef QOC_EIG_WAVE
     default:
       break;
+  }
+  if (eig_big(w.np)) {
+    hipLaunchKernelGGL(k_eig_big, dim3(w.nchunks, w.nb), dim3(kBigTPB), eig_big_lds_doubles(w.np) * sizeof(double),
+                       stream, a);
+    return hipGetLastError();
   }
   const size_t lds = eig_lds_bytes(w.np, a.lds_mats != 0);
   hipLaunchKernelGGL(k_eig_chunk, dim3(w.nchunks, w.nb), dim3(kThreads), lds, stream, a);
@@ -2842,6 +3141,7 @@ QOC_MULTI_KERNEL(km_eig_wave16, 64, 2, EigArgs, body_eig_wave<16>)
 QOC_MULTI_KERNEL(km_eig_wg36, kThreads, EigWgShape<36>::WAVES, EigArgs, body_eig_wg<36>)
 QOC_MULTI_KERNEL(km_eig_wg64, 512, EigWgShape<64>::WAVES, EigArgs, body_eig_wg<64>)
 QOC_MULTI_KERNEL(km_eig_chunk, kThreads, 1, EigArgs, body_eig_chunk)
+QOC_MULTI_KERNEL(km_eig_big, kBigTPB, 1, EigArgs, body_eig_big)
 QOC_MULTI_KERNEL(km_boundary, kThreads, 1, BndArgs, body_boundary)
 QOC_MULTI_KERNEL(km_forward_staged, kThreads, 2, SweepArgs, body_forward<kSweepRegs>)
 QOC_MULTI_KERNEL(km_forward_small, kThreads, 2, SweepArgs, body_forward<kSweepDbuf>)
@@ -2868,6 +3168,7 @@ static const void* multi_fn(MultiKind k) {
     case MultiKind::EigWg36: return (const void*)km_eig_wg36;
     case MultiKind::EigWg64: return (const void*)km_eig_wg64;
     case MultiKind::EigChunk: return (const void*)km_eig_chunk;
+    case MultiKind::EigBig: return (const void*)km_eig_big;
     case MultiKind::Boundary: return (const void*)km_boundary;
     case MultiKind::ForwardStaged: return (const void*)km_forward_staged;
     case MultiKind::ForwardSmall: return (const void*)km_forward_small;
@@ -2890,6 +3191,8 @@ int multi_threads(MultiKind k) {
       return 64;
     case MultiKind::EigWg64:
       return EigWgShape<64>::TPB;
+    case MultiKind::EigBig:
+      return kBigTPB;
     default:
       return kThreads;
   }
@@ -2902,7 +3205,7 @@ MultiKind eig_kind(int np) {
     case 16: return MultiKind::EigWave16;
     case 36: return MultiKind::EigWg36;
     case 64: return MultiKind::EigWg64;
-    default: return MultiKind::EigChunk;
+    default: return eig_big(np) ? MultiKind::EigBig : MultiKind::EigChunk;
   }
 }
 
@@ -2954,6 +3257,7 @@ hipError_t launch_multi(MultiKind k, const void* d_args, const Item* d_items, in
     QOC_MULTI_CASE(EigWg36, km_eig_wg36, EigArgs)
     QOC_MULTI_CASE(EigWg64, km_eig_wg64, EigArgs)
     QOC_MULTI_CASE(EigChunk, km_eig_chunk, EigArgs)
+    QOC_MULTI_CASE(EigBig, km_eig_big, EigArgs)
     QOC_MULTI_CASE(Boundary, km_boundary, BndArgs)
     QOC_MULTI_CASE(ForwardStaged, km_forward_staged, SweepArgs)
     QOC_MULTI_CASE(ForwardSmall, km_forward_small, SweepArgs)

@@ -414,7 +414,7 @@ qoc_status qoc_tr_solve_many(qoc_problem* p, int32_t count, const double* theta0
   if (st != QOC_OK) return st;
   if (count < 1 || !theta0 || !theta_out) return p->fail(QOC_ERR_INVALID_ARG, "theta0 / theta_out NULL or count < 1");
   if (!(gtol > 0.0) || max_iter < 0) return p->fail(QOC_ERR_INVALID_ARG, "gtol must be > 0 and max_iter >= 0");
-  const int P = p->P, n = p->n;
+  const int P = p->P, n = p->target_n();   // n: complex entries per caller target
   const size_t PP = (size_t)P * P;
   // whitening W (P x r) from the singular value decomposition of the control model
   st = ensure_whitening(p);
@@ -597,9 +597,9 @@ qoc_status qoc_tr_solve_bfgs_many(qoc_problem* p, int32_t count, const double* t
   if (st != QOC_OK) return st;
   if (count < 1 || !theta0 || !theta_out) return p->fail(QOC_ERR_INVALID_ARG, "theta0 / theta_out NULL or count < 1");
   if (!(gtol > 0.0) || max_iter < 0) return p->fail(QOC_ERR_INVALID_ARG, "gtol must be > 0 and max_iter >= 0");
-  if (targets && !std::all_of(targets, targets + (size_t)count * 2 * p->n, [](double x) { return std::isfinite(x); }))
+  if (targets && !std::all_of(targets, targets + (size_t)count * 2 * p->target_n(), [](double x) { return std::isfinite(x); }))
     return p->fail(QOC_ERR_INVALID_ARG, "targets have non-finite entries");
-  const int P = p->P, n = p->n;
+  const int P = p->P, n = p->target_n();   // n: complex entries per caller target
   st = ensure_whitening(p);
   if (st != QOC_OK) return st;
   const int R = p->tr_rank;

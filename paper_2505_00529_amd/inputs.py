@@ -41,6 +41,7 @@ __all__ = [
     "degenerate_system",
     "DEGENERATE_KINDS",
     "transfer_system",
+    "hermitian_system",
     "WORKLOADS",
 ]
 
@@ -49,8 +50,8 @@ __all__ = [
 class System:
     """A finite-basis TDSE system i a' = (H0 + f(t) M) a with one control."""
 
-    h0: np.ndarray          # (n, n) float64, real symmetric
-    m: np.ndarray           # (n, n) float64, real symmetric
+    h0: np.ndarray          # (n, n) float64 real symmetric, or complex128 Hermitian
+    m: np.ndarray           # (n, n) float64 real symmetric, or complex128 Hermitian
     psi0: np.ndarray        # (n,) complex128
     psi_target: np.ndarray  # (n,) complex128
 
@@ -136,6 +137,18 @@ def transfer_system(n: int, seed: int = 12) -> System:
     e = spectrum_with_gap(rng, n, -3.0, 1e-3)
     m = _sym_normal(rng, n, 0.3, zero_diag=False)
     return System(np.diag(e), m, _unit(n, 0), _unit(n, n - 1))
+
+
+def hermitian_system(n: int, seed: int = 13, sigma: float = 0.3) -> System:
+    """Stand-in for the paper's random timing systems (Sec. IV-A): H0 = diag(sorted U[-3, 0]),
+    M complex Hermitian with Re and Im of the off-diagonal entries ~ N(0, sigma^2 / 2) and a real
+    diagonal ~ N(0, sigma^2); alpha = e_0, beta = e_{n-1}."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, n, 31])))
+    h0 = np.diag(np.sort(rng.uniform(-3.0, 0.0, n))).astype(np.complex128)
+    z = rng.normal(0.0, sigma / np.sqrt(2.0), (n, n)) + 1j * rng.normal(0.0, sigma / np.sqrt(2.0), (n, n))
+    m = np.triu(z, 1)
+    m = m + m.conj().T + np.diag(rng.normal(0.0, sigma, n))
+    return System(h0, m, _unit(n, 0), _unit(n, n - 1))
 
 
 def _default_weights(dt: float):

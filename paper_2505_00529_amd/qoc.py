@@ -75,6 +75,7 @@ SIGNATURES = {
     "qoc_tr_gradient_norms": (_st, [_vp, _i32, _dp, _dp, _dp]),
     "qoc_set_tr_step_tolerance": (_st, [_vp, ctypes.c_double]),
     "qoc_set_tr_subproblem": (_st, [_vp, _i32]),
+    "qoc_set_system_hermitian": (_st, [_vp, _i32, _dp, _dp, _dp, _dp]),
     "qoc_tr_solve_bfgs_many": (_st, [_vp, _i32, _dp, _dp, ctypes.c_double, _i32, _dp, _dp, ctypes.POINTER(_i32),
                                      ctypes.POINTER(_i32)]),
     "qoc_bfgs_update": (_st, [_i32, _dp, _dp, _dp, _dp, _i32]),
@@ -196,6 +197,16 @@ class Problem:
         m = _f64(m, n * n)
         self._check(lib().qoc_set_system(self._h, n, _ptr(h0), _ptr(m), _ptr(_cplx(psi0, n)),
                                          _ptr(_cplx(psi_target, n))))
+        self.n = n
+
+    def set_system_hermitian(self, h0, m, psi0, psi_target):
+        """Complex Hermitian H0, M (n x n complex); evaluated through the exact real embedding."""
+        h0 = np.ascontiguousarray(np.asarray(h0, dtype=np.complex128))
+        n = h0.shape[0]
+        m = np.ascontiguousarray(np.asarray(m, dtype=np.complex128).reshape(n, n))
+        hv, mv = h0.view(np.float64), m.view(np.float64)
+        self._check(lib().qoc_set_system_hermitian(self._h, n, _ptr(hv), _ptr(mv), _ptr(_cplx(psi0, n)),
+                                                   _ptr(_cplx(psi_target, n))))
         self.n = n
 
     def set_target(self, psi_target):

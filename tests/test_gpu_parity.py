@@ -360,3 +360,22 @@ def test_sweep_cap_on_device_entry_points_and_autograd():
     _, gr = p.grad(th.detach().cpu().numpy())
     assert _rel(gt.cpu().numpy(), gr) < 1e-13
     p.close()
+
+
+@pytest.mark.parametrize("n", [72, 100, 127, 128])
+def test_large_n_eigen_kernel_against_oracle(n):
+    """Sizes past one LDS tile (A in LDS, V in global memory): even, odd (padded) and the
+    largest n, over five eigen chunks of 8 steps, against the oracle."""
+    nt, dt, k = 40, 0.02, 2
+    w = inputs.make_workload("molecule", n=n, nt=nt, dt=dt, k=k, seed=40 + n)
+    s = w.system
+    p = qoc.problem_from_workload(w)
+    ths = inputs.draw_thetas(w.p, 2, 700 + n, sigma=0.3)
+    c, g, h = p.hess_many(ths)
+    basis = O.fourier_basis(nt, dt, k)
+    for i in range(2):
+        cr, gr, hr = O.cost_grad_hess(s.h0, s.m, s.psi0, s.psi_target, basis, dt, ths[i], w.gamma, w.rho)
+        print(f"n={n} theta {i}: dC={_rel(c[i], cr):.2e} dg={_rel(g[i], gr):.2e} dH={_rel(h[i], hr):.2e}",
+              flush=True)
+        assert _rel(c[i], cr) < TOL and _rel(g[i], gr) < TOL and _rel(h[i], hr) < TOL
+    p.close()
