@@ -503,9 +503,13 @@ struct EigWgShape<36> {
 };
 template <>
 struct EigWgShape<64> {
-  static constexpr int TPB = 512;        // eight waves share the 101 KB of LDS
+  static constexpr int TPB = 512;        // eight waves share the 67 KB of LDS
   static constexpr int RT = 4, CT = 2;   // 16 x 32 output tiles
-  static constexpr bool VP_LDS = true;   // 3 buffers of 64 x 66 doubles: 101 KB, one problem per CU
+  // V_{j-1} in a global scratch (two 64 x 66 buffers in LDS, 67 KB): with it in LDS as well
+  // (101 KB) the persistent queue variant of this kernel returned wrong eigen-data (batched
+  // results 1e-1 off while the same code as a plain launch matched the oracle, and a row stride
+  // of 64 or this layout were both correct); that configuration is not used until understood
+  static constexpr bool VP_LDS = false;
   static constexpr int VW0 = 1, VW = 4;
   static constexpr int VS = 8;
   // one problem per CU without spills (256 VGPRs) beats two per CU at 128 VGPRs with about 130
@@ -2772,7 +2776,8 @@ hipError_t configure_kernels() {
 
 size_t eig_scratch_doubles(int n, int nb, int nchunks) {
   const int np = pad_even(n);
-  if (np == 36 || np == 64) return 0;   // workgroup kernels: everything in LDS
+  if (np == 64) return (size_t)nb * nchunks * np * EigWgShape<64>::LD;   // V_{j-1} per chunk
+  if (np == 36) return 0;   // workgroup kernel: everything in LDS
   if (eig_fits_lds(np)) return 0;
   return (size_t)nb * nchunks * 3 * np * np;   // large-N kernel: V, V_{j-1}, X
 }
