@@ -118,6 +118,18 @@ qoc_status qoc_grad_many(qoc_problem* p, int32_t count, const double* thetas,
 qoc_status qoc_hess_many_targets(qoc_problem* p, int32_t count, const double* thetas, const double* targets,
                                  double* costs, double* grads, double* hess);
 
+/* Evaluation at given control samples, for control models that are not linear in theta (the
+ * neural-network models the paper proposes, Sec. II's model f(t; theta) with any smoothness): the
+ * caller evaluates its model at the current parameters, passes the samples f (nt doubles, host)
+ * and sets the model's Jacobian df/dtheta as a DENSE control basis (nt x P).  Outputs (host, each
+ * may be NULL): the cost at f; grad = J^T dC/df; hess = J^T (d2C/df2) J, the part of the Hessian
+ * that the second-order adjoint sweeps give (eq. d2Ldf2 with the model's first derivatives); and
+ * dcdf = dC/df (nt doubles: gamma f_j + q_j), with which the caller adds the model's own
+ * second-order term sum_j dcdf_j d2f_j/dtheta2.  With hess == NULL only the first-order sweeps run.
+ * QOC_ERR_INVALID_ARG if f is NULL or not finite. */
+qoc_status qoc_eval_controls(qoc_problem* p, const double* f, double* cost, double* grad, double* hess,
+                             double* dcdf);
+
 /* Device-pointer twins (same kernels, enqueue only, no synchronisation). */
 qoc_status qoc_cost_dev(qoc_problem* p, const double* theta, double* cost);
 qoc_status qoc_grad_dev(qoc_problem* p, const double* theta, double* cost, double* grad);

@@ -267,7 +267,12 @@ qoc_status qoc_problem::enqueue_into(Work& w, bool ck, Mode mode, int nb, const 
     w.nchunks = (len + w.chunk - 1) / w.chunk;
   };
   const bool store_derivs = mode != Mode::Cost;
-  QOC_LAUNCH("controls", launch_controls(bs, d_theta, w.f, nb, stream));
+  if (d_fgiven) {
+    QOC_LAUNCH("controls", hipMemcpyAsync(w.f, d_fgiven, (size_t)nb * nt * sizeof(double), hipMemcpyDeviceToDevice,
+                                          stream));
+  } else {
+    QOC_LAUNCH("controls", launch_controls(bs, d_theta, w.f, nb, stream));
+  }
   if (mode == Mode::Hvp) QOC_LAUNCH("controls", launch_controls(bs, d_v, w.u, nb, stream));
   if (!ck) {
     set_range(0, nt);
@@ -890,6 +895,50 @@ qoc_status qoc_set_jacobi_tolerance(qoc_problem* p, double tol_rel) {
   if (!std::isfinite(tol_rel) || tol_rel < 0.0 || tol_rel > 1e-6)
     return p->fail(QOC_ERR_INVALID_ARG, "tolerance must be in [0, 1e-6]");
   p->jacobi_tol = tol_rel;
+  return QOC_OK;
+}
+
+qoc_status qoc_eval_controls(qoc_problem* p, const double* f, double* cost, double* grad, double* hess,
+                             double* dcdf) {
+  if (!p) return QOC_ERR_INVALID_ARG;
+  qoc_status st = p->ready();
+  if (st != QOC_OK) return st;
+  const int nt = p->nt, P = p->P;
+  if (!f) return p->fail(QOC_ERR_INVALID_ARG, "f must be non-NULL");
+  if (!all_finite(f, (size_t)nt)) return p->fail(QOC_ERR_INVALID_ARG, "f has non-finite entries");
+  const Mode mode = hess ? Mode::Hess : ((grad || dcdf) ? Mode::Grad : Mode::Cost);
+  st = p->ensure_work(1, 0);
+  if (st != QOC_OK) return st;
+  const size_t nh = hess ? (size_t)P * P : 0;
+  st = p->ensure_io((size_t)nt + 1 + P + nh);
+  if (st != QOC_OK) return st;
+  double* d_f = p->d_io;
+  double* d_c = d_f + nt;
+  double* d_g = d_c + 1;
+  double* d_h = d_g + P;
+  hipError_t e = hipMemcpyAsync(d_f, f, (size_t)nt * sizeof(double), hipMemcpyHostToDevice, p->stream);
+  if (e != hipSuccess) return p->hip_fail(e, "control upload");
+  p->d_fgiven = d_f;
+  st = p->enqueue_into(p->w, false, mode, 1, nullptr, nullptr, d_c, mode == Mode::Cost ? nullptr : d_g,
+                       hess ? d_h : nullptr, nullptr);
+  p->d_fgiven = nullptr;
+  if (st != QOC_OK) return st;
+  double c = 0.0;
+  std::vector<double> g(mode == Mode::Cost ? 0 : P), h(nh), q(dcdf && mode != Mode::Cost ? nt : 0);
+  e = hipMemcpyAsync(&c, d_c, sizeof(double), hipMemcpyDeviceToHost, p->stream);
+  if (e == hipSuccess && !g.empty()) e = hipMemcpyAsync(g.data(), d_g, P * sizeof(double), hipMemcpyDeviceToHost, p->stream);
+  if (e == hipSuccess && nh) e = hipMemcpyAsync(h.data(), d_h, nh * sizeof(double), hipMemcpyDeviceToHost, p->stream);
+  if (e == hipSuccess && !q.empty())
+    e = hipMemcpyAsync(q.data(), p->w.q, (size_t)nt * sizeof(double), hipMemcpyDeviceToHost, p->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+  if (e != hipSuccess) return p->hip_fail(e, "result download");
+  st = p->check_device_status();
+  if (st != QOC_OK) return st;
+  if (cost) *cost = c;
+  if (grad) std::memcpy(grad, g.data(), P * sizeof(double));
+  if (hess) std::memcpy(hess, h.data(), nh * sizeof(double));
+  if (dcdf)
+    for (int j = 0; j < nt; ++j) dcdf[j] = p->gamma * f[j] + q[j];
   return QOC_OK;
 }
 

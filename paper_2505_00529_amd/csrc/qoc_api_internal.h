@@ -45,6 +45,8 @@ struct qoc_problem {
 
   // workspace
   qoc::Work w;
+  // when set, the evaluation takes these control samples (nb x nt, device) instead of B theta
+  const double* d_fgiven = nullptr;
   void* work_mem = nullptr;
   size_t work_bytes = 0;
   int work_key_nb = 0;

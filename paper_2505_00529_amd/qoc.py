@@ -76,6 +76,7 @@ SIGNATURES = {
     "qoc_set_tr_step_tolerance": (_st, [_vp, ctypes.c_double]),
     "qoc_set_tr_subproblem": (_st, [_vp, _i32]),
     "qoc_set_system_hermitian": (_st, [_vp, _i32, _dp, _dp, _dp, _dp]),
+    "qoc_eval_controls": (_st, [_vp, _dp, _dp, _dp, _dp, _dp]),
     "qoc_tr_solve_bfgs_many": (_st, [_vp, _i32, _dp, _dp, ctypes.c_double, _i32, _dp, _dp, ctypes.POINTER(_i32),
                                      ctypes.POINTER(_i32)]),
     "qoc_bfgs_update": (_st, [_i32, _dp, _dp, _dp, _dp, _i32]),
@@ -198,6 +199,17 @@ class Problem:
         self._check(lib().qoc_set_system(self._h, n, _ptr(h0), _ptr(m), _ptr(_cplx(psi0, n)),
                                          _ptr(_cplx(psi_target, n))))
         self.n = n
+
+    def eval_controls(self, f, hessian: bool = True):
+        """(cost, J^T dC/df, J^T d2C/df2 J or None, dC/df) at control samples f, with the model's
+        Jacobian J set as a DENSE basis."""
+        fv = _f64(f, self.nt)
+        c = np.zeros(1)
+        g = np.zeros(self.P)
+        h = np.zeros((self.P, self.P)) if hessian else None
+        w = np.zeros(self.nt)
+        self._check(lib().qoc_eval_controls(self._h, _ptr(fv), _ptr(c), _ptr(g), _ptr(h), _ptr(w)))
+        return float(c[0]), g, h, w
 
     def set_system_hermitian(self, h0, m, psi0, psi_target):
         """Complex Hermitian H0, M (n x n complex); evaluated through the exact real embedding."""
