@@ -169,6 +169,14 @@ qoc_status qoc_set_jacobi_sweep_cap(qoc_problem* p, int32_t max_sweeps);
  * A tolerance of 0 runs the sweeps until the off-diagonal part is exactly zero or the cap. */
 qoc_status qoc_set_jacobi_tolerance(qoc_problem* p, double tol_rel);
 
+/* Length of the warm-started eigen-data chains: each chain of `steps` consecutive time steps is
+ * one workgroup's work, its first step decomposed from scratch and every later one from the
+ * previous step's basis.  0 (default) picks the length from the batch size (enough chains to fill
+ * the device, at least 8 steps each); 1..32 fixes it.  Short chains pay off when the steps are
+ * far apart anyway (large control jumps between steps, e.g. the maximal model with random
+ * parameters), long ones when warm starts converge in few sweeps.  Results agree to rounding.
+ * QOC_ERR_INVALID_ARG outside [0, 32]. */
+qoc_status qoc_set_eig_chunk(qoc_problem* p, int32_t steps);
 /* Checkpoint interval (steps) for the cost / gradient / HVP paths: 0 stores every step's
  * eigen-data; k > 0 keeps only states every k steps and recomputes one segment's
  * eigen-data at a time in the backward sweep (the memory reduction the paper names as

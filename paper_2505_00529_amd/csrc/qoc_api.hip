@@ -182,14 +182,16 @@ size_t layout_work(Work& nw, int n, int nt, int P, int nb, int seg, int chunk_re
 // Lay out (and if needed grow) one evaluation workspace for nb thetas.  seg > 0 sizes the
 // eigen-data for one checkpoint segment of seg steps instead of the whole horizon.
 qoc_status qoc_problem::ensure_work(int nb, int seg) {
-  if (work_mem && work_key_nb == nb && work_key_seg == seg && w.n == n && w.nt == nt && w.P == P) return QOC_OK;
+  if (work_mem && work_key_nb == nb && work_key_seg == seg && work_key_chunk == eig_chunk_req && w.n == n &&
+      w.nt == nt && w.P == P)
+    return QOC_OK;
   release_work();
   Work nw;
-  const size_t total = layout_work(nw, n, nt, P, nb, seg, 0, nullptr);
+  const size_t total = layout_work(nw, n, nt, P, nb, seg, eig_chunk_req, nullptr);
   void* mem = nullptr;
   qoc_status st = dmalloc(&mem, total, "workspace allocation");
   if (st != QOC_OK) return st;
-  layout_work(nw, n, nt, P, nb, seg, 0, mem);
+  layout_work(nw, n, nt, P, nb, seg, eig_chunk_req, mem);
   nw.status = d_status;
   nw.stats = d_stats;
   w = nw;
@@ -197,6 +199,7 @@ qoc_status qoc_problem::ensure_work(int nb, int seg) {
   work_bytes = total;
   work_key_nb = nb;
   work_key_seg = seg;
+  work_key_chunk = eig_chunk_req;
   return QOC_OK;
 }
 
@@ -939,6 +942,13 @@ qoc_status qoc_eval_controls(qoc_problem* p, const double* f, double* cost, doub
   if (hess) std::memcpy(hess, h.data(), nh * sizeof(double));
   if (dcdf)
     for (int j = 0; j < nt; ++j) dcdf[j] = p->gamma * f[j] + q[j];
+  return QOC_OK;
+}
+
+qoc_status qoc_set_eig_chunk(qoc_problem* p, int32_t steps) {
+  if (!p) return QOC_ERR_INVALID_ARG;
+  if (steps < 0 || steps > kMaxWarmChain) return p->fail(QOC_ERR_INVALID_ARG, "chain length must be in [0, 32]");
+  p->eig_chunk_req = steps;
   return QOC_OK;
 }
 

@@ -51,6 +51,8 @@ struct qoc_problem {
   size_t work_bytes = 0;
   int work_key_nb = 0;
   int work_key_seg = -1;
+  int work_key_chunk = 0;
+  int eig_chunk_req = 0;   // length of the warm-started eigen chains (0: automatic)
   double* d_io = nullptr;
   size_t io_bytes = 0;
   double* d_props = nullptr;

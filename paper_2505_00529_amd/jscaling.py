@@ -34,8 +34,9 @@ def _say(msg: str) -> None:
     print(f"[jscaling] {msg}", flush=True)
 
 
-def make_problem(n: int, nt: int, device: int = 0) -> qoc.Problem:
+def make_problem(n: int, nt: int, chunk: int = 0, device: int = 0) -> qoc.Problem:
     p = qoc.Problem(device)
+    p.set_eig_chunk(chunk)
     if n >= 64:
         s = inputs.hermitian_system(n)
         p.set_system_hermitian(s.h0, s.m, s.psi0, s.psi_target)
@@ -69,19 +70,19 @@ def ols_slope(x: np.ndarray, y: np.ndarray) -> float:
     return float(np.linalg.lstsq(a, y, rcond=None)[0][0])
 
 
-def run(n: int, kmin: int, kmax: int, trials: int, seed: int) -> dict:
+def run(n: int, kmin: int, kmax: int, trials: int, seed: int, chunk: int = 0) -> dict:
     rows = []
     for kappa in range(kmin, kmax + 1):
         nt = 2 ** kappa
-        p = make_problem(n, nt)
+        p = make_problem(n, nt, chunk)
         tg, th = time_pair(p, nt, trials, seed)
         p.close()
         rows.append({"J": nt, "grad_ms_mean": 1e3 * tg.mean(), "grad_ms_std": 1e3 * tg.std(),
                      "hess_ms_mean": 1e3 * th.mean(), "hess_ms_std": 1e3 * th.std(),
                      "hess_over_grad": float(th.mean() / tg.mean())})
-        _say(f"N={n} J={nt}: gradient {1e3 * tg.mean():.3f} ms, gradient + Hessian {1e3 * th.mean():.3f} ms")
+        _say(f"N={n} J={nt} chain {chunk}: gradient {1e3 * tg.mean():.3f} ms, gradient + Hessian {1e3 * th.mean():.3f} ms")
     lj = np.log2([r["J"] for r in rows])
-    return {"n": n, "complex_hermitian": n >= 64, "trials": trials, "rows": rows,
+    return {"n": n, "complex_hermitian": n >= 64, "trials": trials, "eig_chunk": chunk, "rows": rows,
             "ols_slope_alg1_grad": ols_slope(lj, np.log2([r["grad_ms_mean"] for r in rows])),
             "ols_slope_alg2_hess": ols_slope(lj, np.log2([r["hess_ms_mean"] for r in rows]))}
 
@@ -95,9 +96,12 @@ def main(argv=None) -> int:
     ap.add_argument("--kmin", type=int, default=2)
     ap.add_argument("--kmax", type=int, default=10)
     ap.add_argument("--seed", type=int, default=14)
+    ap.add_argument("--chunk", type=int, default=1,
+                    help="length of the warm-started eigen chains (0: automatic; 1: every step from "
+                         "scratch and in parallel, the better choice when the steps are cold anyway)")
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
-    res = [run(n, a.kmin, a.kmax, a.trials if n < 64 else a.trials_large, a.seed) for n in a.n]
+    res = [run(n, a.kmin, a.kmax, a.trials if n < 64 else a.trials_large, a.seed, a.chunk) for n in a.n]
     line = json.dumps({"protocol": "J scaling of one evaluation, maximal model", "dt": DT, "rho": RHO,
                        "systems": res})
     print(line, flush=True)

@@ -77,6 +77,7 @@ SIGNATURES = {
     "qoc_set_tr_subproblem": (_st, [_vp, _i32]),
     "qoc_set_system_hermitian": (_st, [_vp, _i32, _dp, _dp, _dp, _dp]),
     "qoc_eval_controls": (_st, [_vp, _dp, _dp, _dp, _dp, _dp]),
+    "qoc_set_eig_chunk": (_st, [_vp, _i32]),
     "qoc_tr_solve_bfgs_many": (_st, [_vp, _i32, _dp, _dp, ctypes.c_double, _i32, _dp, _dp, ctypes.POINTER(_i32),
                                      ctypes.POINTER(_i32)]),
     "qoc_bfgs_update": (_st, [_i32, _dp, _dp, _dp, _dp, _i32]),
@@ -234,6 +235,10 @@ class Problem:
 
     def set_weights(self, gamma: float, rho: float):
         self._check(lib().qoc_set_weights(self._h, gamma, rho))
+
+    def set_eig_chunk(self, steps: int):
+        """Length of the warm-started eigen chains (0: automatic, 1..32: fixed)."""
+        self._check(lib().qoc_set_eig_chunk(self._h, int(steps)))
 
     def set_checkpoint_interval(self, steps: int):
         self._check(lib().qoc_set_checkpoint_interval(self._h, steps))

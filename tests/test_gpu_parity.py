@@ -379,3 +379,27 @@ def test_large_n_eigen_kernel_against_oracle(n):
               flush=True)
         assert _rel(c[i], cr) < TOL and _rel(g[i], gr) < TOL and _rel(h[i], hr) < TOL
     p.close()
+
+
+@pytest.mark.parametrize("n", [4, 36, 100])
+def test_eig_chain_length_setting(n):
+    """Fixed chain lengths 1, 3 and 32 give the automatic setting's results to rounding and the
+    oracle's to the parity tolerance; lengths outside [0, 32] are rejected."""
+    nt, dt, k = 40, 0.02, 2
+    w = inputs.make_workload("molecule", n=n, nt=nt, dt=dt, k=k, seed=50 + n)
+    s = w.system
+    p = qoc.problem_from_workload(w)
+    ths = inputs.draw_thetas(w.p, 2, 800 + n, sigma=0.3)
+    c0, g0, h0 = p.hess_many(ths)
+    basis = O.fourier_basis(nt, dt, k)
+    cr, gr, hr = O.cost_grad_hess(s.h0, s.m, s.psi0, s.psi_target, basis, dt, ths[0], w.gamma, w.rho)
+    for chain in (1, 3, 32):
+        p.set_eig_chunk(chain)
+        c, g, h = p.hess_many(ths)
+        print(f"n={n} chain {chain}: vs auto dH={_rel(h, h0):.2e}, vs oracle dH={_rel(h[0], hr):.2e}", flush=True)
+        assert _rel(c, c0) < 1e-12 and _rel(g, g0) < 1e-11 and _rel(h, h0) < 1e-11
+        assert _rel(c[0], cr) < TOL and _rel(g[0], gr) < TOL and _rel(h[0], hr) < TOL
+    for bad in (-1, 33):
+        with pytest.raises(qoc.QocError):
+            p.set_eig_chunk(bad)
+    p.close()
