@@ -1173,7 +1173,7 @@ constexpr int kBigBlk = 3;   // >= ceil((64 * 65 / 2) / kBigTPB): blocks per thr
 constexpr int kBigV = 8;     // >= 128 * 64 / kBigTPB: V entries per thread at NP = 128
 
 __host__ __device__ inline size_t eig_big_lds_doubles(int np) {
-  return (size_t)np + kBigTPB / 64 + np + (np + 1) / 2 + (size_t)np * np;
+  return (size_t)np + kBigTPB / 64 + np + (np + 1) / 2 + (size_t)np * (np + 1);
 }
 
 // Round r of the circle pairing of np players (np - 1 rounds): player np-1 meets r, the others
@@ -1223,7 +1223,10 @@ __device__ __forceinline__ void body_eig_big(const EigArgs& a, int c, int b) {
   double2* rot2 = (double2*)smem;             // np / 2: (c, s) per pair of the round
   double* red = smem + np;                    // TPB / 64
   double* lamv = red + TPB / 64;              // np
-  double* A = lamv + np + (np + 1) / 2;       // np x np, row-major
+  // np x np, row-major at a row stride of np + 1: with a stride of np (a multiple of the 64 LDS
+  // banks) the transposed block writes of a wave, one column of rows, all hit one bank
+  const int LD = np + 1;
+  double* A = lamv + np + (np + 1) / 2;
   double* Vc = a.gscratch + ((size_t)b * a.nchunks + c) * 3 * (size_t)npp;   // V_j, column-major
   double* Vpc = Vc + npp;                     // V_{j-1}
   double* Xc = Vpc + npp;                     // X = M V_j, then O_{j-1}, column-major
@@ -1257,20 +1260,23 @@ __device__ __forceinline__ void body_eig_big(const EigArgs& a, int c, int b) {
     if (j == j0) {
       for (int idx = tid; idx < npp; idx += TPB) {
         const int i = idx / np, k = idx - (idx / np) * np;
-        A[idx] = (i < n && k < n) ? a.h0[i * n + k] + fj * a.m[i * n + k] : 0.0;
+        A[i * LD + k] = (i < n && k < n) ? a.h0[i * n + k] + fj * a.m[i * n + k] : 0.0;
         Vc[idx] = (i == k) ? 1.0 : 0.0;
       }
     } else {
       const double df = fj - fb[j - 1];
       for (int idx = tid; idx < npp; idx += TPB) {
         const int i = idx / np, k = idx - (idx / np) * np;
-        A[idx] = df * A[idx] + (i == k ? lamv[i] : 0.0);   // A held Mt_{j-1}
+        A[i * LD + k] = df * A[i * LD + k] + (i == k ? lamv[i] : 0.0);   // A held Mt_{j-1}
         Vpc[idx] = Vc[idx];
       }
     }
     __syncthreads();
     double loc = 0.0;
-    for (int idx = tid; idx < npp; idx += TPB) loc = fma(A[idx], A[idx], loc);
+    for (int idx = tid; idx < npp; idx += TPB) {
+      const double x = A[(idx / np) * LD + idx - (idx / np) * np];
+      loc = fma(x, x, loc);
+    }
     const double tol = a.tol_rel * sqrt(wg_sum<TPB>(loc, red));
     int sweep = 0;
     bool conv = false;
@@ -1279,7 +1285,7 @@ __device__ __forceinline__ void body_eig_big(const EigArgs& a, int c, int b) {
       double off = 0.0;
       for (int idx = tid; idx < npp; idx += TPB) {
         const int i = idx / np, k = idx - (idx / np) * np;
-        if (i < k) off = fmax(off, fabs(A[idx]));
+        if (i < k) off = fmax(off, fabs(A[i * LD + k]));
       }
       off = wg_max<TPB>(off, red);
       if (off <= tol) {
@@ -1303,10 +1309,10 @@ __device__ __forceinline__ void body_eig_big(const EigArgs& a, int c, int b) {
             int pI, qI, pK, qK;
             rr_pair_fast(r, bI[t], np, pI, qI);
             rr_pair_fast(r, bK[t], np, pK, qK);
-            x00[t] = A[pI * np + pK];
-            x01[t] = A[pI * np + qK];
-            x10[t] = A[qI * np + pK];
-            x11[t] = A[qI * np + qK];
+            x00[t] = A[pI * LD + pK];
+            x01[t] = A[pI * LD + qK];
+            x10[t] = A[qI * LD + pK];
+            x11[t] = A[qI * LD + qK];
           }
         }
         double vp[kBigV], vq[kBigV];
@@ -1324,7 +1330,7 @@ __device__ __forceinline__ void body_eig_big(const EigArgs& a, int c, int b) {
           int pp, qq;
           rr_pair_fast(r, tid, np, pp, qq);
           double cc, ss;
-          jacobi_rotation(A[pp * np + pp], A[qq * np + qq], A[pp * np + qq], cc, ss);
+          jacobi_rotation(A[pp * LD + pp], A[qq * LD + qq], A[pp * LD + qq], cc, ss);
           rot2[tid] = make_double2(cc, ss);
         }
         __syncthreads();
@@ -1343,19 +1349,19 @@ __device__ __forceinline__ void body_eig_big(const EigArgs& a, int c, int b) {
             const double b00 = RI.x * t00 - RI.y * t10, b01 = RI.x * t01 - RI.y * t11;
             const double b10 = RI.y * t00 + RI.x * t10, b11 = RI.y * t01 + RI.x * t11;
             if (I == K) {
-              A[pI * np + pI] = b00;
-              A[pI * np + qI] = 0.0;
-              A[qI * np + pI] = 0.0;
-              A[qI * np + qI] = b11;
+              A[pI * LD + pI] = b00;
+              A[pI * LD + qI] = 0.0;
+              A[qI * LD + pI] = 0.0;
+              A[qI * LD + qI] = b11;
             } else {
-              A[pI * np + pK] = b00;
-              A[pI * np + qK] = b01;
-              A[qI * np + pK] = b10;
-              A[qI * np + qK] = b11;
-              A[pK * np + pI] = b00;
-              A[qK * np + pI] = b01;
-              A[pK * np + qI] = b10;
-              A[qK * np + qI] = b11;
+              A[pI * LD + pK] = b00;
+              A[pI * LD + qK] = b01;
+              A[qI * LD + pK] = b10;
+              A[qI * LD + qK] = b11;
+              A[pK * LD + pI] = b00;
+              A[qK * LD + pI] = b01;
+              A[pK * LD + qI] = b10;
+              A[qK * LD + qI] = b11;
             }
           }
         }
@@ -1378,7 +1384,7 @@ __device__ __forceinline__ void body_eig_big(const EigArgs& a, int c, int b) {
       atomicAdd(a.stats, 1ull);
       atomicAdd(a.stats + 1, (unsigned long long)sweep);
     }
-    for (int i = tid; i < np; i += TPB) lamv[i] = A[i * np + i];
+    for (int i = tid; i < np; i += TPB) lamv[i] = A[i * LD + i];
     // V_j carries into the next step: unit columns
     if (tid < np) normalize_column_contig(Vc + (size_t)tid * np, np);
     __syncthreads();
@@ -1410,10 +1416,10 @@ __device__ __forceinline__ void body_eig_big(const EigArgs& a, int c, int b) {
       const int i0 = 2 * ti, k0 = 2 * tk;
       double c00, c01, c10, c11;
       big_product_tile(Vc, Xc, np, i0, k0, c00, c01, c10, c11);
-      A[i0 * np + k0] = c00;
-      A[i0 * np + k0 + 1] = c01;
-      A[(i0 + 1) * np + k0] = c10;
-      A[(i0 + 1) * np + k0 + 1] = c11;
+      A[i0 * LD + k0] = c00;
+      A[i0 * LD + k0 + 1] = c01;
+      A[(i0 + 1) * LD + k0] = c10;
+      A[(i0 + 1) * LD + k0 + 1] = c11;
     }
     __syncthreads();
     const size_t step = (size_t)b * a.eig_stride + (j - a.j_base);
@@ -1435,7 +1441,7 @@ __device__ __forceinline__ void body_eig_big(const EigArgs& a, int c, int b) {
     for (int idx = tid; idx < (int)nn; idx += TPB) {
       const int i = idx / n, k = idx - (idx / n) * n;
       if (a.store_derivs) {
-        const double mtv = A[i * np + k];
+        const double mtv = A[i * LD + k];
         a.mt[step * nn + idx] = mtv;
         a.sm[step * nn + idx] = sinc(0.5 * a.dt * (lamv[i] - lamv[k])) * mtv;
       }
