@@ -8,7 +8,9 @@ untimed call per (N, J) that sizes the workspaces.  Systems: N = 4 and 16 stand 
 full-CI molecules (the real transfer systems of the optimiser comparison); N = 64 uses a random
 diagonal H0 and a random complex Hermitian M, evaluated through the real embedding of size 128.
 The time step is 0.1 and the weights 1 and rho = 1e6, as in the optimiser comparison (the paper
-states neither for its timing runs; they do not change the work).
+states neither for its timing runs; they do not change the work).  With theta ~ N(0, I) consecutive
+steps are far apart, so warm-started eigen chains save little: by default every step is its own
+chain (--chunk 1), decomposed from scratch and in parallel with the others.
 
 Reported per (N, J): mean and standard deviation of both wall times over the trials and their
 ratio; per N, the OLS slopes of log2(mean time) against log2(J) for both algorithms.
