@@ -254,7 +254,7 @@ AsmArgs assemble_args(const BasisDev& bs, const Work& w, Mode mode, double gamma
 
 // Multi-problem (queue) launches: one launch per kernel variant covers many problems.
 enum class MultiKind {
-  Controls, EigWave4, EigWave8, EigWave16, EigWg36, EigWg64, EigChunk, EigBig, Boundary, ForwardStaged, ForwardSmall,
+  Controls, EigWave4, EigWave8, EigWave16, EigWg36, EigWg64, EigChunk, EigBig, EigSlot, Boundary, ForwardStaged, ForwardSmall,
   ForwardGlobal, Terminal, BackwardStaged, BackwardSmall, BackwardGlobal, Sterm, Assemble, Count
 };
 MultiKind eig_kind(int np);

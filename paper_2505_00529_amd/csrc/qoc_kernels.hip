@@ -1455,6 +1455,401 @@ __device__ __forceinline__ void body_eig_big(const EigArgs& a, int c, int b) {
 
 __global__ __launch_bounds__(kBigTPB, 1) void k_eig_big(EigArgs a) { body_eig_big(a, blockIdx.x, blockIdx.y); }
 
+// ---------------------------------------------------------------- eigen-data at NP = 128, slot order
+
+// The circle-slot design of body_eig_wg at NP = 128, where two NP x NP buffers do not fit in LDS:
+// the two ping-pong copies of A are the two triangles of one (NP + 1) x kSlotLD array (buffer 0
+// holds entry (x, y), x <= y, at x * kSlotLD + y; buffer 1 at (y + 1) * kSlotLD + x), so a round
+// still reads one buffer and writes the other.  A 2x2 block reads as two 16-byte pairs in either
+// layout: along y in buffer 0, along x in buffer 1.  V stays in registers (a lane holds 32
+// consecutive columns of one row, all eight waves hold V; the last wave also forms the next
+// round's rotations), and at step ends it goes to the same array for the basis products, with V_{j-1} and
+// X = M V_j in the chunk's global scratch.  No perturbative finish: its E and V would need two
+// full buffers; the sweeps run to the tolerance.
+constexpr int kSlotNP = 128;
+constexpr int kSlotTPB = 512;          // eight waves, 256 VGPRs each (1024 threads would allow 128)
+constexpr int kSlotLD = 130;          // even (16-byte pairs in both layouts), 260 dwords a row
+constexpr int kSlotS = 16;            // pairs per V segment
+constexpr int kSlotRT = 8, kSlotCT = 4;   // output tiles of the basis products: 16 x 32 = 512
+
+__host__ __device__ constexpr size_t eig_slot_lds_doubles() {
+  return (size_t)(kSlotNP + 1) * kSlotLD + 4 * (kSlotNP / 2) + kSlotNP + 2 * (kSlotTPB / 64) + kSincTerms + 4;
+}
+__host__ __device__ constexpr size_t eig_slot_scratch_doubles() { return (size_t)2 * kSlotNP * kSlotNP; }   // V_{j-1}, X per chunk
+
+// An opaque copy of v: values derived from it are recomputed where they are used instead of being
+// hoisted out of the round loop, where dozens of loop-invariant addresses would spill.
+__device__ __forceinline__ int opaque(int v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
+template <int PAR>
+__device__ __forceinline__ int slot_addr(int x, int y) {   // x <= y
+  return PAR == 0 ? x * kSlotLD + y : (y + 1) * kSlotLD + x;
+}
+template <int PAR>
+__device__ __forceinline__ int slot_addr_any(int x, int y) {
+  return slot_addr<PAR>(min(x, y), max(x, y));
+}
+// entries (2I, 2K), (2I, 2K + 1), (2I + 1, 2K), (2I + 1, 2K + 1) of a block, I <= K
+template <int PAR>
+__device__ __forceinline__ void slot_read_block(const double* arr, int I, int K, double& a00, double& a01,
+                                                double& a10, double& a11) {
+  if (PAR == 0) {
+    const double2 r0 = *(const double2*)(arr + (2 * I) * kSlotLD + 2 * K);
+    const double2 r1 = *(const double2*)(arr + (2 * I + 1) * kSlotLD + 2 * K);
+    a00 = r0.x;
+    a01 = r0.y;
+    a10 = r1.x;
+    a11 = r1.y;
+  } else {
+    const double2 q0 = *(const double2*)(arr + (2 * K + 1) * kSlotLD + 2 * I);   // (2I, 2K), (2I+1, 2K)
+    const double2 q1 = *(const double2*)(arr + (2 * K + 2) * kSlotLD + 2 * I);   // (2I, 2K+1), (2I+1, 2K+1)
+    a00 = q0.x;
+    a10 = q0.y;
+    a01 = q1.x;
+    a11 = q1.y;
+  }
+}
+
+__device__ __forceinline__ void body_eig_slot(const EigArgs& a, int c, int b) {
+  constexpr int NP = kSlotNP, H = NP / 2, NBLK = H * (H + 1) / 2, TPB = kSlotTPB, LD = kSlotLD;
+  constexpr int BPT = (NBLK + TPB - 1) / TPB;
+  constexpr int S = kSlotS, G = H / S, VRW = 64 / G;   // segments per row, rows per wave
+  constexpr int RT = kSlotRT, CT = kSlotCT, TCOLS = NP / CT;
+  constexpr int ROT0 = TPB - 64;
+  static_assert(G * VRW == 64 && VRW * (TPB / 64) == NP && (NP / RT) * TCOLS == TPB, "slot kernel shape");
+  extern __shared__ __attribute__((aligned(16))) double smem[];
+  double* arr = smem;                                     // (NP + 1) x LD: A buffers 0 / 1; V_j at step ends
+  double2* rot = (double2*)(arr + (NP + 1) * LD);         // 2 x H rotations (c, s)
+  double* lamv = (double*)(rot + 2 * H);
+  double* red = lamv + NP;
+  double* sinc_c = red + 2 * (TPB / 64);
+  double* hnorm = sinc_c + kSincTerms;
+  const int tid = threadIdx.x;
+  const int n = a.n, nt = a.nt;
+  const int j0 = a.j_base + c * a.chunk;
+  const int j1 = min(a.j_base + a.nsteps, j0 + a.chunk);
+  if (j0 >= j1) return;
+  if (tid < kSincTerms) sinc_c[tid] = kSincCoef[tid];
+  const double* fb = a.f + (size_t)b * nt;
+  const size_t nn = (size_t)n * n;
+  double* vpg = a.gscratch + ((size_t)b * a.nchunks + c) * eig_slot_scratch_doubles();   // V_{j-1}, column-major
+  double* xg = vpg + NP * NP;                                                           // X = M V_j, column-major
+  {
+    double hh = 0.0, hm = 0.0, mm = 0.0;
+    for (int idx = tid; idx < (int)nn; idx += TPB) {
+      const double h = a.h0[idx], m = a.m[idx];
+      hh = fma(h, h, hh);
+      hm = fma(h, m, hm);
+      mm = fma(m, m, mm);
+    }
+    hh = wg_sum<TPB>(hh, red);
+    hm = wg_sum<TPB>(hm, red);
+    mm = wg_sum<TPB>(mm, red);
+    if (tid == 0) {
+      hnorm[0] = hh;
+      hnorm[1] = hm;
+      hnorm[2] = mm;
+    }
+  }
+  // fixed blocks (I <= K) of this thread
+  int bI[BPT], bK[BPT];
+#pragma unroll
+  for (int t = 0; t < BPT; ++t) {
+    const int w = tid + TPB * t;
+    int I = -1, K = 0;
+    if (w < NBLK) {
+      I = 0;
+      int rem = w;
+      while (rem >= H - I) {
+        rem -= H - I;
+        ++I;
+      }
+      K = I + rem;
+    }
+    bI[t] = I;
+    bK[t] = K;
+  }
+  // next-round rotation formed by this thread (last wave)
+  const int kr = tid - ROT0;
+  const bool has_rot = kr >= 0 && kr < H;
+  // V registers: every wave, row vrow, pairs vseg*S .. vseg*S + S - 1
+  const int lane = tid & 63;
+  const int vseg = lane % G;
+  const int vrow = (tid >> 6) * VRW + lane / G;
+  double ve[S], vo[S];
+  // output tile
+  const int tr = tid / TCOLS, tc = tid - (tid / TCOLS) * TCOLS;
+  const int i0 = tr * RT, k0 = tc * CT;
+
+  for (int j = j0; j < j1; ++j) {
+    const double fj = fb[j];
+    if (j == j0) {
+      for (int idx = tid; idx < NP * NP; idx += TPB) {
+        const int x = idx / NP, y = idx - (idx / NP) * NP;
+        if (x <= y) arr[x * LD + y] = (x < n && y < n) ? a.h0[x * n + y] + fj * a.m[x * n + y] : 0.0;
+      }
+#pragma unroll
+      for (int k = 0; k < S; ++k) {
+        const int K = vseg * S + k;
+        ve[k] = vrow == 2 * K ? 1.0 : 0.0;
+        vo[k] = vrow == 2 * K + 1 ? 1.0 : 0.0;
+      }
+    } else {
+      const double df = fj - fb[j - 1];
+      for (int idx = tid; idx < NP * NP; idx += TPB) {
+        const int x = idx / NP, y = idx - (idx / NP) * NP;
+        if (x <= y) arr[x * LD + y] = df * arr[x * LD + y] + (x == y ? lamv[x] : 0.0);   // held Mt_{j-1}
+      }
+#pragma unroll
+      for (int k = 0; k < S; ++k) {
+        const int K = vseg * S + k;
+        ve[k] = vpg[(2 * K) * NP + vrow];
+        vo[k] = vpg[(2 * K + 1) * NP + vrow];
+      }
+    }
+    __syncthreads();
+    const double tol = a.tol_rel * sqrt(fmax(fma(fj, fma(fj, hnorm[2], 2.0 * hnorm[1]), hnorm[0]), 0.0));
+    int cur = 0, sweeps_done = 0;
+    bool conv = false;
+#pragma unroll 1
+    for (int sweep = 0;; ++sweep) {
+      sweeps_done = sweep;
+      // sweep boundary: slot order is the index order; A in buffer cur
+      double off = 0.0;
+      if (cur == 0) {
+        if (tid < NP) lamv[tid] = arr[slot_addr<0>(tid, tid)];
+        for (int idx = tid; idx < NP * NP; idx += TPB) {
+          const int x = idx / NP, y = idx - (idx / NP) * NP;
+          if (x < y) off = fmax(off, fabs(arr[slot_addr<0>(x, y)]));
+        }
+      } else {
+        if (tid < NP) lamv[tid] = arr[slot_addr<1>(tid, tid)];
+        for (int idx = tid; idx < NP * NP; idx += TPB) {
+          const int x = idx / NP, y = idx - (idx / NP) * NP;
+          if (x < y) off = fmax(off, fabs(arr[slot_addr<1>(x, y)]));
+        }
+      }
+      off = wg_max<TPB>(off, red);   // its barriers also publish lamv
+      if (off <= tol) {
+        conv = true;
+        break;
+      }
+      if (sweep >= a.max_sweeps) {
+        if (tid == 0) atomicOr(a.status, kStatusNoConv);
+        break;
+      }
+      // first rotations of the sweep, from the current buffer
+      if (has_rot) {
+        double cc, ss;
+        if (cur == 0)
+          jacobi_rotation(arr[slot_addr<0>(2 * kr, 2 * kr)], arr[slot_addr<0>(2 * kr + 1, 2 * kr + 1)],
+                          arr[slot_addr<0>(2 * kr, 2 * kr + 1)], cc, ss);
+        else
+          jacobi_rotation(arr[slot_addr<1>(2 * kr, 2 * kr)], arr[slot_addr<1>(2 * kr + 1, 2 * kr + 1)],
+                          arr[slot_addr<1>(2 * kr, 2 * kr + 1)], cc, ss);
+        rot[kr] = make_double2(cc, ss);
+      }
+      __syncthreads();
+      int rb = 0;   // rotation buffer of the round
+      auto round = [&](auto par) {
+        constexpr int PAR = decltype(par)::value;
+        const double2* R = rot + rb * H;
+#pragma unroll
+        for (int t = 0; t < BPT; ++t) {
+          const int I = opaque(bI[t]);
+          if (I >= 0) {
+            const int K = opaque(bK[t]);
+            double a00, a01, a10, a11;
+            slot_read_block<PAR>(arr, I, K, a00, a01, a10, a11);
+            const bool dg = I == K;
+            double b00, b01, b10, b11;
+            rotate_block(a00, a01, dg ? a01 : a10, a11, R[I], R[K], b00, b01, b10, b11);
+            const int x0 = slot_next<NP>(2 * I), x1 = slot_next<NP>(2 * I + 1);
+            const int y0 = slot_next<NP>(2 * K), y1 = slot_next<NP>(2 * K + 1);
+            arr[slot_addr_any<PAR ^ 1>(x0, y0)] = b00;
+            arr[slot_addr_any<PAR ^ 1>(x0, y1)] = dg ? 0.0 : b01;
+            arr[slot_addr_any<PAR ^ 1>(x1, y0)] = dg ? 0.0 : b10;
+            arr[slot_addr_any<PAR ^ 1>(x1, y1)] = b11;
+          }
+        }
+        if (has_rot) {
+          const int es = slot_prev<NP>(2 * opaque(kr)), os = slot_prev<NP>(2 * opaque(kr) + 1);
+          const int I0 = min(es, os) >> 1, K0 = max(es, os) >> 1;
+          const int rpar = (es < os ? es : os) & 1, cpar = (es < os ? os : es) & 1;
+          const double2 uI = rot_col(R[I0], rpar), uK = rot_col(R[K0], cpar);
+          double gI00, gI01, gI10, gI11, gK00, gK01, gK10, gK11, r00, r01, r10, r11;
+          slot_read_block<PAR>(arr, I0, I0, gI00, gI01, gI10, gI11);
+          slot_read_block<PAR>(arr, K0, K0, gK00, gK01, gK10, gK11);
+          slot_read_block<PAR>(arr, I0, K0, r00, r01, r10, r11);
+          const double dI = rotate_entry(gI00, gI01, gI01, gI11, uI, uI);
+          const double dK = rotate_entry(gK00, gK01, gK01, gK11, uK, uK);
+          const double e = rotate_entry(r00, r01, r10, r11, uI, uK);
+          double cc, ss;
+          jacobi_rotation_nobranch(es < os ? dI : dK, es < os ? dK : dI, e, cc, ss);
+          rot[(rb ^ 1) * H + kr] = make_double2(cc, ss);
+        }
+        {
+          // rotate the segment's pairs and apply the circle shift in place, with one carried
+          // value: even columns move down a pair (ve[k-1] <- e[k]), odd ones up (vo[k] <- o[k-1])
+          const double2* RS = R + vseg * S;
+          double2 RV = RS[0];
+          const double e0 = RV.x * ve[0] - RV.y * vo[0], o0 = RV.y * ve[0] + RV.x * vo[0];
+          RV = RS[1];
+          const double e1 = RV.x * ve[1] - RV.y * vo[1];
+          double carry = RV.y * ve[1] + RV.x * vo[1];   // o[1]
+          vo[1] = o0;
+#pragma unroll
+          for (int k = 2; k < S; ++k) {
+            RV = RS[k];
+            const double ek = RV.x * ve[k] - RV.y * vo[k], ok = RV.y * ve[k] + RV.x * vo[k];
+            ve[k - 1] = ek;
+            vo[k] = carry;
+            carry = ok;
+          }
+          const double e_next = dpp_move<kDppFromNext>(e0);
+          const double o_prev = dpp_move<kDppFromPrev>(carry);
+          ve[0] = vseg == 0 ? e0 : e1;
+          ve[S - 1] = vseg == G - 1 ? carry : e_next;
+          vo[0] = vseg == 0 ? e1 : o_prev;
+        }
+        rb ^= 1;
+        __syncthreads();
+      };
+      const std::integral_constant<int, 0> par0;
+      const std::integral_constant<int, 1> par1;
+      if (cur == 0) {
+#pragma unroll 1
+        for (int r = 0; r + 1 < NP - 1; r += 2) {
+          round(par0);
+          round(par1);
+        }
+        round(par0);
+      } else {
+#pragma unroll 1
+        for (int r = 0; r + 1 < NP - 1; r += 2) {
+          round(par1);
+          round(par0);
+        }
+        round(par1);
+      }
+      cur ^= 1;
+    }
+    if (tid == 0 && a.stats && conv) {
+      atomicAdd(a.stats, 1ull);
+      atomicAdd(a.stats + 1, (unsigned long long)sweeps_done);
+    }
+    // V_j into the array, column-major (Vt[k * LD + i] = V[i][k]); lamv was set at the last
+    // sweep boundary and every read of A there preceded wg_max's barriers
+#pragma unroll
+    for (int k = 0; k < S; ++k) {
+      const int K = vseg * S + k;
+      arr[(2 * K) * LD + vrow] = ve[k];
+      arr[(2 * K + 1) * LD + vrow] = vo[k];
+    }
+    __syncthreads();
+    if (tid < NP) normalize_column_contig(arr + tid * LD, NP);
+    __syncthreads();
+    const size_t step = (size_t)b * a.eig_stride + (j - a.j_base);
+    double acc[RT][CT];
+    // O_{j-1} = V_j^T V_{j-1}
+    if (j > j0) {
+#pragma unroll
+      for (int x = 0; x < RT; ++x)
+#pragma unroll
+        for (int y = 0; y < CT; ++y) acc[x][y] = 0.0;
+#pragma unroll 1
+      for (int r = 0; r < NP; r += 2) {
+        double2 u[RT], w[CT];
+#pragma unroll
+        for (int x = 0; x < RT; ++x) u[x] = *(const double2*)(arr + (i0 + x) * LD + r);
+#pragma unroll
+        for (int y = 0; y < CT; ++y) w[y] = *(const double2*)(vpg + (size_t)(k0 + y) * NP + r);
+#pragma unroll
+        for (int x = 0; x < RT; ++x)
+#pragma unroll
+          for (int y = 0; y < CT; ++y) acc[x][y] = fma(u[x].y, w[y].y, fma(u[x].x, w[y].x, acc[x][y]));
+      }
+      double* dst = a.ov + (step - 1) * nn;
+#pragma unroll
+      for (int x = 0; x < RT; ++x)
+#pragma unroll
+        for (int y = 0; y < CT; ++y)
+          if (i0 + x < n && k0 + y < n) dst[(size_t)(i0 + x) * n + k0 + y] = acc[x][y];
+    }
+    // X = M V_j (column-major in xg; M symmetric, so row i of M is column i)
+#pragma unroll
+    for (int x = 0; x < RT; ++x)
+#pragma unroll
+      for (int y = 0; y < CT; ++y) acc[x][y] = 0.0;
+#pragma unroll 1
+    for (int r = 0; r < n; ++r) {
+      double u[RT], w[CT];
+#pragma unroll
+      for (int x = 0; x < RT; ++x) u[x] = i0 + x < n ? a.m[(size_t)r * n + i0 + x] : 0.0;
+#pragma unroll
+      for (int y = 0; y < CT; ++y) w[y] = arr[(k0 + y) * LD + r];
+#pragma unroll
+      for (int x = 0; x < RT; ++x)
+#pragma unroll
+        for (int y = 0; y < CT; ++y) acc[x][y] = fma(u[x], w[y], acc[x][y]);
+    }
+#pragma unroll
+    for (int y = 0; y < CT; ++y)
+#pragma unroll
+      for (int x = 0; x < RT; ++x) xg[(size_t)(k0 + y) * NP + i0 + x] = acc[x][y];
+    __syncthreads();
+    // Mt_j = V_j^T X into registers; V_j to the global copy for the next step and the chunk ends
+#pragma unroll
+    for (int x = 0; x < RT; ++x)
+#pragma unroll
+      for (int y = 0; y < CT; ++y) acc[x][y] = 0.0;
+#pragma unroll 1
+    for (int r = 0; r < NP; r += 2) {
+      double2 u[RT], w[CT];
+#pragma unroll
+      for (int x = 0; x < RT; ++x) u[x] = *(const double2*)(arr + (i0 + x) * LD + r);
+#pragma unroll
+      for (int y = 0; y < CT; ++y) w[y] = *(const double2*)(xg + (size_t)(k0 + y) * NP + r);
+#pragma unroll
+      for (int x = 0; x < RT; ++x)
+#pragma unroll
+        for (int y = 0; y < CT; ++y) acc[x][y] = fma(u[x].y, w[y].y, fma(u[x].x, w[y].x, acc[x][y]));
+    }
+    for (int idx = tid; idx < NP * NP; idx += TPB) {
+      const int k = idx / NP, i = idx - (idx / NP) * NP;   // arr[k * LD + i] = V[i][k]
+      const double v = arr[k * LD + i];
+      vpg[(size_t)k * NP + i] = v;
+      if (i < n && k < n) {
+        if (j == j0) a.vfirst[((size_t)b * a.nchunks + c) * nn + (size_t)i * n + k] = v;
+        if (j == j1 - 1) a.vlast[((size_t)b * a.nchunks + c) * nn + (size_t)i * n + k] = v;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int x = 0; x < RT; ++x)
+#pragma unroll
+      for (int y = 0; y < CT; ++y) arr[(i0 + x) * LD + k0 + y] = acc[x][y];
+    __syncthreads();
+    if (a.store_derivs) {
+      double* mt = a.mt + step * nn;
+      double* sm = a.sm + step * nn;
+      for (int idx = tid; idx < (int)nn; idx += TPB) {
+        const int i = idx / n, k = idx - (idx / n) * n;
+        const double v = arr[i * LD + k];
+        mt[idx] = v;
+        sm[idx] = sinc_table(0.5 * a.dt * (lamv[i] - lamv[k]), sinc_c) * v;
+      }
+    }
+    if (tid < n) a.lam[step * n + tid] = lamv[tid];
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kSlotTPB, 2) void k_eig_slot(EigArgs a) { body_eig_slot(a, blockIdx.x, blockIdx.y); }
+
 // ---------------------------------------------------------------- sweeps
 
 
@@ -2770,7 +3165,7 @@ static size_t sweep_lds_bytes(int n, int pg) {
 }
 
 hipError_t configure_kernels() {
-  const void* fns[] = {(const void*)k_eig_chunk, (const void*)k_eig_big, (const void*)k_eig_wg<36>, (const void*)k_eig_wg<64>, (const void*)k_sym_eig, (const void*)k_forward<kSweepRegs>, (const void*)k_forward<kSweepDbuf>,
+  const void* fns[] = {(const void*)k_eig_chunk, (const void*)k_eig_big, (const void*)k_eig_slot, (const void*)k_eig_wg<36>, (const void*)k_eig_wg<64>, (const void*)k_sym_eig, (const void*)k_forward<kSweepRegs>, (const void*)k_forward<kSweepDbuf>,
                        (const void*)k_forward<kSweepGlobal>, (const void*)k_backward<kSweepRegs>,
                        (const void*)k_backward<kSweepDbuf>, (const void*)k_backward<kSweepGlobal>};
   for (const void* f : fns) {
@@ -2783,6 +3178,7 @@ hipError_t configure_kernels() {
 size_t eig_scratch_doubles(int n, int nb, int nchunks) {
   const int np = pad_even(n);
   if (np == 64) return (size_t)nb * nchunks * np * EigWgShape<64>::LD;   // V_{j-1} per chunk
+  if (np == kSlotNP) return (size_t)nb * nchunks * eig_slot_scratch_doubles();   // V_{j-1}, X per chunk
   if (np == 36) return 0;   // workgroup kernel: everything in LDS
   if (eig_fits_lds(np)) return 0;
   return (size_t)nb * nchunks * 3 * np * np;   // large-N kernel: V, V_{j-1}, X
@@ -2871,6 +3267,8 @@ size_t eig_launch_lds(int np) {
     case 8:
     case 16:
       return ((size_t)3 * np * np + 2 * np + (np + 1) / 2) * sizeof(double);
+    case kSlotNP:
+      return eig_slot_lds_doubles() * sizeof(double);
     default:
       if (eig_big(np)) return eig_big_lds_doubles(np) * sizeof(double);
       return eig_lds_bytes(np, eig_fits_lds(np));
@@ -2901,6 +3299,11 @@ hipError_t launch_eig(const SysDev& sy, const BasisDev& bs, Work& w, bool store_
 #undef QOC_EIG_WAVE
     default:
       break;
+  }
+  if (w.np == kSlotNP) {
+    hipLaunchKernelGGL(k_eig_slot, dim3(w.nchunks, w.nb), dim3(kSlotTPB), eig_slot_lds_doubles() * sizeof(double),
+                       stream, a);
+    return hipGetLastError();
   }
   if (eig_big(w.np)) {
     hipLaunchKernelGGL(k_eig_big, dim3(w.nchunks, w.nb), dim3(kBigTPB), eig_big_lds_doubles(w.np) * sizeof(double),
@@ -3153,6 +3556,7 @@ QOC_MULTI_KERNEL(km_eig_wg36, kThreads, EigWgShape<36>::WAVES, EigArgs, body_eig
 QOC_MULTI_KERNEL(km_eig_wg64, 512, EigWgShape<64>::WAVES, EigArgs, body_eig_wg<64>)
 QOC_MULTI_KERNEL(km_eig_chunk, kThreads, 1, EigArgs, body_eig_chunk)
 QOC_MULTI_KERNEL(km_eig_big, kBigTPB, 1, EigArgs, body_eig_big)
+QOC_MULTI_KERNEL(km_eig_slot, kSlotTPB, 2, EigArgs, body_eig_slot)
 QOC_MULTI_KERNEL(km_boundary, kThreads, 1, BndArgs, body_boundary)
 QOC_MULTI_KERNEL(km_forward_staged, kThreads, 2, SweepArgs, body_forward<kSweepRegs>)
 QOC_MULTI_KERNEL(km_forward_small, kThreads, 2, SweepArgs, body_forward<kSweepDbuf>)
@@ -3180,6 +3584,7 @@ static const void* multi_fn(MultiKind k) {
     case MultiKind::EigWg64: return (const void*)km_eig_wg64;
     case MultiKind::EigChunk: return (const void*)km_eig_chunk;
     case MultiKind::EigBig: return (const void*)km_eig_big;
+    case MultiKind::EigSlot: return (const void*)km_eig_slot;
     case MultiKind::Boundary: return (const void*)km_boundary;
     case MultiKind::ForwardStaged: return (const void*)km_forward_staged;
     case MultiKind::ForwardSmall: return (const void*)km_forward_small;
@@ -3204,6 +3609,8 @@ int multi_threads(MultiKind k) {
       return EigWgShape<64>::TPB;
     case MultiKind::EigBig:
       return kBigTPB;
+    case MultiKind::EigSlot:
+      return kSlotTPB;
     default:
       return kThreads;
   }
@@ -3216,6 +3623,7 @@ MultiKind eig_kind(int np) {
     case 16: return MultiKind::EigWave16;
     case 36: return MultiKind::EigWg36;
     case 64: return MultiKind::EigWg64;
+    case kSlotNP: return MultiKind::EigSlot;
     default: return eig_big(np) ? MultiKind::EigBig : MultiKind::EigChunk;
   }
 }
@@ -3269,6 +3677,7 @@ hipError_t launch_multi(MultiKind k, const void* d_args, const Item* d_items, in
     QOC_MULTI_CASE(EigWg64, km_eig_wg64, EigArgs)
     QOC_MULTI_CASE(EigChunk, km_eig_chunk, EigArgs)
     QOC_MULTI_CASE(EigBig, km_eig_big, EigArgs)
+    QOC_MULTI_CASE(EigSlot, km_eig_slot, EigArgs)
     QOC_MULTI_CASE(Boundary, km_boundary, BndArgs)
     QOC_MULTI_CASE(ForwardStaged, km_forward_staged, SweepArgs)
     QOC_MULTI_CASE(ForwardSmall, km_forward_small, SweepArgs)
