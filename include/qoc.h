@@ -44,7 +44,7 @@ typedef int32_t qoc_status;
 #define QOC_ERR_INVALID_ARG    -1  /* NULL pointer, bad size, non-finite input, dt <= 0 ...  */
 #define QOC_ERR_NOT_SYMMETRIC  -2  /* |X - X^T| > 1e-12 |X| for H0 or M                      */
 #define QOC_ERR_STATE          -3  /* compute called before system and basis were set          */
-#define QOC_ERR_UNSUPPORTED    -4  /* n above the build limit (128) or P above 4096          */
+#define QOC_ERR_UNSUPPORTED    -4  /* n above the build limit (288) or P above 4096          */
 #define QOC_ERR_NOCONV         -5  /* Jacobi sweep cap reached on some step                   */
 #define QOC_ERR_DEVICE         -6  /* HIP runtime failure (message in qoc_last_error)         */
 #define QOC_ERR_OOM            -7  /* device allocation failed                                 */
@@ -75,7 +75,7 @@ qoc_status qoc_set_system(qoc_problem* p, int32_t n, const double* h0, const dou
 /* Complex Hermitian H0 and M (the random Hermitian dipole matrices of the paper's timing runs,
  * Sec. IV-A): n x n complex, row-major, interleaved (re, im), 2 n^2 doubles each, Hermitian to
  * 1e-12 relative (QOC_ERR_NOT_SYMMETRIC otherwise; the Hermitian part (X + X^H) / 2 is used);
- * psi0, psi_target: n complex.  n <= 64.  The system is evaluated exactly through its real
+ * psi0, psi_target: n complex.  n <= 144.  The system is evaluated exactly through its real
  * embedding E(X) = [[Re X, -Im X], [Im X, Re X]] of size 2n: the states phi(a) = [a; -i a] / sqrt(2)
  * span an invariant subspace on which E(H0 + f M) acts as H0 + f M, and |phi(a) - phi(b)| = |a - b|,
  * so cost, gradient and Hessian are those of the complex system (every eigenvalue of the embedding
@@ -263,7 +263,8 @@ qoc_status qoc_params_from_coords(qoc_problem* p, int32_t count, const double* c
  * weights (later changes to the handles do not affect it) and owns one workspace per problem
  * (every step's eigen-data is stored: about 24 n^2 nt bytes per problem).
  * Errors: QOC_ERR_INVALID_ARG (NULL, count < 1, a handle on another device), QOC_ERR_STATE (a
- * handle without system or basis), QOC_ERR_OOM / QOC_ERR_DEVICE. */
+ * handle without system or basis), QOC_ERR_UNSUPPORTED (a problem with n > 128, the batch's
+ * size limit; single handles go to 288), QOC_ERR_OOM / QOC_ERR_DEVICE. */
 qoc_status qoc_batch_create(int device, int32_t count, qoc_problem* const* problems, qoc_batch** out);
 void       qoc_batch_destroy(qoc_batch* b);   /* NULL-safe */
 /* thetas[i]: P_i doubles (host); costs[i] (1), grads[i] (P_i), hessians[i] (P_i x P_i row-major)

@@ -540,7 +540,7 @@ qoc_status qoc_set_system(qoc_problem* p, int32_t n, const double* h0, const dou
   if (!p) return QOC_ERR_INVALID_ARG;
   if (!h0 || !m || !psi0 || !psi_target) return p->fail(QOC_ERR_INVALID_ARG, "NULL system pointer");
   if (n < 1) return p->fail(QOC_ERR_INVALID_ARG, "n must be >= 1");
-  if (n > kMaxN) return p->fail(QOC_ERR_UNSUPPORTED, "n above the build limit (128)");
+  if (n > kMaxN) return p->fail(QOC_ERR_UNSUPPORTED, "n above the build limit (288)");
   const size_t nn = (size_t)n * n;
   if (!all_finite(h0, nn) || !all_finite(m, nn) || !all_finite(psi0, 2 * (size_t)n) ||
       !all_finite(psi_target, 2 * (size_t)n))
@@ -600,7 +600,7 @@ qoc_status qoc_set_system_hermitian(qoc_problem* p, int32_t n, const double* h0,
   if (!p) return QOC_ERR_INVALID_ARG;
   if (!h0 || !m || !psi0 || !psi_target) return p->fail(QOC_ERR_INVALID_ARG, "NULL system pointer");
   if (n < 1) return p->fail(QOC_ERR_INVALID_ARG, "n must be >= 1");
-  if (2 * n > kMaxN) return p->fail(QOC_ERR_UNSUPPORTED, "complex n above the build limit (64)");
+  if (2 * n > kMaxN) return p->fail(QOC_ERR_UNSUPPORTED, "complex n above the build limit (144)");
   const size_t nn = (size_t)n * n;
   if (!all_finite(h0, 2 * nn) || !all_finite(m, 2 * nn) || !all_finite(psi0, 2 * (size_t)n) ||
       !all_finite(psi_target, 2 * (size_t)n))

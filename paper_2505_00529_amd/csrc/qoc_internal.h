@@ -7,7 +7,8 @@
 
 namespace qoc {
 
-constexpr int kMaxN = 128;       // largest supported system dimension
+constexpr int kMaxN = 288;       // largest supported system dimension (complex 144 embedded)
+constexpr int kBatchMaxN = 128;  // largest dimension of a problem in a batch
 constexpr int kMaxP = 4096;      // largest supported parameter count
 constexpr int kThreads = 256;    // threads per workgroup of every kernel
 constexpr int kMaxPg = 32;       // tangent / second-adjoint columns carried per workgroup

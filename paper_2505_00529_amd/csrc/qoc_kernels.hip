@@ -2025,6 +2025,15 @@ __device__ __forceinline__ void body_forward(const SweepArgs& a, int g, int b) {
       hh[ph_t] = h;
       ph[ph_t] = c_mul(h, h);
     }
+    // rows past the 128 staged in registers (n > 128): read at the commit
+    if (ph_t >= 0) {
+      const double* lj = a.lam + (eb0 + (j - a.eig_j0)) * n;
+      for (int r = ph_t + 128; r < n; r += 128) {
+        const double2 h = phase(0.5 * lj[r], a.dt);
+        hh[r] = h;
+        ph[r] = c_mul(h, h);
+      }
+    }
     if (tid < ncol) fv[tid] = st.pf;
   };
   // on every path through the step, whether or not it loaded or committed st
@@ -2136,10 +2145,12 @@ __device__ __forceinline__ void body_forward(const SweepArgs& a, int g, int b) {
       }
     }
     __syncthreads();
-    if (g == 0 && a.need_y && tid < n) {
-      a.at[vs * n + tid] = cur[tid * w];
-      a.yt[vs * n + tid] = yv[tid];
-      if (a.ah) a.ah[vs * n + tid] = cur[tid * w + 1];
+    if (g == 0 && a.need_y) {
+      for (int r = tid; r < n; r += kThreads) {
+        a.at[vs * n + r] = cur[r * w];
+        a.yt[vs * n + r] = yv[r];
+        if (a.ah) a.ah[vs * n + r] = cur[r * w + 1];
+      }
     }
     {
       ItemWalk it(tid, w);
@@ -2405,6 +2416,20 @@ __device__ __forceinline__ void body_backward(const SweepArgs& a, int g, int b) 
     if (tid < n) {
       yv[tid] = st.py;
       av[tid] = st.pa;
+    }
+    // rows past those staged in registers (n > 128 phases, n > kThreads vectors): read here
+    if (ph_t >= 0) {
+      const double* lj = a.lam + (eb0 + (j - a.eig_j0)) * n;
+      for (int r = ph_t + 128; r < n; r += 128) {
+        const double2 h = c_conj(phase(0.5 * lj[r], a.dt));
+        hh[r] = h;
+        ph[r] = c_mul(h, h);
+      }
+    }
+    for (int r = tid + kThreads; r < n; r += kThreads) {
+      const size_t vsj = vb0 + j;
+      yv[r] = a.yt[vsj * n + r];
+      av[r] = a.hvp ? a.ah[vsj * n + r] : make_double2(0.0, 0.0);
     }
     if (tid < ncol) fv[tid] = st.pf;
   };
@@ -2688,8 +2713,8 @@ __device__ double sterm_pairs_wave(const StermArgs& a, size_t es, size_t vs, int
 // x_q, mu_q and a_q are read at wave-uniform addresses.
 template <int NT>
 __device__ __forceinline__ double2 sterm_moments(const double* Mt, const double* lam, const double2* mu,
-                                                 const double2* at, const double2* coef, double m0, double x0,
-                                                 double x1, int lane, int n) {
+                                                 const double2* at, const double2* coef, double m0, int lane,
+                                                 int n) {
   double2 contrib = make_double2(0.0, 0.0);
   for (int rb = 0; rb * 64 < n; ++rb) {
     const int p = lane + 64 * rb;
@@ -2719,7 +2744,7 @@ __device__ __forceinline__ double2 sterm_moments(const double* Mt, const double*
       }
     }
     if (p < n) {
-      const double xp = rb ? x1 : x0;
+      const double xp = lam[p] - m0;
 #pragma unroll
       for (int m = 0; m < NT; ++m) {
         double2 R = make_double2(0.0, 0.0);
@@ -2749,23 +2774,11 @@ __device__ __forceinline__ void body_sterm(const StermArgs& a, int bx, int nblk)
     const size_t es = (size_t)tb * a.eig_stride + (tj - a.eig_j0);   // eigen-data index
     const size_t vs = (size_t)tb * a.nt + tj;                         // per-step vector index
     const double* lam = a.lam + es * n;
-    // per-lane copies of x, mu, a for rows lane and lane + 64
-    double lv[2];
-    double2 mv[2], av[2];
     double lo = 1e300, hi = -1e300;
-#pragma unroll
-    for (int e = 0; e < 2; ++e) {
-      const int p = lane + 64 * e;
-      lv[e] = 0.0;
-      mv[e] = make_double2(0.0, 0.0);
-      av[e] = make_double2(0.0, 0.0);
-      if (p < n) {
-        lv[e] = lam[p];
-        mv[e] = a.mu[vs * n + p];
-        av[e] = a.at[vs * n + p];
-        lo = fmin(lo, lv[e]);
-        hi = fmax(hi, lv[e]);
-      }
+    for (int p = lane; p < n; p += 64) {
+      const double l = lam[p];
+      lo = fmin(lo, l);
+      hi = fmax(hi, l);
     }
     lo = wave_min_lds(lo);
     hi = wave_max_lds(hi);
@@ -2804,14 +2817,13 @@ __device__ __forceinline__ void body_sterm(const StermArgs& a, int bx, int nblk)
           mag *= a.dt / (double)(k + 3);
         }
       }
-      const double x0 = lv[0] - m0, x1 = lv[1] - m0;
       const double* Mt = a.mt + es * nn;
       const double2* mu = a.mu + vs * n;
       const double2* at = a.at + vs * n;
       double2 contrib = make_double2(0.0, 0.0);
       switch (nmax) {   // wave-uniform
 #define QOC_STERM_CASE(T) \
-  case T - 1: contrib = sterm_moments<T>(Mt, lam, mu, at, coef, m0, x0, x1, lane, n); break;
+  case T - 1: contrib = sterm_moments<T>(Mt, lam, mu, at, coef, m0, lane, n); break;
         QOC_STERM_CASE(1) QOC_STERM_CASE(2) QOC_STERM_CASE(3) QOC_STERM_CASE(4) QOC_STERM_CASE(5)
         QOC_STERM_CASE(6) QOC_STERM_CASE(7) QOC_STERM_CASE(8) QOC_STERM_CASE(9) QOC_STERM_CASE(10)
         QOC_STERM_CASE(11) QOC_STERM_CASE(12) QOC_STERM_CASE(13) QOC_STERM_CASE(14) QOC_STERM_CASE(15)
@@ -3150,8 +3162,9 @@ static size_t eig_lds_bytes(int np, bool lds_mats) {
 }
 
 static bool eig_fits_lds(int np) { return eig_lds_bytes(np, true) <= 160 * 1024; }
-// sizes served by the large-N kernel (its LDS holds A alone)
-static bool eig_big(int np) { return np != 36 && np != 64 && !eig_fits_lds(np); }
+// sizes served by the large-N kernel (its LDS holds A alone); above kSlotNP A does not fit and
+// the generic kernel keeps its four matrices in global memory
+static bool eig_big(int np) { return np != 36 && np != 64 && np < kSlotNP && !eig_fits_lds(np); }
 
 static bool sweep_stage(int n) { return n * n <= kPrefetch * kThreads; }
 // LDS double buffer with 16-byte staging (even n)
@@ -3181,6 +3194,7 @@ size_t eig_scratch_doubles(int n, int nb, int nchunks) {
   if (np == kSlotNP) return (size_t)nb * nchunks * eig_slot_scratch_doubles();   // V_{j-1}, X per chunk
   if (np == 36) return 0;   // workgroup kernel: everything in LDS
   if (eig_fits_lds(np)) return 0;
+  if (np > kSlotNP) return (size_t)nb * nchunks * 4 * np * np;   // generic kernel: A, V, V_{j-1}, X
   return (size_t)nb * nchunks * 3 * np * np;   // large-N kernel: V, V_{j-1}, X
 }
 
@@ -3365,6 +3379,8 @@ SweepArgs sweep_args(const SysDev& sy, const BasisDev& bs, const Work& w, Mode m
     a.f_bstride = 0;
   }
   a.pg = mode == Mode::Hess ? (pg > 0 ? std::min(pg, w.P) : choose_pg(w.P, w.nb)) : 1;
+  // at large n the carried columns bound the group width: [n][1 + pg] twice must fit in LDS
+  while (a.pg > 1 && sweep_lds_bytes(w.n, a.pg) > (size_t)160 * 1024) --a.pg;
   a.ngroups = a.P > 0 ? (a.P + a.pg - 1) / a.pg : 1;
   a.vfirst = w.vfirst;
   a.nchunks = w.nchunks;

@@ -114,3 +114,15 @@ def test_batch_copies_problem_state():
     c1, _, _ = b.hess(th, with_hessian=False)
     assert np.array_equal(c0, c1)
     b.close()
+
+
+def test_batch_rejects_problems_above_its_size_limit():
+    """Single problems go up to n = 288; a batch takes n <= 128 and says so."""
+    ws = _small_batch(2, seed=35)
+    big = inputs.make_workload("molecule", n=150, nt=24, dt=0.02, k=2, seed=36)
+    probs = [qoc.problem_from_workload(w) for w in ws] + [qoc.problem_from_workload(big)]
+    with pytest.raises(qoc.QocError) as ei:
+        qoc.Batch(probs)
+    assert ei.value.status == qoc.QOC_ERR_UNSUPPORTED
+    for p in probs:
+        p.close()

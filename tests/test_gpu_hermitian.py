@@ -2,8 +2,9 @@
 complex matrices directly).  Tolerance 1e-10 normwise relative, as for real systems.
 
 The embedding doubles every eigenvalue, so the eigen kernels see exactly degenerate spectra:
-complex n = 4, 16, 32, 64 run the embedded sizes 8, 32, 64, 128 (one-wave, workgroup NP = 36 and
-64, and the generic kernel)."""
+complex n = 4, 16, 32, 64, 144 run the embedded sizes 8, 32, 64, 128, 288 (one-wave, workgroup
+NP = 36 and 64, the slot-order kernel at 128, and the generic kernel with its matrices in global
+memory at 288, where the sweeps also carry more rows than a workgroup has threads)."""
 import sys
 
 import numpy as np
@@ -36,7 +37,7 @@ def _problem(s, nt, dt, k):
     return p
 
 
-@pytest.mark.parametrize("n", [4, 16, 32, 64])
+@pytest.mark.parametrize("n", [4, 16, 32, 64, 144])
 def test_hermitian_against_oracle(n):
     nt, dt, k = 48, 0.05, 2
     s = inputs.hermitian_system(n)
@@ -87,9 +88,9 @@ def test_hermitian_rejects_non_hermitian_and_large_n():
     e0 = np.eye(4)[0]
     with pytest.raises(qoc.QocError):
         p.set_system_hermitian(h, a, e0, e0)
-    big = np.eye(65, dtype=complex)
+    big = np.eye(145, dtype=complex)
     with pytest.raises(qoc.QocError):
-        p.set_system_hermitian(big, big, np.eye(65)[0], np.eye(65)[1])
+        p.set_system_hermitian(big, big, np.eye(145)[0], np.eye(145)[1])
     p.close()
 
 

@@ -362,10 +362,11 @@ def test_sweep_cap_on_device_entry_points_and_autograd():
     p.close()
 
 
-@pytest.mark.parametrize("n", [72, 100, 127, 128])
+@pytest.mark.parametrize("n", [72, 100, 127, 128, 200])
 def test_large_n_eigen_kernel_against_oracle(n):
-    """Sizes past one LDS tile (A in LDS, V in global memory): even, odd (padded) and the
-    largest n, over five eigen chunks of 8 steps, against the oracle."""
+    """Sizes past one LDS tile: A in LDS and V in global memory (72, 100, odd 127), the slot-order
+    kernel (128), all matrices in global memory with sweeps of more rows than the phase waves
+    (200); five eigen chunks of 8 steps, against the oracle."""
     nt, dt, k = 40, 0.02, 2
     w = inputs.make_workload("molecule", n=n, nt=nt, dt=dt, k=k, seed=40 + n)
     s = w.system
