@@ -5,8 +5,9 @@ Protocol: maximal model f_j = theta_j (P = J), J = 2^kappa for kappa = 2..10, th
 afresh for every trial, alpha = e_0 and beta = e_{N-1}; both evaluations run on the same theta, in
 turn, through the host-pointer C ABI (inputs on the host, results back on the host), after one
 untimed call per (N, J) that sizes the workspaces.  Systems: N = 4 and 16 stand in for the paper's
-full-CI molecules (the real transfer systems of the optimiser comparison); N = 64 uses a random
-diagonal H0 and a random complex Hermitian M, evaluated through the real embedding of size 128.
+full-CI molecules (the real transfer systems of the optimiser comparison); N = 64 and 144 use a
+random diagonal H0 and a random complex Hermitian M, evaluated through the real embedding of size
+128 and 288.
 The time step is 0.1 and the weights 1 and rho = 1e6, as in the optimiser comparison (the paper
 states neither for its timing runs; they do not change the work).  With theta ~ N(0, I) consecutive
 steps are far apart, so warm-started eigen chains save little: by default every step is its own
@@ -15,7 +16,8 @@ chain (--chunk 1), decomposed from scratch and in parallel with the others.
 Reported per (N, J): mean and standard deviation of both wall times over the trials and their
 ratio; per N, the OLS slopes of log2(mean time) against log2(J) for both algorithms.
 
-    python -m paper_2505_00529_amd.jscaling [--n 4 16 64] [--trials 1000] [--trials-large 100] [--kmax 10]
+    python -m paper_2505_00529_amd.jscaling [--n 4 16 64 144] [--trials 1000] [--trials-large 100]
+                                            [--trials-xl 10] [--kmax 10]
 """
 from __future__ import annotations
 
@@ -91,10 +93,12 @@ def run(n: int, kmin: int, kmax: int, trials: int, seed: int, chunk: int = 0) ->
 
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
-    ap.add_argument("--n", type=int, nargs="+", default=[4, 16, 64])
+    ap.add_argument("--n", type=int, nargs="+", default=[4, 16, 64, 144])
     ap.add_argument("--trials", type=int, default=1000)
     ap.add_argument("--trials-large", type=int, default=100,
-                    help="trials per J for the complex N = 64 system (its evaluations take 50-500 ms)")
+                    help="trials per J for the complex N = 64 system (its evaluations take 5-220 ms)")
+    ap.add_argument("--trials-xl", type=int, default=10,
+                    help="trials per J for complex N > 64 (N = 144: 0.27-4 s per evaluation)")
     ap.add_argument("--kmin", type=int, default=2)
     ap.add_argument("--kmax", type=int, default=10)
     ap.add_argument("--seed", type=int, default=14)
@@ -103,7 +107,10 @@ def main(argv=None) -> int:
                          "scratch and in parallel, the better choice when the steps are cold anyway)")
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
-    res = [run(n, a.kmin, a.kmax, a.trials if n < 64 else a.trials_large, a.seed, a.chunk) for n in a.n]
+    def trials(n):
+        return a.trials if n < 64 else (a.trials_large if n == 64 else a.trials_xl)
+
+    res = [run(n, a.kmin, a.kmax, trials(n), a.seed, a.chunk) for n in a.n]
     line = json.dumps({"protocol": "J scaling of one evaluation, maximal model", "dt": DT, "rho": RHO,
                        "systems": res})
     print(line, flush=True)
