@@ -8,7 +8,8 @@ What it computes (paper, Sec. II and Sec. III-A/B):
 * the unwound cost (eq. costunwind, with eq. discretecost's field-energy term)
       C(theta) = (gamma/2) sum_j f_j^2 + (rho/2) || U_{J-1} ... U_1 U_0 alpha - beta ||^2,
   with U_j = exp(Z_j), Z_j = -i dt (H0 + f_j M) (eq. Zdef, eq. discTDSE), f_j = (B theta)_j
-  the control model sampled at t_j = j dt (eq. eom), one control direction;
+  the control model sampled at t_j = j dt (eq. eom), one control direction (the functions
+  ending in _multi at the end of the module take K directions, H0 + sum_k f^k M_k);
 * its gradient and Hessian, which the paper's adjoint methods reproduce exactly
   (eq. gradagree for the gradient; the Hessian is defined as the theta-Hessian of
   the unwound cost at the start of Sec. III-B);
@@ -53,6 +54,13 @@ __all__ = [
     "cost_grad_hess",
     "hvp",
     "trajectory_with_tangents",
+    "controls_multi",
+    "step_propagators_multi",
+    "trajectory_with_tangents_multi",
+    "cost_multi",
+    "cost_grad_multi",
+    "cost_grad_hess_multi",
+    "hvp_multi",
 ]
 
 _TAYLOR_TOL = 2.0 ** -60
@@ -245,3 +253,142 @@ def hvp(h0, m, psi0, psi_target, basis, dt, theta, v, gamma, rho):
     r = a - psi_target
     return gamma * (basis.T @ (basis @ v)) + rho * np.real(a1.conj().T @ av) \
         + rho * np.real(r.conj() @ a2v)
+
+
+# ------------------------------------------------------------- several control directions
+#
+# Sec. II with K control directions (eq. matrixTDSE: H0 + sum_k f^k(t) M_k, K <= 3 in the paper):
+# Z_j = -i dt (H0 + sum_k f^k_j M_k), f^k_j = (B_k theta)_j with one J x P model matrix per
+# direction (a model with a block of theta per direction has zero columns elsewhere).  The
+# theta-derivatives of the unwound cost follow by the chain rule through every direction (the
+# sums over k in the gradient and over k, n in the Hessian, eq. d2Ldf2).  The per-step
+# derivatives come from the same block exponential: U'_k = dU/df^k is its first block for
+# E = -i dt M_k, and the mixed second derivative U''_kn, a symmetric bilinear form in the
+# directions, follows by polarisation from second derivatives along single directions:
+#   U''_kn = (U''[M_k + M_n] - U''[M_k] - U''[M_n]) / 2,   U''[D] = d^2/ds^2 exp(X + s E_D).
+
+
+def controls_multi(bases: np.ndarray, theta: np.ndarray) -> np.ndarray:
+    """f^k_j = sum_l B_k[j, l] theta_l for every direction k: K x J."""
+    return np.einsum("kjl,l->kj", np.asarray(bases, dtype=np.float64), np.asarray(theta, dtype=np.float64))
+
+
+def step_propagators_multi(h0, ms, fvec, dt):
+    """(U, [U'_k], [[U''_kn]]) of U = exp(-i dt (H0 + sum_k f_k M_k))."""
+    K = len(ms)
+    x = -1j * dt * (np.asarray(h0) + sum(fvec[k] * ms[k] for k in range(K)))
+    first, second_single = [], []
+    u = None
+    for k in range(K):
+        f0, f1, f2 = exp_block3(x, -1j * dt * ms[k])
+        u = f0
+        first.append(f1)
+        second_single.append(2.0 * f2)
+    second = [[None] * K for _ in range(K)]
+    for k in range(K):
+        second[k][k] = second_single[k]
+        for n in range(k + 1, K):
+            both = 2.0 * exp_block3(x, -1j * dt * (ms[k] + ms[n]))[2]
+            mixed = 0.5 * (both - second_single[k] - second_single[n])
+            second[k][n] = mixed
+            second[n][k] = mixed
+    return u, first, second
+
+
+def trajectory_with_tangents_multi(h0, ms, psi0, bases, dt, theta, order=1, direction=None):
+    """Forward sweep with K directions; returns as trajectory_with_tangents.
+
+      a'_{j+1}  = U a'_j + sum_k U'_k a_j b_kj^T
+      a''_{j+1} = U a''_j + sum_k U'_k (a'_j b_kj^T + b_kj a'_j^T) + sum_kn U''_kn a_j b_kj b_nj^T
+    with b_kj = B_k[j, :].
+    """
+    bases = np.asarray(bases, dtype=np.float64)
+    K, nt, p = bases.shape
+    n = h0.shape[0]
+    f = controls_multi(bases, theta)
+    a = np.asarray(psi0, dtype=np.complex128).copy()
+    a1 = np.zeros((n, p), dtype=np.complex128)
+    if direction is not None:
+        u = np.einsum("kjl,l->kj", bases, np.asarray(direction, dtype=np.float64))
+        av = np.zeros(n, dtype=np.complex128)
+        a2 = np.zeros((n, p), dtype=np.complex128)
+    elif order >= 2:
+        a2 = np.zeros((n, p, p), dtype=np.complex128)
+    for j in range(nt):
+        uj, u1, u2 = step_propagators_multi(h0, ms, f[:, j], dt)
+        b = bases[:, j, :]
+        if order >= 2 and direction is None:
+            a2_next = (uj @ a2.reshape(n, p * p)).reshape(n, p, p)
+            for k in range(K):
+                w = u1[k] @ a1
+                a2_next += w[:, :, None] * b[k][None, None, :] + w[:, None, :] * b[k][None, :, None]
+                for m in range(K):
+                    a2_next += (u2[k][m] @ a)[:, None, None] * np.outer(b[k], b[m])[None, :, :]
+            a2 = a2_next
+        elif direction is not None:
+            a2_next = uj @ a2
+            av_next = uj @ av
+            for k in range(K):
+                a2_next += (u1[k] @ a1) * u[k, j] + np.outer(u1[k] @ av, b[k])
+                for m in range(K):
+                    a2_next += np.outer(u2[k][m] @ a, b[k]) * u[m, j]
+                av_next += (u1[k] @ a) * u[k, j]
+            a2, av = a2_next, av_next
+        a1_next = uj @ a1
+        for k in range(K):
+            a1_next += np.outer(u1[k] @ a, b[k])
+        a = uj @ a
+        a1 = a1_next
+    if direction is not None:
+        return a, a1, av, a2
+    if order >= 2:
+        return a, a1, a2
+    return a, a1
+
+
+def _field_terms(bases, f):
+    """sum_k B_k^T f^k and sum_k B_k^T B_k."""
+    return np.einsum("kjl,kj->l", bases, f), np.einsum("kjl,kjm->lm", bases, bases)
+
+
+def cost_multi(h0, ms, psi0, psi_target, bases, dt, theta, gamma, rho) -> float:
+    """Unwound cost with K directions; the field energy sums over directions."""
+    bases = np.asarray(bases, dtype=np.float64)
+    f = controls_multi(bases, theta)
+    a, _ = trajectory_with_tangents_multi(h0, ms, psi0, bases, dt, theta, order=1)
+    r = a - psi_target
+    return 0.5 * gamma * float((f * f).sum()) + 0.5 * rho * float(np.vdot(r, r).real)
+
+
+def cost_grad_multi(h0, ms, psi0, psi_target, bases, dt, theta, gamma, rho):
+    """(C, dC/dtheta) with K directions."""
+    bases = np.asarray(bases, dtype=np.float64)
+    f = controls_multi(bases, theta)
+    a, a1 = trajectory_with_tangents_multi(h0, ms, psi0, bases, dt, theta, order=1)
+    r = a - psi_target
+    c = 0.5 * gamma * float((f * f).sum()) + 0.5 * rho * float(np.vdot(r, r).real)
+    bf, _ = _field_terms(bases, f)
+    return c, gamma * bf + rho * np.real(r.conj() @ a1)
+
+
+def cost_grad_hess_multi(h0, ms, psi0, psi_target, bases, dt, theta, gamma, rho):
+    """(C, g, H) with K directions: H = gamma sum_k B_k^T B_k + rho Re(A'^H A' + r^H A'')."""
+    bases = np.asarray(bases, dtype=np.float64)
+    f = controls_multi(bases, theta)
+    a, a1, a2 = trajectory_with_tangents_multi(h0, ms, psi0, bases, dt, theta, order=2)
+    r = a - psi_target
+    c = 0.5 * gamma * float((f * f).sum()) + 0.5 * rho * float(np.vdot(r, r).real)
+    bf, bb = _field_terms(bases, f)
+    g = gamma * bf + rho * np.real(r.conj() @ a1)
+    h = gamma * bb + rho * np.real(a1.conj().T @ a1) + rho * np.real(np.einsum("n,nlm->lm", r.conj(), a2))
+    return c, g, h
+
+
+def hvp_multi(h0, ms, psi0, psi_target, bases, dt, theta, v, gamma, rho):
+    """H v with K directions by directional second-order forward mode."""
+    bases = np.asarray(bases, dtype=np.float64)
+    v = np.asarray(v, dtype=np.float64)
+    a, a1, av, a2v = trajectory_with_tangents_multi(h0, ms, psi0, bases, dt, theta, order=2, direction=v)
+    r = a - psi_target
+    _, bb = _field_terms(bases, np.zeros(bases.shape[:2]))
+    return gamma * (bb @ v) + rho * np.real(a1.conj().T @ av) + rho * np.real(r.conj() @ a2v)
