@@ -84,12 +84,26 @@ qoc_status qoc_set_system(qoc_problem* p, int32_t n, const double* h0, const dou
  * returns QOC_ERR_UNSUPPORTED for such a system. */
 qoc_status qoc_set_system_hermitian(qoc_problem* p, int32_t n, const double* h0, const double* m,
                                     const double* psi0, const double* psi_target);
+/* Several control directions (Sec. II, eq. matrixTDSE: H0 + sum_k f^k(t) M_k; the paper has
+ * K = 3, the x, y, z dipole components): m holds ndir stacked n x n real symmetric matrices
+ * (ndir x n x n doubles, ndir in 1..3); h0, psi0, psi_target as for qoc_set_system, which is this
+ * call with ndir = 1.  The control model then has one nt x P matrix per direction, f^k = B_k theta
+ * (qoc_set_control_basis: a dense b is ndir x nt x P; the Fourier and identity models give each
+ * direction its own block of parameters, P = ndir x the one-direction count), and cost, gradient,
+ * Hessian (with the mixed second derivatives of eq. d2Ldf2 between directions) and HVP come from
+ * every evaluation entry point.  Changing ndir clears the control basis (set it again).  With
+ * ndir > 1, checkpointing, batches, qoc_hess_many_dev_noalloc, qoc_eval_controls and
+ * qoc_step_propagators return QOC_ERR_UNSUPPORTED.  Errors as qoc_set_system, and
+ * QOC_ERR_INVALID_ARG for ndir outside 1..3. */
+qoc_status qoc_set_system_multi(qoc_problem* p, int32_t n, int32_t ndir, const double* h0, const double* m,
+                                const double* psi0, const double* psi_target);
 /* Replace only the target state (2n doubles); cheap, keeps all other settings. */
 qoc_status qoc_set_target(qoc_problem* p, const double* psi_target);
 
 /* Control model f(j dt; theta) (Sec. II) on a grid of nt steps of size dt (T = nt dt).
  * FOURIER: k_or_p = K >= 1, b = NULL.  IDENTITY: k_or_p ignored, b = NULL.
- * DENSE: k_or_p = P >= 1, b = nt x P row-major (copied). */
+ * DENSE: k_or_p = P >= 1, b = nt x P row-major (copied; ndir x nt x P with several control
+ * directions, see qoc_set_system_multi). */
 qoc_status qoc_set_control_basis(qoc_problem* p, qoc_basis_kind kind, int32_t nt, double dt,
                                  int32_t k_or_p, const double* b);
 /* Weights of eq. discretecost: gamma on the field energy (paper: 1), rho on the terminal

@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqoc.so")
-SOURCES = ["qoc_kernels.hip", "qoc_api.hip", "qoc_solver.hip", "qoc_batch.hip", "qoc_mlp.hip"]
+SOURCES = ["qoc_kernels.hip", "qoc_multi.hip", "qoc_api.hip", "qoc_solver.hip", "qoc_batch.hip", "qoc_mlp.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -86,6 +86,10 @@ void qoc_problem::release_work() {
   dfree(work_mem, work_bytes);
   work_mem = nullptr;
   work_bytes = 0;
+  dfree(mc_mem, mc_bytes);
+  mc_mem = nullptr;
+  mc_bytes = 0;
+  mc_key_nb = 0;
   w = Work();
   work_key_nb = 0;
   work_key_seg = -1;
@@ -95,7 +99,7 @@ qoc_problem::~qoc_problem() {
   if (device >= 0) (void)hipSetDevice(device);
   release_work();
   dfree(d_h0, sizeof(double) * n * n);
-  dfree(d_m, sizeof(double) * n * n);
+  dfree(d_m, sizeof(double) * nctl * n * n);
   dfree(d_psi0, sizeof(double) * 2 * n);
   dfree(d_psit, sizeof(double) * 2 * n);
   dfree(d_B, b_bytes);
@@ -229,6 +233,11 @@ qoc_status qoc_problem::ready() {
 // recomputes each segment's eigen-data (same chunking, so bit-identical) newest first.
 qoc_status qoc_problem::enqueue(Mode mode, int nb, const double* d_theta, const double* d_v, double* d_cost,
                                 double* d_grad, double* d_out, const double* d_targets) {
+  if (nctl > 1) {
+    if (ckpt > 0 && ckpt < nt)
+      return fail(QOC_ERR_UNSUPPORTED, "checkpointing is not available with several control directions");
+    return enqueue_multi(mode, nb, d_theta, d_v, d_cost, d_grad, d_out, d_targets);
+  }
   const bool ck = ckpt > 0 && ckpt < nt && mode != Mode::Hess;
   qoc_status st = ensure_work(nb, ck ? ckpt : 0);
   if (st != QOC_OK) return st;
@@ -535,17 +544,21 @@ qoc_status qoc_set_stream(qoc_problem* p, void* hip_stream) {
   return QOC_OK;
 }
 
-qoc_status qoc_set_system(qoc_problem* p, int32_t n, const double* h0, const double* m, const double* psi0,
-                          const double* psi_target) {
+// Real symmetric system with K control operators (m: K stacked n x n matrices).  A change of K
+// invalidates the control basis, whose stacked layout depends on it.
+static qoc_status set_real_system(qoc_problem* p, int32_t n, int32_t K, const double* h0, const double* m,
+                                  const double* psi0, const double* psi_target) {
   if (!p) return QOC_ERR_INVALID_ARG;
   if (!h0 || !m || !psi0 || !psi_target) return p->fail(QOC_ERR_INVALID_ARG, "NULL system pointer");
   if (n < 1) return p->fail(QOC_ERR_INVALID_ARG, "n must be >= 1");
+  if (K < 1 || K > 3) return p->fail(QOC_ERR_INVALID_ARG, "the number of control directions must be 1, 2 or 3");
   if (n > kMaxN) return p->fail(QOC_ERR_UNSUPPORTED, "n above the build limit (288)");
   const size_t nn = (size_t)n * n;
-  if (!all_finite(h0, nn) || !all_finite(m, nn) || !all_finite(psi0, 2 * (size_t)n) ||
+  if (!all_finite(h0, nn) || !all_finite(m, K * nn) || !all_finite(psi0, 2 * (size_t)n) ||
       !all_finite(psi_target, 2 * (size_t)n))
     return p->fail(QOC_ERR_INVALID_ARG, "non-finite system entry");
-  for (const double* x : {h0, m}) {
+  for (int which = 0; which <= K; ++which) {
+    const double* x = which == 0 ? h0 : m + (size_t)(which - 1) * nn;
     double nrm = 0.0, asym = 0.0;
     for (size_t i = 0; i < nn; ++i) nrm += x[i] * x[i];
     for (int i = 0; i < n; ++i)
@@ -554,32 +567,35 @@ qoc_status qoc_set_system(qoc_problem* p, int32_t n, const double* h0, const dou
         asym += 2 * d * d;
       }
     if (std::sqrt(asym) > 1e-12 * std::sqrt(nrm))
-      return p->fail(QOC_ERR_NOT_SYMMETRIC, x == h0 ? "H0 is not symmetric" : "M is not symmetric");
+      return p->fail(QOC_ERR_NOT_SYMMETRIC, which == 0 ? "H0 is not symmetric" : "M is not symmetric");
   }
   hipError_t e = hipSetDevice(p->device);
   if (e != hipSuccess) return p->hip_fail(e, "hipSetDevice");
   p->release_work();
   p->dfree(p->d_h0, sizeof(double) * p->n * p->n);
-  p->dfree(p->d_m, sizeof(double) * p->n * p->n);
+  p->dfree(p->d_m, sizeof(double) * p->nctl * p->n * p->n);
   p->dfree(p->d_psi0, sizeof(double) * 2 * p->n);
   p->dfree(p->d_psit, sizeof(double) * 2 * p->n);
   p->d_h0 = p->d_m = p->d_psi0 = p->d_psit = nullptr;
   p->has_system = false;
+  if (K != p->nctl && p->has_basis) p->has_basis = false;
+  p->nctl = K;
   qoc_status st;
   if ((st = p->dmalloc((void**)&p->d_h0, sizeof(double) * nn, "H0")) != QOC_OK) return st;
-  if ((st = p->dmalloc((void**)&p->d_m, sizeof(double) * nn, "M")) != QOC_OK) return st;
+  if ((st = p->dmalloc((void**)&p->d_m, sizeof(double) * K * nn, "M")) != QOC_OK) return st;
   if ((st = p->dmalloc((void**)&p->d_psi0, sizeof(double) * 2 * n, "psi0")) != QOC_OK) return st;
   if ((st = p->dmalloc((void**)&p->d_psit, sizeof(double) * 2 * n, "psi_target")) != QOC_OK) return st;
   p->n = n;
   // symmetrise exactly (the check above allows 1e-12 relative asymmetry)
-  std::vector<double> hs(nn), ms(nn);
+  std::vector<double> hs(nn), ms(K * nn);
   for (int i = 0; i < n; ++i)
     for (int k = 0; k < n; ++k) {
       hs[i * n + k] = 0.5 * (h0[i * n + k] + h0[k * n + i]);
-      ms[i * n + k] = 0.5 * (m[i * n + k] + m[k * n + i]);
+      for (int c = 0; c < K; ++c)
+        ms[c * nn + i * n + k] = 0.5 * (m[c * nn + i * n + k] + m[c * nn + k * n + i]);
     }
   e = hipMemcpyAsync(p->d_h0, hs.data(), sizeof(double) * nn, hipMemcpyHostToDevice, p->stream);
-  if (e == hipSuccess) e = hipMemcpyAsync(p->d_m, ms.data(), sizeof(double) * nn, hipMemcpyHostToDevice, p->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(p->d_m, ms.data(), sizeof(double) * K * nn, hipMemcpyHostToDevice, p->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(p->d_psi0, psi0, sizeof(double) * 2 * n, hipMemcpyHostToDevice, p->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(p->d_psit, psi_target, sizeof(double) * 2 * n, hipMemcpyHostToDevice, p->stream);
@@ -593,6 +609,16 @@ qoc_status qoc_set_system(qoc_problem* p, int32_t n, const double* h0, const dou
   p->embed = false;
   p->n_user = n;
   return QOC_OK;
+}
+
+qoc_status qoc_set_system(qoc_problem* p, int32_t n, const double* h0, const double* m, const double* psi0,
+                          const double* psi_target) {
+  return set_real_system(p, n, 1, h0, m, psi0, psi_target);
+}
+
+qoc_status qoc_set_system_multi(qoc_problem* p, int32_t n, int32_t ndir, const double* h0, const double* m,
+                                const double* psi0, const double* psi_target) {
+  return set_real_system(p, n, ndir, h0, m, psi0, psi_target);
 }
 
 qoc_status qoc_set_system_hermitian(qoc_problem* p, int32_t n, const double* h0, const double* m, const double* psi0,
@@ -677,11 +703,16 @@ qoc_status qoc_set_control_basis(qoc_problem* p, qoc_basis_kind kind, int32_t nt
       if (k_or_p < 1) return p->fail(QOC_ERR_INVALID_ARG, "dense basis needs P >= 1");
       if (!b) return p->fail(QOC_ERR_INVALID_ARG, "dense basis needs b");
       P = k_or_p;
-      if (!all_finite(b, (size_t)nt * P)) return p->fail(QOC_ERR_INVALID_ARG, "non-finite basis entry");
+      if (!all_finite(b, (size_t)p->nctl * nt * P)) return p->fail(QOC_ERR_INVALID_ARG, "non-finite basis entry");
       break;
     default:
       return p->fail(QOC_ERR_INVALID_ARG, "unknown basis kind");
   }
+  // several directions: the Fourier and identity models get one block of parameters per
+  // direction (theta = [theta^1; ...; theta^K]); a dense model gives every direction its own
+  // nt x P matrix
+  const int K = p->nctl, P0 = P;
+  if (kind != QOC_BASIS_DENSE) P = K * P0;
   if (P > kMaxP) return p->fail(QOC_ERR_UNSUPPORTED, "P above the build limit (4096)");
   hipError_t e = hipSetDevice(p->device);
   if (e != hipSuccess) return p->hip_fail(e, "hipSetDevice");
@@ -690,13 +721,28 @@ qoc_status qoc_set_control_basis(qoc_problem* p, qoc_basis_kind kind, int32_t nt
   p->d_B = nullptr;
   p->b_bytes = 0;
   p->has_basis = false;
-  const size_t bytes = sizeof(double) * (size_t)nt * P;
+  const size_t bytes = sizeof(double) * (size_t)K * nt * P;
   qoc_status st = p->dmalloc((void**)&p->d_B, bytes, "basis");
   if (st != QOC_OK) return st;
   p->b_bytes = bytes;
-  if (kind == QOC_BASIS_FOURIER) e = launch_fourier_basis(p->d_B, nt, k_or_p, p->stream);
-  else if (kind == QOC_BASIS_IDENTITY) e = launch_identity_basis(p->d_B, nt, p->stream);
-  else e = hipMemcpyAsync(p->d_B, b, bytes, hipMemcpyHostToDevice, p->stream);
+  if (kind == QOC_BASIS_DENSE) {
+    e = hipMemcpyAsync(p->d_B, b, bytes, hipMemcpyHostToDevice, p->stream);
+  } else {
+    // the single-direction model, then (K > 1) copied into the diagonal blocks of the stack
+    double* b0 = p->d_B;
+    if (K > 1) {
+      st = p->dmalloc((void**)&b0, sizeof(double) * (size_t)nt * P0, "basis staging");
+      if (st != QOC_OK) return st;
+    }
+    if (kind == QOC_BASIS_FOURIER) e = launch_fourier_basis(b0, nt, k_or_p, p->stream);
+    else e = launch_identity_basis(b0, nt, p->stream);
+    if (e == hipSuccess && K > 1) e = hipMemsetAsync(p->d_B, 0, bytes, p->stream);
+    for (int c = 0; c < K && K > 1 && e == hipSuccess; ++c)
+      e = hipMemcpy2DAsync(p->d_B + ((size_t)c * nt * P + (size_t)c * P0), sizeof(double) * P, b0,
+                           sizeof(double) * P0, sizeof(double) * P0, nt, hipMemcpyDeviceToDevice, p->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+    if (K > 1) p->dfree(b0, sizeof(double) * (size_t)nt * P0);
+  }
   if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
   if (e != hipSuccess) return p->hip_fail(e, "basis setup");
   p->nt = nt;
@@ -804,6 +850,7 @@ qoc_status qoc_hess_many_dev_noalloc(qoc_problem* p, int32_t count, const double
   qoc_status st = p->ready();
   if (st != QOC_OK) return st;
   if (count < 1 || !thetas) return p->fail(QOC_ERR_INVALID_ARG, "theta must be non-NULL and count >= 1");
+  if (p->nctl > 1) return p->fail(QOC_ERR_UNSUPPORTED, "the static workspace serves one control direction");
   double* base = p->device < 64 ? g_scratch_dev[p->device] : nullptr;
   if (!base) return p->fail(QOC_ERR_STATE, "no static workspace on this device");
   Work sw;
@@ -839,6 +886,7 @@ qoc_status qoc_step_propagators(qoc_problem* p, const double* theta, int32_t j, 
   if (!theta) return p->fail(QOC_ERR_INVALID_ARG, "NULL theta");
   if (j < 0 || j >= p->nt) return p->fail(QOC_ERR_INVALID_ARG, "step index out of range");
   if (p->embed) return p->fail(QOC_ERR_UNSUPPORTED, "step propagators of a Hermitian system are not available");
+  if (p->nctl > 1) return p->fail(QOC_ERR_UNSUPPORTED, "step propagators take one control direction");
   st = p->ensure_work(1, 0);
   if (st != QOC_OK) return st;
   st = p->ensure_io(p->P + 6 * (size_t)p->n * p->n);
@@ -907,6 +955,7 @@ qoc_status qoc_eval_controls(qoc_problem* p, const double* f, double* cost, doub
   qoc_status st = p->ready();
   if (st != QOC_OK) return st;
   const int nt = p->nt, P = p->P;
+  if (p->nctl > 1) return p->fail(QOC_ERR_UNSUPPORTED, "given control samples take one control direction");
   if (!f) return p->fail(QOC_ERR_INVALID_ARG, "f must be non-NULL");
   if (!all_finite(f, (size_t)nt)) return p->fail(QOC_ERR_INVALID_ARG, "f has non-finite entries");
   const Mode mode = hess ? Mode::Hess : ((grad || dcdf) ? Mode::Grad : Mode::Cost);

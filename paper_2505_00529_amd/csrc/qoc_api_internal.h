@@ -24,6 +24,9 @@ struct qoc_problem {
   bool embed = false;
   int n_user = 0;
   int target_n() const { return embed ? n_user : n; }
+  // control directions K (Sec. II): d_m holds K stacked n x n operators and d_B K stacked
+  // nt x P model matrices; K > 1 evaluates through enqueue_multi
+  int nctl = 1;
   double* d_h0 = nullptr;
   double* d_m = nullptr;
   double* d_psi0 = nullptr;
@@ -91,6 +94,15 @@ struct qoc_problem {
   qoc_status enqueue_into(qoc::Work& w, bool ck, qoc::Mode mode, int nb, const double* d_theta, const double* d_v,
                           double* d_cost, double* d_grad, double* d_out, const double* d_targets);
   qoc_status check_device_status();
+  // K-direction evaluation (qoc_multi.hip): its own workspace and launch sequence
+  void* mc_mem = nullptr;
+  size_t mc_bytes = 0;
+  int mc_key_nb = 0, mc_key_chunk = 0, mc_key_n = 0, mc_key_nt = 0, mc_key_P = 0, mc_key_K = 0;
+  int mc_chunk = 0, mc_nchunks = 0;
+  bool mc_lds_mats = false;
+  qoc_status ensure_mc_work(int nb);
+  qoc_status enqueue_multi(qoc::Mode mode, int nb, const double* d_theta, const double* d_v, double* d_cost,
+                           double* d_grad, double* d_out, const double* d_targets);
   // targets: NULL (handle's target) or count x 2n doubles (one complex target per theta)
   qoc_status run_host(qoc::Mode mode, int count, const double* theta, const double* v, double* cost, double* grad,
                       double* out, const double* targets = nullptr);

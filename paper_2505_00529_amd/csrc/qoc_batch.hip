@@ -451,7 +451,7 @@ qoc_status qoc_batch_create(int device, int32_t count, qoc_problem* const* probl
     if (!problems[i]) return QOC_ERR_INVALID_ARG;
     if (!problems[i]->has_system || !problems[i]->has_basis) return QOC_ERR_STATE;
     if (problems[i]->device != device) return QOC_ERR_INVALID_ARG;
-    if (problems[i]->n > kBatchMaxN) return QOC_ERR_UNSUPPORTED;
+    if (problems[i]->n > kBatchMaxN || problems[i]->nctl > 1) return QOC_ERR_UNSUPPORTED;
   }
   if (hipSetDevice(device) != hipSuccess) return QOC_ERR_DEVICE;
   qoc_batch* b = new (std::nothrow) qoc_batch();

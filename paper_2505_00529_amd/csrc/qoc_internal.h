@@ -279,6 +279,8 @@ size_t layout_work(Work& w, int n, int nt, int P, int nb, int seg, int chunk, vo
 
 // Largest dynamic LDS request of any kernel; set once per device.
 hipError_t configure_kernels();
+// The same for the kernels of the several-direction path.
+hipError_t configure_mc_kernels();
 size_t eig_scratch_doubles(int n, int nb, int nchunks);
 int choose_pg(int P, int nb);
 

@@ -3185,6 +3185,8 @@ hipError_t configure_kernels() {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
   }
+  hipError_t e = configure_mc_kernels();
+  if (e != hipSuccess) return e;
   return configure_multi_kernels();
 }
 

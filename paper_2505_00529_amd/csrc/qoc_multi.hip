@@ -1,0 +1,825 @@
+// Several control directions (Sec. II, eq. matrixTDSE: H(t) = H0 + sum_k f^k(t) M_k, K <= 3).
+//
+// Each direction has its own model matrix, f^k = B_k theta (B stacked as [K][nt][P]), so a
+// parameter may move any direction.  Per step the eigen-data are those of the single-direction
+// path with one M~_k = V^T M_k V and one S_k = sinc-weighted M~_k per direction; the sweeps
+// carry y_k = U'_k a and z_k = U'_k^H lambda for every direction and force a tangent column l
+// with sum_k B_k[j, l] y_k (eq. gradatheta with the sum over k); the U'' contraction becomes one
+// value per unordered direction pair, from the mixed second derivative of eq. d2Ldf2,
+//   T^{kn}_pq = sum_r phi[l_p, l_r, l_q] (M~_k[p,r] M~_n[r,q] + M~_n[p,r] M~_k[r,q]),
+// and the assembly sums over directions (Alg. 2, final assembly):
+//   g_l  = sum_j sum_k B_k[j,l] (gamma f^k_j + q_kj),
+//   H_lm = sum_j [ gamma sum_k B_k[j,l] B_k[j,m] + sum_k (B_k[j,l] K_{j,m,k} + B_k[j,m] K_{j,l,k})
+//                  + sum_kn B_k[j,l] B_n[j,m] s_{kn,j} ] + rho Re(A'_l^H A'_m),
+//   (Hv)_l = sum_j sum_k B_k[j,l] (gamma u_kj + e_kj + sum_n s_{kn,j} u_nj),   u_k = B_k v.
+//
+// These kernels are the plain form of the path (one workgroup per (theta, chunk) for the
+// eigen-data, per (column group, theta) for the sweeps, per (step, theta) for the U''
+// contraction, and the divided differences of every triple evaluated directly); the tuned
+// single-direction kernels are not involved.  The state, costate and terminal handling are
+// shared with them: the chunk joins (k_boundary_overlap) and the terminal kernel are reused.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "../../include/qoc.h"
+#include "qoc_api_internal.h"
+#include "qoc_device.h"
+#include "qoc_internal.h"
+
+namespace qoc {
+
+constexpr int kMaxCtl = 3;
+constexpr int kMaxPairs = kMaxCtl * (kMaxCtl + 1) / 2;
+
+struct McArgs {
+  int n, np, nt, P, K, nb, chunk, nchunks;
+  int pg, ncols;           // sweep columns per workgroup; tangent columns in all (P, 1 or 0)
+  int mode;                // Mode
+  double dt, tol_rel;
+  int max_sweeps, lds_mats, store_derivs;
+  const double* h0;        // [n][n]
+  const double* m;         // [K][n][n]
+  const double* psi0;      // [n] complex
+  const double* B;         // [K][nt][P]
+  const double* f;         // [K][nb][nt]
+  const double* u;         // [K][nb][nt] (HVP)
+  double* lam;             // [nb][nt][n]
+  double* mt;              // [nb][nt][K][n][n]
+  double* sm;              // [nb][nt][K][n][n]
+  double* ov;              // [nb][nt][n][n]
+  double* vfirst;          // [nb][nchunks][n][n]
+  double* vlast;
+  double* gscratch;        // [nb][nchunks][4][np][np] when the work matrices leave LDS
+  double2* at;             // [nb][nt][n]
+  double2* yt;             // [nb][nt][K][n]
+  double2* ah;             // [nb][nt][n]
+  double2* mu;             // [nb][nt][n]
+  double* q;               // [nb][nt][K]
+  double* e;               // [nb][nt][K]
+  double* s;               // [nb][nt][K(K+1)/2]
+  double* Km;              // [nb][nt][K][P]
+  double2* xf;             // [nb][n][1 + ncols]
+  const double2* binit;    // [nb][n][2]
+  int* status;
+  unsigned long long* stats;
+};
+
+__host__ __device__ inline int pair_index(int k, int n, int K) { return k * K - k * (k - 1) / 2 + (n - k); }
+
+// ---------------------------------------------------------------- eigen-data
+
+// C = (H0 + sum_k fk[k] M_k) B, the n x n global matrices zero-padded to np x np.
+__device__ void gemm_global_left_sum(const double* h0, const double* m, const double* fk, int K, int n,
+                                     const double* B, double* C, int np) {
+  const int nt2 = np / 2;
+  const size_t nn = (size_t)n * n;
+  for (int w = threadIdx.x; w < nt2 * nt2; w += kThreads) {
+    const int ti = w / nt2, tj = w - ti * nt2;
+    const int i0 = 2 * ti, j0 = 2 * tj;
+    double c00 = 0, c01 = 0, c10 = 0, c11 = 0;
+    for (int k = 0; k < n; ++k) {
+      double a0 = i0 < n ? h0[i0 * n + k] : 0.0;
+      double a1 = i0 + 1 < n ? h0[(i0 + 1) * n + k] : 0.0;
+      for (int c = 0; c < K; ++c) {
+        if (i0 < n) a0 = fma(fk[c], m[c * nn + i0 * n + k], a0);
+        if (i0 + 1 < n) a1 = fma(fk[c], m[c * nn + (i0 + 1) * n + k], a1);
+      }
+      const double b0 = B[k * np + j0], b1 = B[k * np + j0 + 1];
+      c00 = fma(a0, b0, c00);
+      c01 = fma(a0, b1, c01);
+      c10 = fma(a1, b0, c10);
+      c11 = fma(a1, b1, c11);
+    }
+    C[i0 * np + j0] = c00;
+    C[i0 * np + j0 + 1] = c01;
+    C[(i0 + 1) * np + j0] = c10;
+    C[(i0 + 1) * np + j0 + 1] = c11;
+  }
+}
+
+__host__ __device__ inline size_t mc_eig_small_doubles(int np) { return (size_t)2 * np + kThreads + np + (np + 1) / 2 + kMaxCtl; }
+
+// One workgroup per (theta, chunk).  The first step of a chunk is decomposed cold; a later step
+// starts from V_{j-1}^T H_j V_{j-1} (nearly diagonal for a smooth control) and accumulates its
+// rotations into V_j = V_{j-1} Q_j.
+__global__ __launch_bounds__(kThreads) void k_mc_eig(McArgs a) {
+  extern __shared__ __attribute__((aligned(16))) double smem[];
+  const int c = blockIdx.x, b = blockIdx.y;
+  const int np = a.np, n = a.n, nt = a.nt, K = a.K;
+  const int j0 = c * a.chunk;
+  const int j1 = min(nt, j0 + a.chunk);
+  if (j0 >= j1) return;
+  const int tid = threadIdx.x;
+  double* rot = smem;
+  double* red = rot + np;
+  double* lamv = red + kThreads;
+  int* prs = (int*)(lamv + np);
+  double* fk = lamv + np + (np + 1) / 2;
+  double* mats = a.lds_mats ? smem + mc_eig_small_doubles(np)
+                            : a.gscratch + ((size_t)b * a.nchunks + c) * 4 * (size_t)np * np;
+  double* A = mats;
+  double* V = A + (size_t)np * np;
+  double* Vp = V + (size_t)np * np;
+  double* X = Vp + (size_t)np * np;
+  const size_t nn = (size_t)n * n;
+  const int npp = np * np;
+
+  for (int j = j0; j < j1; ++j) {
+    if (tid < K) fk[tid] = a.f[((size_t)tid * a.nb + b) * nt + j];
+    __syncthreads();
+    if (j == j0) {
+      for (int idx = tid; idx < npp; idx += kThreads) {
+        const int i = idx / np, k = idx - i * np;
+        double v = 0.0;
+        if (i < n && k < n) {
+          v = a.h0[i * n + k];
+          for (int cc = 0; cc < K; ++cc) v = fma(fk[cc], a.m[cc * nn + i * n + k], v);
+        }
+        A[idx] = v;
+        V[idx] = (i == k) ? 1.0 : 0.0;
+      }
+    } else {
+      for (int idx = tid; idx < npp; idx += kThreads) Vp[idx] = V[idx];
+      gemm_global_left_sum(a.h0, a.m, fk, K, n, V, X, np);   // X = H_j V_{j-1}
+      __syncthreads();
+      gemm_sq<true>(V, X, A, np);                             // A = V_{j-1}^T H_j V_{j-1}
+    }
+    __syncthreads();
+    double loc = 0.0;
+    for (int idx = tid; idx < npp; idx += kThreads) loc += A[idx] * A[idx];
+    const double fro = sqrt(block_sum(loc, red));
+    int sweeps = 0;
+    const bool ok = jacobi_eig(A, V, np, a.tol_rel * fro, a.max_sweeps, rot, prs, red, &sweeps);
+    if (!ok && tid == 0) atomicOr(a.status, kStatusNoConv);
+    if (ok && tid == 0 && a.stats) {
+      atomicAdd(a.stats, 1ull);
+      atomicAdd(a.stats + 1, (unsigned long long)sweeps);
+    }
+    for (int i = tid; i < np; i += kThreads) lamv[i] = A[i * np + i];
+    for (int k = tid; k < np; k += kThreads) normalize_column(V + k, np, np);
+    __syncthreads();
+    const size_t step = (size_t)b * nt + j;
+    for (int i = tid; i < n; i += kThreads) a.lam[step * n + i] = lamv[i];
+    if (j > j0) {
+      gemm_sq<true>(V, Vp, X, np);   // O_{j-1} = V_j^T V_{j-1}
+      __syncthreads();
+      for (int idx = tid; idx < (int)nn; idx += kThreads) {
+        const int i = idx / n, k = idx - i * n;
+        a.ov[(step - 1) * nn + idx] = X[i * np + k];
+      }
+      __syncthreads();
+    }
+    if (a.store_derivs) {
+      for (int cc = 0; cc < K; ++cc) {
+        gemm_global_left(a.m + cc * nn, n, V, X, np);   // X = M_k V_j
+        __syncthreads();
+        gemm_sq<true>(V, X, A, np);                     // A = M~_k
+        __syncthreads();
+        double* mtk = a.mt + (step * K + cc) * nn;
+        double* smk = a.sm + (step * K + cc) * nn;
+        for (int idx = tid; idx < (int)nn; idx += kThreads) {
+          const int i = idx / n, k = idx - i * n;
+          const double v = A[i * np + k];
+          mtk[idx] = v;
+          smk[idx] = sinc(0.5 * a.dt * (lamv[i] - lamv[k])) * v;
+        }
+        __syncthreads();
+      }
+    }
+    if (j == j0 || j == j1 - 1) {
+      double* dst = (j == j0 ? a.vfirst : a.vlast) + ((size_t)b * a.nchunks + c) * nn;
+      for (int idx = tid; idx < (int)nn; idx += kThreads) {
+        const int i = idx / n, k = idx - i * n;
+        dst[idx] = V[i * np + k];
+      }
+      if (j0 == j1 - 1) {
+        double* d2 = a.vlast + ((size_t)b * a.nchunks + c) * nn;
+        for (int idx = tid; idx < (int)nn; idx += kThreads) {
+          const int i = idx / n, k = idx - i * n;
+          d2[idx] = V[i * np + k];
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- sweeps
+
+// Forcing coefficient of direction k for tangent column `col` (global index) at step j: B_k[j,
+// col] for the Hessian, u_k[j] for the HVP (one column).
+__device__ __forceinline__ double mc_forcing(const McArgs& a, int k, int j, int col, int b) {
+  if (a.mode == (int)Mode::Hvp) return a.u[((size_t)k * a.nb + b) * a.nt + j];
+  return a.B[((size_t)k * a.nt + j) * a.P + col];
+}
+
+__host__ __device__ inline size_t mc_sweep_lds_doubles(int n, int pg, int K) {
+  // cur, X: [n][1 + pg] complex; hh, ph, av: [n] complex; yv, zv: [K][n] complex; fv: [K][pg]
+  return (size_t)2 * 2 * n * (1 + pg) + 2 * (3 * n + 2 * K * n) + (size_t)K * (pg > 0 ? pg : 1);
+}
+
+// Forward sweep (Alg. 2, forward state sweep and tangent loop; eq. gradatheta with K directions)
+// for one theta and one group of tangent columns: column 0 the state, columns 1.. the tangents,
+// in the eigenbasis of the current step; the X after the last step goes to xf.
+__global__ __launch_bounds__(kThreads) void k_mc_forward(McArgs a) {
+  extern __shared__ __attribute__((aligned(16))) double smem[];
+  const int g = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
+  const int n = a.n, nt = a.nt, K = a.K;
+  const int c0 = g * a.pg;
+  const int ncol = max(0, min(a.pg, a.ncols - c0));
+  const int w = 1 + ncol;
+  const bool need_y = a.mode != (int)Mode::Cost;
+  const size_t nn = (size_t)n * n;
+  double2* cur = (double2*)smem;
+  double2* X = cur + n * (1 + a.pg);
+  double2* hh = X + n * (1 + a.pg);
+  double2* ph = hh + n;
+  double2* yv = ph + n;                       // [K][n]
+  double* fv = (double*)(yv + K * n + n);     // [K][pg] (after the unused av slot)
+  // a_0 = V_0^T alpha in column 0, zero tangents
+  const double* V0 = a.vfirst + (size_t)b * a.nchunks * nn;
+  for (int idx = tid; idx < n * w; idx += kThreads) {
+    const int p = idx / w, col = idx - p * w;
+    double2 v = make_double2(0.0, 0.0);
+    if (col == 0) {
+      for (int r = 0; r < n; ++r) {
+        const double vr = V0[r * n + p];
+        v.x = fma(vr, a.psi0[2 * r], v.x);
+        v.y = fma(vr, a.psi0[2 * r + 1], v.y);
+      }
+    }
+    cur[idx] = v;
+  }
+  __syncthreads();
+  for (int j = 0; j < nt; ++j) {
+    const size_t es = (size_t)b * nt + j;
+    for (int r = tid; r < n; r += kThreads) {
+      const double2 h = phase(0.5 * a.lam[es * n + r], a.dt);
+      hh[r] = h;
+      ph[r] = c_mul(h, h);
+    }
+    for (int t = tid; t < K * ncol; t += kThreads) {
+      const int k = t / ncol, col = t - k * ncol;
+      fv[k * a.pg + col] = mc_forcing(a, k, j, c0 + col, b);
+    }
+    __syncthreads();
+    if (need_y) {
+      // y_k = -i dt h o (S_k (h o a)), S_k symmetric
+      for (int t = tid; t < K * n; t += kThreads) {
+        const int k = t / n, p = t - k * n;
+        const double* S = a.sm + (es * K + k) * nn;
+        double2 acc = make_double2(0.0, 0.0);
+        for (int r = 0; r < n; ++r) {
+          const double2 x = c_mul(hh[r], cur[r * w]);
+          const double sv = S[(size_t)r * n + p];
+          acc.x = fma(sv, x.x, acc.x);
+          acc.y = fma(sv, x.y, acc.y);
+        }
+        const double2 hp = c_mul(hh[p], acc);
+        yv[k * n + p] = make_double2(a.dt * hp.y, -a.dt * hp.x);
+      }
+      __syncthreads();
+      if (g == 0) {
+        for (int r = tid; r < n; r += kThreads) {
+          a.at[es * n + r] = cur[r * w];
+          if (a.mode == (int)Mode::Hvp) a.ah[es * n + r] = cur[r * w + 1];
+        }
+        for (int t = tid; t < K * n; t += kThreads) a.yt[es * K * n + t] = yv[t];
+      }
+    }
+    for (int idx = tid; idx < n * w; idx += kThreads) {
+      const int p = idx / w, col = idx - p * w;
+      double2 v = c_mul(ph[p], cur[idx]);
+      if (col > 0) {
+        for (int k = 0; k < K; ++k) {
+          const double f = fv[k * a.pg + col - 1];
+          v.x = fma(yv[k * n + p].x, f, v.x);
+          v.y = fma(yv[k * n + p].y, f, v.y);
+        }
+      }
+      X[idx] = v;
+    }
+    __syncthreads();
+    if (j + 1 < nt) {
+      const double* O = a.ov + es * nn;
+      for (int idx = tid; idx < n * w; idx += kThreads) {
+        const int p = idx / w, col = idx - p * w;
+        double2 acc = make_double2(0.0, 0.0);
+        for (int r = 0; r < n; ++r) {
+          const double o = O[(size_t)p * n + r];
+          const double2 x = X[r * w + col];
+          acc.x = fma(o, x.x, acc.x);
+          acc.y = fma(o, x.y, acc.y);
+        }
+        cur[idx] = acc;
+      }
+    } else {
+      double2* dst = a.xf + (size_t)b * n * (1 + a.ncols);
+      for (int idx = tid; idx < n * w; idx += kThreads) {
+        const int p = idx / w, col = idx - p * w;
+        if (col == 0) {
+          if (g == 0) dst[p * (1 + a.ncols)] = X[idx];
+        } else {
+          dst[p * (1 + a.ncols) + c0 + col] = X[idx];
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Backward sweep (Alg. 2, costate sweep and second-adjoint loop; eq. lambdasys, eq. musys with K
+// directions).  Column 0 carries lambda_{j+1} in basis j, columns 1.. the second-adjoint columns
+// xi (Hessian) or the costate tangent nu (HVP).  Per step and direction:
+//   z_k = U'_k^H lambda = i dt conj(h) o (S_k (conj(h) o lambda)),  q_kj = Re(lambda^H y_kj),
+//   K_{j,m,k} = Re(xi_m^H y_kj),  e_kj = Re(nu^H y_kj) + Re(z_kj^H a'_j),
+// and the columns move on as X = [conj(phi) o lambda | conj(phi) o xi + sum_k z_k F_k^T],
+// [lambda_j | xi_{j-1}] = O_{j-1}^T X.
+__global__ __launch_bounds__(kThreads) void k_mc_backward(McArgs a) {
+  extern __shared__ __attribute__((aligned(16))) double smem[];
+  const int g = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
+  const int n = a.n, nt = a.nt, K = a.K;
+  const int c0 = g * a.pg;
+  const int ncol = max(0, min(a.pg, a.ncols - c0));
+  const int w = 1 + ncol;
+  const bool hvp = a.mode == (int)Mode::Hvp, hess = a.mode == (int)Mode::Hess;
+  const size_t nn = (size_t)n * n;
+  double2* cur = (double2*)smem;
+  double2* X = cur + n * (1 + a.pg);
+  double2* hh = X + n * (1 + a.pg);
+  double2* ph = hh + n;
+  double2* av = ph + n;
+  double2* zv = av + n;                       // [K][n]
+  double2* yv = zv + K * n;                   // [K][n]
+  double* fv = (double*)(yv + K * n);         // [K][pg]
+  for (int idx = tid; idx < n * w; idx += kThreads) {
+    const int p = idx / w, col = idx - p * w;
+    double2 v = make_double2(0.0, 0.0);
+    if (col == 0) v = a.binit[((size_t)b * n + p) * 2];
+    else if (hvp) v = a.binit[((size_t)b * n + p) * 2 + 1];
+    cur[idx] = v;
+  }
+  for (int j = nt - 1; j >= 0; --j) {
+    const size_t es = (size_t)b * nt + j;
+    for (int r = tid; r < n; r += kThreads) {
+      const double2 h = c_conj(phase(0.5 * a.lam[es * n + r], a.dt));
+      hh[r] = h;
+      ph[r] = c_mul(h, h);
+      av[r] = hvp ? a.ah[es * n + r] : make_double2(0.0, 0.0);
+    }
+    for (int t = tid; t < K * n; t += kThreads) yv[t] = a.yt[es * K * n + t];
+    for (int t = tid; t < K * ncol; t += kThreads) {
+      const int k = t / ncol, col = t - k * ncol;
+      fv[k * a.pg + col] = mc_forcing(a, k, j, c0 + col, b);
+    }
+    __syncthreads();
+    for (int t = tid; t < K * n; t += kThreads) {
+      const int k = t / n, p = t - k * n;
+      const double* S = a.sm + (es * K + k) * nn;
+      double2 acc = make_double2(0.0, 0.0);
+      for (int r = 0; r < n; ++r) {
+        const double2 x = c_mul(hh[r], cur[r * w]);
+        const double sv = S[(size_t)r * n + p];
+        acc.x = fma(sv, x.x, acc.x);
+        acc.y = fma(sv, x.y, acc.y);
+      }
+      const double2 hp = c_mul(hh[p], acc);
+      zv[k * n + p] = make_double2(-a.dt * hp.y, a.dt * hp.x);   // i dt * hp
+    }
+    __syncthreads();
+    // per-step reductions: one thread per (direction, column) sums over the rows
+    if (g == 0) {
+      for (int r = tid; r < n; r += kThreads) a.mu[es * n + r] = cur[r * w];
+      for (int k = tid; k < K; k += kThreads) {
+        double lq = 0.0, le = 0.0;
+        for (int p = 0; p < n; ++p) {
+          const double2 l = cur[p * w], y = yv[k * n + p];
+          lq += l.x * y.x + l.y * y.y;
+          if (hvp) {
+            const double2 nu = cur[p * w + 1], z = zv[k * n + p];
+            le += nu.x * y.x + nu.y * y.y + z.x * av[p].x + z.y * av[p].y;
+          }
+        }
+        a.q[es * K + k] = lq;
+        if (hvp) a.e[es * K + k] = le;
+      }
+    }
+    if (hess) {
+      for (int t = tid; t < K * ncol; t += kThreads) {
+        const int k = t / ncol, col = t - k * ncol;
+        double acc = 0.0;
+        for (int p = 0; p < n; ++p) {
+          const double2 xi = cur[p * w + 1 + col], y = yv[k * n + p];
+          acc += xi.x * y.x + xi.y * y.y;
+        }
+        a.Km[(es * K + k) * a.P + c0 + col] = acc;
+      }
+    }
+    __syncthreads();
+    if (j >= 1) {
+      for (int idx = tid; idx < n * w; idx += kThreads) {
+        const int p = idx / w, col = idx - p * w;
+        double2 v = c_mul(ph[p], cur[idx]);
+        if (col > 0) {
+          for (int k = 0; k < K; ++k) {
+            const double f = fv[k * a.pg + col - 1];
+            v.x = fma(zv[k * n + p].x, f, v.x);
+            v.y = fma(zv[k * n + p].y, f, v.y);
+          }
+        }
+        X[idx] = v;
+      }
+      __syncthreads();
+      const double* O = a.ov + (es - 1) * nn;   // O_{j-1}, applied transposed
+      for (int idx = tid; idx < n * w; idx += kThreads) {
+        const int p = idx / w, col = idx - p * w;
+        double2 acc = make_double2(0.0, 0.0);
+        for (int r = 0; r < n; ++r) {
+          const double o = O[(size_t)r * n + p];
+          const double2 x = X[r * w + col];
+          acc.x = fma(o, x.x, acc.x);
+          acc.y = fma(o, x.y, acc.y);
+        }
+        cur[idx] = acc;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- U'' contraction
+
+// s_{kn,j} = Re(lambda_{j+1}^H U''_{kn,j} a_j) for every direction pair k <= n, one workgroup per
+// (step, theta): T^{kn}_pq from the second divided differences of every triple (dd2, accurate
+// at every spacing), summed against w_pq = conj(mu_p) a_q + conj(mu_q) a_p (p < q; T symmetric)
+// or conj(mu_p) a_p (p = q).
+__global__ __launch_bounds__(kThreads) void k_mc_sterm(McArgs a) {
+  __shared__ double red[kThreads];
+  const int j = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
+  const int n = a.n, K = a.K, npair = K * (K + 1) / 2;
+  const size_t nn = (size_t)n * n;
+  const size_t es = (size_t)b * a.nt + j;
+  const double* lam = a.lam + es * n;
+  const double2* mu = a.mu + es * n;
+  const double2* at = a.at + es * n;
+  const double* Mt = a.mt + es * K * nn;
+  double loc[kMaxPairs];
+  for (int i = 0; i < kMaxPairs; ++i) loc[i] = 0.0;
+  const int ntri = n * (n + 1) / 2;
+  for (int t = tid; t < ntri; t += kThreads) {
+    // t -> (p, q), p <= q, row by row
+    int p = 0, rem = t;
+    while (rem >= n - p) {
+      rem -= n - p;
+      ++p;
+    }
+    const int q = p + rem;
+    double2 T[kMaxPairs];
+    for (int i = 0; i < kMaxPairs; ++i) T[i] = make_double2(0.0, 0.0);
+    for (int r = 0; r < n; ++r) {
+      const double2 d = dd2(lam[p], lam[r], lam[q], a.dt);
+      for (int k = 0; k < K; ++k)
+        for (int m = k; m < K; ++m) {
+          const double c = Mt[k * nn + p * n + r] * Mt[m * nn + r * n + q] + Mt[m * nn + p * n + r] * Mt[k * nn + r * n + q];
+          const int i = pair_index(k, m, K);
+          T[i].x = fma(d.x, c, T[i].x);
+          T[i].y = fma(d.y, c, T[i].y);
+        }
+    }
+    double2 wgt = c_cmul(mu[p], at[q]);
+    if (p != q) wgt = c_add(wgt, c_cmul(mu[q], at[p]));
+    for (int i = 0; i < npair; ++i) loc[i] += wgt.x * T[i].x - wgt.y * T[i].y;
+  }
+  for (int i = 0; i < npair; ++i) {
+    const double v = block_sum(loc[i], red);
+    if (tid == 0) a.s[es * npair + i] = v;
+  }
+}
+
+// ---------------------------------------------------------------- assembly
+
+struct McAsmOut {
+  const double* rr;
+  const double* aa;
+  double* cost;
+  double* grad;
+  double* out;
+  double gamma, rho;
+};
+
+// Cost, gradient and Hessian (or HVP) of one theta per blockIdx.y; blockIdx.x splits the
+// P x P Hessian entries (block 0 also forms cost and gradient).
+__global__ __launch_bounds__(kThreads) void k_mc_assemble(McArgs a, McAsmOut o) {
+  __shared__ double red[kThreads];
+  const int bx = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
+  const int nt = a.nt, P = a.P, K = a.K, npair = K * (K + 1) / 2;
+  const double* f = a.f;
+  auto Bk = [&](int k, int j, int l) { return a.B[((size_t)k * nt + j) * P + l]; };
+  if (bx == 0) {
+    double loc = 0.0;
+    for (int t = tid; t < K * nt; t += kThreads) {
+      const int k = t / nt, j = t - k * nt;
+      const double x = f[((size_t)k * a.nb + b) * nt + j];
+      loc += x * x;
+    }
+    const double ff = block_sum(loc, red);
+    if (tid == 0 && o.cost) o.cost[b] = 0.5 * o.gamma * ff + 0.5 * o.rho * o.rr[b];
+    if (o.grad && a.mode != (int)Mode::Cost) {
+      for (int l = tid; l < P; l += kThreads) {
+        double acc = 0.0;
+        for (int j = 0; j < nt; ++j) {
+          const size_t es = (size_t)b * nt + j;
+          for (int k = 0; k < K; ++k)
+            acc = fma(Bk(k, j, l), o.gamma * f[((size_t)k * a.nb + b) * nt + j] + a.q[es * K + k], acc);
+        }
+        o.grad[(size_t)b * P + l] = acc;
+      }
+    }
+  }
+  if (a.mode == (int)Mode::Hess) {
+    const int idx = bx * kThreads + tid;
+    if (idx < P * P) {
+      const int l = idx / P, m = idx - l * P;
+      double acc = 0.0;
+      for (int j = 0; j < nt; ++j) {
+        const size_t es = (size_t)b * nt + j;
+        double bl[kMaxCtl], bm[kMaxCtl];
+        for (int k = 0; k < K; ++k) {
+          bl[k] = Bk(k, j, l);
+          bm[k] = Bk(k, j, m);
+        }
+        for (int k = 0; k < K; ++k) {
+          const double kl = a.Km[(es * K + k) * P + l], km = a.Km[(es * K + k) * P + m];
+          acc = fma(bl[k], fma(o.gamma, bm[k], km), acc);
+          acc = fma(bm[k], kl, acc);
+          for (int nn2 = 0; nn2 < K; ++nn2) {
+            const double sv = a.s[es * npair + pair_index(min(k, nn2), max(k, nn2), K)];
+            acc = fma(bl[k] * bm[nn2], sv, acc);
+          }
+        }
+      }
+      const size_t oi = (size_t)b * P * P + idx;
+      o.out[oi] = acc + o.aa[oi];
+    }
+  } else if (a.mode == (int)Mode::Hvp && bx == 0) {
+    for (int l = tid; l < P; l += kThreads) {
+      double acc = 0.0;
+      for (int j = 0; j < nt; ++j) {
+        const size_t es = (size_t)b * nt + j;
+        for (int k = 0; k < K; ++k) {
+          double t = o.gamma * a.u[((size_t)k * a.nb + b) * nt + j] + a.e[es * K + k];
+          for (int nn2 = 0; nn2 < K; ++nn2)
+            t = fma(a.s[es * npair + pair_index(min(k, nn2), max(k, nn2), K)],
+                    a.u[((size_t)nn2 * a.nb + b) * nt + j], t);
+          acc = fma(Bk(k, j, l), t, acc);
+        }
+      }
+      o.out[(size_t)b * P + l] = acc;
+    }
+  }
+}
+
+hipError_t configure_mc_kernels() {
+  const void* fns[] = {(const void*)k_mc_eig, (const void*)k_mc_forward, (const void*)k_mc_backward};
+  for (const void* f : fns) {
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace qoc
+
+using namespace qoc;
+
+namespace {
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+
+// Workspace of a K-direction evaluation for nb thetas (one allocation, carved in place).
+qoc_status qoc_problem::ensure_mc_work(int nb) {
+  const int K = nctl, np = pad_even(n);
+  const int chunk = eig_chunk_req > 0 ? eig_chunk_req : eig_chunk_len(nt, nb, np);
+  const int nchunks = (nt + chunk - 1) / chunk;
+  if (mc_mem && mc_key_nb == nb && mc_key_chunk == chunk && mc_key_n == n && mc_key_nt == nt && mc_key_P == P &&
+      mc_key_K == K)
+    return QOC_OK;
+  dfree(mc_mem, mc_bytes);
+  mc_mem = nullptr;
+  mc_bytes = 0;
+  const size_t nn = (size_t)n * n;
+  const size_t steps = (size_t)nb * nt;
+  const bool lds_mats = (mc_eig_small_doubles(np) + (size_t)4 * np * np) * sizeof(double) <= 160 * 1024;
+  const size_t sizes[] = {
+      sizeof(double) * K * steps,                      // f
+      sizeof(double) * K * steps,                      // u
+      sizeof(double) * steps * n,                      // lam
+      sizeof(double) * steps * K * nn,                 // mt
+      sizeof(double) * steps * K * nn,                 // sm
+      sizeof(double) * steps * nn,                     // ov
+      sizeof(double) * nb * nchunks * nn,              // vfirst
+      sizeof(double) * nb * nchunks * nn,              // vlast
+      lds_mats ? 0 : sizeof(double) * nb * nchunks * 4 * (size_t)np * np,   // gscratch
+      sizeof(double2) * steps * n,                     // at
+      sizeof(double2) * steps * K * n,                 // yt
+      sizeof(double2) * steps * n,                     // ah
+      sizeof(double2) * steps * n,                     // mu
+      sizeof(double) * steps * K,                      // q
+      sizeof(double) * steps * K,                      // e
+      sizeof(double) * steps * K * (K + 1) / 2,        // s
+      sizeof(double) * steps * K * P,                  // Km
+      sizeof(double2) * nb * n * (1 + P),              // xf
+      sizeof(double2) * nb * n * 2,                    // binit
+      sizeof(double) * nb,                             // rr
+      sizeof(double) * nb * P * P,                     // aa
+  };
+  size_t total = 0;
+  for (size_t s : sizes) total += align_up(s);
+  void* mem = nullptr;
+  qoc_status st = dmalloc(&mem, total, "multi-direction workspace");
+  if (st != QOC_OK) return st;
+  mc_mem = mem;
+  mc_bytes = total;
+  mc_key_nb = nb;
+  mc_key_chunk = chunk;
+  mc_key_n = n;
+  mc_key_nt = nt;
+  mc_key_P = P;
+  mc_key_K = K;
+  mc_chunk = chunk;
+  mc_nchunks = nchunks;
+  mc_lds_mats = lds_mats;
+  return QOC_OK;
+}
+
+// Launch sequence of one K-direction evaluation of nb thetas (device pointers).
+qoc_status qoc_problem::enqueue_multi(Mode mode, int nb, const double* d_theta, const double* d_v, double* d_cost,
+                                      double* d_grad, double* d_out, const double* d_targets) {
+  qoc_status st = ensure_mc_work(nb);
+  if (st != QOC_OK) return st;
+  const int K = nctl, np = pad_even(n);
+  const size_t nn = (size_t)n * n;
+  const size_t steps = (size_t)nb * nt;
+  const int ncols = mode == Mode::Hess ? P : (mode == Mode::Hvp ? 1 : 0);
+  McArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.n = n;
+  a.np = np;
+  a.nt = nt;
+  a.P = P;
+  a.K = K;
+  a.nb = nb;
+  a.chunk = mc_chunk;
+  a.nchunks = mc_nchunks;
+  a.ncols = ncols;
+  a.mode = (int)mode;
+  a.dt = dt;
+  a.tol_rel = jacobi_tol;
+  a.max_sweeps = jacobi_max_sweeps;
+  a.lds_mats = mc_lds_mats ? 1 : 0;
+  a.store_derivs = mode != Mode::Cost ? 1 : 0;
+  a.h0 = d_h0;
+  a.m = d_m;
+  a.psi0 = d_psi0;
+  a.B = d_B;
+  // carve the workspace in the order of ensure_mc_work
+  char* base = (char*)mc_mem;
+  auto take = [&](size_t bytes) {
+    char* p = base;
+    base += align_up(bytes);
+    return (void*)p;
+  };
+  double* f = (double*)take(sizeof(double) * K * steps);
+  double* u = (double*)take(sizeof(double) * K * steps);
+  a.f = f;
+  a.u = u;
+  a.lam = (double*)take(sizeof(double) * steps * n);
+  a.mt = (double*)take(sizeof(double) * steps * K * nn);
+  a.sm = (double*)take(sizeof(double) * steps * K * nn);
+  a.ov = (double*)take(sizeof(double) * steps * nn);
+  a.vfirst = (double*)take(sizeof(double) * nb * a.nchunks * nn);
+  a.vlast = (double*)take(sizeof(double) * nb * a.nchunks * nn);
+  a.gscratch = (double*)take(a.lds_mats ? 0 : sizeof(double) * nb * a.nchunks * 4 * (size_t)np * np);
+  a.at = (double2*)take(sizeof(double2) * steps * n);
+  a.yt = (double2*)take(sizeof(double2) * steps * K * n);
+  a.ah = (double2*)take(sizeof(double2) * steps * n);
+  a.mu = (double2*)take(sizeof(double2) * steps * n);
+  a.q = (double*)take(sizeof(double) * steps * K);
+  a.e = (double*)take(sizeof(double) * steps * K);
+  a.s = (double*)take(sizeof(double) * steps * K * (K + 1) / 2);
+  a.Km = (double*)take(sizeof(double) * steps * K * P);
+  a.xf = (double2*)take(sizeof(double2) * nb * n * (1 + P));
+  double2* binit = (double2*)take(sizeof(double2) * nb * n * 2);
+  a.binit = binit;
+  double* rr = (double*)take(sizeof(double) * nb);
+  double* aa = (double*)take(sizeof(double) * nb * P * P);
+  a.status = d_status;
+  a.stats = d_stats;
+  // tangent columns per sweep workgroup: [n][1 + pg] twice must fit in LDS
+  int pg = ncols > 0 ? std::min(ncols, choose_pg(ncols, nb)) : 0;
+  while (pg > 1 && mc_sweep_lds_doubles(n, pg, K) * sizeof(double) > 160 * 1024) --pg;
+  a.pg = std::max(pg, 1);
+  const int ngroups = ncols > 0 ? (ncols + a.pg - 1) / a.pg : 1;
+
+  hipError_t e0 = launch_fill_int(d_status, 1, 0, stream);
+  if (e0 != hipSuccess) return hip_fail(e0, "status reset");
+  hipError_t e;
+  hipEvent_t ev = nullptr;
+#define QOC_MC_LAUNCH(tag, call)                          \
+  do {                                                    \
+    prof_begin(tag, &ev);                                 \
+    e = (call);                                           \
+    if (e != hipSuccess) return hip_fail(e, #call);       \
+    prof_end(tag, ev);                                    \
+  } while (0)
+  for (int k = 0; k < K; ++k) {
+    BasisDev bs;
+    bs.nt = nt;
+    bs.P = P;
+    bs.dt = dt;
+    bs.B = d_B + (size_t)k * nt * P;
+    QOC_MC_LAUNCH("controls", launch_controls(bs, d_theta, f + (size_t)k * nb * nt, nb, stream));
+    if (mode == Mode::Hvp) QOC_MC_LAUNCH("controls", launch_controls(bs, d_v, u + (size_t)k * nb * nt, nb, stream));
+  }
+  const size_t eig_lds = (mc_eig_small_doubles(np) + (a.lds_mats ? (size_t)4 * np * np : 0)) * sizeof(double);
+  prof_begin("eig", &ev);
+  hipLaunchKernelGGL(k_mc_eig, dim3(a.nchunks, nb), dim3(kThreads), eig_lds, stream, a);
+  e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "k_mc_eig");
+  prof_end("eig", ev);
+  // chunk joins and terminal: the single-direction kernels on a view of this workspace
+  Work vw;
+  vw.n = n;
+  vw.np = np;
+  vw.nt = nt;
+  vw.nb = nb;
+  vw.P = ncols;
+  vw.chunk = a.chunk;
+  vw.nchunks = a.nchunks;
+  vw.seg_begin = 0;
+  vw.seg_len = nt;
+  vw.eig_stride = nt;
+  vw.vfirst = a.vfirst;
+  vw.vlast = a.vlast;
+  vw.ov = a.ov;
+  vw.xf = a.xf;
+  vw.binit = binit;
+  vw.rr = rr;
+  vw.aa = aa;
+  QOC_MC_LAUNCH("boundary", launch_boundary(vw, stream));
+  prof_begin("forward", &ev);
+  const McArgs& af = a;
+  const size_t sweep_lds = mc_sweep_lds_doubles(n, a.pg, K) * sizeof(double);
+  hipLaunchKernelGGL(k_mc_forward, dim3(ngroups, nb), dim3(kThreads), sweep_lds, stream, af);
+  e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "k_mc_forward");
+  prof_end("forward", ev);
+  SysDev sy;
+  sy.n = n;
+  sy.h0 = d_h0;
+  sy.m = d_m;
+  sy.psi0 = d_psi0;
+  sy.psit = d_targets ? d_targets : d_psit;
+  sy.psit_bstride = d_targets ? (size_t)2 * n : 0;
+  BasisDev bs0;
+  bs0.nt = nt;
+  bs0.P = P;
+  bs0.dt = dt;
+  bs0.B = d_B;
+  QOC_MC_LAUNCH("terminal", launch_terminal(sy, bs0, vw, mode, rho, stream));
+  if (mode != Mode::Cost) {
+    prof_begin("backward", &ev);
+    hipLaunchKernelGGL(k_mc_backward, dim3(ngroups, nb), dim3(kThreads), sweep_lds, stream, af);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "k_mc_backward");
+    prof_end("backward", ev);
+  }
+  if (mode == Mode::Hess || mode == Mode::Hvp) {
+    prof_begin("sterm", &ev);
+    hipLaunchKernelGGL(k_mc_sterm, dim3(nt, nb), dim3(kThreads), 0, stream, a);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "k_mc_sterm");
+    prof_end("sterm", ev);
+  }
+  McAsmOut o;
+  o.rr = rr;
+  o.aa = aa;
+  o.cost = d_cost;
+  o.grad = d_grad;
+  o.out = d_out;
+  o.gamma = gamma;
+  o.rho = rho;
+  const int gx = mode == Mode::Hess ? std::max(1, (P * P + kThreads - 1) / kThreads) : 1;
+  prof_begin("assemble", &ev);
+  hipLaunchKernelGGL(k_mc_assemble, dim3(gx, nb), dim3(kThreads), 0, stream, a, o);
+  e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "k_mc_assemble");
+  prof_end("assemble", ev);
+#undef QOC_MC_LAUNCH
+  return QOC_OK;
+}

@@ -369,7 +369,8 @@ static void one_sided_jacobi_svd(int nt, int P, const double* B, std::vector<dou
 // direction cannot be optimised in parameter space, so it gets no step.  Computed once per basis.
 static qoc_status ensure_whitening(qoc_problem* p) {
   if (p->tr_rank > 0 && p->tr_basis_version == p->basis_version) return QOC_OK;
-  const int P = p->P, nt = p->nt;
+  // several directions: the stacked K nt x P model, whose Gram matrix weighs the field energy
+  const int P = p->P, nt = p->nt * p->nctl;
   std::vector<double> B((size_t)nt * P);
   hipError_t e = hipMemcpyAsync(B.data(), p->d_B, B.size() * sizeof(double), hipMemcpyDeviceToHost, p->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(p->stream);

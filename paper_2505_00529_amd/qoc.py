@@ -76,6 +76,7 @@ SIGNATURES = {
     "qoc_set_tr_step_tolerance": (_st, [_vp, ctypes.c_double]),
     "qoc_set_tr_subproblem": (_st, [_vp, _i32]),
     "qoc_set_system_hermitian": (_st, [_vp, _i32, _dp, _dp, _dp, _dp]),
+    "qoc_set_system_multi": (_st, [_vp, _i32, _i32, _dp, _dp, _dp, _dp]),
     "qoc_eval_controls": (_st, [_vp, _dp, _dp, _dp, _dp, _dp]),
     "qoc_set_eig_chunk": (_st, [_vp, _i32]),
     "qoc_tr_solve_bfgs_many": (_st, [_vp, _i32, _dp, _dp, ctypes.c_double, _i32, _dp, _dp, ctypes.POINTER(_i32),
@@ -211,6 +212,17 @@ class Problem:
         w = np.zeros(self.nt)
         self._check(lib().qoc_eval_controls(self._h, _ptr(fv), _ptr(c), _ptr(g), _ptr(h), _ptr(w)))
         return float(c[0]), g, h, w
+
+    def set_system_multi(self, h0, ms, psi0, psi_target):
+        """Real symmetric H0 and K = len(ms) control operators M_k (K <= 3); the control basis is
+        set afterwards (one nt x P matrix per direction)."""
+        h0 = _f64(h0)
+        n = int(np.asarray(h0).shape[0])
+        mv = np.ascontiguousarray(np.asarray(ms, dtype=np.float64).reshape(-1, n, n))
+        self._check(lib().qoc_set_system_multi(self._h, n, mv.shape[0], _ptr(h0), _ptr(mv), _ptr(_cplx(psi0, n)),
+                                               _ptr(_cplx(psi_target, n))))
+        self.n = n
+        self.ndir = mv.shape[0]
 
     def set_system_hermitian(self, h0, m, psi0, psi_target):
         """Complex Hermitian H0, M (n x n complex); evaluated through the exact real embedding."""
