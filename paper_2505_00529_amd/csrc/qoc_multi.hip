@@ -453,12 +453,78 @@ __global__ __launch_bounds__(kThreads) void k_mc_backward(McArgs a) {
 // ---------------------------------------------------------------- U'' contraction
 
 // s_{kn,j} = Re(lambda_{j+1}^H U''_{kn,j} a_j) for every direction pair k <= n, one workgroup per
-// (step, theta): T^{kn}_pq from the second divided differences of every triple (dd2, accurate
-// at every spacing), summed against w_pq = conj(mu_p) a_q + conj(mu_q) a_p (p < q; T symmetric)
-// or conj(mu_p) a_p (p = q).
+// (step, theta).  As in the single-direction contraction, the divided differences of exp(c t),
+// c = -i dt, about the spectral centre m are a series in the complete homogeneous polynomials
+// h_n of the shifted eigenvalues x, so with P^k_a = M~_k (x^a o mu) and Q^k_d = M~_k (x^d o a)
+//   mu^H T^{kn} a = exp(c m) sum_n c^{n+2}/(n+2)! sum_{a+b+d=n} sum_r x_r^b
+//                   (conj(P^k_a[r]) Q^n_d[r] + conj(P^n_a[r]) Q^k_d[r]);
+// each wave takes pairs of directions.  A step whose spread needs more than kMcStermNmax + 1
+// terms takes the direct form instead: T^{kn}_pq from the second divided differences of every
+// triple (dd2, accurate at every spacing), summed against w_pq = conj(mu_p) a_q + conj(mu_q) a_p
+// (p < q; T symmetric) or conj(mu_p) a_p (p = q), by the whole workgroup.
+constexpr int kMcStermNmax = 14;
+
+// sum_p sum_m R_m[p] w_m[p] with R_m = sum_{a<=m} conj(P_a) Q_{m-a}, P_a = MtP (x^a o mu),
+// Q_d = MtQ (x^d o a), w_m = sum_b coef_{m+b} x_p^b (one wave, lane = row p).
+template <int NT>
+__device__ __forceinline__ double2 mc_moments(const double* MtP, const double* MtQ, const double* lam, const double2* mu,
+                                              const double2* at, const double2* coef, double m0, int lane, int n) {
+  double2 contrib = make_double2(0.0, 0.0);
+  for (int rb = 0; rb * 64 < n; ++rb) {
+    const int p = lane + 64 * rb;
+    double2 P[NT], Q[NT];
+#pragma unroll
+    for (int k = 0; k < NT; ++k) {
+      P[k] = make_double2(0.0, 0.0);
+      Q[k] = make_double2(0.0, 0.0);
+    }
+    for (int qi = 0; qi < n; ++qi) {
+      const double xq = lam[qi] - m0;
+      const double mp = p < n ? MtP[(size_t)qi * n + p] : 0.0;   // symmetric: coalesced column reads
+      const double mq = p < n ? MtQ[(size_t)qi * n + p] : 0.0;
+      double2 t1 = c_scale(mu[qi], mp), t2 = c_scale(at[qi], mq);
+#pragma unroll
+      for (int k = 0; k < NT; ++k) {
+        P[k] = c_add(P[k], t1);
+        Q[k] = c_add(Q[k], t2);
+        if (k + 1 < NT) {
+          t1 = c_scale(t1, xq);
+          t2 = c_scale(t2, xq);
+        }
+      }
+    }
+    if (p < n) {
+      const double xp = lam[p] - m0;
+#pragma unroll
+      for (int m = 0; m < NT; ++m) {
+        double2 R = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int aa = 0; aa <= m; ++aa) R = c_add(R, c_cmul(P[aa], Q[m - aa]));
+        double2 wm = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int bb = NT - 1 - m; bb >= 0; --bb) {
+          wm = c_scale(wm, xp);
+          wm = c_add(wm, coef[m + bb]);
+        }
+        contrib = c_add(contrib, c_mul(R, wm));
+      }
+    }
+  }
+  return contrib;
+}
+
+template <int NT>
+__device__ double2 mc_pair_moments(const double* Mk, const double* Mn, bool same, const double* lam, const double2* mu,
+                                   const double2* at, const double2* coef, double m0, int lane, int n) {
+  double2 c = mc_moments<NT>(Mk, Mn, lam, mu, at, coef, m0, lane, n);
+  if (same) return c_scale(c, 2.0);
+  return c_add(c, mc_moments<NT>(Mn, Mk, lam, mu, at, coef, m0, lane, n));
+}
+
 __global__ __launch_bounds__(kThreads) void k_mc_sterm(McArgs a) {
   __shared__ double red[kThreads];
   const int j = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
+  const int wv = tid >> 6, lane = tid & 63;
   const int n = a.n, K = a.K, npair = K * (K + 1) / 2;
   const size_t nn = (size_t)n * n;
   const size_t es = (size_t)b * a.nt + j;
@@ -466,6 +532,67 @@ __global__ __launch_bounds__(kThreads) void k_mc_sterm(McArgs a) {
   const double2* mu = a.mu + es * n;
   const double2* at = a.at + es * n;
   const double* Mt = a.mt + es * K * nn;
+  // terms of the series: the first omitted one bounded by (n+2)(n+3) del^(n+1) / (n+3)!
+  double lo = 1e300, hi = -1e300;
+  for (int p = lane; p < n; p += 64) {
+    lo = fmin(lo, lam[p]);
+    hi = fmax(hi, lam[p]);
+  }
+  lo = wave_min_lds(lo);
+  hi = wave_max_lds(hi);
+  const double m0 = 0.5 * (lo + hi);
+  const double del = 0.5 * a.dt * (hi - lo);
+  int nmax = -1;
+  {
+    double dp = del, fact = 6.0;
+    for (int k = 0; k <= kMcStermNmax; ++k) {
+      if ((k + 2.0) * (k + 3.0) * dp / fact < 1e-17) {
+        nmax = k;
+        break;
+      }
+      dp *= del;
+      fact *= (double)(k + 4);
+    }
+  }
+  nmax = __builtin_amdgcn_readfirstlane(nmax);   // the same in every wave: they read the same spectrum
+  if (nmax >= 0) {
+    double2 coef[kMcStermNmax + 1];
+    double mag = 0.5 * a.dt * a.dt;
+#pragma unroll
+    for (int k = 0; k <= kMcStermNmax; ++k) {
+      const int r4 = k & 3;   // (-i)^(k+2)
+      coef[k] = r4 == 0 ? make_double2(-mag, 0.0)
+              : r4 == 1 ? make_double2(0.0, mag)
+              : r4 == 2 ? make_double2(mag, 0.0)
+                        : make_double2(0.0, -mag);
+      mag *= a.dt / (double)(k + 3);
+    }
+    const double2 ph = phase(m0, a.dt);
+    for (int i = wv; i < npair; i += kThreads / 64) {
+      int k = 0, rem = i;
+      while (rem >= K - k) {
+        rem -= K - k;
+        ++k;
+      }
+      const int m = k + rem;
+      const double* Mk = Mt + k * nn;
+      const double* Mm = Mt + m * nn;
+      double2 c = make_double2(0.0, 0.0);
+      switch (nmax) {   // wave-uniform
+#define QOC_MC_STERM_CASE(T) \
+  case T - 1: c = mc_pair_moments<T>(Mk, Mm, k == m, lam, mu, at, coef, m0, lane, n); break;
+        QOC_MC_STERM_CASE(1) QOC_MC_STERM_CASE(2) QOC_MC_STERM_CASE(3) QOC_MC_STERM_CASE(4) QOC_MC_STERM_CASE(5)
+        QOC_MC_STERM_CASE(6) QOC_MC_STERM_CASE(7) QOC_MC_STERM_CASE(8) QOC_MC_STERM_CASE(9) QOC_MC_STERM_CASE(10)
+        QOC_MC_STERM_CASE(11) QOC_MC_STERM_CASE(12) QOC_MC_STERM_CASE(13) QOC_MC_STERM_CASE(14) QOC_MC_STERM_CASE(15)
+#undef QOC_MC_STERM_CASE
+        default: break;
+      }
+      double2 tot = make_double2(wave_sum_lds(c.x), wave_sum_lds(c.y));
+      tot = c_mul(ph, tot);
+      if (lane == 0) a.s[es * npair + i] = tot.x;
+    }
+    return;
+  }
   double loc[kMaxPairs];
   for (int i = 0; i < kMaxPairs; ++i) loc[i] = 0.0;
   const int ntri = n * (n + 1) / 2;

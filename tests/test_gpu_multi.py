@@ -75,6 +75,24 @@ def test_fourier_directions_against_oracle(n, ndir):
     p.close()
 
 
+def test_wide_spectral_spread_takes_the_direct_form():
+    """dt = 0.8: every step's spread needs more series terms than the U'' contraction keeps, so
+    the pair values come from the divided differences of every triple."""
+    n, nt, dt, kf = 6, 12, 0.8, 1
+    s, ms = _ops(n, 2, 75)
+    p = qoc.Problem(0)
+    p.set_system_multi(s.h0, ms, s.psi0, s.psi_target)
+    p.set_control_basis(qoc.QOC_BASIS_FOURIER, nt, dt, kf)
+    p.set_weights(0.3, 2.0)
+    bases = _fourier_stack(nt, dt, kf, 2)
+    th = inputs.draw_thetas(p.P, 1, 76, sigma=0.8)[0]
+    c, g, h = p.hess(th)
+    cr, gr, hr = O.cost_grad_hess_multi(s.h0, ms, s.psi0, s.psi_target, bases, dt, th, 0.3, 2.0)
+    _say(f"wide spread K=2: dC={_rel(c, cr):.2e} dg={_rel(g, gr):.2e} dH={_rel(h, hr):.2e}")
+    assert _rel(c, cr) < TOL and _rel(g, gr) < TOL and _rel(h, hr) < TOL
+    p.close()
+
+
 def test_dense_models_move_every_direction():
     """A dense nt x P model per direction (every parameter moves all three directions)."""
     n, nt, dt, P = 8, 30, 0.05, 5
