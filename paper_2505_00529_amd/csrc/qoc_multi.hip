@@ -71,35 +71,6 @@ __host__ __device__ inline int pair_index(int k, int n, int K) { return k * K - 
 
 // ---------------------------------------------------------------- eigen-data
 
-// C = (H0 + sum_k fk[k] M_k) B, the n x n global matrices zero-padded to np x np.
-__device__ void gemm_global_left_sum(const double* h0, const double* m, const double* fk, int K, int n,
-                                     const double* B, double* C, int np) {
-  const int nt2 = np / 2;
-  const size_t nn = (size_t)n * n;
-  for (int w = threadIdx.x; w < nt2 * nt2; w += kThreads) {
-    const int ti = w / nt2, tj = w - ti * nt2;
-    const int i0 = 2 * ti, j0 = 2 * tj;
-    double c00 = 0, c01 = 0, c10 = 0, c11 = 0;
-    for (int k = 0; k < n; ++k) {
-      double a0 = i0 < n ? h0[i0 * n + k] : 0.0;
-      double a1 = i0 + 1 < n ? h0[(i0 + 1) * n + k] : 0.0;
-      for (int c = 0; c < K; ++c) {
-        if (i0 < n) a0 = fma(fk[c], m[c * nn + i0 * n + k], a0);
-        if (i0 + 1 < n) a1 = fma(fk[c], m[c * nn + (i0 + 1) * n + k], a1);
-      }
-      const double b0 = B[k * np + j0], b1 = B[k * np + j0 + 1];
-      c00 = fma(a0, b0, c00);
-      c01 = fma(a0, b1, c01);
-      c10 = fma(a1, b0, c10);
-      c11 = fma(a1, b1, c11);
-    }
-    C[i0 * np + j0] = c00;
-    C[i0 * np + j0 + 1] = c01;
-    C[(i0 + 1) * np + j0] = c10;
-    C[(i0 + 1) * np + j0 + 1] = c11;
-  }
-}
-
 __host__ __device__ inline size_t mc_eig_small_doubles(int np) { return (size_t)2 * np + kThreads + np + (np + 1) / 2 + kMaxCtl; }
 
 // One workgroup per (theta, chunk).  The first step of a chunk is decomposed cold; a later step
@@ -142,10 +113,21 @@ __global__ __launch_bounds__(kThreads) void k_mc_eig(McArgs a) {
         V[idx] = (i == k) ? 1.0 : 0.0;
       }
     } else {
-      for (int idx = tid; idx < npp; idx += kThreads) Vp[idx] = V[idx];
-      gemm_global_left_sum(a.h0, a.m, fk, K, n, V, X, np);   // X = H_j V_{j-1}
+      // H_j staged in A, then A = V_{j-1}^T (H_j V_{j-1})
+      for (int idx = tid; idx < npp; idx += kThreads) {
+        const int i = idx / np, k = idx - i * np;
+        double v = 0.0;
+        if (i < n && k < n) {
+          v = a.h0[i * n + k];
+          for (int cc = 0; cc < K; ++cc) v = fma(fk[cc], a.m[cc * nn + i * n + k], v);
+        }
+        A[idx] = v;
+        Vp[idx] = V[idx];
+      }
       __syncthreads();
-      gemm_sq<true>(V, X, A, np);                             // A = V_{j-1}^T H_j V_{j-1}
+      gemm_sq<false>(A, V, X, np);
+      __syncthreads();
+      gemm_sq<true>(V, X, A, np);
     }
     __syncthreads();
     double loc = 0.0;
@@ -174,9 +156,15 @@ __global__ __launch_bounds__(kThreads) void k_mc_eig(McArgs a) {
     }
     if (a.store_derivs) {
       for (int cc = 0; cc < K; ++cc) {
-        gemm_global_left(a.m + cc * nn, n, V, X, np);   // X = M_k V_j
+        // M_k staged in A (free after the sweeps), X = M_k V_j, A = V_j^T X = M~_k
+        for (int idx = tid; idx < npp; idx += kThreads) {
+          const int i = idx / np, k = idx - i * np;
+          A[idx] = (i < n && k < n) ? a.m[cc * nn + i * n + k] : 0.0;
+        }
         __syncthreads();
-        gemm_sq<true>(V, X, A, np);                     // A = M~_k
+        gemm_sq<false>(A, V, X, np);
+        __syncthreads();
+        gemm_sq<true>(V, X, A, np);
         __syncthreads();
         double* mtk = a.mt + (step * K + cc) * nn;
         double* smk = a.sm + (step * K + cc) * nn;
