@@ -69,7 +69,7 @@ class WarmStart:
 
     # -- training
     def fit(self, targets, thetas, epochs: int = 200, lr: float = 1e-3, batch: int = 128, seed: int = 0,
-            lr_final: float = 1e-5):
+            lr_final: float = 1e-5, verbose: bool = False):
         """Train on (target, optimal theta) pairs; returns the mean loss of each epoch."""
         import torch
 
@@ -103,6 +103,8 @@ class WarmStart:
                 acc += loss.item()
                 step += 1
             history.append(acc / steps_per_epoch)
+            if verbose and len(history) % 50 == 0:
+                print(f"[warmstart]   epoch {len(history)}/{epochs}: loss {history[-1]:.4f}", flush=True)
         return history
 
     # -- persistence
@@ -276,7 +278,7 @@ def main(argv: Optional[list] = None):
     print(f"[warmstart] training set: {tr_s:.1f} s, mean iters {tr_it.mean():.1f}", flush=True)
     ws = WarmStart(p)
     t0 = time.perf_counter()
-    hist = ws.fit(tr_t[tr_conv], tr_th[tr_conv], epochs=args.epochs, lr=args.lr, batch=args.batch)
+    hist = ws.fit(tr_t[tr_conv], tr_th[tr_conv], epochs=args.epochs, lr=args.lr, batch=args.batch, verbose=True)
     fit_s = time.perf_counter() - t0
     print(f"[warmstart] trained {args.epochs} epochs in {fit_s:.1f} s, loss {hist[0]:.4f} -> {hist[-1]:.4f}",
           flush=True)
