@@ -2025,13 +2025,15 @@ __device__ __forceinline__ void body_forward(const SweepArgs& a, int g, int b) {
       hh[ph_t] = h;
       ph[ph_t] = c_mul(h, h);
     }
-    // rows past the 128 staged in registers (n > 128): read at the commit
-    if (ph_t >= 0) {
-      const double* lj = a.lam + (eb0 + (j - a.eig_j0)) * n;
-      for (int r = ph_t + 128; r < n; r += 128) {
-        const double2 h = phase(0.5 * lj[r], a.dt);
-        hh[r] = h;
-        ph[r] = c_mul(h, h);
+    // rows past the 128 staged in registers (n > 128, global mode only): read at the commit
+    if constexpr (MODE == kSweepGlobal) {
+      if (ph_t >= 0) {
+        const double* lj = a.lam + (eb0 + (j - a.eig_j0)) * n;
+        for (int r = ph_t + 128; r < n; r += 128) {
+          const double2 h = phase(0.5 * lj[r], a.dt);
+          hh[r] = h;
+          ph[r] = c_mul(h, h);
+        }
       }
     }
     if (tid < ncol) fv[tid] = st.pf;
@@ -2146,10 +2148,16 @@ __device__ __forceinline__ void body_forward(const SweepArgs& a, int g, int b) {
     }
     __syncthreads();
     if (g == 0 && a.need_y) {
-      for (int r = tid; r < n; r += kThreads) {
-        a.at[vs * n + r] = cur[r * w];
-        a.yt[vs * n + r] = yv[r];
-        if (a.ah) a.ah[vs * n + r] = cur[r * w + 1];
+      if constexpr (MODE == kSweepGlobal) {
+        for (int r = tid; r < n; r += kThreads) {
+          a.at[vs * n + r] = cur[r * w];
+          a.yt[vs * n + r] = yv[r];
+          if (a.ah) a.ah[vs * n + r] = cur[r * w + 1];
+        }
+      } else if (tid < n) {
+        a.at[vs * n + tid] = cur[tid * w];
+        a.yt[vs * n + tid] = yv[tid];
+        if (a.ah) a.ah[vs * n + tid] = cur[tid * w + 1];
       }
     }
     {
@@ -2417,19 +2425,22 @@ __device__ __forceinline__ void body_backward(const SweepArgs& a, int g, int b) 
       yv[tid] = st.py;
       av[tid] = st.pa;
     }
-    // rows past those staged in registers (n > 128 phases, n > kThreads vectors): read here
-    if (ph_t >= 0) {
-      const double* lj = a.lam + (eb0 + (j - a.eig_j0)) * n;
-      for (int r = ph_t + 128; r < n; r += 128) {
-        const double2 h = c_conj(phase(0.5 * lj[r], a.dt));
-        hh[r] = h;
-        ph[r] = c_mul(h, h);
+    // rows past those staged in registers (n > 128 phases, n > kThreads vectors; global mode
+    // only): read here
+    if constexpr (MODE == kSweepGlobal) {
+      if (ph_t >= 0) {
+        const double* lj = a.lam + (eb0 + (j - a.eig_j0)) * n;
+        for (int r = ph_t + 128; r < n; r += 128) {
+          const double2 h = c_conj(phase(0.5 * lj[r], a.dt));
+          hh[r] = h;
+          ph[r] = c_mul(h, h);
+        }
       }
-    }
-    for (int r = tid + kThreads; r < n; r += kThreads) {
-      const size_t vsj = vb0 + j;
-      yv[r] = a.yt[vsj * n + r];
-      av[r] = a.hvp ? a.ah[vsj * n + r] : make_double2(0.0, 0.0);
+      for (int r = tid + kThreads; r < n; r += kThreads) {
+        const size_t vsj = vb0 + j;
+        yv[r] = a.yt[vsj * n + r];
+        av[r] = a.hvp ? a.ah[vsj * n + r] : make_double2(0.0, 0.0);
+      }
     }
     if (tid < ncol) fv[tid] = st.pf;
   };
@@ -2710,11 +2721,12 @@ __device__ double sterm_pairs_wave(const StermArgs& a, size_t es, size_t vs, int
 // P_k[p] = sum_q M~_pq mu_q x_q^k and Q_k[p] = sum_q M~_pq a_q x_q^k, then
 // sum_p sum_m R_m[p] w_m[p] with R_m = sum_{a<=m} conj(P_a) Q_{m-a} and
 // w_m = sum_b coef_{m+b} x_p^b.  Instantiated per NT so that the term loops have fixed length;
-// x_q, mu_q and a_q are read at wave-uniform addresses.
-template <int NT>
+// x_q, mu_q and a_q are read at wave-uniform addresses.  WIDE (n > 128): rows past the two held
+// in registers take x_p from lam (a separate instance, so the common one keeps its registers).
+template <int NT, bool WIDE>
 __device__ __forceinline__ double2 sterm_moments(const double* Mt, const double* lam, const double2* mu,
-                                                 const double2* at, const double2* coef, double m0, int lane,
-                                                 int n) {
+                                                 const double2* at, const double2* coef, double m0, double x0,
+                                                 double x1, int lane, int n) {
   double2 contrib = make_double2(0.0, 0.0);
   for (int rb = 0; rb * 64 < n; ++rb) {
     const int p = lane + 64 * rb;
@@ -2744,7 +2756,7 @@ __device__ __forceinline__ double2 sterm_moments(const double* Mt, const double*
       }
     }
     if (p < n) {
-      const double xp = lam[p] - m0;
+      const double xp = WIDE ? (rb == 0 ? x0 : (rb == 1 ? x1 : lam[p] - m0)) : (rb ? x1 : x0);
 #pragma unroll
       for (int m = 0; m < NT; ++m) {
         double2 R = make_double2(0.0, 0.0);
@@ -2764,6 +2776,9 @@ __device__ __forceinline__ double2 sterm_moments(const double* Mt, const double*
 }
 
 // Tasks bx * waves + wave, stepping nblk * waves: block bx of nblk covering all tasks.
+// WIDE: n > 128 (rows past the two a lane holds); a separate instance, so that the common one
+// keeps its register allocation.
+template <bool WIDE>
 __device__ __forceinline__ void body_sterm(const StermArgs& a, int bx, int nblk) {
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int n = a.n;
@@ -2774,11 +2789,25 @@ __device__ __forceinline__ void body_sterm(const StermArgs& a, int bx, int nblk)
     const size_t es = (size_t)tb * a.eig_stride + (tj - a.eig_j0);   // eigen-data index
     const size_t vs = (size_t)tb * a.nt + tj;                         // per-step vector index
     const double* lam = a.lam + es * n;
+    // eigenvalues of rows lane and lane + 64 in registers; rows from 128 on (n > 128) are read
+    // where they are used
+    double lv[2];
     double lo = 1e300, hi = -1e300;
-    for (int p = lane; p < n; p += 64) {
-      const double l = lam[p];
-      lo = fmin(lo, l);
-      hi = fmax(hi, l);
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int p = lane + 64 * e;
+      lv[e] = 0.0;
+      if (p < n) {
+        lv[e] = lam[p];
+        lo = fmin(lo, lv[e]);
+        hi = fmax(hi, lv[e]);
+      }
+    }
+    if (WIDE) {
+      for (int p = lane + 128; p < n; p += 64) {
+        lo = fmin(lo, lam[p]);
+        hi = fmax(hi, lam[p]);
+      }
     }
     lo = wave_min_lds(lo);
     hi = wave_max_lds(hi);
@@ -2817,13 +2846,14 @@ __device__ __forceinline__ void body_sterm(const StermArgs& a, int bx, int nblk)
           mag *= a.dt / (double)(k + 3);
         }
       }
+      const double x0 = lv[0] - m0, x1 = lv[1] - m0;
       const double* Mt = a.mt + es * nn;
       const double2* mu = a.mu + vs * n;
       const double2* at = a.at + vs * n;
       double2 contrib = make_double2(0.0, 0.0);
       switch (nmax) {   // wave-uniform
 #define QOC_STERM_CASE(T) \
-  case T - 1: contrib = sterm_moments<T>(Mt, lam, mu, at, coef, m0, lane, n); break;
+  case T - 1: contrib = sterm_moments<T, WIDE>(Mt, lam, mu, at, coef, m0, x0, x1, lane, n); break;
         QOC_STERM_CASE(1) QOC_STERM_CASE(2) QOC_STERM_CASE(3) QOC_STERM_CASE(4) QOC_STERM_CASE(5)
         QOC_STERM_CASE(6) QOC_STERM_CASE(7) QOC_STERM_CASE(8) QOC_STERM_CASE(9) QOC_STERM_CASE(10)
         QOC_STERM_CASE(11) QOC_STERM_CASE(12) QOC_STERM_CASE(13) QOC_STERM_CASE(14) QOC_STERM_CASE(15)
@@ -2838,7 +2868,8 @@ __device__ __forceinline__ void body_sterm(const StermArgs& a, int bx, int nblk)
   }
 }
 
-__global__ __launch_bounds__(kThreads, 2) void k_sterm_wave(StermArgs a) { body_sterm(a, blockIdx.x, gridDim.x); }
+template <bool WIDE>
+__global__ __launch_bounds__(kThreads, 2) void k_sterm_wave(StermArgs a) { body_sterm<WIDE>(a, blockIdx.x, gridDim.x); }
 
 // ---------------------------------------------------------------- assembly
 
@@ -3483,7 +3514,10 @@ hipError_t launch_sterm(const SysDev& sy, const BasisDev& bs, Work& w, hipStream
   const int wpb = kThreads / 64;
   int blocks = (a.ntasks + wpb - 1) / wpb;
   if (blocks > 256 * 64) blocks = 256 * 64;
-  hipLaunchKernelGGL(k_sterm_wave, dim3(blocks), dim3(kThreads), 0, stream, a);
+  if (a.n <= 128)
+    hipLaunchKernelGGL(k_sterm_wave<false>, dim3(blocks), dim3(kThreads), 0, stream, a);
+  else
+    hipLaunchKernelGGL(k_sterm_wave<true>, dim3(blocks), dim3(kThreads), 0, stream, a);
   return hipGetLastError();
 }
 
@@ -3583,7 +3617,7 @@ QOC_MULTI_KERNEL(km_terminal, kThreads, 1, TermArgs, body_terminal)
 QOC_MULTI_KERNEL(km_backward_staged, kThreads, 2, SweepArgs, body_backward<kSweepRegs>)
 QOC_MULTI_KERNEL(km_backward_small, kThreads, 2, SweepArgs, body_backward<kSweepDbuf>)
 QOC_MULTI_KERNEL(km_backward_global, kThreads, 3, SweepArgs, body_backward<kSweepGlobal>)
-QOC_MULTI_KERNEL(km_sterm, kThreads, 2, StermArgs, body_sterm)
+QOC_MULTI_KERNEL(km_sterm, kThreads, 2, StermArgs, body_sterm<false>)   // batches: n <= 128
 QOC_MULTI_KERNEL(km_assemble, kThreads, 1, AsmArgs, body_assemble)
 #undef QOC_MULTI_KERNEL
 
