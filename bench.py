@@ -327,12 +327,111 @@ def run_batched(args) -> int:
     return 0
 
 
+def multi_flops_per_step(kernel: str, n: int, p: int, ndir: int) -> float:
+    """Algorithmic FLOPs per (theta, time step) with ndir control directions: one
+    eigendecomposition and ndir products M~_k = V^T M_k V; per direction one S_k mat-vec in each
+    sweep beside the N x N . N x P tangent product; one U'' contraction per direction pair."""
+    return {
+        "eig": 9.0 * n ** 3 + 4.0 * ndir * n ** 3,
+        "forward": 8.0 * n * n * p + 8.0 * ndir * n * n,
+        "backward": 8.0 * n * n * p + 8.0 * ndir * n * n,
+        "sterm": 8.0 * n ** 3 * ndir * (ndir + 1) / 2,
+    }.get(kernel, 0.0)
+
+
+def run_multi(args) -> int:
+    """Three control directions (Sec. II with the x, y, z dipoles; the mixed second derivatives of
+    eq. d2Ldf2): one step = cost + gradient + Hessian of a batch of theta on the molecule workload
+    with two further dipole operators and a Fourier block of 32 parameters per direction
+    (P = 96).  Rows 0 and 1 of the timed batch are checked against stored oracle values."""
+    import torch
+
+    torch.cuda.set_device(0)
+    w, ms = inputs.multi_direction_workload()
+    s = w.system
+    ndir, n, nt, B = len(ms), w.system.n, w.nt, args.multi_batch
+    prob = qoc.Problem(0)
+    prob.set_system_multi(s.h0, ms, s.psi0, s.psi_target)
+    prob.set_control_basis(qoc.QOC_BASIS_FOURIER, nt, w.dt, w.k)
+    prob.set_weights(w.gamma, w.rho)
+    P = prob.P
+    log(f"bench: three-direction workload n={n} nt={nt} P={P} batch={B}")
+    stream = torch.cuda.current_stream()
+    prob.set_stream(stream.cuda_stream)
+    thetas = torch.tensor(inputs.draw_thetas(P, B, w.seed), dtype=torch.float64, device="cuda")
+    r = timed_batch(prob, thetas, args.steps, args.warmup, stream, "multi")
+    ktimes = r["ktimes"]
+    dom = max(ktimes, key=lambda k: ktimes[k][0])
+    achieved = multi_flops_per_step(dom, n, P, ndir) * nt * B / (ktimes[dom][0] * 1e-3) / 1e12
+    peak = PEAK_FP64 / 1e12
+    parity = parity_vs_oracle("multi", r["costs"], r["grads"], r["hess"])
+    log(f"bench: parity of the timed batch against the oracle: max rel err {parity['max_rel_err']:.2e}")
+    value = B * args.steps / r["elapsed"]
+    f_alg = sum(multi_flops_per_step(k, n, P, ndir) for k in ("eig", "forward", "backward", "sterm")) * nt
+    out = {
+        "metric": f"grad+Hessian evals/s (FP64, N={n}, {ndir} control directions, P={P})",
+        "value": value,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * r["elapsed"] / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"multi: molecule N={n}, J={nt}, dt={w.dt}, {ndir} dipole operators, Fourier "
+                               f"K={w.k} per direction (P={P}), {B} independent theta ~ N(0, 0.1^2) per step",
+                   "n": n, "nt": nt, "P": P, "directions": ndir, "batch": B, "parallelism": "single GPU"},
+        "roofline": {"kernel": dom, "bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": None},
+        "kernel_ms": {k: round(v[0], 4) for k, v in ktimes.items()},
+        "step_ms_median": float(np.median(r["step_ms"])),
+        "jacobi_sweeps_per_step": r["sweeps_per_step"],
+        "path_alg_flops_per_eval": f_alg,
+        "path_roofline_frac": f_alg * value / PEAK_FP64,
+        "parity": parity,
+    }
+    prob.close()
+    if not args.no_cpu_baseline:
+        from oracle import qoc_oracle as O
+        from threadpoolctl import threadpool_info
+
+        log("bench: timing the CPU oracle on a sample of one theta ...")
+        threads = max([int(x.get("num_threads", 1)) for x in threadpool_info()] or [1])
+        ns = min(args.multi_oracle_steps, nt)
+        b0 = O.fourier_basis(nt, w.dt, w.k)[:ns]
+        p0 = b0.shape[1]
+        bases = np.zeros((ndir, ns, ndir * p0))
+        for c in range(ndir):
+            bases[c, :, c * p0:(c + 1) * p0] = b0
+        th = inputs.draw_thetas(P, 1, w.seed)[0]
+        t0 = time.perf_counter()
+        O.cost_grad_hess_multi(s.h0, ms, s.psi0, s.psi_target, bases, w.dt, th, w.gamma, w.rho)
+        dt_s = (time.perf_counter() - t0) * nt / ns
+        out["cpu_baseline"] = {"value": 1.0 / dt_s, "unit": "evals/s", "cores": threads, "kind": "oracle",
+                               "cpu_model": cpu_model(),
+                               "sample": f"the first {ns} of the {nt} steps of one theta (cost+grad+Hessian, "
+                                         f"{ndir} directions, P={P}) on {threads} BLAS threads, "
+                                         f"{dt_s * ns / nt:.1f} s, scaled to the full horizon"}
+    print(json.dumps(out), flush=True)
+    if not parity["ok"]:
+        log(f"bench: PARITY FAILURE: max rel err {parity['max_rel_err']:.3e} above {PARITY_TOL:g}")
+        return 1
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=["molecule", "warm", "batched"], default="molecule",
+    ap.add_argument("--workload", choices=["molecule", "warm", "batched", "multi"], default="molecule",
                     help="molecule: the headline evals/s line (N=36, P=32); warm: the 64-level system "
-                         "(N=64, P=64); batched: 256 uneven problems")
+                         "(N=64, P=64); batched: 256 uneven problems; multi: three control directions "
+                         "(N=36, P=96)")
+    ap.add_argument("--multi-batch", type=int, default=64, help="theta per step of the multi workload")
+    ap.add_argument("--multi-oracle-steps", type=int, default=400,
+                    help="steps of the multi workload's oracle sample (its time is linear in the steps)")
     ap.add_argument("--n64-steps", type=int, default=4,
                     help="with the molecule workload, also time this many steps of the 64-level system "
                          "(256 theta) and report them beside the headline (0: skip)")
@@ -361,6 +460,8 @@ def main() -> int:
 
     if args.workload == "batched":
         return run_batched(args)
+    if args.workload == "multi":
+        return run_multi(args)
 
     import torch
 

@@ -181,6 +181,17 @@ def make_workload(name: str, *, n: Optional[int] = None, nt: Optional[int] = Non
     return Workload(name, sysm, spec["nt"], spec["dt"], spec["k"], gamma, rho, spec["seed"])
 
 
+def multi_direction_workload(ndir: int = 3, seed: int = 17):
+    """The molecule workload with ndir control directions (Sec. II, the x, y, z dipoles): its M is
+    the first operator and the others follow the same recipe (dense N(0, 0.3^2), diagonal
+    included); each direction gets its own block of the Fourier model (P = ndir x 2K).
+    Returns (workload, [M_1, ..., M_ndir])."""
+    w = make_workload("molecule")
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, w.system.n, ndir])))
+    ms = [w.system.m] + [_sym_normal(rng, w.system.n, 0.3, zero_diag=False) for _ in range(ndir - 1)]
+    return w, ms
+
+
 def draw_thetas(p: int, count: int, seed: int, sigma: float = 0.1) -> np.ndarray:
     """(count, p) control coefficients ~ N(0, sigma^2)."""
     rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 7919])))

@@ -48,8 +48,8 @@ class NeuralControl:
             return self._f(self._t(theta)).numpy()
 
     def jacobian(self, theta) -> np.ndarray:
-        """df/dtheta, nt x P."""
-        return torch.func.jacrev(self._f)(self._t(theta)).numpy()
+        """df/dtheta, nt x P, in forward mode (P tangents instead of nt cotangents: P << nt)."""
+        return torch.func.jacfwd(self._f)(self._t(theta)).numpy()
 
     def curvature(self, theta, w) -> np.ndarray:
         """sum_j w_j d2f_j/dtheta2, P x P."""

@@ -228,3 +228,28 @@ def test_multi_direction_limits_are_reported():
     c, g = p.grad(th)
     assert np.isfinite(c) and np.all(np.isfinite(g))
     p.close()
+
+
+def test_benchmark_configuration_against_stored_oracle():
+    """The three-direction workload at full size, in the launch configuration the benchmark times
+    (64 theta, J = 4000, P = 96): rows 0 and 1 against the oracle's stored values
+    (tests/golden/multi_oracle.json, written by make_golden_multi.py)."""
+    import json
+    import os
+
+    with open(os.path.join(os.path.dirname(__file__), "golden", "multi_oracle.json")) as fh:
+        doc = json.load(fh)
+    w, ms = inputs.multi_direction_workload()
+    s = w.system
+    p = qoc.Problem(0)
+    p.set_system_multi(s.h0, ms, s.psi0, s.psi_target)
+    p.set_control_basis(qoc.QOC_BASIS_FOURIER, w.nt, w.dt, w.k)
+    p.set_weights(w.gamma, w.rho)
+    ths = inputs.draw_thetas(p.P, 64, w.seed)
+    c, g, h = p.hess_many(ths)
+    for case in doc["cases"]:
+        i = case["theta_index"]
+        dc, dg, dh = _rel(c[i], case["cost"]), _rel(g[i], case["grad"]), _rel(h[i], case["hess"])
+        _say(f"multi bench config theta {i}: dC={dc:.2e} dg={dg:.2e} dH={dh:.2e}")
+        assert dc < TOL and dg < TOL and dh < TOL
+    p.close()
