@@ -40,6 +40,7 @@ struct McArgs {
   int mode;                // Mode
   double dt, tol_rel;
   int max_sweeps, lds_mats, store_derivs;
+  int stage;               // sweeps: the step's O and S_k staged in LDS (when they fit)
   const double* h0;        // [n][n]
   const double* m;         // [K][n][n]
   const double* psi0;      // [n] complex
@@ -204,9 +205,11 @@ __device__ __forceinline__ double mc_forcing(const McArgs& a, int k, int j, int 
   return a.B[((size_t)k * a.nt + j) * a.P + col];
 }
 
-__host__ __device__ inline size_t mc_sweep_lds_doubles(int n, int pg, int K) {
-  // cur, X: [n][1 + pg] complex; hh, ph, av: [n] complex; yv, zv: [K][n] complex; fv: [K][pg]
-  return (size_t)2 * 2 * n * (1 + pg) + 2 * (3 * n + 2 * K * n) + (size_t)K * (pg > 0 ? pg : 1);
+__host__ __device__ inline size_t mc_sweep_lds_doubles(int n, int pg, int K, bool stage) {
+  // cur, X: [n][1 + pg] complex; hh, ph, av: [n] complex; yv, zv: [K][n] complex; fv: [K][pg];
+  // staged O and S_k: (1 + K) n^2
+  return (size_t)2 * 2 * n * (1 + pg) + 2 * (3 * n + 2 * K * n) + (size_t)K * (pg > 0 ? pg : 1) +
+         (stage ? (size_t)(1 + K) * n * n : 0);
 }
 
 // Forward sweep (Alg. 2, forward state sweep and tangent loop; eq. gradatheta with K directions)
@@ -227,6 +230,8 @@ __global__ __launch_bounds__(kThreads) void k_mc_forward(McArgs a) {
   double2* ph = hh + n;
   double2* yv = ph + n;                       // [K][n]
   double* fv = (double*)(yv + K * n + n);     // [K][pg] (after the unused av slot)
+  double* Ost = fv + K * a.pg;                // staged O_j, then S_k of the step
+  double* Sst = Ost + nn;
   // a_0 = V_0^T alpha in column 0, zero tangents
   const double* V0 = a.vfirst + (size_t)b * a.nchunks * nn;
   for (int idx = tid; idx < n * w; idx += kThreads) {
@@ -244,6 +249,16 @@ __global__ __launch_bounds__(kThreads) void k_mc_forward(McArgs a) {
   __syncthreads();
   for (int j = 0; j < nt; ++j) {
     const size_t es = (size_t)b * nt + j;
+    if (a.stage) {   // the previous step's reads of the staging area ended at its last barrier
+      if (need_y) {
+        const double* gs = a.sm + es * K * nn;
+        for (int idx = tid; idx < K * (int)nn; idx += kThreads) Sst[idx] = gs[idx];
+      }
+      if (j + 1 < nt) {
+        const double* go = a.ov + es * nn;
+        for (int idx = tid; idx < (int)nn; idx += kThreads) Ost[idx] = go[idx];
+      }
+    }
     for (int r = tid; r < n; r += kThreads) {
       const double2 h = phase(0.5 * a.lam[es * n + r], a.dt);
       hh[r] = h;
@@ -258,7 +273,7 @@ __global__ __launch_bounds__(kThreads) void k_mc_forward(McArgs a) {
       // y_k = -i dt h o (S_k (h o a)), S_k symmetric
       for (int t = tid; t < K * n; t += kThreads) {
         const int k = t / n, p = t - k * n;
-        const double* S = a.sm + (es * K + k) * nn;
+        const double* S = a.stage ? Sst + k * nn : a.sm + (es * K + k) * nn;
         double2 acc = make_double2(0.0, 0.0);
         for (int r = 0; r < n; ++r) {
           const double2 x = c_mul(hh[r], cur[r * w]);
@@ -292,7 +307,7 @@ __global__ __launch_bounds__(kThreads) void k_mc_forward(McArgs a) {
     }
     __syncthreads();
     if (j + 1 < nt) {
-      const double* O = a.ov + es * nn;
+      const double* O = a.stage ? Ost : a.ov + es * nn;
       for (int idx = tid; idx < n * w; idx += kThreads) {
         const int p = idx / w, col = idx - p * w;
         double2 acc = make_double2(0.0, 0.0);
@@ -343,6 +358,8 @@ __global__ __launch_bounds__(kThreads) void k_mc_backward(McArgs a) {
   double2* zv = av + n;                       // [K][n]
   double2* yv = zv + K * n;                   // [K][n]
   double* fv = (double*)(yv + K * n);         // [K][pg]
+  double* Ost = fv + K * a.pg;                // staged O_{j-1}, then S_k of the step
+  double* Sst = Ost + nn;
   for (int idx = tid; idx < n * w; idx += kThreads) {
     const int p = idx / w, col = idx - p * w;
     double2 v = make_double2(0.0, 0.0);
@@ -352,6 +369,14 @@ __global__ __launch_bounds__(kThreads) void k_mc_backward(McArgs a) {
   }
   for (int j = nt - 1; j >= 0; --j) {
     const size_t es = (size_t)b * nt + j;
+    if (a.stage) {   // the previous step's reads of the staging area ended at its last barrier
+      const double* gs = a.sm + es * K * nn;
+      for (int idx = tid; idx < K * (int)nn; idx += kThreads) Sst[idx] = gs[idx];
+      if (j >= 1) {
+        const double* go = a.ov + (es - 1) * nn;
+        for (int idx = tid; idx < (int)nn; idx += kThreads) Ost[idx] = go[idx];
+      }
+    }
     for (int r = tid; r < n; r += kThreads) {
       const double2 h = c_conj(phase(0.5 * a.lam[es * n + r], a.dt));
       hh[r] = h;
@@ -366,7 +391,7 @@ __global__ __launch_bounds__(kThreads) void k_mc_backward(McArgs a) {
     __syncthreads();
     for (int t = tid; t < K * n; t += kThreads) {
       const int k = t / n, p = t - k * n;
-      const double* S = a.sm + (es * K + k) * nn;
+      const double* S = a.stage ? Sst + k * nn : a.sm + (es * K + k) * nn;
       double2 acc = make_double2(0.0, 0.0);
       for (int r = 0; r < n; ++r) {
         const double2 x = c_mul(hh[r], cur[r * w]);
@@ -421,7 +446,7 @@ __global__ __launch_bounds__(kThreads) void k_mc_backward(McArgs a) {
         X[idx] = v;
       }
       __syncthreads();
-      const double* O = a.ov + (es - 1) * nn;   // O_{j-1}, applied transposed
+      const double* O = a.stage ? Ost : a.ov + (es - 1) * nn;   // O_{j-1}, applied transposed
       for (int idx = tid; idx < n * w; idx += kThreads) {
         const int p = idx / w, col = idx - p * w;
         double2 acc = make_double2(0.0, 0.0);
@@ -626,7 +651,7 @@ struct McAsmOut {
 };
 
 // Cost, gradient and Hessian (or HVP) of one theta per blockIdx.y; blockIdx.x splits the
-// P x P Hessian entries (block 0 also forms cost and gradient).
+// 4 x 4 tiles of the P x P Hessian (block 0 also forms cost and gradient).
 __global__ __launch_bounds__(kThreads) void k_mc_assemble(McArgs a, McAsmOut o) {
   __shared__ double red[kThreads];
   const int bx = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
@@ -655,29 +680,60 @@ __global__ __launch_bounds__(kThreads) void k_mc_assemble(McArgs a, McAsmOut o) 
     }
   }
   if (a.mode == (int)Mode::Hess) {
-    const int idx = bx * kThreads + tid;
-    if (idx < P * P) {
-      const int l = idx / P, m = idx - l * P;
-      double acc = 0.0;
-      for (int j = 0; j < nt; ++j) {
+    // 4 x 4 tiles of H: a block takes 64 tiles, each wave one slice of the steps (j = wave mod
+    // 4); per step and direction the tile's rows and columns of B_k and K_k, with the pair values
+    // folded as t_k = gamma B_k + K_k + sum_n s_kn B_n on the column block.  The four slices are
+    // added in LDS in a fixed order.
+    constexpr int kSlices = kThreads / 64;
+    __shared__ double part[kSlices][64][16];
+    const int tp = (P + 3) / 4;
+    const int tl = tid & 63, slice = tid >> 6;
+    const int tile = bx * 64 + tl;
+    double acc[4][4];
+    for (int x = 0; x < 4; ++x)
+      for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
+    if (tile < tp * tp) {
+      const int l0 = (tile / tp) * 4, m0 = (tile % tp) * 4;
+      for (int j = slice; j < nt; j += kSlices) {
         const size_t es = (size_t)b * nt + j;
-        double bl[kMaxCtl], bm[kMaxCtl];
+        double bl[kMaxCtl][4], bm[kMaxCtl][4], kl[kMaxCtl][4], km[kMaxCtl][4];
         for (int k = 0; k < K; ++k) {
-          bl[k] = Bk(k, j, l);
-          bm[k] = Bk(k, j, m);
-        }
-        for (int k = 0; k < K; ++k) {
-          const double kl = a.Km[(es * K + k) * P + l], km = a.Km[(es * K + k) * P + m];
-          acc = fma(bl[k], fma(o.gamma, bm[k], km), acc);
-          acc = fma(bm[k], kl, acc);
-          for (int nn2 = 0; nn2 < K; ++nn2) {
-            const double sv = a.s[es * npair + pair_index(min(k, nn2), max(k, nn2), K)];
-            acc = fma(bl[k] * bm[nn2], sv, acc);
+          const double* Bj = a.B + ((size_t)k * nt + j) * P;
+          const double* Kj = a.Km + (es * K + k) * P;
+          for (int x = 0; x < 4; ++x) {
+            bl[k][x] = l0 + x < P ? Bj[l0 + x] : 0.0;
+            kl[k][x] = l0 + x < P ? Kj[l0 + x] : 0.0;
+            bm[k][x] = m0 + x < P ? Bj[m0 + x] : 0.0;
+            km[k][x] = m0 + x < P ? Kj[m0 + x] : 0.0;
           }
         }
+        const double* sj = a.s + es * npair;
+        for (int k = 0; k < K; ++k) {
+          double t[4];
+          for (int y = 0; y < 4; ++y) t[y] = fma(o.gamma, bm[k][y], km[k][y]);
+          for (int nn2 = 0; nn2 < K; ++nn2) {
+            const double sv = sj[pair_index(min(k, nn2), max(k, nn2), K)];
+            for (int y = 0; y < 4; ++y) t[y] = fma(sv, bm[nn2][y], t[y]);
+          }
+          for (int x = 0; x < 4; ++x)
+            for (int y = 0; y < 4; ++y) acc[x][y] = fma(bl[k][x], t[y], fma(bm[k][y], kl[k][x], acc[x][y]));
+        }
       }
-      const size_t oi = (size_t)b * P * P + idx;
-      o.out[oi] = acc + o.aa[oi];
+    }
+    for (int x = 0; x < 4; ++x)
+      for (int y = 0; y < 4; ++y) part[slice][tl][4 * x + y] = acc[x][y];
+    __syncthreads();
+    for (int t = tid; t < 64 * 16; t += kThreads) {
+      const int tt = t >> 4, el = t & 15;
+      const int gt = bx * 64 + tt;
+      if (gt >= tp * tp) continue;
+      double v = 0.0;
+      for (int sl = 0; sl < kSlices; ++sl) v += part[sl][tt][el];
+      const int l = (gt / tp) * 4 + el / 4, m = (gt % tp) * 4 + el % 4;
+      if (l < P && m < P) {
+        const size_t oi = (size_t)b * P * P + (size_t)l * P + m;
+        o.out[oi] = v + o.aa[oi];
+      }
     }
   } else if (a.mode == (int)Mode::Hvp && bx == 0) {
     for (int l = tid; l < P; l += kThreads) {
@@ -835,10 +891,36 @@ qoc_status qoc_problem::enqueue_multi(Mode mode, int nb, const double* d_theta, 
   double* aa = (double*)take(sizeof(double) * nb * P * P);
   a.status = d_status;
   a.stats = d_stats;
-  // tangent columns per sweep workgroup: [n][1 + pg] twice must fit in LDS
-  int pg = ncols > 0 ? std::min(ncols, choose_pg(ncols, nb)) : 0;
-  while (pg > 1 && mc_sweep_lds_doubles(n, pg, K) * sizeof(double) > 160 * 1024) --pg;
+  // Sweep shape: the step's O and S_k are staged in LDS when they fit; the tangent columns per
+  // workgroup are the fewest of {8, 16, 32} that keep every (group, theta) workgroup resident at
+  // once (LDS per workgroup decides how many fit on a CU), else the widest that fits in LDS.
+  constexpr size_t kLds = 160 * 1024;
+  constexpr int kCUs = 256, kMaxWgPerCu = 8;
+  auto sweep_lds_of = [&](int pgv, bool st) { return mc_sweep_lds_doubles(n, pgv, K, st) * sizeof(double); };
+  int pg = 1;
+  bool stage = sweep_lds_of(1, true) <= kLds;
+  if (ncols > 0) {
+    bool chosen = false;
+    for (int cand : {8, 16, 32}) {
+      const int pgv = std::min(cand, ncols);
+      const bool st = sweep_lds_of(pgv, true) <= kLds;
+      const size_t l = sweep_lds_of(pgv, st);
+      if (l > kLds) break;
+      pg = pgv;
+      stage = st;
+      const long resident = (long)kCUs * std::min<long>(kMaxWgPerCu, (long)(kLds / l));
+      if ((long)((ncols + pgv - 1) / pgv) * nb <= resident || pgv == ncols) {
+        chosen = true;
+        break;
+      }
+    }
+    if (!chosen) {
+      while (pg > 1 && sweep_lds_of(pg, false) > kLds) --pg;
+      if (sweep_lds_of(pg, stage) > kLds) stage = false;
+    }
+  }
   a.pg = std::max(pg, 1);
+  a.stage = stage ? 1 : 0;
   const int ngroups = ncols > 0 ? (ncols + a.pg - 1) / a.pg : 1;
 
   hipError_t e0 = launch_fill_int(d_status, 1, 0, stream);
@@ -889,7 +971,7 @@ qoc_status qoc_problem::enqueue_multi(Mode mode, int nb, const double* d_theta, 
   QOC_MC_LAUNCH("boundary", launch_boundary(vw, stream));
   prof_begin("forward", &ev);
   const McArgs& af = a;
-  const size_t sweep_lds = mc_sweep_lds_doubles(n, a.pg, K) * sizeof(double);
+  const size_t sweep_lds = mc_sweep_lds_doubles(n, a.pg, K, a.stage != 0) * sizeof(double);
   hipLaunchKernelGGL(k_mc_forward, dim3(ngroups, nb), dim3(kThreads), sweep_lds, stream, af);
   e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "k_mc_forward");
@@ -929,7 +1011,8 @@ qoc_status qoc_problem::enqueue_multi(Mode mode, int nb, const double* d_theta, 
   o.out = d_out;
   o.gamma = gamma;
   o.rho = rho;
-  const int gx = mode == Mode::Hess ? std::max(1, (P * P + kThreads - 1) / kThreads) : 1;
+  const int tp = (P + 3) / 4;
+  const int gx = mode == Mode::Hess ? std::max(1, (tp * tp + 63) / 64) : 1;   // 64 tiles per block
   prof_begin("assemble", &ev);
   hipLaunchKernelGGL(k_mc_assemble, dim3(gx, nb), dim3(kThreads), 0, stream, a, o);
   e = hipGetLastError();
