@@ -72,6 +72,162 @@ __host__ __device__ inline int pair_index(int k, int n, int K) { return k * K - 
 
 // ---------------------------------------------------------------- eigen-data
 
+// Parallel-order (round-robin) Jacobi on the symmetric np x np A, rotations accumulated into V,
+// with the second-order perturbative finish of the one-direction kernels: at a sweep boundary
+// after the first sweep, once every off-diagonal F_ik is below kMcFinishRatio |d_k - d_i| (or
+// below tol_abs), the remaining sweeps are replaced by Rayleigh-Schroedinger perturbation about
+// d = diag(A) to second order,
+//   E_ik = F_ik / (d_k - d_i),  E2_ik = (F E)_ik / (d_k - d_i) (i != k),  E2_kk = -1/2 sum_i E_ik^2,
+//   V <- V (I + E + E2),  lambda_k = d_k + sum_i E_ik^2 (d_k - d_i),
+// with F E formed from E alone (F_im = E_im (d_m - d_i)); the neglected terms are third order in
+// the ratio.  The eigenvalues go to lam.  W is an np x np scratch (A is the other one during the
+// finish).  Each thread decodes its first two 2 x 2 blocks of A once.
+constexpr double kMcFinishRatio = 1e-5;
+
+__device__ bool mc_jacobi(double* A, double* V, double* W, double* lam, int np, double tol_abs, int max_sweeps,
+                          double* rot, int* prs, double* red, int* sweeps_done) {
+  const int tid = threadIdx.x;
+  const int half = np / 2;
+  const int nblk = half * (half + 1) / 2;
+  auto decode = [&](int w, int& I, int& K) {
+    I = (int)((2.0 * half + 1.0 - sqrt((2.0 * half + 1.0) * (2.0 * half + 1.0) - 8.0 * w)) * 0.5);
+    if (I < 0) I = 0;
+    while (I > 0 && I * half - I * (I - 1) / 2 > w) --I;
+    while ((I + 1) * half - (I + 1) * I / 2 <= w) ++I;
+    K = I + (w - (I * half - I * (I - 1) / 2));
+  };
+  int I0 = 0, K0 = 0, I1 = 0, K1 = 0;
+  if (tid < nblk) decode(tid, I0, K0);
+  if (tid + kThreads < nblk) decode(tid + kThreads, I1, K1);
+  for (int sweep = 0;; ++sweep) {
+    double loc = 0.0, ex = -1.0;
+    for (int idx = tid; idx < np * np; idx += kThreads) {
+      const int i = idx / np, k = idx - i * np;
+      if (i < k) {
+        const double f = fabs(A[idx]);
+        loc = fmax(loc, f);
+        if (f > tol_abs) ex = fmax(ex, f - kMcFinishRatio * fabs(A[k * np + k] - A[i * np + i]));
+      }
+    }
+    const double off = block_max(loc, red);
+    const double excess = sweep > 0 ? block_max(ex, red) : 1.0;
+    if (off <= tol_abs || excess <= 0.0) {
+      if (sweeps_done) *sweeps_done = sweep;
+      if (off <= tol_abs) {
+        for (int i = tid; i < np; i += kThreads) lam[i] = A[i * np + i];
+        __syncthreads();
+        return true;
+      }
+      // the finish: E in W (antisymmetric, zero where F is negligible)
+      for (int idx = tid; idx < np * np; idx += kThreads) {
+        const int i = idx / np, k = idx - i * np;
+        const double f = A[idx];
+        W[idx] = (i == k || fabs(f) <= tol_abs) ? 0.0 : f / (A[k * np + k] - A[i * np + i]);
+      }
+      for (int i = tid; i < np; i += kThreads) lam[i] = A[i * np + i];
+      __syncthreads();
+      // G = E + E2 into A (F is no longer needed: F E = sum_m E_im (d_m - d_i) E_mk)
+      for (int idx = tid; idx < np * np; idx += kThreads) {
+        const int i = idx / np, k = idx - i * np;
+        double g;
+        if (i == k) {
+          double ss = 0.0;
+          for (int m = 0; m < np; ++m) ss = fma(W[m * np + k], W[m * np + k], ss);
+          g = -0.5 * ss;
+        } else {
+          double fe = 0.0;
+          for (int m = 0; m < np; ++m) fe = fma(W[i * np + m] * (lam[m] - lam[i]), W[m * np + k], fe);
+          const double gap = lam[k] - lam[i];
+          g = W[idx] + (gap != 0.0 ? fe / gap : 0.0);   // exactly equal diagonal entries: no E2 term
+        }
+        A[idx] = g;
+      }
+      __syncthreads();
+      // lambda_k = d_k + sum_i E_ik^2 (d_k - d_i), read from W before it is overwritten
+      double lk = 0.0;
+      const int kk = tid;
+      if (kk < np) {
+        lk = lam[kk];
+        for (int i = 0; i < np; ++i) lk = fma(W[i * np + kk] * W[i * np + kk], lam[kk] - lam[i], lk);
+      }
+      __syncthreads();
+      gemm_sq<false>(V, A, W, np);   // W = V G
+      __syncthreads();
+      for (int idx = tid; idx < np * np; idx += kThreads) V[idx] += W[idx];
+      if (kk < np) lam[kk] = lk;
+      __syncthreads();
+      return true;
+    }
+    if (sweep >= max_sweeps) {
+      if (sweeps_done) *sweeps_done = sweep;
+      for (int i = tid; i < np; i += kThreads) lam[i] = A[i * np + i];
+      __syncthreads();
+      return false;
+    }
+    for (int r = 0; r < np - 1; ++r) {
+      if (tid < half) {
+        int p, q;
+        rr_pair(r, tid, np, p, q);
+        double c, s;
+        jacobi_rotation(A[p * np + p], A[q * np + q], A[p * np + q], c, s);
+        rot[2 * tid] = c;
+        rot[2 * tid + 1] = s;
+        prs[2 * tid] = p;
+        prs[2 * tid + 1] = q;
+      }
+      __syncthreads();
+      // A <- J^T A J on 2 x 2 blocks (I, K), I <= K; block (K, I) is the transpose
+      for (int w = tid; w < nblk; w += kThreads) {
+        int I, K;
+        if (w == tid) {
+          I = I0;
+          K = K0;
+        } else if (w == tid + kThreads) {
+          I = I1;
+          K = K1;
+        } else {
+          decode(w, I, K);
+        }
+        const int pI = prs[2 * I], qI = prs[2 * I + 1];
+        const int pK = prs[2 * K], qK = prs[2 * K + 1];
+        const double cI = rot[2 * I], sI = rot[2 * I + 1];
+        const double cK = rot[2 * K], sK = rot[2 * K + 1];
+        const double a00 = A[pI * np + pK], a01 = A[pI * np + qK];
+        const double a10 = A[qI * np + pK], a11 = A[qI * np + qK];
+        const double t00 = a00 * cK - a01 * sK, t01 = a00 * sK + a01 * cK;
+        const double t10 = a10 * cK - a11 * sK, t11 = a10 * sK + a11 * cK;
+        const double b00 = cI * t00 - sI * t10, b01 = cI * t01 - sI * t11;
+        const double b10 = sI * t00 + cI * t10, b11 = sI * t01 + cI * t11;
+        if (I == K) {
+          A[pI * np + pI] = b00;
+          A[pI * np + qI] = 0.0;
+          A[qI * np + pI] = 0.0;
+          A[qI * np + qI] = b11;
+        } else {
+          A[pI * np + pK] = b00;
+          A[pI * np + qK] = b01;
+          A[qI * np + pK] = b10;
+          A[qI * np + qK] = b11;
+          A[pK * np + pI] = b00;
+          A[qK * np + pI] = b01;
+          A[pK * np + qI] = b10;
+          A[qK * np + qI] = b11;
+        }
+      }
+      // V <- V J on column pairs
+      for (int w = tid; w < np * half; w += kThreads) {
+        const int i = w / half, K = w - i * half;
+        const int p = prs[2 * K], q = prs[2 * K + 1];
+        const double c = rot[2 * K], s = rot[2 * K + 1];
+        const double vp = V[i * np + p], vq = V[i * np + q];
+        V[i * np + p] = c * vp - s * vq;
+        V[i * np + q] = s * vp + c * vq;
+      }
+      __syncthreads();
+    }
+  }
+}
+
 __host__ __device__ inline size_t mc_eig_small_doubles(int np) { return (size_t)2 * np + kThreads + np + (np + 1) / 2 + kMaxCtl; }
 
 // One workgroup per (theta, chunk).  The first step of a chunk is decomposed cold; a later step
@@ -135,13 +291,12 @@ __global__ __launch_bounds__(kThreads) void k_mc_eig(McArgs a) {
     for (int idx = tid; idx < npp; idx += kThreads) loc += A[idx] * A[idx];
     const double fro = sqrt(block_sum(loc, red));
     int sweeps = 0;
-    const bool ok = jacobi_eig(A, V, np, a.tol_rel * fro, a.max_sweeps, rot, prs, red, &sweeps);
+    const bool ok = mc_jacobi(A, V, X, lamv, np, a.tol_rel * fro, a.max_sweeps, rot, prs, red, &sweeps);
     if (!ok && tid == 0) atomicOr(a.status, kStatusNoConv);
     if (ok && tid == 0 && a.stats) {
       atomicAdd(a.stats, 1ull);
       atomicAdd(a.stats + 1, (unsigned long long)sweeps);
     }
-    for (int i = tid; i < np; i += kThreads) lamv[i] = A[i * np + i];
     for (int k = tid; k < np; k += kThreads) normalize_column(V + k, np, np);
     __syncthreads();
     const size_t step = (size_t)b * nt + j;
