@@ -7,7 +7,7 @@ for a batch of independent control-coefficient vectors theta on the molecule-siz
 workload (N=36, J=4000 steps of dt=0.02, Fourier model with K=16 harmonics, P=32).
 Inputs are synthetic (seeded generators) and resident in HBM before timing starts.
 
-Prints one JSON line.  --gpus N with N > 1 exits: this build runs on one GPU.
+Prints one JSON line.  --gpus N with N > 1 exits: the benchmark runs on one GPU.
 """
 from __future__ import annotations
 
@@ -454,7 +454,7 @@ def main() -> int:
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build measures one GPU only (one process, one MI355X); "
+        print("bench.py: measures one GPU only (one process, one MI355X); "
               "--gpus above 1 is not supported", file=sys.stderr)
         return 2
 

@@ -1,5 +1,5 @@
 """Learned warm start: trained on solver-generated optima, it must cut trust-region iterations on
-held-out targets while the zero-start solve stays the judge of the final cost."""
+held-out targets while the zero-start solve stays the reference for the final cost."""
 import sys
 
 import numpy as np
