@@ -271,3 +271,32 @@ def test_benchmark_configuration_against_stored_oracle():
         _say(f"multi bench config theta {i}: dC={dc:.2e} dg={dg:.2e} dH={dh:.2e}")
         assert dc < TOL and dg < TOL and dh < TOL
     p.close()
+
+
+def test_autograd_with_three_directions():
+    """The torch.autograd layer (device entry points on torch's stream) on a three-direction
+    problem: cost, gradient and a Hessian-vector product by double backward against the oracle."""
+    import torch
+    from paper_2505_00529_amd import autograd as QA
+
+    n, nt, dt, kf = 6, 40, 0.05, 2
+    s, ms = _ops(n, 3, 96)
+    p = qoc.Problem(0)
+    p.set_system_multi(s.h0, ms, s.psi0, s.psi_target)
+    p.set_control_basis(qoc.QOC_BASIS_FOURIER, nt, dt, kf)
+    p.set_weights(0.3, 2.0)
+    bases = _fourier_stack(nt, dt, kf, 3)
+    th_np = inputs.draw_thetas(p.P, 1, 97, sigma=0.6)[0]
+    v_np = inputs.draw_directions(p.P, 1, 97)[0]
+    th = torch.tensor(th_np, dtype=torch.float64, device="cuda", requires_grad=True)
+    c = QA.cost(th, p)
+    (g,) = torch.autograd.grad(c, th, create_graph=True)
+    (hv,) = torch.autograd.grad(g, th, torch.tensor(v_np, dtype=torch.float64, device="cuda"))
+    p.sync()
+    cr, gr, hr = O.cost_grad_hess_multi(s.h0, ms, s.psi0, s.psi_target, bases, dt, th_np, 0.3, 2.0)
+    _say(f"autograd K=3: dC={_rel(c.item(), cr):.2e} dg={_rel(g.detach().cpu().numpy(), gr):.2e} "
+         f"dHv={_rel(hv.cpu().numpy(), hr @ v_np):.2e}")
+    assert _rel(c.item(), cr) < TOL
+    assert _rel(g.detach().cpu().numpy(), gr) < TOL
+    assert _rel(hv.cpu().numpy(), hr @ v_np) < TOL
+    p.close()
