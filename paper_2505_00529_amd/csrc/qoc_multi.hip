@@ -352,6 +352,680 @@ __global__ __launch_bounds__(kThreads) void k_mc_eig(McArgs a) {
   }
 }
 
+// ---------------------------------------------------------------- eigen-data at NP = 36
+
+// The circle-slot workgroup kernel of the one-direction path (V in registers, both ping-pong
+// copies of A in LDS, one barrier per round, second-order perturbative finish, basis products on
+// register tiles), for K directions: the cold start forms H0 + sum_k f_k M_k, the warm start
+// diag(l_{j-1}) + sum_k (f_kj - f_k,j-1) M~_k,j-1, the stopping tolerance comes from the Gram
+// matrix of (H0, M_1, .., M_K), and the step-end products run once per direction.
+
+template <int NP>
+struct McWgShape;
+template <>
+struct McWgShape<36> {
+  static constexpr int TPB = 256;        // threads per workgroup
+  static constexpr int RT = 2, CT = 3;   // 18 x 12 output tiles
+  static constexpr bool VP_LDS = true;
+  static constexpr int VW0 = 1, VW = 2;  // waves VW0 .. VW0+VW-1 hold V
+  static constexpr int VS = 6;           // pairs per V segment
+  static constexpr int WAVES = 4;        // waves per SIMD (five spill more than they hide)
+  static constexpr int LD = 36;          // row stride of the NP x NP LDS buffers
+};
+
+
+// Slot that slot x moves to in the circle shift after a round.
+template <int NP>
+__host__ __device__ constexpr int mc_slot_next(int x) {
+  return x == 0 ? 0 : ((x & 1) == 0 ? (x == 2 ? 1 : x - 2) : (x == NP - 1 ? NP - 2 : x + 2));
+}
+// Slot that moves into slot x.
+template <int NP>
+__host__ __device__ constexpr int mc_slot_prev(int x) {
+  return x == 0 ? 0 : ((x & 1) == 0 ? (x == NP - 2 ? NP - 1 : x + 2) : (x == 1 ? 2 : x - 2));
+}
+
+// Column x of the rotation J for (c, s): (c, -s) for the first index of the pair, (s, c) for
+// the second.
+__device__ __forceinline__ double2 mc_rot_col(double2 R, int second) {
+  return second ? make_double2(R.y, R.x) : make_double2(R.x, -R.y);
+}
+// One entry u^T [a00 a01; a10 a11] w of a rotated 2x2 block.
+__device__ __forceinline__ double mc_rotate_entry(double a00, double a01, double a10, double a11, double2 u, double2 w) {
+  return u.x * fma(a01, w.y, a00 * w.x) + u.y * fma(a11, w.y, a10 * w.x);
+}
+
+// B = J_I^T [a00 a01; a10 a11] J_K for the rotations RI = (c_I, s_I), RK = (c_K, s_K).
+__device__ __forceinline__ void mc_rotate_block(double a00, double a01, double a10, double a11, double2 RI, double2 RK,
+                                             double& b00, double& b01, double& b10, double& b11) {
+  const double t00 = a00 * RK.x - a01 * RK.y, t01 = a00 * RK.y + a01 * RK.x;
+  const double t10 = a10 * RK.x - a11 * RK.y, t11 = a10 * RK.y + a11 * RK.x;
+  b00 = RI.x * t00 - RI.y * t10;
+  b01 = RI.x * t01 - RI.y * t11;
+  b10 = RI.y * t00 + RI.x * t10;
+  b11 = RI.y * t01 + RI.x * t11;
+}
+
+template <int NP>
+__host__ __device__ constexpr size_t mc_eig_wg_lds_doubles() {
+  return (size_t)(McWgShape<NP>::VP_LDS ? 3 : 2) * NP * McWgShape<NP>::LD + 4 * (NP / 2) + NP +
+         2 * (McWgShape<NP>::TPB / 64) + kSincTerms + 16;   // tail: Gram matrix of up to 4 operators
+}
+
+// Sum / max over a workgroup of TPB threads from the wave partials (red: TPB/64 doubles of LDS).
+template <int TPB>
+__device__ __forceinline__ double mc_wg_sum(double v, double* red) {
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = 0.0;
+#pragma unroll
+  for (int w = 0; w < TPB / 64; ++w) r += red[w];
+  __syncthreads();
+  return r;
+}
+// Both maxima of a pair over a workgroup in one exchange (red: 2 TPB/64 doubles of LDS).
+template <int TPB>
+__device__ __forceinline__ double2 mc_wg_max2(double2 v, double* red) {
+  v.x = wave_max(v.x);
+  v.y = wave_max(v.y);
+  if ((threadIdx.x & 63) == 0) *(double2*)(red + 2 * (threadIdx.x >> 6)) = v;
+  __syncthreads();
+  double2 r = *(const double2*)red;
+#pragma unroll
+  for (int w = 1; w < TPB / 64; ++w) {
+    const double2 q = *(const double2*)(red + 2 * w);
+    r.x = fmax(r.x, q.x);
+    r.y = fmax(r.y, q.y);
+  }
+  __syncthreads();
+  return r;
+}
+template <int TPB>
+__device__ __forceinline__ double mc_wg_max(double v, double* red) {
+  v = wave_max(v);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = red[0];
+#pragma unroll
+  for (int w = 1; w < TPB / 64; ++w) r = fmax(r, red[w]);
+  __syncthreads();
+  return r;
+}
+
+template <int NP>
+__device__ __forceinline__ void body_mc_eig_wg(const McArgs& a, int c, int b) {
+  constexpr int H = NP / 2;
+  constexpr int NBLK = H * (H + 1) / 2;
+  constexpr int TPB = McWgShape<NP>::TPB;
+  constexpr int BPT = (NBLK + TPB - 1) / TPB;
+  constexpr int RT = McWgShape<NP>::RT, CT = McWgShape<NP>::CT;
+  constexpr int TCOLS = NP / CT;                  // tiles per output row
+  constexpr int NTILE = (NP / RT) * TCOLS;
+  constexpr bool VP_LDS = McWgShape<NP>::VP_LDS;
+  constexpr int VW0 = McWgShape<NP>::VW0, VW = McWgShape<NP>::VW;
+  constexpr int S = McWgShape<NP>::VS;          // pairs per V segment
+  constexpr int G = H / S;                       // segments per row
+  constexpr int VRW = NP / VW;                   // V rows per wave
+  constexpr int ROT0 = TPB - 64;                 // first thread forming the next rotations
+  constexpr int LD = McWgShape<NP>::LD;         // row stride of the NP x NP buffers in LDS
+  static_assert(NP % RT == 0 && NP % CT == 0 && NTILE <= TPB, "tile shape");
+  static_assert(H % S == 0 && S >= 2 && NP % VW == 0 && VRW * G <= 64 && VW0 + VW <= TPB / 64 - 1,
+                "register V layout");
+  extern __shared__ __attribute__((aligned(16))) double smem[];
+  double* A = smem;                              // NP x NP; also A buffer 0 during the sweeps
+  double* Vt = A + NP * LD;                      // NP x NP, column-major: Vt[k * LD + i] = V[i][k]; A buffer 1
+  double* Vp = VP_LDS ? Vt + NP * LD : nullptr;  // V_{j-1}, same layout
+  double2* rot = (double2*)(Vt + (VP_LDS ? 2 : 1) * NP * LD);  // 2 x H rotations (c, s)
+  double* lamv = (double*)(rot + 2 * H);         // eigenvalues
+  double* red = lamv + NP;                       // wave partials (pairs)
+  double* sinc_c = red + 2 * (TPB / 64);         // sinc series coefficients
+  double* gram = sinc_c + kSincTerms;            // <X_p, X_q> of X = (H0, M_1, .., M_K), p <= q
+  const int tid = threadIdx.x;
+  const int n = a.n, nt = a.nt, KD = a.K;
+  const int j0 = c * a.chunk;
+  const int j1 = min(nt, j0 + a.chunk);
+  if (j0 >= j1) return;
+  if (tid < kSincTerms) sinc_c[tid] = kSincCoef[tid];
+  const size_t nn = (size_t)n * n;
+  auto fk = [&](int kd, int j) { return a.f[((size_t)kd * a.nb + b) * nt + j]; };
+  auto opx = [&](int p) { return p == 0 ? a.h0 : a.m + (size_t)(p - 1) * nn; };
+  double* vpg = VP_LDS ? nullptr : a.gscratch + ((size_t)b * a.nchunks + c) * NP * LD;
+  // ||H_j||_F^2 = sum_pq c_p c_q <X_p, X_q> with c = (1, f_1j, .., f_Kj) sets each step's stopping
+  // tolerance (the Frobenius norm is invariant under the rotations), so no step needs a reduction
+  // for it: the Gram matrix of the K + 1 operators is summed once
+  for (int p = 0, gi = 0; p <= KD; ++p)
+    for (int q = p; q <= KD; ++q, ++gi) {
+      const double* xp = opx(p);
+      const double* xq = opx(q);
+      double s = 0.0;
+      for (int idx = tid; idx < (int)nn; idx += TPB) s = fma(xp[idx], xq[idx], s);
+      s = mc_wg_sum<TPB>(s, red);
+      if (tid == 0) gram[gi] = s;
+    }
+
+  // fixed 2x2 blocks (I <= K) of this thread: read offset in the current buffer and the four
+  // write offsets (upper triangle of the shifted slots) in the other one
+  int bI[BPT], bK[BPT], bw[BPT][4];
+#pragma unroll
+  for (int t = 0; t < BPT; ++t) {
+    const int w = tid + TPB * t;
+    int I = -1, K = 0;
+    if (w < NBLK) {
+      I = 0;
+      int rem = w;
+      while (rem >= H - I) {
+        rem -= H - I;
+        ++I;
+      }
+      K = I + rem;
+    }
+    bI[t] = I;
+    bK[t] = K;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int x = mc_slot_next<NP>(2 * max(I, 0) + (e >> 1)), y = mc_slot_next<NP>(2 * K + (e & 1));
+      bw[t][e] = min(x, y) * LD + max(x, y);
+    }
+  }
+  // next-round rotation formed by this thread (pair kr of the next round): its even slot comes
+  // from slot es, its odd slot from slot os; the off-diagonal entry is element (ep, op) of the
+  // round's block (I0, K0)
+  const int kr = tid - ROT0;
+  const bool has_rot = kr >= 0 && kr < H;
+  const int es = mc_slot_prev<NP>(2 * kr), os = mc_slot_prev<NP>(2 * kr + 1);
+  const int I0 = min(es, os) >> 1, K0 = max(es, os) >> 1;
+  const int rpar = (es < os ? es : os) & 1, cpar = (es < os ? os : es) & 1;
+  // V registers
+  const int lane = tid & 63;
+  const int vseg = lane % G;                     // segment: pairs vseg*S .. vseg*S+S-1
+  const bool v_wave = (tid >> 6) >= VW0 && (tid >> 6) < VW0 + VW;
+  const bool v_on = v_wave && lane < VRW * G;
+  const int vrow = ((tid >> 6) - VW0) * VRW + lane / G;
+  double ve[S], vo[S];
+  // output tile of this thread
+  const int tr = tid / TCOLS, tc = tid - (tid / TCOLS) * TCOLS;
+  const bool has_tile = tid < NTILE;
+  const int i0 = tr * RT, k0 = tc * CT;
+
+  for (int j = j0; j < j1; ++j) {
+    if (j == j0) {
+      for (int idx = tid; idx < NP * NP; idx += TPB) {
+        const int i = idx / NP, k = idx - (idx / NP) * NP;
+        double v = 0.0;
+        if (i < n && k < n) {
+          v = a.h0[i * n + k];
+          for (int kd = 0; kd < KD; ++kd) v = fma(fk(kd, j), a.m[kd * nn + i * n + k], v);
+        }
+        A[i * LD + k] = v;
+      }
+#pragma unroll
+      for (int k = 0; k < S; ++k) {
+        const int K = vseg * S + k;
+        ve[k] = (v_on && vrow == 2 * K) ? 1.0 : 0.0;
+        vo[k] = (v_on && vrow == 2 * K + 1) ? 1.0 : 0.0;
+      }
+    } else {
+      // diag(l_{j-1}) + sum_k (f_kj - f_k,j-1) M~_k,j-1: A holds M~ of the last direction, the
+      // others come back from this workgroup's own stores of the previous step
+      const double dfl = fk(KD - 1, j) - fk(KD - 1, j - 1);
+      const size_t sp = (size_t)b * nt + (j - 1);
+      for (int idx = tid; idx < NP * NP; idx += TPB) {
+        const int i = idx / NP, k = idx - (idx / NP) * NP;
+        double v = dfl * A[i * LD + k] + (i == k ? lamv[i] : 0.0);
+        if (i < n && k < n)
+          for (int kd = 0; kd + 1 < KD; ++kd)
+            v = fma(fk(kd, j) - fk(kd, j - 1), a.mt[(sp * KD + kd) * nn + (size_t)i * n + k], v);
+        A[i * LD + k] = v;
+        if (VP_LDS) Vp[i * LD + k] = Vt[i * LD + k];
+      }
+      // V_{j-1} back into registers (not kept live through the basis products)
+#pragma unroll
+      for (int k = 0; k < S; ++k) {
+        const int K = vseg * S + k;
+        ve[k] = v_on ? Vt[(2 * K) * LD + vrow] : 0.0;
+        vo[k] = v_on ? Vt[(2 * K + 1) * LD + vrow] : 0.0;
+      }
+    }
+    __syncthreads();
+    double hf = 0.0;
+    for (int p = 0, gi = 0; p <= KD; ++p) {
+      const double cp = p == 0 ? 1.0 : fk(p - 1, j);
+      for (int q = p; q <= KD; ++q, ++gi) {
+        const double cq = q == 0 ? 1.0 : fk(q - 1, j);
+        hf = fma((p == q ? 1.0 : 2.0) * cp * cq, gram[gi], hf);
+      }
+    }
+    const double tol = a.tol_rel * sqrt(fmax(hf, 0.0));
+    int cur = 0, rb = 0;                           // current A buffer and rotation buffer
+    bool finished = false;                         // perturbative finish taken (V_j formed below)
+#pragma unroll 1
+    for (int sweep = 0;; ++sweep) {
+      double* Ac = cur ? Vt : A;
+      // sweep boundary: slot order is the index order
+      if (tid < NP) lamv[tid] = Ac[tid * LD + tid];
+      __syncthreads();
+      // largest off-diagonal entry, and (after the first sweep) largest excess of |F_ik| over the
+      // finish bound
+      double off = 0.0, excess = -1.0;
+      for (int idx = tid; idx < NP * NP; idx += TPB) {
+        const int i = idx / NP, k = idx - (idx / NP) * NP;
+        if (i < k) {
+          const double v = fabs(Ac[i * LD + k]);
+          off = fmax(off, v);
+          if (sweep > 0) excess = fmax(excess, v - kMcFinishRatio * fabs(lamv[k] - lamv[i]));
+        }
+      }
+      const double2 oe = mc_wg_max2<TPB>(make_double2(off, excess), red);
+      off = oe.x;
+      if (off <= tol) {
+        if (tid == 0 && a.stats) {
+          atomicAdd(a.stats, 1ull);
+          atomicAdd(a.stats + 1, (unsigned long long)sweep);
+        }
+        break;
+      }
+      if (sweep >= a.max_sweeps) {
+        if (tid == 0) atomicOr(a.status, kStatusNoConv);
+        break;
+      }
+      if (sweep > 0 && oe.y <= 0.0) {
+        // Perturbative finish: with A = diag(d) + F and every |F_ik| <= 1e-5 |d_k - d_i|, the
+        // eigenvectors are the columns of W = I + E + E2 and the eigenvalues are
+        // d_k + sum_i F_ik E_ik, to within terms of third order in E, where
+        //   E_ik = F_ik / (d_k - d_i)                       (first order, antisymmetric),
+        //   E2_ik = (F E)_ik / (d_k - d_i) (i != k),  E2_kk = -1/2 sum_i E_ik^2
+        // (Rayleigh-Schroedinger perturbation theory about diag(d); F has a zero diagonal).
+        // So V_j = V W and those eigenvalues replace the remaining sweeps.  E^T goes into A's
+        // buffer in place (Ac[k][i] = E_ik), V into the other one; the second-order terms are
+        // formed below from E alone.
+        for (int idx = tid; idx < NP * NP; idx += TPB) {
+          const int i = idx / NP, k = idx - (idx / NP) * NP;
+          if (i < k) {
+            const double f = Ac[i * LD + k];
+            const double e = f == 0.0 ? 0.0 : f / (lamv[k] - lamv[i]);
+            Ac[k * LD + i] = e;
+            Ac[i * LD + k] = -e;
+          } else if (i == k) {
+            Ac[i * LD + k] = 0.0;
+          }
+        }
+        double* Vo = cur ? A : Vt;
+        if (v_on) {
+#pragma unroll
+          for (int k = 0; k < S; ++k) {
+            const int K = vseg * S + k;
+            Vo[(2 * K) * LD + vrow] = ve[k];
+            Vo[(2 * K + 1) * LD + vrow] = vo[k];
+          }
+        }
+        if (tid == 0 && a.stats) {
+          atomicAdd(a.stats, 1ull);
+          atomicAdd(a.stats + 1, (unsigned long long)sweep);
+        }
+        finished = true;
+        break;
+      }
+      if (sweep == 0) {
+        // first rotations of the step; later sweeps get theirs from the last round before
+        if (has_rot) {
+          double cc, ss;
+          jacobi_rotation(Ac[(2 * kr) * LD + 2 * kr], Ac[(2 * kr + 1) * LD + 2 * kr + 1], Ac[(2 * kr) * LD + 2 * kr + 1],
+                          cc, ss);
+          rot[rb * H + kr] = make_double2(cc, ss);
+        }
+        __syncthreads();
+      }
+      // One round with the current A buffer and rotation buffer PAR (they flip together every
+      // round); instantiated for both parities so that every LDS address is a fixed offset.
+      auto round = [&](auto par) {
+        constexpr int PAR = decltype(par)::value;
+        const double* Ar = PAR ? Vt : A;
+        double* An = PAR ? A : Vt;
+        const double2* R = rot + PAR * H;
+#pragma unroll
+        for (int t = 0; t < BPT; ++t) {
+          const int I = bI[t];
+          if (I >= 0) {
+            const int K = bK[t];
+            const double2 RI = R[I], RK = R[K];
+            const double2 r0 = *(const double2*)(Ar + (2 * I) * LD + 2 * K);
+            const double2 r1 = *(const double2*)(Ar + (2 * I + 1) * LD + 2 * K);
+            // a diagonal block (I == K) is symmetric: its lower entry is not stored, and the
+            // rotation annihilates its off-diagonal pair (both writes go to one place)
+            const bool dg = I == K;
+            double b00, b01, b10, b11;
+            mc_rotate_block(r0.x, r0.y, dg ? r0.y : r1.x, r1.y, RI, RK, b00, b01, b10, b11);
+            An[bw[t][0]] = b00;
+            An[bw[t][1]] = dg ? 0.0 : b01;
+            An[bw[t][2]] = dg ? 0.0 : b10;
+            An[bw[t][3]] = b11;
+          }
+        }
+        if (has_rot) {
+          // the next round's pair kr: new diagonal entries of slots es and os (each from its
+          // round-r diagonal block) and the new entry (es, os) (from block (I0, K0))
+          // (the two slots lie in pairs I0 < K0, whose diagonal blocks give the diagonal entries)
+          const double2 uI = mc_rot_col(R[I0], rpar), uK = mc_rot_col(R[K0], cpar);
+          const double2 gI = *(const double2*)(Ar + (2 * I0) * LD + 2 * I0);
+          const double gI11 = Ar[(2 * I0 + 1) * LD + 2 * I0 + 1];
+          const double2 gK = *(const double2*)(Ar + (2 * K0) * LD + 2 * K0);
+          const double gK11 = Ar[(2 * K0 + 1) * LD + 2 * K0 + 1];
+          const double2 r0 = *(const double2*)(Ar + (2 * I0) * LD + 2 * K0);
+          const double2 r1 = *(const double2*)(Ar + (2 * I0 + 1) * LD + 2 * K0);
+          const double dI = mc_rotate_entry(gI.x, gI.y, gI.y, gI11, uI, uI);
+          const double dK = mc_rotate_entry(gK.x, gK.y, gK.y, gK11, uK, uK);
+          const double e = mc_rotate_entry(r0.x, r0.y, r1.x, r1.y, uI, uK);
+          double cc, ss;
+          jacobi_rotation_nobranch(es < os ? dI : dK, es < os ? dK : dI, e, cc, ss);
+          rot[(PAR ^ 1) * H + kr] = make_double2(cc, ss);
+        }
+        if (v_wave) {
+          double e[S], o[S];
+#pragma unroll
+          for (int k = 0; k < S; ++k) {
+            const double2 RV = R[vseg * S + k];
+            e[k] = RV.x * ve[k] - RV.y * vo[k];
+            o[k] = RV.y * ve[k] + RV.x * vo[k];
+          }
+          const double e_next = dpp_move<kDppFromNext>(e[0]);       // next segment's first even
+          const double o_prev = dpp_move<kDppFromPrev>(o[S - 1]);   // previous segment's last odd
+          // circle shift: even columns move down one pair, odd ones up; pair 0's even stays,
+          // its odd takes pair 1's even, and pair H-1's even takes its own odd
+          ve[0] = vseg == 0 ? e[0] : e[1];
+#pragma unroll
+          for (int k = 1; k < S - 1; ++k) ve[k] = e[k + 1];
+          ve[S - 1] = vseg == G - 1 ? o[S - 1] : e_next;
+          vo[0] = vseg == 0 ? e[1] : o_prev;
+#pragma unroll
+          for (int k = 1; k < S; ++k) vo[k] = o[k - 1];
+        }
+        __syncthreads();
+      };
+      const std::integral_constant<int, 0> par0;
+      const std::integral_constant<int, 1> par1;
+      // NP - 1 (odd) rounds: the parity flips over a sweep
+      if (cur == 0) {
+#pragma unroll 1
+        for (int r = 0; r + 1 < NP - 1; r += 2) {
+          round(par0);
+          round(par1);
+        }
+        round(par0);
+      } else {
+#pragma unroll 1
+        for (int r = 0; r + 1 < NP - 1; r += 2) {
+          round(par1);
+          round(par0);
+        }
+        round(par1);
+      }
+      cur ^= 1;
+      rb ^= 1;
+    }
+    // lambda_j is in lamv (set at the last sweep boundary); V_j to Vt
+    if (finished) {
+      double* Ac = cur ? Vt : A;
+      const double* Vo = cur ? A : Vt;
+      __syncthreads();
+      // Second-order terms from E alone.  F_im = E_im (d_m - d_i) and E is antisymmetric, so
+      // rows of Ac serve both factors of (F E)_ik = sum_m E_im (d_m - d_i) E_mk, with
+      // E_im (d_m - d_i) = Ac[i][m] (d_i - d_m) and E_mk = Ac[k][m].  The diagonal needs only
+      // column sums: E2_kk = -s1_k / 2 and lambda_k = d_k + d_k s1_k - s2_k with
+      // s1_k = sum_i E_ik^2, s2_k = sum_i E_ik^2 d_i.
+      // Tile (x, y) is column k = i0 + x, row i = k0 + y, as in the product below.
+      double lam_new = 0.0;
+      {
+        double fe[RT][CT];
+        if (has_tile) {
+          double di[CT];
+#pragma unroll
+          for (int y = 0; y < CT; ++y) di[y] = lamv[k0 + y];
+#pragma unroll
+          for (int x = 0; x < RT; ++x)
+#pragma unroll
+            for (int y = 0; y < CT; ++y) fe[x][y] = 0.0;
+#pragma unroll 2
+          for (int r = 0; r < NP; r += 2) {
+            double2 u[RT], w[CT];
+#pragma unroll
+            for (int x = 0; x < RT; ++x) u[x] = *(const double2*)(Ac + (i0 + x) * LD + r);   // E_{r,k}, E_{r+1,k}
+            const double d0 = lamv[r], d1 = lamv[r + 1];
+#pragma unroll
+            for (int y = 0; y < CT; ++y) {
+              const double2 q = *(const double2*)(Ac + (k0 + y) * LD + r);   // -E_{i,r}, -E_{i,r+1}
+              w[y] = make_double2(q.x * (di[y] - d0), q.y * (di[y] - d1));   // F_{i,r}, F_{i,r+1}
+            }
+#pragma unroll
+            for (int x = 0; x < RT; ++x)
+#pragma unroll
+              for (int y = 0; y < CT; ++y) fe[x][y] = fma(u[x].y, w[y].y, fma(u[x].x, w[y].x, fe[x][y]));
+          }
+        }
+        double s1 = 0.0, s2 = 0.0;
+        if (tid < NP) {
+          for (int i = 0; i < NP; i += 2) {
+            const double2 q = *(const double2*)(Ac + tid * LD + i);   // E_{i,k}, E_{i+1,k}, k = tid
+            const double q0 = q.x * q.x, q1 = q.y * q.y;
+            s1 += q0 + q1;
+            s2 = fma(q0, lamv[i], fma(q1, lamv[i + 1], s2));
+          }
+        }
+        __syncthreads();   // every row of Ac read
+        if (has_tile) {
+#pragma unroll
+          for (int x = 0; x < RT; ++x)
+#pragma unroll
+            for (int y = 0; y < CT; ++y) {
+              const int k = i0 + x, i = k0 + y;
+              const double den = lamv[k] - lamv[i];
+              if (i != k && den != 0.0) Ac[k * LD + i] += fe[x][y] / den;   // (E + E2)^T
+            }
+        }
+        if (tid < NP) {
+          Ac[tid * LD + tid] = -0.5 * s1;
+          lam_new = lamv[tid] + lamv[tid] * s1 - s2;   // written to lamv once no thread reads it
+        }
+      }
+      // V_j = V + V (W - I) from V (in Vo) and (W - I)^T (in Ac)
+      __syncthreads();
+      if (tid < NP) lamv[tid] = lam_new;   // the product below reads only Ac and Vo
+      double acc[RT][CT];
+      if (has_tile) {
+#pragma unroll
+        for (int x = 0; x < RT; ++x)
+#pragma unroll
+          for (int y = 0; y < CT; ++y) acc[x][y] = Vo[(i0 + x) * LD + k0 + y];
+#pragma unroll 2
+        for (int r = 0; r < NP; r += 2) {
+          double2 u[RT], w[CT];
+#pragma unroll
+          for (int x = 0; x < RT; ++x) u[x] = *(const double2*)(Ac + (i0 + x) * LD + r);   // E_{r,k}, E_{r+1,k}
+#pragma unroll
+          for (int y = 0; y < CT; ++y) w[y] = make_double2(Vo[r * LD + k0 + y], Vo[(r + 1) * LD + k0 + y]);
+#pragma unroll
+          for (int x = 0; x < RT; ++x)
+#pragma unroll
+            for (int y = 0; y < CT; ++y) acc[x][y] = fma(u[x].y, w[y].y, fma(u[x].x, w[y].x, acc[x][y]));
+        }
+      }
+      __syncthreads();
+      if (has_tile) {
+#pragma unroll
+        for (int x = 0; x < RT; ++x)
+#pragma unroll
+          for (int y = 0; y < CT; ++y) Vt[(i0 + x) * LD + k0 + y] = acc[x][y];
+      }
+    } else if (v_on) {
+#pragma unroll
+      for (int k = 0; k < S; ++k) {
+        const int K = vseg * S + k;
+        Vt[(2 * K) * LD + vrow] = ve[k];
+        Vt[(2 * K + 1) * LD + vrow] = vo[k];
+      }
+    }
+    __syncthreads();
+    // V_j carries into the next step: unit columns (column k of V is row k of Vt)
+    if (tid < NP) normalize_column_contig(Vt + tid * LD, NP);
+    __syncthreads();
+    const size_t step = (size_t)b * nt + j;
+    double acc[RT][CT];
+    // Basis products on register tiles.  Their inner index r runs over all NP (V and X vanish
+    // in the padding rows), two values per 16-byte load: column-major V, and X stored
+    // transposed.
+    // O_{j-1} = V_j^T V_{j-1}
+    if (j > j0 && has_tile) {
+#pragma unroll
+      for (int x = 0; x < RT; ++x)
+#pragma unroll
+        for (int y = 0; y < CT; ++y) acc[x][y] = 0.0;
+      const double* Vprev = VP_LDS ? Vp : vpg;
+#pragma unroll 2
+      for (int r = 0; r < NP; r += 2) {
+        double2 u[RT], w[CT];
+#pragma unroll
+        for (int x = 0; x < RT; ++x) u[x] = *(const double2*)(Vt + (i0 + x) * LD + r);
+#pragma unroll
+        for (int y = 0; y < CT; ++y) w[y] = *(const double2*)(Vprev + (k0 + y) * LD + r);
+#pragma unroll
+        for (int x = 0; x < RT; ++x)
+#pragma unroll
+          for (int y = 0; y < CT; ++y) acc[x][y] = fma(u[x].y, w[y].y, fma(u[x].x, w[y].x, acc[x][y]));
+      }
+      double* dst = a.ov + (step - 1) * nn;
+#pragma unroll
+      for (int x = 0; x < RT; ++x)
+#pragma unroll
+        for (int y = 0; y < CT; ++y)
+          if (i0 + x < n && k0 + y < n) dst[(size_t)(i0 + x) * n + k0 + y] = acc[x][y];
+    }
+    // per direction (the last one stays in A for the next step's warm start):
+    for (int kd = 0; kd < KD; ++kd) {
+    const double* mk = a.m + (size_t)kd * nn;
+    // X = M V_j, transposed (X^T[k][i] = X[i][k]; M symmetric: row i of M is column i).  With
+    // V_{j-1} in LDS (NP = 36), M is staged into A (free after the sweeps) and X goes to Vp
+    // (free after the O product); without that room (NP = 64) X reads M from global memory and
+    // goes to A.
+    double* Xt = VP_LDS ? Vp : A;
+    if (VP_LDS) {
+      for (int idx = tid; idx < NP * NP; idx += TPB) {
+        const int i = idx / NP, k = idx - (idx / NP) * NP;
+        A[i * LD + k] = (i < n && k < n) ? mk[i * n + k] : 0.0;
+      }
+      __syncthreads();
+    }
+    if (has_tile) {
+#pragma unroll
+      for (int x = 0; x < RT; ++x)
+#pragma unroll
+        for (int y = 0; y < CT; ++y) acc[x][y] = 0.0;
+      if (VP_LDS) {
+#pragma unroll 2
+        for (int r = 0; r < NP; r += 2) {
+          double2 u[RT], w[CT];
+#pragma unroll
+          for (int x = 0; x < RT; ++x) u[x] = *(const double2*)(A + (i0 + x) * LD + r);
+#pragma unroll
+          for (int y = 0; y < CT; ++y) w[y] = *(const double2*)(Vt + (k0 + y) * LD + r);
+#pragma unroll
+          for (int x = 0; x < RT; ++x)
+#pragma unroll
+            for (int y = 0; y < CT; ++y) acc[x][y] = fma(u[x].y, w[y].y, fma(u[x].x, w[y].x, acc[x][y]));
+        }
+      } else {
+#pragma unroll 2
+        for (int r = 0; r < n; r += 2) {
+          double2 u[RT], w[CT];
+#pragma unroll
+          for (int x = 0; x < RT; ++x) {
+            const bool row = i0 + x < n;
+            u[x].x = row ? mk[(i0 + x) * n + r] : 0.0;
+            u[x].y = row && r + 1 < n ? mk[(i0 + x) * n + r + 1] : 0.0;
+          }
+#pragma unroll
+          for (int y = 0; y < CT; ++y) w[y] = *(const double2*)(Vt + (k0 + y) * LD + r);
+#pragma unroll
+          for (int x = 0; x < RT; ++x)
+#pragma unroll
+            for (int y = 0; y < CT; ++y) acc[x][y] = fma(u[x].y, w[y].y, fma(u[x].x, w[y].x, acc[x][y]));
+        }
+      }
+#pragma unroll
+      for (int y = 0; y < CT; ++y)
+#pragma unroll
+        for (int x = 0; x < RT; ++x) Xt[(k0 + y) * LD + i0 + x] = acc[x][y];
+    }
+    __syncthreads();
+    // Mt_j = V_j^T X, kept in A for the next step's warm start and written out with S_j
+    if (has_tile) {
+#pragma unroll
+      for (int x = 0; x < RT; ++x)
+#pragma unroll
+        for (int y = 0; y < CT; ++y) acc[x][y] = 0.0;
+#pragma unroll 2
+      for (int r = 0; r < NP; r += 2) {
+        double2 u[RT], w[CT];
+#pragma unroll
+        for (int x = 0; x < RT; ++x) u[x] = *(const double2*)(Vt + (i0 + x) * LD + r);
+#pragma unroll
+        for (int y = 0; y < CT; ++y) w[y] = *(const double2*)(Xt + (k0 + y) * LD + r);
+#pragma unroll
+        for (int x = 0; x < RT; ++x)
+#pragma unroll
+          for (int y = 0; y < CT; ++y) acc[x][y] = fma(u[x].y, w[y].y, fma(u[x].x, w[y].x, acc[x][y]));
+      }
+    }
+    // (NP = 36: A held M, whose last reads were before the barrier above)
+    if (!VP_LDS) __syncthreads();
+    if (has_tile) {
+#pragma unroll
+      for (int x = 0; x < RT; ++x)
+#pragma unroll
+        for (int y = 0; y < CT; ++y) A[(i0 + x) * LD + k0 + y] = acc[x][y];
+    }
+    {
+      // M~_k,j (always: the next step's warm start reads it back) and S_k,j from LDS in one
+      // coalesced pass (row i, column k of entry idx, stepped without divisions)
+      __syncthreads();
+      double* mt = a.mt + (step * KD + kd) * nn;
+      double* sm = a.sm + (step * KD + kd) * nn;
+      const int dr = TPB / n, dc = TPB - (TPB / n) * n;
+      int i = tid / n, k = tid - (tid / n) * n;
+#pragma unroll 1
+      for (int idx = tid; idx < (int)nn; idx += TPB) {
+        const double v = A[i * LD + k];
+        mt[idx] = v;
+        if (a.store_derivs) sm[idx] = sinc_table(0.5 * a.dt * (lamv[i] - lamv[k]), sinc_c) * v;
+        i += dr;
+        k += dc;
+        if (k >= n) {
+          k -= n;
+          ++i;
+        }
+      }
+    }
+    __syncthreads();   // A and Xt are read above; the next direction restages them
+    }
+    // eigenvalues, V_j for the next step's overlap, and the chunk ends
+    if (tid < n) a.lam[step * n + tid] = lamv[tid];
+    for (int idx = tid; idx < NP * NP; idx += TPB) {
+      const int k = idx / NP, i = idx - (idx / NP) * NP;   // Vt[k * LD + i] = V[i][k]
+      const double v = Vt[k * LD + i];
+      if (!VP_LDS) vpg[k * LD + i] = v;
+      if (i < n && k < n) {
+        if (j == j0) a.vfirst[((size_t)b * a.nchunks + c) * nn + (size_t)i * n + k] = v;
+        if (j == j1 - 1) a.vlast[((size_t)b * a.nchunks + c) * nn + (size_t)i * n + k] = v;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+
+__global__ __launch_bounds__(McWgShape<36>::TPB, McWgShape<36>::WAVES) void k_mc_eig_wg36(McArgs a) {
+  body_mc_eig_wg<36>(a, blockIdx.x, blockIdx.y);
+}
+
 // ---------------------------------------------------------------- sweeps
 
 // Forcing coefficient of direction k for tangent column `col` (global index) at step j: B_k[j,
@@ -910,7 +1584,8 @@ __global__ __launch_bounds__(kThreads) void k_mc_assemble(McArgs a, McAsmOut o) 
 }
 
 hipError_t configure_mc_kernels() {
-  const void* fns[] = {(const void*)k_mc_eig, (const void*)k_mc_forward, (const void*)k_mc_backward};
+  const void* fns[] = {(const void*)k_mc_eig, (const void*)k_mc_eig_wg36, (const void*)k_mc_forward,
+                       (const void*)k_mc_backward};
   for (const void* f : fns) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
@@ -1099,9 +1774,14 @@ qoc_status qoc_problem::enqueue_multi(Mode mode, int nb, const double* d_theta, 
     QOC_MC_LAUNCH("controls", launch_controls(bs, d_theta, f + (size_t)k * nb * nt, nb, stream));
     if (mode == Mode::Hvp) QOC_MC_LAUNCH("controls", launch_controls(bs, d_v, u + (size_t)k * nb * nt, nb, stream));
   }
-  const size_t eig_lds = (mc_eig_small_doubles(np) + (a.lds_mats ? (size_t)4 * np * np : 0)) * sizeof(double);
   prof_begin("eig", &ev);
-  hipLaunchKernelGGL(k_mc_eig, dim3(a.nchunks, nb), dim3(kThreads), eig_lds, stream, a);
+  if (np == 36) {
+    hipLaunchKernelGGL(k_mc_eig_wg36, dim3(a.nchunks, nb), dim3(McWgShape<36>::TPB),
+                       mc_eig_wg_lds_doubles<36>() * sizeof(double), stream, a);
+  } else {
+    const size_t eig_lds = (mc_eig_small_doubles(np) + (a.lds_mats ? (size_t)4 * np * np : 0)) * sizeof(double);
+    hipLaunchKernelGGL(k_mc_eig, dim3(a.nchunks, nb), dim3(kThreads), eig_lds, stream, a);
+  }
   e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "k_mc_eig");
   prof_end("eig", ev);
