@@ -13,9 +13,9 @@
 //                  + sum_kn B_k[j,l] B_n[j,m] s_{kn,j} ] + rho Re(A'_l^H A'_m),
 //   (Hv)_l = sum_j sum_k B_k[j,l] (gamma u_kj + e_kj + sum_n s_{kn,j} u_nj),   u_k = B_k v.
 //
-// These kernels are a simpler form of the path than the tuned single-direction ones: one
-// workgroup per (theta, chunk) for the eigen-data (a parallel-order Jacobi with the second-order
-// perturbative finish), per (column group, theta) for the sweeps (the step's O and S_k staged in
+// Kernels: one workgroup per (theta, chunk) for the eigen-data (at NP = 36 the circle-slot
+// kernel of the single-direction path extended to K directions; other sizes a parallel-order
+// Jacobi with the same second-order perturbative finish), per (column group, theta) for the sweeps (the step's O and S_k staged in
 // LDS when they fit), per (step, theta) for the U'' contraction (the moment series, or the
 // divided differences of every triple for wide spectra), 4 x 4 tiles for the assembly.  The chunk
 // joins (k_boundary_overlap) and the terminal kernel are shared with the single-direction path.
