@@ -1100,19 +1100,25 @@ __global__ __launch_bounds__(kThreads) void k_mc_forward(McArgs a) {
     }
     __syncthreads();
     if (need_y) {
-      // y_k = -i dt h o (S_k (h o a)), S_k symmetric
-      for (int t = tid; t < K * n; t += kThreads) {
+      // y_k = -i dt h o (S_k (h o a)), S_k symmetric; four adjacent lanes per (direction, row),
+      // each summing every fourth r (whole quads stay active: 4 K n and kThreads are multiples
+      // of four)
+      for (int t4 = tid; t4 < 4 * K * n; t4 += kThreads) {
+        const int t = t4 >> 2, part = t4 & 3;
         const int k = t / n, p = t - k * n;
         const double* S = a.stage ? Sst + k * nn : a.sm + (es * K + k) * nn;
         double2 acc = make_double2(0.0, 0.0);
-        for (int r = 0; r < n; ++r) {
+        for (int r = part; r < n; r += 4) {
           const double2 x = c_mul(hh[r], cur[r * w]);
           const double sv = S[(size_t)r * n + p];
           acc.x = fma(sv, x.x, acc.x);
           acc.y = fma(sv, x.y, acc.y);
         }
-        const double2 hp = c_mul(hh[p], acc);
-        yv[k * n + p] = make_double2(a.dt * hp.y, -a.dt * hp.x);
+        acc = quad_sum(acc);
+        if (part == 0) {
+          const double2 hp = c_mul(hh[p], acc);
+          yv[k * n + p] = make_double2(a.dt * hp.y, -a.dt * hp.x);
+        }
       }
       __syncthreads();
       if (g == 0) {
@@ -1138,16 +1144,23 @@ __global__ __launch_bounds__(kThreads) void k_mc_forward(McArgs a) {
     __syncthreads();
     if (j + 1 < nt) {
       const double* O = a.stage ? Ost : a.ov + es * nn;
-      for (int idx = tid; idx < n * w; idx += kThreads) {
-        const int p = idx / w, col = idx - p * w;
-        double2 acc = make_double2(0.0, 0.0);
+      // [a_{j+1} | A'_{j+1}] = O_j X on tiles of three rows x one column
+      const int nrb = (n + 2) / 3;
+      for (int t = tid; t < nrb * w; t += kThreads) {
+        const int rb = t / w, col = t - rb * w;
+        const int p0 = 3 * rb;
+        double2 acc[3];
+        for (int i = 0; i < 3; ++i) acc[i] = make_double2(0.0, 0.0);
         for (int r = 0; r < n; ++r) {
-          const double o = O[(size_t)p * n + r];
           const double2 x = X[r * w + col];
-          acc.x = fma(o, x.x, acc.x);
-          acc.y = fma(o, x.y, acc.y);
+          for (int i = 0; i < 3; ++i) {
+            const double o = p0 + i < n ? O[(size_t)(p0 + i) * n + r] : 0.0;
+            acc[i].x = fma(o, x.x, acc[i].x);
+            acc[i].y = fma(o, x.y, acc[i].y);
+          }
         }
-        cur[idx] = acc;
+        for (int i = 0; i < 3; ++i)
+          if (p0 + i < n) cur[(p0 + i) * w + col] = acc[i];
       }
     } else {
       double2* dst = a.xf + (size_t)b * n * (1 + a.ncols);
@@ -1219,18 +1232,23 @@ __global__ __launch_bounds__(kThreads) void k_mc_backward(McArgs a) {
       fv[k * a.pg + col] = mc_forcing(a, k, j, c0 + col, b);
     }
     __syncthreads();
-    for (int t = tid; t < K * n; t += kThreads) {
+    // z_k, four adjacent lanes per (direction, row) as in the forward y_k
+    for (int t4 = tid; t4 < 4 * K * n; t4 += kThreads) {
+      const int t = t4 >> 2, part = t4 & 3;
       const int k = t / n, p = t - k * n;
       const double* S = a.stage ? Sst + k * nn : a.sm + (es * K + k) * nn;
       double2 acc = make_double2(0.0, 0.0);
-      for (int r = 0; r < n; ++r) {
+      for (int r = part; r < n; r += 4) {
         const double2 x = c_mul(hh[r], cur[r * w]);
         const double sv = S[(size_t)r * n + p];
         acc.x = fma(sv, x.x, acc.x);
         acc.y = fma(sv, x.y, acc.y);
       }
-      const double2 hp = c_mul(hh[p], acc);
-      zv[k * n + p] = make_double2(-a.dt * hp.y, a.dt * hp.x);   // i dt * hp
+      acc = quad_sum(acc);
+      if (part == 0) {
+        const double2 hp = c_mul(hh[p], acc);
+        zv[k * n + p] = make_double2(-a.dt * hp.y, a.dt * hp.x);   // i dt * hp
+      }
     }
     __syncthreads();
     // per-step reductions: one thread per (direction, column) sums over the rows
@@ -1277,16 +1295,22 @@ __global__ __launch_bounds__(kThreads) void k_mc_backward(McArgs a) {
       }
       __syncthreads();
       const double* O = a.stage ? Ost : a.ov + (es - 1) * nn;   // O_{j-1}, applied transposed
-      for (int idx = tid; idx < n * w; idx += kThreads) {
-        const int p = idx / w, col = idx - p * w;
-        double2 acc = make_double2(0.0, 0.0);
+      const int nrb = (n + 2) / 3;
+      for (int t = tid; t < nrb * w; t += kThreads) {
+        const int rb = t / w, col = t - rb * w;
+        const int p0 = 3 * rb;
+        double2 acc[3];
+        for (int i = 0; i < 3; ++i) acc[i] = make_double2(0.0, 0.0);
         for (int r = 0; r < n; ++r) {
-          const double o = O[(size_t)r * n + p];
           const double2 x = X[r * w + col];
-          acc.x = fma(o, x.x, acc.x);
-          acc.y = fma(o, x.y, acc.y);
+          for (int i = 0; i < 3; ++i) {
+            const double o = p0 + i < n ? O[(size_t)r * n + p0 + i] : 0.0;
+            acc[i].x = fma(o, x.x, acc[i].x);
+            acc[i].y = fma(o, x.y, acc[i].y);
+          }
         }
-        cur[idx] = acc;
+        for (int i = 0; i < 3; ++i)
+          if (p0 + i < n) cur[(p0 + i) * w + col] = acc[i];
       }
     }
     __syncthreads();
