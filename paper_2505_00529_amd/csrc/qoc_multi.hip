@@ -1251,12 +1251,14 @@ __global__ __launch_bounds__(kThreads) void k_mc_backward(McArgs a) {
       }
     }
     __syncthreads();
-    // per-step reductions: one thread per (direction, column) sums over the rows
+    // per-step reductions: eight adjacent lanes per (direction) or (direction, column), each
+    // summing every eighth row, then an eight-lane sum (whole groups of eight stay active)
     if (g == 0) {
       for (int r = tid; r < n; r += kThreads) a.mu[es * n + r] = cur[r * w];
-      for (int k = tid; k < K; k += kThreads) {
+      for (int t8 = tid; t8 < 8 * K; t8 += kThreads) {
+        const int k = t8 >> 3, part = t8 & 7;
         double lq = 0.0, le = 0.0;
-        for (int p = 0; p < n; ++p) {
+        for (int p = part; p < n; p += 8) {
           const double2 l = cur[p * w], y = yv[k * n + p];
           lq += l.x * y.x + l.y * y.y;
           if (hvp) {
@@ -1264,19 +1266,25 @@ __global__ __launch_bounds__(kThreads) void k_mc_backward(McArgs a) {
             le += nu.x * y.x + nu.y * y.y + z.x * av[p].x + z.y * av[p].y;
           }
         }
-        a.q[es * K + k] = lq;
-        if (hvp) a.e[es * K + k] = le;
+        lq = oct_sum(lq);
+        if (hvp) le = oct_sum(le);
+        if (part == 0) {
+          a.q[es * K + k] = lq;
+          if (hvp) a.e[es * K + k] = le;
+        }
       }
     }
     if (hess) {
-      for (int t = tid; t < K * ncol; t += kThreads) {
+      for (int t8 = tid; t8 < 8 * K * ncol; t8 += kThreads) {
+        const int t = t8 >> 3, part = t8 & 7;
         const int k = t / ncol, col = t - k * ncol;
         double acc = 0.0;
-        for (int p = 0; p < n; ++p) {
+        for (int p = part; p < n; p += 8) {
           const double2 xi = cur[p * w + 1 + col], y = yv[k * n + p];
           acc += xi.x * y.x + xi.y * y.y;
         }
-        a.Km[(es * K + k) * a.P + c0 + col] = acc;
+        acc = oct_sum(acc);
+        if (part == 0) a.Km[(es * K + k) * a.P + c0 + col] = acc;
       }
     }
     __syncthreads();
