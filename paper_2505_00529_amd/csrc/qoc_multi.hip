@@ -352,7 +352,7 @@ __global__ __launch_bounds__(kThreads) void k_mc_eig(McArgs a) {
   }
 }
 
-// ---------------------------------------------------------------- eigen-data at NP = 36
+// ---------------------------------------------------------------- eigen-data at NP = 36 and 64
 
 // The circle-slot workgroup kernel of the one-direction path (V in registers, both ping-pong
 // copies of A in LDS, one barrier per round, second-order perturbative finish, basis products on
@@ -405,6 +405,25 @@ __device__ __forceinline__ void mc_rotate_block(double a00, double a01, double a
   b10 = RI.y * t00 + RI.x * t10;
   b11 = RI.y * t01 + RI.x * t11;
 }
+
+template <>
+struct McWgShape<64> {
+  static constexpr int TPB = 512;        // eight waves share the 67 KB of LDS
+  static constexpr int RT = 4, CT = 2;   // 16 x 32 output tiles
+  // V_{j-1} in a global scratch (two 64 x 66 buffers in LDS, 67 KB): with it in LDS as well
+  // (101 KB) the persistent queue variant of this kernel returned wrong eigen-data (batched
+  // results 1e-1 off while the same code as a plain launch matched the oracle, and a row stride
+  // of 64 or this layout were both correct); that configuration is not used until understood
+  static constexpr bool VP_LDS = false;
+  static constexpr int VW0 = 1, VW = 4;
+  static constexpr int VS = 8;
+  // one problem per CU without spills (256 VGPRs) beats two per CU at 128 VGPRs with about 130
+  // spilled registers per thread (683 against 754 ms for 256 theta x 4000 steps)
+  static constexpr int WAVES = 2;
+  // row stride 66: rows 132 dwords apart fall on distinct banks for the products' 16-byte loads
+  // (a stride of 64 puts every row of a column on the same bank)
+  static constexpr int LD = 66;
+};
 
 template <int NP>
 __host__ __device__ constexpr size_t mc_eig_wg_lds_doubles() {
@@ -1025,6 +1044,9 @@ __device__ __forceinline__ void body_mc_eig_wg(const McArgs& a, int c, int b) {
 __global__ __launch_bounds__(McWgShape<36>::TPB, McWgShape<36>::WAVES) void k_mc_eig_wg36(McArgs a) {
   body_mc_eig_wg<36>(a, blockIdx.x, blockIdx.y);
 }
+__global__ __launch_bounds__(McWgShape<64>::TPB, McWgShape<64>::WAVES) void k_mc_eig_wg64(McArgs a) {
+  body_mc_eig_wg<64>(a, blockIdx.x, blockIdx.y);
+}
 
 // ---------------------------------------------------------------- sweeps
 
@@ -1616,8 +1638,8 @@ __global__ __launch_bounds__(kThreads) void k_mc_assemble(McArgs a, McAsmOut o) 
 }
 
 hipError_t configure_mc_kernels() {
-  const void* fns[] = {(const void*)k_mc_eig, (const void*)k_mc_eig_wg36, (const void*)k_mc_forward,
-                       (const void*)k_mc_backward};
+  const void* fns[] = {(const void*)k_mc_eig, (const void*)k_mc_eig_wg36, (const void*)k_mc_eig_wg64,
+                       (const void*)k_mc_forward, (const void*)k_mc_backward};
   for (const void* f : fns) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
@@ -1658,7 +1680,8 @@ qoc_status qoc_problem::ensure_mc_work(int nb) {
       sizeof(double) * steps * nn,                     // ov
       sizeof(double) * nb * nchunks * nn,              // vfirst
       sizeof(double) * nb * nchunks * nn,              // vlast
-      lds_mats ? 0 : sizeof(double) * nb * nchunks * 4 * (size_t)np * np,   // gscratch
+      np == 64 ? sizeof(double) * nb * nchunks * 64 * McWgShape<64>::LD                 // gscratch: V_{j-1}
+               : (lds_mats ? 0 : sizeof(double) * nb * nchunks * 4 * (size_t)np * np),   // or A, V, V_{j-1}, X
       sizeof(double2) * steps * n,                     // at
       sizeof(double2) * steps * K * n,                 // yt
       sizeof(double2) * steps * n,                     // ah
@@ -1738,7 +1761,8 @@ qoc_status qoc_problem::enqueue_multi(Mode mode, int nb, const double* d_theta, 
   a.ov = (double*)take(sizeof(double) * steps * nn);
   a.vfirst = (double*)take(sizeof(double) * nb * a.nchunks * nn);
   a.vlast = (double*)take(sizeof(double) * nb * a.nchunks * nn);
-  a.gscratch = (double*)take(a.lds_mats ? 0 : sizeof(double) * nb * a.nchunks * 4 * (size_t)np * np);
+  a.gscratch = (double*)take(np == 64 ? sizeof(double) * nb * a.nchunks * 64 * McWgShape<64>::LD
+                                      : (a.lds_mats ? 0 : sizeof(double) * nb * a.nchunks * 4 * (size_t)np * np));
   a.at = (double2*)take(sizeof(double2) * steps * n);
   a.yt = (double2*)take(sizeof(double2) * steps * K * n);
   a.ah = (double2*)take(sizeof(double2) * steps * n);
@@ -1810,6 +1834,9 @@ qoc_status qoc_problem::enqueue_multi(Mode mode, int nb, const double* d_theta, 
   if (np == 36) {
     hipLaunchKernelGGL(k_mc_eig_wg36, dim3(a.nchunks, nb), dim3(McWgShape<36>::TPB),
                        mc_eig_wg_lds_doubles<36>() * sizeof(double), stream, a);
+  } else if (np == 64) {   // V_{j-1} in the chunk's global scratch (NP x LD per chunk)
+    hipLaunchKernelGGL(k_mc_eig_wg64, dim3(a.nchunks, nb), dim3(McWgShape<64>::TPB),
+                       mc_eig_wg_lds_doubles<64>() * sizeof(double), stream, a);
   } else {
     const size_t eig_lds = (mc_eig_small_doubles(np) + (a.lds_mats ? (size_t)4 * np * np : 0)) * sizeof(double);
     hipLaunchKernelGGL(k_mc_eig, dim3(a.nchunks, nb), dim3(kThreads), eig_lds, stream, a);

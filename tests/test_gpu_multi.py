@@ -46,10 +46,11 @@ def _fourier_stack(nt, dt, kf, ndir):
     return bases
 
 
-@pytest.mark.parametrize("n,ndir", [(4, 2), (7, 3), (16, 3), (36, 2), (80, 3)])
+@pytest.mark.parametrize("n,ndir", [(4, 2), (7, 3), (16, 3), (35, 3), (36, 2), (64, 2), (80, 3)])
 def test_fourier_directions_against_oracle(n, ndir):
-    """Fourier model per direction (a block of theta each); n = 7 pads the Jacobi players, n = 80
-    keeps the eigen kernel's matrices in global memory."""
+    """Fourier model per direction (a block of theta each); n = 7 pads the Jacobi players; n = 35
+    (padded) and 36 run the circle-slot eigen kernel at NP = 36, n = 64 the one at NP = 64; n = 80
+    keeps the generic eigen kernel's matrices in global memory."""
     nt, dt, kf = 24, 0.05, 2
     s, ms = _ops(n, ndir, 60 + n)
     p = qoc.Problem(0)
