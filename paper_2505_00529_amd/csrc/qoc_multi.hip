@@ -1410,12 +1410,71 @@ __device__ __forceinline__ double2 mc_moments(const double* MtP, const double* M
   return contrib;
 }
 
+// A mixed pair k != n in one pass over the rows: P^k, Q^n, P^n, Q^k together (each matrix read
+// once), R_m = sum_a conj(P^k_a) Q^n_{m-a} + conj(P^n_a) Q^k_{m-a}.
+template <int NT>
+__device__ __forceinline__ double2 mc_moments_mixed(const double* Mk, const double* Mn, const double* lam,
+                                                    const double2* mu, const double2* at, const double2* coef,
+                                                    double m0, int lane, int n) {
+  double2 contrib = make_double2(0.0, 0.0);
+  for (int rb = 0; rb * 64 < n; ++rb) {
+    const int p = lane + 64 * rb;
+    double2 Pk[NT], Qn[NT], Pn[NT], Qk[NT];
+#pragma unroll
+    for (int k = 0; k < NT; ++k) {
+      Pk[k] = make_double2(0.0, 0.0);
+      Qn[k] = make_double2(0.0, 0.0);
+      Pn[k] = make_double2(0.0, 0.0);
+      Qk[k] = make_double2(0.0, 0.0);
+    }
+    for (int qi = 0; qi < n; ++qi) {
+      const double xq = lam[qi] - m0;
+      const double mk = p < n ? Mk[(size_t)qi * n + p] : 0.0;   // symmetric: coalesced column reads
+      const double mn = p < n ? Mn[(size_t)qi * n + p] : 0.0;
+      const double2 muq = mu[qi], atq = at[qi];
+      double2 t1 = c_scale(muq, mk), t2 = c_scale(atq, mn), t3 = c_scale(muq, mn), t4 = c_scale(atq, mk);
+#pragma unroll
+      for (int k = 0; k < NT; ++k) {
+        Pk[k] = c_add(Pk[k], t1);
+        Qn[k] = c_add(Qn[k], t2);
+        Pn[k] = c_add(Pn[k], t3);
+        Qk[k] = c_add(Qk[k], t4);
+        if (k + 1 < NT) {
+          t1 = c_scale(t1, xq);
+          t2 = c_scale(t2, xq);
+          t3 = c_scale(t3, xq);
+          t4 = c_scale(t4, xq);
+        }
+      }
+    }
+    if (p < n) {
+      const double xp = lam[p] - m0;
+#pragma unroll
+      for (int m = 0; m < NT; ++m) {
+        double2 R = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int aa = 0; aa <= m; ++aa) {
+          R = c_add(R, c_cmul(Pk[aa], Qn[m - aa]));
+          R = c_add(R, c_cmul(Pn[aa], Qk[m - aa]));
+        }
+        double2 wm = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int bb = NT - 1 - m; bb >= 0; --bb) {
+          wm = c_scale(wm, xp);
+          wm = c_add(wm, coef[m + bb]);
+        }
+        contrib = c_add(contrib, c_mul(R, wm));
+      }
+    }
+  }
+  return contrib;
+}
+
 template <int NT>
 __device__ double2 mc_pair_moments(const double* Mk, const double* Mn, bool same, const double* lam, const double2* mu,
                                    const double2* at, const double2* coef, double m0, int lane, int n) {
-  double2 c = mc_moments<NT>(Mk, Mn, lam, mu, at, coef, m0, lane, n);
-  if (same) return c_scale(c, 2.0);
-  return c_add(c, mc_moments<NT>(Mn, Mk, lam, mu, at, coef, m0, lane, n));
+  if (same) return c_scale(mc_moments<NT>(Mk, Mn, lam, mu, at, coef, m0, lane, n), 2.0);
+  return mc_moments_mixed<NT>(Mk, Mn, lam, mu, at, coef, m0, lane, n);
 }
 
 __global__ __launch_bounds__(kThreads) void k_mc_sterm(McArgs a) {
