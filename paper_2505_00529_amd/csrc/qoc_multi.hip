@@ -1064,6 +1064,39 @@ __host__ __device__ inline size_t mc_sweep_lds_doubles(int n, int pg, int K, boo
          (stage ? (size_t)(1 + K) * n * n : 0);
 }
 
+// Loads per thread in flight while a step's O and S_k are staged into LDS.
+constexpr int kMcStageBatch = 24;
+
+// Stages n1 doubles of src1 into dst1 and n2 of src2 into dst2 (LDS), kMcStageBatch loads per
+// thread issued before the first LDS store: a load-store pair per element would wait out the
+// memory latency once per element.  The loads take clamped, always valid addresses, so they
+// need no branches; only the stores are guarded.  The first batch sits outside the loop, so
+// that loads issued before the call stay in flight into it.
+__device__ __forceinline__ void mc_stage_batch(double* dst1, const double* src1, int n1, double* dst2,
+                                               const double* src2, int total, int base, int tid) {
+  double v[kMcStageBatch];
+#pragma unroll
+  for (int i = 0; i < kMcStageBatch; ++i) {
+    const int idx = min(base + tid + i * kThreads, total - 1);
+    v[i] = idx < n1 ? src1[idx] : src2[idx - n1];
+  }
+#pragma unroll
+  for (int i = 0; i < kMcStageBatch; ++i) {
+    const int idx = base + tid + i * kThreads;
+    if (idx < n1) dst1[idx] = v[i];
+    else if (idx < total) dst2[idx - n1] = v[i];
+  }
+}
+
+__device__ __forceinline__ void mc_stage(double* dst1, const double* src1, int n1, double* dst2, const double* src2,
+                                         int n2, int tid) {
+  const int total = n1 + n2;
+  if (total <= 0) return;
+  mc_stage_batch(dst1, src1, n1, dst2, src2, total, 0, tid);
+  for (int base = kMcStageBatch * kThreads; base < total; base += kMcStageBatch * kThreads)
+    mc_stage_batch(dst1, src1, n1, dst2, src2, total, base, tid);
+}
+
 // Forward sweep (Alg. 2, forward state sweep and tangent loop; eq. gradatheta with K directions)
 // for one theta and one group of tangent columns: column 0 the state, columns 1.. the tangents,
 // in the eigenbasis of the current step; the X after the last step goes to xf.
@@ -1101,24 +1134,21 @@ __global__ __launch_bounds__(kThreads) void k_mc_forward(McArgs a) {
   __syncthreads();
   for (int j = 0; j < nt; ++j) {
     const size_t es = (size_t)b * nt + j;
-    if (a.stage) {   // the previous step's reads of the staging area ended at its last barrier
-      if (need_y) {
-        const double* gs = a.sm + es * K * nn;
-        for (int idx = tid; idx < K * (int)nn; idx += kThreads) Sst[idx] = gs[idx];
-      }
-      if (j + 1 < nt) {
-        const double* go = a.ov + es * nn;
-        for (int idx = tid; idx < (int)nn; idx += kThreads) Ost[idx] = go[idx];
-      }
-    }
+    // the step's first eigenvalue and forcing value of this thread, issued before the staging
+    // loads so that every latency of the step start overlaps
+    const double lam_t = a.lam[es * n + min(tid, n - 1)];
+    const double f_t = tid < K * ncol ? mc_forcing(a, tid / ncol, j, c0 + tid % ncol, b) : 0.0;
+    if (a.stage)   // the previous step's reads of the staging area ended at its last barrier
+      mc_stage(Ost, a.ov + es * nn, j + 1 < nt ? (int)nn : 0, Sst, a.sm + es * K * nn, need_y ? K * (int)nn : 0,
+               tid);
     for (int r = tid; r < n; r += kThreads) {
-      const double2 h = phase(0.5 * a.lam[es * n + r], a.dt);
+      const double2 h = phase(0.5 * (r == tid ? lam_t : a.lam[es * n + r]), a.dt);
       hh[r] = h;
       ph[r] = c_mul(h, h);
     }
     for (int t = tid; t < K * ncol; t += kThreads) {
       const int k = t / ncol, col = t - k * ncol;
-      fv[k * a.pg + col] = mc_forcing(a, k, j, c0 + col, b);
+      fv[k * a.pg + col] = t == tid ? f_t : mc_forcing(a, k, j, c0 + col, b);
     }
     __syncthreads();
     if (need_y) {
@@ -1234,24 +1264,25 @@ __global__ __launch_bounds__(kThreads) void k_mc_backward(McArgs a) {
   }
   for (int j = nt - 1; j >= 0; --j) {
     const size_t es = (size_t)b * nt + j;
-    if (a.stage) {   // the previous step's reads of the staging area ended at its last barrier
-      const double* gs = a.sm + es * K * nn;
-      for (int idx = tid; idx < K * (int)nn; idx += kThreads) Sst[idx] = gs[idx];
-      if (j >= 1) {
-        const double* go = a.ov + (es - 1) * nn;
-        for (int idx = tid; idx < (int)nn; idx += kThreads) Ost[idx] = go[idx];
-      }
-    }
+    // this thread's first entries of the step's small vectors, issued before the staging loads
+    // so that every latency of the step start overlaps
+    const double lam_t = a.lam[es * n + min(tid, n - 1)];
+    const double2 ah_t = hvp ? a.ah[es * n + min(tid, n - 1)] : make_double2(0.0, 0.0);
+    const double2 y_t = a.yt[es * K * n + min(tid, K * n - 1)];
+    const double f_t = tid < K * ncol ? mc_forcing(a, tid / ncol, j, c0 + tid % ncol, b) : 0.0;
+    if (a.stage)   // the previous step's reads of the staging area ended at its last barrier
+      mc_stage(Ost, a.ov + (es - (j >= 1 ? 1 : 0)) * nn, j >= 1 ? (int)nn : 0, Sst, a.sm + es * K * nn, K * (int)nn,
+               tid);
     for (int r = tid; r < n; r += kThreads) {
-      const double2 h = c_conj(phase(0.5 * a.lam[es * n + r], a.dt));
+      const double2 h = c_conj(phase(0.5 * (r == tid ? lam_t : a.lam[es * n + r]), a.dt));
       hh[r] = h;
       ph[r] = c_mul(h, h);
-      av[r] = hvp ? a.ah[es * n + r] : make_double2(0.0, 0.0);
+      av[r] = hvp ? (r == tid ? ah_t : a.ah[es * n + r]) : make_double2(0.0, 0.0);
     }
-    for (int t = tid; t < K * n; t += kThreads) yv[t] = a.yt[es * K * n + t];
+    for (int t = tid; t < K * n; t += kThreads) yv[t] = t == tid ? y_t : a.yt[es * K * n + t];
     for (int t = tid; t < K * ncol; t += kThreads) {
       const int k = t / ncol, col = t - k * ncol;
-      fv[k * a.pg + col] = mc_forcing(a, k, j, c0 + col, b);
+      fv[k * a.pg + col] = t == tid ? f_t : mc_forcing(a, k, j, c0 + col, b);
     }
     __syncthreads();
     // z_k, four adjacent lanes per (direction, row) as in the forward y_k
