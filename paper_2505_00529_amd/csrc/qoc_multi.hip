@@ -1060,7 +1060,7 @@ __device__ __forceinline__ double mc_forcing(const McArgs& a, int k, int j, int 
 __host__ __device__ inline size_t mc_sweep_lds_doubles(int n, int pg, int K, bool stage) {
   // cur, X: [n][1 + pg] complex; hh, ph, av: [n] complex; yv, zv: [K][n] complex; fv: [K][pg];
   // staged O and S_k: (1 + K) n^2
-  return (size_t)2 * 2 * n * (1 + pg) + 2 * (3 * n + 2 * K * n) + (size_t)K * (pg > 0 ? pg : 1) +
+  return (size_t)2 * 2 * n * (1 + pg) + 2 * (3 * n + 2 * K * n) + (size_t)K * (pg > 0 ? pg : 1) + 1 +
          (stage ? (size_t)(1 + K) * n * n : 0);
 }
 
@@ -1097,6 +1097,79 @@ __device__ __forceinline__ void mc_stage(double* dst1, const double* src1, int n
     mc_stage_batch(dst1, src1, n1, dst2, src2, total, base, tid);
 }
 
+// The sweeps' matrix reads go through these inlined helpers, called once with the LDS copy and
+// once with the global one, so that each call site knows its address space (a pointer that may
+// be either compiles to flat loads, which wait on both counters).
+
+// One lane's part of (S (h o x))_p for the symmetric S: every fourth r from `part`, x column 0
+// of cur (row stride w).
+__device__ __forceinline__ double2 mc_sdot(const double* S, const double2* hh, const double2* cur, int n, int w, int p,
+                                           int part) {
+  double2 acc = make_double2(0.0, 0.0);
+#pragma unroll 3
+  for (int r = part; r < n; r += 4) {
+    const double2 x = c_mul(hh[r], cur[r * w]);
+    const double sv = S[(size_t)r * n + p];
+    acc.x = fma(sv, x.x, acc.x);
+    acc.y = fma(sv, x.y, acc.y);
+  }
+  return acc;
+}
+
+// cur = O X (TRANS false) or O^T X (TRANS true) on tiles of three rows x one column of X (row
+// stride w).  The rows of a partial last tile are clamped to n - 1 (valid reads) and not stored.
+// PAIRS (n even, O 16-byte aligned, TRANS false): two consecutive r per 16-byte load of O.
+template <bool TRANS, bool PAIRS>
+__device__ __forceinline__ void mc_product(const double* O, const double2* X, double2* cur, int n, int w, int tid) {
+  const int nrb = (n + 2) / 3;
+  for (int t = tid; t < nrb * w; t += kThreads) {
+    const int rb = t / w, col = t - rb * w;
+    const int p0 = 3 * rb;
+    const int q1 = min(p0 + 1, n - 1), q2 = min(p0 + 2, n - 1);
+    double2 a0 = make_double2(0.0, 0.0), a1 = a0, a2 = a0;
+    if constexpr (PAIRS && !TRANS) {
+      const double* o0 = O + (size_t)p0 * n;
+      const double* o1 = O + (size_t)q1 * n;
+      const double* o2 = O + (size_t)q2 * n;
+#pragma unroll 2
+      for (int r = 0; r < n; r += 2) {
+        const double2 x0 = X[r * w + col], x1 = X[(r + 1) * w + col];
+        const double2 u0 = *(const double2*)(o0 + r), u1 = *(const double2*)(o1 + r),
+                      u2 = *(const double2*)(o2 + r);
+        a0.x = fma(u0.x, x0.x, a0.x);
+        a0.y = fma(u0.x, x0.y, a0.y);
+        a1.x = fma(u1.x, x0.x, a1.x);
+        a1.y = fma(u1.x, x0.y, a1.y);
+        a2.x = fma(u2.x, x0.x, a2.x);
+        a2.y = fma(u2.x, x0.y, a2.y);
+        a0.x = fma(u0.y, x1.x, a0.x);
+        a0.y = fma(u0.y, x1.y, a0.y);
+        a1.x = fma(u1.y, x1.x, a1.x);
+        a1.y = fma(u1.y, x1.y, a1.y);
+        a2.x = fma(u2.y, x1.x, a2.x);
+        a2.y = fma(u2.y, x1.y, a2.y);
+      }
+    } else {
+#pragma unroll 4
+      for (int r = 0; r < n; ++r) {
+        const double2 x = X[r * w + col];
+        const double u0 = TRANS ? O[(size_t)r * n + p0] : O[(size_t)p0 * n + r];
+        const double u1 = TRANS ? O[(size_t)r * n + q1] : O[(size_t)q1 * n + r];
+        const double u2 = TRANS ? O[(size_t)r * n + q2] : O[(size_t)q2 * n + r];
+        a0.x = fma(u0, x.x, a0.x);
+        a0.y = fma(u0, x.y, a0.y);
+        a1.x = fma(u1, x.x, a1.x);
+        a1.y = fma(u1, x.y, a1.y);
+        a2.x = fma(u2, x.x, a2.x);
+        a2.y = fma(u2, x.y, a2.y);
+      }
+    }
+    cur[p0 * w + col] = a0;
+    if (p0 + 1 < n) cur[(p0 + 1) * w + col] = a1;
+    if (p0 + 2 < n) cur[(p0 + 2) * w + col] = a2;
+  }
+}
+
 // Forward sweep (Alg. 2, forward state sweep and tangent loop; eq. gradatheta with K directions)
 // for one theta and one group of tangent columns: column 0 the state, columns 1.. the tangents,
 // in the eigenbasis of the current step; the X after the last step goes to xf.
@@ -1115,7 +1188,7 @@ __global__ __launch_bounds__(kThreads) void k_mc_forward(McArgs a) {
   double2* ph = hh + n;
   double2* yv = ph + n;                       // [K][n]
   double* fv = (double*)(yv + K * n + n);     // [K][pg] (after the unused av slot)
-  double* Ost = fv + K * a.pg;                // staged O_j, then S_k of the step
+  double* Ost = fv + ((K * a.pg + 1) & ~1);   // staged O_j, then S_k of the step (16-byte aligned)
   double* Sst = Ost + nn;
   // a_0 = V_0^T alpha in column 0, zero tangents
   const double* V0 = a.vfirst + (size_t)b * a.nchunks * nn;
@@ -1158,14 +1231,8 @@ __global__ __launch_bounds__(kThreads) void k_mc_forward(McArgs a) {
       for (int t4 = tid; t4 < 4 * K * n; t4 += kThreads) {
         const int t = t4 >> 2, part = t4 & 3;
         const int k = t / n, p = t - k * n;
-        const double* S = a.stage ? Sst + k * nn : a.sm + (es * K + k) * nn;
-        double2 acc = make_double2(0.0, 0.0);
-        for (int r = part; r < n; r += 4) {
-          const double2 x = c_mul(hh[r], cur[r * w]);
-          const double sv = S[(size_t)r * n + p];
-          acc.x = fma(sv, x.x, acc.x);
-          acc.y = fma(sv, x.y, acc.y);
-        }
+        double2 acc = a.stage ? mc_sdot(Sst + k * nn, hh, cur, n, w, p, part)
+                              : mc_sdot(a.sm + (es * K + k) * nn, hh, cur, n, w, p, part);
         acc = quad_sum(acc);
         if (part == 0) {
           const double2 hp = c_mul(hh[p], acc);
@@ -1195,25 +1262,10 @@ __global__ __launch_bounds__(kThreads) void k_mc_forward(McArgs a) {
     }
     __syncthreads();
     if (j + 1 < nt) {
-      const double* O = a.stage ? Ost : a.ov + es * nn;
-      // [a_{j+1} | A'_{j+1}] = O_j X on tiles of three rows x one column
-      const int nrb = (n + 2) / 3;
-      for (int t = tid; t < nrb * w; t += kThreads) {
-        const int rb = t / w, col = t - rb * w;
-        const int p0 = 3 * rb;
-        double2 acc[3];
-        for (int i = 0; i < 3; ++i) acc[i] = make_double2(0.0, 0.0);
-        for (int r = 0; r < n; ++r) {
-          const double2 x = X[r * w + col];
-          for (int i = 0; i < 3; ++i) {
-            const double o = p0 + i < n ? O[(size_t)(p0 + i) * n + r] : 0.0;
-            acc[i].x = fma(o, x.x, acc[i].x);
-            acc[i].y = fma(o, x.y, acc[i].y);
-          }
-        }
-        for (int i = 0; i < 3; ++i)
-          if (p0 + i < n) cur[(p0 + i) * w + col] = acc[i];
-      }
+      // [a_{j+1} | A'_{j+1}] = O_j X
+      if (!a.stage) mc_product<false, false>(a.ov + es * nn, X, cur, n, w, tid);
+      else if (n & 1) mc_product<false, false>(Ost, X, cur, n, w, tid);
+      else mc_product<false, true>(Ost, X, cur, n, w, tid);
     } else {
       double2* dst = a.xf + (size_t)b * n * (1 + a.ncols);
       for (int idx = tid; idx < n * w; idx += kThreads) {
@@ -1253,7 +1305,7 @@ __global__ __launch_bounds__(kThreads) void k_mc_backward(McArgs a) {
   double2* zv = av + n;                       // [K][n]
   double2* yv = zv + K * n;                   // [K][n]
   double* fv = (double*)(yv + K * n);         // [K][pg]
-  double* Ost = fv + K * a.pg;                // staged O_{j-1}, then S_k of the step
+  double* Ost = fv + ((K * a.pg + 1) & ~1);   // staged O_{j-1}, then S_k of the step (16-byte aligned)
   double* Sst = Ost + nn;
   for (int idx = tid; idx < n * w; idx += kThreads) {
     const int p = idx / w, col = idx - p * w;
@@ -1289,14 +1341,8 @@ __global__ __launch_bounds__(kThreads) void k_mc_backward(McArgs a) {
     for (int t4 = tid; t4 < 4 * K * n; t4 += kThreads) {
       const int t = t4 >> 2, part = t4 & 3;
       const int k = t / n, p = t - k * n;
-      const double* S = a.stage ? Sst + k * nn : a.sm + (es * K + k) * nn;
-      double2 acc = make_double2(0.0, 0.0);
-      for (int r = part; r < n; r += 4) {
-        const double2 x = c_mul(hh[r], cur[r * w]);
-        const double sv = S[(size_t)r * n + p];
-        acc.x = fma(sv, x.x, acc.x);
-        acc.y = fma(sv, x.y, acc.y);
-      }
+      double2 acc = a.stage ? mc_sdot(Sst + k * nn, hh, cur, n, w, p, part)
+                            : mc_sdot(a.sm + (es * K + k) * nn, hh, cur, n, w, p, part);
       acc = quad_sum(acc);
       if (part == 0) {
         const double2 hp = c_mul(hh[p], acc);
@@ -1355,24 +1401,9 @@ __global__ __launch_bounds__(kThreads) void k_mc_backward(McArgs a) {
         X[idx] = v;
       }
       __syncthreads();
-      const double* O = a.stage ? Ost : a.ov + (es - 1) * nn;   // O_{j-1}, applied transposed
-      const int nrb = (n + 2) / 3;
-      for (int t = tid; t < nrb * w; t += kThreads) {
-        const int rb = t / w, col = t - rb * w;
-        const int p0 = 3 * rb;
-        double2 acc[3];
-        for (int i = 0; i < 3; ++i) acc[i] = make_double2(0.0, 0.0);
-        for (int r = 0; r < n; ++r) {
-          const double2 x = X[r * w + col];
-          for (int i = 0; i < 3; ++i) {
-            const double o = p0 + i < n ? O[(size_t)r * n + p0 + i] : 0.0;
-            acc[i].x = fma(o, x.x, acc[i].x);
-            acc[i].y = fma(o, x.y, acc[i].y);
-          }
-        }
-        for (int i = 0; i < 3; ++i)
-          if (p0 + i < n) cur[(p0 + i) * w + col] = acc[i];
-      }
+      // [lambda_j | xi_{j-1}] = O_{j-1}^T X
+      if (a.stage) mc_product<true, false>(Ost, X, cur, n, w, tid);
+      else mc_product<true, false>(a.ov + (es - 1) * nn, X, cur, n, w, tid);
     }
     __syncthreads();
   }
