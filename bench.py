@@ -429,7 +429,7 @@ def main() -> int:
                     help="molecule: the headline evals/s line (N=36, P=32); warm: the 64-level system "
                          "(N=64, P=64); batched: 256 uneven problems; multi: three control directions "
                          "(N=36, P=96)")
-    ap.add_argument("--multi-batch", type=int, default=64, help="theta per step of the multi workload")
+    ap.add_argument("--multi-batch", type=int, default=256, help="theta per step of the multi workload")
     ap.add_argument("--multi-oracle-steps", type=int, default=400,
                     help="steps of the multi workload's oracle sample (its time is linear in the steps)")
     ap.add_argument("--n64-steps", type=int, default=4,

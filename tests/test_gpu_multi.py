@@ -251,7 +251,7 @@ def test_multi_direction_limits_are_reported():
 
 def test_benchmark_configuration_against_stored_oracle():
     """The three-direction workload at full size, in the launch configuration the benchmark times
-    (64 theta, J = 4000, P = 96): rows 0 and 1 against the oracle's stored values
+    (256 theta, J = 4000, P = 96): rows 0 and 1 against the oracle's stored values
     (tests/golden/multi_oracle.json, written by make_golden_multi.py)."""
     import json
     import os
@@ -264,7 +264,7 @@ def test_benchmark_configuration_against_stored_oracle():
     p.set_system_multi(s.h0, ms, s.psi0, s.psi_target)
     p.set_control_basis(qoc.QOC_BASIS_FOURIER, w.nt, w.dt, w.k)
     p.set_weights(w.gamma, w.rho)
-    ths = inputs.draw_thetas(p.P, 64, w.seed)
+    ths = inputs.draw_thetas(p.P, 256, w.seed)
     c, g, h = p.hess_many(ths)
     for case in doc["cases"]:
         i = case["theta_index"]
