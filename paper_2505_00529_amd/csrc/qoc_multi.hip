@@ -1532,6 +1532,80 @@ __device__ __forceinline__ double2 mc_moments_mixed(const double* Mk, const doub
   return contrib;
 }
 
+// Series terms kept in LDS by the shared-moment U'' kernel (the largest term count it serves).
+constexpr int kMcStermNT = kMcStermNmax + 1;
+
+// The moments of one direction for every row, kept for all pairs: P_a = M~ (x^a o mu) and the
+// weighted G_a = sum_{d <= NT-1-a} Q_d w_{a+d}, Q_d = M~ (x^d o a), w_m = sum_b coef_{m+b} x_p^b.
+// Regrouping sum_m R_m w_m by a gives, for a pair (k, n),
+//   sum_p sum_m R_m[p] w_m[p] = sum_p sum_a conj(P^k_a[p]) G^n_a[p] + conj(P^n_a[p]) G^k_a[p],
+// so each direction's two moment sets are built once instead of once per pair.  One wave, lane =
+// row p; Pl and Gl are [kMcStermNT][n] (LDS).
+template <int NT>
+__device__ __forceinline__ void mc_dir_moments(const double* M, const double* lam, const double2* mu, const double2* at,
+                                               const double2* coef, double m0, int lane, int n, double2* Pl,
+                                               double2* Gl) {
+  for (int rb = 0; rb * 64 < n; ++rb) {
+    const int p = lane + 64 * rb;
+    double2 P[NT], Q[NT];
+#pragma unroll
+    for (int k = 0; k < NT; ++k) {
+      P[k] = make_double2(0.0, 0.0);
+      Q[k] = make_double2(0.0, 0.0);
+    }
+    for (int qi = 0; qi < n; ++qi) {
+      const double xq = lam[qi] - m0;
+      const double mv = p < n ? M[(size_t)qi * n + p] : 0.0;   // symmetric: coalesced column reads
+      double2 t1 = c_scale(mu[qi], mv), t2 = c_scale(at[qi], mv);
+#pragma unroll
+      for (int k = 0; k < NT; ++k) {
+        P[k] = c_add(P[k], t1);
+        Q[k] = c_add(Q[k], t2);
+        if (k + 1 < NT) {
+          t1 = c_scale(t1, xq);
+          t2 = c_scale(t2, xq);
+        }
+      }
+    }
+    if (p < n) {
+#pragma unroll
+      for (int k = 0; k < NT; ++k) Pl[k * n + p] = P[k];
+      const double xp = lam[p] - m0;
+      double2 G[NT];
+#pragma unroll
+      for (int k = 0; k < NT; ++k) G[k] = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int m = 0; m < NT; ++m) {
+        double2 wm = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int bb = NT - 1 - m; bb >= 0; --bb) {
+          wm = c_scale(wm, xp);
+          wm = c_add(wm, coef[m + bb]);
+        }
+#pragma unroll
+        for (int aa = 0; aa <= m; ++aa) G[aa] = c_add(G[aa], c_mul(Q[m - aa], wm));
+      }
+#pragma unroll
+      for (int k = 0; k < NT; ++k) Gl[k * n + p] = G[k];
+    }
+  }
+}
+
+// sum_p sum_a conj(P^k_a) G^n_a + conj(P^n_a) G^k_a from the kept moments (one wave, lane = row).
+template <int NT>
+__device__ __forceinline__ double2 mc_pair_from_shared(const double2* Pk, const double2* Gk, const double2* Pn,
+                                                       const double2* Gn, int lane, int n) {
+  double2 c = make_double2(0.0, 0.0);
+  for (int p = lane; p < n; p += 64) {
+#pragma unroll
+    for (int k = 0; k < NT; ++k) {
+      c = c_add(c, c_cmul(Pk[k * n + p], Gn[k * n + p]));
+      c = c_add(c, c_cmul(Pn[k * n + p], Gk[k * n + p]));
+    }
+  }
+  return c;
+}
+
 template <int NT>
 __device__ double2 mc_pair_moments(const double* Mk, const double* Mn, bool same, const double* lam, const double2* mu,
                                    const double2* at, const double2* coef, double m0, int lane, int n) {
@@ -1539,8 +1613,17 @@ __device__ double2 mc_pair_moments(const double* Mk, const double* Mn, bool same
   return mc_moments_mixed<NT>(Mk, Mn, lam, mu, at, coef, m0, lane, n);
 }
 
+// LDS of the shared-moment kernel: P and G of every direction, kMcStermNT terms, n rows.
+__host__ __device__ inline size_t mc_sterm_shared_bytes(int n, int K) {
+  return (size_t)2 * K * kMcStermNT * n * 2 * sizeof(double);
+}
+
+// SHARED: each direction's moments built once by one wave and kept in LDS, then one wave per
+// pair combines them (mc_dir_moments); otherwise each wave builds the moments of its pairs.
+template <bool SHARED>
 __global__ __launch_bounds__(kThreads) void k_mc_sterm(McArgs a) {
   __shared__ double red[kThreads];
+  extern __shared__ __attribute__((aligned(16))) double smem_st[];
   const int j = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
   const int wv = tid >> 6, lane = tid & 63;
   const int n = a.n, K = a.K, npair = K * (K + 1) / 2;
@@ -1586,6 +1669,46 @@ __global__ __launch_bounds__(kThreads) void k_mc_sterm(McArgs a) {
       mag *= a.dt / (double)(k + 3);
     }
     const double2 ph = phase(m0, a.dt);
+    if constexpr (SHARED) {
+      double2* Pl = (double2*)smem_st;                      // [K][kMcStermNT][n]
+      double2* Gl = Pl + (size_t)K * kMcStermNT * n;        // [K][kMcStermNT][n]
+      const size_t ds = (size_t)kMcStermNT * n;
+      for (int k = wv; k < K; k += kThreads / 64) {
+        switch (nmax) {   // wave-uniform
+#define QOC_MC_STERM_DIR(T) \
+  case T - 1: mc_dir_moments<T>(Mt + k * nn, lam, mu, at, coef, m0, lane, n, Pl + k * ds, Gl + k * ds); break;
+          QOC_MC_STERM_DIR(1) QOC_MC_STERM_DIR(2) QOC_MC_STERM_DIR(3) QOC_MC_STERM_DIR(4) QOC_MC_STERM_DIR(5)
+          QOC_MC_STERM_DIR(6) QOC_MC_STERM_DIR(7) QOC_MC_STERM_DIR(8) QOC_MC_STERM_DIR(9) QOC_MC_STERM_DIR(10)
+          QOC_MC_STERM_DIR(11) QOC_MC_STERM_DIR(12) QOC_MC_STERM_DIR(13) QOC_MC_STERM_DIR(14) QOC_MC_STERM_DIR(15)
+#undef QOC_MC_STERM_DIR
+          default: break;
+        }
+      }
+      __syncthreads();
+      for (int i = wv; i < npair; i += kThreads / 64) {
+        int k = 0, rem = i;
+        while (rem >= K - k) {
+          rem -= K - k;
+          ++k;
+        }
+        const int m = k + rem;
+        double2 c = make_double2(0.0, 0.0);
+        switch (nmax) {
+#define QOC_MC_STERM_PAIR(T) \
+  case T - 1: c = mc_pair_from_shared<T>(Pl + k * ds, Gl + k * ds, Pl + m * ds, Gl + m * ds, lane, n); break;
+          QOC_MC_STERM_PAIR(1) QOC_MC_STERM_PAIR(2) QOC_MC_STERM_PAIR(3) QOC_MC_STERM_PAIR(4) QOC_MC_STERM_PAIR(5)
+          QOC_MC_STERM_PAIR(6) QOC_MC_STERM_PAIR(7) QOC_MC_STERM_PAIR(8) QOC_MC_STERM_PAIR(9) QOC_MC_STERM_PAIR(10)
+          QOC_MC_STERM_PAIR(11) QOC_MC_STERM_PAIR(12) QOC_MC_STERM_PAIR(13) QOC_MC_STERM_PAIR(14)
+          QOC_MC_STERM_PAIR(15)
+#undef QOC_MC_STERM_PAIR
+          default: break;
+        }
+        double2 tot = make_double2(wave_sum_lds(c.x), wave_sum_lds(c.y));
+        tot = c_mul(ph, tot);
+        if (lane == 0) a.s[es * npair + i] = tot.x;
+      }
+      return;
+    }
     for (int i = wv; i < npair; i += kThreads / 64) {
       int k = 0, rem = i;
       while (rem >= K - k) {
@@ -1765,7 +1888,9 @@ hipError_t configure_mc_kernels() {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
   }
-  return hipSuccess;
+  // the U'' kernel also holds a static reduction array of kThreads doubles
+  return hipFuncSetAttribute((const void*)k_mc_sterm<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             160 * 1024 - kThreads * (int)sizeof(double));
 }
 
 }  // namespace qoc
@@ -2014,7 +2139,12 @@ qoc_status qoc_problem::enqueue_multi(Mode mode, int nb, const double* d_theta, 
   }
   if (mode == Mode::Hess || mode == Mode::Hvp) {
     prof_begin("sterm", &ev);
-    hipLaunchKernelGGL(k_mc_sterm, dim3(nt, nb), dim3(kThreads), 0, stream, a);
+    // each direction's moments shared by its pairs when they fit in LDS (n <= 110 at K = 3)
+    const size_t st_lds = mc_sterm_shared_bytes(n, K);
+    if (st_lds + kThreads * sizeof(double) <= 160 * 1024)
+      hipLaunchKernelGGL(k_mc_sterm<true>, dim3(nt, nb), dim3(kThreads), st_lds, stream, a);
+    else
+      hipLaunchKernelGGL(k_mc_sterm<false>, dim3(nt, nb), dim3(kThreads), 0, stream, a);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "k_mc_sterm");
     prof_end("sterm", ev);
