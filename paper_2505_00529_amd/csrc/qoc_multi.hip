@@ -1778,8 +1778,7 @@ struct McAsmOut {
   double gamma, rho;
 };
 
-// Cost, gradient and Hessian (or HVP) of one theta per blockIdx.y; blockIdx.x splits the
-// 4 x 4 tiles of the P x P Hessian (block 0 also forms cost and gradient).
+// Cost, gradient and HVP of one theta per blockIdx.y (the Hessian: k_mc_hess_tiles).
 __global__ __launch_bounds__(kThreads) void k_mc_assemble(McArgs a, McAsmOut o) {
   __shared__ double red[kThreads];
   const int bx = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
@@ -1807,63 +1806,7 @@ __global__ __launch_bounds__(kThreads) void k_mc_assemble(McArgs a, McAsmOut o) 
       }
     }
   }
-  if (a.mode == (int)Mode::Hess) {
-    // 4 x 4 tiles of H: a block takes 64 tiles, each wave one slice of the steps (j = wave mod
-    // 4); per step and direction the tile's rows and columns of B_k and K_k, with the pair values
-    // folded as t_k = gamma B_k + K_k + sum_n s_kn B_n on the column block.  The four slices are
-    // added in LDS in a fixed order.
-    constexpr int kSlices = kThreads / 64;
-    __shared__ double part[kSlices][64][16];
-    const int tp = (P + 3) / 4;
-    const int tl = tid & 63, slice = tid >> 6;
-    const int tile = bx * 64 + tl;
-    double acc[4][4];
-    for (int x = 0; x < 4; ++x)
-      for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
-    if (tile < tp * tp) {
-      const int l0 = (tile / tp) * 4, m0 = (tile % tp) * 4;
-      for (int j = slice; j < nt; j += kSlices) {
-        const size_t es = (size_t)b * nt + j;
-        double bl[kMaxCtl][4], bm[kMaxCtl][4], kl[kMaxCtl][4], km[kMaxCtl][4];
-        for (int k = 0; k < K; ++k) {
-          const double* Bj = a.B + ((size_t)k * nt + j) * P;
-          const double* Kj = a.Km + (es * K + k) * P;
-          for (int x = 0; x < 4; ++x) {
-            bl[k][x] = l0 + x < P ? Bj[l0 + x] : 0.0;
-            kl[k][x] = l0 + x < P ? Kj[l0 + x] : 0.0;
-            bm[k][x] = m0 + x < P ? Bj[m0 + x] : 0.0;
-            km[k][x] = m0 + x < P ? Kj[m0 + x] : 0.0;
-          }
-        }
-        const double* sj = a.s + es * npair;
-        for (int k = 0; k < K; ++k) {
-          double t[4];
-          for (int y = 0; y < 4; ++y) t[y] = fma(o.gamma, bm[k][y], km[k][y]);
-          for (int nn2 = 0; nn2 < K; ++nn2) {
-            const double sv = sj[pair_index(min(k, nn2), max(k, nn2), K)];
-            for (int y = 0; y < 4; ++y) t[y] = fma(sv, bm[nn2][y], t[y]);
-          }
-          for (int x = 0; x < 4; ++x)
-            for (int y = 0; y < 4; ++y) acc[x][y] = fma(bl[k][x], t[y], fma(bm[k][y], kl[k][x], acc[x][y]));
-        }
-      }
-    }
-    for (int x = 0; x < 4; ++x)
-      for (int y = 0; y < 4; ++y) part[slice][tl][4 * x + y] = acc[x][y];
-    __syncthreads();
-    for (int t = tid; t < 64 * 16; t += kThreads) {
-      const int tt = t >> 4, el = t & 15;
-      const int gt = bx * 64 + tt;
-      if (gt >= tp * tp) continue;
-      double v = 0.0;
-      for (int sl = 0; sl < kSlices; ++sl) v += part[sl][tt][el];
-      const int l = (gt / tp) * 4 + el / 4, m = (gt % tp) * 4 + el % 4;
-      if (l < P && m < P) {
-        const size_t oi = (size_t)b * P * P + (size_t)l * P + m;
-        o.out[oi] = v + o.aa[oi];
-      }
-    }
-  } else if (a.mode == (int)Mode::Hvp && bx == 0) {
+  if (a.mode == (int)Mode::Hvp && bx == 0) {
     for (int l = tid; l < P; l += kThreads) {
       double acc = 0.0;
       for (int j = 0; j < nt; ++j) {
@@ -1879,6 +1822,109 @@ __global__ __launch_bounds__(kThreads) void k_mc_assemble(McArgs a, McAsmOut o) 
       o.out[(size_t)b * P + l] = acc;
     }
   }
+}
+
+// Hessian tiles.  With rows r = (step j, direction k), H = B^T C + K^T B, where
+//   C_r[m] = gamma B_k[j,m] + K_{j,m,k} + sum_n s_{kn,j} B_n[j,m]
+// (the pair values folded on the column side): a sum of nt K rank-2 updates, formed as a tiled
+// product.  One workgroup per (upper tile of kAsmT x kAsmT, theta); each chunk of kAsmR rows
+// (whole steps, every direction) of B and K for the tile's rows and columns is staged in LDS,
+// C formed there, and each thread accumulates a 2 x 2 block over the chunk.  The upper tiles
+// are mirrored, so H comes out exactly symmetric.
+constexpr int kAsmT = 32;
+constexpr int kAsmR = 48;
+constexpr int kAsmLd = kAsmR * kAsmT / kThreads;   // staged elements per thread and array
+
+__global__ __launch_bounds__(kThreads) void k_mc_hess_tiles(McArgs a, McAsmOut o) {
+  __shared__ __attribute__((aligned(16))) double Bl[kAsmR * kAsmT];
+  __shared__ __attribute__((aligned(16))) double Kl[kAsmR * kAsmT];
+  __shared__ __attribute__((aligned(16))) double Bm[kAsmR * kAsmT];
+  __shared__ __attribute__((aligned(16))) double Kq[kAsmR * kAsmT];
+  __shared__ __attribute__((aligned(16))) double Cm[kAsmR * kAsmT];
+  __shared__ double sv[kAsmR * kMaxPairs / 2];
+  const int b = blockIdx.y, tid = threadIdx.x;
+  const int P = a.P, nt = a.nt, K = a.K, npair = K * (K + 1) / 2;
+  const int tp = (P + kAsmT - 1) / kAsmT;
+  int tl = 0, rem = blockIdx.x;   // upper tile (tl <= tm), row by row
+  while (rem >= tp - tl) {
+    rem -= tp - tl;
+    ++tl;
+  }
+  const int tm = tl + rem;
+  const int l0 = tl * kAsmT, m0 = tm * kAsmT;
+  const int lr = (tid >> 4) * 2, mr = (tid & 15) * 2;
+  const int Jc = kAsmR / K;   // whole steps per chunk
+  double h00 = 0.0, h01 = 0.0, h10 = 0.0, h11 = 0.0;
+  for (int j0 = 0; j0 < nt; j0 += Jc) {
+    const int jn = min(Jc, nt - j0);
+    const int rows = jn * K;
+    double vbl[kAsmLd], vkl[kAsmLd], vbm[kAsmLd], vkm[kAsmLd];
+#pragma unroll
+    for (int i = 0; i < kAsmLd; ++i) {   // clamped addresses: every load valid, no branches
+      const int idx = tid + i * kThreads;
+      const int r = idx / kAsmT, c = idx - r * kAsmT;
+      const int jj = r / K, k = r - jj * K;
+      const int j = min(j0 + jj, nt - 1);
+      const double* Bj = a.B + ((size_t)k * nt + j) * P;
+      const double* Kj = a.Km + (((size_t)b * nt + j) * K + k) * P;
+      const int lc = min(l0 + c, P - 1), mc = min(m0 + c, P - 1);
+      vbl[i] = Bj[lc];
+      vkl[i] = Kj[lc];
+      vbm[i] = Bj[mc];
+      vkm[i] = Kj[mc];
+    }
+    const double s_t = tid < jn * npair ? a.s[((size_t)b * nt + j0) * npair + tid] : 0.0;
+    __syncthreads();   // the previous chunk's reads are done
+#pragma unroll
+    for (int i = 0; i < kAsmLd; ++i) {
+      const int idx = tid + i * kThreads;
+      const int r = idx / kAsmT, c = idx - r * kAsmT;
+      const bool rv = r < rows;
+      Bl[idx] = rv && l0 + c < P ? vbl[i] : 0.0;
+      Kl[idx] = rv && l0 + c < P ? vkl[i] : 0.0;
+      Bm[idx] = rv && m0 + c < P ? vbm[i] : 0.0;
+      Kq[idx] = rv && m0 + c < P ? vkm[i] : 0.0;
+    }
+    if (tid < jn * npair) sv[tid] = s_t;
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kAsmLd; ++i) {
+      const int idx = tid + i * kThreads;
+      const int r = idx / kAsmT, c = idx - r * kAsmT;
+      if (r < rows) {
+        const int jj = r / K, k = r - jj * K;
+        double v = fma(o.gamma, Bm[idx], Kq[idx]);
+        for (int n = 0; n < K; ++n)
+          v = fma(sv[jj * npair + pair_index(min(k, n), max(k, n), K)], Bm[(jj * K + n) * kAsmT + c], v);
+        Cm[idx] = v;
+      }
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int r = 0; r < rows; ++r) {
+      const double2 bl = *(const double2*)(Bl + r * kAsmT + lr);
+      const double2 kl = *(const double2*)(Kl + r * kAsmT + lr);
+      const double2 cm = *(const double2*)(Cm + r * kAsmT + mr);
+      const double2 bm = *(const double2*)(Bm + r * kAsmT + mr);
+      h00 = fma(bl.x, cm.x, fma(kl.x, bm.x, h00));
+      h01 = fma(bl.x, cm.y, fma(kl.x, bm.y, h01));
+      h10 = fma(bl.y, cm.x, fma(kl.y, bm.x, h10));
+      h11 = fma(bl.y, cm.y, fma(kl.y, bm.y, h11));
+    }
+  }
+  const double hv[2][2] = {{h00, h01}, {h10, h11}};
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) {
+      const int l = l0 + lr + x, m = m0 + mr + y;
+      if (l < P && m < P && (tl != tm || l <= m)) {
+        const size_t base = (size_t)b * P * P;
+        const double v = hv[x][y] + o.aa[base + (size_t)l * P + m];
+        o.out[base + (size_t)l * P + m] = v;
+        o.out[base + (size_t)m * P + l] = v;
+      }
+    }
 }
 
 hipError_t configure_mc_kernels() {
@@ -2157,12 +2203,16 @@ qoc_status qoc_problem::enqueue_multi(Mode mode, int nb, const double* d_theta, 
   o.out = d_out;
   o.gamma = gamma;
   o.rho = rho;
-  const int tp = (P + 3) / 4;
-  const int gx = mode == Mode::Hess ? std::max(1, (tp * tp + 63) / 64) : 1;   // 64 tiles per block
   prof_begin("assemble", &ev);
-  hipLaunchKernelGGL(k_mc_assemble, dim3(gx, nb), dim3(kThreads), 0, stream, a, o);
+  hipLaunchKernelGGL(k_mc_assemble, dim3(1, nb), dim3(kThreads), 0, stream, a, o);
   e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "k_mc_assemble");
+  if (mode == Mode::Hess) {
+    const int tp = (P + kAsmT - 1) / kAsmT;
+    hipLaunchKernelGGL(k_mc_hess_tiles, dim3(tp * (tp + 1) / 2, nb), dim3(kThreads), 0, stream, a, o);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "k_mc_hess_tiles");
+  }
   prof_end("assemble", ev);
 #undef QOC_MC_LAUNCH
   return QOC_OK;
