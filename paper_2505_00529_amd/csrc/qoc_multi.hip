@@ -1795,14 +1795,37 @@ __global__ __launch_bounds__(kThreads) void k_mc_assemble(McArgs a, McAsmOut o) 
     const double ff = block_sum(loc, red);
     if (tid == 0 && o.cost) o.cost[b] = 0.5 * o.gamma * ff + 0.5 * o.rho * o.rr[b];
     if (o.grad && a.mode != (int)Mode::Cost) {
-      for (int l = tid; l < P; l += kThreads) {
+      // the steps split into kThreads / P slices (P <= kThreads), summed in LDS in slice order
+      const int ns = P <= kThreads ? kThreads / P : 1;
+      const int sl = tid / P, l0 = tid - sl * P;
+      if (P <= kThreads) {
         double acc = 0.0;
-        for (int j = 0; j < nt; ++j) {
-          const size_t es = (size_t)b * nt + j;
-          for (int k = 0; k < K; ++k)
-            acc = fma(Bk(k, j, l), o.gamma * f[((size_t)k * a.nb + b) * nt + j] + a.q[es * K + k], acc);
+        if (sl < ns) {
+#pragma unroll 4
+          for (int j = sl; j < nt; j += ns) {
+            const size_t es = (size_t)b * nt + j;
+            for (int k = 0; k < K; ++k)
+              acc = fma(Bk(k, j, l0), o.gamma * f[((size_t)k * a.nb + b) * nt + j] + a.q[es * K + k], acc);
+          }
         }
-        o.grad[(size_t)b * P + l] = acc;
+        __syncthreads();   // red is free again after the cost's block sum
+        red[tid] = acc;
+        __syncthreads();
+        if (tid < P) {
+          double g = 0.0;
+          for (int t = 0; t < ns; ++t) g += red[t * P + tid];
+          o.grad[(size_t)b * P + tid] = g;
+        }
+      } else {
+        for (int l = tid; l < P; l += kThreads) {
+          double acc = 0.0;
+          for (int j = 0; j < nt; ++j) {
+            const size_t es = (size_t)b * nt + j;
+            for (int k = 0; k < K; ++k)
+              acc = fma(Bk(k, j, l), o.gamma * f[((size_t)k * a.nb + b) * nt + j] + a.q[es * K + k], acc);
+          }
+          o.grad[(size_t)b * P + l] = acc;
+        }
       }
     }
   }
@@ -2072,7 +2095,8 @@ qoc_status qoc_problem::enqueue_multi(Mode mode, int nb, const double* d_theta, 
   a.stats = d_stats;
   // Sweep shape: the step's O and S_k are staged in LDS when they fit; the tangent columns per
   // workgroup are the fewest of {8, 16, 32} that keep every (group, theta) workgroup resident at
-  // once (LDS per workgroup decides how many fit on a CU), else the widest that fits in LDS.
+  // once (LDS per workgroup decides how many fit on a CU), else the widest of those that keep the
+  // most workgroups on a CU (latency hiding within a CU outweighs fewer, wider workgroups).
   constexpr size_t kLds = 160 * 1024;
   constexpr int kCUs = 256, kMaxWgPerCu = 8;
   auto sweep_lds_of = [&](int pgv, bool st) { return mc_sweep_lds_doubles(n, pgv, K, st) * sizeof(double); };
@@ -2080,6 +2104,9 @@ qoc_status qoc_problem::enqueue_multi(Mode mode, int nb, const double* d_theta, 
   bool stage = sweep_lds_of(1, true) <= kLds;
   if (ncols > 0) {
     bool chosen = false;
+    int best_pg = 0;
+    bool best_st = false;
+    long best_per_cu = 0;
     for (int cand : {8, 16, 32}) {
       const int pgv = std::min(cand, ncols);
       const bool st = sweep_lds_of(pgv, true) <= kLds;
@@ -2087,11 +2114,20 @@ qoc_status qoc_problem::enqueue_multi(Mode mode, int nb, const double* d_theta, 
       if (l > kLds) break;
       pg = pgv;
       stage = st;
-      const long resident = (long)kCUs * std::min<long>(kMaxWgPerCu, (long)(kLds / l));
-      if ((long)((ncols + pgv - 1) / pgv) * nb <= resident || pgv == ncols) {
+      const long per_cu = std::min<long>(kMaxWgPerCu, (long)(kLds / l));
+      if (per_cu >= best_per_cu) {   // the widest among those with the most workgroups per CU
+        best_per_cu = per_cu;
+        best_pg = pgv;
+        best_st = st;
+      }
+      if ((long)((ncols + pgv - 1) / pgv) * nb <= (long)kCUs * per_cu || pgv == ncols) {
         chosen = true;
         break;
       }
+    }
+    if (!chosen && best_pg > 0) {
+      pg = best_pg;
+      stage = best_st;
     }
     if (!chosen) {
       while (pg > 1 && sweep_lds_of(pg, false) > kLds) --pg;
