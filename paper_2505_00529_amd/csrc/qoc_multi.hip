@@ -15,8 +15,8 @@
 //
 // Kernels: one workgroup per (theta, chunk) for the eigen-data (at NP = 36 the circle-slot
 // kernel of the single-direction path extended to K directions; other sizes a parallel-order
-// Jacobi with the same second-order perturbative finish), per (column group, theta) for the sweeps (the step's O and S_k staged in
-// LDS when they fit), per (step, theta) for the U'' contraction (the moment series, or the
+// Jacobi with the same second-order perturbative finish), per (column group, theta) for the sweeps (the step's O staged in LDS
+// when it fits, S_k read from global memory), per (step, theta) for the U'' contraction (the moment series, or the
 // divided differences of every triple for wide spectra), 4 x 4 tiles for the assembly.  The chunk
 // joins (k_boundary_overlap) and the terminal kernel are shared with the single-direction path.
 #include <hip/hip_runtime.h>
@@ -41,7 +41,7 @@ struct McArgs {
   int mode;                // Mode
   double dt, tol_rel;
   int max_sweeps, lds_mats, store_derivs;
-  int stage;               // sweeps: the step's O and S_k staged in LDS (when they fit)
+  int stage;               // sweeps: the step's O staged in LDS (when it fits)
   const double* h0;        // [n][n]
   const double* m;         // [K][n][n]
   const double* psi0;      // [n] complex
@@ -1059,12 +1059,12 @@ __device__ __forceinline__ double mc_forcing(const McArgs& a, int k, int j, int 
 
 __host__ __device__ inline size_t mc_sweep_lds_doubles(int n, int pg, int K, bool stage) {
   // cur, X: [n][1 + pg] complex; hh, ph, av: [n] complex; yv, zv: [K][n] complex; fv: [K][pg];
-  // staged O and S_k: (1 + K) n^2
+  // staged O: n^2
   return (size_t)2 * 2 * n * (1 + pg) + 2 * (3 * n + 2 * K * n) + (size_t)K * (pg > 0 ? pg : 1) + 1 +
-         (stage ? (size_t)(1 + K) * n * n : 0);
+         (stage ? (size_t)n * n : 0);
 }
 
-// Loads per thread in flight while a step's O and S_k are staged into LDS.
+// Loads per thread in flight while a step's O is staged into LDS.
 constexpr int kMcStageBatch = 24;
 
 // Stages n1 doubles of src1 into dst1 and n2 of src2 into dst2 (LDS), kMcStageBatch loads per
@@ -1188,8 +1188,7 @@ __global__ __launch_bounds__(kThreads) void k_mc_forward(McArgs a) {
   double2* ph = hh + n;
   double2* yv = ph + n;                       // [K][n]
   double* fv = (double*)(yv + K * n + n);     // [K][pg] (after the unused av slot)
-  double* Ost = fv + ((K * a.pg + 1) & ~1);   // staged O_j, then S_k of the step (16-byte aligned)
-  double* Sst = Ost + nn;
+  double* Ost = fv + ((K * a.pg + 1) & ~1);   // staged O_j (16-byte aligned)
   // a_0 = V_0^T alpha in column 0, zero tangents
   const double* V0 = a.vfirst + (size_t)b * a.nchunks * nn;
   for (int idx = tid; idx < n * w; idx += kThreads) {
@@ -1212,8 +1211,7 @@ __global__ __launch_bounds__(kThreads) void k_mc_forward(McArgs a) {
     const double lam_t = a.lam[es * n + min(tid, n - 1)];
     const double f_t = tid < K * ncol ? mc_forcing(a, tid / ncol, j, c0 + tid % ncol, b) : 0.0;
     if (a.stage)   // the previous step's reads of the staging area ended at its last barrier
-      mc_stage(Ost, a.ov + es * nn, j + 1 < nt ? (int)nn : 0, Sst, a.sm + es * K * nn, need_y ? K * (int)nn : 0,
-               tid);
+      mc_stage(Ost, a.ov + es * nn, j + 1 < nt ? (int)nn : 0, Ost, a.ov + es * nn, 0, tid);
     for (int r = tid; r < n; r += kThreads) {
       const double2 h = phase(0.5 * (r == tid ? lam_t : a.lam[es * n + r]), a.dt);
       hh[r] = h;
@@ -1231,9 +1229,7 @@ __global__ __launch_bounds__(kThreads) void k_mc_forward(McArgs a) {
       for (int t4 = tid; t4 < 4 * K * n; t4 += kThreads) {
         const int t = t4 >> 2, part = t4 & 3;
         const int k = t / n, p = t - k * n;
-        double2 acc = a.stage ? mc_sdot(Sst + k * nn, hh, cur, n, w, p, part)
-                              : mc_sdot(a.sm + (es * K + k) * nn, hh, cur, n, w, p, part);
-        acc = quad_sum(acc);
+        const double2 acc = quad_sum(mc_sdot(a.sm + (es * K + k) * nn, hh, cur, n, w, p, part));
         if (part == 0) {
           const double2 hp = c_mul(hh[p], acc);
           yv[k * n + p] = make_double2(a.dt * hp.y, -a.dt * hp.x);
@@ -1305,8 +1301,7 @@ __global__ __launch_bounds__(kThreads) void k_mc_backward(McArgs a) {
   double2* zv = av + n;                       // [K][n]
   double2* yv = zv + K * n;                   // [K][n]
   double* fv = (double*)(yv + K * n);         // [K][pg]
-  double* Ost = fv + ((K * a.pg + 1) & ~1);   // staged O_{j-1}, then S_k of the step (16-byte aligned)
-  double* Sst = Ost + nn;
+  double* Ost = fv + ((K * a.pg + 1) & ~1);   // staged O_{j-1} (16-byte aligned)
   for (int idx = tid; idx < n * w; idx += kThreads) {
     const int p = idx / w, col = idx - p * w;
     double2 v = make_double2(0.0, 0.0);
@@ -1323,8 +1318,7 @@ __global__ __launch_bounds__(kThreads) void k_mc_backward(McArgs a) {
     const double2 y_t = a.yt[es * K * n + min(tid, K * n - 1)];
     const double f_t = tid < K * ncol ? mc_forcing(a, tid / ncol, j, c0 + tid % ncol, b) : 0.0;
     if (a.stage)   // the previous step's reads of the staging area ended at its last barrier
-      mc_stage(Ost, a.ov + (es - (j >= 1 ? 1 : 0)) * nn, j >= 1 ? (int)nn : 0, Sst, a.sm + es * K * nn, K * (int)nn,
-               tid);
+      mc_stage(Ost, a.ov + (es - (j >= 1 ? 1 : 0)) * nn, j >= 1 ? (int)nn : 0, Ost, a.ov, 0, tid);
     for (int r = tid; r < n; r += kThreads) {
       const double2 h = c_conj(phase(0.5 * (r == tid ? lam_t : a.lam[es * n + r]), a.dt));
       hh[r] = h;
@@ -1341,9 +1335,7 @@ __global__ __launch_bounds__(kThreads) void k_mc_backward(McArgs a) {
     for (int t4 = tid; t4 < 4 * K * n; t4 += kThreads) {
       const int t = t4 >> 2, part = t4 & 3;
       const int k = t / n, p = t - k * n;
-      double2 acc = a.stage ? mc_sdot(Sst + k * nn, hh, cur, n, w, p, part)
-                            : mc_sdot(a.sm + (es * K + k) * nn, hh, cur, n, w, p, part);
-      acc = quad_sum(acc);
+      const double2 acc = quad_sum(mc_sdot(a.sm + (es * K + k) * nn, hh, cur, n, w, p, part));
       if (part == 0) {
         const double2 hp = c_mul(hh[p], acc);
         zv[k * n + p] = make_double2(-a.dt * hp.y, a.dt * hp.x);   // i dt * hp
@@ -2093,43 +2085,51 @@ qoc_status qoc_problem::enqueue_multi(Mode mode, int nb, const double* d_theta, 
   double* aa = (double*)take(sizeof(double) * nb * P * P);
   a.status = d_status;
   a.stats = d_stats;
-  // Sweep shape: the step's O and S_k are staged in LDS when they fit; the tangent columns per
-  // workgroup are the fewest of {8, 16, 32} that keep every (group, theta) workgroup resident at
-  // once (LDS per workgroup decides how many fit on a CU), else the widest of those that keep the
-  // most workgroups on a CU (latency hiding within a CU outweighs fewer, wider workgroups).
+  // Sweep shape: the step's O is staged in LDS when it fits (S_k is read from global memory: the
+  // smaller LDS footprint keeps more workgroups on a CU, which hides more than staging saves).
+  // Every workgroup repeats the step's fixed work (staging, phases, the K mat-vecs), so the
+  // column groups are the widest of {8, 16, 32} that keep every (group, theta) workgroup resident
+  // and still give each CU one; else the narrowest that keeps them all resident (few theta);
+  // else the widest that fits in LDS (more workgroups than the GPU holds at once).
   constexpr size_t kLds = 160 * 1024;
   constexpr int kCUs = 256, kMaxWgPerCu = 8;
   auto sweep_lds_of = [&](int pgv, bool st) { return mc_sweep_lds_doubles(n, pgv, K, st) * sizeof(double); };
   int pg = 1;
   bool stage = sweep_lds_of(1, true) <= kLds;
   if (ncols > 0) {
-    bool chosen = false;
-    int best_pg = 0;
-    bool best_st = false;
-    long best_per_cu = 0;
+    int fill_pg = 0, res_pg = 0, fit_pg = 0;
+    bool fill_st = false, res_st = false, fit_st = false;
     for (int cand : {8, 16, 32}) {
       const int pgv = std::min(cand, ncols);
       const bool st = sweep_lds_of(pgv, true) <= kLds;
       const size_t l = sweep_lds_of(pgv, st);
       if (l > kLds) break;
-      pg = pgv;
-      stage = st;
+      fit_pg = pgv;   // widest that fits
+      fit_st = st;
       const long per_cu = std::min<long>(kMaxWgPerCu, (long)(kLds / l));
-      if (per_cu >= best_per_cu) {   // the widest among those with the most workgroups per CU
-        best_per_cu = per_cu;
-        best_pg = pgv;
-        best_st = st;
+      const long wgs = (long)((ncols + pgv - 1) / pgv) * nb;
+      if (wgs <= (long)kCUs * per_cu) {
+        if (res_pg == 0) {   // narrowest all resident
+          res_pg = pgv;
+          res_st = st;
+        }
+        if (wgs >= kCUs) {   // widest all resident with a workgroup per CU
+          fill_pg = pgv;
+          fill_st = st;
+        }
       }
-      if ((long)((ncols + pgv - 1) / pgv) * nb <= (long)kCUs * per_cu || pgv == ncols) {
-        chosen = true;
-        break;
-      }
+      if (pgv == ncols) break;
     }
-    if (!chosen && best_pg > 0) {
-      pg = best_pg;
-      stage = best_st;
-    }
-    if (!chosen) {
+    if (fill_pg > 0) {
+      pg = fill_pg;
+      stage = fill_st;
+    } else if (res_pg > 0) {
+      pg = res_pg;
+      stage = res_st;
+    } else if (fit_pg > 0) {
+      pg = fit_pg;
+      stage = fit_st;
+    } else {
       while (pg > 1 && sweep_lds_of(pg, false) > kLds) --pg;
       if (sweep_lds_of(pg, stage) > kLds) stage = false;
     }
