@@ -136,6 +136,35 @@ def test_dense_models_move_every_direction():
     p.close()
 
 
+@pytest.mark.parametrize("ndir,P,nt", [(3, 45, 50), (2, 70, 37)])
+def test_hessian_tiles_ragged_against_oracle(ndir, P, nt):
+    """Dense models with P spanning several 32-column Hessian tiles, the last one ragged, and a
+    horizon that is not a whole number of the assembly's step chunks (16 steps at K = 3, 24 at
+    K = 2): the tiled Hessian against the oracle, exactly symmetric (upper tiles mirrored), and
+    the gradient and a Hessian-vector product through their own kernels."""
+    n, dt = 8, 0.05
+    s, ms = _ops(n, ndir, 170 + P)
+    rng = np.random.default_rng(171 + P)
+    bases = rng.normal(size=(ndir, nt, P)) * 0.3
+    p = qoc.Problem(0)
+    p.set_system_multi(s.h0, ms, s.psi0, s.psi_target)
+    p.set_control_basis(qoc.QOC_BASIS_DENSE, nt, dt, P, bases)
+    p.set_weights(0.3, 2.0)
+    ths = inputs.draw_thetas(P, 2, 172 + P, sigma=0.5)
+    c, g, h = p.hess_many(ths)
+    for i, th in enumerate(ths):
+        cr, gr, hr = O.cost_grad_hess_multi(s.h0, ms, s.psi0, s.psi_target, bases, dt, th, 0.3, 2.0)
+        _say(f"tiles K={ndir} P={P} nt={nt} theta {i}: dC={_rel(c[i], cr):.2e} dg={_rel(g[i], gr):.2e} "
+             f"dH={_rel(h[i], hr):.2e}")
+        assert _rel(c[i], cr) < TOL and _rel(g[i], gr) < TOL and _rel(h[i], hr) < TOL
+        assert np.array_equal(h[i], h[i].T)
+    v = rng.normal(size=P)
+    hv = p.hvp(ths[0], v)
+    _say(f"  hvp against H v: {_rel(hv, h[0] @ v):.2e}")
+    assert _rel(hv, h[0] @ v) < TOL
+    p.close()
+
+
 def test_one_direction_through_the_multi_setter_is_the_single_path():
     w = inputs.make_workload("tiny", nt=80)
     s = w.system
