@@ -76,20 +76,23 @@ def test_fourier_directions_against_oracle(n, ndir):
     p.close()
 
 
-def test_above_128_levels():
+@pytest.mark.parametrize("n,ndir,nt", [(130, 2, 24), (120, 3, 16)])
+def test_above_128_levels(n, ndir, nt):
     """n = 130, two directions: the eigen kernel's matrices in global memory, sweeps reading O and
-    S_k from global memory (too large to stage), rows past 128 in the U'' moments."""
-    n, nt, dt, kf = 130, 24, 0.05, 1
-    s, ms = _ops(n, 2, 190)
+    S_k from global memory (too large to stage), rows past 128 in the U'' moments (kept in LDS for
+    all pairs).  n = 120, three directions: the U'' moments of three directions no longer fit in
+    LDS, so each pair builds its own (the per-pair kernel)."""
+    dt, kf = 0.05, 1
+    s, ms = _ops(n, ndir, 190 + ndir)
     p = qoc.Problem(0)
     p.set_system_multi(s.h0, ms, s.psi0, s.psi_target)
     p.set_control_basis(qoc.QOC_BASIS_FOURIER, nt, dt, kf)
     p.set_weights(0.3, 2.0)
-    bases = _fourier_stack(nt, dt, kf, 2)
+    bases = _fourier_stack(nt, dt, kf, ndir)
     th = inputs.draw_thetas(p.P, 1, 191, sigma=0.8)[0]
     c, g, h = p.hess(th)
     cr, gr, hr = O.cost_grad_hess_multi(s.h0, ms, s.psi0, s.psi_target, bases, dt, th, 0.3, 2.0)
-    _say(f"n=130 K=2: dC={_rel(c, cr):.2e} dg={_rel(g, gr):.2e} dH={_rel(h, hr):.2e}")
+    _say(f"n={n} K={ndir}: dC={_rel(c, cr):.2e} dg={_rel(g, gr):.2e} dH={_rel(h, hr):.2e}")
     assert _rel(c, cr) < TOL and _rel(g, gr) < TOL and _rel(h, hr) < TOL
     p.close()
 
