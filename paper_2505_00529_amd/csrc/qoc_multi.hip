@@ -1527,60 +1527,55 @@ __device__ __forceinline__ double2 mc_moments_mixed(const double* Mk, const doub
 // Series terms kept in LDS by the shared-moment U'' kernel (the largest term count it serves).
 constexpr int kMcStermNT = kMcStermNmax + 1;
 
-// The moments of one direction for every row, kept for all pairs: P_a = M~ (x^a o mu) and the
-// weighted G_a = sum_{d <= NT-1-a} Q_d w_{a+d}, Q_d = M~ (x^d o a), w_m = sum_b coef_{m+b} x_p^b.
+// The moments of one direction and row, kept for all pairs: P_a = M~ (x^a o mu) and the weighted
+// G_a = sum_{d <= NT-1-a} Q_d w_{a+d}, Q_d = M~ (x^d o a), w_m = sum_b coef_{m+b} x_p^b.
 // Regrouping sum_m R_m w_m by a gives, for a pair (k, n),
 //   sum_p sum_m R_m[p] w_m[p] = sum_p sum_a conj(P^k_a[p]) G^n_a[p] + conj(P^n_a[p]) G^k_a[p],
-// so each direction's two moment sets are built once instead of once per pair.  One wave, lane =
-// row p; Pl and Gl are [kMcStermNT][n] (LDS).
+// so each direction's two moment sets are built once instead of once per pair.  One thread per
+// (direction, row p), packed over the workgroup; Pl and Gl are [kMcStermNT][n] (LDS).
 template <int NT>
 __device__ __forceinline__ void mc_dir_moments(const double* M, const double* lam, const double2* mu, const double2* at,
-                                               const double2* coef, double m0, int lane, int n, double2* Pl,
+                                               const double2* coef, double m0, int p, int n, double2* Pl,
                                                double2* Gl) {
-  for (int rb = 0; rb * 64 < n; ++rb) {
-    const int p = lane + 64 * rb;
-    double2 P[NT], Q[NT];
+  double2 P[NT], Q[NT];
+#pragma unroll
+  for (int k = 0; k < NT; ++k) {
+    P[k] = make_double2(0.0, 0.0);
+    Q[k] = make_double2(0.0, 0.0);
+  }
+  for (int qi = 0; qi < n; ++qi) {
+    const double xq = lam[qi] - m0;
+    const double mv = M[(size_t)qi * n + p];   // symmetric: coalesced column reads
+    double2 t1 = c_scale(mu[qi], mv), t2 = c_scale(at[qi], mv);
 #pragma unroll
     for (int k = 0; k < NT; ++k) {
-      P[k] = make_double2(0.0, 0.0);
-      Q[k] = make_double2(0.0, 0.0);
-    }
-    for (int qi = 0; qi < n; ++qi) {
-      const double xq = lam[qi] - m0;
-      const double mv = p < n ? M[(size_t)qi * n + p] : 0.0;   // symmetric: coalesced column reads
-      double2 t1 = c_scale(mu[qi], mv), t2 = c_scale(at[qi], mv);
-#pragma unroll
-      for (int k = 0; k < NT; ++k) {
-        P[k] = c_add(P[k], t1);
-        Q[k] = c_add(Q[k], t2);
-        if (k + 1 < NT) {
-          t1 = c_scale(t1, xq);
-          t2 = c_scale(t2, xq);
-        }
+      P[k] = c_add(P[k], t1);
+      Q[k] = c_add(Q[k], t2);
+      if (k + 1 < NT) {
+        t1 = c_scale(t1, xq);
+        t2 = c_scale(t2, xq);
       }
-    }
-    if (p < n) {
-#pragma unroll
-      for (int k = 0; k < NT; ++k) Pl[k * n + p] = P[k];
-      const double xp = lam[p] - m0;
-      double2 G[NT];
-#pragma unroll
-      for (int k = 0; k < NT; ++k) G[k] = make_double2(0.0, 0.0);
-#pragma unroll
-      for (int m = 0; m < NT; ++m) {
-        double2 wm = make_double2(0.0, 0.0);
-#pragma unroll
-        for (int bb = NT - 1 - m; bb >= 0; --bb) {
-          wm = c_scale(wm, xp);
-          wm = c_add(wm, coef[m + bb]);
-        }
-#pragma unroll
-        for (int aa = 0; aa <= m; ++aa) G[aa] = c_add(G[aa], c_mul(Q[m - aa], wm));
-      }
-#pragma unroll
-      for (int k = 0; k < NT; ++k) Gl[k * n + p] = G[k];
     }
   }
+#pragma unroll
+  for (int k = 0; k < NT; ++k) Pl[k * n + p] = P[k];
+  const double xp = lam[p] - m0;
+  double2 G[NT];
+#pragma unroll
+  for (int k = 0; k < NT; ++k) G[k] = make_double2(0.0, 0.0);
+#pragma unroll
+  for (int m = 0; m < NT; ++m) {
+    double2 wm = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int bb = NT - 1 - m; bb >= 0; --bb) {
+      wm = c_scale(wm, xp);
+      wm = c_add(wm, coef[m + bb]);
+    }
+#pragma unroll
+    for (int aa = 0; aa <= m; ++aa) G[aa] = c_add(G[aa], c_mul(Q[m - aa], wm));
+  }
+#pragma unroll
+  for (int k = 0; k < NT; ++k) Gl[k * n + p] = G[k];
 }
 
 // sum_p sum_a conj(P^k_a) G^n_a + conj(P^n_a) G^k_a from the kept moments (one wave, lane = row).
@@ -1610,8 +1605,9 @@ __host__ __device__ inline size_t mc_sterm_shared_bytes(int n, int K) {
   return (size_t)2 * K * kMcStermNT * n * 2 * sizeof(double);
 }
 
-// SHARED: each direction's moments built once by one wave and kept in LDS, then one wave per
-// pair combines them (mc_dir_moments); otherwise each wave builds the moments of its pairs.
+// SHARED: each direction's moments built once (one thread per direction and row) and kept in
+// LDS, then one wave per pair combines them (mc_dir_moments); otherwise each wave builds the
+// moments of its pairs.
 template <bool SHARED>
 __global__ __launch_bounds__(kThreads) void k_mc_sterm(McArgs a) {
   __shared__ double red[kThreads];
@@ -1665,10 +1661,13 @@ __global__ __launch_bounds__(kThreads) void k_mc_sterm(McArgs a) {
       double2* Pl = (double2*)smem_st;                      // [K][kMcStermNT][n]
       double2* Gl = Pl + (size_t)K * kMcStermNT * n;        // [K][kMcStermNT][n]
       const size_t ds = (size_t)kMcStermNT * n;
-      for (int k = wv; k < K; k += kThreads / 64) {
-        switch (nmax) {   // wave-uniform
+      // (direction, row) pairs packed over the threads: K n of them (108 at N = 36, K = 3) keep
+      // fewer waves busy than one wave per direction would
+      for (int t = tid; t < K * n; t += kThreads) {
+        const int k = t / n, p = t - k * n;
+        switch (nmax) {   // workgroup-uniform
 #define QOC_MC_STERM_DIR(T) \
-  case T - 1: mc_dir_moments<T>(Mt + k * nn, lam, mu, at, coef, m0, lane, n, Pl + k * ds, Gl + k * ds); break;
+  case T - 1: mc_dir_moments<T>(Mt + k * nn, lam, mu, at, coef, m0, p, n, Pl + k * ds, Gl + k * ds); break;
           QOC_MC_STERM_DIR(1) QOC_MC_STERM_DIR(2) QOC_MC_STERM_DIR(3) QOC_MC_STERM_DIR(4) QOC_MC_STERM_DIR(5)
           QOC_MC_STERM_DIR(6) QOC_MC_STERM_DIR(7) QOC_MC_STERM_DIR(8) QOC_MC_STERM_DIR(9) QOC_MC_STERM_DIR(10)
           QOC_MC_STERM_DIR(11) QOC_MC_STERM_DIR(12) QOC_MC_STERM_DIR(13) QOC_MC_STERM_DIR(14) QOC_MC_STERM_DIR(15)
