@@ -2105,7 +2105,14 @@ qoc_status qoc_problem::enqueue_multi(Mode mode, int nb, const double* d_theta, 
       if (l > kLds) break;
       fit_pg = pgv;   // widest that fits
       fit_st = st;
-      const long per_cu = std::min<long>(kMaxWgPerCu, (long)(kLds / l));
+      // resident workgroups per CU: the LDS bound, and the runtime's occupancy of both sweeps
+      // (registers) at this LDS size
+      long per_cu = std::min<long>(kMaxWgPerCu, (long)(kLds / l));
+      for (const void* kf : {(const void*)k_mc_forward, (const void*)k_mc_backward}) {
+        int blocks = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, kf, kThreads, l) == hipSuccess && blocks > 0)
+          per_cu = std::min<long>(per_cu, blocks);
+      }
       const long wgs = (long)((ncols + pgv - 1) / pgv) * nb;
       if (wgs <= (long)kCUs * per_cu) {
         if (res_pg == 0) {   // narrowest all resident
