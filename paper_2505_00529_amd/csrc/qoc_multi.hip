@@ -1106,7 +1106,8 @@ __device__ __forceinline__ void mc_stage(double* dst1, const double* src1, int n
 __device__ __forceinline__ double2 mc_sdot(const double* S, const double2* hh, const double2* cur, int n, int w, int p,
                                            int part) {
   double2 acc = make_double2(0.0, 0.0);
-#pragma unroll 3
+  // unrolled by nine (the whole row at n = 36): every S_k load of the lane in flight at once
+#pragma unroll 9
   for (int r = part; r < n; r += 4) {
     const double2 x = c_mul(hh[r], cur[r * w]);
     const double sv = S[(size_t)r * n + p];
