@@ -1067,34 +1067,27 @@ __host__ __device__ inline size_t mc_sweep_lds_doubles(int n, int pg, int K, boo
 // Loads per thread in flight while a step's O is staged into LDS.
 constexpr int kMcStageBatch = 24;
 
-// Stages n1 doubles of src1 into dst1 and n2 of src2 into dst2 (LDS), kMcStageBatch loads per
-// thread issued before the first LDS store: a load-store pair per element would wait out the
-// memory latency once per element.  The loads take clamped, always valid addresses, so they
-// need no branches; only the stores are guarded.  The first batch sits outside the loop, so
-// that loads issued before the call stay in flight into it.
-__device__ __forceinline__ void mc_stage_batch(double* dst1, const double* src1, int n1, double* dst2,
-                                               const double* src2, int total, int base, int tid) {
+// Stages count doubles of src into dst (LDS), kMcStageBatch loads per thread issued before the
+// first LDS store: a load-store pair per element would wait out the memory latency once per
+// element.  The loads take clamped, always valid addresses, so they need no branches; only the
+// stores are guarded.  The first batch sits outside the loop, so that loads issued before the
+// call stay in flight into it.
+__device__ __forceinline__ void mc_stage_batch(double* dst, const double* src, int count, int base, int tid) {
   double v[kMcStageBatch];
 #pragma unroll
-  for (int i = 0; i < kMcStageBatch; ++i) {
-    const int idx = min(base + tid + i * kThreads, total - 1);
-    v[i] = idx < n1 ? src1[idx] : src2[idx - n1];
-  }
+  for (int i = 0; i < kMcStageBatch; ++i) v[i] = src[min(base + tid + i * kThreads, count - 1)];
 #pragma unroll
   for (int i = 0; i < kMcStageBatch; ++i) {
     const int idx = base + tid + i * kThreads;
-    if (idx < n1) dst1[idx] = v[i];
-    else if (idx < total) dst2[idx - n1] = v[i];
+    if (idx < count) dst[idx] = v[i];
   }
 }
 
-__device__ __forceinline__ void mc_stage(double* dst1, const double* src1, int n1, double* dst2, const double* src2,
-                                         int n2, int tid) {
-  const int total = n1 + n2;
-  if (total <= 0) return;
-  mc_stage_batch(dst1, src1, n1, dst2, src2, total, 0, tid);
-  for (int base = kMcStageBatch * kThreads; base < total; base += kMcStageBatch * kThreads)
-    mc_stage_batch(dst1, src1, n1, dst2, src2, total, base, tid);
+__device__ __forceinline__ void mc_stage(double* dst, const double* src, int count, int tid) {
+  if (count <= 0) return;
+  mc_stage_batch(dst, src, count, 0, tid);
+  for (int base = kMcStageBatch * kThreads; base < count; base += kMcStageBatch * kThreads)
+    mc_stage_batch(dst, src, count, base, tid);
 }
 
 // The sweeps' matrix reads go through these inlined helpers, called once with the LDS copy and
@@ -1212,7 +1205,7 @@ __global__ __launch_bounds__(kThreads) void k_mc_forward(McArgs a) {
     const double lam_t = a.lam[es * n + min(tid, n - 1)];
     const double f_t = tid < K * ncol ? mc_forcing(a, tid / ncol, j, c0 + tid % ncol, b) : 0.0;
     if (a.stage)   // the previous step's reads of the staging area ended at its last barrier
-      mc_stage(Ost, a.ov + es * nn, j + 1 < nt ? (int)nn : 0, Ost, a.ov + es * nn, 0, tid);
+      mc_stage(Ost, a.ov + es * nn, j + 1 < nt ? (int)nn : 0, tid);
     for (int r = tid; r < n; r += kThreads) {
       const double2 h = phase(0.5 * (r == tid ? lam_t : a.lam[es * n + r]), a.dt);
       hh[r] = h;
@@ -1319,7 +1312,7 @@ __global__ __launch_bounds__(kThreads) void k_mc_backward(McArgs a) {
     const double2 y_t = a.yt[es * K * n + min(tid, K * n - 1)];
     const double f_t = tid < K * ncol ? mc_forcing(a, tid / ncol, j, c0 + tid % ncol, b) : 0.0;
     if (a.stage)   // the previous step's reads of the staging area ended at its last barrier
-      mc_stage(Ost, a.ov + (es - (j >= 1 ? 1 : 0)) * nn, j >= 1 ? (int)nn : 0, Ost, a.ov, 0, tid);
+      mc_stage(Ost, a.ov + (es - (j >= 1 ? 1 : 0)) * nn, j >= 1 ? (int)nn : 0, tid);
     for (int r = tid; r < n; r += kThreads) {
       const double2 h = c_conj(phase(0.5 * (r == tid ? lam_t : a.lam[es * n + r]), a.dt));
       hh[r] = h;
