@@ -2080,25 +2080,26 @@ qoc_status qoc_problem::enqueue_multi(Mode mode, int nb, const double* d_theta, 
   a.stats = d_stats;
   // Sweep shape: the step's O is staged in LDS when it fits (S_k is read from global memory: the
   // smaller LDS footprint keeps more workgroups on a CU, which hides more than staging saves).
-  // Every workgroup repeats the step's fixed work (staging, phases, the K mat-vecs), so the
-  // column groups are the widest of {8, 16, 32} that keep every (group, theta) workgroup resident
-  // and still give each CU one; else the narrowest that keeps them all resident (few theta);
-  // else the widest that fits in LDS (more workgroups than the GPU holds at once).
+  // The (column group, theta) workgroups should fill the slots the GPU holds at once (CUs times
+  // the workgroups per CU that LDS and registers allow) in as few rounds as possible: a last,
+  // partly filled round runs at a fraction of the occupancy.  So the column width is the one
+  // with the fewest rounds, then the fullest rounds, then the most workgroups per CU, then the
+  // widest (each workgroup repeats the step's fixed work: staging, phases, the K mat-vecs).
   constexpr size_t kLds = 160 * 1024;
   constexpr int kCUs = 256, kMaxWgPerCu = 8;
   auto sweep_lds_of = [&](int pgv, bool st) { return mc_sweep_lds_doubles(n, pgv, K, st) * sizeof(double); };
   int pg = 1;
   bool stage = sweep_lds_of(1, true) <= kLds;
   if (ncols > 0) {
-    int fill_pg = 0, res_pg = 0, fit_pg = 0;
-    bool fill_st = false, res_st = false, fit_st = false;
-    for (int cand : {8, 16, 32}) {
+    int best_pg = 0;
+    bool best_st = false;
+    long best_rounds = 0, best_per_cu = 0;
+    double best_fill = 0.0;
+    for (int cand : {4, 6, 8, 12, 16, 24, 32, 48, 64, 96}) {
       const int pgv = std::min(cand, ncols);
       const bool st = sweep_lds_of(pgv, true) <= kLds;
       const size_t l = sweep_lds_of(pgv, st);
       if (l > kLds) break;
-      fit_pg = pgv;   // widest that fits
-      fit_st = st;
       // resident workgroups per CU: the LDS bound, and the runtime's occupancy of both sweeps
       // (registers) at this LDS size
       long per_cu = std::min<long>(kMaxWgPerCu, (long)(kLds / l));
@@ -2107,28 +2108,25 @@ qoc_status qoc_problem::enqueue_multi(Mode mode, int nb, const double* d_theta, 
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, kf, kThreads, l) == hipSuccess && blocks > 0)
           per_cu = std::min<long>(per_cu, blocks);
       }
+      const long slots = (long)kCUs * per_cu;
       const long wgs = (long)((ncols + pgv - 1) / pgv) * nb;
-      if (wgs <= (long)kCUs * per_cu) {
-        if (res_pg == 0) {   // narrowest all resident
-          res_pg = pgv;
-          res_st = st;
-        }
-        if (wgs >= kCUs) {   // widest all resident with a workgroup per CU
-          fill_pg = pgv;
-          fill_st = st;
-        }
+      const long rounds = (wgs + slots - 1) / slots;
+      const double fill = (double)wgs / (double)(rounds * slots);
+      const bool better = best_pg == 0 || rounds < best_rounds ||
+                          (rounds == best_rounds && (fill > best_fill + 1e-9 ||
+                                                     (fill > best_fill - 1e-9 && per_cu >= best_per_cu)));
+      if (better) {
+        best_pg = pgv;
+        best_st = st;
+        best_rounds = rounds;
+        best_fill = fill;
+        best_per_cu = per_cu;
       }
       if (pgv == ncols) break;
     }
-    if (fill_pg > 0) {
-      pg = fill_pg;
-      stage = fill_st;
-    } else if (res_pg > 0) {
-      pg = res_pg;
-      stage = res_st;
-    } else if (fit_pg > 0) {
-      pg = fit_pg;
-      stage = fit_st;
+    if (best_pg > 0) {
+      pg = best_pg;
+      stage = best_st;
     } else {
       while (pg > 1 && sweep_lds_of(pg, false) > kLds) --pg;
       if (sweep_lds_of(pg, stage) > kLds) stage = false;
