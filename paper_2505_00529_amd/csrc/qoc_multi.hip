@@ -1602,10 +1602,18 @@ __host__ __device__ inline size_t mc_sterm_shared_bytes(int n, int K) {
 // SHARED: each direction's moments built once (one thread per direction and row) and kept in
 // LDS, then one wave per pair combines them (mc_dir_moments); otherwise each wave builds the
 // moments of its pairs.
+// The shared variant runs at three workgroups per CU (168 registers, a few spilled, and no static
+// LDS: its block reduction on the direct path reuses the moments' LDS).
 template <bool SHARED>
-__global__ __launch_bounds__(kThreads) void k_mc_sterm(McArgs a) {
-  __shared__ double red[kThreads];
+__global__ __launch_bounds__(kThreads, SHARED ? 3 : 1) void k_mc_sterm(McArgs a) {
   extern __shared__ __attribute__((aligned(16))) double smem_st[];
+  double* red;
+  if constexpr (SHARED) {
+    red = smem_st;   // the moments' LDS is free on the direct path
+  } else {
+    __shared__ double red_s[kThreads];
+    red = red_s;
+  }
   const int j = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
   const int wv = tid >> 6, lane = tid & 63;
   const int n = a.n, K = a.K, npair = K * (K + 1) / 2;
@@ -1942,9 +1950,7 @@ hipError_t configure_mc_kernels() {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
   }
-  // the U'' kernel also holds a static reduction array of kThreads doubles
-  return hipFuncSetAttribute((const void*)k_mc_sterm<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             160 * 1024 - kThreads * (int)sizeof(double));
+  return hipFuncSetAttribute((const void*)k_mc_sterm<true>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
 }
 
 }  // namespace qoc
@@ -2219,9 +2225,9 @@ qoc_status qoc_problem::enqueue_multi(Mode mode, int nb, const double* d_theta, 
   }
   if (mode == Mode::Hess || mode == Mode::Hvp) {
     prof_begin("sterm", &ev);
-    // each direction's moments shared by its pairs when they fit in LDS (n <= 110 at K = 3)
-    const size_t st_lds = mc_sterm_shared_bytes(n, K);
-    if (st_lds + kThreads * sizeof(double) <= 160 * 1024)
+    // each direction's moments shared by its pairs when they fit in LDS (n <= 113 at K = 3)
+    const size_t st_lds = std::max(mc_sterm_shared_bytes(n, K), kThreads * sizeof(double));
+    if (st_lds <= 160 * 1024)
       hipLaunchKernelGGL(k_mc_sterm<true>, dim3(nt, nb), dim3(kThreads), st_lds, stream, a);
     else
       hipLaunchKernelGGL(k_mc_sterm<false>, dim3(nt, nb), dim3(kThreads), 0, stream, a);
